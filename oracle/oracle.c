@@ -1,0 +1,920 @@
+/*
+ * oracle.c -- plain, slow CPU oracle for the encrypted WiSARD hot path of
+ * "Homomorphic WiSARDs" (arXiv 2403.20190).
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  The GPU product path
+ * neither links nor calls it, and the two share no code, headers or tables.
+ *
+ * What it computes, in the paper's terms:
+ *   ring R_q = Z_q[X]/(X^N+1)                          (Sec. 2.1, Notation)
+ *   SecretKeyGen / EncRLWE / EncRGSW / DecRLWE / DecLWE (Sec. 2.4.1)
+ *   external product, CMUX, ExtractLWE, BlindRotate     (Sec. 2.4.1)
+ *   Vertical Packing                                    (Sec. 2.4.2, Alg. 3)
+ *   CDEMUX gate and tree, Inverse Vertical Packing      (Sec. 3.3, Alg. 5)
+ *   homomorphic training                                (Sec. 3.4, Alg. 6)
+ *   homomorphic inference, PD-act branch                (Sec. 3.6, Alg. 7)
+ *   class counter for dataset balancing                 (Sec. 3.7.1)
+ * The paper works over a 64-bit torus; this oracle uses residues modulo 30-bit
+ * NTT-friendly primes in RNS, a ternary secret, a discrete Gaussian of
+ * sigma = 3.2 and an exact RNS gadget of base 2^6 with 5 digits per prime.
+ * Every reading taken where the paper is silent or garbled is stated next to
+ * the function that takes it.
+ *
+ * All arithmetic is exact: residues live in uint64_t, products of two residues
+ * (< 2^60) are reduced with the C '%' operator, CRT values use unsigned
+ * __int128.  Negacyclic products go through a textbook radix-2 NTT (a library
+ * step); the tests pin it to schoolbook multiplication.
+ *
+ * Layouts (all uint32_t residues in [0, q_i), coefficient domain):
+ *   polynomial over all primes : [prime][N]
+ *   RLWE                       : [poly a=0, b=1][prime][N]
+ *   RGSW                       : [row 0..2D)[poly][prime][N], D = digits*nq;
+ *                                rows 0..D-1 carry the gadget in b, rows
+ *                                D..2D-1 carry it in a; within a side, row
+ *                                i*digits + j is prime i, digit j.
+ *   LWE                        : [prime][N+1]  (a_0..a_{N-1}, b)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+#define ORC_MAXQ 4
+#define DOM_KEY 1u
+#define DOM_PERM 2u
+#define DOM_ENC_A 3u
+#define DOM_ENC_E 4u
+#define CDT_TAIL 41
+
+/* ------------------------------------------------------------------------ */
+/* modular integer helpers                                                  */
+/* ------------------------------------------------------------------------ */
+
+static uint64_t mulmod(uint64_t a, uint64_t b, uint64_t q) { return (a * b) % q; }
+static uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) { return (a + b) % q; }
+static uint64_t submod(uint64_t a, uint64_t b, uint64_t q) { return (a + q - b) % q; }
+
+static uint64_t powmod(uint64_t b, uint64_t e, uint64_t q) {
+  uint64_t r = 1 % q;
+  b %= q;
+  while (e) {
+    if (e & 1) r = mulmod(r, b, q);
+    b = mulmod(b, b, q);
+    e >>= 1;
+  }
+  return r;
+}
+
+/* inverse of a modulo the prime q, by Fermat's little theorem */
+static uint64_t invmod(uint64_t a, uint64_t q) { return powmod(a, q - 2, q); }
+
+/* primality by trial division; fine for the < 2^32 moduli used here */
+int orc_is_prime(uint64_t n) {
+  if (n < 2) return 0;
+  if (n % 2 == 0) return n == 2;
+  for (uint64_t d = 3; d * d <= n; d += 2)
+    if (n % d == 0) return 0;
+  return 1;
+}
+
+/* Parameter rule: the nq largest primes q < 2^30 with q = 1 (mod 2N), in
+ * decreasing order.  The paper fixes only a torus modulus (Table 2); the prime
+ * choice is this implementation's reading.  Returns 0 on success. */
+int orc_find_primes(uint32_t N, uint32_t nq, uint32_t* out) {
+  uint64_t m = 2ull * N;
+  uint64_t q = ((((1ull << 30) - 1) - 1) / m) * m + 1;
+  uint32_t found = 0;
+  while (found < nq && q > m) {
+    if (orc_is_prime(q)) out[found++] = (uint32_t)q;
+    q -= m;
+  }
+  return found == nq ? 0 : -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the 64-bit draw     */
+/* ------------------------------------------------------------------------ */
+
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u; /* Weyl key schedule */
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c[1] ^ k0;
+    uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+  memcpy(out, c, sizeof c);
+}
+
+/* Counter-based 64-bit draw number `index` of stream (seed, domain): the key is
+ * the seed, the counter is (index/2, domain, 0); even indices take output
+ * words 0,1, odd indices words 2,3 (low word first).  The paper does not name
+ * a generator; this is the reading used by both implementations. */
+uint64_t orc_w64(uint64_t seed, uint32_t domain, uint64_t index) {
+  uint64_t blk = index >> 1;
+  uint32_t ctr[4] = {(uint32_t)blk, (uint32_t)(blk >> 32), domain, 0u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t o[4];
+  orc_philox4x32_10(ctr, key, o);
+  if (index & 1) return (uint64_t)o[2] | ((uint64_t)o[3] << 32);
+  return (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+}
+
+/* ------------------------------------------------------------------------ */
+/* discrete Gaussian by cumulative distribution table                        */
+/* ------------------------------------------------------------------------ */
+
+/* T[k] = floor(2^63 * P(|X| <= k)) for X the discrete Gaussian of standard
+ * deviation sigma cut at |X| <= 41, with rho(x) = exp(-x^2 / (2 sigma^2)).
+ * The cumulative sums run over x = 0, 1, 2, ... with weight 1 for x = 0 and
+ * 2*rho(x) otherwise, in that order, in double precision; T[41] = 2^63. */
+void orc_cdt_table(double sigma, uint64_t* T) {
+  double cum[CDT_TAIL + 1];
+  double acc = 0.0;
+  for (int x = 0; x <= CDT_TAIL; ++x) {
+    double w = (x == 0) ? 1.0 : 2.0 * exp(-((double)x * (double)x) / (2.0 * sigma * sigma));
+    acc = acc + w;
+    cum[x] = acc;
+  }
+  for (int x = 0; x < CDT_TAIL; ++x) T[x] = (uint64_t)floor(ldexp(cum[x] / cum[CDT_TAIL], 63));
+  T[CDT_TAIL] = 1ull << 63;
+}
+
+/* magnitude = smallest k with (w >> 1) < T[k]; sign from bit 0 of w; a zero
+ * magnitude ignores the sign */
+int64_t orc_cdt_sample(const uint64_t* T, uint64_t w) {
+  uint64_t r = w >> 1;
+  int64_t k = 0;
+  while (!(r < T[k])) ++k;
+  if (k != 0 && (w & 1)) return -k;
+  return k;
+}
+
+/* ------------------------------------------------------------------------ */
+/* context                                                                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  uint32_t N, logN, nq, log_base, digits, D;
+  uint64_t p;
+  uint64_t q[ORC_MAXQ];
+  u128 Q, delta;                  /* Q = prod q_i, delta = floor(Q / p) */
+  uint64_t delta_mod[ORC_MAXQ];   /* delta mod q_i */
+  uint64_t crt_inv[ORC_MAXQ];     /* [(Q/q_i)^{-1}]_{q_i} */
+  uint64_t psi[ORC_MAXQ];         /* primitive 2N-th root of unity mod q_i */
+  uint64_t* psi_pow[ORC_MAXQ];    /* psi^j, j < N */
+  uint64_t* psi_ipow[ORC_MAXQ];   /* psi^{-j}, j < N */
+  uint64_t* omega_pow[ORC_MAXQ];  /* omega^j, omega = psi^2, j < N */
+  uint64_t* omega_ipow[ORC_MAXQ]; /* omega^{-j} */
+  uint64_t n_inv[ORC_MAXQ];
+  uint64_t cdt[CDT_TAIL + 1];
+  double sigma;
+} orc_ctx;
+
+/* smallest x >= 2 such that psi = x^((q-1)/2N) has psi^N = -1 mod q; such a
+ * psi has multiplicative order exactly 2N */
+static uint64_t find_psi(uint64_t q, uint32_t N) {
+  for (uint64_t x = 2; x < q; ++x) {
+    uint64_t psi = powmod(x, (q - 1) / (2ull * N), q);
+    if (powmod(psi, N, q) == q - 1) return psi;
+  }
+  return 0;
+}
+
+void orc_ctx_free(orc_ctx* c) {
+  if (!c) return;
+  for (uint32_t i = 0; i < ORC_MAXQ; ++i) {
+    free(c->psi_pow[i]);
+    free(c->psi_ipow[i]);
+    free(c->omega_pow[i]);
+    free(c->omega_ipow[i]);
+  }
+  free(c);
+}
+
+/* primes[] == NULL or primes[0] == 0 selects the rule of orc_find_primes */
+orc_ctx* orc_ctx_new(uint32_t N, uint32_t nq, const uint32_t* primes, uint32_t log_base,
+                     uint32_t digits, uint64_t p, double sigma) {
+  if (N < 2 || (N & (N - 1)) || nq < 1 || nq > ORC_MAXQ) return NULL;
+  orc_ctx* c = (orc_ctx*)calloc(1, sizeof(orc_ctx));
+  c->N = N;
+  c->logN = 0;
+  while ((1u << c->logN) < N) c->logN++;
+  c->nq = nq;
+  c->log_base = log_base;
+  c->digits = digits;
+  c->D = digits * nq;
+  c->p = p;
+  c->sigma = sigma;
+  uint32_t pr[ORC_MAXQ] = {0};
+  if (primes && primes[0]) {
+    for (uint32_t i = 0; i < nq; ++i) pr[i] = primes[i];
+  } else if (orc_find_primes(N, nq, pr) != 0) {
+    free(c);
+    return NULL;
+  }
+  c->Q = 1;
+  for (uint32_t i = 0; i < nq; ++i) {
+    uint64_t q = pr[i];
+    if (!orc_is_prime(q) || (q - 1) % (2ull * N) != 0) {
+      orc_ctx_free(c);
+      return NULL;
+    }
+    c->q[i] = q;
+    c->Q *= q;
+  }
+  c->delta = c->Q / p;
+  for (uint32_t i = 0; i < nq; ++i) {
+    uint64_t q = c->q[i];
+    c->delta_mod[i] = (uint64_t)(c->delta % q);
+    uint64_t Mi = (uint64_t)((c->Q / q) % q);
+    c->crt_inv[i] = invmod(Mi, q);
+    c->psi[i] = find_psi(q, N);
+    uint64_t psi = c->psi[i], psi_inv = invmod(psi, q);
+    uint64_t om = mulmod(psi, psi, q), om_inv = invmod(om, q);
+    c->psi_pow[i] = (uint64_t*)malloc(sizeof(uint64_t) * N);
+    c->psi_ipow[i] = (uint64_t*)malloc(sizeof(uint64_t) * N);
+    c->omega_pow[i] = (uint64_t*)malloc(sizeof(uint64_t) * N);
+    c->omega_ipow[i] = (uint64_t*)malloc(sizeof(uint64_t) * N);
+    uint64_t a = 1, b = 1, d = 1, e = 1;
+    for (uint32_t j = 0; j < N; ++j) {
+      c->psi_pow[i][j] = a;
+      c->psi_ipow[i][j] = b;
+      c->omega_pow[i][j] = d;
+      c->omega_ipow[i][j] = e;
+      a = mulmod(a, psi, q);
+      b = mulmod(b, psi_inv, q);
+      d = mulmod(d, om, q);
+      e = mulmod(e, om_inv, q);
+    }
+    c->n_inv[i] = invmod(N, q);
+  }
+  orc_cdt_table(sigma, c->cdt);
+  return c;
+}
+
+void orc_ctx_info(const orc_ctx* c, uint32_t* primes, uint64_t* delta_mod, uint64_t* q_words,
+                  uint64_t* delta_words) {
+  for (uint32_t i = 0; i < c->nq; ++i) {
+    primes[i] = (uint32_t)c->q[i];
+    delta_mod[i] = c->delta_mod[i];
+  }
+  q_words[0] = (uint64_t)c->Q;
+  q_words[1] = (uint64_t)(c->Q >> 64);
+  delta_words[0] = (uint64_t)c->delta;
+  delta_words[1] = (uint64_t)(c->delta >> 64);
+}
+
+void orc_ctx_cdt(const orc_ctx* c, uint64_t* T) { memcpy(T, c->cdt, sizeof c->cdt); }
+
+/* ------------------------------------------------------------------------ */
+/* polynomial arithmetic in Z_q[X]/(X^N+1)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* negacyclic product by the definition: X^N = -1 (Notation, Sec. 2.1) */
+void orc_negmul_schoolbook(uint32_t N, uint64_t q, const uint64_t* a, const uint64_t* b,
+                           uint64_t* out) {
+  for (uint32_t k = 0; k < N; ++k) out[k] = 0;
+  for (uint32_t i = 0; i < N; ++i)
+    for (uint32_t j = 0; j < N; ++j) {
+      uint64_t t = mulmod(a[i] % q, b[j] % q, q);
+      uint32_t k = i + j;
+      if (k < N)
+        out[k] = addmod(out[k], t, q);
+      else
+        out[k - N] = submod(out[k - N], t, q);
+    }
+}
+
+static uint32_t bitrev(uint32_t x, uint32_t bits) {
+  uint32_t r = 0;
+  for (uint32_t i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
+
+/* textbook iterative radix-2 cyclic NTT, A[k] = sum_j a[j] w^{jk}; `wpow`
+ * holds w^j for j < N */
+static void cyclic_ntt(uint64_t* a, uint32_t N, uint32_t logN, uint64_t q, const uint64_t* wpow) {
+  for (uint32_t i = 0; i < N; ++i) {
+    uint32_t r = bitrev(i, logN);
+    if (r > i) {
+      uint64_t t = a[i];
+      a[i] = a[r];
+      a[r] = t;
+    }
+  }
+  for (uint32_t len = 2; len <= N; len <<= 1) {
+    uint32_t half = len >> 1, step = N / len;
+    for (uint32_t s = 0; s < N; s += len)
+      for (uint32_t j = 0; j < half; ++j) {
+        uint64_t u = a[s + j];
+        uint64_t v = mulmod(a[s + j + half], wpow[j * step], q);
+        a[s + j] = addmod(u, v, q);
+        a[s + j + half] = submod(u, v, q);
+      }
+  }
+}
+
+/* negacyclic product through the psi-twisted cyclic NTT:
+ * c = psi^{-j} * INTT( NTT(a psi^j) * NTT(b psi^j) ) */
+static void negmul_ntt(const orc_ctx* c, uint32_t i, const uint64_t* a, const uint64_t* b,
+                       uint64_t* out) {
+  uint32_t N = c->N;
+  uint64_t q = c->q[i];
+  uint64_t* A = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  uint64_t* B = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  for (uint32_t j = 0; j < N; ++j) {
+    A[j] = mulmod(a[j] % q, c->psi_pow[i][j], q);
+    B[j] = mulmod(b[j] % q, c->psi_pow[i][j], q);
+  }
+  cyclic_ntt(A, N, c->logN, q, c->omega_pow[i]);
+  cyclic_ntt(B, N, c->logN, q, c->omega_pow[i]);
+  for (uint32_t j = 0; j < N; ++j) A[j] = mulmod(A[j], B[j], q);
+  cyclic_ntt(A, N, c->logN, q, c->omega_ipow[i]);
+  for (uint32_t j = 0; j < N; ++j)
+    out[j] = mulmod(mulmod(A[j], c->n_inv[i], q), c->psi_ipow[i][j], q);
+  free(A);
+  free(B);
+}
+
+/* exported for the pins: product of two residue polynomials mod q_i */
+void orc_negmul(const orc_ctx* c, uint32_t i, const uint64_t* a, const uint64_t* b, uint64_t* out) {
+  negmul_ntt(c, i, a, b, out);
+}
+
+/* out (+)= poly * (integer polynomial d lifted mod q_i), all for prime i */
+static void mul_acc_small(const orc_ctx* c, uint32_t i, const int32_t* d, const uint32_t* poly,
+                          uint32_t* acc) {
+  uint32_t N = c->N;
+  uint64_t q = c->q[i];
+  uint64_t* A = (uint64_t*)calloc(N, sizeof(uint64_t));
+  uint64_t* B = (uint64_t*)calloc(N, sizeof(uint64_t));
+  uint64_t* P = (uint64_t*)calloc(N, sizeof(uint64_t));
+  for (uint32_t j = 0; j < N; ++j) {
+    int64_t v = d[j];
+    A[j] = (uint64_t)(v < 0 ? v + (int64_t)q : v);
+    B[j] = poly[j];
+  }
+  negmul_ntt(c, i, A, B, P);
+  for (uint32_t j = 0; j < N; ++j) acc[j] = (uint32_t)addmod(acc[j], P[j], q);
+  free(A);
+  free(B);
+  free(P);
+}
+
+/* RLWE helpers; an RLWE holds 2*nq*N words */
+static size_t rlwe_words(const orc_ctx* c) { return 2ull * c->nq * c->N; }
+static size_t rgsw_words(const orc_ctx* c) { return 2ull * c->D * rlwe_words(c); }
+
+static void rlwe_add(const orc_ctx* c, const uint32_t* x, const uint32_t* y, uint32_t* out) {
+  for (uint32_t p = 0; p < 2; ++p)
+    for (uint32_t i = 0; i < c->nq; ++i)
+      for (uint32_t k = 0; k < c->N; ++k) {
+        size_t o = ((size_t)p * c->nq + i) * c->N + k;
+        out[o] = (uint32_t)addmod(x[o], y[o], c->q[i]);
+      }
+}
+
+static void rlwe_sub(const orc_ctx* c, const uint32_t* x, const uint32_t* y, uint32_t* out) {
+  for (uint32_t p = 0; p < 2; ++p)
+    for (uint32_t i = 0; i < c->nq; ++i)
+      for (uint32_t k = 0; k < c->N; ++k) {
+        size_t o = ((size_t)p * c->nq + i) * c->N + k;
+        out[o] = (uint32_t)submod(x[o], y[o], c->q[i]);
+      }
+}
+
+/* Multiplication by the monomial X^e, e any integer (negacyclic: X^N = -1),
+ * applied to both polynomials of an RLWE. */
+void orc_rlwe_rotate(const orc_ctx* c, const uint32_t* in, int64_t e, uint32_t* out) {
+  uint32_t N = c->N;
+  int64_t twoN = 2 * (int64_t)N;
+  int64_t em = ((e % twoN) + twoN) % twoN;
+  for (uint32_t p = 0; p < 2; ++p)
+    for (uint32_t i = 0; i < c->nq; ++i) {
+      const uint32_t* src = in + ((size_t)p * c->nq + i) * N;
+      uint32_t* dst = out + ((size_t)p * c->nq + i) * N;
+      uint64_t q = c->q[i];
+      for (uint32_t j = 0; j < N; ++j) {
+        int64_t t = j + em;
+        int neg = 0;
+        if (t >= twoN) t -= twoN;
+        if (t >= N) {
+          t -= N;
+          neg = 1;
+        }
+        dst[t] = neg ? (uint32_t)((q - src[j]) % q) : src[j];
+      }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* keys, encryption, decryption (Sec. 2.4.1)                                 */
+/* ------------------------------------------------------------------------ */
+
+/* ternary secret s_k = (w64(seed, KEY, k) mod 3) - 1; the paper samples a
+ * binary key, the ternary key is this implementation's parameter choice */
+void orc_keygen(const orc_ctx* c, uint64_t seed, int32_t* s) {
+  for (uint32_t k = 0; k < c->N; ++k) s[k] = (int32_t)(orc_w64(seed, DOM_KEY, k) % 3) - 1;
+}
+
+/* EncRLWE of an integer polynomial mu (coefficients in [0, p)):
+ * b = a*s + Delta*mu + e.  The draws of row `row` of ciphertext `ct` among
+ * `rows` rows per ciphertext are
+ *   a_{i,k} = w64(seed, ENC_A, ((ct*rows + row)*nq + i)*N + k) mod q_i
+ *   e_k     = CDT(w64(seed, ENC_E, (ct*rows + row)*N + k)),
+ * e being one integer polynomial shared by all primes.  mu == NULL encrypts 0. */
+void orc_enc_rlwe_row(const orc_ctx* c, const int32_t* s, const uint64_t* mu, uint64_t seed,
+                      uint64_t ct, uint64_t rows, uint64_t row, uint32_t* out) {
+  uint32_t N = c->N, nq = c->nq;
+  uint64_t* A = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  uint64_t* S = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  uint64_t* P = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  int64_t* e = (int64_t*)malloc(sizeof(int64_t) * N);
+  uint64_t rid = ct * rows + row;
+  for (uint32_t k = 0; k < N; ++k) e[k] = orc_cdt_sample(c->cdt, orc_w64(seed, DOM_ENC_E, rid * N + k));
+  for (uint32_t i = 0; i < nq; ++i) {
+    uint64_t q = c->q[i];
+    for (uint32_t k = 0; k < N; ++k) {
+      A[k] = orc_w64(seed, DOM_ENC_A, (rid * nq + i) * N + k) % q;
+      S[k] = (uint64_t)(s[k] < 0 ? (int64_t)q + s[k] : s[k]);
+    }
+    negmul_ntt(c, i, A, S, P);
+    uint32_t* oa = out + (size_t)i * N;
+    uint32_t* ob = out + ((size_t)nq + i) * N;
+    for (uint32_t k = 0; k < N; ++k) {
+      uint64_t ek = (uint64_t)(e[k] < 0 ? (int64_t)q + e[k] : e[k]);
+      uint64_t m = mu ? mulmod(c->delta_mod[i], mu[k] % q, q) : 0;
+      oa[k] = (uint32_t)A[k];
+      ob[k] = (uint32_t)addmod(addmod(P[k], m, q), ek, q);
+    }
+  }
+  free(A);
+  free(S);
+  free(P);
+  free(e);
+}
+
+void orc_enc_rlwe(const orc_ctx* c, const int32_t* s, const uint64_t* mu, uint64_t seed, uint64_t ct,
+                  uint32_t* out) {
+  orc_enc_rlwe_row(c, s, mu, seed, ct, 1, 0, out);
+}
+
+/* EncRGSW of a bit m: 2D rows, each an encryption of 0, plus m * g_{i,j} on
+ * residue i of the b part (rows i*digits+j) or of the a part (rows
+ * D + i*digits + j), g_{i,j} = base^j.  The paper's gadget entry carries a
+ * stray 1/p factor (Sec. 2.4.1, EncRGSW); the exact gadget base^j is the
+ * reading taken here, in its RNS form (one gadget row per prime and digit). */
+void orc_enc_rgsw(const orc_ctx* c, const int32_t* s, uint32_t m, uint64_t seed, uint64_t ct,
+                  uint32_t* out) {
+  uint32_t N = c->N, nq = c->nq, D = c->D, rows = 2 * D;
+  size_t rw = rlwe_words(c);
+  for (uint32_t r = 0; r < rows; ++r) {
+    uint32_t* row = out + r * rw;
+    orc_enc_rlwe_row(c, s, NULL, seed, ct, rows, r, row);
+    if (m) {
+      uint32_t side = r < D ? 1u : 0u; /* b for the first D rows, a after */
+      uint32_t rr = r % D, i = rr / c->digits, j = rr % c->digits;
+      uint64_t q = c->q[i];
+      uint64_t g = powmod(1ull << c->log_base, j, q);
+      uint32_t* poly = row + ((size_t)side * nq + i) * N;
+      poly[0] = (uint32_t)addmod(poly[0], g, q);
+    }
+  }
+}
+
+/* a noiseless RGSW m*G, used by the pins (a trivial encryption) */
+void orc_trivial_rgsw(const orc_ctx* c, uint32_t m, uint32_t* out) {
+  uint32_t N = c->N, nq = c->nq, D = c->D;
+  size_t rw = rlwe_words(c);
+  memset(out, 0, sizeof(uint32_t) * rgsw_words(c));
+  if (!m) return;
+  for (uint32_t r = 0; r < 2 * D; ++r) {
+    uint32_t side = r < D ? 1u : 0u;
+    uint32_t rr = r % D, i = rr / c->digits, j = rr % c->digits;
+    out[r * rw + ((size_t)side * nq + i) * N] = (uint32_t)powmod(1ull << c->log_base, j, c->q[i]);
+  }
+}
+
+/* CRT: the unique phi in [0, Q) with phi = x_i mod q_i */
+static u128 crt(const orc_ctx* c, const uint64_t* x) {
+  u128 phi = 0;
+  for (uint32_t i = 0; i < c->nq; ++i) {
+    uint64_t q = c->q[i];
+    uint64_t y = mulmod(x[i] % q, c->crt_inv[i], q);
+    u128 Mi = c->Q / q;
+    phi += (u128)y * Mi;
+    while (phi >= c->Q) phi -= c->Q;
+  }
+  return phi;
+}
+
+/* decode: mu = floor((p*phi + floor(Q/2)) / Q) mod p, i.e. phi/Delta rounded
+ * half up (the paper's rounding of (b - <a,s>)/(q/p), Sec. 2.4.1) */
+static uint64_t decode(const orc_ctx* c, u128 phi) {
+  u128 num = (u128)c->p * phi + c->Q / 2;
+  return (uint64_t)((num / c->Q) % c->p);
+}
+
+/* phase b - a*s of an RLWE, per prime, coefficient domain */
+static void rlwe_phase(const orc_ctx* c, const int32_t* s, const uint32_t* ct, uint64_t* ph) {
+  uint32_t N = c->N, nq = c->nq;
+  uint64_t* A = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  uint64_t* S = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  uint64_t* P = (uint64_t*)malloc(sizeof(uint64_t) * N);
+  for (uint32_t i = 0; i < nq; ++i) {
+    uint64_t q = c->q[i];
+    for (uint32_t k = 0; k < N; ++k) {
+      A[k] = ct[(size_t)i * N + k];
+      S[k] = (uint64_t)(s[k] < 0 ? (int64_t)q + s[k] : s[k]);
+    }
+    negmul_ntt(c, i, A, S, P);
+    for (uint32_t k = 0; k < N; ++k) ph[(size_t)i * N + k] = submod(ct[((size_t)nq + i) * N + k], P[k], q);
+  }
+  free(A);
+  free(S);
+  free(P);
+}
+
+void orc_dec_rlwe(const orc_ctx* c, const int32_t* s, const uint32_t* ct, uint64_t* mu) {
+  uint32_t N = c->N, nq = c->nq;
+  uint64_t* ph = (uint64_t*)malloc(sizeof(uint64_t) * nq * N);
+  rlwe_phase(c, s, ct, ph);
+  for (uint32_t k = 0; k < N; ++k) {
+    uint64_t x[ORC_MAXQ];
+    for (uint32_t i = 0; i < nq; ++i) x[i] = ph[(size_t)i * N + k];
+    mu[k] = decode(c, crt(c, x));
+  }
+  free(ph);
+}
+
+/* signed noise phi - Delta*mu (centered mod Q) per coefficient, as a double;
+ * returns the largest magnitude */
+double orc_noise_rlwe(const orc_ctx* c, const int32_t* s, const uint32_t* ct, const uint64_t* mu,
+                      double* noise_out) {
+  uint32_t N = c->N, nq = c->nq;
+  uint64_t* ph = (uint64_t*)malloc(sizeof(uint64_t) * nq * N);
+  rlwe_phase(c, s, ct, ph);
+  double mx = 0;
+  for (uint32_t k = 0; k < N; ++k) {
+    uint64_t x[ORC_MAXQ];
+    for (uint32_t i = 0; i < nq; ++i) x[i] = ph[(size_t)i * N + k];
+    u128 phi = crt(c, x);
+    u128 dm = (c->delta * (u128)(mu[k] % c->p)) % c->Q;
+    u128 d = phi >= dm ? phi - dm : phi + c->Q - dm;
+    double v = (d > c->Q / 2) ? -(double)(c->Q - d) : (double)d;
+    if (noise_out) noise_out[k] = v;
+    if (fabs(v) > mx) mx = fabs(v);
+  }
+  free(ph);
+  return mx;
+}
+
+/* DecLWE: phi = b - <a, s> (Sec. 2.4.1) then the same rounding */
+void orc_dec_lwe(const orc_ctx* c, const int32_t* s, const uint32_t* lwe, uint64_t* mu) {
+  uint32_t N = c->N, nq = c->nq;
+  uint64_t x[ORC_MAXQ];
+  for (uint32_t i = 0; i < nq; ++i) {
+    uint64_t q = c->q[i];
+    const uint32_t* a = lwe + (size_t)i * (N + 1);
+    uint64_t acc = 0;
+    for (uint32_t k = 0; k < N; ++k) {
+      uint64_t sk = (uint64_t)(s[k] < 0 ? (int64_t)q + s[k] : s[k]);
+      acc = addmod(acc, mulmod(a[k], sk, q), q);
+    }
+    x[i] = submod(a[N], acc, q);
+  }
+  *mu = decode(c, crt(c, x));
+}
+
+/* ------------------------------------------------------------------------ */
+/* gadget decomposition and the external product                             */
+/* ------------------------------------------------------------------------ */
+
+/* Balanced base-2^log_base digits of each residue: v = the residue centered
+ * in (-q/2, q/2); for j < digits-1: d = v mod B in [0, B), d -= B if
+ * d >= B/2, v = (v - d)/B; the last digit is what remains of v.  Then
+ * sum_j d_j B^j = v exactly.  Output digit polynomial (i, j) at
+ * out[(i*digits + j)*N + k]. */
+void orc_decompose(const orc_ctx* c, const uint32_t* poly, int32_t* out) {
+  uint32_t N = c->N;
+  int64_t B = 1ll << c->log_base;
+  for (uint32_t i = 0; i < c->nq; ++i) {
+    int64_t q = (int64_t)c->q[i];
+    for (uint32_t k = 0; k < N; ++k) {
+      int64_t v = poly[(size_t)i * N + k];
+      if (v > (q - 1) / 2) v -= q;
+      for (uint32_t j = 0; j + 1 < c->digits; ++j) {
+        int64_t d = ((v % B) + B) % B;
+        if (d >= B / 2) d -= B;
+        out[((size_t)i * c->digits + j) * N + k] = (int32_t)d;
+        v = (v - d) / B;
+      }
+      out[((size_t)i * c->digits + c->digits - 1) * N + k] = (int32_t)v;
+    }
+  }
+}
+
+/* External product C [.] (a, b) = sum_{i,j} dec(b)_{i,j} * C[B(i,j)]
+ *                               + sum_{i,j} dec(a)_{i,j} * C[A(i,j)]
+ * with B(i,j) = i*digits + j and A(i,j) = D + i*digits + j; each digit
+ * polynomial is lifted into every prime (Sec. 2.4.1, multiplication). */
+void orc_extprod(const orc_ctx* c, const uint32_t* C, const uint32_t* in, uint32_t* out) {
+  uint32_t N = c->N, nq = c->nq, D = c->D;
+  size_t rw = rlwe_words(c);
+  int32_t* dig = (int32_t*)malloc(sizeof(int32_t) * (size_t)D * N);
+  memset(out, 0, sizeof(uint32_t) * rw);
+  for (uint32_t side = 0; side < 2; ++side) {
+    /* side 0 decomposes b against the B-rows, side 1 decomposes a against the A-rows */
+    const uint32_t* src = in + (side == 0 ? (size_t)nq * N : 0);
+    uint32_t row0 = side == 0 ? 0 : D;
+    orc_decompose(c, src, dig);
+    for (uint32_t r = 0; r < D; ++r) {
+      const uint32_t* row = C + (size_t)(row0 + r) * rw;
+      for (uint32_t ip = 0; ip < nq; ++ip) {
+        mul_acc_small(c, ip, dig + (size_t)r * N, row + (size_t)ip * N, out + (size_t)ip * N);
+        mul_acc_small(c, ip, dig + (size_t)r * N, row + ((size_t)nq + ip) * N,
+                      out + ((size_t)nq + ip) * N);
+      }
+    }
+  }
+  free(dig);
+}
+
+/* CMUX(C, d1, d0) = d0 + C [.] (d1 - d0): selects d1 when C encrypts 1 */
+void orc_cmux(const orc_ctx* c, const uint32_t* C, const uint32_t* d1, const uint32_t* d0,
+              uint32_t* out) {
+  size_t rw = rlwe_words(c);
+  uint32_t* diff = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  uint32_t* h = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  rlwe_sub(c, d1, d0, diff);
+  orc_extprod(c, C, diff, h);
+  rlwe_add(c, d0, h, out);
+  free(diff);
+  free(h);
+}
+
+/* BlindRotate: for t = 0, 1, ..., k-1: acc <- CMUX(C_t, X^{e_t} acc, acc).
+ * With C_t encrypting S_t the result encrypts v * X^{sum_t S_t e_t}; the
+ * paper's I_t is -e_t (Sec. 2.4.1). */
+void orc_blind_rotate(const orc_ctx* c, const uint32_t* in, const uint32_t* const* C,
+                      const int64_t* e, uint32_t k, uint32_t* out) {
+  size_t rw = rlwe_words(c);
+  uint32_t* rot = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  uint32_t* tmp = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  memcpy(out, in, sizeof(uint32_t) * rw);
+  for (uint32_t t = 0; t < k; ++t) {
+    orc_rlwe_rotate(c, out, e[t], rot);
+    orc_cmux(c, C[t], rot, out, tmp);
+    memcpy(out, tmp, sizeof(uint32_t) * rw);
+  }
+  free(rot);
+  free(tmp);
+}
+
+/* CDEMUX(C, d) = (d - C [.] d, C [.] d)  (Sec. 3.3.1) */
+void orc_cdemux(const orc_ctx* c, const uint32_t* C, const uint32_t* in, uint32_t* out0,
+                uint32_t* out1) {
+  size_t rw = rlwe_words(c);
+  uint32_t* h = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  orc_extprod(c, C, in, h);
+  rlwe_sub(c, in, h, out0);
+  memcpy(out1, h, sizeof(uint32_t) * rw);
+  free(h);
+}
+
+/* Inverse Vertical Packing (Alg. 5) on nb bits C[0..nb): nr = min(nb, log2 N)
+ * rotation bits C[z..nb) with exponents +2^t, then the CDEMUX tree over
+ * C[0..z), level i pairing L_j with L_{j+2^i}.  out receives 2^z RLWE; cell
+ * m of the table sits at ciphertext m mod 2^z, coefficient m >> z.  The
+ * algorithm's loop bound "0 to n" is read as j in [0, n). */
+void orc_ivp(const orc_ctx* c, const uint32_t* const* C, uint32_t nb, const uint32_t* in,
+             uint32_t* out) {
+  size_t rw = rlwe_words(c);
+  uint32_t nr = nb < c->logN ? nb : c->logN;
+  uint32_t z = nb - nr;
+  int64_t* e = (int64_t*)malloc(sizeof(int64_t) * (nr ? nr : 1));
+  for (uint32_t t = 0; t < nr; ++t) e[t] = (int64_t)1 << t;
+  orc_blind_rotate(c, in, C + z, e, nr, out);
+  uint32_t* t0 = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  for (uint32_t i = 0; i < z; ++i) {
+    uint32_t n = 1u << i;
+    for (uint32_t j = 0; j < n; ++j) {
+      orc_cdemux(c, C[i], out + j * rw, t0, out + (j + n) * rw);
+      memcpy(out + j * rw, t0, sizeof(uint32_t) * rw);
+    }
+  }
+  free(t0);
+  free(e);
+}
+
+/* ExtractLWE(c, 0): a'_0 = a_0, a'_k = -a_{N-k} (k >= 1), b' = b_0 */
+void orc_extract_lwe0(const orc_ctx* c, const uint32_t* in, uint32_t* lwe) {
+  uint32_t N = c->N, nq = c->nq;
+  for (uint32_t i = 0; i < nq; ++i) {
+    uint64_t q = c->q[i];
+    const uint32_t* a = in + (size_t)i * N;
+    uint32_t* o = lwe + (size_t)i * (N + 1);
+    o[0] = a[0];
+    for (uint32_t k = 1; k < N; ++k) o[k] = (uint32_t)((q - a[N - k]) % q);
+    o[N] = in[((size_t)nq + i) * N];
+  }
+}
+
+/* Vertical Packing (Alg. 3) of one LUT of 2^z RLWE under nb bits, where bit u
+ * is either encrypted (C[u] != NULL) or the cleartext clear[u].  Levels run
+ * from i = z-1 down to 0, level i pairing T[j] with T[j + 2^i] and taking
+ * T[j + 2^i] when bit i is 1 (the inverse of the IVP layout; Alg. 3 as printed
+ * pairs its bits in the opposite order, which is not the inverse of Alg. 5).
+ * Then the blind rotation by X^{-2^t} over bits z..nb and ExtractLWE(., 0).
+ * A cleartext bit is applied as the exact selection a noiseless RGSW of that
+ * bit produces. */
+void orc_vp(const orc_ctx* c, const uint32_t* const* C, const uint8_t* clear, uint32_t nb,
+            const uint32_t* lut, uint32_t* lwe) {
+  size_t rw = rlwe_words(c);
+  uint32_t nr = nb < c->logN ? nb : c->logN;
+  uint32_t z = nb - nr;
+  uint32_t nt = 1u << z;
+  uint32_t* T = (uint32_t*)malloc(sizeof(uint32_t) * rw * nt);
+  uint32_t* rot = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  uint32_t* tmp = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  memcpy(T, lut, sizeof(uint32_t) * rw * nt);
+  for (int i = (int)z - 1; i >= 0; --i) {
+    uint32_t n = 1u << i;
+    for (uint32_t j = 0; j < n; ++j) {
+      uint32_t* lo = T + j * rw;
+      uint32_t* hi = T + (j + n) * rw;
+      if (C[i]) {
+        orc_cmux(c, C[i], hi, lo, tmp);
+        memcpy(lo, tmp, sizeof(uint32_t) * rw);
+      } else if (clear[i]) {
+        memcpy(lo, hi, sizeof(uint32_t) * rw);
+      }
+    }
+  }
+  uint32_t* acc = T;
+  for (uint32_t t = 0; t < nr; ++t) {
+    uint32_t u = z + t;
+    int64_t e = -((int64_t)1 << t);
+    if (C[u]) {
+      orc_rlwe_rotate(c, acc, e, rot);
+      orc_cmux(c, C[u], rot, acc, tmp);
+      memcpy(acc, tmp, sizeof(uint32_t) * rw);
+    } else if (clear[u]) {
+      orc_rlwe_rotate(c, acc, e, rot);
+      memcpy(acc, rot, sizeof(uint32_t) * rw);
+    }
+  }
+  orc_extract_lwe0(c, acc, lwe);
+  free(T);
+  free(rot);
+  free(tmp);
+}
+
+/* ------------------------------------------------------------------------ */
+/* WiSARD layer (Def. 1-2, Alg. 6, Alg. 7)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* pi_r: Fisher-Yates over [0, s): for k = s-1 down to 1, j = w64(seed, PERM,
+ * s-1-k) mod (k+1), swap(pi[k], pi[j]).  The permuted input is t[k] =
+ * x[pi[k]].  The paper leaves the permutation's generator unspecified. */
+void orc_permutation(uint64_t seed, uint32_t s, uint32_t* pi) {
+  for (uint32_t k = 0; k < s; ++k) pi[k] = k;
+  for (int64_t k = (int64_t)s - 1; k >= 1; --k) {
+    uint32_t j = (uint32_t)(orc_w64(seed, DOM_PERM, (uint64_t)((int64_t)s - 1 - k)) % (uint64_t)(k + 1));
+    uint32_t t = pi[k];
+    pi[k] = pi[j];
+    pi[j] = t;
+  }
+}
+
+static uint32_t ceil_log2(uint32_t l) {
+  uint32_t L = 0;
+  while ((1u << L) < l) ++L;
+  return L;
+}
+
+/* geometry of RAM j: a_j tuple bits, nb = L + a_j, z = nb - min(nb, log2 N) */
+static void ram_geometry(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, uint32_t j,
+                         uint32_t* aj, uint32_t* nb, uint32_t* z) {
+  uint32_t L = ceil_log2(l);
+  uint32_t rem = s - j * a;
+  *aj = rem < a ? rem : a;
+  *nb = L + *aj;
+  uint32_t nr = *nb < c->logN ? *nb : c->logN;
+  *z = *nb - nr;
+}
+
+/* k1 = 2^z of a full RAM: the number of RLWE per RAM row of H.  Definition 2
+ * prints ceil(l 2^a / N); the bit count of the IVP index gives 2^z, which is
+ * the reading taken (equal to the printed value when l is a power of two). */
+uint32_t orc_k1(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a) {
+  uint32_t aj, nb, z;
+  ram_geometry(c, s, l, a, 0, &aj, &nb, &z);
+  (void)aj;
+  (void)nb;
+  return 1u << z;
+}
+
+/* Homomorphic training (Alg. 6) restricted to RAMs [ram_lo, ram_hi):
+ * for each sample i in order and each RAM j: b = [Y_i bits 0..L), X_i[pi[j a
+ * + t]] for t < a_j]; h = IVP(b, (0, Delta)); H[j][d] += h[d].  The input of
+ * the IVP, "(0,1)" in the paper, is read as the trivial RLWE (0, Delta).  The
+ * tuple of RAM j is t_{ja} .. t_{ja+a-1} (the printed t_j .. t_{j+a-1}
+ * overlaps tuples).  x_ptr[i*s + k] points at the RGSW of input bit k of
+ * sample i, y_ptr[i*L + u] at label bit u (LSB first); H is [k0][k1] RLWE. */
+void orc_train(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const uint32_t* pi,
+               const uint32_t* const* x_ptr, const uint32_t* const* y_ptr, uint64_t n,
+               uint32_t ram_lo, uint32_t ram_hi, uint32_t* H) {
+  size_t rw = rlwe_words(c);
+  uint32_t L = ceil_log2(l);
+  uint32_t k1 = orc_k1(c, s, l, a);
+  const uint32_t** bits = (const uint32_t**)malloc(sizeof(uint32_t*) * (L + a + 1));
+  uint32_t* in = (uint32_t*)calloc(rw, sizeof(uint32_t));
+  uint32_t* h = (uint32_t*)malloc(sizeof(uint32_t) * rw * k1);
+  for (uint32_t i = 0; i < c->nq; ++i) in[((size_t)c->nq + i) * c->N] = (uint32_t)c->delta_mod[i];
+  for (uint64_t smp = 0; smp < n; ++smp) {
+    for (uint32_t j = ram_lo; j < ram_hi; ++j) {
+      uint32_t aj, nb, z;
+      ram_geometry(c, s, l, a, j, &aj, &nb, &z);
+      for (uint32_t u = 0; u < L; ++u) bits[u] = y_ptr[smp * L + u];
+      for (uint32_t t = 0; t < aj; ++t) bits[L + t] = x_ptr[smp * s + pi[j * a + t]];
+      orc_ivp(c, bits, nb, in, h);
+      for (uint32_t d = 0; d < (1u << z); ++d) {
+        uint32_t* dst = H + ((size_t)j * k1 + d) * rw;
+        rlwe_add(c, dst, h + (size_t)d * rw, dst);
+      }
+    }
+  }
+  free(bits);
+  free(in);
+  free(h);
+}
+
+/* class counter for balancing (Sec. 3.7.1): cnt += BlindRotate((0, Delta),
+ * Y_i bits, +2^u) for every sample, i.e. Delta at coefficient y_i */
+void orc_class_count(const orc_ctx* c, uint32_t l, const uint32_t* const* y_ptr, uint64_t n,
+                     uint32_t* cnt) {
+  size_t rw = rlwe_words(c);
+  uint32_t L = ceil_log2(l);
+  uint32_t* in = (uint32_t*)calloc(rw, sizeof(uint32_t));
+  uint32_t* h = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  int64_t* e = (int64_t*)malloc(sizeof(int64_t) * (L ? L : 1));
+  for (uint32_t i = 0; i < c->nq; ++i) in[((size_t)c->nq + i) * c->N] = (uint32_t)c->delta_mod[i];
+  for (uint32_t u = 0; u < L; ++u) e[u] = (int64_t)1 << u;
+  for (uint64_t smp = 0; smp < n; ++smp) {
+    orc_blind_rotate(c, in, y_ptr + smp * L, e, L, h);
+    rlwe_add(c, cnt, h, cnt);
+  }
+  free(in);
+  free(h);
+  free(e);
+}
+
+/* Homomorphic inference, PD-act branch (Alg. 7) for one sample, RAM j and
+ * label c: b = [bits of c (cleartext), X[pi[j a + t]]], u = VP(b, H[j]).
+ * x_ptr[k] points at the RGSW of input bit k of the sample. */
+void orc_infer_one(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const uint32_t* pi,
+                   const uint32_t* H, const uint32_t* const* x_ptr, uint32_t j, uint32_t label,
+                   uint32_t* lwe) {
+  size_t rw = rlwe_words(c);
+  uint32_t L = ceil_log2(l);
+  uint32_t k1 = orc_k1(c, s, l, a);
+  uint32_t aj, nb, z;
+  ram_geometry(c, s, l, a, j, &aj, &nb, &z);
+  const uint32_t** bits = (const uint32_t**)calloc(nb + 1, sizeof(uint32_t*));
+  uint8_t* clear = (uint8_t*)calloc(nb + 1, 1);
+  for (uint32_t u = 0; u < L; ++u) clear[u] = (uint8_t)((label >> u) & 1u);
+  for (uint32_t t = 0; t < aj; ++t) bits[L + t] = x_ptr[pi[j * a + t]];
+  orc_vp(c, bits, clear, nb, H + (size_t)j * k1 * rw, lwe);
+  free(bits);
+  free(clear);
+}
+
+/* LWE addition, used for the per-class sums u_c = sum_j u[c][j] */
+void orc_lwe_add(const orc_ctx* c, const uint32_t* x, const uint32_t* y, uint32_t* out) {
+  for (uint32_t i = 0; i < c->nq; ++i)
+    for (uint32_t k = 0; k <= c->N; ++k) {
+      size_t o = (size_t)i * (c->N + 1) + k;
+      out[o] = (uint32_t)addmod(x[o], y[o], c->q[i]);
+    }
+}
+
+/* exported sizes for the Python wrapper */
+uint64_t orc_rlwe_words(const orc_ctx* c) { return rlwe_words(c); }
+uint64_t orc_rgsw_words(const orc_ctx* c) { return rgsw_words(c); }
+uint32_t orc_logN(const orc_ctx* c) { return c->logN; }

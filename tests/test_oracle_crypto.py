@@ -1,0 +1,180 @@
+"""Pins of the oracle's TFHE building blocks (Sec. 2.4.1, Alg. 3, Alg. 5):
+noiseless special cases that must hold bit-exactly, decryption semantics of
+every gate including negacyclic signs, brute force of IVP and VP over every
+index on small rings, CRT decoding and noise health."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+# a small ring so brute force over indices stays cheap; 30-bit primes = 1 mod 2N
+SMALL = dict(N=16, nq=2, p=16)
+
+
+def rand_rlwe(c, rng):
+    return np.stack([np.stack([rng.integers(0, q, c.N) for q in c.primes]) for _ in range(2)]).astype(np.uint32)
+
+
+@pytest.mark.parametrize("N,nq", [(16, 1), (16, 2), (1024, 1), (2048, 2), (64, 3)])
+def test_trivial_rgsw_is_identity(N, nq):
+    """G [.] c = c and 0 [.] c = 0 bit-exactly: fixes row order, digit order, sides."""
+    c = O.Ctx(N, nq, 64)
+    rng = np.random.default_rng(N + nq)
+    ct = rand_rlwe(c, rng)
+    assert np.array_equal(c.extprod(c.trivial_rgsw(1), ct), ct)
+    assert not c.extprod(c.trivial_rgsw(0), ct).any()
+    # CMUX with trivial selectors is exact selection
+    d1 = rand_rlwe(c, rng)
+    assert np.array_equal(c.cmux(c.trivial_rgsw(1), d1, ct), d1)
+    assert np.array_equal(c.cmux(c.trivial_rgsw(0), d1, ct), ct)
+
+
+@pytest.mark.parametrize("N,nq,p", [(1024, 1, 64), (2048, 2, 1024), (4096, 3, 16384)])
+def test_enc_dec_roundtrip(N, nq, p):
+    c = O.Ctx(N, nq, p)
+    s = c.keygen(1)
+    rng = np.random.default_rng(p)
+    mu = rng.integers(0, p, N).astype(np.uint64)
+    ct = c.enc_rlwe(s, mu, 3, 5)
+    assert np.array_equal(c.dec_rlwe(s, ct), mu)
+    mx, _ = c.noise_rlwe(s, ct, mu)
+    assert mx <= 41
+    # RGSW row 0 decrypts like an RLWE of m * g_{0,0} = m in coefficient 0 (gadget in b)
+    rg = c.enc_rgsw(s, 1, 3, 9)
+    assert rg.shape == (2 * 5 * nq, 2, nq, N)
+
+
+def test_crt_decode_rounding():
+    c = O.Ctx(16, 2, 16)
+    s = np.zeros(16, np.int32)  # zero key: the phase is b itself
+    Q, d = c.Q, c.delta
+    for mu in [0, 1, 7, 15]:
+        for off in [0, 1, -1, d // 2 - 1, -(d // 2) + 1]:
+            phi = (mu * d + off) % Q
+            ct = np.zeros((2, 2, 16), np.uint32)
+            for i, q in enumerate(c.primes):
+                ct[1, i, 0] = phi % q
+            assert c.dec_rlwe(s, ct)[0] == mu
+    # the half-way point rounds up: phi = floor(Q/2)/p*... checked against the formula
+    for phi in [Q // 2, Q - 1, Q // 32, Q // 32 - 1]:
+        ct = np.zeros((2, 2, 16), np.uint32)
+        for i, q in enumerate(c.primes):
+            ct[1, i, 0] = phi % q
+        assert c.dec_rlwe(s, ct)[0] == ((16 * phi + Q // 2) // Q) % 16
+
+
+def test_extprod_decrypts_to_product():
+    c = O.Ctx(1024, 1, 64)
+    s = c.keygen(2)
+    rng = np.random.default_rng(0)
+    mu = rng.integers(0, 64, 1024).astype(np.uint64)
+    ct = c.enc_rlwe(s, mu, 5, 0)
+    for m in (0, 1):
+        out = c.extprod(c.enc_rgsw(s, m, 6, m), ct)
+        assert np.array_equal(c.dec_rlwe(s, out), (m * mu) % 64)
+
+
+def test_cmux_cdemux_semantics():
+    c = O.Ctx(1024, 1, 64)
+    s = c.keygen(3)
+    rng = np.random.default_rng(1)
+    m1 = rng.integers(0, 64, 1024).astype(np.uint64)
+    m0 = rng.integers(0, 64, 1024).astype(np.uint64)
+    d1, d0 = c.enc_rlwe(s, m1, 7, 0), c.enc_rlwe(s, m0, 7, 1)
+    for bit in (0, 1):
+        C = c.enc_rgsw(s, bit, 8, bit)
+        assert np.array_equal(c.dec_rlwe(s, c.cmux(C, d1, d0)), m1 if bit else m0)
+        o0, o1 = c.cdemux(C, d1)
+        assert np.array_equal(c.dec_rlwe(s, o0), m1 * (1 - bit))
+        assert np.array_equal(c.dec_rlwe(s, o1), m1 * bit)
+
+
+def _negacyclic_shift(v, e, p):
+    N = len(v)
+    out = np.zeros(N, np.int64)
+    for j in range(N):
+        t = (j + e) % (2 * N)
+        if t < N:
+            out[t] = (out[t] + v[j]) % p
+        else:
+            out[t - N] = (out[t - N] - v[j]) % p
+    return out
+
+
+def test_blind_rotate_semantics_with_wrap():
+    c = O.Ctx(16, 2, 16)
+    s = c.keygen(4)
+    rng = np.random.default_rng(2)
+    v = rng.integers(0, 16, 16).astype(np.uint64)
+    ct = c.enc_rlwe(s, v, 9, 0)
+    exps = [3, 7, 11, -5]
+    for bits in itertools.product([0, 1], repeat=4):
+        Cs = [c.enc_rgsw(s, b, 10, 4 * sum(x << i for i, x in enumerate(bits)) + t) for t, b in enumerate(bits)]
+        out = c.blind_rotate(ct, Cs, exps)
+        tot = sum(b * e for b, e in zip(bits, exps))
+        assert np.array_equal(c.dec_rlwe(s, out).astype(np.int64), _negacyclic_shift(v.astype(np.int64), tot, 16))
+
+
+def _bits_rgsw(c, s, m, nb, seed, ct0):
+    return [c.enc_rgsw(s, (m >> u) & 1, seed, ct0 + u) for u in range(nb)]
+
+
+@pytest.mark.parametrize("nb", [3, 5, 6])
+def test_ivp_one_hot_brute_force(nb):
+    """IVP output decrypts to zero everywhere except cell m, which holds f(m) (Alg. 5)."""
+    c = O.Ctx(**SMALL)  # log2 N = 4 -> nb = 5, 6 exercise the CDEMUX tree (z = 1, 2)
+    s = c.keygen(5)
+    z = nb - min(nb, c.logN)
+    for m in range(1 << nb):
+        val = 1 + (m % 13)
+        Cs = _bits_rgsw(c, s, m, nb, 11, 100 * m)
+        out = c.ivp(Cs, c.trivial_rlwe(val))
+        assert out.shape[0] == 1 << z
+        dec = np.stack([c.dec_rlwe(s, o) for o in out])
+        want = np.zeros_like(dec)
+        want[m % (1 << z), m >> z] = val
+        assert np.array_equal(dec, want), m
+
+
+def test_vp_inverts_ivp_brute_force():
+    """VP(bits(m'), IVP(bits(m), x)) decrypts to x [m' = m] (Alg. 3 read as the inverse of Alg. 5),
+    with the low bits given in the clear like the label bits of Alg. 7."""
+    c = O.Ctx(8, 1, 16)  # log2 N = 3
+    s = c.keygen(6)
+    nb, n_clear = 5, 1  # z = 2 > number of cleartext bits: one encrypted tree level
+    for m in range(1 << nb):
+        lut = c.ivp(_bits_rgsw(c, s, m, nb, 12, 50 * m), c.trivial_rlwe(5))
+        for mp in range(1 << nb):
+            rg = _bits_rgsw(c, s, mp, nb, 13, 1000 + 50 * mp)
+            clear = [(mp >> u) & 1 for u in range(nb)]
+            rg = [None if u < n_clear else rg[u] for u in range(nb)]
+            lwe = c.vp(rg, clear, lut)
+            assert c.dec_lwe(s, lwe) == (5 if mp == m else 0), (m, mp)
+
+
+def test_extract_lwe_coefficient_zero():
+    c = O.Ctx(1024, 1, 64)
+    s = c.keygen(7)
+    rng = np.random.default_rng(3)
+    mu = rng.integers(0, 64, 1024).astype(np.uint64)
+    ct = c.enc_rlwe(s, mu, 14, 0)
+    for e in [0, -1, -37, -1023]:
+        lwe = c.extract_lwe0(c.rotate(ct, e))
+        assert c.dec_lwe(s, lwe) == _negacyclic_shift(mu.astype(np.int64), e, 64)[0]
+    # LWE addition adds messages
+    l2 = c.lwe_add(c.extract_lwe0(ct), c.extract_lwe0(c.rotate(ct, -1)))
+    assert c.dec_lwe(s, l2) == (int(mu[0]) + int(mu[1])) % 64
+
+
+def test_noise_health_after_chain():
+    """Noise after a full rotation chain stays far below Delta/2 (margin >= 2^4)."""
+    c = O.Ctx(2048, 2, 1024)
+    s = c.keygen(8)
+    Cs = _bits_rgsw(c, s, 0b10110110101, 11, 15, 0)
+    out = c.ivp(Cs, c.trivial_rlwe(1))
+    mu = np.zeros(2048, np.uint64)
+    mu[0b10110110101] = 1
+    mx, _ = c.noise_rlwe(s, out[0], mu)
+    assert mx * 16 < c.delta / 2

@@ -1,0 +1,164 @@
+"""Pins of the oracle's WiSARD layer: the paper's worked examples (Sec. 2.2.4,
+Fig. 1, Fig. 2), encrypted training against the plaintext Integer WiSARD
+(Alg. 4 vs Alg. 6, cell by cell), PD-act inference against Alg. 2, and the
+additivity of the encrypted model."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import plain as P
+from paper_2403_20190_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+EX = json.load(open(os.path.join(GOLD, "paper_examples.json")))
+
+
+def test_thermometer_examples():
+    for case in EX["thermometer"]["cases"]:
+        assert P.thermometer(case["x"], case["size"]) == case["bits"]
+    assert P.encode(np.array([[3, 1]]), 4).tolist() == [[1, 1, 1, 0, 1, 0, 0, 0]]
+
+
+def test_quantize_levels():
+    v = np.arange(256)
+    q = P.quantize_u8(v, 2)
+    assert q.min() == 0 and q.max() == 2 and np.all(np.diff(q) >= 0)
+    assert (q == 0).sum() == 86 and (q == 2).sum() == 85  # floor(3v/256)
+
+
+def test_figure1_permutation_and_score():
+    f = EX["figure1"]
+    x = np.array(f["input"])
+    t = x[np.array(f["perm"])]
+    assert t.tolist() == f["address_bits"]
+    W = np.array([f["rams"]])  # one discriminator
+    # the figure labels cells as written strings t0 t1 (MSB first); read those
+    drawn = ["".join(str(int(b)) for b in t[2 * j:2 * j + 2]) for j in range(2)]
+    assert drawn == f["marked_cells_as_drawn"]
+    assert sum(W[0, j, int(drawn[j], 2)] for j in range(2)) == f["score"]
+    # with the LSB-first f_comp of Def. 1 the score of this discriminator is the same
+    u = P.ram_scores(W, x, 2, np.array(f["perm"]))
+    assert u.sum() == f["score"]
+
+
+@pytest.mark.parametrize("key", ["figure2a", "figure2b"])
+def test_figure2_scores(key):
+    f = EX[key]
+    W = np.array([f["rams"]])
+    u = P.ram_scores(W, np.array(f["input"]), 2, np.arange(4))
+    assert P.act_bin(u, f["threshold"]).sum() == f["score"]
+
+
+def test_activations():
+    x = np.array([0, 1, 2, 3, 4, 7, 8, 100])
+    assert P.act_log(x).tolist() == [0, 1, 1, 2, 2, 3, 3, 6]
+    assert P.act_blog(x, 2).tolist() == [0, 1, 1, 2, 2, 2, 2, 2]
+    assert P.act_bin(x, 2).tolist() == [0, 0, 0, 1, 1, 1, 1, 1]
+    assert P.argmax_lowest([1, 3, 3, 2]) == 1
+
+
+def test_train_integer_counts():
+    rng = np.random.default_rng(0)
+    X = rng.integers(0, 2, (30, 10)).astype(np.uint8)
+    y = rng.integers(0, 3, 30)
+    pi = O.permutation(9, 10)
+    W = P.train_integer(X, y, 3, 4, pi)
+    assert W.shape == (3, 3, 16)
+    assert W.sum() == 30 * 3
+    for c in range(3):
+        assert W[c].sum() == 3 * (y == c).sum()
+
+
+class Micro:
+    """Small encrypted WiSARD: exercises a ragged last tuple, an encrypted
+    CDEMUX/CMUX tree level (z > L) and cleartext label bits in the chain."""
+
+    def __init__(self, N, s, l, a, n, p=64, nq=1, seed=0):
+        self.c = O.Ctx(N, nq, p)
+        self.s, self.l, self.a, self.n = s, l, a, n
+        self.L = O.ceil_log2(l)
+        self.k0 = -(-s // a)
+        self.k1 = self.c.k1(s, l, a)
+        X, y = synth.prototype_bits(seed, n, s, l, flip=0.2)
+        self.X, self.y = X, y
+        self.sk = self.c.keygen(100 + seed)
+        self.pi = O.permutation(200 + seed, s)
+        self.xr = self.c.enc_rgsw_bits(self.sk, X.reshape(-1), 300 + seed, 0).reshape(n, s, -1)
+        yb = np.array([[(v >> u) & 1 for u in range(self.L)] for v in y]).reshape(-1)
+        self.yr = self.c.enc_rgsw_bits(self.sk, yb, 400 + seed, 0).reshape(n, self.L, -1)
+
+    def train(self, idx=None):
+        idx = list(range(self.n)) if idx is None else list(idx)
+        H = np.zeros((self.k0, self.k1, 2, self.c.nq, self.c.N), np.uint32)
+        self.c.train(self.s, self.l, self.a, self.pi, lambda i, k: self.xr[idx[i], k],
+                     lambda i, u: self.yr[idx[i], u], len(idx), H)
+        return H
+
+
+CONFIGS = [
+    dict(N=16, s=14, l=3, a=4, n=6),   # nb = 6, log N = 4: z = 2 = L -> tree levels are the label bits
+    dict(N=8, s=10, l=2, a=4, n=5),    # nb = 5, log N = 3: z = 2 > L = 1 -> one encrypted tree level
+    dict(N=32, s=9, l=5, a=3, n=6),    # nb = 6, log N = 5: z = 1 < L = 3 -> label bits in the chain
+]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS)
+def test_encrypted_training_matches_integer_wisard(cfg):
+    m = Micro(**cfg)
+    H = m.train()
+    W = P.train_integer(m.X, m.y, m.l, m.a, m.pi)
+    want = P.expected_model_cells(W, m.s, m.l, m.a, m.c.N)
+    got = np.stack([[m.c.dec_rlwe(m.sk, H[j, d]) for d in range(m.k1)] for j in range(m.k0)])
+    assert np.array_equal(got.astype(np.int64), want)
+    # noise health of the trained model
+    for j in range(m.k0):
+        for d in range(m.k1):
+            mx, _ = m.c.noise_rlwe(m.sk, H[j, d], want[j, d].astype(np.uint64))
+            assert mx * 16 < m.c.delta / 2
+
+
+@pytest.mark.parametrize("cfg", CONFIGS)
+def test_encrypted_inference_pd_act(cfg):
+    m = Micro(**cfg)
+    H = m.train()
+    W = P.train_integer(m.X, m.y, m.l, m.a, m.pi)
+    Xt, _ = synth.prototype_bits(cfg.get("seed", 0) + 50, 3, m.s, m.l, flip=0.3)
+    for t in range(3):
+        xr = m.c.enc_rgsw_bits(m.sk, Xt[t], 500 + t, 0)
+        cells = np.zeros((m.l, m.k0), np.int64)
+        sums = []
+        for c in range(m.l):
+            acc = None
+            for j in range(m.k0):
+                lwe = m.c.infer_one(m.s, m.l, m.a, m.pi, H, lambda k: xr[k], j, c)
+                cells[c, j] = m.c.dec_lwe(m.sk, lwe)
+                acc = lwe if acc is None else m.c.lwe_add(acc, lwe)
+            sums.append(m.c.dec_lwe(m.sk, acc))
+        want = P.ram_scores(W, Xt[t], m.a, m.pi)
+        assert np.array_equal(cells, want)
+        assert sums == list(want.sum(axis=1) % m.c.p)
+        for kind in ("bin", "log", "blog"):
+            assert P.pd_act_predict(cells, kind) == P.predict(W, Xt[t], m.a, m.pi, kind)
+
+
+def test_model_additivity_and_order():
+    """H(A u B) = H(A) + H(B) and any sample order gives the same bits (Sec. 3.7.2)."""
+    m = Micro(N=16, s=14, l=3, a=4, n=6)
+    H = m.train()
+    HA = m.train(range(0, 3))
+    HB = m.train(range(3, 6))
+    q = m.c.primes[0]
+    assert np.array_equal(H, ((HA.astype(np.uint64) + HB) % q).astype(np.uint32))
+    assert np.array_equal(H, m.train([5, 2, 0, 4, 1, 3]))
+
+
+def test_class_counter():
+    m = Micro(N=16, s=14, l=3, a=4, n=6)
+    cnt = np.zeros((2, 1, 16), np.uint32)
+    m.c.class_count(m.l, lambda i, u: m.yr[i, u], m.n, cnt)
+    dec = m.c.dec_rlwe(m.sk, cnt)
+    assert dec[:3].tolist() == [int((m.y == c).sum()) for c in range(3)]
+    assert not dec[3:].any()

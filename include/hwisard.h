@@ -1,0 +1,193 @@
+/*
+ * hwisard.h -- C ABI of the MI355X (gfx950) hot path of encrypted WiSARD
+ * training and inference (Homomorphic WiSARDs, arXiv 2403.20190).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Status.      Every call returns hw_status (0 = HW_OK).  Arguments are checked
+ *              on the host before anything is enqueued, so a call that fails
+ *              its checks has written nothing.  Errors raised by the device
+ *              runtime while enqueueing are returned as HW_EDEVICE; faults of
+ *              work already enqueued surface at the next synchronisation of
+ *              the caller's stream.  hw_last_error() gives a message for the
+ *              last failing call of the calling thread.
+ * Ownership.   The caller owns every buffer it passes; device pointers ("_dev")
+ *              must stay valid until the work on `stream` has completed.  The
+ *              library owns only the context, its tables and its workspace.
+ * Streams.     Device work is enqueued on the caller's `stream` (NULL = the
+ *              default stream) and returns without waiting for it.  Calls on
+ *              one context must be serialised by the caller (they share its
+ *              workspace); distinct contexts are independent.
+ * Residues.    Ciphertext words are uint32 residues in [0, q_i).  Coefficient
+ *              order: a polynomial over all primes is [prime][N]; an RLWE
+ *              ciphertext is [poly a=0, b=1][prime][N]; an LWE ciphertext is
+ *              [prime][N+1] (a_0..a_{N-1}, b); RGSW ciphertexts use a device
+ *              layout (NTT domain, internal coefficient order) of
+ *              hw_sizes().rgsw bytes each, exported to the coefficient domain
+ *              by hw_rgsw_export_canonical.
+ * Secret key.  int32[N] with entries in {-1, 0, 1}.
+ */
+#ifndef HWISARD_H
+#define HWISARD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HW_OK = 0,
+  HW_EINVAL = -1,        /* invalid argument or shape */
+  HW_ENOMEM = -2,        /* device allocation failed */
+  HW_EDEVICE = -3,       /* HIP runtime error */
+  HW_EUNSUPPORTED = -4,  /* parameter set outside the compiled kernels */
+  HW_EBUSY = -5,         /* serving engine: request refused for lack of memory */
+  HW_ECANCELLED = -6     /* serving engine: request cancelled */
+} hw_status;
+
+/* One RLWE parameter set (Setup, Sec. 2.4.1).  The paper fixes a 64-bit torus
+ * modulus (Table 2); this library uses residues modulo 30-bit NTT-friendly
+ * primes instead. */
+typedef struct {
+  uint32_t N;          /* ring degree: 1024, 2048 or 4096 */
+  uint32_t nq;         /* number of primes: 1, 2 or 3 */
+  uint32_t primes[4];  /* distinct primes q < 2^30, q = 1 mod 2N; primes[0] == 0
+                          selects the nq largest such primes, decreasing */
+  uint32_t log_base;   /* gadget base 2^log_base; must be 6 */
+  uint32_t digits;     /* gadget digits per prime; must be 5 */
+  double sigma;        /* standard deviation of the discrete Gaussian error */
+  uint64_t plain_mod;  /* plaintext modulus p: a power of two, 2 <= p <= 2^20 */
+} hw_params;
+
+/* WiSARD shape (Def. 1-2): s input bits, l classes, tuple (address) size a,
+ * seed of the pseudo-random input permutation pi_r. */
+typedef struct {
+  uint32_t s;
+  uint32_t l;
+  uint32_t a;
+  uint32_t reserved;   /* must be 0 */
+  uint64_t perm_seed;
+} hw_wisard_shape;
+
+typedef struct hw_ctx hw_ctx;
+
+/* Create a context for `params` on HIP device `device`: validates the
+ * parameters, derives the primes, NTT twiddle tables, Delta = floor(Q/p) and
+ * CRT constants, and uploads them.  On success *out owns them. */
+hw_status hw_ctx_create(const hw_params* params, int device, hw_ctx** out);
+
+/* Release a context and its device memory; waits for the device first. */
+void hw_ctx_destroy(hw_ctx* ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* hw_last_error(void);
+
+/* The resolved parameter set (primes filled in). */
+hw_status hw_ctx_params(const hw_ctx* ctx, hw_params* out);
+
+/* Bytes of one RLWE, one RGSW (device layout) and one LWE ciphertext. */
+hw_status hw_sizes(const hw_ctx* ctx, uint64_t* rlwe_bytes, uint64_t* rgsw_bytes,
+                   uint64_t* lwe_bytes);
+
+/* Model geometry of Def. 2: k0 = ceil(s/a) RAMs, k1 = 2^z RLWE per RAM where
+ * z = L + a - min(L + a, log2 N) and L = ceil(log2 l); model_bytes is the size
+ * of H = [k0][k1] RLWE.  (Def. 2 prints k1 = ceil(l 2^a / N); the IVP index
+ * has L + a bits, which gives 2^z.) */
+hw_status hw_wisard_dims(const hw_ctx* ctx, const hw_wisard_shape* shape, uint32_t* k0,
+                         uint32_t* k1, uint64_t* model_bytes);
+
+/* The permutation pi_r of Def. 1 for `shape` (host output, s entries):
+ * Fisher-Yates driven by the library's counter-based generator; the permuted
+ * input is t[k] = x[pi[k]]. */
+hw_status hw_permutation(const hw_wisard_shape* shape, uint32_t* perm_host);
+
+/* ---- client side (Sec. 2.4.1), run on the device for throughput ---------- */
+
+/* SecretKeyGen: ternary RLWE key s_k = (w64(seed, KEY, k) mod 3) - 1.
+ * sk_dev: int32[N]. */
+hw_status hw_keygen(hw_ctx* ctx, uint64_t seed, int32_t* sk_dev, hipStream_t stream);
+
+/* EncRGSW of nbits bits (bits_dev: uint8 0/1, nbits entries); ciphertext
+ * number ct_index0 + k encrypts bit k and is written at
+ * rgsw_dev + k * rgsw_bytes.  Rows: 2D = 2 * digits * nq encryptions of 0,
+ * the first D carrying bit * base^j on residue i of b, the next D on residue
+ * i of a (row i*digits + j within a half).  Randomness: draw streams of the
+ * library's generator keyed by `seed`, a function of (ciphertext, row) only. */
+hw_status hw_encrypt_rgsw_bits(hw_ctx* ctx, const int32_t* sk_dev, const uint8_t* bits_dev,
+                               uint64_t nbits, uint64_t seed, uint64_t ct_index0,
+                               uint32_t* rgsw_dev, hipStream_t stream);
+
+/* EncRLWE of `count` plaintext polynomials msg_dev[count][N] (uint64 in
+ * [0, p); NULL encrypts zeros): b = a s + Delta msg + e.  Output
+ * rlwe_dev[count] in the coefficient domain. */
+hw_status hw_encrypt_rlwe(hw_ctx* ctx, const int32_t* sk_dev, const uint64_t* msg_dev,
+                          uint64_t count, uint64_t seed, uint64_t ct_index0, uint32_t* rlwe_dev,
+                          hipStream_t stream);
+
+/* DecRLWE: msg_dev[count][N] = round(p (b - a s) / Q) mod p, the phase taken
+ * through the CRT (round half up). */
+hw_status hw_decrypt_rlwe(hw_ctx* ctx, const int32_t* sk_dev, const uint32_t* rlwe_dev,
+                          uint64_t count, uint64_t* msg_dev, hipStream_t stream);
+
+/* DecLWE: msg_dev[count] = round(p (b - <a, s>) / Q) mod p. */
+hw_status hw_decrypt_lwe(hw_ctx* ctx, const int32_t* sk_dev, const uint32_t* lwe_dev,
+                         uint64_t count, uint64_t* msg_dev, hipStream_t stream);
+
+/* Copy `count` device-layout RGSW ciphertexts to the coefficient domain,
+ * out_dev[count][2D][2][nq][N] (for checks against other implementations). */
+hw_status hw_rgsw_export_canonical(hw_ctx* ctx, const uint32_t* rgsw_dev, uint64_t count,
+                                   uint32_t* out_dev, hipStream_t stream);
+
+/* ---- ring and ciphertext kernels ----------------------------------------- */
+
+/* In-place negacyclic NTT of `count` polynomials polys_dev[count][nq][N]
+ * (every residue transformed modulo its own prime).  inverse = 0: coefficient
+ * domain -> evaluation domain in the library's internal order; inverse = 1:
+ * back (including the 1/N factor).  Pointwise products in the evaluation
+ * domain followed by the inverse give negacyclic products (Sec. 2.1). */
+hw_status hw_ntt(hw_ctx* ctx, uint32_t* polys_dev, uint64_t count, int inverse,
+                 hipStream_t stream);
+
+/* External product (Sec. 2.4.1): out[k] = rgsw[k] [.] in[k] for k < count,
+ * i.e. sum_{i,j} dec(b)_{i,j} C[i*digits+j] + sum_{i,j} dec(a)_{i,j}
+ * C[D+i*digits+j] with balanced base-2^6 digits of the centered residues.
+ * in_dev/out_dev: RLWE[count]; rgsw_dev: RGSW[count] in device layout.
+ * out must not alias in. */
+hw_status hw_external_product(hw_ctx* ctx, const uint32_t* rgsw_dev, const uint32_t* in_dev,
+                              uint64_t count, uint32_t* out_dev, hipStream_t stream);
+
+/* ---- server side: the hot path -------------------------------------------- */
+
+/* Homomorphic training (Alg. 6) of n samples, accumulated into the model in
+ * place.  x_rgsw_dev: RGSW[n][s] of the unpermuted input bits; y_rgsw_dev:
+ * RGSW[n][L] of the label bits, LSB first (L = ceil(log2 l)).  For sample i
+ * and RAM j the IVP (Alg. 5) runs on b = [label bits, x[pi[j a + t]] for
+ * t < a_j] (a_j = min(a, s - j a)) with input (0, Delta) and its 2^z_j outputs
+ * are added to model_dev[j][0 .. 2^z_j) (RLWE[k0][k1], coefficient domain).
+ * class_count_dev (one RLWE, may be NULL) receives the balancing counter
+ * (Sec. 3.7.1): the IVP of the label bits alone.  Results are exact:
+ * independent of chunking, sample order and launch configuration. */
+hw_status hw_wisard_train_encrypted(hw_ctx* ctx, const hw_wisard_shape* shape,
+                                    const uint32_t* x_rgsw_dev, const uint32_t* y_rgsw_dev,
+                                    uint64_t n, uint32_t* model_dev, uint32_t* class_count_dev,
+                                    hipStream_t stream);
+
+/* Homomorphic inference, PD-act branch (Alg. 7): for each sample, RAM j and
+ * label c < l, the Vertical Packing (Alg. 3, read as the inverse of the IVP
+ * layout) of model row j with the label bits of c in the clear and the
+ * sample's permuted tuple bits encrypted, then ExtractLWE(., 0).
+ * ram_scores_dev: LWE[n][l][k0]; class_scores_dev (may be NULL):
+ * LWE[n][l], the sums over j.  model_dev is read only. */
+hw_status hw_wisard_infer_encrypted(hw_ctx* ctx, const hw_wisard_shape* shape,
+                                    const uint32_t* model_dev, const uint32_t* x_rgsw_dev,
+                                    uint64_t n, uint32_t* ram_scores_dev,
+                                    uint32_t* class_scores_dev, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HWISARD_H */

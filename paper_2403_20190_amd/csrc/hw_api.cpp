@@ -1,0 +1,594 @@
+// hw_api.cpp -- host side of the C ABI in include/hwisard.h: parameter
+// derivation (primes, roots of unity, NTT twiddles, Delta, CRT constants,
+// Gaussian table), argument checks, workspace management and the
+// orchestration of the kernels in hw_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hwisard.h"
+#include "hw_internal.h"
+
+using hw::Tabs;
+typedef unsigned __int128 u128;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static hw_status fail(hw_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+static hw_status ok() {
+  g_err.clear();
+  return HW_OK;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? HW_ENOMEM : HW_EDEVICE, "%s: %s", #expr, \
+                  hipGetErrorString(e_));                                              \
+  } while (0)
+
+extern "C" const char* hw_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// number theory on the host
+// ---------------------------------------------------------------------------
+
+static uint64_t mulm(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+
+static uint64_t powm(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1 % m;
+  b %= m;
+  for (; e; e >>= 1, b = mulm(b, b, m))
+    if (e & 1) r = mulm(r, b, m);
+  return r;
+}
+
+// deterministic Miller-Rabin for n < 2^32 (witnesses 2, 7, 61)
+static bool is_prime32(uint64_t n) {
+  if (n < 2) return false;
+  for (uint64_t p : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull, 61ull})
+    if (n % p == 0) return n == p;
+  uint64_t d = n - 1;
+  int r = 0;
+  while (!(d & 1)) {
+    d >>= 1;
+    ++r;
+  }
+  for (uint64_t a : {2ull, 7ull, 61ull}) {
+    uint64_t x = powm(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int i = 1; i < r && comp; ++i) {
+      x = mulm(x, x, n);
+      if (x == n - 1) comp = false;
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+static uint32_t brv(uint32_t x, int bits) {
+  uint32_t r = 0;
+  for (int i = 0; i < bits; ++i) r = (r << 1) | ((x >> i) & 1u);
+  return r;
+}
+
+// Shoup companion floor(w * 2^32 / q)
+static uint32_t shoup(uint32_t w, uint32_t q) { return (uint32_t)(((uint64_t)w << 32) / q); }
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 on the host (for the permutation) and the Gaussian table
+// ---------------------------------------------------------------------------
+
+static void philox_host(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0], p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, n1 = (uint32_t)p1;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1, n3 = (uint32_t)p0;
+    c[0] = n0;
+    c[1] = n1;
+    c[2] = n2;
+    c[3] = n3;
+  }
+}
+
+static uint64_t draw64(uint64_t seed, uint32_t domain, uint64_t index) {
+  const uint64_t blk = index >> 1;
+  uint32_t c[4] = {(uint32_t)blk, (uint32_t)(blk >> 32), domain, 0u};
+  philox_host(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return (index & 1) ? ((uint64_t)c[2] | ((uint64_t)c[3] << 32)) : ((uint64_t)c[0] | ((uint64_t)c[1] << 32));
+}
+
+// T[k] = floor(2^63 P(|X| <= k)), X ~ discrete Gaussian(sigma) cut at 41; the
+// cumulative weights 1, 2 rho(1), 2 rho(2), ... are summed in increasing order
+static void build_cdt(double sigma, uint64_t T[42]) {
+  double cum[42], acc = 0.0;
+  for (int x = 0; x < 42; ++x) {
+    const double w = x == 0 ? 1.0 : 2.0 * std::exp(-((double)x * (double)x) / (2.0 * sigma * sigma));
+    acc = acc + w;
+    cum[x] = acc;
+  }
+  for (int x = 0; x < 41; ++x) T[x] = (uint64_t)std::floor(std::ldexp(cum[x] / cum[41], 63));
+  T[41] = 1ull << 63;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+struct hw_ctx {
+  hw_params prm;
+  int device;
+  int logN;
+  Tabs tabs;
+  hw::CrtTab crt;
+  hw::Cdt cdt;
+  u128 Q;
+  void* d_tables = nullptr;        // twiddle tables of every prime
+  uint32_t* d_skhat = nullptr;     // [nq][N]
+  void* d_ws = nullptr;            // workspace
+  size_t ws_bytes = 0;
+  size_t ws_budget = 0;
+  uint32_t* d_perm = nullptr;      // cached permutation
+  uint32_t perm_s = 0;
+  uint64_t perm_seed = 0;
+  bool perm_valid = false;
+  std::vector<uint32_t> h_perm;
+};
+
+static size_t rlwe_words(const hw_ctx* c) { return (size_t)2 * c->prm.nq * c->prm.N; }
+static size_t rgsw_words(const hw_ctx* c) { return (size_t)2 * 5 * c->prm.nq * rlwe_words(c); }
+static size_t lwe_words(const hw_ctx* c) { return (size_t)c->prm.nq * (c->prm.N + 1); }
+
+extern "C" hw_status hw_ctx_create(const hw_params* params, int device, hw_ctx** out) {
+  if (!params || !out) return fail(HW_EINVAL, "null argument");
+  *out = nullptr;
+  hw_params P = *params;
+  int logN = 0;
+  while ((1u << logN) < P.N) ++logN;
+  if ((1u << logN) != P.N || logN < 10 || logN > 12)
+    return fail(HW_EUNSUPPORTED, "N = %u: supported ring degrees are 1024, 2048, 4096", P.N);
+  if (P.nq < 1 || P.nq > 3) return fail(HW_EUNSUPPORTED, "nq = %u: 1..3 primes supported", P.nq);
+  if (P.log_base != 6 || P.digits != 5)
+    return fail(HW_EUNSUPPORTED, "gadget base 2^%u with %u digits: only base 2^6 with 5 digits is compiled",
+                P.log_base, P.digits);
+  if (!(P.sigma > 0.0 && P.sigma < 16.0)) return fail(HW_EINVAL, "sigma = %g out of range (0, 16)", P.sigma);
+  if (P.plain_mod < 2 || P.plain_mod > (1ull << 20) || (P.plain_mod & (P.plain_mod - 1)))
+    return fail(HW_EINVAL, "plain_mod = %llu: a power of two in [2, 2^20] is required",
+                (unsigned long long)P.plain_mod);
+  const uint64_t m = 2ull * P.N;
+  if (P.primes[0] == 0) {
+    uint64_t q = ((((1ull << 30) - 2)) / m) * m + 1;
+    uint32_t found = 0;
+    for (; found < P.nq && q > m; q -= m)
+      if (is_prime32(q)) P.primes[found++] = (uint32_t)q;
+    if (found != P.nq) return fail(HW_EINVAL, "not enough primes");
+  }
+  for (uint32_t i = 0; i < P.nq; ++i) {
+    const uint32_t q = P.primes[i];
+    if (q >= (1u << 30) || !is_prime32(q) || (q - 1) % m)
+      return fail(HW_EINVAL, "prime %u: need a prime < 2^30 with q = 1 mod 2N", q);
+    for (uint32_t j = 0; j < i; ++j)
+      if (P.primes[j] == q) return fail(HW_EINVAL, "primes must be distinct");
+  }
+  for (uint32_t i = P.nq; i < 4; ++i) P.primes[i] = 0;
+
+  HIP_TRY(hipSetDevice(device));
+  hw_ctx* c = new hw_ctx();
+  c->prm = P;
+  c->device = device;
+  c->logN = logN;
+  const uint32_t N = P.N;
+  c->Q = 1;
+  for (uint32_t i = 0; i < P.nq; ++i) c->Q *= P.primes[i];
+  const u128 delta = c->Q / P.plain_mod;
+  if (delta < 2) {
+    delete c;
+    return fail(HW_EINVAL, "plain_mod too large for Q");
+  }
+
+  // tables: for each prime fwd[N] then inv[N] of (w, Shoup)
+  std::vector<uint2> host((size_t)2 * P.nq * N);
+  for (uint32_t i = 0; i < P.nq; ++i) {
+    const uint32_t q = P.primes[i];
+    uint64_t g = 2;  // smallest quadratic non-residue: psi = g^((q-1)/2N) has order 2N
+    while (powm(g, (q - 1) / 2, q) != q - 1) ++g;
+    const uint64_t psi = powm(g, (q - 1) / m, q);
+    const uint64_t psi_inv = powm(psi, q - 2, q);
+    uint2* fw = host.data() + (size_t)2 * i * N;
+    uint2* iv = fw + N;
+    for (uint32_t k = 0; k < N; ++k) {
+      const uint32_t w = (uint32_t)powm(psi, brv(k, logN), q);
+      const uint32_t wi = (uint32_t)powm(psi_inv, brv(k, logN), q);
+      fw[k] = make_uint2(w, shoup(w, q));
+      iv[k] = make_uint2(wi, shoup(wi, q));
+    }
+    hw::PrimeTab& pt = c->tabs.pt[i];
+    pt.q = q;
+    pt.two_q = 2 * q;
+    pt.ninv = (uint32_t)powm(N, q - 2, q);
+    pt.ninv_sh = shoup(pt.ninv, q);
+    pt.r32 = (uint32_t)((1ull << 32) % q);
+    pt.r32_sh = shoup(pt.r32, q);
+    pt.one_sh = (uint32_t)((1ull << 32) / q);
+    pt.delta = (uint32_t)(delta % q);
+    const u128 Mi = c->Q / q;
+    c->crt.M_lo[i] = (uint64_t)Mi;
+    c->crt.M_hi[i] = (uint64_t)(Mi >> 64);
+    c->crt.inv[i] = (uint32_t)powm((uint64_t)(Mi % q), q - 2, q);
+  }
+  c->crt.Q_lo = (uint64_t)c->Q;
+  c->crt.Q_hi = (uint64_t)(c->Q >> 64);
+  c->crt.half_lo = (uint64_t)(c->Q / 2);
+  c->crt.half_hi = (uint64_t)((c->Q / 2) >> 64);
+  c->crt.p = P.plain_mod;
+  build_cdt(P.sigma, c->cdt.T);
+
+  hipError_t e = hipMalloc(&c->d_tables, host.size() * sizeof(uint2));
+  if (e == hipSuccess) e = hipMemcpy(c->d_tables, host.data(), host.size() * sizeof(uint2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&c->d_skhat, sizeof(uint32_t) * P.nq * N);
+  if (e != hipSuccess) {
+    hw_ctx_destroy(c);
+    return fail(e == hipErrorOutOfMemory ? HW_ENOMEM : HW_EDEVICE, "table upload: %s", hipGetErrorString(e));
+  }
+  for (uint32_t i = 0; i < P.nq; ++i) {
+    c->tabs.fwd[i] = reinterpret_cast<const uint2*>(c->d_tables) + (size_t)2 * i * N;
+    c->tabs.inv[i] = c->tabs.fwd[i] + N;
+  }
+  const char* wb = getenv("HWISARD_WS_BYTES");
+  c->ws_budget = wb ? (size_t)strtoull(wb, nullptr, 10) : ((size_t)16 << 30);
+  *out = c;
+  return ok();
+}
+
+extern "C" void hw_ctx_destroy(hw_ctx* c) {
+  if (!c) return;
+  hipSetDevice(c->device);
+  hipDeviceSynchronize();
+  if (c->d_tables) hipFree(c->d_tables);
+  if (c->d_skhat) hipFree(c->d_skhat);
+  if (c->d_ws) hipFree(c->d_ws);
+  if (c->d_perm) hipFree(c->d_perm);
+  delete c;
+}
+
+extern "C" hw_status hw_ctx_params(const hw_ctx* c, hw_params* out) {
+  if (!c || !out) return fail(HW_EINVAL, "null argument");
+  *out = c->prm;
+  return ok();
+}
+
+extern "C" hw_status hw_sizes(const hw_ctx* c, uint64_t* rlwe, uint64_t* rgsw, uint64_t* lwe) {
+  if (!c) return fail(HW_EINVAL, "null context");
+  if (rlwe) *rlwe = 4 * rlwe_words(c);
+  if (rgsw) *rgsw = 4 * rgsw_words(c);
+  if (lwe) *lwe = 4 * lwe_words(c);
+  return ok();
+}
+
+static uint32_t ceil_log2(uint32_t l) {
+  uint32_t L = 0;
+  while ((1u << L) < l) ++L;
+  return L;
+}
+
+struct Dims {
+  uint32_t L, k0, k1, z;
+};
+
+static hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d) {
+  if (!sh) return fail(HW_EINVAL, "null shape");
+  if (sh->reserved) return fail(HW_EINVAL, "shape.reserved must be 0");
+  if (sh->s < 1 || sh->s > (1u << 24)) return fail(HW_EINVAL, "s = %u out of range [1, 2^24]", sh->s);
+  if (sh->l < 1 || sh->l > 256) return fail(HW_EINVAL, "l = %u out of range [1, 256]", sh->l);
+  if (sh->a < 1 || sh->a > 20) return fail(HW_EINVAL, "a = %u out of range [1, 20]", sh->a);
+  d->L = ceil_log2(sh->l);
+  d->k0 = (sh->s + sh->a - 1) / sh->a;
+  const uint32_t nb = d->L + sh->a;
+  const uint32_t nr = nb < (uint32_t)c->logN ? nb : (uint32_t)c->logN;
+  d->z = nb - nr;
+  d->k1 = 1u << d->z;
+  return HW_OK;
+}
+
+extern "C" hw_status hw_wisard_dims(const hw_ctx* c, const hw_wisard_shape* sh, uint32_t* k0, uint32_t* k1,
+                                    uint64_t* model_bytes) {
+  if (!c) return fail(HW_EINVAL, "null context");
+  Dims d;
+  hw_status st = check_shape(c, sh, &d);
+  if (st) return st;
+  if (k0) *k0 = d.k0;
+  if (k1) *k1 = d.k1;
+  if (model_bytes) *model_bytes = (uint64_t)d.k0 * d.k1 * 4 * rlwe_words(c);
+  return ok();
+}
+
+static void make_perm(uint32_t s, uint64_t seed, uint32_t* pi) {
+  for (uint32_t k = 0; k < s; ++k) pi[k] = k;
+  for (int64_t k = (int64_t)s - 1; k >= 1; --k) {
+    const uint64_t j = draw64(seed, 2u, (uint64_t)((int64_t)s - 1 - k)) % (uint64_t)(k + 1);
+    std::swap(pi[k], pi[j]);
+  }
+}
+
+extern "C" hw_status hw_permutation(const hw_wisard_shape* sh, uint32_t* perm_host) {
+  if (!sh || !perm_host) return fail(HW_EINVAL, "null argument");
+  if (sh->s < 1 || sh->s > (1u << 24)) return fail(HW_EINVAL, "s out of range");
+  make_perm(sh->s, sh->perm_seed, perm_host);
+  return ok();
+}
+
+static hw_status ensure_ws(hw_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return HW_OK;
+  if (c->d_ws) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(c->d_ws));
+    c->d_ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  HIP_TRY(hipMalloc(&c->d_ws, bytes));
+  c->ws_bytes = bytes;
+  return HW_OK;
+}
+
+static hw_status ensure_perm(hw_ctx* c, const hw_wisard_shape* sh, hipStream_t st) {
+  if (c->perm_valid && c->perm_s == sh->s && c->perm_seed == sh->perm_seed) return HW_OK;
+  if (c->d_perm) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(c->d_perm));
+    c->d_perm = nullptr;
+  }
+  c->perm_valid = false;
+  c->h_perm.resize(sh->s);
+  make_perm(sh->s, sh->perm_seed, c->h_perm.data());
+  HIP_TRY(hipMalloc(&c->d_perm, sizeof(uint32_t) * sh->s));
+  HIP_TRY(hipMemcpyAsync(c->d_perm, c->h_perm.data(), sizeof(uint32_t) * sh->s, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  c->perm_s = sh->s;
+  c->perm_seed = sh->perm_seed;
+  c->perm_valid = true;
+  return HW_OK;
+}
+
+static hw_status enter(hw_ctx* c) {
+  if (!c) return fail(HW_EINVAL, "null context");
+  HIP_TRY(hipSetDevice(c->device));
+  return HW_OK;
+}
+
+#define CHECK(expr)            \
+  do {                         \
+    hw_status s_ = (expr);     \
+    if (s_ != HW_OK) return s_; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// client side
+// ---------------------------------------------------------------------------
+
+extern "C" hw_status hw_keygen(hw_ctx* c, uint64_t seed, int32_t* sk, hipStream_t st) {
+  CHECK(enter(c));
+  if (!sk) return fail(HW_EINVAL, "null key buffer");
+  HIP_TRY(hw::launch_keygen(c->prm.N, seed, sk, st));
+  return ok();
+}
+
+static hw_status sk_hat(hw_ctx* c, const int32_t* sk, hipStream_t st) {
+  if (!sk) return fail(HW_EINVAL, "null key");
+  HIP_TRY(hw::launch_sk_hat(c->logN, c->prm.nq, c->tabs, sk, c->d_skhat, st));
+  return HW_OK;
+}
+
+extern "C" hw_status hw_encrypt_rgsw_bits(hw_ctx* c, const int32_t* sk, const uint8_t* bits, uint64_t nbits,
+                                          uint64_t seed, uint64_t ct0, uint32_t* out, hipStream_t st) {
+  CHECK(enter(c));
+  if (nbits == 0) return ok();
+  if (!bits || !out) return fail(HW_EINVAL, "null buffer");
+  CHECK(sk_hat(c, sk, st));
+  hw::EncArgs A{};
+  A.sk = sk;
+  A.sk_hat = c->d_skhat;
+  A.bits = bits;
+  A.out = out;
+  A.seed = seed;
+  A.ct0 = ct0;
+  A.log_base = c->prm.log_base;
+  HIP_TRY(hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, nbits, st));
+  return ok();
+}
+
+extern "C" hw_status hw_encrypt_rlwe(hw_ctx* c, const int32_t* sk, const uint64_t* msg, uint64_t count,
+                                     uint64_t seed, uint64_t ct0, uint32_t* out, hipStream_t st) {
+  CHECK(enter(c));
+  if (count == 0) return ok();
+  if (!out) return fail(HW_EINVAL, "null output");
+  CHECK(sk_hat(c, sk, st));
+  hw::EncArgs A{};
+  A.sk = sk;
+  A.sk_hat = c->d_skhat;
+  A.msg = msg;
+  A.out = out;
+  A.seed = seed;
+  A.ct0 = ct0;
+  A.log_base = c->prm.log_base;
+  HIP_TRY(hw::launch_enc_rlwe(c->logN, c->prm.nq, c->tabs, c->cdt, A, count, st));
+  return ok();
+}
+
+extern "C" hw_status hw_decrypt_rlwe(hw_ctx* c, const int32_t* sk, const uint32_t* ct, uint64_t count,
+                                     uint64_t* msg, hipStream_t st) {
+  CHECK(enter(c));
+  if (count == 0) return ok();
+  if (!ct || !msg) return fail(HW_EINVAL, "null buffer");
+  CHECK(sk_hat(c, sk, st));
+  HIP_TRY(hw::launch_dec_rlwe(c->logN, c->prm.nq, c->tabs, c->crt, c->d_skhat, ct, count, msg, st));
+  return ok();
+}
+
+extern "C" hw_status hw_decrypt_lwe(hw_ctx* c, const int32_t* sk, const uint32_t* lwe, uint64_t count,
+                                    uint64_t* msg, hipStream_t st) {
+  CHECK(enter(c));
+  if (count == 0) return ok();
+  if (!sk || !lwe || !msg) return fail(HW_EINVAL, "null buffer");
+  HIP_TRY(hw::launch_dec_lwe(c->logN, c->prm.nq, c->tabs, c->crt, sk, lwe, count, msg, st));
+  return ok();
+}
+
+extern "C" hw_status hw_rgsw_export_canonical(hw_ctx* c, const uint32_t* rgsw, uint64_t count, uint32_t* out,
+                                              hipStream_t st) {
+  CHECK(enter(c));
+  if (count == 0) return ok();
+  if (!rgsw || !out) return fail(HW_EINVAL, "null buffer");
+  if (rgsw == out) return fail(HW_EINVAL, "output must not alias input");
+  HIP_TRY(hw::launch_rgsw_export(c->logN, c->prm.nq, c->tabs, rgsw, count, out, st));
+  return ok();
+}
+
+extern "C" hw_status hw_ntt(hw_ctx* c, uint32_t* polys, uint64_t count, int inverse, hipStream_t st) {
+  CHECK(enter(c));
+  if (count == 0) return ok();
+  if (!polys) return fail(HW_EINVAL, "null buffer");
+  if (inverse != 0 && inverse != 1) return fail(HW_EINVAL, "inverse must be 0 or 1");
+  HIP_TRY(hw::launch_ntt(c->logN, c->prm.nq, c->tabs, polys, count, inverse, st));
+  return ok();
+}
+
+extern "C" hw_status hw_external_product(hw_ctx* c, const uint32_t* rgsw, const uint32_t* in, uint64_t count,
+                                         uint32_t* out, hipStream_t st) {
+  CHECK(enter(c));
+  if (count == 0) return ok();
+  if (!rgsw || !in || !out) return fail(HW_EINVAL, "null buffer");
+  if (in == out) return fail(HW_EINVAL, "output must not alias input");
+  HIP_TRY(hw::launch_xp(c->logN, c->prm.nq, c->tabs, rgsw, in, count, out, st));
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// server side
+// ---------------------------------------------------------------------------
+
+extern "C" hw_status hw_wisard_train_encrypted(hw_ctx* c, const hw_wisard_shape* sh, const uint32_t* x_rgsw,
+                                               const uint32_t* y_rgsw, uint64_t n, uint32_t* model,
+                                               uint32_t* class_count, hipStream_t st) {
+  CHECK(enter(c));
+  Dims d;
+  CHECK(check_shape(c, sh, &d));
+  if (n == 0) return ok();
+  if (!x_rgsw || !model) return fail(HW_EINVAL, "null buffer");
+  if (d.L > 0 && !y_rgsw) return fail(HW_EINVAL, "null label ciphertexts");
+  const size_t rw = rlwe_words(c);
+  const size_t per_sample = (size_t)(d.k0 + 1) * (d.k1 + 1) * rw * 4;  // k1 outputs + input slot
+  uint64_t n_sub = c->ws_budget / per_sample;
+  if (n_sub < 1) n_sub = 1;
+  if (n_sub > n) n_sub = n;
+  if (n_sub > 65535) n_sub = 65535;
+  CHECK(ensure_ws(c, n_sub * per_sample));
+  CHECK(ensure_perm(c, sh, st));
+  hw::TrainArgs A{};
+  A.x_rgsw = x_rgsw;
+  A.y_rgsw = y_rgsw;
+  A.perm = c->d_perm;
+  A.out = static_cast<uint32_t*>(c->d_ws);
+  A.rgsw_words = rgsw_words(c);
+  A.s = sh->s;
+  A.a = sh->a;
+  A.L = d.L;
+  A.k0 = d.k0;
+  A.k1 = d.k1;
+  hw::ReduceArgs R{};
+  R.out = A.out;
+  R.model = model;
+  R.cnt = class_count;
+  R.s = sh->s;
+  R.a = sh->a;
+  R.L = d.L;
+  R.k0 = d.k0;
+  R.k1 = d.k1;
+  R.logN = c->logN;
+  R.N = c->prm.N;
+  R.nq = c->prm.nq;
+  const uint32_t nram = d.k0 + (class_count ? 1 : 0);
+  for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
+    const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
+    A.i0 = i0;
+    HIP_TRY(hw::launch_train(c->logN, c->prm.nq, c->tabs, A, nram, (uint32_t)m, st));
+    R.n_sub = m;
+    HIP_TRY(hw::launch_reduce_model(c->tabs, R, st));
+  }
+  return ok();
+}
+
+extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape* sh, const uint32_t* model,
+                                               const uint32_t* x_rgsw, uint64_t n, uint32_t* ram_scores,
+                                               uint32_t* class_scores, hipStream_t st) {
+  CHECK(enter(c));
+  Dims d;
+  CHECK(check_shape(c, sh, &d));
+  if (n == 0) return ok();
+  if (!model || !x_rgsw || !ram_scores) return fail(HW_EINVAL, "null buffer");
+  const size_t rw = rlwe_words(c);
+  const uint32_t slots = d.z > d.L + 1 ? (1u << (d.z - d.L - 1)) : 1u;
+  const size_t per_sample = (size_t)sh->l * d.k0 * (slots + 1) * rw * 4;  // + input slot
+  uint64_t n_sub = c->ws_budget / per_sample;
+  if (n_sub < 1) n_sub = 1;
+  if (n_sub > n) n_sub = n;
+  if (n_sub > 65535) n_sub = 65535;
+  CHECK(ensure_ws(c, n_sub * per_sample));
+  CHECK(ensure_perm(c, sh, st));
+  hw::InferArgs A{};
+  A.model = model;
+  A.x_rgsw = x_rgsw;
+  A.perm = c->d_perm;
+  A.scores = ram_scores;
+  A.scratch = static_cast<uint32_t*>(c->d_ws);
+  A.rgsw_words = rgsw_words(c);
+  A.s = sh->s;
+  A.a = sh->a;
+  A.L = d.L;
+  A.l = sh->l;
+  A.k0 = d.k0;
+  A.k1 = d.k1;
+  A.slots = slots;
+  for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
+    const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
+    A.i0 = i0;
+    HIP_TRY(hw::launch_infer(c->logN, c->prm.nq, c->tabs, A, (uint32_t)m, st));
+  }
+  if (class_scores) {
+    hw::SumArgs S{};
+    S.scores = ram_scores;
+    S.sums = class_scores;
+    S.n = n;
+    S.l = sh->l;
+    S.k0 = d.k0;
+    S.N = c->prm.N;
+    S.nq = c->prm.nq;
+    HIP_TRY(hw::launch_class_sums(c->tabs, S, st));
+  }
+  return ok();
+}

@@ -1,0 +1,477 @@
+// hw_device.h -- device building blocks for gfx950: modular arithmetic on
+// 32-bit lanes, the workgroup-wide negacyclic NTT and the fused external
+// product (decompose -> NTT -> multiply-accumulate -> inverse NTT).
+//
+// Ring R_q = Z_q[X]/(X^N+1) (Sec. 2.1); external product of Sec. 2.4.1 with
+// an RNS gadget of base 2^6 and 5 digits per prime.
+//
+// Thread mapping.  One workgroup of T = N/8 threads owns one polynomial at a
+// time; each thread keeps 8 coefficients in registers.  The NTT's log2 N
+// stages are split into four phases of at most three stages; inside a phase
+// every butterfly is thread-local (radix-8 on registers), and between phases
+// the coefficients are exchanged through LDS.  In phase P a thread holds the
+// 8 elements whose indices differ only in three consecutive bits:
+//   P=0 (natural layout): k = t + T e
+//   P=1: bits N/8..N/64 vary, P=2: bits N/512..N/4096 vary
+//   P=3: k = 8t + e (the evaluation-domain layout used for all pointwise work)
+// The LDS index k + 4*(k>>5) keeps every exchange free of bank conflicts.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hw {
+
+// ---------------------------------------------------------------------------
+// per-prime constants and tables
+// ---------------------------------------------------------------------------
+
+struct PrimeTab {
+  uint32_t q, two_q;
+  uint32_t ninv, ninv_sh;   // N^{-1} mod q and its Shoup companion
+  uint32_t r32, r32_sh;     // 2^32 mod q and companion
+  uint32_t one_sh;          // floor(2^32 / q): Shoup companion of 1
+  uint32_t delta;           // Delta mod q
+};
+
+constexpr int MAXQ = 3;
+
+struct Tabs {
+  PrimeTab pt[MAXQ];
+  const uint2* fwd[MAXQ];   // [N]: (psi^{brv(k)}, Shoup companion), k >= 1
+  const uint2* inv[MAXQ];   // [N]: (psi^{-brv(k)}, Shoup companion)
+};
+
+// ---------------------------------------------------------------------------
+// modular arithmetic (q < 2^30, lazily reduced values below 4q < 2^32)
+// ---------------------------------------------------------------------------
+
+// x * w mod q in [0, 2q) for any 32-bit x (Shoup's method, w < q)
+__device__ __forceinline__ uint32_t mulsh(uint32_t x, uint32_t w, uint32_t wsh, uint32_t q) {
+  const uint32_t qh = __umulhi(x, wsh);
+  return x * w - qh * q;
+}
+
+// [0, 2m) -> [0, m) for m < 2^31: min(x, x - m) picks x - m exactly when x >= m
+__device__ __forceinline__ uint32_t csub(uint32_t x, uint32_t m) { return min(x, x - m); }
+
+__device__ __forceinline__ uint32_t addq(uint32_t a, uint32_t b, uint32_t q) { return csub(a + b, q); }
+__device__ __forceinline__ uint32_t subq(uint32_t a, uint32_t b, uint32_t q) { return csub(a + q - b, q); }
+
+// 64-bit value -> [0, q)
+__device__ __forceinline__ uint32_t red64(uint64_t v, const PrimeTab& P) {
+  const uint32_t hi = (uint32_t)(v >> 32), lo = (uint32_t)v;
+  uint32_t r = mulsh(hi, P.r32, P.r32_sh, P.q) + mulsh(lo, 1u, P.one_sh, P.q);  // [0, 4q)
+  return csub(csub(r, P.two_q), P.q);
+}
+
+// data x data product mod q, both in [0, q)
+__device__ __forceinline__ uint32_t mulq(uint32_t a, uint32_t b, const PrimeTab& P) {
+  return red64((uint64_t)a * b, P);
+}
+
+// Harvey butterflies: forward (Cooley-Tukey) on [0, 4q), inverse
+// (Gentleman-Sande) on [0, 2q).
+__device__ __forceinline__ void bf_fwd(uint32_t& X, uint32_t& Y, uint32_t w, uint32_t wsh, uint32_t q,
+                                       uint32_t two_q) {
+  const uint32_t x = csub(X, two_q);
+  const uint32_t t = mulsh(Y, w, wsh, q);
+  X = x + t;
+  Y = x - t + two_q;
+}
+
+__device__ __forceinline__ void bf_inv(uint32_t& X, uint32_t& Y, uint32_t w, uint32_t wsh, uint32_t q,
+                                       uint32_t two_q) {
+  const uint32_t x = X, y = Y;
+  X = csub(x + y, two_q);
+  Y = mulsh(x - y + two_q, w, wsh, q);
+}
+
+// ---------------------------------------------------------------------------
+// layouts
+// ---------------------------------------------------------------------------
+
+template <int LOGN>
+struct Geo {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int T = N / 8;            // threads per polynomial
+  static constexpr int R = LOGN - 9;         // stages in the last phase (1..3)
+  static constexpr int LDSW = N + N / 8;     // padded words of one exchange buffer
+  static_assert(LOGN >= 10 && LOGN <= 12, "N must be 1024, 2048 or 4096");
+};
+
+__host__ __device__ constexpr uint32_t lds_ix(uint32_t k) { return k + ((k >> 5) << 2); }
+
+// In layouts P = 0..2 the index of element e of thread t splits into two
+// disjoint bit fields, k = tpart(t) | (e << eshift), so its LDS index is
+// lds_ix(tpart) + lds_ix(e << eshift): one base register plus an immediate.
+template <int LOGN, int P>
+__host__ __device__ constexpr int eshift() {
+  return P == 0 ? LOGN - 3 : (P == 1 ? LOGN - 6 : LOGN - 9);
+}
+
+template <int LOGN, int P>
+__device__ __forceinline__ uint32_t tpart(uint32_t t) {
+  if constexpr (P == 0) {
+    return t;
+  } else {
+    constexpr int b = eshift<LOGN, P>();
+    return ((t >> b) << (b + 3)) | (t & ((1u << b) - 1));
+  }
+}
+
+template <int LOGN, int P>
+__device__ __forceinline__ uint32_t pos(uint32_t t, uint32_t e) {
+  if constexpr (P == 3) return (t << 3) | e;
+  else return tpart<LOGN, P>(t) | (e << eshift<LOGN, P>());
+}
+
+// Exchange through LDS from layout PF to layout PT.  Two buffers alternate
+// (selected by the running counter xc) so that one barrier per exchange
+// suffices: a buffer is written again only after the next exchange's barrier.
+template <int LOGN, int PF, int PT>
+__device__ __forceinline__ void xchg(uint32_t (&x)[8], uint32_t* lds, uint32_t& xc, uint32_t t) {
+  uint32_t* buf = lds + (xc & 1u) * Geo<LOGN>::LDSW;
+  ++xc;
+  if constexpr (PF == 3) {
+    uint4* p = reinterpret_cast<uint4*>(buf + lds_ix(t << 3));
+    p[0] = make_uint4(x[0], x[1], x[2], x[3]);
+    p[1] = make_uint4(x[4], x[5], x[6], x[7]);
+  } else {
+    uint32_t* b = buf + lds_ix(tpart<LOGN, PF>(t));
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b[lds_ix((uint32_t)e << eshift<LOGN, PF>())] = x[e];
+  }
+  __syncthreads();
+  if constexpr (PT == 3) {
+    const uint4* p = reinterpret_cast<const uint4*>(buf + lds_ix(t << 3));
+    const uint4 u = p[0], v = p[1];
+    x[0] = u.x; x[1] = u.y; x[2] = u.z; x[3] = u.w;
+    x[4] = v.x; x[5] = v.y; x[6] = v.z; x[7] = v.w;
+  } else {
+    const uint32_t* b = buf + lds_ix(tpart<LOGN, PT>(t));
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = b[lds_ix((uint32_t)e << eshift<LOGN, PT>())];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward NTT (natural layout in registers -> layout P=3)
+// ---------------------------------------------------------------------------
+// Stage s (0 <= s < log2 N) pairs elements at distance N >> (s+1); the pair
+// whose lower element has index k uses psi^{brv(2^s + (k >> (log2 N - s)))}.
+
+// Twiddles of phase 0 are uniform over the workgroup and read from the global
+// table (scalar loads); those of phases 1..3 are read from a copy of the
+// prime's table in LDS (`twl`, N entries), a few per phase.
+
+// copy the forward table of one prime into LDS (caller synchronises after)
+template <int LOGN>
+__device__ __forceinline__ void load_tw_lds(uint2* __restrict__ twl, const uint2* __restrict__ tab, uint32_t t) {
+  constexpr int TT = Geo<LOGN>::T;
+  const uint4* src = reinterpret_cast<const uint4*>(tab);
+  uint4* dst = reinterpret_cast<uint4*>(twl);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) (dst + TT * e)[t] = (src + TT * e)[t];
+}
+
+// three forward stages with twiddle (w, Shoup) pairs w0 | w1,w2 | w3..w6
+__device__ __forceinline__ void fwd8(uint32_t (&x)[8], const uint2 (&w)[7], uint32_t q, uint32_t two_q) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) bf_fwd(x[e], x[e + 4], w[0].x, w[0].y, q, two_q);
+  bf_fwd(x[0], x[2], w[1].x, w[1].y, q, two_q);
+  bf_fwd(x[1], x[3], w[1].x, w[1].y, q, two_q);
+  bf_fwd(x[4], x[6], w[2].x, w[2].y, q, two_q);
+  bf_fwd(x[5], x[7], w[2].x, w[2].y, q, two_q);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) bf_fwd(x[2 * e], x[2 * e + 1], w[3 + e].x, w[3 + e].y, q, two_q);
+}
+
+// the seven twiddles of a radix-8 phase whose stage s0 index base is b0:
+// 2^s0 + h, 2^{s0+1} + 2h + {0,1}, 2^{s0+2} + 4h + {0..3}
+__device__ __forceinline__ void tw_phase(uint2 (&w)[7], const uint2* __restrict__ twl, uint32_t s0, uint32_t h) {
+  w[0] = twl[(1u << s0) + h];
+  const uint4 v = *reinterpret_cast<const uint4*>(twl + (2u << s0) + 2 * h);
+  w[1] = make_uint2(v.x, v.y);
+  w[2] = make_uint2(v.z, v.w);
+  const uint4 u0 = *reinterpret_cast<const uint4*>(twl + (4u << s0) + 4 * h);
+  const uint4 u1 = *reinterpret_cast<const uint4*>(twl + (4u << s0) + 4 * h + 2);
+  w[3] = make_uint2(u0.x, u0.y);
+  w[4] = make_uint2(u0.z, u0.w);
+  w[5] = make_uint2(u1.x, u1.y);
+  w[6] = make_uint2(u1.z, u1.w);
+}
+
+// Output values are left in [0, 4q).
+template <int LOGN>
+__device__ __forceinline__ void ntt_fwd(uint32_t (&x)[8], const uint2* __restrict__ tab, const uint2* __restrict__ twl,
+                                        uint32_t q, uint32_t two_q, uint32_t* lds, uint32_t& xc, uint32_t t) {
+  constexpr int R = Geo<LOGN>::R;
+  {  // phase 0: stages 0..2, twiddles uniform over the workgroup
+    const uint2 w1 = tab[1], w2 = tab[2], w3 = tab[3], w4 = tab[4], w5 = tab[5], w6 = tab[6], w7 = tab[7];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bf_fwd(x[e], x[e + 4], w1.x, w1.y, q, two_q);
+    bf_fwd(x[0], x[2], w2.x, w2.y, q, two_q);
+    bf_fwd(x[1], x[3], w2.x, w2.y, q, two_q);
+    bf_fwd(x[4], x[6], w3.x, w3.y, q, two_q);
+    bf_fwd(x[5], x[7], w3.x, w3.y, q, two_q);
+    bf_fwd(x[0], x[1], w4.x, w4.y, q, two_q);
+    bf_fwd(x[2], x[3], w5.x, w5.y, q, two_q);
+    bf_fwd(x[4], x[5], w6.x, w6.y, q, two_q);
+    bf_fwd(x[6], x[7], w7.x, w7.y, q, two_q);
+  }
+  xchg<LOGN, 0, 1>(x, lds, xc, t);
+  {
+    uint2 w[7];
+    tw_phase(w, twl, 3, t >> (LOGN - 6));
+    fwd8(x, w, q, two_q);
+  }
+  xchg<LOGN, 1, 2>(x, lds, xc, t);
+  {
+    uint2 w[7];
+    tw_phase(w, twl, 6, t >> (LOGN - 9));
+    fwd8(x, w, q, two_q);
+  }
+  xchg<LOGN, 2, 3>(x, lds, xc, t);
+  if constexpr (R == 3) {
+    uint2 w[7];
+    tw_phase(w, twl, 9, t);
+    fwd8(x, w, q, two_q);
+  } else if constexpr (R == 2) {
+    const uint4 v = *reinterpret_cast<const uint4*>(twl + 512 + 2 * t);
+    bf_fwd(x[0], x[2], v.x, v.y, q, two_q);
+    bf_fwd(x[1], x[3], v.x, v.y, q, two_q);
+    bf_fwd(x[4], x[6], v.z, v.w, q, two_q);
+    bf_fwd(x[5], x[7], v.z, v.w, q, two_q);
+    const uint4 u0 = *reinterpret_cast<const uint4*>(twl + 1024 + 4 * t);
+    const uint4 u1 = *reinterpret_cast<const uint4*>(twl + 1024 + 4 * t + 2);
+    bf_fwd(x[0], x[1], u0.x, u0.y, q, two_q);
+    bf_fwd(x[2], x[3], u0.z, u0.w, q, two_q);
+    bf_fwd(x[4], x[5], u1.x, u1.y, q, two_q);
+    bf_fwd(x[6], x[7], u1.z, u1.w, q, two_q);
+  } else {
+    const uint4 u0 = *reinterpret_cast<const uint4*>(twl + 512 + 4 * t);
+    const uint4 u1 = *reinterpret_cast<const uint4*>(twl + 512 + 4 * t + 2);
+    bf_fwd(x[0], x[1], u0.x, u0.y, q, two_q);
+    bf_fwd(x[2], x[3], u0.z, u0.w, q, two_q);
+    bf_fwd(x[4], x[5], u1.x, u1.y, q, two_q);
+    bf_fwd(x[6], x[7], u1.z, u1.w, q, two_q);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inverse NTT (layout P=3 -> natural layout), input in [0, 2q), output [0, q)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void inv_bf(uint32_t& X, uint32_t& Y, const uint2* __restrict__ tab, uint32_t idx,
+                                       uint32_t q, uint32_t two_q) {
+  const uint2 w = tab[idx];
+  bf_inv(X, Y, w.x, w.y, q, two_q);
+}
+
+// three inverse stages (s0+2, s0+1, s0) of a phase whose index bits vary with e;
+// base(s) gives 2^s + (k >> (log2 N - s)) with the e-dependent part removed
+__device__ __forceinline__ void inv8(uint32_t (&x)[8], const uint2* __restrict__ tab, uint32_t i2,
+                                     uint32_t i1, uint32_t i0, uint32_t q, uint32_t two_q) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) inv_bf(x[2 * e], x[2 * e + 1], tab, i2 + e, q, two_q);
+  inv_bf(x[0], x[2], tab, i1, q, two_q);
+  inv_bf(x[1], x[3], tab, i1, q, two_q);
+  inv_bf(x[4], x[6], tab, i1 + 1, q, two_q);
+  inv_bf(x[5], x[7], tab, i1 + 1, q, two_q);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) inv_bf(x[e], x[e + 4], tab, i0, q, two_q);
+}
+
+template <int LOGN>
+__device__ __forceinline__ void ntt_inv(uint32_t (&x)[8], const uint2* __restrict__ tab, const PrimeTab& P,
+                                        uint32_t* lds, uint32_t& xc, uint32_t t) {
+  constexpr int R = Geo<LOGN>::R;
+  const uint32_t q = P.q, two_q = P.two_q;
+  if constexpr (R == 3) {
+    inv8(x, tab, 2048 + (t << 2), 1024 + (t << 1), 512 + t, q, two_q);
+  } else if constexpr (R == 2) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) inv_bf(x[2 * e], x[2 * e + 1], tab, 1024 + (t << 2) + e, q, two_q);
+    inv_bf(x[0], x[2], tab, 512 + (t << 1), q, two_q);
+    inv_bf(x[1], x[3], tab, 512 + (t << 1), q, two_q);
+    inv_bf(x[4], x[6], tab, 512 + (t << 1) + 1, q, two_q);
+    inv_bf(x[5], x[7], tab, 512 + (t << 1) + 1, q, two_q);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) inv_bf(x[2 * e], x[2 * e + 1], tab, 512 + (t << 2) + e, q, two_q);
+  }
+  xchg<LOGN, 3, 2>(x, lds, xc, t);
+  {
+    const uint32_t tc = t >> (LOGN - 9);
+    inv8(x, tab, 256 + (tc << 2), 128 + (tc << 1), 64 + tc, q, two_q);
+  }
+  xchg<LOGN, 2, 1>(x, lds, xc, t);
+  {
+    const uint32_t tb = t >> (LOGN - 6);
+    inv8(x, tab, 32 + (tb << 2), 16 + (tb << 1), 8 + tb, q, two_q);
+  }
+  xchg<LOGN, 1, 0>(x, lds, xc, t);
+  inv8(x, tab, 4, 2, 1, q, two_q);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) x[e] = csub(mulsh(x[e], P.ninv, P.ninv_sh, q), q);
+}
+
+// reduce forward-NTT output [0, 4q) -> [0, q)
+__device__ __forceinline__ uint32_t red4q(uint32_t x, uint32_t q, uint32_t two_q) {
+  return csub(csub(x, two_q), q);
+}
+
+// ---------------------------------------------------------------------------
+// fused external product
+// ---------------------------------------------------------------------------
+// xin: the input RLWE [poly a=0,b=1][prime][N] in global memory; thread t
+// reads only its own coefficients t + T e, so no synchronisation is needed
+// between whoever wrote them (the same thread) and the transform.
+// C: one RGSW in device layout [row 2D][poly 2][prime NQ][N] (evaluation
+// domain, layout P=3).  For every output prime ip the 2D digit polynomials
+// (the digits of b against rows 0..D-1, then those of a against rows
+// D..2D-1) are transformed and multiplied into 64-bit accumulators; the two
+// accumulators are brought back by the inverse NTT and handed to
+// epi(ip, ha, hb) in the natural layout, values in [0, q).
+// twl: LDS space for one prime's forward table (N uint2).  Outputs may alias
+// xin only as dst == src (each thread reads then writes its own coefficient).
+
+// What happens to h = C [.] xin, per output prime, coefficient k (natural):
+//   XP_STORE : dst[k] = h
+//   XP_ADD   : dst[k] = src[k] + h            (CMUX: d0 + C [.] (d1 - d0))
+//   XP_DEMUX : dst[k] = src[k] - h, dst2[k] = h (CDEMUX)
+enum XpMode : int { XP_STORE = 0, XP_ADD = 1, XP_DEMUX = 2 };
+
+struct XpOut {
+  uint32_t* dst;
+  const uint32_t* src;
+  uint32_t* dst2;
+  int mode;
+};
+
+template <int LOGN, int NQ>
+__device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const uint32_t* __restrict__ C,
+                                      const Tabs& T, uint32_t* lds, uint2* twl, uint32_t& xc, uint32_t t,
+                                      XpOut out) {
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  constexpr int D = 5 * NQ;
+  constexpr size_t ROW = (size_t)2 * NQ * N;
+#pragma unroll 1
+  for (int ip = 0; ip < NQ; ++ip) {
+    const PrimeTab P = T.pt[ip];
+    load_tw_lds<LOGN>(twl, T.fwd[ip], t);
+    __syncthreads();
+    uint64_t acc_a[8], acc_b[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc_a[e] = acc_b[e] = 0;
+    int cnt = 0;
+#pragma unroll 1
+    for (int g = 0; g < 2 * NQ; ++g) {  // g = side * NQ + i
+      const int side = g / NQ, i = g - side * NQ;
+      const int p = side == 0 ? 1 : 0;
+      const uint32_t qi = T.pt[i].q;
+      const uint32_t* src = xin + ((size_t)p * NQ + i) * N;
+      int32_t v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t r = (src + TT * e)[t];
+        v[e] = r > (qi - 1) / 2 ? (int32_t)(r - qi) : (int32_t)r;
+      }
+#pragma unroll 1
+      for (int j = 0; j < 5; ++j) {
+        const uint4* cra = reinterpret_cast<const uint4*>(C + (size_t)(side * D + i * 5 + j) * ROW + (size_t)ip * N);
+        const uint4* crb = cra + (size_t)NQ * N / 4;
+        const uint4 ca0 = cra[2 * t], ca1 = cra[2 * t + 1];
+        const uint4 cb0 = crb[2 * t], cb1 = crb[2 * t + 1];
+        uint32_t x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          int32_t d;
+          if (j < 4) {
+            d = ((v[e] + 32) & 63) - 32;
+            v[e] = (v[e] - d) >> 6;
+          } else {
+            d = v[e];
+          }
+          x[e] = d < 0 ? (uint32_t)(d + (int32_t)P.q) : (uint32_t)d;
+        }
+        ntt_fwd<LOGN>(x, T.fwd[ip], twl, P.q, P.two_q, lds, xc, t);
+        const uint32_t ca[8] = {ca0.x, ca0.y, ca0.z, ca0.w, ca1.x, ca1.y, ca1.z, ca1.w};
+        const uint32_t cb[8] = {cb0.x, cb0.y, cb0.z, cb0.w, cb1.x, cb1.y, cb1.z, cb1.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t xr = red4q(x[e], P.q, P.two_q);
+          acc_a[e] += (uint64_t)xr * ca[e];
+          acc_b[e] += (uint64_t)xr * cb[e];
+        }
+        if (++cnt == 15) {
+          cnt = 0;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            acc_a[e] = red64(acc_a[e], P);
+            acc_b[e] = red64(acc_b[e], P);
+          }
+        }
+      }
+    }
+    uint32_t ha[8], hb[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      ha[e] = red64(acc_a[e], P);
+      hb[e] = red64(acc_b[e], P);
+    }
+    ntt_inv<LOGN>(ha, T.inv[ip], P, lds, xc, t);
+    ntt_inv<LOGN>(hb, T.inv[ip], P, lds, xc, t);
+    const size_t oa = (size_t)ip * N, ob = (size_t)(NQ + ip) * N;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const size_t ea = oa + TT * e, eb = ob + TT * e;
+      if (out.mode == XP_STORE) {
+        (out.dst + ea)[t] = ha[e];
+        (out.dst + eb)[t] = hb[e];
+      } else if (out.mode == XP_ADD) {
+        (out.dst + ea)[t] = addq((out.src + ea)[t], ha[e], P.q);
+        (out.dst + eb)[t] = addq((out.src + eb)[t], hb[e], P.q);
+      } else {
+        (out.dst + ea)[t] = subq((out.src + ea)[t], ha[e], P.q);
+        (out.dst + eb)[t] = subq((out.src + eb)[t], hb[e], P.q);
+        (out.dst2 + ea)[t] = ha[e];
+        (out.dst2 + eb)[t] = hb[e];
+      }
+    }
+  }
+}
+
+// LDS needed by a kernel that runs ext_prod: two exchange buffers + one table
+template <int LOGN>
+struct XpLds {
+  static constexpr int WORDS = 2 * Geo<LOGN>::LDSW + 2 * (1 << LOGN);
+};
+
+// ---------------------------------------------------------------------------
+// RLWE slots in global memory, natural layout
+// ---------------------------------------------------------------------------
+
+template <int LOGN, int NQ>
+__device__ __forceinline__ void load_rlwe(uint32_t (&r)[2][NQ][8], const uint32_t* __restrict__ src, uint32_t t) {
+  constexpr int N = 1 << LOGN, TT = N / 8;
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int i = 0; i < NQ; ++i)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) r[p][i][e] = src[((size_t)p * NQ + i) * N + t + TT * e];
+}
+
+// coefficient k of X^e * f (e in (-2N, 2N)), polynomial f of one prime
+template <int LOGN>
+__device__ __forceinline__ uint32_t rot_coef(const uint32_t* __restrict__ f, int32_t k, int32_t e, uint32_t q) {
+  constexpr int32_t N = 1 << LOGN;
+  int32_t u = k - e;
+  u = (u % (2 * N) + 2 * N) % (2 * N);
+  if (u < N) return f[u];
+  const uint32_t v = f[u - N];
+  return v ? q - v : 0u;
+}
+
+}  // namespace hw

@@ -1,0 +1,93 @@
+// hw_internal.h -- argument blocks shared by the host API and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hw_device.h"
+
+namespace hw {
+
+// CRT constants for decryption: phi = sum_i [phi_i * inv_i]_{q_i} * M_i mod Q
+struct CrtTab {
+  uint64_t Q_lo, Q_hi;          // Q = prod q_i
+  uint64_t M_lo[MAXQ], M_hi[MAXQ];  // M_i = Q / q_i
+  uint32_t inv[MAXQ];           // (Q/q_i)^{-1} mod q_i
+  uint64_t half_lo, half_hi;    // floor(Q / 2)
+  uint64_t p;                   // plaintext modulus (power of two)
+};
+
+struct Cdt {
+  uint64_t T[42];
+};
+
+struct EncArgs {
+  const int32_t* sk;        // [N]
+  const uint32_t* sk_hat;   // [NQ][N] evaluation domain (layout P=3)
+  const uint8_t* bits;      // RGSW: one bit per ciphertext
+  const uint64_t* msg;      // RLWE: [count][N] or nullptr
+  uint32_t* out;
+  uint64_t seed;
+  uint64_t ct0;             // ciphertext index of the first output
+  uint32_t log_base;
+};
+
+struct TrainArgs {
+  const uint32_t* x_rgsw;   // [n][s] RGSW
+  const uint32_t* y_rgsw;   // [n][L] RGSW
+  const uint32_t* perm;     // [s]
+  uint32_t* out;            // [n_sub][k0 + 1][k1] RLWE (per-sample IVP outputs)
+  uint64_t rgsw_words;
+  uint64_t i0;              // first sample of the sub-batch
+  uint32_t s, a, L, k0, k1;
+};
+
+struct ReduceArgs {
+  const uint32_t* out;      // as TrainArgs::out
+  uint32_t* model;          // [k0][k1] RLWE
+  uint32_t* cnt;            // one RLWE or nullptr
+  uint64_t n_sub;
+  uint32_t s, a, L, k0, k1, logN, N, nq;
+};
+
+struct InferArgs {
+  const uint32_t* model;    // [k0][k1] RLWE
+  const uint32_t* x_rgsw;   // [n][s] RGSW
+  const uint32_t* perm;     // [s]
+  uint32_t* scores;         // [n][l][k0] LWE
+  uint32_t* scratch;        // [n_sub][l][k0][slots] RLWE
+  uint64_t rgsw_words;
+  uint64_t i0;
+  uint32_t s, a, L, l, k0, k1, slots;
+};
+
+struct SumArgs {
+  const uint32_t* scores;   // [n][l][k0] LWE
+  uint32_t* sums;           // [n][l] LWE
+  uint64_t n;
+  uint32_t l, k0, N, nq;
+};
+
+// launchers (hw_kernels.hip); return hipSuccess or the launch error
+hipError_t launch_keygen(uint32_t N, uint64_t seed, int32_t* sk, hipStream_t st);
+hipError_t launch_sk_hat(int logN, int nq, const Tabs& T, const int32_t* sk, uint32_t* sk_hat, hipStream_t st);
+hipError_t launch_enc_rgsw(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
+                           hipStream_t st);
+hipError_t launch_enc_rlwe(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
+                           hipStream_t st);
+hipError_t launch_dec_rlwe(int logN, int nq, const Tabs& T, const CrtTab& K, const uint32_t* sk_hat,
+                           const uint32_t* ct, uint64_t count, uint64_t* msg, hipStream_t st);
+hipError_t launch_dec_lwe(int logN, int nq, const Tabs& T, const CrtTab& K, const int32_t* sk,
+                          const uint32_t* lwe, uint64_t count, uint64_t* msg, hipStream_t st);
+hipError_t launch_rgsw_export(int logN, int nq, const Tabs& T, const uint32_t* rgsw, uint64_t count,
+                              uint32_t* out, hipStream_t st);
+hipError_t launch_ntt(int logN, int nq, const Tabs& T, uint32_t* polys, uint64_t count, int inverse,
+                      hipStream_t st);
+hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, const uint32_t* in, uint64_t count,
+                     uint32_t* out, hipStream_t st);
+hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, uint32_t nram, uint32_t n_sub,
+                        hipStream_t st);
+hipError_t launch_reduce_model(const Tabs& T, const ReduceArgs& A, hipStream_t st);
+hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, uint32_t n_sub, hipStream_t st);
+hipError_t launch_class_sums(const Tabs& T, const SumArgs& A, hipStream_t st);
+
+}  // namespace hw

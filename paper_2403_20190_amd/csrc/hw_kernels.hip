@@ -1,0 +1,808 @@
+// hw_kernels.hip -- HIP kernels for gfx950 of the encrypted WiSARD hot path
+// and their launchers.  Template parameters: LOGN = log2 N (10..12), NQ =
+// number of primes (1..3); one workgroup of N/8 threads per polynomial job.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hw_device.h"
+#include "hw_internal.h"
+
+namespace hw {
+
+typedef unsigned __int128 u128;
+
+// Occupancy target of the external-product kernels (waves per SIMD): lets the
+// compiler rematerialise loop-invariant addresses instead of keeping them live.
+#ifndef WAVES_XP
+#define WAVES_XP 3
+#endif
+
+// ---------------------------------------------------------------------------
+// counter-based generator: Philox4x32-10 (Salmon et al., SC'11)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+// the two 64-bit draws 2*blk and 2*blk+1 of stream (seed, domain)
+__device__ __forceinline__ void draw_pair(uint64_t seed, uint32_t domain, uint64_t blk, uint64_t& d0,
+                                          uint64_t& d1) {
+  const uint4 o = philox10(make_uint4((uint32_t)blk, (uint32_t)(blk >> 32), domain, 0u), (uint32_t)seed,
+                           (uint32_t)(seed >> 32));
+  d0 = (uint64_t)o.x | ((uint64_t)o.y << 32);
+  d1 = (uint64_t)o.z | ((uint64_t)o.w << 32);
+}
+
+constexpr uint32_t DOM_KEY = 1, DOM_ENC_A = 3, DOM_ENC_E = 4;
+
+__device__ __forceinline__ int32_t cdt_sample(const uint64_t* T, uint64_t w) {
+  const uint64_t r = w >> 1;
+  int lo = 0, hi = 41;  // smallest k with r < T[k]; T[41] = 2^63 > r
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (r < T[mid]) hi = mid; else lo = mid + 1;
+  }
+  return (lo != 0 && (w & 1)) ? -lo : lo;
+}
+
+// ---------------------------------------------------------------------------
+// keys
+// ---------------------------------------------------------------------------
+
+__global__ void k_keygen(uint32_t N, uint64_t seed, int32_t* sk) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= N) return;
+  uint64_t d0, d1;
+  draw_pair(seed, DOM_KEY, k >> 1, d0, d1);
+  const uint64_t w = (k & 1) ? d1 : d0;
+  sk[k] = (int32_t)(w % 3) - 1;
+}
+
+// sk_hat[i] = NTT(s mod q_i), evaluation layout
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_sk_hat(Tabs T, const int32_t* __restrict__ sk,
+                                                          uint32_t* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  const uint32_t t = threadIdx.x, i = blockIdx.x;
+  const PrimeTab P = T.pt[i];
+  uint32_t x[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int32_t v = sk[t + TT * e];
+    x[e] = v < 0 ? (uint32_t)(v + (int32_t)P.q) : (uint32_t)v;
+  }
+  load_tw_lds<LOGN>(twl, T.fwd[i], t);
+  __syncthreads();
+  uint32_t xc = 0;
+  ntt_fwd<LOGN>(x, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
+  uint4* o = reinterpret_cast<uint4*>(out + (size_t)i * N + (t << 3));
+  o[0] = make_uint4(red4q(x[0], P.q, P.two_q), red4q(x[1], P.q, P.two_q), red4q(x[2], P.q, P.two_q),
+                    red4q(x[3], P.q, P.two_q));
+  o[1] = make_uint4(red4q(x[4], P.q, P.two_q), red4q(x[5], P.q, P.two_q), red4q(x[6], P.q, P.two_q),
+                    red4q(x[7], P.q, P.two_q));
+}
+
+// ---------------------------------------------------------------------------
+// encryption
+// ---------------------------------------------------------------------------
+// Draws of row `rid` (= ciphertext * rows + row): a_{i,k} is draw
+// (rid*NQ + i)*N + k of stream ENC_A reduced mod q_i; e_k is the CDT sample of
+// draw rid*N + k of stream ENC_E.  Threads generate pairs of draws and stage
+// them through LDS into the natural layout.
+
+template <int LOGN>
+__device__ __forceinline__ void gen_uniform(uint64_t seed, uint64_t base_blk, const PrimeTab& P,
+                                            uint32_t* __restrict__ stage, uint32_t t, uint32_t (&x)[8]) {
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const uint32_t b = t + TT * f;
+    uint64_t d0, d1;
+    draw_pair(seed, DOM_ENC_A, base_blk + b, d0, d1);
+    *reinterpret_cast<uint2*>(stage + 2 * b) = make_uint2(red64(d0, P), red64(d1, P));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 8; ++e) x[e] = stage[t + TT * e];
+}
+
+template <int LOGN>
+__device__ __forceinline__ void gen_gauss(uint64_t seed, uint64_t base_blk, const uint64_t* cdt,
+                                          uint32_t* __restrict__ stage, uint32_t t, int32_t (&ev)[8]) {
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const uint32_t b = t + TT * f;
+    uint64_t d0, d1;
+    draw_pair(seed, DOM_ENC_E, base_blk + b, d0, d1);
+    *reinterpret_cast<int2*>(stage + 2 * b) = make_int2(cdt_sample(cdt, d0), cdt_sample(cdt, d1));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 8; ++e) ev[e] = (int32_t)stage[t + TT * e];
+}
+
+// RGSW rows directly in the evaluation domain: a_hat = NTT(a),
+// b_hat = a_hat * s_hat + NTT(e); the gadget constant m*base^j is added to
+// every evaluation point (the transform of a constant polynomial is constant).
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncArgs A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  __shared__ __attribute__((aligned(16))) uint32_t stage[1 << LOGN];
+  __shared__ uint64_t tab[42];
+  constexpr int N = 1 << LOGN, D = 5 * NQ, ROWS = 2 * D;
+  const uint32_t t = threadIdx.x, r = blockIdx.x;
+  const uint64_t c = blockIdx.y + (uint64_t)blockIdx.z * gridDim.y;
+  if (t < 42) tab[t] = cdt.T[t];
+  const uint64_t ct = A.ct0 + c;
+  const uint64_t rid = ct * ROWS + r;
+  const uint32_t m = A.bits[c];
+  int32_t ev[8];
+  gen_gauss<LOGN>(A.seed, rid * (N / 2), tab, stage, t, ev);
+  const bool brow = r < D;
+  const uint32_t gi = (r % D) / 5, gj = (r % D) % 5;
+  uint32_t* row = A.out + (c * ROWS + r) * (size_t)(2 * NQ * N);
+  uint32_t xc = 0;
+#pragma unroll 1
+  for (int i = 0; i < NQ; ++i) {
+    const PrimeTab P = T.pt[i];
+    __syncthreads();
+    load_tw_lds<LOGN>(twl, T.fwd[i], t);
+    uint32_t xa[8], xe[8];
+    gen_uniform<LOGN>(A.seed, (rid * NQ + i) * (N / 2), P, stage, t, xa);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) xe[e] = ev[e] < 0 ? (uint32_t)(ev[e] + (int32_t)P.q) : (uint32_t)ev[e];
+    ntt_fwd<LOGN>(xa, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
+    ntt_fwd<LOGN>(xe, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
+    const uint32_t g = (m && gi == (uint32_t)i) ? (1u << (A.log_base * gj)) : 0u;
+    const uint4* sp = reinterpret_cast<const uint4*>(A.sk_hat + (size_t)i * N + (t << 3));
+    const uint4 s0 = sp[0], s1 = sp[1];
+    const uint32_t sh[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+    uint32_t oa[8], ob[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t a = red4q(xa[e], P.q, P.two_q);
+      const uint32_t ee = red4q(xe[e], P.q, P.two_q);
+      uint32_t b = addq(mulq(a, sh[e], P), ee, P.q);
+      oa[e] = brow ? a : addq(a, g, P.q);
+      ob[e] = brow ? addq(b, g, P.q) : b;
+    }
+    uint4* pa = reinterpret_cast<uint4*>(row + (size_t)i * N + (t << 3));
+    uint4* pb = reinterpret_cast<uint4*>(row + (size_t)(NQ + i) * N + (t << 3));
+    pa[0] = make_uint4(oa[0], oa[1], oa[2], oa[3]);
+    pa[1] = make_uint4(oa[4], oa[5], oa[6], oa[7]);
+    pb[0] = make_uint4(ob[0], ob[1], ob[2], ob[3]);
+    pb[1] = make_uint4(ob[4], ob[5], ob[6], ob[7]);
+  }
+}
+
+// RLWE encryption in the coefficient domain: b = a*s + Delta*msg + e
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rlwe(Tabs T, Cdt cdt, EncArgs A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  __shared__ __attribute__((aligned(16))) uint32_t stage[1 << LOGN];
+  __shared__ uint64_t tab[42];
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  const uint32_t t = threadIdx.x;
+  const uint64_t c = blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+  if (t < 42) tab[t] = cdt.T[t];
+  const uint64_t rid = A.ct0 + c;  // one row per ciphertext
+  int32_t ev[8];
+  gen_gauss<LOGN>(A.seed, rid * (N / 2), tab, stage, t, ev);
+  uint32_t* out = A.out + c * (size_t)(2 * NQ * N);
+  uint32_t xc = 0;
+#pragma unroll 1
+  for (int i = 0; i < NQ; ++i) {
+    const PrimeTab P = T.pt[i];
+    __syncthreads();
+    load_tw_lds<LOGN>(twl, T.fwd[i], t);
+    uint32_t xa[8], a0[8];
+    gen_uniform<LOGN>(A.seed, (rid * NQ + i) * (N / 2), P, stage, t, xa);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a0[e] = xa[e];
+    ntt_fwd<LOGN>(xa, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
+    const uint4* sp = reinterpret_cast<const uint4*>(A.sk_hat + (size_t)i * N + (t << 3));
+    const uint4 s0 = sp[0], s1 = sp[1];
+    const uint32_t sh[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) xa[e] = csub(mulq(red4q(xa[e], P.q, P.two_q), sh[e], P), P.two_q);
+    ntt_inv<LOGN>(xa, T.inv[i], P, lds, xc, t);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t k = t + TT * e;
+      const uint32_t ee = ev[e] < 0 ? (uint32_t)(ev[e] + (int32_t)P.q) : (uint32_t)ev[e];
+      uint32_t b = addq(xa[e], ee, P.q);
+      if (A.msg) b = addq(b, mulq(P.delta, red64(A.msg[c * N + k], P), P), P.q);
+      out[(size_t)i * N + k] = a0[e];
+      out[(size_t)(NQ + i) * N + k] = b;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// decryption
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double u128_to_double(u128 v) {
+  return (double)(uint64_t)(v >> 64) * 18446744073709551616.0 + (double)(uint64_t)v;
+}
+
+// round(p * phi / Q) mod p with phi given by its residues (CRT), rounding half up
+template <int NQ>
+__device__ __forceinline__ uint64_t crt_decode(const uint32_t (&ph)[NQ], const Tabs& T, const CrtTab& K) {
+  const u128 Q = ((u128)K.Q_hi << 64) | K.Q_lo;
+  u128 acc = 0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const uint32_t y = mulq(ph[i], K.inv[i], T.pt[i]);
+    const u128 M = ((u128)K.M_hi[i] << 64) | K.M_lo[i];
+    acc += (u128)y * M;
+    if (acc >= Q) acc -= Q;
+  }
+  const u128 num = (u128)K.p * acc + (((u128)K.half_hi << 64) | K.half_lo);
+  uint64_t qt = (uint64_t)(u128_to_double(num) / u128_to_double(Q));
+  while (qt > 0 && (u128)qt * Q > num) --qt;
+  while ((u128)(qt + 1) * Q <= num) ++qt;
+  return qt & (K.p - 1);
+}
+
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_dec_rlwe(Tabs T, CrtTab K, const uint32_t* __restrict__ sk_hat,
+                                                            const uint32_t* __restrict__ ct,
+                                                            uint64_t* __restrict__ msg) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  const uint32_t t = threadIdx.x;
+  const uint64_t c = blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+  const uint32_t* in = ct + c * (size_t)(2 * NQ * N);
+  uint32_t ph[8][NQ];
+  uint32_t xc = 0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const PrimeTab P = T.pt[i];
+    __syncthreads();
+    load_tw_lds<LOGN>(twl, T.fwd[i], t);
+    uint32_t x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = in[(size_t)i * N + t + TT * e];
+    ntt_fwd<LOGN>(x, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
+    const uint4* sp = reinterpret_cast<const uint4*>(sk_hat + (size_t)i * N + (t << 3));
+    const uint4 s0 = sp[0], s1 = sp[1];
+    const uint32_t sh[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = mulq(red4q(x[e], P.q, P.two_q), sh[e], P);
+    ntt_inv<LOGN>(x, T.inv[i], P, lds, xc, t);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ph[e][i] = subq(in[(size_t)(NQ + i) * N + t + TT * e], x[e], P.q);
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) msg[c * N + t + TT * e] = crt_decode<NQ>(ph[e], T, K);
+}
+
+// one wavefront per LWE ciphertext
+template <int NQ>
+__global__ __launch_bounds__(256) void k_dec_lwe(Tabs T, CrtTab K, uint32_t N, const int32_t* __restrict__ sk,
+                                                 const uint32_t* __restrict__ lwe, uint64_t count,
+                                                 uint64_t* __restrict__ msg) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t c = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= count) return;
+  const uint32_t* L = lwe + c * (size_t)NQ * (N + 1);
+  uint32_t ph[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const uint32_t q = T.pt[i].q;
+    uint64_t acc = 0;
+    for (uint32_t k = lane; k < N; k += 64) {
+      const int32_t s = sk[k];
+      const uint32_t a = L[(size_t)i * (N + 1) + k];
+      acc += s == 1 ? a : (s == -1 ? (a ? q - a : 0u) : 0u);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    ph[i] = subq(L[(size_t)i * (N + 1) + N], red64(acc, T.pt[i]), q);
+  }
+  if (lane == 0) msg[c] = crt_decode<NQ>(ph, T, K);
+}
+
+// ---------------------------------------------------------------------------
+// transforms
+// ---------------------------------------------------------------------------
+
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_ntt(Tabs T, uint32_t* __restrict__ polys, int inverse) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  const uint32_t t = threadIdx.x, i = blockIdx.x;
+  const uint64_t c = blockIdx.y + (uint64_t)blockIdx.z * gridDim.y;
+  const PrimeTab P = T.pt[i];
+  uint32_t* p = polys + (c * NQ + i) * (size_t)N;
+  uint32_t x[8];
+  uint32_t xc = 0;
+  if (!inverse) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = p[t + TT * e];
+    __syncthreads();
+    load_tw_lds<LOGN>(twl, T.fwd[i], t);
+    ntt_fwd<LOGN>(x, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
+    uint4* o = reinterpret_cast<uint4*>(p + (t << 3));
+    o[0] = make_uint4(red4q(x[0], P.q, P.two_q), red4q(x[1], P.q, P.two_q), red4q(x[2], P.q, P.two_q),
+                      red4q(x[3], P.q, P.two_q));
+    o[1] = make_uint4(red4q(x[4], P.q, P.two_q), red4q(x[5], P.q, P.two_q), red4q(x[6], P.q, P.two_q),
+                      red4q(x[7], P.q, P.two_q));
+  } else {
+    const uint4* s = reinterpret_cast<const uint4*>(p + (t << 3));
+    const uint4 u = s[0], v = s[1];
+    x[0] = u.x; x[1] = u.y; x[2] = u.z; x[3] = u.w; x[4] = v.x; x[5] = v.y; x[6] = v.z; x[7] = v.w;
+    __syncthreads();  // every thread has read its inputs before anyone overwrites them
+    ntt_inv<LOGN>(x, T.inv[i], P, lds, xc, t);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) p[t + TT * e] = x[e];
+  }
+}
+
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_rgsw_export(Tabs T, const uint32_t* __restrict__ rgsw,
+                                                               uint32_t* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  const uint32_t t = threadIdx.x;
+  const uint64_t poly = blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;  // (ct, row, a|b)
+  uint32_t xc = 0;
+#pragma unroll 1
+  for (int i = 0; i < NQ; ++i) {
+    const PrimeTab P = T.pt[i];
+    const size_t off = (poly * NQ + i) * (size_t)N;
+    const uint4* s = reinterpret_cast<const uint4*>(rgsw + off + (t << 3));
+    const uint4 u = s[0], v = s[1];
+    uint32_t x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+    ntt_inv<LOGN>(x, T.inv[i], P, lds, xc, t);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) out[off + t + TT * e] = x[e];
+  }
+}
+
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_xp(Tabs T, const uint32_t* __restrict__ rgsw,
+                                                      const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                      uint64_t rgsw_words) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr int N = 1 << LOGN;
+  const uint32_t t = threadIdx.x;
+  const uint64_t c = blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+  uint32_t* o = out + c * (size_t)(2 * NQ * N);
+  uint32_t xc = 0;
+  ext_prod<LOGN, NQ>(in + c * (size_t)(2 * NQ * N), rgsw + c * rgsw_words, T, lds, twl, xc, t,
+                     XpOut{o, nullptr, nullptr, XP_STORE});
+}
+
+// ---------------------------------------------------------------------------
+// shared pieces of the training and inference kernels
+// ---------------------------------------------------------------------------
+
+// xin <- X^ex * acc - acc (coefficients t + T e of every polynomial)
+template <int LOGN, int NQ>
+__device__ __forceinline__ void rot_diff(const Tabs& T, const uint32_t* __restrict__ acc, int32_t ex,
+                                         uint32_t* __restrict__ xin, uint32_t t) {
+  constexpr int N = 1 << LOGN, TT = N / 8;
+#pragma unroll 1
+  for (int w = 0; w < 2 * NQ; ++w) {
+    const uint32_t* f = acc + (size_t)w * N;
+    uint32_t* o = xin + (size_t)w * N;
+    const uint32_t q = T.pt[w % NQ].q;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int32_t k = t + TT * e;
+      (o + TT * e)[t] = subq(rot_coef<LOGN>(f, k, ex, q), (f + TT * e)[t], q);
+    }
+  }
+}
+
+// CMUX step of a blind rotation: acc <- acc + C [.] (X^ex acc - acc)
+template <int LOGN, int NQ>
+__device__ __forceinline__ void cmux_rot(const Tabs& T, uint32_t* __restrict__ acc, int32_t ex,
+                                         const uint32_t* __restrict__ C, uint32_t* __restrict__ xin, uint32_t* lds,
+                                         uint2* twl, uint32_t& xc, uint32_t t) {
+  rot_diff<LOGN, NQ>(T, acc, ex, xin, t);
+  ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t, XpOut{acc, acc, nullptr, XP_ADD});
+  __syncthreads();  // the next rotation reads coefficients other threads wrote
+}
+
+template <int LOGN, int NQ>
+__device__ __forceinline__ void copy_rlwe(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, uint32_t t) {
+  constexpr int N = 1 << LOGN, TT = N / 8;
+#pragma unroll 1
+  for (int w = 0; w < 2 * NQ; ++w)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) (dst + (size_t)w * N + TT * e)[t] = (src + (size_t)w * N + TT * e)[t];
+}
+
+// ---------------------------------------------------------------------------
+// training: one workgroup per (RAM, sample)
+// ---------------------------------------------------------------------------
+// The workgroup's block holds k1 output slots and one input slot (xin).
+// Slot 0 is the accumulator of the rotation chain (CMUX(C_t, X^{2^t} acc,
+// acc)); the CDEMUX tree then expands it in place: level i turns slot j into
+// (slot j - C_i [.] slot j, C_i [.] slot j) at slots j and j + 2^i.  The
+// `ram == k0` workgroup builds the class counter from the label bits alone.
+
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_train(Tabs T, TrainArgs A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  constexpr size_t RW = (size_t)2 * NQ * N;
+  const uint32_t t = threadIdx.x, ram = blockIdx.x, smp = blockIdx.y;
+  const uint64_t gi = A.i0 + smp;
+  uint32_t nb;
+  if (ram < A.k0) {
+    const uint32_t rem = A.s - ram * A.a;
+    nb = A.L + (rem < A.a ? rem : A.a);
+  } else {
+    nb = A.L;
+  }
+  const uint32_t nr = nb < (uint32_t)LOGN ? nb : (uint32_t)LOGN;
+  const uint32_t z = nb - nr;
+  uint32_t* slot0 = A.out + ((size_t)smp * (A.k0 + 1) + ram) * (A.k1 + 1) * RW;
+  uint32_t* xin = slot0 + (size_t)A.k1 * RW;
+  auto bit_rgsw = [&](uint32_t u) -> const uint32_t* {
+    if (u < A.L) return A.y_rgsw + (gi * A.L + u) * A.rgsw_words;
+    return A.x_rgsw + (gi * A.s + A.perm[ram * A.a + (u - A.L)]) * A.rgsw_words;
+  };
+  // acc = (0, Delta)
+#pragma unroll 1
+  for (int w = 0; w < 2 * NQ; ++w) {
+    const uint32_t d0 = w >= NQ ? T.pt[w - NQ].delta : 0u;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) (slot0 + (size_t)w * N + TT * e)[t] = (e == 0 && t == 0) ? d0 : 0u;
+  }
+  __syncthreads();
+  uint32_t xc = 0;
+#pragma unroll 1
+  for (uint32_t st = 0; st < nr; ++st)
+    cmux_rot<LOGN, NQ>(T, slot0, 1 << st, bit_rgsw(z + st), xin, lds, twl, xc, t);
+#pragma unroll 1
+  for (uint32_t lev = 0; lev < z; ++lev) {
+    const uint32_t* C = bit_rgsw(lev);
+    const uint32_t n = 1u << lev;
+#pragma unroll 1
+    for (uint32_t j = 0; j < n; ++j) {
+      uint32_t* sj = slot0 + j * RW;
+      uint32_t* sn = slot0 + (j + n) * RW;
+      copy_rlwe<LOGN, NQ>(xin, sj, t);
+      ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t, XpOut{sj, xin, sn, XP_DEMUX});
+    }
+  }
+}
+
+// model[j][d] += sum over the sub-batch of out[smp][j][d] for d < 2^{z_j};
+// cnt += sum of out[smp][k0][0].  One thread per model word.
+__global__ __launch_bounds__(256) void k_reduce_model(Tabs T, ReduceArgs A) {
+  const size_t RW = (size_t)2 * A.nq * A.N;
+  const size_t per_ram = (size_t)A.k1 * RW;
+  const size_t model_words = (size_t)A.k0 * per_ram;
+  const size_t total = model_words + (A.cnt ? RW : 0);
+  const size_t blk = (size_t)(A.k1 + 1) * RW;      // one (sample, RAM) block
+  const size_t stride = (size_t)(A.k0 + 1) * blk;  // one sample
+  for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (size_t)gridDim.x * blockDim.x) {
+    uint32_t ram, d;
+    size_t rem;
+    if (w < model_words) {
+      ram = (uint32_t)(w / per_ram);
+      rem = w - (size_t)ram * per_ram;
+      d = (uint32_t)(rem / RW);
+      rem -= (size_t)d * RW;
+      const uint32_t left = A.s - ram * A.a;
+      const uint32_t nb = A.L + (left < A.a ? left : A.a);
+      const uint32_t nr = nb < A.logN ? nb : A.logN;
+      if (d >= (1u << (nb - nr))) continue;
+    } else {
+      ram = A.k0;
+      d = 0;
+      rem = w - model_words;
+    }
+    const uint32_t i = (uint32_t)((rem / A.N) % A.nq);
+    const PrimeTab P = T.pt[i];
+    const size_t src = (size_t)ram * blk + (size_t)d * RW + rem;
+    uint64_t acc = 0;
+    for (uint64_t s = 0; s < A.n_sub; ++s) acc += A.out[s * stride + src];
+    uint32_t* dst = (w < model_words) ? (A.model + w) : (A.cnt + rem);
+    *dst = addq(*dst, red64(acc, P), P.q);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inference: one workgroup per (RAM, label, sample)
+// ---------------------------------------------------------------------------
+// Vertical Packing of row `ram` of the model for the label bits of c (clear)
+// and the sample's tuple bits (encrypted).  Levels of the selection tree that
+// carry label bits select exactly; only the 2^{z-L} - 1 CMUXes whose outputs
+// reach the result are evaluated (the discarded ones do not change it).
+
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_infer(Tabs T, InferArgs A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  constexpr size_t RW = (size_t)2 * NQ * N;
+  const uint32_t t = threadIdx.x, ram = blockIdx.x, lab = blockIdx.y, smp = blockIdx.z;
+  const uint64_t gi = A.i0 + smp;
+  const uint32_t rem = A.s - ram * A.a;
+  const uint32_t aj = rem < A.a ? rem : A.a;
+  const uint32_t nb = A.L + aj;
+  const uint32_t nr = nb < (uint32_t)LOGN ? nb : (uint32_t)LOGN;
+  const uint32_t z = nb - nr;
+  const uint32_t* H = A.model + (size_t)ram * A.k1 * RW;
+  uint32_t* acc = A.scratch + (((size_t)smp * A.l + lab) * A.k0 + ram) * (A.slots + 1) * RW;
+  uint32_t* xin = acc + (size_t)A.slots * RW;
+  auto xbit = [&](uint32_t u) -> const uint32_t* {
+    return A.x_rgsw + (gi * A.s + A.perm[ram * A.a + (u - A.L)]) * A.rgsw_words;
+  };
+  uint32_t xc = 0;
+  if (z > A.L) {
+    // encrypted levels z-1 .. L over the leaves lab + (w << L); the clear
+    // levels below L then select leaf index lab exactly
+#pragma unroll 1
+    for (int lev = (int)z - 1; lev >= (int)A.L; --lev) {
+      const uint32_t* C = xbit((uint32_t)lev);
+      const uint32_t cnt = 1u << (lev - A.L);
+#pragma unroll 1
+      for (uint32_t w = 0; w < cnt; ++w) {
+        const bool leaf = lev == (int)z - 1;
+        const uint32_t* lo = leaf ? H + (size_t)(lab + (w << A.L)) * RW : acc + (size_t)w * RW;
+        const uint32_t* hi = leaf ? H + (size_t)(lab + (w << A.L) + (1u << lev)) * RW : acc + (size_t)(w + cnt) * RW;
+        uint32_t* dst = acc + (size_t)w * RW;
+#pragma unroll 1
+        for (int pw = 0; pw < 2 * NQ; ++pw) {
+          const uint32_t q = T.pt[pw % NQ].q;
+          const size_t o = (size_t)pw * N;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            (xin + o + TT * e)[t] = subq((hi + o + TT * e)[t], (lo + o + TT * e)[t], q);
+        }
+        ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t, XpOut{dst, lo, nullptr, XP_ADD});
+      }
+    }
+  } else {
+    copy_rlwe<LOGN, NQ>(acc, H + (size_t)(lab & ((1u << z) - 1)) * RW, t);
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (uint32_t st = 0; st < nr; ++st) {
+    const uint32_t u = z + st;
+    const int32_t ex = -(1 << st);
+    if (u < A.L) {
+      if ((lab >> u) & 1u) {  // clear bit 1: exact rotation by X^{-2^st}
+        rot_diff<LOGN, NQ>(T, acc, ex, xin, t);  // xin = X^ex acc - acc
+        __syncthreads();
+#pragma unroll 1
+        for (int w = 0; w < 2 * NQ; ++w) {
+          const uint32_t q = T.pt[w % NQ].q;
+          const size_t o = (size_t)w * N;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            (acc + o + TT * e)[t] = addq((acc + o + TT * e)[t], (xin + o + TT * e)[t], q);
+        }
+        __syncthreads();
+      }
+      continue;
+    }
+    cmux_rot<LOGN, NQ>(T, acc, ex, xbit(u), xin, lds, twl, xc, t);
+  }
+  // ExtractLWE(acc, 0): a'_0 = a_0, a'_k = -a_{N-k}, b' = b_0
+  uint32_t* out = A.scores + ((gi * A.l + lab) * A.k0 + ram) * (size_t)NQ * (N + 1);
+#pragma unroll 1
+  for (int i = 0; i < NQ; ++i) {
+    const uint32_t q = T.pt[i].q;
+    const uint32_t* a = acc + (size_t)i * N;
+    uint32_t* o = out + (size_t)i * (N + 1);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t k = t + TT * e;
+      const uint32_t x = a[(N - k) & (N - 1)];  // k = 0 reads a_0
+      (o + TT * e)[t] = (k == 0 || x == 0) ? x : q - x;
+    }
+    if (t == 0) o[N] = acc[(size_t)(NQ + i) * N];
+  }
+}
+
+// sums[i][c] = sum_j scores[i][c][j] (LWE addition), one thread per word
+__global__ __launch_bounds__(256) void k_class_sums(Tabs T, SumArgs A) {
+  const size_t LW = (size_t)A.nq * (A.N + 1);
+  const size_t total = (size_t)A.n * A.l * LW;
+  for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (size_t)gridDim.x * blockDim.x) {
+    const size_t ic = w / LW, rem = w - ic * LW;
+    const uint32_t i = (uint32_t)(rem / (A.N + 1));
+    const uint32_t* src = A.scores + ic * A.k0 * LW + rem;
+    uint64_t acc = 0;
+    for (uint32_t j = 0; j < A.k0; ++j) acc += src[(size_t)j * LW];
+    A.sums[w] = red64(acc, T.pt[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+// launch a 1-D family of `count` jobs as exact rectangles of (x, y) blocks;
+// a kernel recovers its job as blockIdx.x + blockIdx.y * gridDim.x (or the
+// same over y, z when x indexes something else)
+template <class F>
+static hipError_t for_rect(uint64_t count, F&& f) {
+  uint64_t done = 0;
+  while (done < count) {
+    const uint64_t left = count - done;
+    uint32_t x, y;
+    if (left <= 65535) {
+      x = (uint32_t)left;
+      y = 1;
+    } else {
+      x = 65535;
+      y = (uint32_t)(left / 65535 < 65535 ? left / 65535 : 65535);
+    }
+    const hipError_t e = f(done, dim3(x, y));
+    if (e != hipSuccess) return e;
+    done += (uint64_t)x * y;
+  }
+  return hipSuccess;
+}
+
+#define HW_DISPATCH(logN, nq, ...)                                                     \
+  do {                                                                                 \
+    if (logN == 10 && nq == 1) { constexpr int LN = 10, NQ = 1; __VA_ARGS__; }         \
+    else if (logN == 10 && nq == 2) { constexpr int LN = 10, NQ = 2; __VA_ARGS__; }    \
+    else if (logN == 10 && nq == 3) { constexpr int LN = 10, NQ = 3; __VA_ARGS__; }    \
+    else if (logN == 11 && nq == 1) { constexpr int LN = 11, NQ = 1; __VA_ARGS__; }    \
+    else if (logN == 11 && nq == 2) { constexpr int LN = 11, NQ = 2; __VA_ARGS__; }    \
+    else if (logN == 11 && nq == 3) { constexpr int LN = 11, NQ = 3; __VA_ARGS__; }    \
+    else if (logN == 12 && nq == 1) { constexpr int LN = 12, NQ = 1; __VA_ARGS__; }    \
+    else if (logN == 12 && nq == 2) { constexpr int LN = 12, NQ = 2; __VA_ARGS__; }    \
+    else if (logN == 12 && nq == 3) { constexpr int LN = 12, NQ = 3; __VA_ARGS__; }    \
+    else return hipErrorInvalidValue;                                                  \
+  } while (0)
+
+hipError_t launch_keygen(uint32_t N, uint64_t seed, int32_t* sk, hipStream_t st) {
+  hipLaunchKernelGGL(k_keygen, dim3((N + 255) / 256), dim3(256), 0, st, N, seed, sk);
+  return hipGetLastError();
+}
+
+hipError_t launch_sk_hat(int logN, int nq, const Tabs& T, const int32_t* sk, uint32_t* sk_hat, hipStream_t st) {
+  HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_sk_hat<LN, NQ>), dim3(NQ), dim3(Geo<LN>::T), 0, st, T, sk, sk_hat));
+  return hipGetLastError();
+}
+
+hipError_t launch_enc_rgsw(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
+                           hipStream_t st) {
+  const size_t rg = (size_t)2 * 5 * nq * 2 * nq * ((size_t)1 << logN);
+  return for_rect(count, [&](uint64_t off, dim3 g) -> hipError_t {
+    EncArgs B = A;
+    B.bits = A.bits + off;
+    B.out = A.out + off * rg;
+    B.ct0 = A.ct0 + off;
+    HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ>), dim3(2 * 5 * NQ, g.x, g.y), dim3(Geo<LN>::T), 0,
+                                              st, T, cdt, B));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_enc_rlwe(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
+                           hipStream_t st) {
+  const size_t N = 1u << logN;
+  return for_rect(count, [&](uint64_t off, dim3 g) -> hipError_t {
+    EncArgs B = A;
+    B.ct0 = A.ct0 + off;
+    B.out = A.out + off * 2 * nq * N;
+    B.msg = A.msg ? A.msg + off * N : nullptr;
+    HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rlwe<LN, NQ>), g, dim3(Geo<LN>::T), 0, st, T, cdt, B));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_dec_rlwe(int logN, int nq, const Tabs& T, const CrtTab& K, const uint32_t* sk_hat,
+                           const uint32_t* ct, uint64_t count, uint64_t* msg, hipStream_t st) {
+  const size_t N = 1u << logN;
+  return for_rect(count, [&](uint64_t off, dim3 g) -> hipError_t {
+    HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_dec_rlwe<LN, NQ>), g, dim3(Geo<LN>::T), 0, st, T, K, sk_hat,
+                                              ct + off * 2 * nq * N, msg + off * N));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_dec_lwe(int logN, int nq, const Tabs& T, const CrtTab& K, const int32_t* sk,
+                          const uint32_t* lwe, uint64_t count, uint64_t* msg, hipStream_t st) {
+  const uint32_t N = 1u << logN;
+  const uint64_t per_launch = 4ull * 65535 * 256;
+  for (uint64_t off = 0; off < count; off += per_launch) {
+    const uint64_t c = count - off < per_launch ? count - off : per_launch;
+    const uint32_t blocks = (uint32_t)((c + 3) / 4);
+    const uint32_t* l = lwe + off * (size_t)nq * (N + 1);
+    if (nq == 1) hipLaunchKernelGGL(k_dec_lwe<1>, dim3(blocks), dim3(256), 0, st, T, K, N, sk, l, c, msg + off);
+    else if (nq == 2) hipLaunchKernelGGL(k_dec_lwe<2>, dim3(blocks), dim3(256), 0, st, T, K, N, sk, l, c, msg + off);
+    else if (nq == 3) hipLaunchKernelGGL(k_dec_lwe<3>, dim3(blocks), dim3(256), 0, st, T, K, N, sk, l, c, msg + off);
+    else return hipErrorInvalidValue;
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_rgsw_export(int logN, int nq, const Tabs& T, const uint32_t* rgsw, uint64_t count,
+                              uint32_t* out, hipStream_t st) {
+  const size_t N = 1u << logN;
+  const uint64_t polys = count * 2 * 5 * nq * 2;
+  return for_rect(polys, [&](uint64_t off, dim3 g) -> hipError_t {
+    HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_rgsw_export<LN, NQ>), g, dim3(Geo<LN>::T), 0, st, T,
+                                              rgsw + off * nq * N, out + off * nq * N));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_ntt(int logN, int nq, const Tabs& T, uint32_t* polys, uint64_t count, int inverse,
+                      hipStream_t st) {
+  const size_t N = 1u << logN;
+  return for_rect(count, [&](uint64_t off, dim3 g) -> hipError_t {
+    HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_ntt<LN, NQ>), dim3(NQ, g.x, g.y), dim3(Geo<LN>::T), 0, st, T,
+                                              polys + off * nq * N, inverse));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, const uint32_t* in, uint64_t count,
+                     uint32_t* out, hipStream_t st) {
+  const size_t N = 1u << logN;
+  const uint64_t rw = 2ull * nq * N, gw = 2ull * 5 * nq * rw;
+  return for_rect(count, [&](uint64_t off, dim3 g) -> hipError_t {
+    HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_xp<LN, NQ>), g, dim3(Geo<LN>::T), 0, st, T, rgsw + off * gw,
+                                              in + off * rw, out + off * rw, gw));
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, uint32_t nram, uint32_t n_sub,
+                        hipStream_t st) {
+  HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_train<LN, NQ>), dim3(nram, n_sub), dim3(Geo<LN>::T), 0, st, T, A));
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_model(const Tabs& T, const ReduceArgs& A, hipStream_t st) {
+  const size_t RW = (size_t)2 * A.nq * A.N;
+  const size_t total = (size_t)A.k0 * A.k1 * RW + (A.cnt ? RW : 0);
+  const uint32_t blocks = (uint32_t)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+  hipLaunchKernelGGL(k_reduce_model, dim3(blocks), dim3(256), 0, st, T, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, uint32_t n_sub, hipStream_t st) {
+  HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_infer<LN, NQ>), dim3(A.k0, A.l, n_sub), dim3(Geo<LN>::T), 0, st, T, A));
+  return hipGetLastError();
+}
+
+hipError_t launch_class_sums(const Tabs& T, const SumArgs& A, hipStream_t st) {
+  const size_t total = (size_t)A.n * A.l * A.nq * (A.N + 1);
+  const uint32_t blocks = (uint32_t)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+  hipLaunchKernelGGL(k_class_sums, dim3(blocks), dim3(256), 0, st, T, A);
+  return hipGetLastError();
+}
+
+}  // namespace hw

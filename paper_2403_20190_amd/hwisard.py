@@ -1,0 +1,175 @@
+"""ctypes binding of libhwisard.so (C ABI in include/hwisard.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+the library.  Device buffers are torch tensors on the GPU (int32/int64
+storage holding the ABI's uint32/uint64 words); work is enqueued on torch's
+current stream.  The library must be built (``python -m
+paper_2403_20190_amd.build``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhwisard.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libhwisard.so is not built: run `python -m paper_2403_20190_amd.build` "
+                      "(the encrypted WiSARD path has no CPU fallback)")
+
+_lib = C.CDLL(LIB_PATH)
+
+HW_OK, HW_EINVAL, HW_ENOMEM, HW_EDEVICE, HW_EUNSUPPORTED, HW_EBUSY, HW_ECANCELLED = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {0: "HW_OK", -1: "HW_EINVAL", -2: "HW_ENOMEM", -3: "HW_EDEVICE", -4: "HW_EUNSUPPORTED",
+          -5: "HW_EBUSY", -6: "HW_ECANCELLED"}
+
+
+class HwError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("N", C.c_uint32), ("nq", C.c_uint32), ("primes", C.c_uint32 * 4), ("log_base", C.c_uint32),
+                ("digits", C.c_uint32), ("sigma", C.c_double), ("plain_mod", C.c_uint64)]
+
+
+class Shape(C.Structure):
+    _fields_ = [("s", C.c_uint32), ("l", C.c_uint32), ("a", C.c_uint32), ("reserved", C.c_uint32),
+                ("perm_seed", C.c_uint64)]
+
+
+_vp, _u64, _u32, _i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
+_SIG = {
+    "hw_ctx_create": [C.POINTER(Params), _i32, C.POINTER(C.c_void_p)],
+    "hw_ctx_params": [_vp, C.POINTER(Params)],
+    "hw_sizes": [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)],
+    "hw_wisard_dims": [_vp, C.POINTER(Shape), C.POINTER(_u32), C.POINTER(_u32), C.POINTER(_u64)],
+    "hw_permutation": [C.POINTER(Shape), _vp],
+    "hw_keygen": [_vp, _u64, _vp, _vp],
+    "hw_encrypt_rgsw_bits": [_vp, _vp, _vp, _u64, _u64, _u64, _vp, _vp],
+    "hw_encrypt_rlwe": [_vp, _vp, _vp, _u64, _u64, _u64, _vp, _vp],
+    "hw_decrypt_rlwe": [_vp, _vp, _vp, _u64, _vp, _vp],
+    "hw_decrypt_lwe": [_vp, _vp, _vp, _u64, _vp, _vp],
+    "hw_rgsw_export_canonical": [_vp, _vp, _u64, _vp, _vp],
+    "hw_ntt": [_vp, _vp, _u64, _i32, _vp],
+    "hw_external_product": [_vp, _vp, _vp, _u64, _vp, _vp],
+    "hw_wisard_train_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
+    "hw_wisard_infer_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
+}
+for _n, _a in _SIG.items():
+    _f = getattr(_lib, _n)
+    _f.restype = C.c_int
+    _f.argtypes = _a
+_lib.hw_ctx_destroy.restype = None
+_lib.hw_ctx_destroy.argtypes = [_vp]
+_lib.hw_last_error.restype = C.c_char_p
+_lib.hw_last_error.argtypes = []
+
+
+def exported_symbols():
+    """Names the library exports (for the ABI test)."""
+    return sorted(_SIG) + ["hw_ctx_destroy", "hw_last_error"]
+
+
+def _check(st: int):
+    if st != HW_OK:
+        raise HwError(st, _lib.hw_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def shape(s: int, l: int, a: int, perm_seed: int) -> Shape:
+    return Shape(s, l, a, 0, perm_seed)
+
+
+def permutation(sh: Shape) -> np.ndarray:
+    out = np.zeros(max(1, sh.s), np.uint32)
+    _check(_lib.hw_permutation(C.byref(sh), out.ctypes.data_as(C.c_void_p)))
+    return out[:sh.s]
+
+
+class Context:
+    """One parameter set on one device (hw_ctx)."""
+
+    def __init__(self, N: int, nq: int, p: int, primes=None, sigma: float = 3.2, device: int = 0):
+        prm = Params()
+        prm.N, prm.nq, prm.log_base, prm.digits, prm.sigma, prm.plain_mod = N, nq, 6, 5, sigma, p
+        for i, q in enumerate(primes or []):
+            prm.primes[i] = q
+        h = C.c_void_p()
+        _check(_lib.hw_ctx_create(C.byref(prm), device, C.byref(h)))
+        self._h = h
+        out = Params()
+        _check(_lib.hw_ctx_params(h, C.byref(out)))
+        self.N, self.nq, self.p, self.device = N, nq, p, device
+        self.primes = [int(out.primes[i]) for i in range(nq)]
+        r, g, w = _u64(), _u64(), _u64()
+        _check(_lib.hw_sizes(h, C.byref(r), C.byref(g), C.byref(w)))
+        self.rlwe_words, self.rgsw_words, self.lwe_words = r.value // 4, g.value // 4, w.value // 4
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hw_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- geometry -------------------------------------------------------------
+    def dims(self, sh: Shape):
+        k0, k1, mb = _u32(), _u32(), _u64()
+        _check(_lib.hw_wisard_dims(self._h, C.byref(sh), C.byref(k0), C.byref(k1), C.byref(mb)))
+        return k0.value, k1.value, mb.value
+
+    # -- client side ------------------------------------------------------------
+    def keygen(self, seed: int, sk):
+        _check(_lib.hw_keygen(self._h, seed, _ptr(sk), _stream()))
+
+    def encrypt_rgsw_bits(self, sk, bits, seed: int, ct0: int, out):
+        _check(_lib.hw_encrypt_rgsw_bits(self._h, _ptr(sk), _ptr(bits), bits.numel(), seed, ct0, _ptr(out),
+                                         _stream()))
+
+    def encrypt_rlwe(self, sk, msg, count: int, seed: int, ct0: int, out):
+        _check(_lib.hw_encrypt_rlwe(self._h, _ptr(sk), _ptr(msg), count, seed, ct0, _ptr(out), _stream()))
+
+    def decrypt_rlwe(self, sk, ct, count: int, out):
+        _check(_lib.hw_decrypt_rlwe(self._h, _ptr(sk), _ptr(ct), count, _ptr(out), _stream()))
+
+    def decrypt_lwe(self, sk, lwe, count: int, out):
+        _check(_lib.hw_decrypt_lwe(self._h, _ptr(sk), _ptr(lwe), count, _ptr(out), _stream()))
+
+    def rgsw_export(self, rgsw, count: int, out):
+        _check(_lib.hw_rgsw_export_canonical(self._h, _ptr(rgsw), count, _ptr(out), _stream()))
+
+    # -- ring / ciphertext kernels ------------------------------------------------
+    def ntt(self, polys, count: int, inverse: bool):
+        _check(_lib.hw_ntt(self._h, _ptr(polys), count, 1 if inverse else 0, _stream()))
+
+    def external_product(self, rgsw, rin, count: int, rout):
+        _check(_lib.hw_external_product(self._h, _ptr(rgsw), _ptr(rin), count, _ptr(rout), _stream()))
+
+    # -- server side ----------------------------------------------------------------
+    def train(self, sh: Shape, x_rgsw, y_rgsw, n: int, model, class_count=None):
+        _check(_lib.hw_wisard_train_encrypted(self._h, C.byref(sh), _ptr(x_rgsw), _ptr(y_rgsw), n, _ptr(model),
+                                              _ptr(class_count), _stream()))
+
+    def infer(self, sh: Shape, model, x_rgsw, n: int, ram_scores, class_scores=None):
+        _check(_lib.hw_wisard_infer_encrypted(self._h, C.byref(sh), _ptr(model), _ptr(x_rgsw), n,
+                                              _ptr(ram_scores), _ptr(class_scores), _stream()))

@@ -1,0 +1,263 @@
+"""GPU parity of the hot path: encrypted training (Alg. 6, IVP of Alg. 5 and
+the class counter) and PD-act inference (Alg. 7, VP of Alg. 3) of the HIP
+library against the CPU oracle, bit-exact, plus decryption-level properties
+against the plaintext Integer WiSARD at full workload sizes."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import plain as P
+from gpu_helpers import Pair, dev, host_u32, host_u64, zeros_u32, zeros_u64
+from paper_2403_20190_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def client():
+    from paper_2403_20190_amd import client as CL
+    return CL
+
+
+def decrypt_model(pair, H):
+    """decrypted cells of H, shape [k0][k1][N], via the GPU decryption"""
+    cnt = pair.k0 * pair.k1
+    out = zeros_u64(cnt, pair.N)
+    pair.ctx.decrypt_rlwe(pair.sk, H, cnt, out)
+    return host_u64(out).reshape(pair.k0, pair.k1, pair.N).astype(np.int64)
+
+
+def train_dev(pair, class_count=True):
+    xr = pair.encrypt_dev()
+    yr = pair.encrypt_labels_dev()
+    H = zeros_u32(pair.k0, pair.k1, 2, pair.nq, pair.N)
+    cnt = zeros_u32(2, pair.nq, pair.N) if class_count else None
+    pair.ctx.train(pair.shape, xr, yr, pair.n, H, cnt)
+    return H, cnt, xr, yr
+
+
+# --------------------------------------------------------------------------
+# tiny configuration: full parity, train and inference
+# --------------------------------------------------------------------------
+
+def tiny_pair():
+    CL = client()
+    Xtr, ytr, Xte, yte = synth.tiny(0)
+    bits = CL.thermometer(CL.quantize_u8(Xtr, 2), 2)
+    assert np.array_equal(bits, P.encode(P.quantize_u8(Xtr, 2), 2))  # client parity
+    pair = Pair(1024, 1, 64, 128, 2, 8, bits, ytr, seed=1)
+    test_bits = CL.thermometer(CL.quantize_u8(Xte, 2), 2)
+    return pair, test_bits, yte
+
+
+def test_tiny_training_and_inference_bit_exact():
+    pair, test_bits, _ = tiny_pair()
+    H, cnt, _, _ = train_dev(pair)
+    Ho = pair.oracle_train(range(pair.k0))
+    assert np.array_equal(host_u32(H), Ho)
+    cnt_o = np.zeros((2, 1, 1024), np.uint32)
+    pair.orc.class_count(pair.l, pair.yo, pair.n, cnt_o)
+    assert np.array_equal(host_u32(cnt), cnt_o)
+    # decrypted model = plaintext Integer WiSARD counts
+    W = P.train_integer(pair.X, pair.y, pair.l, pair.a, pair.pi)
+    assert np.array_equal(decrypt_model(pair, H), P.expected_model_cells(W, pair.s, pair.l, pair.a, pair.N))
+    # inference over the 16 test samples
+    nt = len(test_bits)
+    xt = pair.encrypt_dev(test_bits, seed_x=99)
+    scores = zeros_u32(nt, pair.l, pair.k0, pair.orc.lwe_words)
+    sums = zeros_u32(nt, pair.l, pair.orc.lwe_words)
+    pair.ctx.infer(pair.shape, H, xt, nt, scores, sums)
+    got = host_u32(scores).reshape(nt, pair.l, pair.k0, 1, 1025)
+    gsum = host_u32(sums).reshape(nt, pair.l, 1, 1025)
+    jobs = [(i, c, j) for i in range(nt) for c in range(pair.l) for j in range(pair.k0)]
+    want = {}
+
+    def one(job):
+        i, c, j = job
+        want[job] = pair.orc.infer_one(pair.s, pair.l, pair.a, pair.pi, Ho,
+                                       lambda k: pair.xo(i, k, test_bits, 99, "test"), j, c)
+
+    O._parallel(one, jobs)
+    for job in jobs:
+        assert np.array_equal(got[job], want[job]), job
+    for i in range(nt):
+        for c in range(pair.l):
+            acc = want[(i, c, 0)]
+            for j in range(1, pair.k0):
+                acc = pair.orc.lwe_add(acc, want[(i, c, j)])
+            assert np.array_equal(gsum[i, c], acc)
+    # PD-act on decrypted cells = plaintext Alg. 2
+    dec = zeros_u64(nt * pair.l * pair.k0)
+    pair.ctx.decrypt_lwe(pair.sk, scores, nt * pair.l * pair.k0, dec)
+    cells = host_u64(dec).reshape(nt, pair.l, pair.k0).astype(np.int64)
+    for i in range(nt):
+        assert np.array_equal(cells[i], P.ram_scores(W, test_bits[i], pair.a, pair.pi))
+    pred = client().pd_act_predict(cells, "bin")
+    assert [int(v) for v in pred] == [P.predict(W, test_bits[i], pair.a, pair.pi, "bin") for i in range(nt)]
+
+
+# --------------------------------------------------------------------------
+# shapes with an encrypted selection level, ragged tuples, l = 1
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cfg", [
+    dict(N=1024, nq=2, p=64, s=30, l=3, a=11, n=3),   # nb = 13 > log N: z = 3 > L = 2; ragged last tuple (8 bits)
+    dict(N=2048, nq=1, p=32, s=20, l=1, a=7, n=2),    # l = 1: no label bits; ragged last tuple
+    dict(N=4096, nq=2, p=64, s=14, l=5, a=14, n=2),   # nb = 17: z = 5 > L = 3, single RAM
+])
+def test_odd_shapes_bit_exact(cfg):
+    n = cfg.pop("n")
+    X, y = synth.prototype_bits(5, n, cfg["s"], cfg["l"], flip=0.2)
+    pair = Pair(X=X, y=y, seed=2, **cfg)
+    H, cnt, _, _ = train_dev(pair)
+    Ho = pair.oracle_train(range(pair.k0))
+    assert np.array_equal(host_u32(H), Ho)
+    W = P.train_integer(pair.X, pair.y, pair.l, pair.a, pair.pi)
+    assert np.array_equal(decrypt_model(pair, H), P.expected_model_cells(W, pair.s, pair.l, pair.a, pair.N))
+    Xt, _ = synth.prototype_bits(6, 1, cfg["s"], cfg["l"], flip=0.3)
+    xt = pair.encrypt_dev(Xt, seed_x=55)
+    scores = zeros_u32(1, pair.l, pair.k0, pair.orc.lwe_words)
+    pair.ctx.infer(pair.shape, H, xt, 1, scores, None)
+    got = host_u32(scores).reshape(1, pair.l, pair.k0, pair.nq, pair.N + 1)
+    for c in range(pair.l):
+        for j in range(pair.k0):
+            want = pair.orc.infer_one(pair.s, pair.l, pair.a, pair.pi, Ho, lambda k: pair.xo(0, k, Xt, 55, "t"), j, c)
+            assert np.array_equal(got[0, c, j], want), (c, j)
+
+
+# --------------------------------------------------------------------------
+# full-size shapes, sampled against the oracle
+# --------------------------------------------------------------------------
+
+def mnist_pair(n):
+    CL = client()
+    Xtr, ytr, Xte, yte = synth.mnist_like(1, per_class_train=1, per_class_test=1)
+    bits = CL.thermometer(CL.quantize_u8(Xtr[:n], 3), 3)
+    pair = Pair(2048, 2, 1024, 2352, 10, 12, bits, ytr[:n], seed=3)
+    tb = CL.thermometer(CL.quantize_u8(Xte[:1], 3), 3)
+    return pair, tb
+
+
+def test_mnist_shape_training_sampled():
+    pair, _ = mnist_pair(2)
+    assert (pair.k0, pair.k1) == (196, 32)
+    H, cnt, _, _ = train_dev(pair)
+    rams = [0, 97, 195]
+    Ho = pair.oracle_train(rams)
+    Hg = host_u32(H)
+    for j in rams:
+        assert np.array_equal(Hg[j], Ho[j]), j
+    cnt_o = np.zeros((2, 2, 2048), np.uint32)
+    pair.orc.class_count(pair.l, pair.yo, pair.n, cnt_o)
+    assert np.array_equal(host_u32(cnt), cnt_o)
+    # every RAM, by decryption: the Alg. 4 counts in the Def. 2 layout
+    W = P.train_integer(pair.X, pair.y, pair.l, pair.a, pair.pi)
+    assert np.array_equal(decrypt_model(pair, H), P.expected_model_cells(W, pair.s, pair.l, pair.a, pair.N))
+
+
+def test_mnist_shape_inference_sampled():
+    pair, tb = mnist_pair(2)
+    H, _, _, _ = train_dev(pair, class_count=False)
+    xt = pair.encrypt_dev(tb, seed_x=77)
+    scores = zeros_u32(1, 10, 196, pair.orc.lwe_words)
+    sums = zeros_u32(1, 10, pair.orc.lwe_words)
+    pair.ctx.infer(pair.shape, H, xt, 1, scores, sums)
+    got = host_u32(scores).reshape(1, 10, 196, 2, 2049)
+    # the oracle needs model rows 0 and 195 only: train them on its side
+    rams = [0, 195]
+    Ho = pair.oracle_train(rams)
+    jobs = [(c, j) for c in range(10) for j in rams]
+    want = {}
+    O._parallel(lambda cj: want.__setitem__(cj, pair.orc.infer_one(
+        pair.s, pair.l, pair.a, pair.pi, Ho, lambda k: pair.xo(0, k, tb, 77, "t"), cj[1], cj[0])), jobs)
+    for cj in jobs:
+        assert np.array_equal(got[0, cj[0], cj[1]], want[cj]), cj
+    # all cells by decryption, and the class sums
+    W = P.train_integer(pair.X, pair.y, pair.l, pair.a, pair.pi)
+    dec = zeros_u64(10 * 196)
+    pair.ctx.decrypt_lwe(pair.sk, scores, 10 * 196, dec)
+    cells = host_u64(dec).reshape(10, 196).astype(np.int64)
+    assert np.array_equal(cells, P.ram_scores(W, tb[0], pair.a, pair.pi))
+    ds = zeros_u64(10)
+    pair.ctx.decrypt_lwe(pair.sk, sums, 10, ds)
+    assert np.array_equal(host_u64(ds).astype(np.int64), cells.sum(axis=1) % 1024)
+
+
+def test_ham_shape_sampled():
+    CL = client()
+    Xtr, ytr, Xte, _ = synth.ham_like(3, n_train=20, n_test=1)
+    bits = CL.thermometer(CL.quantize_u8(Xtr[:1], 2), 2)
+    pair = Pair(4096, 3, 16384, 4704, 7, 12, bits, ytr[:1], seed=4)
+    assert (pair.k0, pair.k1) == (392, 8)
+    H, cnt, _, _ = train_dev(pair)
+    rams = [0, 391]
+    Ho = pair.oracle_train(rams)
+    Hg = host_u32(H)
+    for j in rams:
+        assert np.array_equal(Hg[j], Ho[j]), j
+    W = P.train_integer(pair.X, pair.y, pair.l, pair.a, pair.pi)
+    assert np.array_equal(decrypt_model(pair, H), P.expected_model_cells(W, pair.s, pair.l, pair.a, pair.N))
+    tb = CL.thermometer(CL.quantize_u8(Xte[:1], 2), 2)
+    xt = pair.encrypt_dev(tb, seed_x=66)
+    scores = zeros_u32(1, 7, 392, pair.orc.lwe_words)
+    pair.ctx.infer(pair.shape, H, xt, 1, scores, None)
+    got = host_u32(scores).reshape(1, 7, 392, 3, 4097)
+    want = {}
+    O._parallel(lambda c: want.__setitem__(c, pair.orc.infer_one(
+        pair.s, pair.l, pair.a, pair.pi, Ho, lambda k: pair.xo(0, k, tb, 66, "t"), 0, c)), range(7))
+    for c in range(7):
+        assert np.array_equal(got[0, c, 0], want[c]), c
+
+
+# --------------------------------------------------------------------------
+# exactness invariants of the launch configuration
+# --------------------------------------------------------------------------
+
+def test_chunking_and_order_invariance():
+    X, y = synth.prototype_bits(8, 6, 40, 4, flip=0.2)
+    pair = Pair(1024, 2, 64, 40, 4, 10, X, y, seed=5)
+    xr = pair.encrypt_dev()
+    yr = pair.encrypt_labels_dev()
+    sh = pair.shape
+    H1 = zeros_u32(pair.k0, pair.k1, 2, 2, 1024)
+    pair.ctx.train(sh, xr, yr, 6, H1, None)
+    # two calls over disjoint halves (pointer offsets) give the same bits
+    H2 = zeros_u32(pair.k0, pair.k1, 2, 2, 1024)
+    pair.ctx.train(sh, xr[:3 * 40], yr[:3 * 2], 3, H2, None)
+    pair.ctx.train(sh, xr[3 * 40:], yr[3 * 2:], 3, H2, None)
+    assert np.array_equal(host_u32(H1), host_u32(H2))
+    # a context whose workspace holds one sample at a time (many sub-batches)
+    os.environ["HWISARD_WS_BYTES"] = "1"
+    try:
+        from paper_2403_20190_amd import hwisard as HW
+        small = HW.Context(1024, 2, 64)
+    finally:
+        del os.environ["HWISARD_WS_BYTES"]
+    H3 = zeros_u32(pair.k0, pair.k1, 2, 2, 1024)
+    small.train(sh, xr, yr, 6, H3, None)
+    assert np.array_equal(host_u32(H1), host_u32(H3))
+    # repeated runs are identical
+    H4 = zeros_u32(pair.k0, pair.k1, 2, 2, 1024)
+    pair.ctx.train(sh, xr, yr, 6, H4, None)
+    assert np.array_equal(host_u32(H1), host_u32(H4))
+
+
+def test_argument_checks():
+    from paper_2403_20190_amd import hwisard as HW
+    ctx = HW.Context(1024, 1, 64)
+    H = zeros_u32(1, 1, 2, 1, 1024)
+    with pytest.raises(HW.HwError) as e:
+        ctx.train(HW.shape(0, 2, 8, 1), H, H, 1, H)
+    assert e.value.status == HW.HW_EINVAL
+    with pytest.raises(HW.HwError):
+        ctx.train(HW.shape(16, 2, 0, 1), H, H, 1, H)
+    with pytest.raises(HW.HwError) as e:
+        HW.Context(1000, 1, 64)
+    assert e.value.status == HW.HW_EUNSUPPORTED
+    with pytest.raises(HW.HwError):
+        HW.Context(1024, 1, 63)
+    # n = 0 is a no-op
+    before = host_u32(H).copy()
+    ctx.train(HW.shape(16, 2, 8, 1), H, H, 0, H)
+    assert np.array_equal(host_u32(H), before)

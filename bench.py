@@ -1,0 +1,340 @@
+#!/usr/bin/env python3
+"""Benchmark of the encrypted WiSARD hot path on one MI355X.
+
+Workload (default): MNIST-shaped synthetic data -- 28x28 uint8 images, 10
+balanced classes, 3-level thermometer code (s = 2352 bits), tuple size 12
+(196 RAMs), 1000 training + 1000 test samples, RLWE N = 2048 with two 30-bit
+primes, plaintext modulus 1024.
+
+A step is one encrypted training pass over the 1000 training samples: the
+client-side RGSW encryption of every input and label bit (on the device, from
+thermometer bits resident in HBM) followed by homomorphic training (Alg. 6)
+into a zeroed model, chunk by chunk.  `value` = training samples per second of
+that whole step.  After the timed steps the same run measures, untimed by the
+step clock: kernel-level times (HIP events on the launch stream), encrypted
+inference of the 1000 test samples with PD-act decoding, a batched NTT, the
+oracle on the host cores (cpu_baseline) and the roofline of the dominant
+kernel.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks used for the roofline fractions
+PEAK_HBM_GBS = 8000.0
+CU, LANES, CLOCK_GHZ = 256, 64, 2.4
+PEAK_INT32_TOPS = CU * LANES * CLOCK_GHZ / 1000.0  # 39.32 T 32-bit lane ops/s
+
+WORKLOADS = {
+    "mnist": dict(name="mnist-shaped 28x28x1, 10 classes, therm 3, tuple 12, 1000 train + 1000 test, N=2048 x 2 primes",
+                  N=2048, nq=2, p=1024, l=10, a=12, T=3, n_train=1000, n_test=1000, chunk=50, balance=False),
+    "ham": dict(name="ham10000-shaped 28x28x3, 7 skewed classes, therm 2, tuple 12, 10000 train + 1000 test, N=4096 x 3 primes",
+                N=4096, nq=3, p=16384, l=7, a=12, T=2, n_train=10000, n_test=1000, chunk=10, balance=True),
+    "tiny": dict(name="tiny 8x8, 2 classes, therm 2, tuple 8, 32 train + 16 test, N=1024 x 1 prime",
+                 N=1024, nq=1, p=64, l=2, a=8, T=2, n_train=32, n_test=16, chunk=32, balance=False),
+}
+
+
+def ops_per_xp(N: int, nq: int) -> float:
+    """Algorithmic 32-bit integer operations of one external product.
+
+    Model: a forward (Cooley-Tukey, Harvey lazy) butterfly = 9 ops (Shoup
+    product 4, lazy correction 2, add 1, sub 2); an inverse (Gentleman-Sande)
+    butterfly = 9 ops; the 1/N scaling 6 ops per coefficient; a
+    multiply-accumulate term = 2 ops (32x32->64 product, 64-bit add); a
+    balanced digit = 6 ops (extract 3, lift 2, shift 1).  Per product: 10 nq^2
+    forward and 2 nq inverse NTTs of (N/2) log2 N butterflies, 20 nq^2 N MAC
+    terms, 10 nq^2 N digit coefficients."""
+    logN = N.bit_length() - 1
+    bf = (N // 2) * logN
+    return (9.0 * bf * (10 * nq * nq + 2 * nq) + 6.0 * N * 2 * nq + 2.0 * 20 * nq * nq * N
+            + 6.0 * 10 * nq * nq * N)
+
+
+def modmul_per_xp(N: int, nq: int) -> float:
+    """Modular multiplications of one external product:
+    (2 l nq^2 + 2 nq) (N/2) log2 N + 4 l nq^2 N with l = 5 digits."""
+    logN = N.bit_length() - 1
+    return (10 * nq * nq + 2 * nq) * (N // 2) * logN + 20 * nq * nq * N
+
+
+def rgsw_bytes(N: int, nq: int) -> int:
+    """2D rows x 2 polynomials x nq residues x N words"""
+    return 2 * 5 * nq * 2 * nq * N * 4
+
+
+def gen_data(wl: str, W: dict):
+    from paper_2403_20190_amd import synth
+    if wl == "mnist":
+        return synth.mnist_like(1, per_class_train=W["n_train"] // 10, per_class_test=W["n_test"] // 10)
+    if wl == "ham":
+        return synth.ham_like(3, n_train=W["n_train"], n_test=W["n_test"])
+    return synth.tiny(0, W["n_train"], W["n_test"])
+
+
+def cpu_baseline(W: dict, Xtr, ytr, threads: int, seeds: dict):
+    """The oracle, as it is, on a bounded sample: client encryption plus
+    homomorphic training of ONE training sample over every RAM."""
+    import numpy as np
+
+    import oracle as O
+    from oracle import plain as P
+    N, nq, p, l, a, T = W["N"], W["nq"], W["p"], W["l"], W["a"], W["T"]
+    orc = O.Ctx(N, nq, p)
+    bits = P.encode(P.quantize_u8(Xtr[:1], T), T)
+    s = bits.shape[1]
+    L = O.ceil_log2(l)
+    sk = orc.keygen(seeds["key"])
+    pi = O.permutation(seeds["perm"], s)
+    k0, k1 = -(-s // a), orc.k1(s, l, a)
+    t0 = time.perf_counter()
+    xr = {}
+    yr = {}
+
+    def enc_x(k):
+        xr[k] = orc.enc_rgsw(sk, int(bits[0, k]), seeds["x"], k)
+
+    def enc_y(u):
+        yr[u] = orc.enc_rgsw(sk, (int(ytr[0]) >> u) & 1, seeds["y"], u)
+
+    O._parallel(enc_x, range(s), threads)
+    O._parallel(enc_y, range(L), threads)
+    H = np.zeros((k0, k1, 2, nq, N), np.uint32)
+    orc.train(s, l, a, pi, lambda i, k: xr[k], lambda i, u: yr[u], 1, H, threads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=1.0 / dt, unit="samples/s", cores=threads, kind="oracle",
+                sample="1 training sample: oracle encryption of its %d RGSW + IVP training of all %d RAMs "
+                       "(%.1f s on %d threads)" % (s + L, k0, dt, threads))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mnist", choices=sorted(WORKLOADS))
+    ap.add_argument("--n-train", type=int, default=None, help="override the number of training samples")
+    ap.add_argument("--chunk", type=int, default=None, help="samples encrypted and trained per call")
+    ap.add_argument("--no-extras", action="store_true", help="only the timed steps (for profiler runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", type=int, default=0, help="also run a plain device copy of this many MiB")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; multi-GPU sharding is designed but not run "
+              "(see DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2403_20190_amd import client as CL
+    from paper_2403_20190_amd import hwisard as HW
+
+    W = dict(WORKLOADS[args.workload])
+    if args.n_train:
+        W["n_train"] = args.n_train
+    if args.chunk:
+        W["chunk"] = args.chunk
+    torch.cuda.set_device(0)
+    N, nq, p, l, a, T = W["N"], W["nq"], W["p"], W["l"], W["a"], W["T"]
+    seeds = dict(key=11, x=12, y=13, perm=14, xt=15)
+    Xtr, ytr, Xte, yte = gen_data(args.workload, W)
+    Xtr, ytr = Xtr[:W["n_train"]], ytr[:W["n_train"]]
+    n = len(Xtr)
+    bits_tr = CL.thermometer(CL.quantize_u8(Xtr, T), T)
+    s = bits_tr.shape[1]
+    L = CL.ceil_log2(l)
+    lab_tr = CL.label_bits(ytr, l)
+    ctx = HW.Context(N, nq, p)
+    sh = HW.shape(s, l, a, seeds["perm"])
+    k0, k1, model_bytes = ctx.dims(sh)
+    dev = torch.device("cuda:0")
+    # inputs resident in HBM before timing: thermometer bits, label bits, key
+    xb = torch.from_numpy(bits_tr).to(dev)
+    yb = torch.from_numpy(lab_tr).to(dev)
+    sk = torch.zeros(N, dtype=torch.int32, device=dev)
+    ctx.keygen(seeds["key"], sk)
+    chunk = W["chunk"]
+    xr = torch.empty(chunk * s, ctx.rgsw_words, dtype=torch.int32, device=dev)
+    yr = torch.empty(max(1, chunk * L), ctx.rgsw_words, dtype=torch.int32, device=dev)
+    H = torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(2, nq, N, dtype=torch.int32, device=dev) if W["balance"] else None
+
+    def train_step():
+        H.zero_()
+        if cnt is not None:
+            cnt.zero_()
+        for c0 in range(0, n, chunk):
+            m = min(chunk, n - c0)
+            ctx.encrypt_rgsw_bits(sk, xb[c0:c0 + m].reshape(-1), seeds["x"], c0 * s, xr[:m * s])
+            if L:
+                ctx.encrypt_rgsw_bits(sk, yb[c0:c0 + m].reshape(-1), seeds["y"], c0 * L, yr[:m * L])
+            ctx.train(sh, xr, yr, m, H, cnt)
+
+    print("bench: workload %s, n_train %d, chunk %d, k0 %d, k1 %d" % (args.workload, n, chunk, k0, k1),
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        train_step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        train_step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    value = n / (ms_per_step / 1000.0)
+    tr_ms, tr_launch, tr_xp = ctx.profile_read("train")
+    rd_ms, _, _ = ctx.profile_read("reduce")
+    en_ms, en_launch, en_rows = ctx.profile_read("encrypt_rgsw")
+    ctx.profile(False)
+    print("bench: %.1f ms/step, %.2f samples/s" % (ms_per_step, value), file=sys.stderr, flush=True)
+
+    if args.calib_copy:
+        src = torch.empty(args.calib_copy * (1 << 20) // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    steps_xp = tr_xp / args.steps
+    train_kernel_ms = tr_ms / args.steps
+    opx = ops_per_xp(N, nq)
+    result = {
+        "metric": "encrypted train samples/s",
+        "value": round(value, 3),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": W["name"], "n_train": n, "s": s, "k0": k0, "k1": k1,
+                   "chunk": chunk, "step": "device RGSW encryption + homomorphic training of n_train samples"},
+    }
+    a_ops = tr_xp / tr_launch * opx / (tr_ms / tr_launch / 1000.0) / 1e12 if tr_launch else 0.0
+    result["roofline"] = {
+        "bound": "alu", "kernel": "k_train", "achieved": round(a_ops, 3), "peak": round(PEAK_INT32_TOPS, 2),
+        "unit": "TOPS(int32)", "frac": round(a_ops / PEAK_INT32_TOPS, 4), "traffic": None,
+        "launches": tr_launch, "avg_launch_ms": round(tr_ms / max(1, tr_launch), 3),
+        "xp_per_launch": tr_xp / max(1, tr_launch), "ops_per_xp": opx,
+    }
+    result["kernels"] = {
+        "train_ms_per_step": round(train_kernel_ms, 2),
+        "reduce_ms_per_step": round(rd_ms / args.steps, 2),
+        "encrypt_ms_per_step": round(en_ms / args.steps, 2),
+        "train_only_samples_per_s": round(n / (train_kernel_ms / 1000.0), 3) if train_kernel_ms else None,
+        "encrypt_only_samples_per_s": round(n / (en_ms / args.steps / 1000.0), 3) if en_ms else None,
+        "xp_per_s": round(steps_xp / (train_kernel_ms / 1000.0), 1) if train_kernel_ms else None,
+        "ntt_per_s_in_xp": round(steps_xp * (10 * nq * nq + 2 * nq) / (train_kernel_ms / 1000.0), 1)
+        if train_kernel_ms else None,
+        "modmul_per_s": round(steps_xp * modmul_per_xp(N, nq) / (train_kernel_ms / 1000.0), 1)
+        if train_kernel_ms else None,
+        "rgsw_read_gbs": round(steps_xp * rgsw_bytes(N, nq) / (train_kernel_ms / 1000.0) / 1e9, 1)
+        if train_kernel_ms else None,
+    }
+
+    del xr, yr, xb, yb
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        result["inference"] = infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev)
+        result["ntt"] = ntt_pass(ctx, N, nq, dev)
+        result["hbm_copy_gbs"] = hbm_copy(dev)
+    if not args.no_cpu_baseline and not args.no_extras:
+        result["cpu_baseline"] = cpu_baseline(W, Xtr, ytr, min(16, os.cpu_count() or 1), seeds)
+    print(json.dumps(result), flush=True)
+
+
+def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
+    """Encrypted inference of the test set (device encryption + VP + PD-act)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_20190_amd import client as CL
+    T, l = W["T"], W["l"]
+    bits = CL.thermometer(CL.quantize_u8(Xte[:W["n_test"]], T), T)
+    nt, s = bits.shape
+    xb = torch.from_numpy(bits).to(dev)
+    chunk = max(1, W["chunk"])
+    xr = torch.empty(chunk * s, ctx.rgsw_words, dtype=torch.int32, device=dev)
+    scores = torch.empty(chunk, l, k0, ctx.lwe_words, dtype=torch.int32, device=dev)
+    dec = torch.empty(chunk * l * k0, dtype=torch.int64, device=dev)
+    cells = np.zeros((nt, l, k0), np.int64)
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c0 in range(0, nt, chunk):
+        m = min(chunk, nt - c0)
+        ctx.encrypt_rgsw_bits(sk, xb[c0:c0 + m].reshape(-1), seeds["xt"], c0 * s, xr[:m * s])
+        ctx.infer(sh, H, xr, m, scores, None)
+        ctx.decrypt_lwe(sk, scores, m * l * k0, dec)
+        cells[c0:c0 + m] = dec[:m * l * k0].cpu().numpy().reshape(m, l, k0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    inf_ms, inf_launch, inf_xp = ctx.profile_read("infer")
+    ctx.profile(False)
+    pred = CL.pd_act_predict(cells, "bin")
+    acc = float((pred == np.asarray(yte[:nt])).mean())
+    return {
+        "samples_per_s": round(nt / dt, 3),
+        "infer_kernel_samples_per_s": round(nt / (inf_ms / 1000.0), 3) if inf_ms else None,
+        "xp_per_s": round(inf_xp / (inf_ms / 1000.0), 1) if inf_ms else None,
+        "n_test": nt, "pd_act": "bin", "test_accuracy": round(acc, 4),
+    }
+
+
+def ntt_pass(ctx, N, nq, dev):
+    """Batched standalone NTT: 2^15 polynomials, forward then inverse."""
+    import torch
+    count = 1 << 15
+    polys = torch.randint(0, min(ctx.primes), (count, nq, N), dtype=torch.int32, device=dev)
+    ctx.ntt(polys, count, False)
+    ctx.ntt(polys, count, True)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_reset()
+    for _ in range(3):
+        ctx.ntt(polys, count, False)
+        ctx.ntt(polys, count, True)
+    ms, launches, work = ctx.profile_read("ntt")
+    ctx.profile(False)
+    nt_s = work / (ms / 1000.0)
+    bytes_moved = work * N * 4 * 2  # read + write per transform
+    return {"polys": count * nq, "ntt_per_s": round(nt_s, 1), "gbs": round(bytes_moved / (ms / 1000.0) / 1e9, 1),
+            "hbm_frac": round(bytes_moved / (ms / 1000.0) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
+def hbm_copy(dev):
+    import torch
+    n = (4 << 30) // 4
+    a = torch.ones(n, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    return round(2 * n * 4 / (ms / 1000.0) / 1e9, 1)
+
+
+if __name__ == "__main__":
+    main()

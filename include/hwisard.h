@@ -48,7 +48,7 @@ typedef enum {
   HW_ECANCELLED = -6     /* serving engine: request cancelled */
 } hw_status;
 
-/* One RLWE parameter set (Setup, Sec. 2.4.1).  The paper fixes a 64-bit torus
+/* One RLWE parameter set (Setup, Sec. 2.5.1).  The paper fixes a 64-bit torus
  * modulus (Table 2); this library uses residues modulo 30-bit NTT-friendly
  * primes instead. */
 typedef struct {
@@ -104,7 +104,7 @@ hw_status hw_wisard_dims(const hw_ctx* ctx, const hw_wisard_shape* shape, uint32
  * input is t[k] = x[pi[k]]. */
 hw_status hw_permutation(const hw_wisard_shape* shape, uint32_t* perm_host);
 
-/* ---- client side (Sec. 2.4.1), run on the device for throughput ---------- */
+/* ---- client side (Sec. 2.5.1), run on the device for throughput ---------- */
 
 /* SecretKeyGen: ternary RLWE key s_k = (w64(seed, KEY, k) mod 3) - 1.
  * sk_dev: int32[N]. */
@@ -151,7 +151,7 @@ hw_status hw_rgsw_export_canonical(hw_ctx* ctx, const uint32_t* rgsw_dev, uint64
 hw_status hw_ntt(hw_ctx* ctx, uint32_t* polys_dev, uint64_t count, int inverse,
                  hipStream_t stream);
 
-/* External product (Sec. 2.4.1): out[k] = rgsw[k] [.] in[k] for k < count,
+/* External product (Sec. 2.5.1): out[k] = rgsw[k] [.] in[k] for k < count,
  * i.e. sum_{i,j} dec(b)_{i,j} C[i*digits+j] + sum_{i,j} dec(a)_{i,j}
  * C[D+i*digits+j] with balanced base-2^6 digits of the centered residues.
  * in_dev/out_dev: RLWE[count]; rgsw_dev: RGSW[count] in device layout.
@@ -185,6 +185,25 @@ hw_status hw_wisard_infer_encrypted(hw_ctx* ctx, const hw_wisard_shape* shape,
                                     const uint32_t* model_dev, const uint32_t* x_rgsw_dev,
                                     uint64_t n, uint32_t* ram_scores_dev,
                                     uint32_t* class_scores_dev, hipStream_t stream);
+
+/* ---- per-kernel timing ------------------------------------------------------ */
+
+/* While enabled, every kernel launch made by the calls of this context is
+ * bracketed by a pair of HIP events recorded on the caller's stream.  Kernel
+ * names: "train", "reduce", "infer", "class_sums", "encrypt_rgsw",
+ * "encrypt_rlwe", "decrypt_rlwe", "decrypt_lwe", "xp", "ntt". */
+hw_status hw_profile_enable(hw_ctx* ctx, int enable);
+
+/* Waits for the recorded events and returns, for kernel `name`, the summed
+ * event time in ms, the number of launches and the algorithmic work those
+ * launches did: external products for "train", "infer" and "xp", ciphertext
+ * rows for the encryptions, polynomials for "ntt" and the decryptions, model
+ * or output words for the reductions.  Unknown names give zeros. */
+hw_status hw_profile_read(hw_ctx* ctx, const char* name, double* total_ms, uint64_t* launches,
+                          double* work);
+
+/* Drop every accumulated record. */
+hw_status hw_profile_reset(hw_ctx* ctx);
 
 #ifdef __cplusplus
 }

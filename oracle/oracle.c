@@ -8,9 +8,9 @@
  *
  * What it computes, in the paper's terms:
  *   ring R_q = Z_q[X]/(X^N+1)                          (Sec. 2.1, Notation)
- *   SecretKeyGen / EncRLWE / EncRGSW / DecRLWE / DecLWE (Sec. 2.4.1)
- *   external product, CMUX, ExtractLWE, BlindRotate     (Sec. 2.4.1)
- *   Vertical Packing                                    (Sec. 2.4.2, Alg. 3)
+ *   SecretKeyGen / EncRLWE / EncRGSW / DecRLWE / DecLWE (Sec. 2.5.1)
+ *   external product, CMUX, ExtractLWE, BlindRotate     (Sec. 2.5.1)
+ *   Vertical Packing                                    (Sec. 2.5.2, Alg. 3)
  *   CDEMUX gate and tree, Inverse Vertical Packing      (Sec. 3.3, Alg. 5)
  *   homomorphic training                                (Sec. 3.4, Alg. 6)
  *   homomorphic inference, PD-act branch                (Sec. 3.6, Alg. 7)
@@ -423,7 +423,7 @@ void orc_rlwe_rotate(const orc_ctx* c, const uint32_t* in, int64_t e, uint32_t* 
 }
 
 /* ------------------------------------------------------------------------ */
-/* keys, encryption, decryption (Sec. 2.4.1)                                 */
+/* keys, encryption, decryption (Sec. 2.5.1)                                 */
 /* ------------------------------------------------------------------------ */
 
 /* ternary secret s_k = (w64(seed, KEY, k) mod 3) - 1; the paper samples a
@@ -477,7 +477,7 @@ void orc_enc_rlwe(const orc_ctx* c, const int32_t* s, const uint64_t* mu, uint64
 /* EncRGSW of a bit m: 2D rows, each an encryption of 0, plus m * g_{i,j} on
  * residue i of the b part (rows i*digits+j) or of the a part (rows
  * D + i*digits + j), g_{i,j} = base^j.  The paper's gadget entry carries a
- * stray 1/p factor (Sec. 2.4.1, EncRGSW); the exact gadget base^j is the
+ * stray 1/p factor (Sec. 2.5.1, EncRGSW); the exact gadget base^j is the
  * reading taken here, in its RNS form (one gadget row per prime and digit). */
 void orc_enc_rgsw(const orc_ctx* c, const int32_t* s, uint32_t m, uint64_t seed, uint64_t ct,
                   uint32_t* out) {
@@ -524,7 +524,7 @@ static u128 crt(const orc_ctx* c, const uint64_t* x) {
 }
 
 /* decode: mu = floor((p*phi + floor(Q/2)) / Q) mod p, i.e. phi/Delta rounded
- * half up (the paper's rounding of (b - <a,s>)/(q/p), Sec. 2.4.1) */
+ * half up (the paper's rounding of (b - <a,s>)/(q/p), Sec. 2.5.1) */
 static uint64_t decode(const orc_ctx* c, u128 phi) {
   u128 num = (u128)c->p * phi + c->Q / 2;
   return (uint64_t)((num / c->Q) % c->p);
@@ -584,7 +584,7 @@ double orc_noise_rlwe(const orc_ctx* c, const int32_t* s, const uint32_t* ct, co
   return mx;
 }
 
-/* DecLWE: phi = b - <a, s> (Sec. 2.4.1) then the same rounding */
+/* DecLWE: phi = b - <a, s> (Sec. 2.5.1) then the same rounding */
 void orc_dec_lwe(const orc_ctx* c, const int32_t* s, const uint32_t* lwe, uint64_t* mu) {
   uint32_t N = c->N, nq = c->nq;
   uint64_t x[ORC_MAXQ];
@@ -632,7 +632,7 @@ void orc_decompose(const orc_ctx* c, const uint32_t* poly, int32_t* out) {
 /* External product C [.] (a, b) = sum_{i,j} dec(b)_{i,j} * C[B(i,j)]
  *                               + sum_{i,j} dec(a)_{i,j} * C[A(i,j)]
  * with B(i,j) = i*digits + j and A(i,j) = D + i*digits + j; each digit
- * polynomial is lifted into every prime (Sec. 2.4.1, multiplication). */
+ * polynomial is lifted into every prime (Sec. 2.5.1, multiplication). */
 void orc_extprod(const orc_ctx* c, const uint32_t* C, const uint32_t* in, uint32_t* out) {
   uint32_t N = c->N, nq = c->nq, D = c->D;
   size_t rw = rlwe_words(c);
@@ -670,7 +670,7 @@ void orc_cmux(const orc_ctx* c, const uint32_t* C, const uint32_t* d1, const uin
 
 /* BlindRotate: for t = 0, 1, ..., k-1: acc <- CMUX(C_t, X^{e_t} acc, acc).
  * With C_t encrypting S_t the result encrypts v * X^{sum_t S_t e_t}; the
- * paper's I_t is -e_t (Sec. 2.4.1). */
+ * paper's I_t is -e_t (Sec. 2.5.1). */
 void orc_blind_rotate(const orc_ctx* c, const uint32_t* in, const uint32_t* const* C,
                       const int64_t* e, uint32_t k, uint32_t* out) {
   size_t rw = rlwe_words(c);

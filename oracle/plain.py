@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE: only tests, the smoke check and the CPU-baseline leg of
 the benchmark use it.
 
-* quantisation and thermometer encoding (Sec. 2.2.3-2.2.4)
+* quantisation and thermometer encoding (Sec. 2.4.2-2.4.3)
 * f_comp and the Integer WiSARD: training (Alg. 4), evaluation (Alg. 2)
 * activations used with PD-act (Sec. 3.2, 3.5.1) and ArgMax
 * the layout map from a plaintext model W to the decrypted cells of the
@@ -19,13 +19,13 @@ from . import ceil_log2, permutation
 # -- client preprocessing ------------------------------------------------------
 
 def thermometer(x: int, size: int) -> list[int]:
-    """T_size(x): t_i = 1 for i < x, 0 otherwise (Sec. 2.2.4)."""
+    """T_size(x): t_i = 1 for i < x, 0 otherwise (Sec. 2.4.3)."""
     return [1 if i < x else 0 for i in range(size)]
 
 
 def quantize_u8(v: np.ndarray, levels: int) -> np.ndarray:
     """Linear quantisation of uint8 values to [0, levels]:
-    min(levels, floor(v * (levels + 1) / 256)) (Sec. 2.2.3 with r = 256/(levels+1))."""
+    min(levels, floor(v * (levels + 1) / 256)) (Sec. 2.4.2 with r = 256/(levels+1))."""
     v = np.asarray(v, np.int64)
     return np.minimum(levels, (v * (levels + 1)) // 256)
 

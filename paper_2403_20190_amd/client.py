@@ -1,7 +1,7 @@
 """Client-side steps around the encrypted path (numpy, vectorised).
 
-* preprocessing: linear / min-max quantisation (Sec. 2.2.3) and thermometer
-  encoding (Sec. 2.2.4) of each sample on its own;
+* preprocessing: linear / min-max quantisation (Sec. 2.4.2) and thermometer
+  encoding (Sec. 2.4.3) of each sample on its own;
 * label bits, LSB first (Alg. 6 feeds them before the tuple bits);
 * PD-act (Sec. 3.5.1): decrypted per-RAM cells -> activation -> sum ->
   ArgMax, ties to the lowest class.

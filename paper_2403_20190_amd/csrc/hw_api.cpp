@@ -4,11 +4,13 @@
 // orchestration of the kernels in hw_kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -159,7 +161,36 @@ struct hw_ctx {
   uint64_t perm_seed = 0;
   bool perm_valid = false;
   std::vector<uint32_t> h_perm;
+  // per-kernel timing
+  bool prof = false;
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+    double work;
+  };
+  std::vector<Rec> pending;
+  struct Acc {
+    double ms = 0, work = 0;
+    uint64_t launches = 0;
+  };
+  std::map<std::string, Acc> acc;
 };
+
+// run `launch` between two events on `st` when profiling is on
+template <class F>
+static hipError_t timed(hw_ctx* c, const char* name, double work, hipStream_t st, F&& launch) {
+  if (!c->prof) return launch();
+  hw_ctx::Rec r{name, nullptr, nullptr, work};
+  hipError_t e = hipEventCreate(&r.a);
+  if (e == hipSuccess) e = hipEventCreate(&r.b);
+  if (e == hipSuccess) e = hipEventRecord(r.a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(r.b, st);
+  if (e == hipSuccess) c->pending.push_back(r);
+  return e;
+}
 
 static size_t rlwe_words(const hw_ctx* c) { return (size_t)2 * c->prm.nq * c->prm.N; }
 static size_t rgsw_words(const hw_ctx* c) { return (size_t)2 * 5 * c->prm.nq * rlwe_words(c); }
@@ -418,7 +449,8 @@ extern "C" hw_status hw_encrypt_rgsw_bits(hw_ctx* c, const int32_t* sk, const ui
   A.seed = seed;
   A.ct0 = ct0;
   A.log_base = c->prm.log_base;
-  HIP_TRY(hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, nbits, st));
+  HIP_TRY(timed(c, "encrypt_rgsw", (double)nbits * 10 * c->prm.nq, st,
+                [&] { return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, nbits, st); }));
   return ok();
 }
 
@@ -436,7 +468,8 @@ extern "C" hw_status hw_encrypt_rlwe(hw_ctx* c, const int32_t* sk, const uint64_
   A.seed = seed;
   A.ct0 = ct0;
   A.log_base = c->prm.log_base;
-  HIP_TRY(hw::launch_enc_rlwe(c->logN, c->prm.nq, c->tabs, c->cdt, A, count, st));
+  HIP_TRY(timed(c, "encrypt_rlwe", (double)count, st,
+                [&] { return hw::launch_enc_rlwe(c->logN, c->prm.nq, c->tabs, c->cdt, A, count, st); }));
   return ok();
 }
 
@@ -446,7 +479,9 @@ extern "C" hw_status hw_decrypt_rlwe(hw_ctx* c, const int32_t* sk, const uint32_
   if (count == 0) return ok();
   if (!ct || !msg) return fail(HW_EINVAL, "null buffer");
   CHECK(sk_hat(c, sk, st));
-  HIP_TRY(hw::launch_dec_rlwe(c->logN, c->prm.nq, c->tabs, c->crt, c->d_skhat, ct, count, msg, st));
+  HIP_TRY(timed(c, "decrypt_rlwe", (double)count, st, [&] {
+    return hw::launch_dec_rlwe(c->logN, c->prm.nq, c->tabs, c->crt, c->d_skhat, ct, count, msg, st);
+  }));
   return ok();
 }
 
@@ -455,7 +490,8 @@ extern "C" hw_status hw_decrypt_lwe(hw_ctx* c, const int32_t* sk, const uint32_t
   CHECK(enter(c));
   if (count == 0) return ok();
   if (!sk || !lwe || !msg) return fail(HW_EINVAL, "null buffer");
-  HIP_TRY(hw::launch_dec_lwe(c->logN, c->prm.nq, c->tabs, c->crt, sk, lwe, count, msg, st));
+  HIP_TRY(timed(c, "decrypt_lwe", (double)count, st,
+                [&] { return hw::launch_dec_lwe(c->logN, c->prm.nq, c->tabs, c->crt, sk, lwe, count, msg, st); }));
   return ok();
 }
 
@@ -474,7 +510,8 @@ extern "C" hw_status hw_ntt(hw_ctx* c, uint32_t* polys, uint64_t count, int inve
   if (count == 0) return ok();
   if (!polys) return fail(HW_EINVAL, "null buffer");
   if (inverse != 0 && inverse != 1) return fail(HW_EINVAL, "inverse must be 0 or 1");
-  HIP_TRY(hw::launch_ntt(c->logN, c->prm.nq, c->tabs, polys, count, inverse, st));
+  HIP_TRY(timed(c, "ntt", (double)count * c->prm.nq, st,
+                [&] { return hw::launch_ntt(c->logN, c->prm.nq, c->tabs, polys, count, inverse, st); }));
   return ok();
 }
 
@@ -484,7 +521,8 @@ extern "C" hw_status hw_external_product(hw_ctx* c, const uint32_t* rgsw, const 
   if (count == 0) return ok();
   if (!rgsw || !in || !out) return fail(HW_EINVAL, "null buffer");
   if (in == out) return fail(HW_EINVAL, "output must not alias input");
-  HIP_TRY(hw::launch_xp(c->logN, c->prm.nq, c->tabs, rgsw, in, count, out, st));
+  HIP_TRY(timed(c, "xp", (double)count, st,
+                [&] { return hw::launch_xp(c->logN, c->prm.nq, c->tabs, rgsw, in, count, out, st); }));
   return ok();
 }
 
@@ -533,12 +571,20 @@ extern "C" hw_status hw_wisard_train_encrypted(hw_ctx* c, const hw_wisard_shape*
   R.N = c->prm.N;
   R.nq = c->prm.nq;
   const uint32_t nram = d.k0 + (class_count ? 1 : 0);
+  // external products per sample: the rotation chain and the CDEMUX tree of every RAM
+  double xp_per_sample = 0;
+  for (uint32_t j = 0; j < nram; ++j) {
+    const uint32_t nb = j < d.k0 ? d.L + std::min(sh->a, sh->s - j * sh->a) : d.L;
+    const uint32_t nr = std::min(nb, (uint32_t)c->logN);
+    xp_per_sample += nr + ((1u << (nb - nr)) - 1);
+  }
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
     const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
     A.i0 = i0;
-    HIP_TRY(hw::launch_train(c->logN, c->prm.nq, c->tabs, A, nram, (uint32_t)m, st));
+    HIP_TRY(timed(c, "train", (double)m * xp_per_sample, st,
+                  [&] { return hw::launch_train(c->logN, c->prm.nq, c->tabs, A, nram, (uint32_t)m, st); }));
     R.n_sub = m;
-    HIP_TRY(hw::launch_reduce_model(c->tabs, R, st));
+    HIP_TRY(timed(c, "reduce", (double)d.k0 * d.k1 * rw, st, [&] { return hw::launch_reduce_model(c->tabs, R, st); }));
   }
   return ok();
 }
@@ -560,6 +606,16 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
   if (n_sub > 65535) n_sub = 65535;
   CHECK(ensure_ws(c, n_sub * per_sample));
   CHECK(ensure_perm(c, sh, st));
+  // external products per sample: for every RAM and label, the encrypted
+  // selection levels and the encrypted positions of the rotation chain
+  double xp_per_sample = 0;
+  for (uint32_t j = 0; j < d.k0; ++j) {
+    const uint32_t nb = d.L + std::min(sh->a, sh->s - j * sh->a);
+    const uint32_t nr = std::min(nb, (uint32_t)c->logN), z = nb - nr;
+    const uint32_t tree = z > d.L ? (1u << (z - d.L)) - 1 : 0;
+    const uint32_t chain = z >= d.L ? nr : (nr > d.L - z ? nr - (d.L - z) : 0);
+    xp_per_sample += (double)sh->l * (tree + chain);
+  }
   hw::InferArgs A{};
   A.model = model;
   A.x_rgsw = x_rgsw;
@@ -577,7 +633,8 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
     const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
     A.i0 = i0;
-    HIP_TRY(hw::launch_infer(c->logN, c->prm.nq, c->tabs, A, (uint32_t)m, st));
+    HIP_TRY(timed(c, "infer", (double)m * xp_per_sample, st,
+                  [&] { return hw::launch_infer(c->logN, c->prm.nq, c->tabs, A, (uint32_t)m, st); }));
   }
   if (class_scores) {
     hw::SumArgs S{};
@@ -588,7 +645,54 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
     S.k0 = d.k0;
     S.N = c->prm.N;
     S.nq = c->prm.nq;
-    HIP_TRY(hw::launch_class_sums(c->tabs, S, st));
+    HIP_TRY(timed(c, "class_sums", (double)n * sh->l * lwe_words(c), st, [&] { return hw::launch_class_sums(c->tabs, S, st); }));
   }
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
+// per-kernel timing
+// ---------------------------------------------------------------------------
+
+extern "C" hw_status hw_profile_enable(hw_ctx* c, int enable) {
+  if (!c) return fail(HW_EINVAL, "null context");
+  c->prof = enable != 0;
+  return ok();
+}
+
+static hw_status drain(hw_ctx* c) {
+  for (auto& r : c->pending) {
+    HIP_TRY(hipEventSynchronize(r.b));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+    auto& a = c->acc[r.name];
+    a.ms += ms;
+    a.work += r.work;
+    a.launches += 1;
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  c->pending.clear();
+  return HW_OK;
+}
+
+extern "C" hw_status hw_profile_read(hw_ctx* c, const char* name, double* total_ms, uint64_t* launches,
+                                     double* work) {
+  if (!c || !name) return fail(HW_EINVAL, "null argument");
+  CHECK(enter(c));
+  CHECK(drain(c));
+  auto it = c->acc.find(name);
+  const hw_ctx::Acc a = it == c->acc.end() ? hw_ctx::Acc{} : it->second;
+  if (total_ms) *total_ms = a.ms;
+  if (launches) *launches = a.launches;
+  if (work) *work = a.work;
+  return ok();
+}
+
+extern "C" hw_status hw_profile_reset(hw_ctx* c) {
+  if (!c) return fail(HW_EINVAL, "null context");
+  CHECK(enter(c));
+  CHECK(drain(c));
+  c->acc.clear();
   return ok();
 }

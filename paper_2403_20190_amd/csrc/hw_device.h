@@ -2,7 +2,7 @@
 // 32-bit lanes, the workgroup-wide negacyclic NTT and the fused external
 // product (decompose -> NTT -> multiply-accumulate -> inverse NTT).
 //
-// Ring R_q = Z_q[X]/(X^N+1) (Sec. 2.1); external product of Sec. 2.4.1 with
+// Ring R_q = Z_q[X]/(X^N+1) (Sec. 2.1); external product of Sec. 2.5.1 with
 // an RNS gadget of base 2^6 and 5 digits per prime.
 //
 // Thread mapping.  One workgroup of T = N/8 threads owns one polynomial at a

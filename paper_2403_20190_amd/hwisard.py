@@ -60,6 +60,9 @@ _SIG = {
     "hw_external_product": [_vp, _vp, _vp, _u64, _vp, _vp],
     "hw_wisard_train_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_wisard_infer_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
+    "hw_profile_enable": [_vp, _i32],
+    "hw_profile_read": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(_u64), C.POINTER(C.c_double)],
+    "hw_profile_reset": [_vp],
 }
 for _n, _a in _SIG.items():
     _f = getattr(_lib, _n)
@@ -164,6 +167,19 @@ class Context:
 
     def external_product(self, rgsw, rin, count: int, rout):
         _check(_lib.hw_external_product(self._h, _ptr(rgsw), _ptr(rin), count, _ptr(rout), _stream()))
+
+    # -- per-kernel timing ----------------------------------------------------------
+    def profile(self, enable: bool = True):
+        _check(_lib.hw_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self, name: str):
+        """(total ms, launches, algorithmic work) accumulated for kernel `name`"""
+        ms, n, w = C.c_double(), _u64(), C.c_double()
+        _check(_lib.hw_profile_read(self._h, name.encode(), C.byref(ms), C.byref(n), C.byref(w)))
+        return ms.value, n.value, w.value
+
+    def profile_reset(self):
+        _check(_lib.hw_profile_reset(self._h))
 
     # -- server side ----------------------------------------------------------------
     def train(self, sh: Shape, x_rgsw, y_rgsw, n: int, model, class_count=None):

@@ -1,4 +1,4 @@
-"""Pins of the oracle's TFHE building blocks (Sec. 2.4.1, Alg. 3, Alg. 5):
+"""Pins of the oracle's TFHE building blocks (Sec. 2.5.1, Alg. 3, Alg. 5):
 noiseless special cases that must hold bit-exactly, decryption semantics of
 every gate including negacyclic signs, brute force of IVP and VP over every
 index on small rings, CRT decoding and noise health."""

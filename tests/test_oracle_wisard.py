@@ -1,4 +1,4 @@
-"""Pins of the oracle's WiSARD layer: the paper's worked examples (Sec. 2.2.4,
+"""Pins of the oracle's WiSARD layer: the paper's worked examples (Sec. 2.4.3,
 Fig. 1, Fig. 2), encrypted training against the plaintext Integer WiSARD
 (Alg. 4 vs Alg. 6, cell by cell), PD-act inference against Alg. 2, and the
 additivity of the encrypted model."""

@@ -125,6 +125,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", type=int, default=0, help="also run a plain device copy of this many MiB")
+    ap.add_argument("--batched-scale", type=float, nargs="*", default=[1.0 / 64, 1.0 / 512],
+                    help="job sizes of the 256-job batched workload are scaled by these factors")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU sharding is designed but not run "
@@ -254,6 +257,8 @@ def main():
         result["inference"] = infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev)
         result["ntt"] = ntt_pass(ctx, N, nq, dev)
         result["hbm_copy_gbs"] = hbm_copy(dev)
+        if not args.no_batched:
+            result["batched"] = [batched_pass(sc, dev) for sc in args.batched_scale]
     if not args.no_cpu_baseline and not args.no_extras:
         result["cpu_baseline"] = cpu_baseline(W, Xtr, ytr, min(16, os.cpu_count() or 1), seeds)
     print(json.dumps(result), flush=True)
@@ -317,6 +322,87 @@ def ntt_pass(ctx, N, nq, dev):
     bytes_moved = work * N * 4 * 2  # read + write per transform
     return {"polys": count * nq, "ntt_per_s": round(nt_s, 1), "gbs": round(bytes_moved / (ms / 1000.0) / 1e9, 1),
             "hbm_frac": round(bytes_moved / (ms / 1000.0) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
+def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
+    """256 uneven training jobs (sizes U{32..2000} x scale, s U{128..2352},
+    a U{8..12}, l U{2..10}, N 2048 or 4096): batched persistent launches versus
+    the same kernels one job at a time, on the same encrypted inputs.  Jobs of
+    one ring degree share a context (p = 4096 covers every job's counts)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_20190_amd import client as CL
+    from paper_2403_20190_amd import hwisard as HW
+    from paper_2403_20190_amd import synth
+    jobs = synth.batched_jobs(2)
+    groups = {}
+    for j, J in enumerate(jobs):
+        groups.setdefault(J["N"], []).append((j, J))
+    out = {"jobs": len(jobs), "scale": scale, "samples": 0, "xp": 0.0, "batched_ms": 0.0, "single_ms": 0.0,
+           "bit_identical": True}
+    for N, members in sorted(groups.items()):
+        nq = 2 if N == 2048 else 3
+        ctx = HW.Context(N, nq, 4096)
+        sk = torch.zeros(N, dtype=torch.int32, device=dev)
+        ctx.keygen(101, sk)
+        rg = ctx.rgsw_words * 4
+        window = []
+        used = 0
+
+        def run(window):
+            bufs = []
+            for j, J, n in window:
+                X, y = synth.prototype_bits(J["seed"] % (2 ** 31), n, J["s"], J["l"])
+                L = CL.ceil_log2(J["l"])
+                xr = torch.empty(n * J["s"], ctx.rgsw_words, dtype=torch.int32, device=dev)
+                ctx.encrypt_rgsw_bits(sk, torch.from_numpy(X.reshape(-1)).to(dev), 1000 + j, 0, xr)
+                yr = None
+                if L:
+                    yr = torch.empty(n * L, ctx.rgsw_words, dtype=torch.int32, device=dev)
+                    ctx.encrypt_rgsw_bits(sk, torch.from_numpy(CL.label_bits(y, J["l"]).reshape(-1)).to(dev),
+                                          2000 + j, 0, yr)
+                sh = HW.shape(J["s"], J["l"], J["a"], 3000 + j)
+                k0, k1, _ = ctx.dims(sh)
+                bufs.append((sh, xr, yr, n, k0, k1))
+            mb = [torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev) for (_, _, _, _, k0, k1) in bufs]
+            ms = [torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev) for (_, _, _, _, k0, k1) in bufs]
+            ctx.profile(True)
+            ctx.profile_reset()
+            torch.cuda.synchronize()
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record()
+            ctx.batch_train([(sh, xr, yr, n, m, None) for (sh, xr, yr, n, _, _), m in zip(bufs, mb)])
+            e1.record()
+            for (sh, xr, yr, n, _, _), m in zip(bufs, ms):
+                ctx.train(sh, xr, yr, n, m, None)
+            e2.record()
+            torch.cuda.synchronize()
+            out["batched_ms"] += e0.elapsed_time(e1)
+            out["single_ms"] += e1.elapsed_time(e2)
+            out["xp"] += ctx.profile_read("train_batch")[2]
+            ctx.profile(False)
+            out["samples"] += sum(b[3] for b in bufs)
+            out["bit_identical"] &= all(torch.equal(a, b) for a, b in zip(mb, ms))
+
+        for j, J in members:
+            n = max(1, int(round(J["n"] * scale)))
+            need = n * (J["s"] + 4) * rg
+            if window and used + need > window_bytes:
+                run(window)
+                window, used = [], 0
+            window.append((j, J, n))
+            used += need
+        if window:
+            run(window)
+        ctx.close()
+    out["batched_samples_per_s"] = round(out["samples"] / (out["batched_ms"] / 1000.0), 2)
+    out["single_job_samples_per_s"] = round(out["samples"] / (out["single_ms"] / 1000.0), 2)
+    out["batched_xp_per_s"] = round(out["xp"] / (out["batched_ms"] / 1000.0), 1)
+    out["speedup"] = round(out["single_ms"] / out["batched_ms"], 3)
+    out["batched_ms"] = round(out["batched_ms"], 1)
+    out["single_ms"] = round(out["single_ms"], 1)
+    return out
 
 
 def hbm_copy(dev):

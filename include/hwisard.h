@@ -186,11 +186,31 @@ hw_status hw_wisard_infer_encrypted(hw_ctx* ctx, const hw_wisard_shape* shape,
                                     uint64_t n, uint32_t* ram_scores_dev,
                                     uint32_t* class_scores_dev, hipStream_t stream);
 
+/* ---- batching ----------------------------------------------------------------- */
+
+typedef struct {
+  hw_wisard_shape shape;
+  const uint32_t* x_rgsw_dev;   /* [n][s] RGSW of the input bits */
+  const uint32_t* y_rgsw_dev;   /* [n][L] RGSW of the label bits (may be NULL when L = 0) */
+  uint64_t n;                   /* samples */
+  uint32_t* model_dev;          /* [k0][k1] RLWE, accumulated in place */
+  uint32_t* class_count_dev;    /* one RLWE or NULL */
+} hw_train_job;
+
+/* Batched homomorphic training (Alg. 6 for every job).  The jobs share this
+ * context's parameter set and may differ in shape and size.  They run as
+ * persistent launches over one queue of (job, sample, RAM) items, longest
+ * first, in windows whose per-sample output blocks fit the workspace; each
+ * window ends with one exact modular reduction into every job's model.  The
+ * result of each job is bit-identical to hw_wisard_train_encrypted on it.
+ * Jobs must not share model or counter buffers. */
+hw_status hw_batch_train(hw_ctx* ctx, const hw_train_job* jobs, uint32_t njobs, hipStream_t stream);
+
 /* ---- per-kernel timing ------------------------------------------------------ */
 
 /* While enabled, every kernel launch made by the calls of this context is
  * bracketed by a pair of HIP events recorded on the caller's stream.  Kernel
- * names: "train", "reduce", "infer", "class_sums", "encrypt_rgsw",
+ * names: "train", "reduce", "train_batch", "reduce_batch", "infer", "class_sums", "encrypt_rgsw",
  * "encrypt_rlwe", "decrypt_rlwe", "decrypt_lwe", "xp", "ntt". */
 hw_status hw_profile_enable(hw_ctx* ctx, int enable);
 

@@ -156,11 +156,13 @@ struct hw_ctx {
   void* d_ws = nullptr;            // workspace
   size_t ws_bytes = 0;
   size_t ws_budget = 0;
-  uint32_t* d_perm = nullptr;      // cached permutation
-  uint32_t perm_s = 0;
-  uint64_t perm_seed = 0;
-  bool perm_valid = false;
-  std::vector<uint32_t> h_perm;
+  // permutations on the device, by (s, seed)
+  std::map<std::pair<uint32_t, uint64_t>, uint32_t*> perms;
+  // batched training: job/item tables (pinned host staging, device copy), queue counter
+  void* h_btab = nullptr;
+  void* d_btab = nullptr;
+  size_t btab_bytes = 0;
+  uint32_t* d_counter = nullptr;
   // per-kernel timing
   bool prof = false;
   struct Rec {
@@ -304,7 +306,10 @@ extern "C" void hw_ctx_destroy(hw_ctx* c) {
   if (c->d_tables) hipFree(c->d_tables);
   if (c->d_skhat) hipFree(c->d_skhat);
   if (c->d_ws) hipFree(c->d_ws);
-  if (c->d_perm) hipFree(c->d_perm);
+  for (auto& kv : c->perms) hipFree(kv.second);
+  if (c->h_btab) hipHostFree(c->h_btab);
+  if (c->d_btab) hipFree(c->d_btab);
+  if (c->d_counter) hipFree(c->d_counter);
   delete c;
 }
 
@@ -387,22 +392,20 @@ static hw_status ensure_ws(hw_ctx* c, size_t bytes) {
   return HW_OK;
 }
 
-static hw_status ensure_perm(hw_ctx* c, const hw_wisard_shape* sh, hipStream_t st) {
-  if (c->perm_valid && c->perm_s == sh->s && c->perm_seed == sh->perm_seed) return HW_OK;
-  if (c->d_perm) {
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipFree(c->d_perm));
-    c->d_perm = nullptr;
+// the device permutation of (s, seed), uploaded once and kept with the context
+static hw_status perm_for(hw_ctx* c, const hw_wisard_shape* sh, hipStream_t st, const uint32_t** out) {
+  const auto key = std::make_pair(sh->s, sh->perm_seed);
+  auto it = c->perms.find(key);
+  if (it == c->perms.end()) {
+    std::vector<uint32_t> h(sh->s);
+    make_perm(sh->s, sh->perm_seed, h.data());
+    uint32_t* d = nullptr;
+    HIP_TRY(hipMalloc(&d, sizeof(uint32_t) * sh->s));
+    HIP_TRY(hipMemcpyAsync(d, h.data(), sizeof(uint32_t) * sh->s, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    it = c->perms.emplace(key, d).first;
   }
-  c->perm_valid = false;
-  c->h_perm.resize(sh->s);
-  make_perm(sh->s, sh->perm_seed, c->h_perm.data());
-  HIP_TRY(hipMalloc(&c->d_perm, sizeof(uint32_t) * sh->s));
-  HIP_TRY(hipMemcpyAsync(c->d_perm, c->h_perm.data(), sizeof(uint32_t) * sh->s, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  c->perm_s = sh->s;
-  c->perm_seed = sh->perm_seed;
-  c->perm_valid = true;
+  *out = it->second;
   return HW_OK;
 }
 
@@ -546,11 +549,12 @@ extern "C" hw_status hw_wisard_train_encrypted(hw_ctx* c, const hw_wisard_shape*
   if (n_sub > n) n_sub = n;
   if (n_sub > 65535) n_sub = 65535;
   CHECK(ensure_ws(c, n_sub * per_sample));
-  CHECK(ensure_perm(c, sh, st));
+  const uint32_t* perm = nullptr;
+  CHECK(perm_for(c, sh, st, &perm));
   hw::TrainArgs A{};
   A.x_rgsw = x_rgsw;
   A.y_rgsw = y_rgsw;
-  A.perm = c->d_perm;
+  A.perm = perm;
   A.out = static_cast<uint32_t*>(c->d_ws);
   A.rgsw_words = rgsw_words(c);
   A.s = sh->s;
@@ -605,7 +609,8 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
   if (n_sub > n) n_sub = n;
   if (n_sub > 65535) n_sub = 65535;
   CHECK(ensure_ws(c, n_sub * per_sample));
-  CHECK(ensure_perm(c, sh, st));
+  const uint32_t* perm = nullptr;
+  CHECK(perm_for(c, sh, st, &perm));
   // external products per sample: for every RAM and label, the encrypted
   // selection levels and the encrypted positions of the rotation chain
   double xp_per_sample = 0;
@@ -619,7 +624,7 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
   hw::InferArgs A{};
   A.model = model;
   A.x_rgsw = x_rgsw;
-  A.perm = c->d_perm;
+  A.perm = perm;
   A.scores = ram_scores;
   A.scratch = static_cast<uint32_t*>(c->d_ws);
   A.rgsw_words = rgsw_words(c);
@@ -651,6 +656,142 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
 }
 
 // ---------------------------------------------------------------------------
+// batched training
+// ---------------------------------------------------------------------------
+
+static uint32_t item_xp(uint32_t nb, int logN) {
+  const uint32_t nr = std::min(nb, (uint32_t)logN);
+  return nr + ((1u << (nb - nr)) - 1);
+}
+
+extern "C" hw_status hw_batch_train(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs, hipStream_t st) {
+  CHECK(enter(c));
+  if (njobs == 0) return ok();
+  if (!jobs) return fail(HW_EINVAL, "null job list");
+  std::vector<Dims> dims(njobs);
+  std::vector<const uint32_t*> perms(njobs, nullptr);
+  for (uint32_t j = 0; j < njobs; ++j) {
+    const hw_train_job& J = jobs[j];
+    hw_status e = check_shape(c, &J.shape, &dims[j]);
+    if (e) return fail(e, "job %u: %s", j, hw_last_error());
+    if (J.n == 0) continue;
+    if (!J.x_rgsw_dev || !J.model_dev) return fail(HW_EINVAL, "job %u: null buffer", j);
+    if (dims[j].L > 0 && !J.y_rgsw_dev) return fail(HW_EINVAL, "job %u: null label ciphertexts", j);
+    for (uint32_t i = 0; i < j; ++i)
+      if (jobs[i].n && (jobs[i].model_dev == J.model_dev ||
+                        (J.class_count_dev && jobs[i].class_count_dev == J.class_count_dev)))
+        return fail(HW_EINVAL, "jobs %u and %u share an output buffer", i, j);
+  }
+  for (uint32_t j = 0; j < njobs; ++j)
+    if (jobs[j].n) CHECK(perm_for(c, &jobs[j].shape, st, &perms[j]));
+  const size_t rw = rlwe_words(c);
+  const size_t budget_words = c->ws_budget / 4;
+  if (!c->d_counter) HIP_TRY(hipMalloc(&c->d_counter, 64));
+
+  struct Piece {
+    uint32_t job;
+    uint64_t s0, cnt;
+  };
+  std::vector<Piece> win;
+  size_t used = 0;
+
+  auto flush = [&]() -> hw_status {
+    if (win.empty()) return HW_OK;
+    std::vector<hw::BJob> bj(win.size());
+    std::vector<hw::BItem> items;
+    uint64_t block = 0, words = 0;
+    double xp_total = 0;
+    for (size_t p = 0; p < win.size(); ++p) {
+      const Piece& P = win[p];
+      const hw_train_job& J = jobs[P.job];
+      const Dims& d = dims[P.job];
+      hw::BJob& b = bj[p];
+      b.x = J.x_rgsw_dev + P.s0 * J.shape.s * rgsw_words(c);
+      b.y = J.y_rgsw_dev ? J.y_rgsw_dev + P.s0 * d.L * rgsw_words(c) : nullptr;
+      b.perm = perms[P.job];
+      b.model = J.model_dev;
+      b.cnt = J.class_count_dev;
+      b.block0 = block;
+      b.words0 = words;
+      b.s = J.shape.s;
+      b.a = J.shape.a;
+      b.L = d.L;
+      b.k0 = d.k0;
+      b.k1 = d.k1;
+      b.nsmp = (uint32_t)P.cnt;
+      block += P.cnt * (size_t)(d.k0 + 1) * (d.k1 + 1) * rw;
+      words += (size_t)d.k0 * d.k1 * rw + (J.class_count_dev ? rw : 0);
+      const uint32_t nram = d.k0 + (J.class_count_dev ? 1 : 0);
+      for (uint32_t smp = 0; smp < P.cnt; ++smp)
+        for (uint32_t r = 0; r < nram; ++r) {
+          const uint32_t nb = r < d.k0 ? d.L + std::min(J.shape.a, J.shape.s - r * J.shape.a) : d.L;
+          const uint32_t xp = item_xp(nb, c->logN);
+          items.push_back(hw::BItem{(uint32_t)p, smp, r, xp});
+          xp_total += xp;
+        }
+    }
+    // longest items first: the queue then ends with short ones
+    std::stable_sort(items.begin(), items.end(),
+                     [](const hw::BItem& x, const hw::BItem& y) { return x.xp > y.xp; });
+    const size_t jb = bj.size() * sizeof(hw::BJob), ib = items.size() * sizeof(hw::BItem);
+    const size_t need = jb + ib + 256;
+    HIP_TRY(hipStreamSynchronize(st));  // the previous window has released the tables
+    if (need > c->btab_bytes) {
+      if (c->h_btab) HIP_TRY(hipHostFree(c->h_btab));
+      if (c->d_btab) HIP_TRY(hipFree(c->d_btab));
+      c->h_btab = c->d_btab = nullptr;
+      c->btab_bytes = 0;
+      HIP_TRY(hipHostMalloc(&c->h_btab, need));
+      HIP_TRY(hipMalloc(&c->d_btab, need));
+      c->btab_bytes = need;
+    }
+    char* h = static_cast<char*>(c->h_btab);
+    memcpy(h, bj.data(), jb);
+    const size_t ioff = (jb + 255) / 256 * 256;
+    memcpy(h + ioff, items.data(), ib);
+    HIP_TRY(hipMemcpyAsync(c->d_btab, c->h_btab, ioff + ib, hipMemcpyHostToDevice, st));
+    const hw::BJob* djobs = static_cast<const hw::BJob*>(c->d_btab);
+    hw::BatchArgs A{};
+    A.jobs = djobs;
+    A.items = reinterpret_cast<const hw::BItem*>(static_cast<char*>(c->d_btab) + ioff);
+    A.nitems = (uint32_t)items.size();
+    A.counter = c->d_counter;
+    A.ws = static_cast<uint32_t*>(c->d_ws);
+    A.rgsw_words = rgsw_words(c);
+    HIP_TRY(timed(c, "train_batch", xp_total, st,
+                  [&] { return hw::launch_train_batch(c->logN, c->prm.nq, c->tabs, A, st); }));
+    HIP_TRY(timed(c, "reduce_batch", (double)words, st, [&] {
+      return hw::launch_reduce_batch(c->tabs, djobs, (uint32_t)bj.size(), words, c->logN, c->prm.N, c->prm.nq,
+                                     A.ws, st);
+    }));
+    win.clear();
+    used = 0;
+    return HW_OK;
+  };
+
+  // workspace: the budget, or one sample's block if that is larger
+  size_t max_block = 0;
+  for (uint32_t j = 0; j < njobs; ++j)
+    if (jobs[j].n) max_block = std::max(max_block, (size_t)(dims[j].k0 + 1) * (dims[j].k1 + 1) * rw);
+  const size_t cap = std::max(budget_words, max_block);
+  size_t need_ws = 0;
+  for (uint32_t j = 0; j < njobs; ++j)
+    need_ws += jobs[j].n * (size_t)(dims[j].k0 + 1) * (dims[j].k1 + 1) * rw;
+  CHECK(ensure_ws(c, 4 * std::min(cap, need_ws)));
+  for (uint32_t j = 0; j < njobs; ++j) {
+    const size_t blk = (size_t)(dims[j].k0 + 1) * (dims[j].k1 + 1) * rw;
+    for (uint64_t smp = 0; smp < jobs[j].n; ++smp) {
+      if (used + blk > cap) CHECK(flush());
+      if (win.empty() || win.back().job != j) win.push_back(Piece{j, smp, 0});
+      win.back().cnt += 1;
+      used += blk;
+    }
+  }
+  CHECK(flush());
+  return ok();
+}
+
+// ---------------------------------------------------------------------------
 // per-kernel timing
 // ---------------------------------------------------------------------------
 
@@ -669,8 +810,8 @@ static hw_status drain(hw_ctx* c) {
     a.ms += ms;
     a.work += r.work;
     a.launches += 1;
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
   c->pending.clear();
   return HW_OK;

@@ -60,6 +60,31 @@ struct InferArgs {
   uint32_t s, a, L, l, k0, k1, slots;
 };
 
+// batched training: one entry per job (its samples of the current window)
+struct BJob {
+  const uint32_t* x;        // RGSW of the window's first sample: [nsmp][s]
+  const uint32_t* y;        // [nsmp][L]
+  const uint32_t* perm;     // [s]
+  uint32_t* model;          // [k0][k1] RLWE
+  uint32_t* cnt;            // class counter or nullptr
+  uint64_t block0;          // word offset of the job's first block in the workspace
+  uint64_t words0;          // prefix of model (+ counter) words over the jobs
+  uint32_t s, a, L, k0, k1, nsmp;
+};
+
+struct BItem {
+  uint32_t job, smp, ram, xp;  // xp: external products of the item (queue order)
+};
+
+struct BatchArgs {
+  const BJob* jobs;
+  const BItem* items;
+  uint32_t nitems;
+  uint32_t* counter;
+  uint32_t* ws;
+  uint64_t rgsw_words;
+};
+
 struct SumArgs {
   const uint32_t* scores;   // [n][l][k0] LWE
   uint32_t* sums;           // [n][l] LWE
@@ -87,6 +112,9 @@ hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, cons
 hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, uint32_t nram, uint32_t n_sub,
                         hipStream_t st);
 hipError_t launch_reduce_model(const Tabs& T, const ReduceArgs& A, hipStream_t st);
+hipError_t launch_train_batch(int logN, int nq, const Tabs& T, const BatchArgs& A, hipStream_t st);
+hipError_t launch_reduce_batch(const Tabs& T, const BJob* jobs, uint32_t njobs, uint64_t total, uint32_t logN,
+                               uint32_t N, uint32_t nq, const uint32_t* ws, hipStream_t st);
 hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, uint32_t n_sub, hipStream_t st);
 hipError_t launch_class_sums(const Tabs& T, const SumArgs& A, hipStream_t st);
 

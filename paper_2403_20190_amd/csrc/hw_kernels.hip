@@ -447,30 +447,16 @@ __device__ __forceinline__ void copy_rlwe(uint32_t* __restrict__ dst, const uint
 // (slot j - C_i [.] slot j, C_i [.] slot j) at slots j and j + 2^i.  The
 // `ram == k0` workgroup builds the class counter from the label bits alone.
 
-template <int LOGN, int NQ>
-__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_train(Tabs T, TrainArgs A) {
-  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
-  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+// IVP of one (sample, RAM) into its block: acc = (0, Delta), the rotation
+// chain over bits z..nb-1, then the CDEMUX tree over bits 0..z-1.
+// bit(u) returns the RGSW of bit u of the IVP index.
+template <int LOGN, int NQ, class BitFn>
+__device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ slot0, uint32_t* __restrict__ xin,
+                                          uint32_t nb, BitFn&& bit, uint32_t* lds, uint2* twl, uint32_t t) {
   constexpr int N = 1 << LOGN, TT = N / 8;
   constexpr size_t RW = (size_t)2 * NQ * N;
-  const uint32_t t = threadIdx.x, ram = blockIdx.x, smp = blockIdx.y;
-  const uint64_t gi = A.i0 + smp;
-  uint32_t nb;
-  if (ram < A.k0) {
-    const uint32_t rem = A.s - ram * A.a;
-    nb = A.L + (rem < A.a ? rem : A.a);
-  } else {
-    nb = A.L;
-  }
   const uint32_t nr = nb < (uint32_t)LOGN ? nb : (uint32_t)LOGN;
   const uint32_t z = nb - nr;
-  uint32_t* slot0 = A.out + ((size_t)smp * (A.k0 + 1) + ram) * (A.k1 + 1) * RW;
-  uint32_t* xin = slot0 + (size_t)A.k1 * RW;
-  auto bit_rgsw = [&](uint32_t u) -> const uint32_t* {
-    if (u < A.L) return A.y_rgsw + (gi * A.L + u) * A.rgsw_words;
-    return A.x_rgsw + (gi * A.s + A.perm[ram * A.a + (u - A.L)]) * A.rgsw_words;
-  };
-  // acc = (0, Delta)
 #pragma unroll 1
   for (int w = 0; w < 2 * NQ; ++w) {
     const uint32_t d0 = w >= NQ ? T.pt[w - NQ].delta : 0u;
@@ -480,11 +466,10 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WA
   __syncthreads();
   uint32_t xc = 0;
 #pragma unroll 1
-  for (uint32_t st = 0; st < nr; ++st)
-    cmux_rot<LOGN, NQ>(T, slot0, 1 << st, bit_rgsw(z + st), xin, lds, twl, xc, t);
+  for (uint32_t st = 0; st < nr; ++st) cmux_rot<LOGN, NQ>(T, slot0, 1 << st, bit(z + st), xin, lds, twl, xc, t);
 #pragma unroll 1
   for (uint32_t lev = 0; lev < z; ++lev) {
-    const uint32_t* C = bit_rgsw(lev);
+    const uint32_t* C = bit(lev);
     const uint32_t n = 1u << lev;
 #pragma unroll 1
     for (uint32_t j = 0; j < n; ++j) {
@@ -493,6 +478,113 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WA
       copy_rlwe<LOGN, NQ>(xin, sj, t);
       ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t, XpOut{sj, xin, sn, XP_DEMUX});
     }
+  }
+}
+
+__device__ __forceinline__ uint32_t ram_bits(uint32_t ram, uint32_t k0, uint32_t s, uint32_t a, uint32_t L) {
+  if (ram >= k0) return L;  // the class counter: label bits only
+  const uint32_t rem = s - ram * a;
+  return L + (rem < a ? rem : a);
+}
+
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_train(Tabs T, TrainArgs A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr size_t RW = (size_t)2 * NQ * (1 << LOGN);
+  const uint32_t t = threadIdx.x, ram = blockIdx.x, smp = blockIdx.y;
+  const uint64_t gi = A.i0 + smp;
+  uint32_t* slot0 = A.out + ((size_t)smp * (A.k0 + 1) + ram) * (A.k1 + 1) * RW;
+  ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)A.k1 * RW, ram_bits(ram, A.k0, A.s, A.a, A.L),
+                      [&](uint32_t u) -> const uint32_t* {
+                        if (u < A.L) return A.y_rgsw + (gi * A.L + u) * A.rgsw_words;
+                        return A.x_rgsw + (gi * A.s + A.perm[ram * A.a + (u - A.L)]) * A.rgsw_words;
+                      },
+                      lds, twl, t);
+}
+
+// ---------------------------------------------------------------------------
+// batched training: one persistent launch over many jobs of one parameter set
+// ---------------------------------------------------------------------------
+// Items (job, sample, RAM) are taken from a queue (a device counter), longest
+// first; each writes the block of its (job, sample) like k_train, and
+// k_reduce_batch then adds every job's blocks into its model.  A workgroup
+// leaves when the queue is exhausted.
+
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_train_batch(
+    Tabs T, BatchArgs A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  __shared__ uint32_t next;
+  constexpr size_t RW = (size_t)2 * NQ * (1 << LOGN);
+  const uint32_t t = threadIdx.x;
+#pragma unroll 1
+  for (;;) {
+    if (t == 0) next = atomicAdd(A.counter, 1u);
+    __syncthreads();
+    const uint32_t it = next;
+    __syncthreads();
+    if (it >= A.nitems) break;
+    const BItem I = A.items[it];
+    const BJob J = A.jobs[I.job];
+    uint32_t* slot0 = A.ws + J.block0 + ((size_t)I.smp * (J.k0 + 1) + I.ram) * (J.k1 + 1) * RW;
+    const uint64_t gi = I.smp;
+    ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)J.k1 * RW, ram_bits(I.ram, J.k0, J.s, J.a, J.L),
+                        [&](uint32_t u) -> const uint32_t* {
+                          if (u < J.L) return J.y + (gi * J.L + u) * A.rgsw_words;
+                          return J.x + (gi * J.s + J.perm[I.ram * J.a + (u - J.L)]) * A.rgsw_words;
+                        },
+                        lds, twl, t);
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_u32(uint32_t* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// every job's model[j][d] (+ counter) += sum over the window's samples of its
+// blocks; one thread per model word, the job found by binary search
+__global__ __launch_bounds__(256) void k_reduce_batch(Tabs T, const BJob* __restrict__ jobs, uint32_t njobs,
+                                                      uint64_t total, uint32_t logN, uint32_t N, uint32_t nq,
+                                                      const uint32_t* __restrict__ ws) {
+  const size_t RW = (size_t)2 * nq * N;
+  for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (size_t)gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = njobs;  // last job with words0 <= w
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (jobs[mid].words0 <= w) lo = mid; else hi = mid;
+    }
+    const BJob J = jobs[lo];
+    const size_t per_ram = (size_t)J.k1 * RW;
+    const size_t model_words = (size_t)J.k0 * per_ram;
+    size_t x = w - J.words0;
+    uint32_t ram, d;
+    size_t rem;
+    if (x < model_words) {
+      ram = (uint32_t)(x / per_ram);
+      rem = x - (size_t)ram * per_ram;
+      d = (uint32_t)(rem / RW);
+      rem -= (size_t)d * RW;
+      const uint32_t nb = ram_bits(ram, J.k0, J.s, J.a, J.L);
+      const uint32_t nr = nb < logN ? nb : logN;
+      if (d >= (1u << (nb - nr))) continue;
+    } else {
+      ram = J.k0;
+      d = 0;
+      rem = x - model_words;
+    }
+    const uint32_t i = (uint32_t)((rem / N) % nq);
+    const PrimeTab P = T.pt[i];
+    const size_t blk = (size_t)(J.k1 + 1) * RW;
+    const size_t stride = (size_t)(J.k0 + 1) * blk;
+    const uint32_t* src = ws + J.block0 + (size_t)ram * blk + (size_t)d * RW + rem;
+    uint64_t acc = 0;
+    for (uint32_t s = 0; s < J.nsmp; ++s) acc += src[(size_t)s * stride];
+    uint32_t* dst = x < model_words ? J.model + x : J.cnt + rem;
+    *dst = addq(*dst, red64(acc, P), P.q);
   }
 }
 
@@ -782,6 +874,34 @@ hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, cons
 hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, uint32_t nram, uint32_t n_sub,
                         hipStream_t st) {
   HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_train<LN, NQ>), dim3(nram, n_sub), dim3(Geo<LN>::T), 0, st, T, A));
+  return hipGetLastError();
+}
+
+template <int LN, int NQ>
+static hipError_t launch_batch_t(const Tabs& T, const BatchArgs& A, uint32_t nitems_cap, hipStream_t st) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_train_batch<LN, NQ>, Geo<LN>::T, 0);
+  if (e != hipSuccess) return e;
+  uint32_t grid = (uint32_t)(cus * (per_cu > 0 ? per_cu : 1));
+  if (grid > nitems_cap) grid = nitems_cap;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, A.counter, 1u);
+  hipLaunchKernelGGL((k_train_batch<LN, NQ>), dim3(grid), dim3(Geo<LN>::T), 0, st, T, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_train_batch(int logN, int nq, const Tabs& T, const BatchArgs& A, hipStream_t st) {
+  HW_DISPATCH(logN, nq, return launch_batch_t<LN, NQ>(T, A, A.nitems, st));
+  return hipSuccess;
+}
+
+hipError_t launch_reduce_batch(const Tabs& T, const BJob* jobs, uint32_t njobs, uint64_t total, uint32_t logN,
+                               uint32_t N, uint32_t nq, const uint32_t* ws, hipStream_t st) {
+  const uint32_t blocks = (uint32_t)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+  if (!blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_batch, dim3(blocks), dim3(256), 0, st, T, jobs, njobs, total, logN, N, nq, ws);
   return hipGetLastError();
 }
 

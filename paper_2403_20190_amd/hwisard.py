@@ -20,6 +20,13 @@ if not os.path.exists(LIB_PATH):
     raise ImportError("libhwisard.so is not built: run `python -m paper_2403_20190_amd.build` "
                       "(the encrypted WiSARD path has no CPU fallback)")
 
+# One HIP runtime per process: load torch's runtime first, so that the
+# library's libamdhip64.so.7 dependency resolves (by soname) to the copy torch
+# uses for memory and streams instead of loading a second runtime.
+import torch as _torch  # noqa: E402
+
+if _torch.cuda.is_available():
+    _torch.cuda.init()
 _lib = C.CDLL(LIB_PATH)
 
 HW_OK, HW_EINVAL, HW_ENOMEM, HW_EDEVICE, HW_EUNSUPPORTED, HW_EBUSY, HW_ECANCELLED = 0, -1, -2, -3, -4, -5, -6
@@ -43,6 +50,11 @@ class Shape(C.Structure):
                 ("perm_seed", C.c_uint64)]
 
 
+class TrainJob(C.Structure):
+    _fields_ = [("shape", Shape), ("x_rgsw", C.c_void_p), ("y_rgsw", C.c_void_p), ("n", C.c_uint64),
+                ("model", C.c_void_p), ("class_count", C.c_void_p)]
+
+
 _vp, _u64, _u32, _i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
 _SIG = {
     "hw_ctx_create": [C.POINTER(Params), _i32, C.POINTER(C.c_void_p)],
@@ -60,6 +72,7 @@ _SIG = {
     "hw_external_product": [_vp, _vp, _vp, _u64, _vp, _vp],
     "hw_wisard_train_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_wisard_infer_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
+    "hw_batch_train": [_vp, C.POINTER(TrainJob), _u32, _vp],
     "hw_profile_enable": [_vp, _i32],
     "hw_profile_read": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(_u64), C.POINTER(C.c_double)],
     "hw_profile_reset": [_vp],
@@ -185,6 +198,15 @@ class Context:
     def train(self, sh: Shape, x_rgsw, y_rgsw, n: int, model, class_count=None):
         _check(_lib.hw_wisard_train_encrypted(self._h, C.byref(sh), _ptr(x_rgsw), _ptr(y_rgsw), n, _ptr(model),
                                               _ptr(class_count), _stream()))
+
+    def batch_train(self, jobs):
+        """jobs: iterable of (shape, x_rgsw, y_rgsw, n, model, class_count) -- one
+        persistent launch per workspace window for all of them"""
+        jobs = list(jobs)
+        arr = (TrainJob * max(1, len(jobs)))()
+        for i, (sh, x, y, n, model, cnt) in enumerate(jobs):
+            arr[i] = TrainJob(sh, _ptr(x), _ptr(y), n, _ptr(model), _ptr(cnt))
+        _check(_lib.hw_batch_train(self._h, arr, len(jobs), _stream()))
 
     def infer(self, sh: Shape, model, x_rgsw, n: int, ram_scores, class_scores=None):
         _check(_lib.hw_wisard_infer_encrypted(self._h, C.byref(sh), _ptr(model), _ptr(x_rgsw), n,

@@ -128,6 +128,11 @@ def main():
     ap.add_argument("--batched-scale", type=float, nargs="*", default=[1.0 / 64, 1.0 / 512],
                     help="job sizes of the 256-job batched workload are scaled by these factors")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=200)
+    ap.add_argument("--served-max-size", type=int, default=50,
+                    help="request sizes are U{1..max}; the served workload's 1..500 scaled down")
+    ap.add_argument("--served-load", type=float, default=0.7, help="offered load as a fraction of saturation")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; multi-GPU sharding is designed but not run "
@@ -259,6 +264,8 @@ def main():
         result["hbm_copy_gbs"] = hbm_copy(dev)
         if not args.no_batched:
             result["batched"] = [batched_pass(sc, dev) for sc in args.batched_scale]
+        if not args.no_served:
+            result["served"] = served_pass(dev, args.served_requests, args.served_max_size, args.served_load)
     if not args.no_cpu_baseline and not args.no_extras:
         result["cpu_baseline"] = cpu_baseline(W, Xtr, ytr, min(16, os.cpu_count() or 1), seeds)
     print(json.dumps(result), flush=True)
@@ -335,6 +342,7 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     from paper_2403_20190_amd import client as CL
     from paper_2403_20190_amd import hwisard as HW
     from paper_2403_20190_amd import synth
+    torch.cuda.empty_cache()
     jobs = synth.batched_jobs(2)
     groups = {}
     for j, J in enumerate(jobs):
@@ -396,6 +404,7 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
         if window:
             run(window)
         ctx.close()
+        torch.cuda.empty_cache()
     out["batched_samples_per_s"] = round(out["samples"] / (out["batched_ms"] / 1000.0), 2)
     out["single_job_samples_per_s"] = round(out["samples"] / (out["single_ms"] / 1000.0), 2)
     out["batched_xp_per_s"] = round(out["xp"] / (out["batched_ms"] / 1000.0), 1)
@@ -403,6 +412,97 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     out["batched_ms"] = round(out["batched_ms"], 1)
     out["single_ms"] = round(out["single_ms"], 1)
     return out
+
+
+def served_pass(dev, n_req: int, max_size: int, load: float):
+    """Continuous batching of Poisson-arrival train/infer requests: half
+    Wisconsin-shaped (30 features, 2 classes 357/212, min-max + 16-level
+    thermometer = 480 bits, tuple 8), half MNIST-shaped, 4 resident models of
+    each shape pre-trained with 64 samples, one parameter set (N=2048, two
+    primes, p=2^16).  First all requests at once (saturation), then Poisson
+    arrivals at `load` x the saturated request rate: p50/p99 latency."""
+    import numpy as np
+    import torch
+
+    from paper_2403_20190_amd import client as CL
+    from paper_2403_20190_amd import hwisard as HW
+    from paper_2403_20190_amd import synth
+    N, nq, p = 2048, 2, 1 << 16
+    torch.cuda.empty_cache()
+    ctx = HW.Context(N, nq, p)
+    sk = torch.zeros(N, dtype=torch.int32, device=dev)
+    ctx.keygen(202, sk)
+    # data pools
+    Xw, yw = synth.wisconsin_like(4)
+    lo, hi = Xw.min(axis=0), Xw.max(axis=0)
+    bits_w = CL.thermometer(CL.quantize_minmax(Xw, 16, lo, hi), 16)
+    Xm, ym, _, _ = synth.mnist_like(1, per_class_train=60, per_class_test=1)
+    bits_m = CL.thermometer(CL.quantize_u8(Xm, 3), 3)
+    shapes = {"wisconsin": (bits_w, yw, 2, 8), "mnist": (bits_m, ym, 10, 12)}
+    g = np.random.Generator(np.random.PCG64(5))
+
+    def make_engine():
+        eng = HW.Engine(N, nq, p, sk, slots=4, chunk=8, max_s=2352, max_cells=2048, arena_bytes=64 << 30)
+        jobs = []
+        for name, (bits, y, l, a) in shapes.items():
+            for r in range(4):
+                sh = HW.shape(bits.shape[1], l, a, 7000 + 10 * len(jobs))
+                k0, k1, _ = ctx.dims(sh)
+                H = torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev)
+                j = eng.add_job(sh, H)
+                idx = g.integers(0, len(bits), 64)
+                rid = eng.submit(j, "train", bits[idx], 8000 + j, labels=CL.label_bits(y[idx], l))
+                eng.wait(rid)
+                jobs.append((j, name, H, k0))
+        return eng, jobs
+
+    reqs = []
+    for k in range(n_req):
+        name = "wisconsin" if g.random() < 0.5 else "mnist"
+        bits, y, l, a = shapes[name]
+        size = int(g.integers(1, max_size + 1))
+        idx = g.integers(0, len(bits), size)
+        reqs.append(dict(shape=name, kind="train" if g.random() < 0.5 else "infer", job=int(g.integers(0, 4)),
+                         bits=bits[idx], labels=CL.label_bits(y[idx], l), l=l, size=size, seed=9000 + 7 * k))
+
+    def play(arrivals):
+        eng, jobs = make_engine()
+        by = {}
+        for j, name, H, k0 in jobs:
+            by.setdefault(name, []).append((j, k0))
+        t0 = time.perf_counter()
+        ids = []
+        for r, t_arr in zip(reqs, arrivals):
+            dt = t0 + t_arr - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            j, k0 = by[r["shape"]][r["job"]]
+            cells = np.zeros((r["size"], r["l"], k0), np.uint64) if r["kind"] == "infer" else None
+            ids.append(eng.submit(j, r["kind"], r["bits"], r["seed"],
+                                  labels=r["labels"] if r["kind"] == "train" else None, cells=cells))
+        lat = [eng.wait(i)[1] for i in ids]
+        span = time.perf_counter() - t0
+        st = eng.stats()
+        eng.close()
+        return np.array(lat), span, st
+
+    lat0, span0, st0 = play([0.0] * n_req)
+    sat_rps = n_req / span0
+    qps = load * sat_rps
+    arr = synth.poisson_arrivals(6, qps, n_req)
+    lat1, span1, st1 = play(list(arr - arr[0]))
+    samples = sum(r["size"] for r in reqs)
+    ctx.close()
+    return {
+        "requests": n_req, "sizes": "U{1..%d}" % max_size, "samples": samples,
+        "saturated_req_per_s": round(sat_rps, 3), "saturated_samples_per_s": round(samples / span0, 2),
+        "offered_qps": round(qps, 3), "load": load,
+        "p50_ms": round(float(np.percentile(lat1, 50)), 2), "p99_ms": round(float(np.percentile(lat1, 99)), 2),
+        "throughput_samples_per_s": round(samples / span1, 2),
+        "saturated_p50_ms": round(float(np.percentile(lat0, 50)), 2),
+        "saturated_p99_ms": round(float(np.percentile(lat0, 99)), 2),
+        "peak_inflight_chunks": st1["peak_inflight"], "peak_arena_gib": round(st1["peak_arena_bytes"] / 2**30, 2),
+    }
 
 
 def hbm_copy(dev):

@@ -206,6 +206,75 @@ typedef struct {
  * Jobs must not share model or counter buffers. */
 hw_status hw_batch_train(hw_ctx* ctx, const hw_train_job* jobs, uint32_t njobs, hipStream_t stream);
 
+/* ---- serving engine (continuous batching) ------------------------------------- */
+
+/* A request loop on one device: train and infer requests against resident
+ * models are cut into chunks of samples; a scheduler thread starts a chunk
+ * as soon as a stream slot is free and the chunk's device footprint (input
+ * ciphertexts, workspace, scores) fits in the engine's arena, interleaving
+ * chunks of all admitted requests.  Requests on one model run in submission
+ * order (a request starts after the previous one on its model completed;
+ * training chunks of a request run one after another); requests on
+ * different models overlap on the device.  Results depend only on the
+ * model state and the request, so each is bit-identical alone and in a mix.
+ * For measurement the engine also plays the client: it encrypts request bits
+ * on the device with the key it was given and returns decrypted PD-act cells. */
+typedef struct hw_engine hw_engine;
+
+typedef struct {
+  uint32_t slots;        /* chunks in flight at once, one HIP stream each: 1..16 */
+  uint32_t chunk;        /* samples per chunk, >= 1 */
+  uint32_t max_s;        /* largest input width served (host staging size) */
+  uint32_t max_cells;    /* largest l * k0 served (host staging size) */
+  uint64_t arena_bytes;  /* device memory for the chunks in flight */
+} hw_engine_config;
+
+typedef struct {
+  uint32_t job;                /* id from hw_engine_add_job */
+  uint32_t kind;               /* 0 = train, 1 = infer */
+  const uint8_t* bits_host;    /* [n][s] input bits; host, read until the request completes */
+  const uint8_t* labels_host;  /* train: [n][L] label bits, LSB first; NULL when L = 0 */
+  uint64_t n;                  /* samples */
+  uint64_t enc_seed;           /* input bits use seed enc_seed, labels enc_seed + 1; ciphertext
+                                  index = sample * s + bit (sample * L + bit for labels) */
+  uint64_t* cells_host;        /* infer: [n][l][k0] decrypted per-RAM scores */
+} hw_request;
+
+enum { HW_REQ_QUEUED = 0, HW_REQ_RUNNING = 1, HW_REQ_DONE = 2, HW_REQ_FAILED = 3, HW_REQ_CANCELLED = 4 };
+
+/* Create an engine for `params` on `device` with the client key sk_dev
+ * (caller-owned, device, valid until destroy).  Fails with HW_ENOMEM when the
+ * arena cannot be allocated. */
+hw_status hw_engine_create(const hw_params* params, int device, const int32_t* sk_dev,
+                           const hw_engine_config* config, hw_engine** out);
+
+/* Wait for the chunks in flight, stop the scheduler and free the engine. */
+void hw_engine_destroy(hw_engine* engine);
+
+/* Register a resident model (caller-owned device buffers, [k0][k1] RLWE and
+ * an optional class counter) of the given shape; *job_id names it.  Call
+ * before submitting requests that use it. */
+hw_status hw_engine_add_job(hw_engine* engine, const hw_wisard_shape* shape, uint32_t* model_dev,
+                            uint32_t* class_count_dev, uint32_t* job_id);
+
+/* Queue a request.  HW_EBUSY: one chunk of it would not fit in the arena
+ * (it could never be admitted); HW_EINVAL: bad job or buffers. */
+hw_status hw_engine_submit(hw_engine* engine, const hw_request* request, uint64_t* request_id);
+
+/* State of a request (HW_REQ_*) and, once finished, its latency from submission. */
+hw_status hw_engine_poll(hw_engine* engine, uint64_t request_id, int* state, double* latency_ms);
+
+/* Block until the request has finished (done, failed or cancelled). */
+hw_status hw_engine_wait(hw_engine* engine, uint64_t request_id, int* state, double* latency_ms);
+
+/* Cancel a request: no further chunks start; chunks in flight complete (a
+ * cancelled training request may have updated the model with them). */
+hw_status hw_engine_cancel(hw_engine* engine, uint64_t request_id);
+
+/* Counters: chunks started, peak arena bytes in use, peak chunks in flight. */
+hw_status hw_engine_stats(hw_engine* engine, uint64_t* chunks, uint64_t* peak_arena_bytes,
+                          uint32_t* peak_inflight);
+
 /* ---- per-kernel timing ------------------------------------------------------ */
 
 /* While enabled, every kernel launch made by the calls of this context is

@@ -11,8 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhwisard.so")
-SOURCES = ["hw_kernels.hip", "hw_api.cpp"]
-HEADERS = ["hw_device.h", "hw_internal.h"]
+SOURCES = ["hw_kernels.hip", "hw_api.cpp", "hw_engine.cpp"]
+HEADERS = ["hw_device.h", "hw_internal.h", "hw_ctx.h"]
 
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -16,10 +16,9 @@
 #include <vector>
 
 #include "../../include/hwisard.h"
+#include "hw_ctx.h"
 #include "hw_internal.h"
 
-using hw::Tabs;
-typedef unsigned __int128 u128;
 
 // ---------------------------------------------------------------------------
 // errors
@@ -27,7 +26,7 @@ typedef unsigned __int128 u128;
 
 static thread_local std::string g_err;
 
-static hw_status fail(hw_status st, const char* fmt, ...) {
+hw_status fail(hw_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -37,18 +36,11 @@ static hw_status fail(hw_status st, const char* fmt, ...) {
   return st;
 }
 
-static hw_status ok() {
+hw_status ok() {
   g_err.clear();
   return HW_OK;
 }
 
-#define HIP_TRY(expr)                                                                  \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return fail(e_ == hipErrorOutOfMemory ? HW_ENOMEM : HW_EDEVICE, "%s: %s", #expr, \
-                  hipGetErrorString(e_));                                              \
-  } while (0)
 
 extern "C" const char* hw_last_error(void) { return g_err.c_str(); }
 
@@ -143,60 +135,6 @@ static void build_cdt(double sigma, uint64_t T[42]) {
 // context
 // ---------------------------------------------------------------------------
 
-struct hw_ctx {
-  hw_params prm;
-  int device;
-  int logN;
-  Tabs tabs;
-  hw::CrtTab crt;
-  hw::Cdt cdt;
-  u128 Q;
-  void* d_tables = nullptr;        // twiddle tables of every prime
-  uint32_t* d_skhat = nullptr;     // [nq][N]
-  void* d_ws = nullptr;            // workspace
-  size_t ws_bytes = 0;
-  size_t ws_budget = 0;
-  // permutations on the device, by (s, seed)
-  std::map<std::pair<uint32_t, uint64_t>, uint32_t*> perms;
-  // batched training: job/item tables (pinned host staging, device copy), queue counter
-  void* h_btab = nullptr;
-  void* d_btab = nullptr;
-  size_t btab_bytes = 0;
-  uint32_t* d_counter = nullptr;
-  // per-kernel timing
-  bool prof = false;
-  struct Rec {
-    std::string name;
-    hipEvent_t a, b;
-    double work;
-  };
-  std::vector<Rec> pending;
-  struct Acc {
-    double ms = 0, work = 0;
-    uint64_t launches = 0;
-  };
-  std::map<std::string, Acc> acc;
-};
-
-// run `launch` between two events on `st` when profiling is on
-template <class F>
-static hipError_t timed(hw_ctx* c, const char* name, double work, hipStream_t st, F&& launch) {
-  if (!c->prof) return launch();
-  hw_ctx::Rec r{name, nullptr, nullptr, work};
-  hipError_t e = hipEventCreate(&r.a);
-  if (e == hipSuccess) e = hipEventCreate(&r.b);
-  if (e == hipSuccess) e = hipEventRecord(r.a, st);
-  if (e != hipSuccess) return e;
-  e = launch();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(r.b, st);
-  if (e == hipSuccess) c->pending.push_back(r);
-  return e;
-}
-
-static size_t rlwe_words(const hw_ctx* c) { return (size_t)2 * c->prm.nq * c->prm.N; }
-static size_t rgsw_words(const hw_ctx* c) { return (size_t)2 * 5 * c->prm.nq * rlwe_words(c); }
-static size_t lwe_words(const hw_ctx* c) { return (size_t)c->prm.nq * (c->prm.N + 1); }
 
 extern "C" hw_status hw_ctx_create(const hw_params* params, int device, hw_ctx** out) {
   if (!params || !out) return fail(HW_EINVAL, "null argument");
@@ -333,11 +271,8 @@ static uint32_t ceil_log2(uint32_t l) {
   return L;
 }
 
-struct Dims {
-  uint32_t L, k0, k1, z;
-};
 
-static hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d) {
+hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d) {
   if (!sh) return fail(HW_EINVAL, "null shape");
   if (sh->reserved) return fail(HW_EINVAL, "shape.reserved must be 0");
   if (sh->s < 1 || sh->s > (1u << 24)) return fail(HW_EINVAL, "s = %u out of range [1, 2^24]", sh->s);
@@ -393,7 +328,7 @@ static hw_status ensure_ws(hw_ctx* c, size_t bytes) {
 }
 
 // the device permutation of (s, seed), uploaded once and kept with the context
-static hw_status perm_for(hw_ctx* c, const hw_wisard_shape* sh, hipStream_t st, const uint32_t** out) {
+hw_status perm_for(hw_ctx* c, const hw_wisard_shape* sh, hipStream_t st, const uint32_t** out) {
   const auto key = std::make_pair(sh->s, sh->perm_seed);
   auto it = c->perms.find(key);
   if (it == c->perms.end()) {
@@ -415,11 +350,6 @@ static hw_status enter(hw_ctx* c) {
   return HW_OK;
 }
 
-#define CHECK(expr)            \
-  do {                         \
-    hw_status s_ = (expr);     \
-    if (s_ != HW_OK) return s_; \
-  } while (0)
 
 // ---------------------------------------------------------------------------
 // client side
@@ -533,29 +463,28 @@ extern "C" hw_status hw_external_product(hw_ctx* c, const uint32_t* rgsw, const 
 // server side
 // ---------------------------------------------------------------------------
 
-extern "C" hw_status hw_wisard_train_encrypted(hw_ctx* c, const hw_wisard_shape* sh, const uint32_t* x_rgsw,
-                                               const uint32_t* y_rgsw, uint64_t n, uint32_t* model,
-                                               uint32_t* class_count, hipStream_t st) {
-  CHECK(enter(c));
-  Dims d;
-  CHECK(check_shape(c, sh, &d));
-  if (n == 0) return ok();
-  if (!x_rgsw || !model) return fail(HW_EINVAL, "null buffer");
-  if (d.L > 0 && !y_rgsw) return fail(HW_EINVAL, "null label ciphertexts");
+size_t train_ws_per_sample(const hw_ctx* c, const Dims& d) {
+  return (size_t)(d.k0 + 1) * (d.k1 + 1) * rlwe_words(c) * 4;  // k1 outputs + input slot per RAM
+}
+
+size_t infer_ws_per_sample(const hw_ctx* c, const hw_wisard_shape* sh, const Dims& d) {
+  const uint32_t slots = d.z > d.L + 1 ? (1u << (d.z - d.L - 1)) : 1u;
+  return (size_t)sh->l * d.k0 * (slots + 1) * rlwe_words(c) * 4;  // + input slot
+}
+
+hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const uint32_t* perm,
+                     const uint32_t* x_rgsw, const uint32_t* y_rgsw, uint64_t n, uint32_t* model,
+                     uint32_t* class_count, uint32_t* ws, size_t ws_bytes, hipStream_t st, bool timing) {
   const size_t rw = rlwe_words(c);
-  const size_t per_sample = (size_t)(d.k0 + 1) * (d.k1 + 1) * rw * 4;  // k1 outputs + input slot
-  uint64_t n_sub = c->ws_budget / per_sample;
-  if (n_sub < 1) n_sub = 1;
+  uint64_t n_sub = ws_bytes / train_ws_per_sample(c, d);
+  if (n_sub < 1) return fail(HW_ENOMEM, "training workspace smaller than one sample");
   if (n_sub > n) n_sub = n;
   if (n_sub > 65535) n_sub = 65535;
-  CHECK(ensure_ws(c, n_sub * per_sample));
-  const uint32_t* perm = nullptr;
-  CHECK(perm_for(c, sh, st, &perm));
   hw::TrainArgs A{};
   A.x_rgsw = x_rgsw;
   A.y_rgsw = y_rgsw;
   A.perm = perm;
-  A.out = static_cast<uint32_t*>(c->d_ws);
+  A.out = ws;
   A.rgsw_words = rgsw_words(c);
   A.s = sh->s;
   A.a = sh->a;
@@ -582,35 +511,47 @@ extern "C" hw_status hw_wisard_train_encrypted(hw_ctx* c, const hw_wisard_shape*
     const uint32_t nr = std::min(nb, (uint32_t)c->logN);
     xp_per_sample += nr + ((1u << (nb - nr)) - 1);
   }
+  const bool tm = timing && c->prof;
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
     const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
     A.i0 = i0;
-    HIP_TRY(timed(c, "train", (double)m * xp_per_sample, st,
-                  [&] { return hw::launch_train(c->logN, c->prm.nq, c->tabs, A, nram, (uint32_t)m, st); }));
+    auto lt = [&] { return hw::launch_train(c->logN, c->prm.nq, c->tabs, A, nram, (uint32_t)m, st); };
+    HIP_TRY(tm ? timed(c, "train", (double)m * xp_per_sample, st, lt) : lt());
     R.n_sub = m;
-    HIP_TRY(timed(c, "reduce", (double)d.k0 * d.k1 * rw, st, [&] { return hw::launch_reduce_model(c->tabs, R, st); }));
+    auto lr = [&] { return hw::launch_reduce_model(c->tabs, R, st); };
+    HIP_TRY(tm ? timed(c, "reduce", (double)d.k0 * d.k1 * rw, st, lr) : lr());
   }
-  return ok();
+  return HW_OK;
 }
 
-extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape* sh, const uint32_t* model,
-                                               const uint32_t* x_rgsw, uint64_t n, uint32_t* ram_scores,
-                                               uint32_t* class_scores, hipStream_t st) {
+extern "C" hw_status hw_wisard_train_encrypted(hw_ctx* c, const hw_wisard_shape* sh, const uint32_t* x_rgsw,
+                                               const uint32_t* y_rgsw, uint64_t n, uint32_t* model,
+                                               uint32_t* class_count, hipStream_t st) {
   CHECK(enter(c));
   Dims d;
   CHECK(check_shape(c, sh, &d));
   if (n == 0) return ok();
-  if (!model || !x_rgsw || !ram_scores) return fail(HW_EINVAL, "null buffer");
-  const size_t rw = rlwe_words(c);
-  const uint32_t slots = d.z > d.L + 1 ? (1u << (d.z - d.L - 1)) : 1u;
-  const size_t per_sample = (size_t)sh->l * d.k0 * (slots + 1) * rw * 4;  // + input slot
-  uint64_t n_sub = c->ws_budget / per_sample;
-  if (n_sub < 1) n_sub = 1;
-  if (n_sub > n) n_sub = n;
-  if (n_sub > 65535) n_sub = 65535;
+  if (!x_rgsw || !model) return fail(HW_EINVAL, "null buffer");
+  if (d.L > 0 && !y_rgsw) return fail(HW_EINVAL, "null label ciphertexts");
+  const size_t per_sample = train_ws_per_sample(c, d);
+  uint64_t n_sub = std::max<uint64_t>(1, c->ws_budget / per_sample);
+  n_sub = std::min<uint64_t>(std::min<uint64_t>(n_sub, n), 65535);
   CHECK(ensure_ws(c, n_sub * per_sample));
   const uint32_t* perm = nullptr;
   CHECK(perm_for(c, sh, st, &perm));
+  CHECK(train_core(c, sh, d, perm, x_rgsw, y_rgsw, n, model, class_count, static_cast<uint32_t*>(c->d_ws),
+                   n_sub * per_sample, st, true));
+  return ok();
+}
+
+hw_status infer_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const uint32_t* perm,
+                     const uint32_t* model, const uint32_t* x_rgsw, uint64_t n, uint32_t* ram_scores,
+                     uint32_t* class_scores, uint32_t* ws, size_t ws_bytes, hipStream_t st, bool timing) {
+  uint64_t n_sub = ws_bytes / infer_ws_per_sample(c, sh, d);
+  if (n_sub < 1) return fail(HW_ENOMEM, "inference workspace smaller than one sample");
+  if (n_sub > n) n_sub = n;
+  if (n_sub > 65535) n_sub = 65535;
+  const uint32_t slots = d.z > d.L + 1 ? (1u << (d.z - d.L - 1)) : 1u;
   // external products per sample: for every RAM and label, the encrypted
   // selection levels and the encrypted positions of the rotation chain
   double xp_per_sample = 0;
@@ -626,7 +567,7 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
   A.x_rgsw = x_rgsw;
   A.perm = perm;
   A.scores = ram_scores;
-  A.scratch = static_cast<uint32_t*>(c->d_ws);
+  A.scratch = ws;
   A.rgsw_words = rgsw_words(c);
   A.s = sh->s;
   A.a = sh->a;
@@ -635,11 +576,12 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
   A.k0 = d.k0;
   A.k1 = d.k1;
   A.slots = slots;
+  const bool tm = timing && c->prof;
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
     const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
     A.i0 = i0;
-    HIP_TRY(timed(c, "infer", (double)m * xp_per_sample, st,
-                  [&] { return hw::launch_infer(c->logN, c->prm.nq, c->tabs, A, (uint32_t)m, st); }));
+    auto li = [&] { return hw::launch_infer(c->logN, c->prm.nq, c->tabs, A, (uint32_t)m, st); };
+    HIP_TRY(tm ? timed(c, "infer", (double)m * xp_per_sample, st, li) : li());
   }
   if (class_scores) {
     hw::SumArgs S{};
@@ -650,8 +592,28 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
     S.k0 = d.k0;
     S.N = c->prm.N;
     S.nq = c->prm.nq;
-    HIP_TRY(timed(c, "class_sums", (double)n * sh->l * lwe_words(c), st, [&] { return hw::launch_class_sums(c->tabs, S, st); }));
+    auto ls = [&] { return hw::launch_class_sums(c->tabs, S, st); };
+    HIP_TRY(tm ? timed(c, "class_sums", (double)n * sh->l * lwe_words(c), st, ls) : ls());
   }
+  return HW_OK;
+}
+
+extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape* sh, const uint32_t* model,
+                                               const uint32_t* x_rgsw, uint64_t n, uint32_t* ram_scores,
+                                               uint32_t* class_scores, hipStream_t st) {
+  CHECK(enter(c));
+  Dims d;
+  CHECK(check_shape(c, sh, &d));
+  if (n == 0) return ok();
+  if (!model || !x_rgsw || !ram_scores) return fail(HW_EINVAL, "null buffer");
+  const size_t per_sample = infer_ws_per_sample(c, sh, d);
+  uint64_t n_sub = std::max<uint64_t>(1, c->ws_budget / per_sample);
+  n_sub = std::min<uint64_t>(std::min<uint64_t>(n_sub, n), 65535);
+  CHECK(ensure_ws(c, n_sub * per_sample));
+  const uint32_t* perm = nullptr;
+  CHECK(perm_for(c, sh, st, &perm));
+  CHECK(infer_core(c, sh, d, perm, model, x_rgsw, n, ram_scores, class_scores, static_cast<uint32_t*>(c->d_ws),
+                   n_sub * per_sample, st, true));
   return ok();
 }
 

@@ -1,0 +1,110 @@
+// hw_ctx.h -- the context object behind the C ABI and the host helpers that
+// the API (hw_api.cpp) and the serving engine (hw_engine.cpp) share.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/hwisard.h"
+#include "hw_internal.h"
+
+using hw::Tabs;
+typedef unsigned __int128 u128;
+
+struct hw_ctx {
+  hw_params prm;
+  int device;
+  int logN;
+  Tabs tabs;
+  hw::CrtTab crt;
+  hw::Cdt cdt;
+  u128 Q;
+  void* d_tables = nullptr;        // twiddle tables of every prime
+  uint32_t* d_skhat = nullptr;     // [nq][N]
+  void* d_ws = nullptr;            // workspace
+  size_t ws_bytes = 0;
+  size_t ws_budget = 0;
+  // permutations on the device, by (s, seed)
+  std::map<std::pair<uint32_t, uint64_t>, uint32_t*> perms;
+  // batched training: job/item tables (pinned host staging, device copy), queue counter
+  void* h_btab = nullptr;
+  void* d_btab = nullptr;
+  size_t btab_bytes = 0;
+  uint32_t* d_counter = nullptr;
+  // per-kernel timing
+  bool prof = false;
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+    double work;
+  };
+  std::vector<Rec> pending;
+  struct Acc {
+    double ms = 0, work = 0;
+    uint64_t launches = 0;
+  };
+  std::map<std::string, Acc> acc;
+};
+
+// run `launch` between two events on `st` when profiling is on
+template <class F>
+static hipError_t timed(hw_ctx* c, const char* name, double work, hipStream_t st, F&& launch) {
+  if (!c->prof) return launch();
+  hw_ctx::Rec r{name, nullptr, nullptr, work};
+  hipError_t e = hipEventCreate(&r.a);
+  if (e == hipSuccess) e = hipEventCreate(&r.b);
+  if (e == hipSuccess) e = hipEventRecord(r.a, st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(r.b, st);
+  if (e == hipSuccess) c->pending.push_back(r);
+  return e;
+}
+
+static size_t rlwe_words(const hw_ctx* c) { return (size_t)2 * c->prm.nq * c->prm.N; }
+static size_t rgsw_words(const hw_ctx* c) { return (size_t)2 * 5 * c->prm.nq * rlwe_words(c); }
+static size_t lwe_words(const hw_ctx* c) { return (size_t)c->prm.nq * (c->prm.N + 1); }
+
+struct Dims {
+  uint32_t L, k0, k1, z;
+};
+
+
+// error reporting: sets the calling thread's message
+hw_status fail(hw_status st, const char* fmt, ...);
+hw_status ok();
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(e_ == hipErrorOutOfMemory ? HW_ENOMEM : HW_EDEVICE, "%s: %s", #expr, \
+                  hipGetErrorString(e_));                                              \
+  } while (0)
+
+#define CHECK(expr)            \
+  do {                         \
+    hw_status s_ = (expr);     \
+    if (s_ != HW_OK) return s_; \
+  } while (0)
+
+hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d);
+hw_status perm_for(hw_ctx* c, const hw_wisard_shape* sh, hipStream_t st, const uint32_t** out);
+
+// workspace bytes per sample of one training / inference call
+size_t train_ws_per_sample(const hw_ctx* c, const Dims& d);
+size_t infer_ws_per_sample(const hw_ctx* c, const hw_wisard_shape* sh, const Dims& d);
+
+// training / inference of n samples with an explicit workspace of ws_bytes
+// (at least one sample's worth) and a resolved device permutation; the
+// arguments are not checked again.  `timing` records per-kernel events.
+hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const uint32_t* perm,
+                     const uint32_t* x, const uint32_t* y, uint64_t n, uint32_t* model, uint32_t* cnt,
+                     uint32_t* ws, size_t ws_bytes, hipStream_t st, bool timing);
+hw_status infer_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const uint32_t* perm,
+                     const uint32_t* model, const uint32_t* x, uint64_t n, uint32_t* scores, uint32_t* sums,
+                     uint32_t* ws, size_t ws_bytes, hipStream_t st, bool timing);

@@ -55,6 +55,18 @@ class TrainJob(C.Structure):
                 ("model", C.c_void_p), ("class_count", C.c_void_p)]
 
 
+class EngineConfig(C.Structure):
+    _fields_ = [("slots", C.c_uint32), ("chunk", C.c_uint32), ("max_s", C.c_uint32), ("max_cells", C.c_uint32),
+                ("arena_bytes", C.c_uint64)]
+
+
+class Request(C.Structure):
+    _fields_ = [("job", C.c_uint32), ("kind", C.c_uint32), ("bits_host", C.c_void_p), ("labels_host", C.c_void_p),
+                ("n", C.c_uint64), ("enc_seed", C.c_uint64), ("cells_host", C.c_void_p)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED, REQ_CANCELLED = 0, 1, 2, 3, 4
+
 _vp, _u64, _u32, _i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
 _SIG = {
     "hw_ctx_create": [C.POINTER(Params), _i32, C.POINTER(C.c_void_p)],
@@ -73,6 +85,13 @@ _SIG = {
     "hw_wisard_train_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_wisard_infer_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_batch_train": [_vp, C.POINTER(TrainJob), _u32, _vp],
+    "hw_engine_create": [C.POINTER(Params), _i32, _vp, C.POINTER(EngineConfig), C.POINTER(C.c_void_p)],
+    "hw_engine_add_job": [_vp, C.POINTER(Shape), _vp, _vp, C.POINTER(_u32)],
+    "hw_engine_submit": [_vp, C.POINTER(Request), C.POINTER(_u64)],
+    "hw_engine_poll": [_vp, _u64, C.POINTER(_i32), C.POINTER(C.c_double)],
+    "hw_engine_wait": [_vp, _u64, C.POINTER(_i32), C.POINTER(C.c_double)],
+    "hw_engine_cancel": [_vp, _u64],
+    "hw_engine_stats": [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u32)],
     "hw_profile_enable": [_vp, _i32],
     "hw_profile_read": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(_u64), C.POINTER(C.c_double)],
     "hw_profile_reset": [_vp],
@@ -83,13 +102,15 @@ for _n, _a in _SIG.items():
     _f.argtypes = _a
 _lib.hw_ctx_destroy.restype = None
 _lib.hw_ctx_destroy.argtypes = [_vp]
+_lib.hw_engine_destroy.restype = None
+_lib.hw_engine_destroy.argtypes = [_vp]
 _lib.hw_last_error.restype = C.c_char_p
 _lib.hw_last_error.argtypes = []
 
 
 def exported_symbols():
     """Names the library exports (for the ABI test)."""
-    return sorted(_SIG) + ["hw_ctx_destroy", "hw_last_error"]
+    return sorted(_SIG) + ["hw_ctx_destroy", "hw_engine_destroy", "hw_last_error"]
 
 
 def _check(st: int):
@@ -211,3 +232,69 @@ class Context:
     def infer(self, sh: Shape, model, x_rgsw, n: int, ram_scores, class_scores=None):
         _check(_lib.hw_wisard_infer_encrypted(self._h, C.byref(sh), _ptr(model), _ptr(x_rgsw), n,
                                               _ptr(ram_scores), _ptr(class_scores), _stream()))
+
+
+class Engine:
+    """Serving engine (hw_engine_*): continuous batching of train / infer
+    requests against resident models.  Host buffers handed to submit() are
+    kept alive here until the request has finished."""
+
+    def __init__(self, N: int, nq: int, p: int, sk, slots: int = 4, chunk: int = 8, max_s: int = 4096,
+                 max_cells: int = 4096, arena_bytes: int = 32 << 30, device: int = 0, sigma: float = 3.2):
+        prm = Params()
+        prm.N, prm.nq, prm.log_base, prm.digits, prm.sigma, prm.plain_mod = N, nq, 6, 5, sigma, p
+        cfg = EngineConfig(slots, chunk, max_s, max_cells, arena_bytes)
+        h = C.c_void_p()
+        _check(_lib.hw_engine_create(C.byref(prm), device, _ptr(sk), C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._sk = sk
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hw_engine_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_job(self, sh: Shape, model, class_count=None) -> int:
+        j = _u32()
+        _check(_lib.hw_engine_add_job(self._h, C.byref(sh), _ptr(model), _ptr(class_count), C.byref(j)))
+        self._keep[("job", j.value)] = (model, class_count)
+        return j.value
+
+    def submit(self, job: int, kind: str, bits: np.ndarray, enc_seed: int, labels: np.ndarray = None,
+               cells: np.ndarray = None) -> int:
+        bits = np.ascontiguousarray(bits, np.uint8)
+        labels = None if labels is None else np.ascontiguousarray(labels, np.uint8)
+        r = Request(job, 0 if kind == "train" else 1, bits.ctypes.data,
+                    None if labels is None or labels.size == 0 else labels.ctypes.data, bits.shape[0], enc_seed,
+                    None if cells is None else cells.ctypes.data)
+        rid = _u64()
+        _check(_lib.hw_engine_submit(self._h, C.byref(r), C.byref(rid)))
+        self._keep[rid.value] = (bits, labels, cells)
+        return rid.value
+
+    def poll(self, rid: int):
+        st, lat = _i32(), C.c_double()
+        _check(_lib.hw_engine_poll(self._h, rid, C.byref(st), C.byref(lat)))
+        return st.value, lat.value
+
+    def wait(self, rid: int):
+        st, lat = _i32(), C.c_double()
+        _check(_lib.hw_engine_wait(self._h, rid, C.byref(st), C.byref(lat)))
+        self._keep.pop(rid, None)
+        return st.value, lat.value
+
+    def cancel(self, rid: int):
+        _check(_lib.hw_engine_cancel(self._h, rid))
+
+    def stats(self):
+        c, pk, pi = _u64(), _u64(), _u32()
+        _check(_lib.hw_engine_stats(self._h, C.byref(c), C.byref(pk), C.byref(pi)))
+        return {"chunks": c.value, "peak_arena_bytes": pk.value, "peak_inflight": pi.value}

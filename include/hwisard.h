@@ -206,6 +206,27 @@ typedef struct {
  * Jobs must not share model or counter buffers. */
 hw_status hw_batch_train(hw_ctx* ctx, const hw_train_job* jobs, uint32_t njobs, hipStream_t stream);
 
+/* A batch plan: the windows and queues of hw_batch_train for a fixed list of
+ * jobs, computed once, with their tables uploaded to the device and every
+ * launch (queue reset, persistent training launch, reduction into the
+ * models, per window) captured into one HIP graph.  hw_batch_plan_launch
+ * replays that graph on `stream`: it reads the jobs' input ciphertexts as
+ * they are at replay time and adds their samples into the models, exactly
+ * as hw_batch_train on the same jobs would, with no host work per window.
+ * The plan owns its own workspace (hw_batch_plan_info: bytes) and tables;
+ * the job buffers stay caller-owned and must outlive the plan, and so must
+ * the context.  Replays of one plan must not overlap (they share the
+ * workspace); plans and contexts are independent of each other otherwise.
+ * Errors: those of hw_batch_train, plus HW_EDEVICE if capture fails. */
+typedef struct hw_batch_plan hw_batch_plan;
+hw_status hw_batch_plan_create(hw_ctx* ctx, const hw_train_job* jobs, uint32_t njobs,
+                               hw_batch_plan** plan);
+hw_status hw_batch_plan_launch(hw_batch_plan* plan, hipStream_t stream);
+hw_status hw_batch_plan_info(const hw_batch_plan* plan, uint32_t* windows, uint64_t* items,
+                             double* external_products, uint64_t* workspace_bytes);
+/* Waits for the device to finish the plan's replays, then frees it. */
+void hw_batch_plan_destroy(hw_batch_plan* plan);
+
 /* ---- serving engine (continuous batching) ------------------------------------- */
 
 /* A request loop on one device: train and infer requests against resident
@@ -279,8 +300,9 @@ hw_status hw_engine_stats(hw_engine* engine, uint64_t* chunks, uint64_t* peak_ar
 
 /* While enabled, every kernel launch made by the calls of this context is
  * bracketed by a pair of HIP events recorded on the caller's stream.  Kernel
- * names: "train", "reduce", "train_batch", "reduce_batch", "infer", "class_sums", "encrypt_rgsw",
- * "encrypt_rlwe", "decrypt_rlwe", "decrypt_lwe", "xp", "ntt". */
+ * names: "train", "reduce", "train_batch", "reduce_batch", "batch_plan" (a whole
+ * plan replay), "infer", "class_sums", "encrypt_rgsw", "encrypt_rlwe",
+ * "decrypt_rlwe", "decrypt_lwe", "xp", "ntt". */
 hw_status hw_profile_enable(hw_ctx* ctx, int enable);
 
 /* Waits for the recorded events and returns, for kernel `name`, the summed

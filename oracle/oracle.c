@@ -432,14 +432,32 @@ void orc_keygen(const orc_ctx* c, uint64_t seed, int32_t* s) {
   for (uint32_t k = 0; k < c->N; ++k) s[k] = (int32_t)(orc_w64(seed, DOM_KEY, k) % 3) - 1;
 }
 
+/* The polynomial of prime i whose value at the point psi^(2 brv(k) + 1) is
+ * ev[k] for every k < N (brv: bit reversal over log2 N bits).  Evaluation at
+ * the N roots psi^(2m+1) of X^N + 1 is a bijection of R_q onto Z_q^N (the
+ * ring isomorphism behind NTT multiplication, Sec. 2.1); its inverse is
+ * a_j = psi^{-j} N^{-1} sum_m E_m omega^{-m j} with E_m = ev[brv(m)], the
+ * value at psi^(2m+1), and omega = psi^2. */
+static void from_evaluations(const orc_ctx* c, uint32_t i, const uint64_t* ev, uint64_t* a) {
+  uint32_t N = c->N;
+  uint64_t q = c->q[i];
+  for (uint32_t m = 0; m < N; ++m) a[m] = ev[bitrev(m, c->logN)];
+  cyclic_ntt(a, N, c->logN, q, c->omega_ipow[i]);
+  for (uint32_t j = 0; j < N; ++j) a[j] = mulmod(mulmod(a[j], c->n_inv[i], q), c->psi_ipow[i][j], q);
+}
+
 /* EncRLWE of an integer polynomial mu (coefficients in [0, p)):
- * b = a*s + Delta*mu + e.  The draws of row `row` of ciphertext `ct` among
- * `rows` rows per ciphertext are
- *   a_{i,k} = w64(seed, ENC_A, ((ct*rows + row)*nq + i)*N + k) mod q_i
+ * b = a*s + Delta*mu + e, a uniform in R_q (Sec. 2.5.1).  The draws of row
+ * `row` of ciphertext `ct` among `rows` rows per ciphertext are
+ *   u_{i,k} = w64(seed, ENC_A, ((ct*rows + row)*nq + i)*N + k) mod q_i
  *   e_k     = CDT(w64(seed, ENC_E, (ct*rows + row)*N + k)),
- * e being one integer polynomial shared by all primes.  mu == NULL encrypts 0. */
-void orc_enc_rlwe_row(const orc_ctx* c, const int32_t* s, const uint64_t* mu, uint64_t seed,
-                      uint64_t ct, uint64_t rows, uint64_t row, uint32_t* out) {
+ * e being one integer polynomial shared by all primes.  With a_eval == 0
+ * the u_{i,k} are the coefficients of a mod q_i; with a_eval != 0 they are
+ * its values at the points psi_i^(2 brv(k) + 1) (the same uniform
+ * distribution on R_q, since evaluation is a bijection).  mu == NULL
+ * encrypts 0. */
+static void enc_row(const orc_ctx* c, const int32_t* s, const uint64_t* mu, uint64_t seed, uint64_t ct,
+                    uint64_t rows, uint64_t row, int a_eval, uint32_t* out) {
   uint32_t N = c->N, nq = c->nq;
   uint64_t* A = (uint64_t*)malloc(sizeof(uint64_t) * N);
   uint64_t* S = (uint64_t*)malloc(sizeof(uint64_t) * N);
@@ -450,9 +468,13 @@ void orc_enc_rlwe_row(const orc_ctx* c, const int32_t* s, const uint64_t* mu, ui
   for (uint32_t i = 0; i < nq; ++i) {
     uint64_t q = c->q[i];
     for (uint32_t k = 0; k < N; ++k) {
-      A[k] = orc_w64(seed, DOM_ENC_A, (rid * nq + i) * N + k) % q;
+      P[k] = orc_w64(seed, DOM_ENC_A, (rid * nq + i) * N + k) % q;
       S[k] = (uint64_t)(s[k] < 0 ? (int64_t)q + s[k] : s[k]);
     }
+    if (a_eval)
+      from_evaluations(c, i, P, A);
+    else
+      memcpy(A, P, sizeof(uint64_t) * N);
     negmul_ntt(c, i, A, S, P);
     uint32_t* oa = out + (size_t)i * N;
     uint32_t* ob = out + ((size_t)nq + i) * N;
@@ -469,23 +491,30 @@ void orc_enc_rlwe_row(const orc_ctx* c, const int32_t* s, const uint64_t* mu, ui
   free(e);
 }
 
+void orc_enc_rlwe_row(const orc_ctx* c, const int32_t* s, const uint64_t* mu, uint64_t seed,
+                      uint64_t ct, uint64_t rows, uint64_t row, uint32_t* out) {
+  enc_row(c, s, mu, seed, ct, rows, row, 0, out);
+}
+
+/* RLWE ciphertexts draw a by its coefficients */
 void orc_enc_rlwe(const orc_ctx* c, const int32_t* s, const uint64_t* mu, uint64_t seed, uint64_t ct,
                   uint32_t* out) {
-  orc_enc_rlwe_row(c, s, mu, seed, ct, 1, 0, out);
+  enc_row(c, s, mu, seed, ct, 1, 0, 0, out);
 }
 
 /* EncRGSW of a bit m: 2D rows, each an encryption of 0, plus m * g_{i,j} on
  * residue i of the b part (rows i*digits+j) or of the a part (rows
  * D + i*digits + j), g_{i,j} = base^j.  The paper's gadget entry carries a
  * stray 1/p factor (Sec. 2.5.1, EncRGSW); the exact gadget base^j is the
- * reading taken here, in its RNS form (one gadget row per prime and digit). */
+ * reading taken here, in its RNS form (one gadget row per prime and digit).
+ * Each row draws its a by its values at the evaluation points (enc_row). */
 void orc_enc_rgsw(const orc_ctx* c, const int32_t* s, uint32_t m, uint64_t seed, uint64_t ct,
                   uint32_t* out) {
   uint32_t N = c->N, nq = c->nq, D = c->D, rows = 2 * D;
   size_t rw = rlwe_words(c);
   for (uint32_t r = 0; r < rows; ++r) {
     uint32_t* row = out + r * rw;
-    orc_enc_rlwe_row(c, s, NULL, seed, ct, rows, r, row);
+    enc_row(c, s, NULL, seed, ct, rows, r, 1, row);
     if (m) {
       uint32_t side = r < D ? 1u : 0u; /* b for the first D rows, a after */
       uint32_t rr = r % D, i = rr / c->digits, j = rr % c->digits;

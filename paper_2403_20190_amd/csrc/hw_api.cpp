@@ -626,10 +626,25 @@ static uint32_t item_xp(uint32_t nb, int logN) {
   return nr + ((1u << (nb - nr)) - 1);
 }
 
-extern "C" hw_status hw_batch_train(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs, hipStream_t st) {
-  CHECK(enter(c));
-  if (njobs == 0) return ok();
-  if (!jobs) return fail(HW_EINVAL, "null job list");
+namespace {
+// one persistent launch: its jobs (sample ranges of the caller's jobs) and
+// its queue of (job, sample, RAM) items, longest first
+struct BWindow {
+  std::vector<hw::BJob> jobs;
+  std::vector<hw::BItem> items;
+  uint64_t words = 0;  // model (+ counter) words the reduction writes
+  double xp = 0;       // external products of the window
+};
+}  // namespace
+
+// Validate the jobs, resolve their permutations and cut their samples into
+// windows whose per-sample blocks fit the workspace budget (or one sample's
+// block if that is larger).  *ws_words: workspace the largest window needs.
+static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs, hipStream_t st,
+                            std::vector<BWindow>& wins, size_t* ws_words) {
+  wins.clear();
+  *ws_words = 0;
+  if (njobs && !jobs) return fail(HW_EINVAL, "null job list");
   std::vector<Dims> dims(njobs);
   std::vector<const uint32_t*> perms(njobs, nullptr);
   for (uint32_t j = 0; j < njobs; ++j) {
@@ -639,6 +654,7 @@ extern "C" hw_status hw_batch_train(hw_ctx* c, const hw_train_job* jobs, uint32_
     if (J.n == 0) continue;
     if (!J.x_rgsw_dev || !J.model_dev) return fail(HW_EINVAL, "job %u: null buffer", j);
     if (dims[j].L > 0 && !J.y_rgsw_dev) return fail(HW_EINVAL, "job %u: null label ciphertexts", j);
+    if (J.n > (1ull << 32) - 1) return fail(HW_EINVAL, "job %u: too many samples", j);
     for (uint32_t i = 0; i < j; ++i)
       if (jobs[i].n && (jobs[i].model_dev == J.model_dev ||
                         (J.class_count_dev && jobs[i].class_count_dev == J.class_count_dev)))
@@ -647,8 +663,10 @@ extern "C" hw_status hw_batch_train(hw_ctx* c, const hw_train_job* jobs, uint32_
   for (uint32_t j = 0; j < njobs; ++j)
     if (jobs[j].n) CHECK(perm_for(c, &jobs[j].shape, st, &perms[j]));
   const size_t rw = rlwe_words(c);
-  const size_t budget_words = c->ws_budget / 4;
-  if (!c->d_counter) HIP_TRY(hipMalloc(&c->d_counter, 64));
+  size_t max_block = 0;
+  for (uint32_t j = 0; j < njobs; ++j)
+    if (jobs[j].n) max_block = std::max(max_block, (size_t)(dims[j].k0 + 1) * (dims[j].k1 + 1) * rw);
+  const size_t cap = std::max(c->ws_budget / 4, max_block);
 
   struct Piece {
     uint32_t job;
@@ -656,25 +674,23 @@ extern "C" hw_status hw_batch_train(hw_ctx* c, const hw_train_job* jobs, uint32_
   };
   std::vector<Piece> win;
   size_t used = 0;
-
-  auto flush = [&]() -> hw_status {
+  auto close = [&]() -> hw_status {
     if (win.empty()) return HW_OK;
-    std::vector<hw::BJob> bj(win.size());
-    std::vector<hw::BItem> items;
-    uint64_t block = 0, words = 0;
-    double xp_total = 0;
+    BWindow W;
+    W.jobs.resize(win.size());
+    uint64_t block = 0;
     for (size_t p = 0; p < win.size(); ++p) {
       const Piece& P = win[p];
       const hw_train_job& J = jobs[P.job];
       const Dims& d = dims[P.job];
-      hw::BJob& b = bj[p];
+      hw::BJob& b = W.jobs[p];
       b.x = J.x_rgsw_dev + P.s0 * J.shape.s * rgsw_words(c);
       b.y = J.y_rgsw_dev ? J.y_rgsw_dev + P.s0 * d.L * rgsw_words(c) : nullptr;
       b.perm = perms[P.job];
       b.model = J.model_dev;
       b.cnt = J.class_count_dev;
       b.block0 = block;
-      b.words0 = words;
+      b.words0 = W.words;
       b.s = J.shape.s;
       b.a = J.shape.a;
       b.L = d.L;
@@ -682,21 +698,85 @@ extern "C" hw_status hw_batch_train(hw_ctx* c, const hw_train_job* jobs, uint32_
       b.k1 = d.k1;
       b.nsmp = (uint32_t)P.cnt;
       block += P.cnt * (size_t)(d.k0 + 1) * (d.k1 + 1) * rw;
-      words += (size_t)d.k0 * d.k1 * rw + (J.class_count_dev ? rw : 0);
+      W.words += (size_t)d.k0 * d.k1 * rw + (J.class_count_dev ? rw : 0);
       const uint32_t nram = d.k0 + (J.class_count_dev ? 1 : 0);
       for (uint32_t smp = 0; smp < P.cnt; ++smp)
         for (uint32_t r = 0; r < nram; ++r) {
           const uint32_t nb = r < d.k0 ? d.L + std::min(J.shape.a, J.shape.s - r * J.shape.a) : d.L;
           const uint32_t xp = item_xp(nb, c->logN);
-          items.push_back(hw::BItem{(uint32_t)p, smp, r, xp});
-          xp_total += xp;
+          W.items.push_back(hw::BItem{(uint32_t)p, smp, r, xp});
+          W.xp += xp;
         }
     }
+    if (W.items.size() > 0xFFFFFFFFull) return fail(HW_EINVAL, "too many items in one window");
     // longest items first: the queue then ends with short ones
-    std::stable_sort(items.begin(), items.end(),
+    std::stable_sort(W.items.begin(), W.items.end(),
                      [](const hw::BItem& x, const hw::BItem& y) { return x.xp > y.xp; });
-    const size_t jb = bj.size() * sizeof(hw::BJob), ib = items.size() * sizeof(hw::BItem);
-    const size_t need = jb + ib + 256;
+    *ws_words = std::max(*ws_words, (size_t)block);
+    wins.push_back(std::move(W));
+    win.clear();
+    used = 0;
+    return HW_OK;
+  };
+  for (uint32_t j = 0; j < njobs; ++j) {
+    const size_t blk = (size_t)(dims[j].k0 + 1) * (dims[j].k1 + 1) * rw;
+    for (uint64_t smp = 0; smp < jobs[j].n; ++smp) {
+      if (used + blk > cap) CHECK(close());
+      if (win.empty() || win.back().job != j) win.push_back(Piece{j, smp, 0});
+      win.back().cnt += 1;
+      used += blk;
+    }
+  }
+  return close();
+}
+
+// byte offsets of each window's job and item tables in one table buffer
+static size_t table_layout(const std::vector<BWindow>& wins, std::vector<size_t>& joff, std::vector<size_t>& ioff) {
+  size_t off = 0;
+  joff.resize(wins.size());
+  ioff.resize(wins.size());
+  for (size_t w = 0; w < wins.size(); ++w) {
+    joff[w] = off;
+    off = (off + wins[w].jobs.size() * sizeof(hw::BJob) + 255) / 256 * 256;
+    ioff[w] = off;
+    off = (off + wins[w].items.size() * sizeof(hw::BItem) + 255) / 256 * 256;
+  }
+  return off;
+}
+
+// enqueue one window: queue reset, persistent launch, reduction into the models
+static hw_status run_window(hw_ctx* c, const BWindow& W, const hw::BJob* djobs, const hw::BItem* ditems,
+                            uint32_t* counter, uint32_t* ws, hipStream_t st, bool timing) {
+  hw::BatchArgs A{};
+  A.jobs = djobs;
+  A.items = ditems;
+  A.nitems = (uint32_t)W.items.size();
+  A.counter = counter;
+  A.ws = ws;
+  A.rgsw_words = rgsw_words(c);
+  const bool tm = timing && c->prof;
+  auto lt = [&] { return hw::launch_train_batch(c->logN, c->prm.nq, c->tabs, A, st); };
+  HIP_TRY(tm ? timed(c, "train_batch", W.xp, st, lt) : lt());
+  auto lr = [&] {
+    return hw::launch_reduce_batch(c->tabs, djobs, (uint32_t)W.jobs.size(), W.words, c->logN, c->prm.N, c->prm.nq,
+                                   ws, st);
+  };
+  HIP_TRY(tm ? timed(c, "reduce_batch", (double)W.words, st, lr) : lr());
+  return HW_OK;
+}
+
+extern "C" hw_status hw_batch_train(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs, hipStream_t st) {
+  CHECK(enter(c));
+  if (njobs == 0) return ok();
+  std::vector<BWindow> wins;
+  size_t ws_words = 0;
+  CHECK(plan_batch(c, jobs, njobs, st, wins, &ws_words));
+  if (wins.empty()) return ok();
+  if (!c->d_counter) HIP_TRY(hipMalloc(&c->d_counter, 64));
+  CHECK(ensure_ws(c, 4 * ws_words));
+  for (const BWindow& W : wins) {
+    const size_t jb = W.jobs.size() * sizeof(hw::BJob), io = (jb + 255) / 256 * 256;
+    const size_t need = io + W.items.size() * sizeof(hw::BItem);
     HIP_TRY(hipStreamSynchronize(st));  // the previous window has released the tables
     if (need > c->btab_bytes) {
       if (c->h_btab) HIP_TRY(hipHostFree(c->h_btab));
@@ -708,49 +788,125 @@ extern "C" hw_status hw_batch_train(hw_ctx* c, const hw_train_job* jobs, uint32_
       c->btab_bytes = need;
     }
     char* h = static_cast<char*>(c->h_btab);
-    memcpy(h, bj.data(), jb);
-    const size_t ioff = (jb + 255) / 256 * 256;
-    memcpy(h + ioff, items.data(), ib);
-    HIP_TRY(hipMemcpyAsync(c->d_btab, c->h_btab, ioff + ib, hipMemcpyHostToDevice, st));
-    const hw::BJob* djobs = static_cast<const hw::BJob*>(c->d_btab);
-    hw::BatchArgs A{};
-    A.jobs = djobs;
-    A.items = reinterpret_cast<const hw::BItem*>(static_cast<char*>(c->d_btab) + ioff);
-    A.nitems = (uint32_t)items.size();
-    A.counter = c->d_counter;
-    A.ws = static_cast<uint32_t*>(c->d_ws);
-    A.rgsw_words = rgsw_words(c);
-    HIP_TRY(timed(c, "train_batch", xp_total, st,
-                  [&] { return hw::launch_train_batch(c->logN, c->prm.nq, c->tabs, A, st); }));
-    HIP_TRY(timed(c, "reduce_batch", (double)words, st, [&] {
-      return hw::launch_reduce_batch(c->tabs, djobs, (uint32_t)bj.size(), words, c->logN, c->prm.N, c->prm.nq,
-                                     A.ws, st);
-    }));
-    win.clear();
-    used = 0;
-    return HW_OK;
-  };
-
-  // workspace: the budget, or one sample's block if that is larger
-  size_t max_block = 0;
-  for (uint32_t j = 0; j < njobs; ++j)
-    if (jobs[j].n) max_block = std::max(max_block, (size_t)(dims[j].k0 + 1) * (dims[j].k1 + 1) * rw);
-  const size_t cap = std::max(budget_words, max_block);
-  size_t need_ws = 0;
-  for (uint32_t j = 0; j < njobs; ++j)
-    need_ws += jobs[j].n * (size_t)(dims[j].k0 + 1) * (dims[j].k1 + 1) * rw;
-  CHECK(ensure_ws(c, 4 * std::min(cap, need_ws)));
-  for (uint32_t j = 0; j < njobs; ++j) {
-    const size_t blk = (size_t)(dims[j].k0 + 1) * (dims[j].k1 + 1) * rw;
-    for (uint64_t smp = 0; smp < jobs[j].n; ++smp) {
-      if (used + blk > cap) CHECK(flush());
-      if (win.empty() || win.back().job != j) win.push_back(Piece{j, smp, 0});
-      win.back().cnt += 1;
-      used += blk;
-    }
+    memcpy(h, W.jobs.data(), jb);
+    memcpy(h + io, W.items.data(), W.items.size() * sizeof(hw::BItem));
+    HIP_TRY(hipMemcpyAsync(c->d_btab, c->h_btab, need, hipMemcpyHostToDevice, st));
+    char* d = static_cast<char*>(c->d_btab);
+    CHECK(run_window(c, W, reinterpret_cast<const hw::BJob*>(d), reinterpret_cast<const hw::BItem*>(d + io),
+                     c->d_counter, static_cast<uint32_t*>(c->d_ws), st, true));
   }
-  CHECK(flush());
   return ok();
+}
+
+// ---------------------------------------------------------------------------
+// batch plans: the same windows, tables uploaded once, launches captured
+// into a HIP graph
+// ---------------------------------------------------------------------------
+
+struct hw_batch_plan {
+  hw_ctx* ctx = nullptr;
+  int device = 0;
+  void* d_tab = nullptr;
+  uint32_t* d_ws = nullptr;
+  uint32_t* d_counter = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint32_t windows = 0;
+  uint64_t items = 0;
+  double xp = 0;
+  size_t ws_bytes = 0;
+};
+
+static void free_plan(hw_batch_plan* P) {
+  if (!P) return;
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->d_tab) (void)hipFree(P->d_tab);
+  if (P->d_ws) (void)hipFree(P->d_ws);
+  if (P->d_counter) (void)hipFree(P->d_counter);
+  delete P;
+}
+
+static hw_status build_plan(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs, hipStream_t cs, hw_batch_plan* P) {
+  std::vector<BWindow> wins;
+  size_t ws_words = 0;
+  CHECK(plan_batch(c, jobs, njobs, cs, wins, &ws_words));
+  std::vector<size_t> joff, ioff;
+  const size_t tab_bytes = table_layout(wins, joff, ioff);
+  P->windows = (uint32_t)wins.size();
+  for (const BWindow& W : wins) {
+    P->items += W.items.size();
+    P->xp += W.xp;
+  }
+  P->ws_bytes = 4 * ws_words;
+  HIP_TRY(hipMalloc(&P->d_counter, 64));
+  if (tab_bytes) {
+    std::vector<char> h(tab_bytes, 0);
+    for (size_t w = 0; w < wins.size(); ++w) {
+      memcpy(h.data() + joff[w], wins[w].jobs.data(), wins[w].jobs.size() * sizeof(hw::BJob));
+      memcpy(h.data() + ioff[w], wins[w].items.data(), wins[w].items.size() * sizeof(hw::BItem));
+    }
+    HIP_TRY(hipMalloc(&P->d_tab, tab_bytes));
+    HIP_TRY(hipMemcpy(P->d_tab, h.data(), tab_bytes, hipMemcpyHostToDevice));
+  }
+  if (P->ws_bytes) HIP_TRY(hipMalloc(&P->d_ws, P->ws_bytes));
+  // capture: kernel launches only (the queue counter is cleared by a kernel)
+  HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  hw_status st = HW_OK;
+  char* d = static_cast<char*>(P->d_tab);
+  for (size_t w = 0; w < wins.size() && st == HW_OK; ++w)
+    st = run_window(c, wins[w], reinterpret_cast<const hw::BJob*>(d + joff[w]),
+                    reinterpret_cast<const hw::BItem*>(d + ioff[w]), P->d_counter, P->d_ws, cs, false);
+  const hipError_t ec = hipStreamEndCapture(cs, &P->graph);
+  if (st != HW_OK) return st;
+  HIP_TRY(ec);
+  HIP_TRY(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+  return HW_OK;
+}
+
+extern "C" hw_status hw_batch_plan_create(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
+                                          hw_batch_plan** out) {
+  CHECK(enter(c));
+  if (!out) return fail(HW_EINVAL, "null output");
+  *out = nullptr;
+  hipStream_t cs = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hw_batch_plan* P = new hw_batch_plan();
+  P->ctx = c;
+  P->device = c->device;
+  const hw_status st = build_plan(c, jobs, njobs, cs, P);
+  (void)hipStreamDestroy(cs);
+  if (st != HW_OK) {
+    free_plan(P);
+    return st;
+  }
+  *out = P;
+  return ok();
+}
+
+extern "C" hw_status hw_batch_plan_launch(hw_batch_plan* P, hipStream_t st) {
+  if (!P) return fail(HW_EINVAL, "null plan");
+  hw_ctx* c = P->ctx;
+  CHECK(enter(c));
+  HIP_TRY(timed(c, "batch_plan", P->xp, st, [&] { return hipGraphLaunch(P->exec, st); }));
+  return ok();
+}
+
+extern "C" hw_status hw_batch_plan_info(const hw_batch_plan* P, uint32_t* windows, uint64_t* items, double* xp,
+                                        uint64_t* ws_bytes) {
+  if (!P) return fail(HW_EINVAL, "null plan");
+  if (windows) *windows = P->windows;
+  if (items) *items = P->items;
+  if (xp) *xp = P->xp;
+  if (ws_bytes) *ws_bytes = P->ws_bytes;
+  return ok();
+}
+
+extern "C" void hw_batch_plan_destroy(hw_batch_plan* P) {
+  if (!P) return;
+  (void)hipSetDevice(P->device);
+  (void)hipDeviceSynchronize();  // a launch still in flight reads the plan's buffers
+  free_plan(P);
 }
 
 // ---------------------------------------------------------------------------

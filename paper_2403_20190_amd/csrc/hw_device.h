@@ -45,10 +45,21 @@ struct Tabs {
 // modular arithmetic (q < 2^30, lazily reduced values below 4q < 2^32)
 // ---------------------------------------------------------------------------
 
-// x * w mod q in [0, 2q) for any 32-bit x (Shoup's method, w < q)
+// a * b + c on 64 bits in one VALU instruction (v_mad_u64_u32, full rate on
+// gfx950).  In asm because the compiler narrows a product whose high half is
+// unused to mul_lo + add and splits a full product into mul_lo + mul_hi.
+__device__ __forceinline__ uint64_t mad64(uint32_t a, uint32_t b, uint64_t c) {
+  uint64_t d, carry;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(d), "=s"(carry) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
+// x * w mod q in [0, 2q) for any 32-bit x (Shoup's method, w < q):
+// x w - floor(x wsh / 2^32) q, the subtraction folded into a multiply-add
+// with 2^32 - q (only the low 32 bits are kept)
 __device__ __forceinline__ uint32_t mulsh(uint32_t x, uint32_t w, uint32_t wsh, uint32_t q) {
   const uint32_t qh = __umulhi(x, wsh);
-  return x * w - qh * q;
+  return (uint32_t)mad64(qh, 0u - q, (uint64_t)(x * w));
 }
 
 // [0, 2m) -> [0, m) for m < 2^31: min(x, x - m) picks x - m exactly when x >= m
@@ -70,13 +81,20 @@ __device__ __forceinline__ uint32_t mulq(uint32_t a, uint32_t b, const PrimeTab&
 }
 
 // Harvey butterflies: forward (Cooley-Tukey) on [0, 4q), inverse
-// (Gentleman-Sande) on [0, 2q).
-__device__ __forceinline__ void bf_fwd(uint32_t& X, uint32_t& Y, uint32_t w, uint32_t wsh, uint32_t q,
-                                       uint32_t two_q) {
-  const uint32_t x = csub(X, two_q);
+// (Gentleman-Sande) on [0, 2q).  bf_fwd0 is the forward butterfly for an
+// upper input already below 2q (the first stage: transform inputs are < 2q).
+__device__ __forceinline__ void bf_fwd0(uint32_t& X, uint32_t& Y, uint32_t w, uint32_t wsh, uint32_t q,
+                                        uint32_t two_q) {
+  const uint32_t x = X;
   const uint32_t t = mulsh(Y, w, wsh, q);
   X = x + t;
   Y = x - t + two_q;
+}
+
+__device__ __forceinline__ void bf_fwd(uint32_t& X, uint32_t& Y, uint32_t w, uint32_t wsh, uint32_t q,
+                                       uint32_t two_q) {
+  X = csub(X, two_q);
+  bf_fwd0(X, Y, w, wsh, q, two_q);
 }
 
 __device__ __forceinline__ void bf_inv(uint32_t& X, uint32_t& Y, uint32_t w, uint32_t wsh, uint32_t q,
@@ -201,7 +219,7 @@ __device__ __forceinline__ void tw_phase(uint2 (&w)[7], const uint2* __restrict_
   w[6] = make_uint2(u1.z, u1.w);
 }
 
-// Output values are left in [0, 4q).
+// Input values below 2q; output values are left in [0, 4q).
 template <int LOGN>
 __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[8], const uint2* __restrict__ tab, const uint2* __restrict__ twl,
                                         uint32_t q, uint32_t two_q, uint32_t* lds, uint32_t& xc, uint32_t t) {
@@ -209,7 +227,7 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[8], const uint2* __restric
   {  // phase 0: stages 0..2, twiddles uniform over the workgroup
     const uint2 w1 = tab[1], w2 = tab[2], w3 = tab[3], w4 = tab[4], w5 = tab[5], w6 = tab[6], w7 = tab[7];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bf_fwd(x[e], x[e + 4], w1.x, w1.y, q, two_q);
+    for (int e = 0; e < 4; ++e) bf_fwd0(x[e], x[e + 4], w1.x, w1.y, q, two_q);
     bf_fwd(x[0], x[2], w2.x, w2.y, q, two_q);
     bf_fwd(x[1], x[3], w2.x, w2.y, q, two_q);
     bf_fwd(x[4], x[6], w3.x, w3.y, q, two_q);

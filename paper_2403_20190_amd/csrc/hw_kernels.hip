@@ -28,9 +28,9 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    // each 32 x 32 -> 64-bit product in one instruction (both halves used)
+    const uint64_t p0 = mad64(0xD2511F53u, c.x, 0ull), p1 = mad64(0xCD9E8D57u, c.z, 0ull);
+    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
   }
   return c;
 }
@@ -98,10 +98,11 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_sk_hat(Tabs T, const int32_t* 
 // ---------------------------------------------------------------------------
 // encryption
 // ---------------------------------------------------------------------------
-// Draws of row `rid` (= ciphertext * rows + row): a_{i,k} is draw
-// (rid*NQ + i)*N + k of stream ENC_A reduced mod q_i; e_k is the CDT sample of
-// draw rid*N + k of stream ENC_E.  Threads generate pairs of draws and stage
-// them through LDS into the natural layout.
+// Draws of row `rid` (= ciphertext * rows + row): u_{i,k} is draw
+// (rid*NQ + i)*N + k of stream ENC_A reduced mod q_i, the coefficient k of a
+// for an RLWE ciphertext and the value of a at psi^(2 brv(k) + 1) for an RGSW
+// row; e_k is the CDT sample of draw rid*N + k of stream ENC_E.  Coefficient
+// draws are generated in pairs and staged through LDS into the natural layout.
 
 template <int LOGN>
 __device__ __forceinline__ void gen_uniform(uint64_t seed, uint64_t base_blk, const PrimeTab& P,
@@ -137,9 +138,12 @@ __device__ __forceinline__ void gen_gauss(uint64_t seed, uint64_t base_blk, cons
   for (int e = 0; e < 8; ++e) ev[e] = (int32_t)stage[t + TT * e];
 }
 
-// RGSW rows directly in the evaluation domain: a_hat = NTT(a),
-// b_hat = a_hat * s_hat + NTT(e); the gadget constant m*base^j is added to
-// every evaluation point (the transform of a constant polynomial is constant).
+// RGSW rows directly in the evaluation domain.  Draw k of prime i is the
+// value of a at the point psi^(2 brv(k) + 1), which is position k of the
+// forward transform's output (thread t holds positions 8t..8t+7, i.e. the
+// draw pairs 4t..4t+3): a_hat needs no transform.  b_hat = a_hat * s_hat +
+// NTT(e); the gadget constant m*base^j is added to every evaluation point
+// (the transform of a constant polynomial is constant).
 template <int LOGN, int NQ>
 __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
@@ -165,10 +169,16 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncA
     __syncthreads();
     load_tw_lds<LOGN>(twl, T.fwd[i], t);
     uint32_t xa[8], xe[8];
-    gen_uniform<LOGN>(A.seed, (rid * NQ + i) * (N / 2), P, stage, t, xa);
+    const uint64_t blk0 = (rid * NQ + i) * (N / 2) + 4 * t;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      uint64_t d0, d1;
+      draw_pair(A.seed, DOM_ENC_A, blk0 + f, d0, d1);
+      xa[2 * f] = red64(d0, P);
+      xa[2 * f + 1] = red64(d1, P);
+    }
 #pragma unroll
     for (int e = 0; e < 8; ++e) xe[e] = ev[e] < 0 ? (uint32_t)(ev[e] + (int32_t)P.q) : (uint32_t)ev[e];
-    ntt_fwd<LOGN>(xa, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
     ntt_fwd<LOGN>(xe, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
     const uint32_t g = (m && gi == (uint32_t)i) ? (1u << (A.log_base * gj)) : 0u;
     const uint4* sp = reinterpret_cast<const uint4*>(A.sk_hat + (size_t)i * N + (t << 3));
@@ -177,7 +187,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncA
     uint32_t oa[8], ob[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const uint32_t a = red4q(xa[e], P.q, P.two_q);
+      const uint32_t a = xa[e];
       const uint32_t ee = red4q(xe[e], P.q, P.two_q);
       uint32_t b = addq(mulq(a, sh[e], P), ee, P.q);
       oa[e] = brow ? a : addq(a, g, P.q);

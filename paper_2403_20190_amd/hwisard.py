@@ -85,6 +85,9 @@ _SIG = {
     "hw_wisard_train_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_wisard_infer_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_batch_train": [_vp, C.POINTER(TrainJob), _u32, _vp],
+    "hw_batch_plan_create": [_vp, C.POINTER(TrainJob), _u32, C.POINTER(C.c_void_p)],
+    "hw_batch_plan_launch": [_vp, _vp],
+    "hw_batch_plan_info": [_vp, C.POINTER(_u32), C.POINTER(_u64), C.POINTER(C.c_double), C.POINTER(_u64)],
     "hw_engine_create": [C.POINTER(Params), _i32, _vp, C.POINTER(EngineConfig), C.POINTER(C.c_void_p)],
     "hw_engine_add_job": [_vp, C.POINTER(Shape), _vp, _vp, C.POINTER(_u32)],
     "hw_engine_submit": [_vp, C.POINTER(Request), C.POINTER(_u64)],
@@ -104,13 +107,15 @@ _lib.hw_ctx_destroy.restype = None
 _lib.hw_ctx_destroy.argtypes = [_vp]
 _lib.hw_engine_destroy.restype = None
 _lib.hw_engine_destroy.argtypes = [_vp]
+_lib.hw_batch_plan_destroy.restype = None
+_lib.hw_batch_plan_destroy.argtypes = [_vp]
 _lib.hw_last_error.restype = C.c_char_p
 _lib.hw_last_error.argtypes = []
 
 
 def exported_symbols():
     """Names the library exports (for the ABI test)."""
-    return sorted(_SIG) + ["hw_ctx_destroy", "hw_engine_destroy", "hw_last_error"]
+    return sorted(_SIG) + ["hw_ctx_destroy", "hw_engine_destroy", "hw_batch_plan_destroy", "hw_last_error"]
 
 
 def _check(st: int):
@@ -229,9 +234,46 @@ class Context:
             arr[i] = TrainJob(sh, _ptr(x), _ptr(y), n, _ptr(model), _ptr(cnt))
         _check(_lib.hw_batch_train(self._h, arr, len(jobs), _stream()))
 
+    def batch_plan(self, jobs):
+        """A BatchPlan for the jobs of batch_train: launches captured once into
+        a HIP graph, replayed with plan.launch()."""
+        return BatchPlan(self, jobs)
+
     def infer(self, sh: Shape, model, x_rgsw, n: int, ram_scores, class_scores=None):
         _check(_lib.hw_wisard_infer_encrypted(self._h, C.byref(sh), _ptr(model), _ptr(x_rgsw), n,
                                               _ptr(ram_scores), _ptr(class_scores), _stream()))
+
+
+class BatchPlan:
+    """hw_batch_plan_*: the windows of a batch computed once and captured into
+    a HIP graph; launch() replays it on the current stream.  The job buffers
+    are kept referenced here for the plan's lifetime."""
+
+    def __init__(self, ctx: "Context", jobs):
+        jobs = list(jobs)
+        arr = (TrainJob * max(1, len(jobs)))()
+        for i, (sh, x, y, n, model, cnt) in enumerate(jobs):
+            arr[i] = TrainJob(sh, _ptr(x), _ptr(y), n, _ptr(model), _ptr(cnt))
+        h = C.c_void_p()
+        _check(_lib.hw_batch_plan_create(ctx._h, arr, len(jobs), C.byref(h)))
+        self._h, self._ctx, self._jobs = h, ctx, jobs
+        w, it, xp, ws = _u32(), _u64(), C.c_double(), _u64()
+        _check(_lib.hw_batch_plan_info(h, C.byref(w), C.byref(it), C.byref(xp), C.byref(ws)))
+        self.windows, self.items, self.external_products, self.workspace_bytes = w.value, it.value, xp.value, ws.value
+
+    def launch(self):
+        _check(_lib.hw_batch_plan_launch(self._h, _stream()))
+
+    def close(self):
+        if self._h:
+            _lib.hw_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Engine:

@@ -102,3 +102,81 @@ def test_batch_argument_checks():
     before = host_u32(H).copy()
     ctx.batch_train([])
     assert np.array_equal(host_u32(H), before)
+
+
+def _fresh_outputs(pairs, bufs):
+    return [(pair.shape, b[0], b[1], pair.n, zeros_u32(pair.k0, pair.k1, 2, pair.nq, pair.N),
+             zeros_u32(2, pair.nq, pair.N) if cnt else None) for (pair, cnt), b in zip(pairs, bufs)]
+
+
+def _same(jobs, ref):
+    for j, r in zip(jobs, ref):
+        if not np.array_equal(host_u32(j[4]), host_u32(r[4])):
+            return False
+        if j[5] is not None and not np.array_equal(host_u32(j[5]), host_u32(r[5])):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("ws_bytes", [None, "1"])
+def test_batch_plan_replays_match_eager(ws_bytes):
+    """A batch plan (windows computed once, launches captured into a HIP
+    graph) replayed three times, with eager work and synchronisations between
+    the replays, equals the eager batched call every time; a replay without
+    clearing the models adds the batch again; replays read the inputs as they
+    are at replay time.  ws_bytes="1" forces one window per sample."""
+    import torch
+    from paper_2403_20190_amd import hwisard as HW
+    if ws_bytes:
+        os.environ["HWISARD_WS_BYTES"] = ws_bytes
+    try:
+        ctx = HW.Context(1024, 2, 64)
+    finally:
+        os.environ.pop("HWISARD_WS_BYTES", None)
+    pairs = make_jobs(dict(N=1024, nq=2, p=64), seed0=60)
+    for pair, _ in pairs:
+        pair.ctx, pair.sk, pair.sk_o = ctx, pairs[0][0].sk, pairs[0][0].sk_o
+    bufs = run_batch(ctx, pairs)
+    ref = [(None, None, None, None, b[2], b[3]) for b in bufs]
+    jobs = _fresh_outputs(pairs, bufs)
+    plan = ctx.batch_plan(jobs)
+    assert plan.windows > 1 if ws_bytes else plan.windows == 1
+    assert plan.items > 0 and plan.external_products > 0
+    for rep in range(3):
+        for j in jobs:
+            j[4].zero_()
+            if j[5] is not None:
+                j[5].zero_()
+        plan.launch()
+        torch.cuda.synchronize()
+        assert _same(jobs, ref), rep
+        # unrelated eager work on the same context between replays
+        pair = pairs[2][0]
+        H = zeros_u32(pair.k0, pair.k1, 2, pair.nq, pair.N)
+        ctx.train(pair.shape, bufs[2][0], bufs[2][1], pair.n, H, None)
+        torch.cuda.synchronize()
+    # a second replay on top of the first adds the batch again (mod q)
+    plan.launch()
+    torch.cuda.synchronize()
+    primes = pairs[0][0].orc.primes
+    for j, r in zip(jobs, ref):
+        twice = host_u32(r[4]).astype(np.uint64) * 2
+        for i, q in enumerate(primes):
+            twice[:, :, :, i, :] %= q
+        assert np.array_equal(host_u32(j[4]), twice.astype(np.uint32))
+    # new input bits encrypted into job 0's buffer: the replay sees them
+    pair = pairs[0][0]
+    X2, _ = synth.prototype_bits(99, pair.n, pair.s, pair.l, flip=0.3)
+    ctx.encrypt_rgsw_bits(pair.sk, dev(np.ascontiguousarray(X2, np.uint8).reshape(-1)), pair.seed_x + 5, 0,
+                          bufs[0][0])
+    for j in jobs:
+        j[4].zero_()
+        if j[5] is not None:
+            j[5].zero_()
+    plan.launch()
+    eager = _fresh_outputs(pairs, bufs)
+    ctx.batch_train(eager)
+    torch.cuda.synchronize()
+    assert _same(jobs, eager)
+    assert not np.array_equal(host_u32(jobs[0][4]), host_u32(ref[0][4]))
+    plan.close()

@@ -178,3 +178,46 @@ def test_noise_health_after_chain():
     mu[0b10110110101] = 1
     mx, _ = c.noise_rlwe(s, out[0], mu)
     assert mx * 16 < c.delta / 2
+
+
+def _psi(q, N):
+    """psi = g^((q-1)/2N) for the smallest quadratic non-residue g >= 2 (Euler's
+    criterion), a primitive 2N-th root of unity mod q: psi^N = -1."""
+    g = 2
+    while pow(g, (q - 1) // 2, q) != q - 1:
+        g += 1
+    psi = pow(g, (q - 1) // (2 * N), q)
+    assert pow(psi, N, q) == q - 1
+    return psi
+
+
+def _brv(k, bits):
+    return int(format(k, "0%db" % bits)[::-1], 2)
+
+
+@pytest.mark.parametrize("N,nq", [(1024, 1), (2048, 2)])
+def test_rgsw_rows_draw_a_by_its_evaluations(N, nq):
+    """An RGSW row's uniform a is drawn as its values at the points
+    psi^(2 brv(k) + 1): evaluating the oracle's coefficient-form a there by
+    Horner's rule (brute force, no transform) gives back draw k.  RLWE
+    ciphertexts draw a by its coefficients."""
+    c = O.Ctx(N, nq, 64)
+    s = c.keygen(5)
+    seed, ct = 77, 3
+    rows = 2 * 5 * nq
+    rg = c.enc_rgsw(s, 0, seed, ct)  # bit 0: no gadget term on the a side
+    logN = N.bit_length() - 1
+    for r in (0, rows - 1):
+        for i, q in enumerate(c.primes):
+            a = [int(v) for v in rg[r, 0, i]]
+            psi = _psi(q, N)
+            for k in (0, 1, 2, N // 2 + 3, N - 1):
+                x = pow(psi, 2 * _brv(k, logN) + 1, q)
+                acc = 0
+                for coef in reversed(a):
+                    acc = (acc * x + coef) % q
+                assert acc == O.w64(seed, 3, ((ct * rows + r) * nq + i) * N + k) % q, (r, i, k)
+    rl = c.enc_rlwe(s, np.zeros(N, np.uint64), seed, ct)
+    for i, q in enumerate(c.primes):
+        for k in (0, 5, N - 1):
+            assert int(rl[0, i, k]) == O.w64(seed, 3, (ct * nq + i) * N + k) % q

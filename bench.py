@@ -256,6 +256,7 @@ def main():
         if train_kernel_ms else None,
     }
 
+    result["schedule"] = ctx.schedule()
     del xr, yr, xb, yb
     torch.cuda.empty_cache()
     if not args.no_extras:
@@ -266,6 +267,8 @@ def main():
             result["batched"] = [batched_pass(sc, dev) for sc in args.batched_scale]
         if not args.no_served:
             result["served"] = served_pass(dev, args.served_requests, args.served_max_size, args.served_load)
+    if not args.no_extras:
+        result["schedule"] = ctx.schedule()
     if not args.no_cpu_baseline and not args.no_extras:
         result["cpu_baseline"] = cpu_baseline(W, Xtr, ytr, min(16, os.cpu_count() or 1), seeds)
     print(json.dumps(result), flush=True)
@@ -318,6 +321,10 @@ def ntt_pass(ctx, N, nq, dev):
     ctx.ntt(polys, count, False)
     ctx.ntt(polys, count, True)
     torch.cuda.synchronize()
+    for _ in range(10):  # the first launches tune the schedule (polynomials per workgroup)
+        ctx.ntt(polys, count, False)
+        ctx.ntt(polys, count, True)
+    torch.cuda.synchronize()
     ctx.profile(True)
     ctx.profile_reset()
     for _ in range(3):
@@ -333,9 +340,11 @@ def ntt_pass(ctx, N, nq, dev):
 
 def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     """256 uneven training jobs (sizes U{32..2000} x scale, s U{128..2352},
-    a U{8..12}, l U{2..10}, N 2048 or 4096): batched persistent launches versus
-    the same kernels one job at a time, on the same encrypted inputs.  Jobs of
-    one ring degree share a context (p = 4096 covers every job's counts)."""
+    a U{8..12}, l U{2..10}, N 2048 or 4096): batched persistent launches, and
+    the replay of a batch plan (the same launches captured into a HIP graph),
+    versus the same kernels one job at a time, on the same encrypted inputs.
+    Jobs of one ring degree share a context (p = 4096 covers every job's
+    counts)."""
     import numpy as np
     import torch
 
@@ -348,7 +357,7 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     for j, J in enumerate(jobs):
         groups.setdefault(J["N"], []).append((j, J))
     out = {"jobs": len(jobs), "scale": scale, "samples": 0, "xp": 0.0, "batched_ms": 0.0, "single_ms": 0.0,
-           "bit_identical": True}
+           "plan_ms": 0.0, "plan_max_pieces": 0, "kernel_ms": {}, "bit_identical": True}
     for N, members in sorted(groups.items()):
         nq = 2 if N == 2048 else 3
         ctx = HW.Context(N, nq, 4096)
@@ -375,23 +384,33 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
                 bufs.append((sh, xr, yr, n, k0, k1))
             mb = [torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev) for (_, _, _, _, k0, k1) in bufs]
             ms = [torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev) for (_, _, _, _, k0, k1) in bufs]
+            mp = [torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev) for (_, _, _, _, k0, k1) in bufs]
+            plan = ctx.batch_plan([(sh, xr, yr, n, m, None) for (sh, xr, yr, n, _, _), m in zip(bufs, mp)])
             ctx.profile(True)
             ctx.profile_reset()
             torch.cuda.synchronize()
-            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
             e0.record()
             ctx.batch_train([(sh, xr, yr, n, m, None) for (sh, xr, yr, n, _, _), m in zip(bufs, mb)])
             e1.record()
             for (sh, xr, yr, n, _, _), m in zip(bufs, ms):
                 ctx.train(sh, xr, yr, n, m, None)
             e2.record()
+            plan.launch()
+            e3.record()
             torch.cuda.synchronize()
             out["batched_ms"] += e0.elapsed_time(e1)
             out["single_ms"] += e1.elapsed_time(e2)
+            out["plan_ms"] += e2.elapsed_time(e3)
+            out["plan_max_pieces"] = max(out["plan_max_pieces"], plan.max_pieces)
             out["xp"] += ctx.profile_read("train_batch")[2]
+            for k in ("train_batch", "reduce_batch", "train", "reduce", "batch_plan"):
+                out["kernel_ms"][k] = out["kernel_ms"].get(k, 0.0) + ctx.profile_read(k)[0]
             ctx.profile(False)
+            plan.close()
             out["samples"] += sum(b[3] for b in bufs)
             out["bit_identical"] &= all(torch.equal(a, b) for a, b in zip(mb, ms))
+            out["bit_identical"] &= all(torch.equal(a, b) for a, b in zip(mb, mp))
 
         for j, J in members:
             n = max(1, int(round(J["n"] * scale)))
@@ -409,8 +428,11 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     out["single_job_samples_per_s"] = round(out["samples"] / (out["single_ms"] / 1000.0), 2)
     out["batched_xp_per_s"] = round(out["xp"] / (out["batched_ms"] / 1000.0), 1)
     out["speedup"] = round(out["single_ms"] / out["batched_ms"], 3)
+    out["plan_speedup"] = round(out["single_ms"] / out["plan_ms"], 3)
     out["batched_ms"] = round(out["batched_ms"], 1)
     out["single_ms"] = round(out["single_ms"], 1)
+    out["plan_ms"] = round(out["plan_ms"], 1)
+    out["kernel_ms"] = {k: round(v, 1) for k, v in out["kernel_ms"].items()}
     return out
 
 

@@ -198,31 +198,36 @@ typedef struct {
 } hw_train_job;
 
 /* Batched homomorphic training (Alg. 6 for every job).  The jobs share this
- * context's parameter set and may differ in shape and size.  They run as
- * persistent launches over one queue of (job, sample, RAM) items, longest
- * first, in windows whose per-sample output blocks fit the workspace; each
- * window ends with one exact modular reduction into every job's model.  The
- * result of each job is bit-identical to hw_wisard_train_encrypted on it.
- * Jobs must not share model or counter buffers. */
+ * context's parameter set and may differ in shape and size.  They run as one
+ * persistent launch over one queue of (job, RAM, piece) items, longest first:
+ * a piece is a run of consecutive samples of the job, whose IVP outputs the
+ * workgroup adds into the model row itself (first piece of the RAM) or into
+ * a workspace accumulator (further pieces), added into the model by one
+ * exact modular reduction afterwards.  Pieces are sized for load balance and
+ * lengthened until their accumulators fit the workspace budget, so the
+ * workspace does not grow with the number of samples.  The result of each
+ * job is bit-identical to hw_wisard_train_encrypted on it.  Jobs must not
+ * share model or counter buffers. */
 hw_status hw_batch_train(hw_ctx* ctx, const hw_train_job* jobs, uint32_t njobs, hipStream_t stream);
 
-/* A batch plan: the windows and queues of hw_batch_train for a fixed list of
- * jobs, computed once, with their tables uploaded to the device and every
- * launch (queue reset, persistent training launch, reduction into the
- * models, per window) captured into one HIP graph.  hw_batch_plan_launch
- * replays that graph on `stream`: it reads the jobs' input ciphertexts as
- * they are at replay time and adds their samples into the models, exactly
- * as hw_batch_train on the same jobs would, with no host work per window.
- * The plan owns its own workspace (hw_batch_plan_info: bytes) and tables;
+/* A batch plan: the queue and pieces of hw_batch_train for a fixed list of
+ * jobs, computed once, with their tables uploaded to the device and the
+ * launches (queue reset, persistent training launch, reduction of the
+ * accumulators) captured into one HIP graph.  hw_batch_plan_launch replays
+ * that graph on `stream`: it reads the jobs' input ciphertexts as they are
+ * at replay time and adds their samples into the models, exactly as
+ * hw_batch_train on the same jobs would, with no host work.  The plan owns
+ * its workspace (hw_batch_plan_info: bytes; also the queue items, the most
+ * pieces of any RAM and the external products of one replay) and tables;
  * the job buffers stay caller-owned and must outlive the plan, and so must
  * the context.  Replays of one plan must not overlap (they share the
- * workspace); plans and contexts are independent of each other otherwise.
- * Errors: those of hw_batch_train, plus HW_EDEVICE if capture fails. */
+ * workspace).  Errors: those of hw_batch_train, plus HW_EDEVICE if capture
+ * fails. */
 typedef struct hw_batch_plan hw_batch_plan;
 hw_status hw_batch_plan_create(hw_ctx* ctx, const hw_train_job* jobs, uint32_t njobs,
                                hw_batch_plan** plan);
 hw_status hw_batch_plan_launch(hw_batch_plan* plan, hipStream_t stream);
-hw_status hw_batch_plan_info(const hw_batch_plan* plan, uint32_t* windows, uint64_t* items,
+hw_status hw_batch_plan_info(const hw_batch_plan* plan, uint64_t* items, uint32_t* max_pieces,
                              double* external_products, uint64_t* workspace_bytes);
 /* Waits for the device to finish the plan's replays, then frees it. */
 void hw_batch_plan_destroy(hw_batch_plan* plan);
@@ -295,6 +300,47 @@ hw_status hw_engine_cancel(hw_engine* engine, uint64_t request_id);
 /* Counters: chunks started, peak arena bytes in use, peak chunks in flight. */
 hw_status hw_engine_stats(hw_engine* engine, uint64_t* chunks, uint64_t* peak_arena_bytes,
                           uint32_t* peak_inflight);
+
+/* ---- schedule tuning ------------------------------------------------------------ */
+
+/* Kernels with more than one launch schedule; every variant computes the
+ * same bits, only its speed differs:
+ *   "train"        0: 2-D grid, the RAMs of a sample on consecutive workgroups;
+ *                  1: 1-D grid, XCD x (workgroup id mod 8) takes the x-th
+ *                     eighth of the (sample, RAM) items (label ciphertexts of
+ *                     a sample stay in one XCD's L2);
+ *                  2, 3 (N = 4096 only): 0 and 1 compiled for 4 waves per
+ *                     SIMD instead of 3 (two 512-thread workgroups per CU,
+ *                     a few registers spilled)
+ *   "infer"        0: 3-D grid (RAM, label, sample); 1: 1-D grid, the labels of
+ *                     a (sample, RAM) adjacent, grouped by XCD as above;
+ *                  2, 3 (N = 4096 only): as for "train"
+ *   "train_batch"  0: 3 waves per SIMD; 1 (N = 4096 only): 4 waves per SIMD
+ *   "ntt"          v: 2^v polynomials per workgroup (v < 4), the twiddle table
+ *                     copied to LDS once for all of them (forward transforms)
+ *   "ntt_inverse"  the same for inverse transforms
+ *   "encrypt_rgsw" 0, 1, 2: 1, 2 or 5 rows of an RGSW per workgroup
+ * By default each is tuned online per context: its first launches cycle
+ * through the variants, timed with HIP events on the launch stream, until
+ * each variant has two timings; the variant with the least time per unit of
+ * work (external products, polynomials, rows) is then used for the rest of
+ * the context's life (by hw_wisard_*, hw_batch_*, hw_ntt and
+ * hw_encrypt_rgsw_bits, and by a serving engine's own context).  Only launches large enough to fill the chip are
+ * timed (50,000 external products, 16,384 polynomials, 20,000 RGSW rows);
+ * smaller ones, and launches under stream capture, use the best variant so
+ * far (variant 0 before any timing).  The environment variable HWISARD_TUNE=0 (read at context
+ * creation) turns tuning off: variant 0 everywhere. */
+
+/* Force `variant` for `kernel` (-1: forget the timings and tune again).
+ * HW_EINVAL for an unknown kernel or a variant out of range. */
+hw_status hw_tune_set(hw_ctx* ctx, const char* kernel, int variant);
+
+/* The variant in use (-1 while still tuning), the number of timings taken
+ * and the number of variants. */
+hw_status hw_tune_get(hw_ctx* ctx, const char* kernel, int* variant, int* timings, int* count);
+
+/* Description of a variant, or NULL for an unknown kernel or variant. */
+const char* hw_tune_variant_name(const char* kernel, int variant);
 
 /* ---- per-kernel timing ------------------------------------------------------ */
 

@@ -233,6 +233,8 @@ extern "C" hw_status hw_ctx_create(const hw_params* params, int device, hw_ctx**
   }
   const char* wb = getenv("HWISARD_WS_BYTES");
   c->ws_budget = wb ? (size_t)strtoull(wb, nullptr, 10) : ((size_t)16 << 30);
+  const char* tn = getenv("HWISARD_TUNE");
+  c->tune_off = tn && strcmp(tn, "0") == 0;
   *out = c;
   return ok();
 }
@@ -248,6 +250,11 @@ extern "C" void hw_ctx_destroy(hw_ctx* c) {
   if (c->h_btab) hipHostFree(c->h_btab);
   if (c->d_btab) hipFree(c->d_btab);
   if (c->d_counter) hipFree(c->d_counter);
+  for (auto& kv : c->tune)
+    for (auto& p : kv.second.pend) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
   delete c;
 }
 
@@ -382,8 +389,12 @@ extern "C" hw_status hw_encrypt_rgsw_bits(hw_ctx* c, const int32_t* sk, const ui
   A.seed = seed;
   A.ct0 = ct0;
   A.log_base = c->prm.log_base;
-  HIP_TRY(timed(c, "encrypt_rgsw", (double)nbits * 10 * c->prm.nq, st,
-                [&] { return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, nbits, st); }));
+  const double rows = (double)nbits * 10 * c->prm.nq;
+  HIP_TRY(timed(c, "encrypt_rgsw", rows, st, [&] {
+    return tuned(c, "encrypt_rgsw", rows, st, [&](int v) {
+      return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, nbits, enc_rows_per_wg(v), st);
+    });
+  }));
   return ok();
 }
 
@@ -443,8 +454,12 @@ extern "C" hw_status hw_ntt(hw_ctx* c, uint32_t* polys, uint64_t count, int inve
   if (count == 0) return ok();
   if (!polys) return fail(HW_EINVAL, "null buffer");
   if (inverse != 0 && inverse != 1) return fail(HW_EINVAL, "inverse must be 0 or 1");
-  HIP_TRY(timed(c, "ntt", (double)count * c->prm.nq, st,
-                [&] { return hw::launch_ntt(c->logN, c->prm.nq, c->tabs, polys, count, inverse, st); }));
+  const double work = (double)count * c->prm.nq;
+  HIP_TRY(timed(c, "ntt", work, st, [&] {
+    return tuned(c, inverse ? "ntt_inverse" : "ntt", work, st, [&](int v) {
+      return hw::launch_ntt(c->logN, c->prm.nq, c->tabs, polys, count, inverse, 1u << v, st);
+    });
+  }));
   return ok();
 }
 
@@ -478,8 +493,10 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   const size_t rw = rlwe_words(c);
   uint64_t n_sub = ws_bytes / train_ws_per_sample(c, d);
   if (n_sub < 1) return fail(HW_ENOMEM, "training workspace smaller than one sample");
+  const uint32_t nram = d.k0 + (class_count ? 1 : 0);
   if (n_sub > n) n_sub = n;
-  if (n_sub > 65535) n_sub = 65535;
+  n_sub = std::min<uint64_t>(n_sub, std::min<uint64_t>(65535, (1u << 22) / nram));
+  if (n_sub < 1) return fail(HW_EINVAL, "too many RAMs for one launch");
   hw::TrainArgs A{};
   A.x_rgsw = x_rgsw;
   A.y_rgsw = y_rgsw;
@@ -503,7 +520,7 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   R.logN = c->logN;
   R.N = c->prm.N;
   R.nq = c->prm.nq;
-  const uint32_t nram = d.k0 + (class_count ? 1 : 0);
+  A.nram = nram;
   // external products per sample: the rotation chain and the CDEMUX tree of every RAM
   double xp_per_sample = 0;
   for (uint32_t j = 0; j < nram; ++j) {
@@ -515,8 +532,15 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
     const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
     A.i0 = i0;
-    auto lt = [&] { return hw::launch_train(c->logN, c->prm.nq, c->tabs, A, nram, (uint32_t)m, st); };
-    HIP_TRY(tm ? timed(c, "train", (double)m * xp_per_sample, st, lt) : lt());
+    A.nsub = (uint32_t)m;
+    const double xp = (double)m * xp_per_sample;
+    auto lt = [&] {
+      return tuned(c, "train", xp, st, [&](int v) {
+        A.map = (uint32_t)(v & 1);
+        return hw::launch_train(c->logN, c->prm.nq, c->tabs, A, v & 2 ? 4 : 3, st);
+      });
+    };
+    HIP_TRY(tm ? timed(c, "train", xp, st, lt) : lt());
     R.n_sub = m;
     auto lr = [&] { return hw::launch_reduce_model(c->tabs, R, st); };
     HIP_TRY(tm ? timed(c, "reduce", (double)d.k0 * d.k1 * rw, st, lr) : lr());
@@ -550,7 +574,8 @@ hw_status infer_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   uint64_t n_sub = ws_bytes / infer_ws_per_sample(c, sh, d);
   if (n_sub < 1) return fail(HW_ENOMEM, "inference workspace smaller than one sample");
   if (n_sub > n) n_sub = n;
-  if (n_sub > 65535) n_sub = 65535;
+  n_sub = std::min<uint64_t>(n_sub, std::min<uint64_t>(65535, (1u << 22) / ((uint64_t)d.k0 * sh->l)));
+  if (n_sub < 1) return fail(HW_EINVAL, "too many (RAM, label) pairs for one launch");
   const uint32_t slots = d.z > d.L + 1 ? (1u << (d.z - d.L - 1)) : 1u;
   // external products per sample: for every RAM and label, the encrypted
   // selection levels and the encrypted positions of the rotation chain
@@ -580,8 +605,15 @@ hw_status infer_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
     const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
     A.i0 = i0;
-    auto li = [&] { return hw::launch_infer(c->logN, c->prm.nq, c->tabs, A, (uint32_t)m, st); };
-    HIP_TRY(tm ? timed(c, "infer", (double)m * xp_per_sample, st, li) : li());
+    A.nsub = (uint32_t)m;
+    const double xp = (double)m * xp_per_sample;
+    auto li = [&] {
+      return tuned(c, "infer", xp, st, [&](int v) {
+        A.map = (uint32_t)(v & 1);
+        return hw::launch_infer(c->logN, c->prm.nq, c->tabs, A, v & 2 ? 4 : 3, st);
+      });
+    };
+    HIP_TRY(tm ? timed(c, "infer", xp, st, li) : li());
   }
   if (class_scores) {
     hw::SumArgs S{};
@@ -627,23 +659,29 @@ static uint32_t item_xp(uint32_t nb, int logN) {
 }
 
 namespace {
-// one persistent launch: its jobs (sample ranges of the caller's jobs) and
-// its queue of (job, sample, RAM) items, longest first
-struct BWindow {
+// one persistent launch: the jobs, the queue of (job, RAM, piece) items
+// (longest first) and the workspace it needs
+struct BPlan {
   std::vector<hw::BJob> jobs;
   std::vector<hw::BItem> items;
-  uint64_t words = 0;  // model (+ counter) words the reduction writes
-  double xp = 0;       // external products of the window
+  uint64_t words = 0;          // model (+ counter) words the reduction writes
+  uint64_t acc_words = 0;      // accumulators of pieces >= 1
+  uint64_t scratch_words = 0;  // per persistent workgroup
+  uint32_t grid = 0;           // persistent workgroups: the larger of grid_occ[]
+  uint32_t grid_occ[2] = {0, 0};  // for occupancy targets 3 and 4 (0: variant absent)
+  uint32_t max_pieces = 0;
+  double xp = 0;               // external products of the batch
+  size_t ws_words() const { return (size_t)grid * scratch_words + acc_words; }
 };
 }  // namespace
 
-// Validate the jobs, resolve their permutations and cut their samples into
-// windows whose per-sample blocks fit the workspace budget (or one sample's
-// block if that is larger).  *ws_words: workspace the largest window needs.
-static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs, hipStream_t st,
-                            std::vector<BWindow>& wins, size_t* ws_words) {
-  wins.clear();
-  *ws_words = 0;
+// Validate the jobs, resolve their permutations and cut every (job, RAM)
+// into pieces of consecutive samples.  A piece is aimed at 1/8 of one
+// workgroup's share of the batch (load balance of the longest-first queue);
+// pieces are made longer, down to one piece per RAM, until their
+// accumulators and the workgroups' scratch fit the workspace budget.
+static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs, hipStream_t st, BPlan& B) {
+  B = BPlan();
   if (njobs && !jobs) return fail(HW_EINVAL, "null job list");
   std::vector<Dims> dims(njobs);
   std::vector<const uint32_t*> perms(njobs, nullptr);
@@ -654,7 +692,7 @@ static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
     if (J.n == 0) continue;
     if (!J.x_rgsw_dev || !J.model_dev) return fail(HW_EINVAL, "job %u: null buffer", j);
     if (dims[j].L > 0 && !J.y_rgsw_dev) return fail(HW_EINVAL, "job %u: null label ciphertexts", j);
-    if (J.n > (1ull << 32) - 1) return fail(HW_EINVAL, "job %u: too many samples", j);
+    if (J.n > 0xFFFFFFFFull) return fail(HW_EINVAL, "job %u: too many samples", j);
     for (uint32_t i = 0; i < j; ++i)
       if (jobs[i].n && (jobs[i].model_dev == J.model_dev ||
                         (J.class_count_dev && jobs[i].class_count_dev == J.class_count_dev)))
@@ -662,145 +700,155 @@ static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
   }
   for (uint32_t j = 0; j < njobs; ++j)
     if (jobs[j].n) CHECK(perm_for(c, &jobs[j].shape, st, &perms[j]));
+  for (int v = 0; v < tune_variants(c, "train_batch"); ++v)
+    HIP_TRY(hw::batch_grid(c->logN, c->prm.nq, v ? 4 : 3, &B.grid_occ[v]));
+  B.grid = std::max(B.grid_occ[0], B.grid_occ[1]);
   const size_t rw = rlwe_words(c);
-  size_t max_block = 0;
-  for (uint32_t j = 0; j < njobs; ++j)
-    if (jobs[j].n) max_block = std::max(max_block, (size_t)(dims[j].k0 + 1) * (dims[j].k1 + 1) * rw);
-  const size_t cap = std::max(c->ws_budget / 4, max_block);
-
-  struct Piece {
-    uint32_t job;
-    uint64_t s0, cnt;
-  };
-  std::vector<Piece> win;
-  size_t used = 0;
-  auto close = [&]() -> hw_status {
-    if (win.empty()) return HW_OK;
-    BWindow W;
-    W.jobs.resize(win.size());
-    uint64_t block = 0;
-    for (size_t p = 0; p < win.size(); ++p) {
-      const Piece& P = win[p];
-      const hw_train_job& J = jobs[P.job];
-      const Dims& d = dims[P.job];
-      hw::BJob& b = W.jobs[p];
-      b.x = J.x_rgsw_dev + P.s0 * J.shape.s * rgsw_words(c);
-      b.y = J.y_rgsw_dev ? J.y_rgsw_dev + P.s0 * d.L * rgsw_words(c) : nullptr;
-      b.perm = perms[P.job];
-      b.model = J.model_dev;
-      b.cnt = J.class_count_dev;
-      b.block0 = block;
-      b.words0 = W.words;
-      b.s = J.shape.s;
-      b.a = J.shape.a;
-      b.L = d.L;
-      b.k0 = d.k0;
-      b.k1 = d.k1;
-      b.nsmp = (uint32_t)P.cnt;
-      block += P.cnt * (size_t)(d.k0 + 1) * (d.k1 + 1) * rw;
-      W.words += (size_t)d.k0 * d.k1 * rw + (J.class_count_dev ? rw : 0);
-      const uint32_t nram = d.k0 + (J.class_count_dev ? 1 : 0);
-      for (uint32_t smp = 0; smp < P.cnt; ++smp)
-        for (uint32_t r = 0; r < nram; ++r) {
-          const uint32_t nb = r < d.k0 ? d.L + std::min(J.shape.a, J.shape.s - r * J.shape.a) : d.L;
-          const uint32_t xp = item_xp(nb, c->logN);
-          W.items.push_back(hw::BItem{(uint32_t)p, smp, r, xp});
-          W.xp += xp;
-        }
-    }
-    if (W.items.size() > 0xFFFFFFFFull) return fail(HW_EINVAL, "too many items in one window");
-    // longest items first: the queue then ends with short ones
-    std::stable_sort(W.items.begin(), W.items.end(),
-                     [](const hw::BItem& x, const hw::BItem& y) { return x.xp > y.xp; });
-    *ws_words = std::max(*ws_words, (size_t)block);
-    wins.push_back(std::move(W));
-    win.clear();
-    used = 0;
-    return HW_OK;
-  };
+  // per job: RAMs, external products per (sample, RAM) and per sample
+  std::vector<uint32_t> nram(njobs, 0), xp_max(njobs, 0);
+  std::vector<double> xp_smp(njobs, 0);
+  double W = 0;
+  uint32_t k1max = 0;
   for (uint32_t j = 0; j < njobs; ++j) {
-    const size_t blk = (size_t)(dims[j].k0 + 1) * (dims[j].k1 + 1) * rw;
-    for (uint64_t smp = 0; smp < jobs[j].n; ++smp) {
-      if (used + blk > cap) CHECK(close());
-      if (win.empty() || win.back().job != j) win.push_back(Piece{j, smp, 0});
-      win.back().cnt += 1;
-      used += blk;
+    if (!jobs[j].n) continue;
+    const Dims& d = dims[j];
+    nram[j] = d.k0 + (jobs[j].class_count_dev ? 1 : 0);
+    for (uint32_t r = 0; r < nram[j]; ++r) {
+      const uint32_t nb = r < d.k0 ? d.L + std::min(jobs[j].shape.a, jobs[j].shape.s - r * jobs[j].shape.a) : d.L;
+      const uint32_t xp = item_xp(nb, c->logN);
+      xp_max[j] = std::max(xp_max[j], xp);
+      xp_smp[j] += xp;
     }
+    W += xp_smp[j] * (double)jobs[j].n;
+    k1max = std::max(k1max, d.k1);
   }
-  return close();
+  if (W == 0) return HW_OK;
+  B.scratch_words = (uint64_t)(k1max + 1) * rw;
+  std::vector<uint32_t> per(njobs, 1), pieces(njobs, 0);
+  double target = std::max(1.0, W / (8.0 * B.grid));
+  for (;;) {
+    B.acc_words = 0;
+    bool single = true;
+    for (uint32_t j = 0; j < njobs; ++j) {
+      if (!jobs[j].n) continue;
+      const uint64_t n = jobs[j].n;
+      per[j] = (uint32_t)std::min<uint64_t>(n, std::max<uint64_t>(1, (uint64_t)(target / xp_max[j])));
+      pieces[j] = (uint32_t)((n + per[j] - 1) / per[j]);
+      B.acc_words += (uint64_t)(pieces[j] - 1) * nram[j] * dims[j].k1 * rw;
+      single &= pieces[j] == 1;
+    }
+    if (single || 4 * B.ws_words() <= c->ws_budget) break;
+    target *= 2;
+  }
+  uint64_t acc0 = 0;
+  for (uint32_t j = 0; j < njobs; ++j) {
+    if (!jobs[j].n) continue;
+    const hw_train_job& J = jobs[j];
+    const Dims& d = dims[j];
+    hw::BJob b{};
+    b.x = J.x_rgsw_dev;
+    b.y = J.y_rgsw_dev;
+    b.perm = perms[j];
+    b.model = J.model_dev;
+    b.cnt = J.class_count_dev;
+    b.acc0 = acc0;
+    b.words0 = B.words;
+    b.s = J.shape.s;
+    b.a = J.shape.a;
+    b.L = d.L;
+    b.k0 = d.k0;
+    b.k1 = d.k1;
+    b.nsmp = (uint32_t)J.n;
+    b.nram = nram[j];
+    b.per = per[j];
+    b.pieces = pieces[j];
+    acc0 += (uint64_t)(pieces[j] - 1) * nram[j] * d.k1 * rw;
+    if (pieces[j] > 1) B.words += (uint64_t)d.k0 * d.k1 * rw + (J.class_count_dev ? rw : 0);
+    B.max_pieces = std::max(B.max_pieces, pieces[j]);
+    const uint32_t jb = (uint32_t)B.jobs.size();
+    // piece-major: the RAMs of one piece (one run of samples) are adjacent in
+    // the queue, so workgroups running at the same time share the samples'
+    // label ciphertexts in L2
+    for (uint32_t p = 0; p < pieces[j]; ++p) {
+      const uint64_t cnt = std::min<uint64_t>(per[j], J.n - (uint64_t)p * per[j]);
+      for (uint32_t r = 0; r < nram[j]; ++r) {
+        const uint32_t nb = r < d.k0 ? d.L + std::min(J.shape.a, J.shape.s - r * J.shape.a) : d.L;
+        const uint64_t ixp = cnt * item_xp(nb, c->logN);
+        B.items.push_back(hw::BItem{jb, r, p, (uint32_t)std::min<uint64_t>(ixp, 0xFFFFFFFFull)});
+        B.xp += (double)ixp;
+      }
+    }
+    B.jobs.push_back(b);
+  }
+  if (B.items.size() > 0xFFFFFFFFull) return fail(HW_EINVAL, "too many work items");
+  // longest items first: the queue then ends with short ones
+  std::stable_sort(B.items.begin(), B.items.end(),
+                   [](const hw::BItem& x, const hw::BItem& y) { return x.xp > y.xp; });
+  return HW_OK;
 }
 
-// byte offsets of each window's job and item tables in one table buffer
-static size_t table_layout(const std::vector<BWindow>& wins, std::vector<size_t>& joff, std::vector<size_t>& ioff) {
-  size_t off = 0;
-  joff.resize(wins.size());
-  ioff.resize(wins.size());
-  for (size_t w = 0; w < wins.size(); ++w) {
-    joff[w] = off;
-    off = (off + wins[w].jobs.size() * sizeof(hw::BJob) + 255) / 256 * 256;
-    ioff[w] = off;
-    off = (off + wins[w].items.size() * sizeof(hw::BItem) + 255) / 256 * 256;
-  }
-  return off;
-}
-
-// enqueue one window: queue reset, persistent launch, reduction into the models
-static hw_status run_window(hw_ctx* c, const BWindow& W, const hw::BJob* djobs, const hw::BItem* ditems,
-                            uint32_t* counter, uint32_t* ws, hipStream_t st, bool timing) {
+// enqueue the persistent launch and the reduction of the accumulators
+static hw_status run_batch(hw_ctx* c, const BPlan& B, const hw::BJob* djobs, const hw::BItem* ditems,
+                           uint32_t* counter, uint32_t* ws, hipStream_t st, bool timing) {
   hw::BatchArgs A{};
   A.jobs = djobs;
   A.items = ditems;
-  A.nitems = (uint32_t)W.items.size();
+  A.nitems = (uint32_t)B.items.size();
   A.counter = counter;
   A.ws = ws;
+  A.scratch_words = B.scratch_words;
+  A.acc = ws + (size_t)B.grid * B.scratch_words;
   A.rgsw_words = rgsw_words(c);
   const bool tm = timing && c->prof;
-  auto lt = [&] { return hw::launch_train_batch(c->logN, c->prm.nq, c->tabs, A, st); };
-  HIP_TRY(tm ? timed(c, "train_batch", W.xp, st, lt) : lt());
-  auto lr = [&] {
-    return hw::launch_reduce_batch(c->tabs, djobs, (uint32_t)W.jobs.size(), W.words, c->logN, c->prm.N, c->prm.nq,
-                                   ws, st);
+  auto lt = [&] {
+    return tuned(c, "train_batch", B.xp, st, [&](int v) {
+      return hw::launch_train_batch(c->logN, c->prm.nq, c->tabs, A, B.grid_occ[v], v ? 4 : 3, st);
+    });
   };
-  HIP_TRY(tm ? timed(c, "reduce_batch", (double)W.words, st, lr) : lr());
+  HIP_TRY(tm ? timed(c, "train_batch", B.xp, st, lt) : lt());
+  if (B.words) {
+    auto lr = [&] {
+      return hw::launch_reduce_batch(c->tabs, djobs, (uint32_t)B.jobs.size(), B.words, c->logN, c->prm.N,
+                                     c->prm.nq, A.acc, st);
+    };
+    HIP_TRY(tm ? timed(c, "reduce_batch", (double)B.words, st, lr) : lr());
+  }
   return HW_OK;
 }
 
 extern "C" hw_status hw_batch_train(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs, hipStream_t st) {
   CHECK(enter(c));
   if (njobs == 0) return ok();
-  std::vector<BWindow> wins;
-  size_t ws_words = 0;
-  CHECK(plan_batch(c, jobs, njobs, st, wins, &ws_words));
-  if (wins.empty()) return ok();
+  BPlan B;
+  CHECK(plan_batch(c, jobs, njobs, st, B));
+  if (B.items.empty()) return ok();
   if (!c->d_counter) HIP_TRY(hipMalloc(&c->d_counter, 64));
-  CHECK(ensure_ws(c, 4 * ws_words));
-  for (const BWindow& W : wins) {
-    const size_t jb = W.jobs.size() * sizeof(hw::BJob), io = (jb + 255) / 256 * 256;
-    const size_t need = io + W.items.size() * sizeof(hw::BItem);
-    HIP_TRY(hipStreamSynchronize(st));  // the previous window has released the tables
-    if (need > c->btab_bytes) {
-      if (c->h_btab) HIP_TRY(hipHostFree(c->h_btab));
-      if (c->d_btab) HIP_TRY(hipFree(c->d_btab));
-      c->h_btab = c->d_btab = nullptr;
-      c->btab_bytes = 0;
-      HIP_TRY(hipHostMalloc(&c->h_btab, need));
-      HIP_TRY(hipMalloc(&c->d_btab, need));
-      c->btab_bytes = need;
-    }
-    char* h = static_cast<char*>(c->h_btab);
-    memcpy(h, W.jobs.data(), jb);
-    memcpy(h + io, W.items.data(), W.items.size() * sizeof(hw::BItem));
-    HIP_TRY(hipMemcpyAsync(c->d_btab, c->h_btab, need, hipMemcpyHostToDevice, st));
-    char* d = static_cast<char*>(c->d_btab);
-    CHECK(run_window(c, W, reinterpret_cast<const hw::BJob*>(d), reinterpret_cast<const hw::BItem*>(d + io),
-                     c->d_counter, static_cast<uint32_t*>(c->d_ws), st, true));
+  CHECK(ensure_ws(c, 4 * B.ws_words()));
+  const size_t jb = B.jobs.size() * sizeof(hw::BJob), io = (jb + 255) / 256 * 256;
+  const size_t need = io + B.items.size() * sizeof(hw::BItem);
+  HIP_TRY(hipStreamSynchronize(st));  // an earlier batch on this stream has released the tables
+  if (need > c->btab_bytes) {
+    if (c->h_btab) HIP_TRY(hipHostFree(c->h_btab));
+    if (c->d_btab) HIP_TRY(hipFree(c->d_btab));
+    c->h_btab = c->d_btab = nullptr;
+    c->btab_bytes = 0;
+    HIP_TRY(hipHostMalloc(&c->h_btab, need));
+    HIP_TRY(hipMalloc(&c->d_btab, need));
+    c->btab_bytes = need;
   }
+  char* h = static_cast<char*>(c->h_btab);
+  memcpy(h, B.jobs.data(), jb);
+  memcpy(h + io, B.items.data(), B.items.size() * sizeof(hw::BItem));
+  HIP_TRY(hipMemcpyAsync(c->d_btab, c->h_btab, need, hipMemcpyHostToDevice, st));
+  char* d = static_cast<char*>(c->d_btab);
+  CHECK(run_batch(c, B, reinterpret_cast<const hw::BJob*>(d), reinterpret_cast<const hw::BItem*>(d + io),
+                  c->d_counter, static_cast<uint32_t*>(c->d_ws), st, true));
   return ok();
 }
 
 // ---------------------------------------------------------------------------
-// batch plans: the same windows, tables uploaded once, launches captured
-// into a HIP graph
+// batch plans: the same queue computed once, tables uploaded once, launches
+// captured into a HIP graph
 // ---------------------------------------------------------------------------
 
 struct hw_batch_plan {
@@ -811,8 +859,8 @@ struct hw_batch_plan {
   uint32_t* d_counter = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  uint32_t windows = 0;
   uint64_t items = 0;
+  uint32_t max_pieces = 0;
   double xp = 0;
   size_t ws_bytes = 0;
 };
@@ -828,24 +876,19 @@ static void free_plan(hw_batch_plan* P) {
 }
 
 static hw_status build_plan(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs, hipStream_t cs, hw_batch_plan* P) {
-  std::vector<BWindow> wins;
-  size_t ws_words = 0;
-  CHECK(plan_batch(c, jobs, njobs, cs, wins, &ws_words));
-  std::vector<size_t> joff, ioff;
-  const size_t tab_bytes = table_layout(wins, joff, ioff);
-  P->windows = (uint32_t)wins.size();
-  for (const BWindow& W : wins) {
-    P->items += W.items.size();
-    P->xp += W.xp;
-  }
-  P->ws_bytes = 4 * ws_words;
+  BPlan B;
+  CHECK(plan_batch(c, jobs, njobs, cs, B));
+  P->items = B.items.size();
+  P->max_pieces = B.max_pieces;
+  P->xp = B.xp;
+  P->ws_bytes = 4 * B.ws_words();
   HIP_TRY(hipMalloc(&P->d_counter, 64));
-  if (tab_bytes) {
+  const size_t jb = B.jobs.size() * sizeof(hw::BJob), io = (jb + 255) / 256 * 256;
+  const size_t tab_bytes = io + B.items.size() * sizeof(hw::BItem);
+  if (!B.items.empty()) {
     std::vector<char> h(tab_bytes, 0);
-    for (size_t w = 0; w < wins.size(); ++w) {
-      memcpy(h.data() + joff[w], wins[w].jobs.data(), wins[w].jobs.size() * sizeof(hw::BJob));
-      memcpy(h.data() + ioff[w], wins[w].items.data(), wins[w].items.size() * sizeof(hw::BItem));
-    }
+    memcpy(h.data(), B.jobs.data(), jb);
+    memcpy(h.data() + io, B.items.data(), B.items.size() * sizeof(hw::BItem));
     HIP_TRY(hipMalloc(&P->d_tab, tab_bytes));
     HIP_TRY(hipMemcpy(P->d_tab, h.data(), tab_bytes, hipMemcpyHostToDevice));
   }
@@ -853,10 +896,11 @@ static hw_status build_plan(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
   // capture: kernel launches only (the queue counter is cleared by a kernel)
   HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   hw_status st = HW_OK;
-  char* d = static_cast<char*>(P->d_tab);
-  for (size_t w = 0; w < wins.size() && st == HW_OK; ++w)
-    st = run_window(c, wins[w], reinterpret_cast<const hw::BJob*>(d + joff[w]),
-                    reinterpret_cast<const hw::BItem*>(d + ioff[w]), P->d_counter, P->d_ws, cs, false);
+  if (!B.items.empty()) {
+    char* d = static_cast<char*>(P->d_tab);
+    st = run_batch(c, B, reinterpret_cast<const hw::BJob*>(d), reinterpret_cast<const hw::BItem*>(d + io),
+                   P->d_counter, P->d_ws, cs, false);
+  }
   const hipError_t ec = hipStreamEndCapture(cs, &P->graph);
   if (st != HW_OK) return st;
   HIP_TRY(ec);
@@ -892,11 +936,11 @@ extern "C" hw_status hw_batch_plan_launch(hw_batch_plan* P, hipStream_t st) {
   return ok();
 }
 
-extern "C" hw_status hw_batch_plan_info(const hw_batch_plan* P, uint32_t* windows, uint64_t* items, double* xp,
+extern "C" hw_status hw_batch_plan_info(const hw_batch_plan* P, uint64_t* items, uint32_t* max_pieces, double* xp,
                                         uint64_t* ws_bytes) {
   if (!P) return fail(HW_EINVAL, "null plan");
-  if (windows) *windows = P->windows;
   if (items) *items = P->items;
+  if (max_pieces) *max_pieces = P->max_pieces;
   if (xp) *xp = P->xp;
   if (ws_bytes) *ws_bytes = P->ws_bytes;
   return ok();
@@ -907,6 +951,130 @@ extern "C" void hw_batch_plan_destroy(hw_batch_plan* P) {
   (void)hipSetDevice(P->device);
   (void)hipDeviceSynchronize();  // a launch still in flight reads the plan's buffers
   free_plan(P);
+}
+
+// ---------------------------------------------------------------------------
+// schedule tuning
+// ---------------------------------------------------------------------------
+
+namespace {
+struct TuneKernel {
+  const char* kernel;
+  double min_work;  // launches with less work (too few workgroups to fill the chip) are not timed
+  std::vector<const char*> variants;
+};
+// variants past the first two of "train" / "infer" and past the first of
+// "train_batch" (occupancy target 4) exist for N = 4096 only
+const std::vector<TuneKernel>& tune_table() {
+  static const std::vector<TuneKernel> t = {
+      {"train", 5e4, {"ram-major 2-D grid", "xcd-grouped 1-D grid", "ram-major 2-D grid, 4 waves/SIMD",
+                      "xcd-grouped 1-D grid, 4 waves/SIMD"}},
+      {"infer", 5e4, {"ram-major 3-D grid", "labels-adjacent xcd-grouped 1-D grid",
+                      "ram-major 3-D grid, 4 waves/SIMD", "labels-adjacent xcd-grouped 1-D grid, 4 waves/SIMD"}},
+      {"train_batch", 5e4, {"persistent, 3 waves/SIMD", "persistent, 4 waves/SIMD"}},
+      {"ntt", 16384, {"1 polynomial/workgroup", "2 polynomials/workgroup", "4 polynomials/workgroup",
+                      "8 polynomials/workgroup"}},
+      {"ntt_inverse", 16384, {"1 polynomial/workgroup", "2 polynomials/workgroup", "4 polynomials/workgroup",
+                              "8 polynomials/workgroup"}},
+      {"encrypt_rgsw", 2e4, {"1 row/workgroup", "2 rows/workgroup", "5 rows/workgroup"}},
+  };
+  return t;
+}
+}  // namespace
+
+int enc_rows_per_wg(int v) { return v == 2 ? 5 : v + 1; }
+
+static int table_variants(const char* kernel) {
+  for (const auto& k : tune_table())
+    if (!strcmp(k.kernel, kernel)) return (int)k.variants.size();
+  return 0;
+}
+
+int tune_variants(const hw_ctx* c, const char* kernel) {
+  const int n = table_variants(kernel);
+  if (c->logN == 12) return n;
+  if (!strcmp(kernel, "train") || !strcmp(kernel, "infer")) return 2;
+  if (!strcmp(kernel, "train_batch")) return 1;
+  return n;
+}
+
+double tune_min_work(const char* kernel) {
+  for (const auto& k : tune_table())
+    if (!strcmp(k.kernel, kernel)) return k.min_work;
+  return 0;
+}
+
+const char* tune_variant_name(const char* kernel, int v) {
+  for (const auto& k : tune_table())
+    if (!strcmp(k.kernel, kernel)) return v >= 0 && v < (int)k.variants.size() ? k.variants[v] : nullptr;
+  return nullptr;
+}
+
+void tune_settle(TuneState& S) {
+  for (size_t i = 0; i < S.pend.size();) {
+    TuneState::Pend& p = S.pend[i];
+    const hipError_t q = hipEventQuery(p.b);
+    if (q == hipErrorNotReady) {
+      ++i;
+      continue;
+    }
+    float ms = 0;
+    if (q == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess && p.work > 0) {
+      S.best[p.v] = std::min(S.best[p.v], (double)ms / p.work);
+      S.runs[p.v] += 1;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+    S.pend.erase(S.pend.begin() + i);
+  }
+  if (S.chosen >= 0 || S.runs.empty()) return;
+  for (int r : S.runs)
+    if (r < TUNE_RUNS) return;
+  int best = 0;
+  for (int v = 1; v < (int)S.best.size(); ++v)
+    if (S.best[v] < S.best[best]) best = v;
+  S.chosen = best;
+}
+
+extern "C" hw_status hw_tune_set(hw_ctx* c, const char* kernel, int variant) {
+  if (!c || !kernel) return fail(HW_EINVAL, "null argument");
+  const int n = tune_variants(c, kernel);
+  if (n == 0) return fail(HW_EINVAL, "no tunable kernel named '%s'", kernel);
+  if (variant < -1 || variant >= n) return fail(HW_EINVAL, "variant %d out of range [-1, %d)", variant, n);
+  CHECK(enter(c));
+  TuneState& S = c->tune[kernel];
+  for (auto& p : S.pend) {  // drop timings in flight
+    (void)hipEventSynchronize(p.b);
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  S = TuneState();
+  S.forced = variant;
+  return ok();
+}
+
+extern "C" hw_status hw_tune_get(hw_ctx* c, const char* kernel, int* variant, int* timings, int* count) {
+  if (!c || !kernel) return fail(HW_EINVAL, "null argument");
+  const int n = tune_variants(c, kernel);
+  if (n == 0) return fail(HW_EINVAL, "no tunable kernel named '%s'", kernel);
+  CHECK(enter(c));
+  TuneState& S = c->tune[kernel];
+  if ((int)S.runs.size() != n) {
+    S.runs.assign(n, 0);
+    S.best.assign(n, 1e300);
+  }
+  if (S.chosen < 0 && S.forced < 0 && (c->tune_off || n == 1)) S.chosen = 0;
+  tune_settle(S);
+  int t = 0;
+  for (int r : S.runs) t += r;
+  if (variant) *variant = S.forced >= 0 ? S.forced : S.chosen;
+  if (timings) *timings = t;
+  if (count) *count = n;
+  return ok();
+}
+
+extern "C" const char* hw_tune_variant_name(const char* kernel, int variant) {
+  return kernel ? tune_variant_name(kernel, variant) : nullptr;
 }
 
 // ---------------------------------------------------------------------------

@@ -14,6 +14,31 @@
 using hw::Tabs;
 typedef unsigned __int128 u128;
 
+// Online tuning of a kernel's schedule: every variant computes the same
+// bits; the first launches on a context cycle through the variants between
+// HIP events until each has been timed TUNE_RUNS times, then the one with the
+// least time per unit of work is kept.
+struct TuneState {
+  int forced = -1;                 // hw_tune_set
+  int chosen = -1;                 // after tuning
+  std::vector<double> best;        // per variant: least ms per unit of work seen
+  std::vector<int> runs;           // per variant: completed timings
+  struct Pend {
+    int v;
+    hipEvent_t a, b;
+    double work;
+  };
+  std::vector<Pend> pend;
+};
+constexpr int TUNE_RUNS = 2;
+
+struct hw_ctx;
+// the tuned kernels and their variants; nullptr past the last one
+const char* tune_variant_name(const char* kernel, int v);
+int tune_variants(const hw_ctx* c, const char* kernel);  // variants that exist for c's parameters
+int enc_rows_per_wg(int variant);  // "encrypt_rgsw" variant -> RGSW rows per workgroup
+double tune_min_work(const char* kernel);
+
 struct hw_ctx {
   hw_params prm;
   int device;
@@ -47,7 +72,55 @@ struct hw_ctx {
     uint64_t launches = 0;
   };
   std::map<std::string, Acc> acc;
+  // schedule tuning, by kernel name
+  bool tune_off = false;
+  std::map<std::string, TuneState> tune;
 };
+
+// fold finished timings in; choose once every variant has TUNE_RUNS of them
+void tune_settle(TuneState& S);
+
+// launch(v) with the variant the tuner picks for `kernel`, timing it while
+// tuning (not under stream capture, where the best variant so far is used)
+template <class F>
+static hipError_t tuned(hw_ctx* c, const char* kernel, double work, hipStream_t st, F&& launch) {
+  const int n = tune_variants(c, kernel);
+  TuneState& S = c->tune[kernel];
+  if ((int)S.runs.size() != n) {
+    S.runs.assign(n, 0);
+    S.best.assign(n, 1e300);
+  }
+  if (S.forced >= 0) return launch(S.forced);
+  if (S.chosen < 0 && (c->tune_off || n <= 1)) S.chosen = 0;
+  if (S.chosen < 0) tune_settle(S);
+  if (S.chosen >= 0) return launch(S.chosen);
+  int best = 0;
+  for (int v = 1; v < n; ++v)
+    if (S.best[v] < S.best[best]) best = v;
+  if (work < tune_min_work(kernel)) return launch(best);
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return launch(best);
+  // the variant with the fewest timings, pending ones included
+  std::vector<int> cnt(S.runs);
+  for (const auto& p : S.pend) cnt[p.v] += 1;
+  int v = 0;
+  for (int u = 1; u < n; ++u)
+    if (cnt[u] < cnt[v]) v = u;
+  if (cnt[v] >= TUNE_RUNS) return launch(best);  // all timed; waiting for results
+  TuneState::Pend p{v, nullptr, nullptr, work};
+  hipError_t e = hipEventCreate(&p.a);
+  if (e == hipSuccess) e = hipEventCreate(&p.b);
+  if (e == hipSuccess) e = hipEventRecord(p.a, st);
+  if (e == hipSuccess) e = launch(v);
+  if (e == hipSuccess) e = hipEventRecord(p.b, st);
+  if (e == hipSuccess) {
+    S.pend.push_back(p);
+  } else {
+    if (p.a) (void)hipEventDestroy(p.a);
+    if (p.b) (void)hipEventDestroy(p.b);
+  }
+  return e;
+}
 
 // run `launch` between two events on `st` when profiling is on
 template <class F>

@@ -355,10 +355,12 @@ __device__ __forceinline__ uint32_t red4q(uint32_t x, uint32_t q, uint32_t two_q
 // xin only as dst == src (each thread reads then writes its own coefficient).
 
 // What happens to h = C [.] xin, per output prime, coefficient k (natural):
-//   XP_STORE : dst[k] = h
-//   XP_ADD   : dst[k] = src[k] + h            (CMUX: d0 + C [.] (d1 - d0))
-//   XP_DEMUX : dst[k] = src[k] - h, dst2[k] = h (CDEMUX)
-enum XpMode : int { XP_STORE = 0, XP_ADD = 1, XP_DEMUX = 2 };
+//   XP_STORE     : dst[k] = h
+//   XP_ADD       : dst[k] = src[k] + h            (CMUX: d0 + C [.] (d1 - d0))
+//   XP_DEMUX     : dst[k] = src[k] - h, dst2[k] = h (CDEMUX)
+//   XP_DEMUX_ACC : dst[k] += src[k] - h, dst2[k] += h (CDEMUX outputs added
+//                  into accumulators)
+enum XpMode : int { XP_STORE = 0, XP_ADD = 1, XP_DEMUX = 2, XP_DEMUX_ACC = 3 };
 
 struct XpOut {
   uint32_t* dst;
@@ -450,11 +452,16 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
       } else if (out.mode == XP_ADD) {
         (out.dst + ea)[t] = addq((out.src + ea)[t], ha[e], P.q);
         (out.dst + eb)[t] = addq((out.src + eb)[t], hb[e], P.q);
-      } else {
+      } else if (out.mode == XP_DEMUX) {
         (out.dst + ea)[t] = subq((out.src + ea)[t], ha[e], P.q);
         (out.dst + eb)[t] = subq((out.src + eb)[t], hb[e], P.q);
         (out.dst2 + ea)[t] = ha[e];
         (out.dst2 + eb)[t] = hb[e];
+      } else {
+        (out.dst + ea)[t] = addq((out.dst + ea)[t], subq((out.src + ea)[t], ha[e], P.q), P.q);
+        (out.dst + eb)[t] = addq((out.dst + eb)[t], subq((out.src + eb)[t], hb[e], P.q), P.q);
+        (out.dst2 + ea)[t] = addq((out.dst2 + ea)[t], ha[e], P.q);
+        (out.dst2 + eb)[t] = addq((out.dst2 + eb)[t], hb[e], P.q);
       }
     }
   }

@@ -179,7 +179,9 @@ static hw_status launch_chunk(hw_engine* E, Slot& S, Req& R, const Job& J) {
   A.seed = R.r.enc_seed;
   A.ct0 = o * s;
   A.log_base = c->prm.log_base;
-  HIP_TRY(hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, m * s, S.st));
+  HIP_TRY(tuned(c, "encrypt_rgsw", (double)m * s * 10 * c->prm.nq, S.st, [&](int v) {
+    return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, m * s, enc_rows_per_wg(v), S.st);
+  }));
   if (R.r.kind == 0) {
     uint32_t* yr = reinterpret_cast<uint32_t*>(carve(p, m * L * rgsw_words(c) * 4));
     if (L) {
@@ -187,7 +189,9 @@ static hw_status launch_chunk(hw_engine* E, Slot& S, Req& R, const Job& J) {
       A.out = yr;
       A.seed = R.r.enc_seed + 1;
       A.ct0 = o * L;
-      HIP_TRY(hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, m * L, S.st));
+      HIP_TRY(tuned(c, "encrypt_rgsw", (double)m * L * 10 * c->prm.nq, S.st, [&](int v) {
+        return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, m * L, enc_rows_per_wg(v), S.st);
+      }));
     }
     const size_t wsb = m * train_ws_per_sample(c, J.d);
     uint32_t* ws = reinterpret_cast<uint32_t*>(carve(p, wsb));

@@ -39,6 +39,8 @@ struct TrainArgs {
   uint64_t rgsw_words;
   uint64_t i0;              // first sample of the sub-batch
   uint32_t s, a, L, k0, k1;
+  uint32_t nram, nsub;      // grid: nram RAM items (k0, + 1 for the counter) x nsub samples
+  uint32_t map;             // 0: 2-D grid (RAM, sample); 1: 1-D, XCD-grouped
 };
 
 struct ReduceArgs {
@@ -58,22 +60,26 @@ struct InferArgs {
   uint64_t rgsw_words;
   uint64_t i0;
   uint32_t s, a, L, l, k0, k1, slots;
+  uint32_t nsub;            // samples of this launch
+  uint32_t map;             // 0: 3-D grid (RAM, label, sample); 1: 1-D, labels adjacent, XCD-grouped
 };
 
-// batched training: one entry per job (its samples of the current window)
+// batched training: one entry per job
 struct BJob {
-  const uint32_t* x;        // RGSW of the window's first sample: [nsmp][s]
+  const uint32_t* x;        // RGSW of the job's first sample: [nsmp][s]
   const uint32_t* y;        // [nsmp][L]
   const uint32_t* perm;     // [s]
   uint32_t* model;          // [k0][k1] RLWE
   uint32_t* cnt;            // class counter or nullptr
-  uint64_t block0;          // word offset of the job's first block in the workspace
-  uint64_t words0;          // prefix of model (+ counter) words over the jobs
+  uint64_t acc0;            // word offset of the accumulators of pieces 1.. ([piece-1][nram][k1] RLWE)
+  uint64_t words0;          // prefix over the jobs of the model (+ counter) words the reduction writes
   uint32_t s, a, L, k0, k1, nsmp;
+  uint32_t nram;            // k0, + 1 with a class counter
+  uint32_t per, pieces;     // samples per piece, pieces per RAM
 };
 
 struct BItem {
-  uint32_t job, smp, ram, xp;  // xp: external products of the item (queue order)
+  uint32_t job, ram, piece, xp;  // xp: external products of the item (queue order)
 };
 
 struct BatchArgs {
@@ -81,7 +87,9 @@ struct BatchArgs {
   const BItem* items;
   uint32_t nitems;
   uint32_t* counter;
-  uint32_t* ws;
+  uint32_t* ws;             // per persistent workgroup: scratch_words (k1max + 1 RLWE slots)
+  uint64_t scratch_words;
+  uint32_t* acc;            // accumulators of pieces >= 1
   uint64_t rgsw_words;
 };
 
@@ -96,7 +104,7 @@ struct SumArgs {
 hipError_t launch_keygen(uint32_t N, uint64_t seed, int32_t* sk, hipStream_t st);
 hipError_t launch_sk_hat(int logN, int nq, const Tabs& T, const int32_t* sk, uint32_t* sk_hat, hipStream_t st);
 hipError_t launch_enc_rgsw(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
-                           hipStream_t st);
+                           int rows_per_wg, hipStream_t st);
 hipError_t launch_enc_rlwe(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
                            hipStream_t st);
 hipError_t launch_dec_rlwe(int logN, int nq, const Tabs& T, const CrtTab& K, const uint32_t* sk_hat,
@@ -106,16 +114,18 @@ hipError_t launch_dec_lwe(int logN, int nq, const Tabs& T, const CrtTab& K, cons
 hipError_t launch_rgsw_export(int logN, int nq, const Tabs& T, const uint32_t* rgsw, uint64_t count,
                               uint32_t* out, hipStream_t st);
 hipError_t launch_ntt(int logN, int nq, const Tabs& T, uint32_t* polys, uint64_t count, int inverse,
-                      hipStream_t st);
+                      uint32_t per, hipStream_t st);
 hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, const uint32_t* in, uint64_t count,
                      uint32_t* out, hipStream_t st);
-hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, uint32_t nram, uint32_t n_sub,
-                        hipStream_t st);
+// occ: occupancy target of the external-product kernels, 3 or 4 (4 only for log2 N = 12)
+hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st);
 hipError_t launch_reduce_model(const Tabs& T, const ReduceArgs& A, hipStream_t st);
-hipError_t launch_train_batch(int logN, int nq, const Tabs& T, const BatchArgs& A, hipStream_t st);
+hipError_t batch_grid(int logN, int nq, int occ, uint32_t* grid);  // persistent workgroups that fit the device
+hipError_t launch_train_batch(int logN, int nq, const Tabs& T, const BatchArgs& A, uint32_t grid, int occ,
+                              hipStream_t st);
 hipError_t launch_reduce_batch(const Tabs& T, const BJob* jobs, uint32_t njobs, uint64_t total, uint32_t logN,
-                               uint32_t N, uint32_t nq, const uint32_t* ws, hipStream_t st);
-hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, uint32_t n_sub, hipStream_t st);
+                               uint32_t N, uint32_t nq, const uint32_t* acc, hipStream_t st);
+hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int occ, hipStream_t st);
 hipError_t launch_class_sums(const Tabs& T, const SumArgs& A, hipStream_t st);
 
 }  // namespace hw

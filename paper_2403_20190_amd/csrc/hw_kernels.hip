@@ -11,11 +11,11 @@ namespace hw {
 
 typedef unsigned __int128 u128;
 
-// Occupancy target of the external-product kernels (waves per SIMD): lets the
-// compiler rematerialise loop-invariant addresses instead of keeping them live.
-#ifndef WAVES_XP
-#define WAVES_XP 3
-#endif
+// Occupancy target of the external-product kernels (waves per SIMD, template
+// parameter OCC of the training and inference kernels): 3 keeps every value
+// in registers (about 150 VGPRs); 4 (N = 4096 only) lets two workgroups of
+// 512 threads share a CU at the price of a few spilled registers.
+constexpr int WAVES_XP = 3;
 
 // ---------------------------------------------------------------------------
 // counter-based generator: Philox4x32-10 (Salmon et al., SC'11)
@@ -143,62 +143,70 @@ __device__ __forceinline__ void gen_gauss(uint64_t seed, uint64_t base_blk, cons
 // forward transform's output (thread t holds positions 8t..8t+7, i.e. the
 // draw pairs 4t..4t+3): a_hat needs no transform.  b_hat = a_hat * s_hat +
 // NTT(e); the gadget constant m*base^j is added to every evaluation point
-// (the transform of a constant polynomial is constant).
-template <int LOGN, int NQ>
+// (the transform of a constant polynomial is constant).  A workgroup builds
+// R consecutive rows of one ciphertext, so each prime's twiddle table is
+// copied to LDS once per R rows.
+template <int LOGN, int NQ, int R>
 __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   __shared__ __attribute__((aligned(16))) uint32_t stage[1 << LOGN];
   __shared__ uint64_t tab[42];
   constexpr int N = 1 << LOGN, D = 5 * NQ, ROWS = 2 * D;
-  const uint32_t t = threadIdx.x, r = blockIdx.x;
+  static_assert(ROWS % R == 0, "rows per workgroup must divide the rows of an RGSW");
+  const uint32_t t = threadIdx.x, r0 = blockIdx.x * R;
   const uint64_t c = blockIdx.y + (uint64_t)blockIdx.z * gridDim.y;
   if (t < 42) tab[t] = cdt.T[t];
   const uint64_t ct = A.ct0 + c;
-  const uint64_t rid = ct * ROWS + r;
   const uint32_t m = A.bits[c];
-  int32_t ev[8];
-  gen_gauss<LOGN>(A.seed, rid * (N / 2), tab, stage, t, ev);
-  const bool brow = r < D;
-  const uint32_t gi = (r % D) / 5, gj = (r % D) % 5;
-  uint32_t* row = A.out + (c * ROWS + r) * (size_t)(2 * NQ * N);
+  int32_t ev[R][8];
+#pragma unroll
+  for (int k = 0; k < R; ++k) gen_gauss<LOGN>(A.seed, (ct * ROWS + r0 + k) * (N / 2), tab, stage, t, ev[k]);
   uint32_t xc = 0;
 #pragma unroll 1
   for (int i = 0; i < NQ; ++i) {
     const PrimeTab P = T.pt[i];
     __syncthreads();
     load_tw_lds<LOGN>(twl, T.fwd[i], t);
-    uint32_t xa[8], xe[8];
-    const uint64_t blk0 = (rid * NQ + i) * (N / 2) + 4 * t;
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      uint64_t d0, d1;
-      draw_pair(A.seed, DOM_ENC_A, blk0 + f, d0, d1);
-      xa[2 * f] = red64(d0, P);
-      xa[2 * f + 1] = red64(d1, P);
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) xe[e] = ev[e] < 0 ? (uint32_t)(ev[e] + (int32_t)P.q) : (uint32_t)ev[e];
-    ntt_fwd<LOGN>(xe, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
-    const uint32_t g = (m && gi == (uint32_t)i) ? (1u << (A.log_base * gj)) : 0u;
     const uint4* sp = reinterpret_cast<const uint4*>(A.sk_hat + (size_t)i * N + (t << 3));
     const uint4 s0 = sp[0], s1 = sp[1];
     const uint32_t sh[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
-    uint32_t oa[8], ob[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const uint32_t a = xa[e];
-      const uint32_t ee = red4q(xe[e], P.q, P.two_q);
-      uint32_t b = addq(mulq(a, sh[e], P), ee, P.q);
-      oa[e] = brow ? a : addq(a, g, P.q);
-      ob[e] = brow ? addq(b, g, P.q) : b;
+    for (int k = 0; k < R; ++k) {
+      const uint32_t r = r0 + k;
+      const uint64_t rid = ct * ROWS + r;
+      uint32_t xa[8], xe[8];
+      const uint64_t blk0 = (rid * NQ + i) * (N / 2) + 4 * t;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        uint64_t d0, d1;
+        draw_pair(A.seed, DOM_ENC_A, blk0 + f, d0, d1);
+        xa[2 * f] = red64(d0, P);
+        xa[2 * f + 1] = red64(d1, P);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xe[e] = ev[k][e] < 0 ? (uint32_t)(ev[k][e] + (int32_t)P.q) : (uint32_t)ev[k][e];
+      ntt_fwd<LOGN>(xe, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
+      const bool brow = r < D;
+      const uint32_t gi = (r % D) / 5, gj = (r % D) % 5;
+      const uint32_t g = (m && gi == (uint32_t)i) ? (1u << (A.log_base * gj)) : 0u;
+      uint32_t oa[8], ob[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t av = xa[e];
+        const uint32_t ee = red4q(xe[e], P.q, P.two_q);
+        const uint32_t bv = addq(mulq(av, sh[e], P), ee, P.q);
+        oa[e] = brow ? av : addq(av, g, P.q);
+        ob[e] = brow ? addq(bv, g, P.q) : bv;
+      }
+      uint32_t* row = A.out + (c * ROWS + r) * (size_t)(2 * NQ * N);
+      uint4* pa = reinterpret_cast<uint4*>(row + (size_t)i * N + (t << 3));
+      uint4* pb = reinterpret_cast<uint4*>(row + (size_t)(NQ + i) * N + (t << 3));
+      pa[0] = make_uint4(oa[0], oa[1], oa[2], oa[3]);
+      pa[1] = make_uint4(oa[4], oa[5], oa[6], oa[7]);
+      pb[0] = make_uint4(ob[0], ob[1], ob[2], ob[3]);
+      pb[1] = make_uint4(ob[4], ob[5], ob[6], ob[7]);
     }
-    uint4* pa = reinterpret_cast<uint4*>(row + (size_t)i * N + (t << 3));
-    uint4* pb = reinterpret_cast<uint4*>(row + (size_t)(NQ + i) * N + (t << 3));
-    pa[0] = make_uint4(oa[0], oa[1], oa[2], oa[3]);
-    pa[1] = make_uint4(oa[4], oa[5], oa[6], oa[7]);
-    pb[0] = make_uint4(ob[0], ob[1], ob[2], ob[3]);
-    pb[1] = make_uint4(ob[4], ob[5], ob[6], ob[7]);
   }
 }
 
@@ -337,36 +345,43 @@ __global__ __launch_bounds__(256) void k_dec_lwe(Tabs T, CrtTab K, uint32_t N, c
 // transforms
 // ---------------------------------------------------------------------------
 
+// `per` consecutive polynomials of one prime per workgroup (the prime's
+// forward table is copied to LDS once for all of them)
 template <int LOGN, int NQ>
-__global__ __launch_bounds__(Geo<LOGN>::T) void k_ntt(Tabs T, uint32_t* __restrict__ polys, int inverse) {
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_ntt(Tabs T, uint32_t* __restrict__ polys, uint64_t count,
+                                                     uint32_t per, int inverse) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   constexpr int N = 1 << LOGN, TT = N / 8;
   const uint32_t t = threadIdx.x, i = blockIdx.x;
-  const uint64_t c = blockIdx.y + (uint64_t)blockIdx.z * gridDim.y;
+  const uint64_t grp = blockIdx.y + (uint64_t)blockIdx.z * gridDim.y;
   const PrimeTab P = T.pt[i];
-  uint32_t* p = polys + (c * NQ + i) * (size_t)N;
-  uint32_t x[8];
   uint32_t xc = 0;
-  if (!inverse) {
+  if (!inverse) load_tw_lds<LOGN>(twl, T.fwd[i], t);  // read after the first exchange's barrier
+#pragma unroll 1
+  for (uint32_t k = 0; k < per; ++k) {
+    const uint64_t c = grp * per + k;
+    if (c >= count) break;
+    uint32_t* p = polys + (c * NQ + i) * (size_t)N;
+    uint32_t x[8];
+    if (!inverse) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) x[e] = p[t + TT * e];
-    __syncthreads();
-    load_tw_lds<LOGN>(twl, T.fwd[i], t);
-    ntt_fwd<LOGN>(x, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
-    uint4* o = reinterpret_cast<uint4*>(p + (t << 3));
-    o[0] = make_uint4(red4q(x[0], P.q, P.two_q), red4q(x[1], P.q, P.two_q), red4q(x[2], P.q, P.two_q),
-                      red4q(x[3], P.q, P.two_q));
-    o[1] = make_uint4(red4q(x[4], P.q, P.two_q), red4q(x[5], P.q, P.two_q), red4q(x[6], P.q, P.two_q),
-                      red4q(x[7], P.q, P.two_q));
-  } else {
-    const uint4* s = reinterpret_cast<const uint4*>(p + (t << 3));
-    const uint4 u = s[0], v = s[1];
-    x[0] = u.x; x[1] = u.y; x[2] = u.z; x[3] = u.w; x[4] = v.x; x[5] = v.y; x[6] = v.z; x[7] = v.w;
-    __syncthreads();  // every thread has read its inputs before anyone overwrites them
-    ntt_inv<LOGN>(x, T.inv[i], P, lds, xc, t);
+      for (int e = 0; e < 8; ++e) x[e] = p[t + TT * e];
+      ntt_fwd<LOGN>(x, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
+      uint4* o = reinterpret_cast<uint4*>(p + (t << 3));
+      o[0] = make_uint4(red4q(x[0], P.q, P.two_q), red4q(x[1], P.q, P.two_q), red4q(x[2], P.q, P.two_q),
+                        red4q(x[3], P.q, P.two_q));
+      o[1] = make_uint4(red4q(x[4], P.q, P.two_q), red4q(x[5], P.q, P.two_q), red4q(x[6], P.q, P.two_q),
+                        red4q(x[7], P.q, P.two_q));
+    } else {
+      const uint4* s = reinterpret_cast<const uint4*>(p + (t << 3));
+      const uint4 u = s[0], v = s[1];
+      x[0] = u.x; x[1] = u.y; x[2] = u.z; x[3] = u.w; x[4] = v.x; x[5] = v.y; x[6] = v.z; x[7] = v.w;
+      __syncthreads();  // every thread has read its inputs before anyone overwrites them
+      ntt_inv<LOGN>(x, T.inv[i], P, lds, xc, t);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) p[t + TT * e] = x[e];
+      for (int e = 0; e < 8; ++e) p[t + TT * e] = x[e];
+    }
   }
 }
 
@@ -374,7 +389,6 @@ template <int LOGN, int NQ>
 __global__ __launch_bounds__(Geo<LOGN>::T) void k_rgsw_export(Tabs T, const uint32_t* __restrict__ rgsw,
                                                                uint32_t* __restrict__ out) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
-  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   constexpr int N = 1 << LOGN, TT = N / 8;
   const uint32_t t = threadIdx.x;
   const uint64_t poly = blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;  // (ct, row, a|b)
@@ -459,10 +473,13 @@ __device__ __forceinline__ void copy_rlwe(uint32_t* __restrict__ dst, const uint
 
 // IVP of one (sample, RAM) into its block: acc = (0, Delta), the rotation
 // chain over bits z..nb-1, then the CDEMUX tree over bits 0..z-1.
-// bit(u) returns the RGSW of bit u of the IVP index.
+// bit(u) returns the RGSW of bit u of the IVP index.  With `dest`, the 2^z
+// outputs go to dest[0 .. 2^z) instead of the slots: stored when `store`,
+// else added (the last tree level writes them there directly).
 template <int LOGN, int NQ, class BitFn>
 __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ slot0, uint32_t* __restrict__ xin,
-                                          uint32_t nb, BitFn&& bit, uint32_t* lds, uint2* twl, uint32_t t) {
+                                          uint32_t nb, BitFn&& bit, uint32_t* lds, uint2* twl, uint32_t t,
+                                          uint32_t* __restrict__ dest = nullptr, bool store = false) {
   constexpr int N = 1 << LOGN, TT = N / 8;
   constexpr size_t RW = (size_t)2 * NQ * N;
   const uint32_t nr = nb < (uint32_t)LOGN ? nb : (uint32_t)LOGN;
@@ -481,12 +498,27 @@ __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ 
   for (uint32_t lev = 0; lev < z; ++lev) {
     const uint32_t* C = bit(lev);
     const uint32_t n = 1u << lev;
+    const bool last = dest && lev + 1 == z;
 #pragma unroll 1
     for (uint32_t j = 0; j < n; ++j) {
       uint32_t* sj = slot0 + j * RW;
-      uint32_t* sn = slot0 + (j + n) * RW;
       copy_rlwe<LOGN, NQ>(xin, sj, t);
-      ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t, XpOut{sj, xin, sn, XP_DEMUX});
+      if (last)
+        ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t,
+                           XpOut{dest + j * RW, xin, dest + (j + n) * RW, store ? XP_DEMUX : XP_DEMUX_ACC});
+      else
+        ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t, XpOut{sj, xin, slot0 + (j + n) * RW, XP_DEMUX});
+    }
+  }
+  if (dest && z == 0) {  // no tree: the chain's accumulator is the output
+#pragma unroll 1
+    for (int w = 0; w < 2 * NQ; ++w) {
+      const uint32_t q = T.pt[w % NQ].q;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const size_t k = (size_t)w * N + TT * e + t;
+        dest[k] = store ? slot0[k] : addq(dest[k], slot0[k], q);
+      }
     }
   }
 }
@@ -497,12 +529,23 @@ __device__ __forceinline__ uint32_t ram_bits(uint32_t ram, uint32_t k0, uint32_t
   return L + (rem < a ? rem : a);
 }
 
-template <int LOGN, int NQ>
-__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_train(Tabs T, TrainArgs A) {
+template <int LOGN, int NQ, int OCC>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_train(Tabs T, TrainArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   constexpr size_t RW = (size_t)2 * NQ * (1 << LOGN);
-  const uint32_t t = threadIdx.x, ram = blockIdx.x, smp = blockIdx.y;
+  const uint32_t t = threadIdx.x;
+  uint32_t ram, smp;
+  if (A.map == 0) {  // 2-D grid, RAMs of one sample on consecutive workgroups
+    ram = blockIdx.x;
+    smp = blockIdx.y;
+  } else {  // 1-D grid; XCD x (= workgroup id mod 8) takes the x-th eighth of the items
+    const uint32_t G = A.nram * A.nsub, per = (G + 7) >> 3;
+    const uint32_t lg = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    if (lg >= G) return;
+    ram = lg % A.nram;
+    smp = lg / A.nram;
+  }
   const uint64_t gi = A.i0 + smp;
   uint32_t* slot0 = A.out + ((size_t)smp * (A.k0 + 1) + ram) * (A.k1 + 1) * RW;
   ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)A.k1 * RW, ram_bits(ram, A.k0, A.s, A.a, A.L),
@@ -516,37 +559,51 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WA
 // ---------------------------------------------------------------------------
 // batched training: one persistent launch over many jobs of one parameter set
 // ---------------------------------------------------------------------------
-// Items (job, sample, RAM) are taken from a queue (a device counter), longest
-// first; each writes the block of its (job, sample) like k_train, and
-// k_reduce_batch then adds every job's blocks into its model.  A workgroup
-// leaves when the queue is exhausted.
+// An item is (job, RAM, piece): the piece's samples [piece*per, ...) run the
+// IVP of that RAM one after another in the workgroup's private scratch (k1
+// slots + the input slot); the last CDEMUX level of each sample adds its 2^z
+// outputs into the piece's destination: the model row itself for piece 0 (no
+// other item writes it), else the piece's accumulator in the workspace
+// (stored by the piece's first sample).  Items come from a queue (a device counter),
+// longest first; a workgroup leaves when the queue is exhausted.
+// k_reduce_batch then adds the accumulators of pieces >= 1 into the models.
 
-template <int LOGN, int NQ>
-__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_train_batch(
+template <int LOGN, int NQ, int OCC>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_train_batch(
     Tabs T, BatchArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   __shared__ uint32_t next;
   constexpr size_t RW = (size_t)2 * NQ * (1 << LOGN);
   const uint32_t t = threadIdx.x;
+  uint32_t* slot0 = A.ws + (size_t)blockIdx.x * A.scratch_words;
 #pragma unroll 1
   for (;;) {
     if (t == 0) next = atomicAdd(A.counter, 1u);
     __syncthreads();
-    const uint32_t it = next;
+    // uniform over the workgroup: item and job descriptors then come through
+    // scalar loads and their address arithmetic stays on the scalar unit
+    const uint32_t it = __builtin_amdgcn_readfirstlane(next);
     __syncthreads();
     if (it >= A.nitems) break;
     const BItem I = A.items[it];
     const BJob J = A.jobs[I.job];
-    uint32_t* slot0 = A.ws + J.block0 + ((size_t)I.smp * (J.k0 + 1) + I.ram) * (J.k1 + 1) * RW;
-    const uint64_t gi = I.smp;
-    ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)J.k1 * RW, ram_bits(I.ram, J.k0, J.s, J.a, J.L),
-                        [&](uint32_t u) -> const uint32_t* {
-                          if (u < J.L) return J.y + (gi * J.L + u) * A.rgsw_words;
-                          return J.x + (gi * J.s + J.perm[I.ram * J.a + (u - J.L)]) * A.rgsw_words;
-                        },
-                        lds, twl, t);
-    __syncthreads();
+    const uint32_t nb = ram_bits(I.ram, J.k0, J.s, J.a, J.L);
+    uint32_t* dest = I.piece == 0 ? (I.ram < J.k0 ? J.model + (size_t)I.ram * J.k1 * RW : J.cnt)
+                                  : A.acc + J.acc0 + ((size_t)(I.piece - 1) * J.nram + I.ram) * J.k1 * RW;
+    const uint32_t s0 = I.piece * J.per;
+    const uint32_t s1 = s0 + J.per < J.nsmp ? s0 + J.per : J.nsmp;
+#pragma unroll 1
+    for (uint32_t smp = s0; smp < s1; ++smp) {
+      const uint64_t gi = smp;
+      ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)J.k1 * RW, nb,
+                          [&](uint32_t u) -> const uint32_t* {
+                            if (u < J.L) return J.y + (gi * J.L + u) * A.rgsw_words;
+                            return J.x + (gi * J.s + J.perm[I.ram * J.a + (u - J.L)]) * A.rgsw_words;
+                          },
+                          lds, twl, t, dest, I.piece != 0 && smp == s0);
+      __syncthreads();
+    }
   }
 }
 
@@ -555,11 +612,12 @@ __global__ void k_zero_u32(uint32_t* p, uint32_t n) {
   if (i < n) p[i] = 0u;
 }
 
-// every job's model[j][d] (+ counter) += sum over the window's samples of its
-// blocks; one thread per model word, the job found by binary search
+// model[j][d] (+ counter) += the accumulators of pieces 1..pieces-1 of every
+// job with more than one piece; one thread per model word, the job found by
+// binary search over the prefix words0 (jobs with one piece span no words)
 __global__ __launch_bounds__(256) void k_reduce_batch(Tabs T, const BJob* __restrict__ jobs, uint32_t njobs,
                                                       uint64_t total, uint32_t logN, uint32_t N, uint32_t nq,
-                                                      const uint32_t* __restrict__ ws) {
+                                                      const uint32_t* __restrict__ acc) {
   const size_t RW = (size_t)2 * nq * N;
   for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (size_t)gridDim.x * blockDim.x) {
     uint32_t lo = 0, hi = njobs;  // last job with words0 <= w
@@ -570,31 +628,26 @@ __global__ __launch_bounds__(256) void k_reduce_batch(Tabs T, const BJob* __rest
     const BJob J = jobs[lo];
     const size_t per_ram = (size_t)J.k1 * RW;
     const size_t model_words = (size_t)J.k0 * per_ram;
-    size_t x = w - J.words0;
-    uint32_t ram, d;
-    size_t rem;
+    const size_t x = w - J.words0;
+    uint32_t ram;
+    size_t off;  // word within the RAM's k1 slots
     if (x < model_words) {
       ram = (uint32_t)(x / per_ram);
-      rem = x - (size_t)ram * per_ram;
-      d = (uint32_t)(rem / RW);
-      rem -= (size_t)d * RW;
+      off = x - (size_t)ram * per_ram;
       const uint32_t nb = ram_bits(ram, J.k0, J.s, J.a, J.L);
       const uint32_t nr = nb < logN ? nb : logN;
-      if (d >= (1u << (nb - nr))) continue;
+      if (off / RW >= (1u << (nb - nr))) continue;
     } else {
       ram = J.k0;
-      d = 0;
-      rem = x - model_words;
+      off = x - model_words;
     }
-    const uint32_t i = (uint32_t)((rem / N) % nq);
-    const PrimeTab P = T.pt[i];
-    const size_t blk = (size_t)(J.k1 + 1) * RW;
-    const size_t stride = (size_t)(J.k0 + 1) * blk;
-    const uint32_t* src = ws + J.block0 + (size_t)ram * blk + (size_t)d * RW + rem;
-    uint64_t acc = 0;
-    for (uint32_t s = 0; s < J.nsmp; ++s) acc += src[(size_t)s * stride];
-    uint32_t* dst = x < model_words ? J.model + x : J.cnt + rem;
-    *dst = addq(*dst, red64(acc, P), P.q);
+    const PrimeTab P = T.pt[(off / N) % nq];
+    const uint32_t* src = acc + J.acc0 + (size_t)ram * per_ram + off;
+    const size_t stride = (size_t)J.nram * per_ram;  // one piece
+    uint64_t sum = 0;
+    for (uint32_t p = 1; p < J.pieces; ++p) sum += src[(size_t)(p - 1) * stride];
+    uint32_t* dst = x < model_words ? J.model + x : J.cnt + off;
+    *dst = addq(*dst, red64(sum, P), P.q);
   }
 }
 
@@ -642,13 +695,26 @@ __global__ __launch_bounds__(256) void k_reduce_model(Tabs T, ReduceArgs A) {
 // carry label bits select exactly; only the 2^{z-L} - 1 CMUXes whose outputs
 // reach the result are evaluated (the discarded ones do not change it).
 
-template <int LOGN, int NQ>
-__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_infer(Tabs T, InferArgs A) {
+template <int LOGN, int NQ, int OCC>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_infer(Tabs T, InferArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   constexpr int N = 1 << LOGN, TT = N / 8;
   constexpr size_t RW = (size_t)2 * NQ * N;
-  const uint32_t t = threadIdx.x, ram = blockIdx.x, lab = blockIdx.y, smp = blockIdx.z;
+  const uint32_t t = threadIdx.x;
+  uint32_t ram, lab, smp;
+  if (A.map == 0) {  // 3-D grid (RAM, label, sample)
+    ram = blockIdx.x;
+    lab = blockIdx.y;
+    smp = blockIdx.z;
+  } else {  // 1-D grid, the labels of one (sample, RAM) adjacent, XCD x takes the x-th eighth
+    const uint32_t G = A.k0 * A.l * A.nsub, per = (G + 7) >> 3;
+    const uint32_t lg = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    if (lg >= G) return;
+    lab = lg % A.l;
+    ram = (lg / A.l) % A.k0;
+    smp = lg / A.l / A.k0;
+  }
   const uint64_t gi = A.i0 + smp;
   const uint32_t rem = A.s - ram * A.a;
   const uint32_t aj = rem < A.a ? rem : A.a;
@@ -784,6 +850,19 @@ static hipError_t for_rect(uint64_t count, F&& f) {
     else return hipErrorInvalidValue;                                                  \
   } while (0)
 
+// HW_DISPATCH with the occupancy target OC: 4 exists for log2 N = 12 only
+#define HW_DISPATCH_OCC(logN, nq, occ, ...)                                              \
+  do {                                                                                 \
+    if (logN == 12 && occ == 4) {                                                      \
+      if (nq == 1) { constexpr int LN = 12, NQ = 1, OC = 4; __VA_ARGS__; }             \
+      else if (nq == 2) { constexpr int LN = 12, NQ = 2, OC = 4; __VA_ARGS__; }        \
+      else if (nq == 3) { constexpr int LN = 12, NQ = 3, OC = 4; __VA_ARGS__; }        \
+      else return hipErrorInvalidValue;                                                \
+    } else {                                                                           \
+      HW_DISPATCH(logN, nq, constexpr int OC = WAVES_XP; __VA_ARGS__);                 \
+    }                                                                                  \
+  } while (0)
+
 hipError_t launch_keygen(uint32_t N, uint64_t seed, int32_t* sk, hipStream_t st) {
   hipLaunchKernelGGL(k_keygen, dim3((N + 255) / 256), dim3(256), 0, st, N, seed, sk);
   return hipGetLastError();
@@ -795,15 +874,30 @@ hipError_t launch_sk_hat(int logN, int nq, const Tabs& T, const int32_t* sk, uin
 }
 
 hipError_t launch_enc_rgsw(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
-                           hipStream_t st) {
+                           int rows_per_wg, hipStream_t st) {
   const size_t rg = (size_t)2 * 5 * nq * 2 * nq * ((size_t)1 << logN);
+  const uint32_t rows = 2 * 5 * nq;
   return for_rect(count, [&](uint64_t off, dim3 g) -> hipError_t {
     EncArgs B = A;
     B.bits = A.bits + off;
     B.out = A.out + off * rg;
     B.ct0 = A.ct0 + off;
-    HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ>), dim3(2 * 5 * NQ, g.x, g.y), dim3(Geo<LN>::T), 0,
-                                              st, T, cdt, B));
+    switch (rows_per_wg) {
+      case 1:
+        HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ, 1>), dim3(rows, g.x, g.y), dim3(Geo<LN>::T),
+                                                  0, st, T, cdt, B));
+        break;
+      case 2:
+        HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ, 2>), dim3(rows / 2, g.x, g.y),
+                                                  dim3(Geo<LN>::T), 0, st, T, cdt, B));
+        break;
+      case 5:
+        HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ, 5>), dim3(rows / 5, g.x, g.y),
+                                                  dim3(Geo<LN>::T), 0, st, T, cdt, B));
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   });
 }
@@ -861,11 +955,13 @@ hipError_t launch_rgsw_export(int logN, int nq, const Tabs& T, const uint32_t* r
 }
 
 hipError_t launch_ntt(int logN, int nq, const Tabs& T, uint32_t* polys, uint64_t count, int inverse,
-                      hipStream_t st) {
+                      uint32_t per, hipStream_t st) {
   const size_t N = 1u << logN;
-  return for_rect(count, [&](uint64_t off, dim3 g) -> hipError_t {
+  if (per < 1) return hipErrorInvalidValue;
+  const uint64_t groups = (count + per - 1) / per;
+  return for_rect(groups, [&](uint64_t off, dim3 g) -> hipError_t {
     HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_ntt<LN, NQ>), dim3(NQ, g.x, g.y), dim3(Geo<LN>::T), 0, st, T,
-                                              polys + off * nq * N, inverse));
+                                              polys + off * per * nq * N, count - off * per, per, inverse));
     return hipGetLastError();
   });
 }
@@ -881,37 +977,49 @@ hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, cons
   });
 }
 
-hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, uint32_t nram, uint32_t n_sub,
-                        hipStream_t st) {
-  HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_train<LN, NQ>), dim3(nram, n_sub), dim3(Geo<LN>::T), 0, st, T, A));
+hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st) {
+  const uint64_t G = (uint64_t)A.nram * A.nsub;
+  if (G == 0) return hipSuccess;
+  if (G > (1u << 22)) return hipErrorInvalidValue;
+  const dim3 grid = A.map == 0 ? dim3(A.nram, A.nsub) : dim3((uint32_t)((G + 7) / 8 * 8));
+  HW_DISPATCH_OCC(logN, nq, occ,
+                  hipLaunchKernelGGL((k_train<LN, NQ, OC>), grid, dim3(Geo<LN>::T), 0, st, T, A));
   return hipGetLastError();
 }
 
-template <int LN, int NQ>
-static hipError_t launch_batch_t(const Tabs& T, const BatchArgs& A, uint32_t nitems_cap, hipStream_t st) {
+template <int LN, int NQ, int OC>
+static hipError_t batch_grid_t(uint32_t* grid) {
   int dev = 0, cus = 0, per_cu = 0;
-  hipGetDevice(&dev);
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_train_batch<LN, NQ>, Geo<LN>::T, 0);
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_train_batch<LN, NQ, OC>, Geo<LN>::T,
+                                                     0);
   if (e != hipSuccess) return e;
-  uint32_t grid = (uint32_t)(cus * (per_cu > 0 ? per_cu : 1));
-  if (grid > nitems_cap) grid = nitems_cap;
-  if (grid == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, A.counter, 1u);
-  hipLaunchKernelGGL((k_train_batch<LN, NQ>), dim3(grid), dim3(Geo<LN>::T), 0, st, T, A);
-  return hipGetLastError();
-}
-
-hipError_t launch_train_batch(int logN, int nq, const Tabs& T, const BatchArgs& A, hipStream_t st) {
-  HW_DISPATCH(logN, nq, return launch_batch_t<LN, NQ>(T, A, A.nitems, st));
+  *grid = (uint32_t)(cus * (per_cu > 0 ? per_cu : 1));
   return hipSuccess;
 }
 
+hipError_t batch_grid(int logN, int nq, int occ, uint32_t* grid) {
+  HW_DISPATCH_OCC(logN, nq, occ, return batch_grid_t<LN, NQ, OC>(grid));
+  return hipSuccess;
+}
+
+hipError_t launch_train_batch(int logN, int nq, const Tabs& T, const BatchArgs& A, uint32_t grid, int occ,
+                              hipStream_t st) {
+  if (grid > A.nitems) grid = A.nitems;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, A.counter, 1u);
+  HW_DISPATCH_OCC(logN, nq, occ,
+                  hipLaunchKernelGGL((k_train_batch<LN, NQ, OC>), dim3(grid), dim3(Geo<LN>::T), 0, st, T, A));
+  return hipGetLastError();
+}
+
 hipError_t launch_reduce_batch(const Tabs& T, const BJob* jobs, uint32_t njobs, uint64_t total, uint32_t logN,
-                               uint32_t N, uint32_t nq, const uint32_t* ws, hipStream_t st) {
+                               uint32_t N, uint32_t nq, const uint32_t* acc, hipStream_t st) {
   const uint32_t blocks = (uint32_t)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
   if (!blocks) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_batch, dim3(blocks), dim3(256), 0, st, T, jobs, njobs, total, logN, N, nq, ws);
+  hipLaunchKernelGGL(k_reduce_batch, dim3(blocks), dim3(256), 0, st, T, jobs, njobs, total, logN, N, nq, acc);
   return hipGetLastError();
 }
 
@@ -923,8 +1031,13 @@ hipError_t launch_reduce_model(const Tabs& T, const ReduceArgs& A, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, uint32_t n_sub, hipStream_t st) {
-  HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_infer<LN, NQ>), dim3(A.k0, A.l, n_sub), dim3(Geo<LN>::T), 0, st, T, A));
+hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int occ, hipStream_t st) {
+  const uint64_t G = (uint64_t)A.k0 * A.l * A.nsub;
+  if (G == 0) return hipSuccess;
+  if (G > (1u << 22)) return hipErrorInvalidValue;
+  const dim3 grid = A.map == 0 ? dim3(A.k0, A.l, A.nsub) : dim3((uint32_t)((G + 7) / 8 * 8));
+  HW_DISPATCH_OCC(logN, nq, occ,
+                  hipLaunchKernelGGL((k_infer<LN, NQ, OC>), grid, dim3(Geo<LN>::T), 0, st, T, A));
   return hipGetLastError();
 }
 

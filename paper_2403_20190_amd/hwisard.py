@@ -87,7 +87,7 @@ _SIG = {
     "hw_batch_train": [_vp, C.POINTER(TrainJob), _u32, _vp],
     "hw_batch_plan_create": [_vp, C.POINTER(TrainJob), _u32, C.POINTER(C.c_void_p)],
     "hw_batch_plan_launch": [_vp, _vp],
-    "hw_batch_plan_info": [_vp, C.POINTER(_u32), C.POINTER(_u64), C.POINTER(C.c_double), C.POINTER(_u64)],
+    "hw_batch_plan_info": [_vp, C.POINTER(_u64), C.POINTER(_u32), C.POINTER(C.c_double), C.POINTER(_u64)],
     "hw_engine_create": [C.POINTER(Params), _i32, _vp, C.POINTER(EngineConfig), C.POINTER(C.c_void_p)],
     "hw_engine_add_job": [_vp, C.POINTER(Shape), _vp, _vp, C.POINTER(_u32)],
     "hw_engine_submit": [_vp, C.POINTER(Request), C.POINTER(_u64)],
@@ -95,6 +95,8 @@ _SIG = {
     "hw_engine_wait": [_vp, _u64, C.POINTER(_i32), C.POINTER(C.c_double)],
     "hw_engine_cancel": [_vp, _u64],
     "hw_engine_stats": [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u32)],
+    "hw_tune_set": [_vp, C.c_char_p, _i32],
+    "hw_tune_get": [_vp, C.c_char_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)],
     "hw_profile_enable": [_vp, _i32],
     "hw_profile_read": [_vp, C.c_char_p, C.POINTER(C.c_double), C.POINTER(_u64), C.POINTER(C.c_double)],
     "hw_profile_reset": [_vp],
@@ -111,11 +113,21 @@ _lib.hw_batch_plan_destroy.restype = None
 _lib.hw_batch_plan_destroy.argtypes = [_vp]
 _lib.hw_last_error.restype = C.c_char_p
 _lib.hw_last_error.argtypes = []
+_lib.hw_tune_variant_name.restype = C.c_char_p
+_lib.hw_tune_variant_name.argtypes = [C.c_char_p, _i32]
+
+TUNED_KERNELS = ("train", "infer", "train_batch", "ntt", "ntt_inverse", "encrypt_rgsw")
+
+
+def tune_variant_name(kernel: str, variant: int):
+    r = _lib.hw_tune_variant_name(kernel.encode(), variant)
+    return r.decode() if r else None
 
 
 def exported_symbols():
     """Names the library exports (for the ABI test)."""
-    return sorted(_SIG) + ["hw_ctx_destroy", "hw_engine_destroy", "hw_batch_plan_destroy", "hw_last_error"]
+    return sorted(_SIG) + ["hw_ctx_destroy", "hw_engine_destroy", "hw_batch_plan_destroy", "hw_last_error",
+                           "hw_tune_variant_name"]
 
 
 def _check(st: int):
@@ -227,12 +239,30 @@ class Context:
 
     def batch_train(self, jobs):
         """jobs: iterable of (shape, x_rgsw, y_rgsw, n, model, class_count) -- one
-        persistent launch per workspace window for all of them"""
+        persistent launch over a queue of (job, RAM, piece of samples) items"""
         jobs = list(jobs)
         arr = (TrainJob * max(1, len(jobs)))()
         for i, (sh, x, y, n, model, cnt) in enumerate(jobs):
             arr[i] = TrainJob(sh, _ptr(x), _ptr(y), n, _ptr(model), _ptr(cnt))
         _check(_lib.hw_batch_train(self._h, arr, len(jobs), _stream()))
+
+    def tune_set(self, kernel: str, variant: int):
+        """force a schedule variant of a tuned kernel (-1: tune again)"""
+        _check(_lib.hw_tune_set(self._h, kernel.encode(), variant))
+
+    def tune_get(self, kernel: str):
+        """(variant in use or -1 while tuning, timings taken, variants)"""
+        v, t, n = _i32(), _i32(), _i32()
+        _check(_lib.hw_tune_get(self._h, kernel.encode(), C.byref(v), C.byref(t), C.byref(n)))
+        return v.value, t.value, n.value
+
+    def schedule(self):
+        """{kernel: description of the variant in use, or None while tuning}"""
+        out = {}
+        for k in TUNED_KERNELS:
+            v, _, _ = self.tune_get(k)
+            out[k] = tune_variant_name(k, v) if v >= 0 else None
+        return out
 
     def batch_plan(self, jobs):
         """A BatchPlan for the jobs of batch_train: launches captured once into
@@ -245,7 +275,7 @@ class Context:
 
 
 class BatchPlan:
-    """hw_batch_plan_*: the windows of a batch computed once and captured into
+    """hw_batch_plan_*: the queue of a batch computed once and captured into
     a HIP graph; launch() replays it on the current stream.  The job buffers
     are kept referenced here for the plan's lifetime."""
 
@@ -257,9 +287,10 @@ class BatchPlan:
         h = C.c_void_p()
         _check(_lib.hw_batch_plan_create(ctx._h, arr, len(jobs), C.byref(h)))
         self._h, self._ctx, self._jobs = h, ctx, jobs
-        w, it, xp, ws = _u32(), _u64(), C.c_double(), _u64()
-        _check(_lib.hw_batch_plan_info(h, C.byref(w), C.byref(it), C.byref(xp), C.byref(ws)))
-        self.windows, self.items, self.external_products, self.workspace_bytes = w.value, it.value, xp.value, ws.value
+        it, mp, xp, ws = _u64(), _u32(), C.c_double(), _u64()
+        _check(_lib.hw_batch_plan_info(h, C.byref(it), C.byref(mp), C.byref(xp), C.byref(ws)))
+        self.items, self.max_pieces, self.external_products, self.workspace_bytes = (
+            it.value, mp.value, xp.value, ws.value)
 
     def launch(self):
         _check(_lib.hw_batch_plan_launch(self._h, _stream()))

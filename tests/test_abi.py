@@ -44,3 +44,16 @@ def test_host_only_calls():
         assert np.array_equal(HW.permutation(HW.shape(s, 2, 8, seed)), O.permutation(seed, s))
     with pytest.raises(HW.HwError):
         HW.permutation(HW.shape(0, 2, 8, 1))
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhwisard.so not built")
+def test_tune_variant_names():
+    """The tuned kernels and their variant tables (host only)."""
+    from paper_2403_20190_amd import hwisard as HW
+    counts = {"train": 4, "infer": 4, "train_batch": 2, "ntt": 4, "ntt_inverse": 4, "encrypt_rgsw": 3}
+    assert set(counts) == set(HW.TUNED_KERNELS)
+    for k, n in counts.items():
+        names = [HW.tune_variant_name(k, v) for v in range(n)]
+        assert all(names) and len(set(names)) == n
+        assert HW.tune_variant_name(k, n) is None and HW.tune_variant_name(k, -1) is None
+    assert HW.tune_variant_name("xp", 0) is None

@@ -68,13 +68,16 @@ def test_batch_equals_single_job_and_oracle():
     assert np.array_equal(host_u32(bufs[1][2]), Ho)
 
 
-def test_batch_windows_do_not_change_bits():
+def test_batch_pieces_do_not_change_bits():
+    """A workspace budget of one byte forces one piece per RAM (every model
+    row accumulated in place, no reduction); the default budget cuts these
+    small jobs into one-sample pieces.  Same bits either way."""
     pairs = make_jobs(dict(N=2048, nq=2, p=1024), seed0=40)
     ctx = pairs[0][0].ctx
     for pair, _ in pairs:
         pair.ctx, pair.sk, pair.sk_o = ctx, pairs[0][0].sk, pairs[0][0].sk_o
     big = run_batch(ctx, pairs)
-    os.environ["HWISARD_WS_BYTES"] = "1"  # every window holds one sample's block
+    os.environ["HWISARD_WS_BYTES"] = "1"
     try:
         from paper_2403_20190_amd import hwisard as HW
         small = HW.Context(2048, 2, 1024)
@@ -120,11 +123,11 @@ def _same(jobs, ref):
 
 @pytest.mark.parametrize("ws_bytes", [None, "1"])
 def test_batch_plan_replays_match_eager(ws_bytes):
-    """A batch plan (windows computed once, launches captured into a HIP
-    graph) replayed three times, with eager work and synchronisations between
-    the replays, equals the eager batched call every time; a replay without
+    """A batch plan (queue computed once, launches captured into a HIP graph)
+    replayed three times, with eager work and synchronisations between the
+    replays, equals the eager batched call every time; a replay without
     clearing the models adds the batch again; replays read the inputs as they
-    are at replay time.  ws_bytes="1" forces one window per sample."""
+    are at replay time.  ws_bytes="1" forces one piece per RAM."""
     import torch
     from paper_2403_20190_amd import hwisard as HW
     if ws_bytes:
@@ -140,7 +143,8 @@ def test_batch_plan_replays_match_eager(ws_bytes):
     ref = [(None, None, None, None, b[2], b[3]) for b in bufs]
     jobs = _fresh_outputs(pairs, bufs)
     plan = ctx.batch_plan(jobs)
-    assert plan.windows > 1 if ws_bytes else plan.windows == 1
+    info = (plan.max_pieces, plan.items, plan.workspace_bytes)
+    assert (plan.max_pieces == 1) if ws_bytes else (plan.max_pieces > 1), info
     assert plan.items > 0 and plan.external_products > 0
     for rep in range(3):
         for j in jobs:

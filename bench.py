@@ -42,6 +42,29 @@ WORKLOADS = {
 }
 
 
+KERNEL_SOURCES = ["hw_device.h", "hw_kernels.hip", "hw_internal.h"]
+
+
+def measured_traffic():
+    """HBM bytes (read + write) per k_train launch measured with rocprofv3
+    FETCH_SIZE / WRITE_SIZE (profiles/k_train_mnist_pmc.md), or None when the
+    kernel sources changed since (their sha256 no longer matches)."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, "profiles", "k_train_mnist_pmc.md")).read()
+    except OSError:
+        return None
+    t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    h = re.search(r"kernel_sources_sha256:\s*([0-9a-f]{64})", text)
+    if not t or not h:
+        return None
+    sha = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        sha.update(open(os.path.join(ROOT, "paper_2403_20190_amd", "csrc", f), "rb").read())
+    return int(t.group(1)) if sha.hexdigest() == h.group(1) else None
+
+
 def ops_per_xp(N: int, nq: int) -> float:
     """Algorithmic 32-bit integer operations of one external product.
 
@@ -237,7 +260,9 @@ def main():
     a_ops = tr_xp / tr_launch * opx / (tr_ms / tr_launch / 1000.0) / 1e12 if tr_launch else 0.0
     result["roofline"] = {
         "bound": "alu", "kernel": "k_train", "achieved": round(a_ops, 3), "peak": round(PEAK_INT32_TOPS, 2),
-        "unit": "TOPS(int32)", "frac": round(a_ops / PEAK_INT32_TOPS, 4), "traffic": None,
+        "unit": "TOPS(int32)", "frac": round(a_ops / PEAK_INT32_TOPS, 4),
+        "traffic": measured_traffic() if args.workload == "mnist" and chunk == 50 else None,
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
         "launches": tr_launch, "avg_launch_ms": round(tr_ms / max(1, tr_launch), 3),
         "xp_per_launch": tr_xp / max(1, tr_launch), "ops_per_xp": opx,
     }

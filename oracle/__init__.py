@@ -73,6 +73,8 @@ def lib():
                 "orc_blind_rotate": (None, [C.c_void_p, u32p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_uint32, u32p]),
                 "orc_cdemux": (None, [C.c_void_p, u32p, u32p, u32p, u32p]),
                 "orc_ivp": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.c_uint32, u32p, u32p]),
+                "orc_ivp_pruned": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.c_uint32, C.c_uint32, u32p, u32p]),
+                "orc_leaf_row": (C.c_int32, [C.c_uint32, C.c_uint32, C.c_uint32]),
                 "orc_extract_lwe0": (None, [C.c_void_p, u32p, u32p]),
                 "orc_vp": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_uint8), C.c_uint32, u32p, u32p]),
                 "orc_permutation": (None, [C.c_uint64, C.c_uint32, u32p]),
@@ -129,6 +131,11 @@ def philox4x32_10(ctr, key) -> list[int]:
     o = np.zeros(4, np.uint32)
     lib().orc_philox4x32_10(_p(c, u32p), _p(k, u32p), _p(o, u32p))
     return [int(x) for x in o]
+
+
+def leaf_row(d: int, z: int, l: int) -> int:
+    """model row of tree leaf d (z tree bits, l classes), -1 for no class < l"""
+    return int(lib().orc_leaf_row(d, z, l))
 
 
 def w64(seed: int, domain: int, index: int) -> int:
@@ -334,6 +341,17 @@ class Ctx:
         out = self.rlwe(1 << (nb - nr))
         ct = np.ascontiguousarray(ct, np.uint32)
         lib().orc_ivp(self.h, _ptr_array(rg), nb, _p(ct, u32p), _p(out, u32p))
+        return out
+
+    def ivp_pruned(self, rgsws, l, ct) -> np.ndarray:
+        """IVP over [label bits, tuple bits] creating only the tree nodes that
+        lead to a class below l; the other leaves are returned as zeros."""
+        rg = [np.ascontiguousarray(r, np.uint32) for r in rgsws]
+        nb = len(rg)
+        nr = min(nb, self.logN)
+        out = self.rlwe(1 << (nb - nr))
+        ct = np.ascontiguousarray(ct, np.uint32)
+        lib().orc_ivp_pruned(self.h, _ptr_array(rg), nb, l, _p(ct, u32p), _p(out, u32p))
         return out
 
     def vp(self, rgsws, clear, lut) -> np.ndarray:

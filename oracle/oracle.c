@@ -700,6 +700,12 @@ void orc_cmux(const orc_ctx* c, const uint32_t* C, const uint32_t* d1, const uin
 /* BlindRotate: for t = 0, 1, ..., k-1: acc <- CMUX(C_t, X^{e_t} acc, acc).
  * With C_t encrypting S_t the result encrypts v * X^{sum_t S_t e_t}; the
  * paper's I_t is -e_t (Sec. 2.5.1). */
+static uint32_t ceil_log2_u(uint32_t l) {
+  uint32_t L = 0;
+  while ((1u << L) < l) ++L;
+  return L;
+}
+
 void orc_blind_rotate(const orc_ctx* c, const uint32_t* in, const uint32_t* const* C,
                       const int64_t* e, uint32_t k, uint32_t* out) {
   size_t rw = rlwe_words(c);
@@ -749,6 +755,57 @@ void orc_ivp(const orc_ctx* c, const uint32_t* const* C, uint32_t nb, const uint
   }
   free(t0);
   free(e);
+}
+
+/* Node u of the CDEMUX tree (after the level that creates it) leads to a
+ * cell of a class below l.  Index bits 0..L-1 are the label bits, so the
+ * label of every leaf under u is congruent to u mod 2^min(level+1, L); with
+ * z >= L the node is live iff (u mod 2^L) < l (for u < 2^L the smallest label
+ * under it is u itself); with z < L every leaf receives some class < l,
+ * because 2^z <= 2^(L-1) < l. */
+static int node_live(uint32_t u, uint32_t z, uint32_t L, uint32_t l) {
+  return z < L || (u & ((1u << L) - 1u)) < l;
+}
+
+/* IVP (Alg. 5) over the index [label bits (L), tuple bits] that creates only
+ * the live tree nodes: a split of L_j whose new branch L_{j+2^i} is not live
+ * is skipped, L_j keeping the undivided value (that branch would encrypt 0
+ * for every index whose label is below l).  out: 2^z RLWE, the non-live
+ * leaves left as zero.  This is the IVP behind the model of Definition 2,
+ * whose rows hold only the ciphertexts of classes below l. */
+void orc_ivp_pruned(const orc_ctx* c, const uint32_t* const* C, uint32_t nb, uint32_t l,
+                    const uint32_t* in, uint32_t* out) {
+  size_t rw = rlwe_words(c);
+  uint32_t L = ceil_log2_u(l);
+  uint32_t nr = nb < c->logN ? nb : c->logN;
+  uint32_t z = nb - nr;
+  memset(out, 0, sizeof(uint32_t) * rw * ((size_t)1 << z));
+  int64_t* e = (int64_t*)malloc(sizeof(int64_t) * (nr ? nr : 1));
+  for (uint32_t t = 0; t < nr; ++t) e[t] = (int64_t)1 << t;
+  orc_blind_rotate(c, in, C + z, e, nr, out);
+  uint32_t* t0 = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  for (uint32_t i = 0; i < z; ++i) {
+    uint32_t n = 1u << i;
+    for (uint32_t j = 0; j < n; ++j) {
+      if (!node_live(j, z, L, l) || !node_live(j + n, z, L, l)) continue;
+      orc_cdemux(c, C[i], out + j * rw, t0, out + (j + n) * rw);
+      memcpy(out + j * rw, t0, sizeof(uint32_t) * rw);
+    }
+  }
+  free(t0);
+  free(e);
+}
+
+/* Row position of tree leaf d (z tree bits, L label bits) in the model of
+ * Definition 2, or -1 for a leaf that holds no class below l.  With z >= L,
+ * leaf d = c + 2^L w (class c < l, w < 2^(z-L)) goes to row w l + c, so a row
+ * holds l 2^(z-L) = l 2^a / N ciphertexts; with z < L row d = leaf d. */
+int32_t orc_leaf_row(uint32_t d, uint32_t z, uint32_t l) {
+  uint32_t L = ceil_log2_u(l);
+  if (z < L) return (int32_t)d;
+  uint32_t cls = d & ((1u << L) - 1u);
+  if (cls >= l) return -1;
+  return (int32_t)((d >> L) * l + cls);
 }
 
 /* ExtractLWE(c, 0): a'_0 = a_0, a'_k = -a_{N-k} (k >= 1), b' = b_0 */
@@ -831,16 +888,10 @@ void orc_permutation(uint64_t seed, uint32_t s, uint32_t* pi) {
   }
 }
 
-static uint32_t ceil_log2(uint32_t l) {
-  uint32_t L = 0;
-  while ((1u << L) < l) ++L;
-  return L;
-}
-
 /* geometry of RAM j: a_j tuple bits, nb = L + a_j, z = nb - min(nb, log2 N) */
 static void ram_geometry(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, uint32_t j,
                          uint32_t* aj, uint32_t* nb, uint32_t* z) {
-  uint32_t L = ceil_log2(l);
+  uint32_t L = ceil_log2_u(l);
   uint32_t rem = s - j * a;
   *aj = rem < a ? rem : a;
   *nb = L + *aj;
@@ -848,33 +899,42 @@ static void ram_geometry(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, u
   *z = *nb - nr;
 }
 
-/* k1 = 2^z of a full RAM: the number of RLWE per RAM row of H.  Definition 2
- * prints ceil(l 2^a / N); the bit count of the IVP index gives 2^z, which is
- * the reading taken (equal to the printed value when l is a power of two). */
+/* rows of RAM row of H for a RAM with z tree bits: the live leaves */
+static uint32_t live_leaves(uint32_t z, uint32_t l) {
+  uint32_t L = ceil_log2_u(l);
+  return z >= L ? l << (z - L) : 1u << z;
+}
+
+/* k1 of Definition 2, ceil(l 2^a / N): the live leaves of a full RAM, l
+ * 2^(z-L) when z >= L (equal to the printed value); when z < L the IVP
+ * layout needs all 2^z (the printed value then undercounts). */
 uint32_t orc_k1(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a) {
   uint32_t aj, nb, z;
   ram_geometry(c, s, l, a, 0, &aj, &nb, &z);
   (void)aj;
   (void)nb;
-  return 1u << z;
+  return live_leaves(z, l);
 }
 
 /* Homomorphic training (Alg. 6) restricted to RAMs [ram_lo, ram_hi):
  * for each sample i in order and each RAM j: b = [Y_i bits 0..L), X_i[pi[j a
- * + t]] for t < a_j]; h = IVP(b, (0, Delta)); H[j][d] += h[d].  The input of
- * the IVP, "(0,1)" in the paper, is read as the trivial RLWE (0, Delta).  The
- * tuple of RAM j is t_{ja} .. t_{ja+a-1} (the printed t_j .. t_{j+a-1}
- * overlaps tuples).  x_ptr[i*s + k] points at the RGSW of input bit k of
- * sample i, y_ptr[i*L + u] at label bit u (LSB first); H is [k0][k1] RLWE. */
+ * + t]] for t < a_j]; h = IVP(b, (0, Delta)) with the live tree nodes only;
+ * H[j][row(d)] += h[d] for every live leaf d.  The input of the IVP, "(0,1)"
+ * in the paper, is read as the trivial RLWE (0, Delta).  The tuple of RAM j
+ * is t_{ja} .. t_{ja+a-1} (the printed t_j .. t_{j+a-1} overlaps tuples).
+ * x_ptr[i*s + k] points at the RGSW of input bit k of sample i, y_ptr[i*L +
+ * u] at label bit u (LSB first); H is [k0][k1] RLWE. */
 void orc_train(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const uint32_t* pi,
                const uint32_t* const* x_ptr, const uint32_t* const* y_ptr, uint64_t n,
                uint32_t ram_lo, uint32_t ram_hi, uint32_t* H) {
   size_t rw = rlwe_words(c);
-  uint32_t L = ceil_log2(l);
+  uint32_t L = ceil_log2_u(l);
   uint32_t k1 = orc_k1(c, s, l, a);
   const uint32_t** bits = (const uint32_t**)malloc(sizeof(uint32_t*) * (L + a + 1));
   uint32_t* in = (uint32_t*)calloc(rw, sizeof(uint32_t));
-  uint32_t* h = (uint32_t*)malloc(sizeof(uint32_t) * rw * k1);
+  uint32_t aj0, nb0, z0;
+  ram_geometry(c, s, l, a, 0, &aj0, &nb0, &z0);
+  uint32_t* h = (uint32_t*)malloc(sizeof(uint32_t) * rw * ((size_t)1 << z0));
   for (uint32_t i = 0; i < c->nq; ++i) in[((size_t)c->nq + i) * c->N] = (uint32_t)c->delta_mod[i];
   for (uint64_t smp = 0; smp < n; ++smp) {
     for (uint32_t j = ram_lo; j < ram_hi; ++j) {
@@ -882,9 +942,11 @@ void orc_train(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const uint3
       ram_geometry(c, s, l, a, j, &aj, &nb, &z);
       for (uint32_t u = 0; u < L; ++u) bits[u] = y_ptr[smp * L + u];
       for (uint32_t t = 0; t < aj; ++t) bits[L + t] = x_ptr[smp * s + pi[j * a + t]];
-      orc_ivp(c, bits, nb, in, h);
+      orc_ivp_pruned(c, bits, nb, l, in, h);
       for (uint32_t d = 0; d < (1u << z); ++d) {
-        uint32_t* dst = H + ((size_t)j * k1 + d) * rw;
+        int32_t row = orc_leaf_row(d, z, l);
+        if (row < 0) continue;
+        uint32_t* dst = H + ((size_t)j * k1 + (uint32_t)row) * rw;
         rlwe_add(c, dst, h + (size_t)d * rw, dst);
       }
     }
@@ -899,7 +961,7 @@ void orc_train(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const uint3
 void orc_class_count(const orc_ctx* c, uint32_t l, const uint32_t* const* y_ptr, uint64_t n,
                      uint32_t* cnt) {
   size_t rw = rlwe_words(c);
-  uint32_t L = ceil_log2(l);
+  uint32_t L = ceil_log2_u(l);
   uint32_t* in = (uint32_t*)calloc(rw, sizeof(uint32_t));
   uint32_t* h = (uint32_t*)malloc(sizeof(uint32_t) * rw);
   int64_t* e = (int64_t*)malloc(sizeof(int64_t) * (L ? L : 1));
@@ -915,13 +977,14 @@ void orc_class_count(const orc_ctx* c, uint32_t l, const uint32_t* const* y_ptr,
 }
 
 /* Homomorphic inference, PD-act branch (Alg. 7) for one sample, RAM j and
- * label c: b = [bits of c (cleartext), X[pi[j a + t]]], u = VP(b, H[j]).
+ * label c: b = [bits of c (cleartext), X[pi[j a + t]]], u = VP(b, H[j]) over
+ * the row's leaves in tree order.
  * x_ptr[k] points at the RGSW of input bit k of the sample. */
 void orc_infer_one(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const uint32_t* pi,
                    const uint32_t* H, const uint32_t* const* x_ptr, uint32_t j, uint32_t label,
                    uint32_t* lwe) {
   size_t rw = rlwe_words(c);
-  uint32_t L = ceil_log2(l);
+  uint32_t L = ceil_log2_u(l);
   uint32_t k1 = orc_k1(c, s, l, a);
   uint32_t aj, nb, z;
   ram_geometry(c, s, l, a, j, &aj, &nb, &z);
@@ -929,7 +992,15 @@ void orc_infer_one(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const u
   uint8_t* clear = (uint8_t*)calloc(nb + 1, 1);
   for (uint32_t u = 0; u < L; ++u) clear[u] = (uint8_t)((label >> u) & 1u);
   for (uint32_t t = 0; t < aj; ++t) bits[L + t] = x_ptr[pi[j * a + t]];
-  orc_vp(c, bits, clear, nb, H + (size_t)j * k1 * rw, lwe);
+  /* the row's live leaves in tree order; a leaf of no class below l is zero
+   * (the clear label bits never select it) */
+  uint32_t* lut = (uint32_t*)calloc(rw * ((size_t)1 << z), sizeof(uint32_t));
+  for (uint32_t d = 0; d < (1u << z); ++d) {
+    int32_t row = orc_leaf_row(d, z, l);
+    if (row >= 0) memcpy(lut + (size_t)d * rw, H + ((size_t)j * k1 + (uint32_t)row) * rw, sizeof(uint32_t) * rw);
+  }
+  orc_vp(c, bits, clear, nb, lut, lwe);
+  free(lut);
   free(bits);
   free(clear);
 }

@@ -141,15 +141,27 @@ def pd_act_predict(u_cells, kind="bin", thr=0, cap=4) -> int:
 
 # -- layout of the homomorphic model -----------------------------------------------
 
+def model_row(d: int, z: int, L: int, l: int) -> int:
+    """Row of H that holds tree leaf d of a RAM with z tree bits: with z >= L,
+    leaf d = c + 2^L w (class c < l) is row w l + c, so a row holds
+    l 2^(z-L) = l 2^a / N ciphertexts (Def. 2); with z < L row d is leaf d."""
+    if z < L:
+        return d
+    c, w = d % (1 << L), d >> L
+    return w * l + c if c < l else -1
+
+
 def expected_model_cells(W: np.ndarray, s: int, l: int, a: int, N: int) -> np.ndarray:
     """Decrypted content of H (shape [k0][k1][N]) implied by a plaintext Integer
-    WiSARD W: with m = c + 2^L addr, ciphertext m mod 2^z_j of RAM j holds
-    W[c][j][addr] at coefficient m >> z_j; every other cell is 0."""
+    WiSARD W: with m = c + 2^L addr, tree leaf d = m mod 2^z_j of RAM j holds
+    W[c][j][addr] at coefficient m >> z_j, and leaf d is row model_row(d) of
+    H[j]; every other cell is 0."""
     L = ceil_log2(l)
     logN = N.bit_length() - 1
     k0 = -(-s // a)
     nb_full = L + a
-    k1 = 1 << (nb_full - min(nb_full, logN))
+    z0 = nb_full - min(nb_full, logN)
+    k1 = l << (z0 - L) if z0 >= L else 1 << z0
     out = np.zeros((k0, k1, N), np.int64)
     for j in range(k0):
         aj = min(a, s - j * a)
@@ -158,12 +170,12 @@ def expected_model_cells(W: np.ndarray, s: int, l: int, a: int, N: int) -> np.nd
         for c in range(l):
             for addr in range(1 << aj):
                 m = c + (addr << L)
-                out[j, m % (1 << z), m >> z] = W[c, j, addr]
+                out[j, model_row(m % (1 << z), z, L, l), m >> z] = W[c, j, addr]
     return out
 
 
 __all__ = [
     "thermometer", "quantize_u8", "quantize_minmax", "encode", "f_comp", "train_integer",
     "act_bin", "act_log", "act_blog", "activate", "argmax_lowest", "ram_scores", "predict",
-    "pd_act_predict", "expected_model_cells", "permutation",
+    "pd_act_predict", "model_row", "expected_model_cells", "permutation",
 ]

@@ -138,6 +138,38 @@ def test_ivp_one_hot_brute_force(nb):
         assert np.array_equal(dec, want), m
 
 
+@pytest.mark.parametrize("N,nb,l", [(8, 6, 3), (16, 6, 3), (8, 7, 5), (16, 5, 2)])
+def test_pruned_ivp_brute_force(N, nb, l):
+    """The IVP with only the tree nodes that lead to a class below l: for
+    every index m = c + 2^L addr with c < l, the live leaves decrypt to the
+    one-hot table of the full IVP (Alg. 5), the leaf count is k1 of
+    Definition 2, and a non-live leaf is never written.  Also the external
+    products it saves: live leaves - 1 instead of 2^z - 1."""
+    c = O.Ctx(N, 1, 16)
+    s = c.keygen(8)
+    L = O.ceil_log2(l)
+    z = nb - min(nb, c.logN)
+    live = [d for d in range(1 << z) if O.leaf_row(d, z, l) >= 0]
+    assert len(live) == (l << (z - L) if z >= L else 1 << z)
+    assert sorted(O.leaf_row(d, z, l) for d in live) == list(range(len(live)))
+    for m in range(1 << nb):
+        if m % (1 << L) >= l:
+            continue
+        val = 1 + (m % 7)
+        Cs = _bits_rgsw(c, s, m, nb, 21, 100 * m)
+        full = c.ivp(Cs, c.trivial_rlwe(val))
+        pr = c.ivp_pruned(Cs, l, c.trivial_rlwe(val))
+        for d in range(1 << z):
+            if d in live:
+                want = np.zeros(N, np.int64)
+                if d == m % (1 << z):
+                    want[m >> z] = val
+                assert np.array_equal(c.dec_rlwe(s, pr[d]), want), (m, d)
+                assert np.array_equal(c.dec_rlwe(s, full[d]), want), (m, d)
+            else:
+                assert not pr[d].any(), (m, d)
+
+
 def test_vp_inverts_ivp_brute_force():
     """VP(bits(m'), IVP(bits(m), x)) decrypts to x [m' = m] (Alg. 3 read as the inverse of Alg. 5),
     with the low bits given in the clear like the label bits of Alg. 7."""

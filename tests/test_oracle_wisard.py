@@ -102,6 +102,7 @@ CONFIGS = [
     dict(N=16, s=14, l=3, a=4, n=6),   # nb = 6, log N = 4: z = 2 = L -> tree levels are the label bits
     dict(N=8, s=10, l=2, a=4, n=5),    # nb = 5, log N = 3: z = 2 > L = 1 -> one encrypted tree level
     dict(N=32, s=9, l=5, a=3, n=6),    # nb = 6, log N = 5: z = 1 < L = 3 -> label bits in the chain
+    dict(N=8, s=10, l=3, a=4, n=6),    # nb = 6, log N = 3: z = 3 > L = 2, l = 3: pruned label and tuple nodes
 ]
 
 

@@ -92,10 +92,12 @@ hw_status hw_ctx_params(const hw_ctx* ctx, hw_params* out);
 hw_status hw_sizes(const hw_ctx* ctx, uint64_t* rlwe_bytes, uint64_t* rgsw_bytes,
                    uint64_t* lwe_bytes);
 
-/* Model geometry of Def. 2: k0 = ceil(s/a) RAMs, k1 = 2^z RLWE per RAM where
- * z = L + a - min(L + a, log2 N) and L = ceil(log2 l); model_bytes is the size
- * of H = [k0][k1] RLWE.  (Def. 2 prints k1 = ceil(l 2^a / N); the IVP index
- * has L + a bits, which gives 2^z.) */
+/* Model geometry of Def. 2: k0 = ceil(s/a) RAMs and k1 RLWE per RAM, the
+ * ciphertexts that hold a class below l.  With L = ceil(log2 l) label bits
+ * and z = L + a - min(L + a, log2 N) tree bits, the IVP's leaf d = c + 2^L w
+ * holds class c; a RAM row keeps the leaves with c < l in row w l + c, so
+ * k1 = l 2^(z-L) = ceil(l 2^a / N) when z >= L, and k1 = 2^z otherwise.
+ * model_bytes is the size of H = [k0][k1] RLWE. */
 hw_status hw_wisard_dims(const hw_ctx* ctx, const hw_wisard_shape* shape, uint32_t* k0,
                          uint32_t* k1, uint64_t* model_bytes);
 
@@ -165,8 +167,10 @@ hw_status hw_external_product(hw_ctx* ctx, const uint32_t* rgsw_dev, const uint3
  * place.  x_rgsw_dev: RGSW[n][s] of the unpermuted input bits; y_rgsw_dev:
  * RGSW[n][L] of the label bits, LSB first (L = ceil(log2 l)).  For sample i
  * and RAM j the IVP (Alg. 5) runs on b = [label bits, x[pi[j a + t]] for
- * t < a_j] (a_j = min(a, s - j a)) with input (0, Delta) and its 2^z_j outputs
- * are added to model_dev[j][0 .. 2^z_j) (RLWE[k0][k1], coefficient domain).
+ * t < a_j] (a_j = min(a, s - j a)) with input (0, Delta), creating only the
+ * CDEMUX tree nodes that lead to a class below l, and each such leaf is
+ * added to its row of model_dev[j] (RLWE[k0][k1], coefficient domain; see
+ * hw_wisard_dims).
  * class_count_dev (one RLWE, may be NULL) receives the balancing counter
  * (Sec. 3.7.1): the IVP of the label bits alone.  Results are exact:
  * independent of chunking, sample order and launch configuration. */

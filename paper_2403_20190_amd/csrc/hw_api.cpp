@@ -279,6 +279,18 @@ static uint32_t ceil_log2(uint32_t l) {
 }
 
 
+// rows of a model RAM with z tree bits, L label bits and l classes: the
+// leaves of the IVP tree that hold a class below l (Definition 2's k1 when
+// z >= L; all 2^z leaves when z < L)
+uint32_t live_rows(uint32_t z, uint32_t L, uint32_t l) { return z >= L ? l << (z - L) : 1u << z; }
+
+// external products of one IVP over nb index bits: the rotation chain and
+// the live tree nodes (one split per live leaf beyond the first)
+uint32_t ivp_xp(uint32_t nb, int logN, uint32_t L, uint32_t l) {
+  const uint32_t nr = std::min(nb, (uint32_t)logN);
+  return nr + live_rows(nb - nr, L, l) - 1;
+}
+
 hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d) {
   if (!sh) return fail(HW_EINVAL, "null shape");
   if (sh->reserved) return fail(HW_EINVAL, "shape.reserved must be 0");
@@ -290,7 +302,8 @@ hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d) {
   const uint32_t nb = d->L + sh->a;
   const uint32_t nr = nb < (uint32_t)c->logN ? nb : (uint32_t)c->logN;
   d->z = nb - nr;
-  d->k1 = 1u << d->z;
+  d->kt = 1u << d->z;
+  d->k1 = live_rows(d->z, d->L, sh->l);
   return HW_OK;
 }
 
@@ -479,7 +492,7 @@ extern "C" hw_status hw_external_product(hw_ctx* c, const uint32_t* rgsw, const 
 // ---------------------------------------------------------------------------
 
 size_t train_ws_per_sample(const hw_ctx* c, const Dims& d) {
-  return (size_t)(d.k0 + 1) * (d.k1 + 1) * rlwe_words(c) * 4;  // k1 outputs + input slot per RAM
+  return (size_t)(d.k0 + 1) * (d.kt + 1) * rlwe_words(c) * 4;  // the tree's 2^z leaves + input slot per RAM
 }
 
 size_t infer_ws_per_sample(const hw_ctx* c, const hw_wisard_shape* sh, const Dims& d) {
@@ -508,6 +521,8 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   A.L = d.L;
   A.k0 = d.k0;
   A.k1 = d.k1;
+  A.kt = d.kt;
+  A.l = sh->l;
   hw::ReduceArgs R{};
   R.out = A.out;
   R.model = model;
@@ -517,16 +532,17 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   R.L = d.L;
   R.k0 = d.k0;
   R.k1 = d.k1;
+  R.kt = d.kt;
+  R.l = sh->l;
   R.logN = c->logN;
   R.N = c->prm.N;
   R.nq = c->prm.nq;
   A.nram = nram;
-  // external products per sample: the rotation chain and the CDEMUX tree of every RAM
+  // external products per sample: the rotation chain and the live CDEMUX tree of every RAM
   double xp_per_sample = 0;
   for (uint32_t j = 0; j < nram; ++j) {
     const uint32_t nb = j < d.k0 ? d.L + std::min(sh->a, sh->s - j * sh->a) : d.L;
-    const uint32_t nr = std::min(nb, (uint32_t)c->logN);
-    xp_per_sample += nr + ((1u << (nb - nr)) - 1);
+    xp_per_sample += ivp_xp(nb, c->logN, d.L, sh->l);
   }
   const bool tm = timing && c->prof;
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
@@ -653,10 +669,6 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
 // batched training
 // ---------------------------------------------------------------------------
 
-static uint32_t item_xp(uint32_t nb, int logN) {
-  const uint32_t nr = std::min(nb, (uint32_t)logN);
-  return nr + ((1u << (nb - nr)) - 1);
-}
 
 namespace {
 // one persistent launch: the jobs, the queue of (job, RAM, piece) items
@@ -715,12 +727,12 @@ static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
     nram[j] = d.k0 + (jobs[j].class_count_dev ? 1 : 0);
     for (uint32_t r = 0; r < nram[j]; ++r) {
       const uint32_t nb = r < d.k0 ? d.L + std::min(jobs[j].shape.a, jobs[j].shape.s - r * jobs[j].shape.a) : d.L;
-      const uint32_t xp = item_xp(nb, c->logN);
+      const uint32_t xp = ivp_xp(nb, c->logN, d.L, jobs[j].shape.l);
       xp_max[j] = std::max(xp_max[j], xp);
       xp_smp[j] += xp;
     }
     W += xp_smp[j] * (double)jobs[j].n;
-    k1max = std::max(k1max, d.k1);
+    k1max = std::max(k1max, d.kt);
   }
   if (W == 0) return HW_OK;
   B.scratch_words = (uint64_t)(k1max + 1) * rw;
@@ -758,6 +770,8 @@ static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
     b.L = d.L;
     b.k0 = d.k0;
     b.k1 = d.k1;
+    b.kt = d.kt;
+    b.l = J.shape.l;
     b.nsmp = (uint32_t)J.n;
     b.nram = nram[j];
     b.per = per[j];
@@ -773,7 +787,7 @@ static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
       const uint64_t cnt = std::min<uint64_t>(per[j], J.n - (uint64_t)p * per[j]);
       for (uint32_t r = 0; r < nram[j]; ++r) {
         const uint32_t nb = r < d.k0 ? d.L + std::min(J.shape.a, J.shape.s - r * J.shape.a) : d.L;
-        const uint64_t ixp = cnt * item_xp(nb, c->logN);
+        const uint64_t ixp = cnt * ivp_xp(nb, c->logN, d.L, J.shape.l);
         B.items.push_back(hw::BItem{jb, r, p, (uint32_t)std::min<uint64_t>(ixp, 0xFFFFFFFFull)});
         B.xp += (double)ixp;
       }

@@ -144,7 +144,11 @@ static size_t lwe_words(const hw_ctx* c) { return (size_t)c->prm.nq * (c->prm.N 
 
 struct Dims {
   uint32_t L, k0, k1, z;
+  uint32_t kt;  // 2^z: leaves of a full RAM's IVP tree (k1 of them hold a class below l)
 };
+
+uint32_t live_rows(uint32_t z, uint32_t L, uint32_t l);
+uint32_t ivp_xp(uint32_t nb, int logN, uint32_t L, uint32_t l);
 
 
 // error reporting: sets the calling thread's message

@@ -35,20 +35,22 @@ struct TrainArgs {
   const uint32_t* x_rgsw;   // [n][s] RGSW
   const uint32_t* y_rgsw;   // [n][L] RGSW
   const uint32_t* perm;     // [s]
-  uint32_t* out;            // [n_sub][k0 + 1][k1] RLWE (per-sample IVP outputs)
+  uint32_t* out;            // [n_sub][k0 + 1][kt + 1] RLWE (per-sample IVP leaves + input slot)
   uint64_t rgsw_words;
   uint64_t i0;              // first sample of the sub-batch
   uint32_t s, a, L, k0, k1;
+  uint32_t l, kt;           // classes; 2^z leaves of a full RAM's tree (slots per block: kt + 1)
   uint32_t nram, nsub;      // grid: nram RAM items (k0, + 1 for the counter) x nsub samples
   uint32_t map;             // 0: 2-D grid (RAM, sample); 1: 1-D, XCD-grouped
 };
 
 struct ReduceArgs {
   const uint32_t* out;      // as TrainArgs::out
-  uint32_t* model;          // [k0][k1] RLWE
+  uint32_t* model;          // [k0][k1] RLWE (live leaves, Def. 2 rows)
   uint32_t* cnt;            // one RLWE or nullptr
   uint64_t n_sub;
   uint32_t s, a, L, k0, k1, logN, N, nq;
+  uint32_t l, kt;           // classes; tree leaves per block (block = kt + 1 slots)
 };
 
 struct InferArgs {
@@ -74,6 +76,7 @@ struct BJob {
   uint64_t acc0;            // word offset of the accumulators of pieces 1.. ([piece-1][nram][k1] RLWE)
   uint64_t words0;          // prefix over the jobs of the model (+ counter) words the reduction writes
   uint32_t s, a, L, k0, k1, nsmp;
+  uint32_t l, kt;           // classes; tree leaves of a full RAM (scratch slots beyond the input slot)
   uint32_t nram;            // k0, + 1 with a class counter
   uint32_t per, pieces;     // samples per piece, pieces per RAM
 };

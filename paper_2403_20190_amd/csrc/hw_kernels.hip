@@ -471,15 +471,46 @@ __device__ __forceinline__ void copy_rlwe(uint32_t* __restrict__ dst, const uint
 // (slot j - C_i [.] slot j, C_i [.] slot j) at slots j and j + 2^i.  The
 // `ram == k0` workgroup builds the class counter from the label bits alone.
 
+// Tree node u (created by the level that splits it off) leads to a cell of a
+// class below l: with z >= L iff (u mod 2^L) < l, else always (Def. 2: a
+// model row holds only those cells).  Leaf d sits in row leaf_row(d) of the
+// model: (d >> L) l + (d mod 2^L) when z >= L, d otherwise.
+__device__ __forceinline__ bool node_live(uint32_t u, uint32_t z, uint32_t L, uint32_t l) {
+  return z < L || (u & ((1u << L) - 1u)) < l;
+}
+
+__device__ __forceinline__ uint32_t leaf_row(uint32_t d, uint32_t z, uint32_t L, uint32_t l) {
+  return z < L ? d : (d >> L) * l + (d & ((1u << L) - 1u));
+}
+
+// dst (=|+=) src over one RLWE, each thread its own coefficients t + T e
+template <int LOGN, int NQ>
+__device__ __forceinline__ void acc_rlwe(const Tabs& T, uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                         bool store, uint32_t t) {
+  constexpr int N = 1 << LOGN, TT = N / 8;
+#pragma unroll 1
+  for (int w = 0; w < 2 * NQ; ++w) {
+    const uint32_t q = T.pt[w % NQ].q;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const size_t k = (size_t)w * N + TT * e + t;
+      dst[k] = store ? src[k] : addq(dst[k], src[k], q);
+    }
+  }
+}
+
 // IVP of one (sample, RAM) into its block: acc = (0, Delta), the rotation
-// chain over bits z..nb-1, then the CDEMUX tree over bits 0..z-1.
-// bit(u) returns the RGSW of bit u of the IVP index.  With `dest`, the 2^z
-// outputs go to dest[0 .. 2^z) instead of the slots: stored when `store`,
-// else added (the last tree level writes them there directly).
+// chain over bits z..nb-1, then the CDEMUX tree over bits 0..z-1 creating
+// only the live nodes (a split whose new branch is not live is skipped).
+// bit(u) returns the RGSW of bit u of the IVP index; the index has L label
+// bits and l classes.  Without `dest` leaf d is left in slot d.  With
+// `dest`, live leaf d goes to dest[leaf_row(d)] instead: stored when
+// `store`, else added (the last tree level writes there directly).
 template <int LOGN, int NQ, class BitFn>
 __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ slot0, uint32_t* __restrict__ xin,
-                                          uint32_t nb, BitFn&& bit, uint32_t* lds, uint2* twl, uint32_t t,
-                                          uint32_t* __restrict__ dest = nullptr, bool store = false) {
+                                          uint32_t nb, uint32_t L, uint32_t l, BitFn&& bit, uint32_t* lds,
+                                          uint2* twl, uint32_t t, uint32_t* __restrict__ dest = nullptr,
+                                          bool store = false) {
   constexpr int N = 1 << LOGN, TT = N / 8;
   constexpr size_t RW = (size_t)2 * NQ * N;
   const uint32_t nr = nb < (uint32_t)LOGN ? nb : (uint32_t)LOGN;
@@ -501,32 +532,34 @@ __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ 
     const bool last = dest && lev + 1 == z;
 #pragma unroll 1
     for (uint32_t j = 0; j < n; ++j) {
+      if (!node_live(j, z, L, l)) continue;
       uint32_t* sj = slot0 + j * RW;
-      copy_rlwe<LOGN, NQ>(xin, sj, t);
-      if (last)
-        ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t,
-                           XpOut{dest + j * RW, xin, dest + (j + n) * RW, store ? XP_DEMUX : XP_DEMUX_ACC});
-      else
-        ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t, XpOut{sj, xin, slot0 + (j + n) * RW, XP_DEMUX});
-    }
-  }
-  if (dest && z == 0) {  // no tree: the chain's accumulator is the output
-#pragma unroll 1
-    for (int w = 0; w < 2 * NQ; ++w) {
-      const uint32_t q = T.pt[w % NQ].q;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const size_t k = (size_t)w * N + TT * e + t;
-        dest[k] = store ? slot0[k] : addq(dest[k], slot0[k], q);
+      if (node_live(j + n, z, L, l)) {
+        copy_rlwe<LOGN, NQ>(xin, sj, t);
+        if (last)
+          ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t,
+                             XpOut{dest + leaf_row(j, z, L, l) * RW, xin, dest + leaf_row(j + n, z, L, l) * RW,
+                                   store ? XP_DEMUX : XP_DEMUX_ACC});
+        else
+          ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t, XpOut{sj, xin, slot0 + (j + n) * RW, XP_DEMUX});
+      } else if (last) {  // unsplit live leaf
+        acc_rlwe<LOGN, NQ>(T, dest + leaf_row(j, z, L, l) * RW, sj, store, t);
       }
     }
   }
+  if (dest && z == 0) acc_rlwe<LOGN, NQ>(T, dest, slot0, store, t);  // no tree: the chain's accumulator
 }
 
 __device__ __forceinline__ uint32_t ram_bits(uint32_t ram, uint32_t k0, uint32_t s, uint32_t a, uint32_t L) {
   if (ram >= k0) return L;  // the class counter: label bits only
   const uint32_t rem = s - ram * a;
   return L + (rem < a ? rem : a);
+}
+
+// model rows of a RAM with nb index bits: its live leaves
+__device__ __forceinline__ uint32_t ram_rows(uint32_t nb, uint32_t logN, uint32_t L, uint32_t l) {
+  const uint32_t z = nb - (nb < logN ? nb : logN);
+  return z >= L ? l << (z - L) : 1u << z;
 }
 
 template <int LOGN, int NQ, int OCC>
@@ -547,8 +580,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
     smp = lg / A.nram;
   }
   const uint64_t gi = A.i0 + smp;
-  uint32_t* slot0 = A.out + ((size_t)smp * (A.k0 + 1) + ram) * (A.k1 + 1) * RW;
-  ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)A.k1 * RW, ram_bits(ram, A.k0, A.s, A.a, A.L),
+  uint32_t* slot0 = A.out + ((size_t)smp * (A.k0 + 1) + ram) * (A.kt + 1) * RW;
+  ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)A.kt * RW, ram_bits(ram, A.k0, A.s, A.a, A.L), A.L, A.l,
                       [&](uint32_t u) -> const uint32_t* {
                         if (u < A.L) return A.y_rgsw + (gi * A.L + u) * A.rgsw_words;
                         return A.x_rgsw + (gi * A.s + A.perm[ram * A.a + (u - A.L)]) * A.rgsw_words;
@@ -596,7 +629,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
 #pragma unroll 1
     for (uint32_t smp = s0; smp < s1; ++smp) {
       const uint64_t gi = smp;
-      ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)J.k1 * RW, nb,
+      ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)J.kt * RW, nb, J.L, J.l,
                           [&](uint32_t u) -> const uint32_t* {
                             if (u < J.L) return J.y + (gi * J.L + u) * A.rgsw_words;
                             return J.x + (gi * J.s + J.perm[I.ram * J.a + (u - J.L)]) * A.rgsw_words;
@@ -634,9 +667,7 @@ __global__ __launch_bounds__(256) void k_reduce_batch(Tabs T, const BJob* __rest
     if (x < model_words) {
       ram = (uint32_t)(x / per_ram);
       off = x - (size_t)ram * per_ram;
-      const uint32_t nb = ram_bits(ram, J.k0, J.s, J.a, J.L);
-      const uint32_t nr = nb < logN ? nb : logN;
-      if (off / RW >= (1u << (nb - nr))) continue;
+      if (off / RW >= ram_rows(ram_bits(ram, J.k0, J.s, J.a, J.L), logN, J.L, J.l)) continue;
     } else {
       ram = J.k0;
       off = x - model_words;
@@ -651,14 +682,15 @@ __global__ __launch_bounds__(256) void k_reduce_batch(Tabs T, const BJob* __rest
   }
 }
 
-// model[j][d] += sum over the sub-batch of out[smp][j][d] for d < 2^{z_j};
-// cnt += sum of out[smp][k0][0].  One thread per model word.
+// model[j][row] += sum over the sub-batch of out[smp][j][leaf] for every live
+// leaf of RAM j (row = leaf_row(leaf)); cnt += sum of out[smp][k0][0].  One
+// thread per model word.
 __global__ __launch_bounds__(256) void k_reduce_model(Tabs T, ReduceArgs A) {
   const size_t RW = (size_t)2 * A.nq * A.N;
   const size_t per_ram = (size_t)A.k1 * RW;
   const size_t model_words = (size_t)A.k0 * per_ram;
   const size_t total = model_words + (A.cnt ? RW : 0);
-  const size_t blk = (size_t)(A.k1 + 1) * RW;      // one (sample, RAM) block
+  const size_t blk = (size_t)(A.kt + 1) * RW;      // one (sample, RAM) block: the tree's leaves + input slot
   const size_t stride = (size_t)(A.k0 + 1) * blk;  // one sample
   for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (size_t)gridDim.x * blockDim.x) {
     uint32_t ram, d;
@@ -666,12 +698,12 @@ __global__ __launch_bounds__(256) void k_reduce_model(Tabs T, ReduceArgs A) {
     if (w < model_words) {
       ram = (uint32_t)(w / per_ram);
       rem = w - (size_t)ram * per_ram;
-      d = (uint32_t)(rem / RW);
-      rem -= (size_t)d * RW;
-      const uint32_t left = A.s - ram * A.a;
-      const uint32_t nb = A.L + (left < A.a ? left : A.a);
-      const uint32_t nr = nb < A.logN ? nb : A.logN;
-      if (d >= (1u << (nb - nr))) continue;
+      const uint32_t row = (uint32_t)(rem / RW);
+      rem -= (size_t)row * RW;
+      const uint32_t nb = ram_bits(ram, A.k0, A.s, A.a, A.L);
+      if (row >= ram_rows(nb, A.logN, A.L, A.l)) continue;
+      const uint32_t z = nb - (nb < A.logN ? nb : A.logN);
+      d = z < A.L ? row : ((row / A.l) << A.L) + row % A.l;  // the leaf of this row
     } else {
       ram = A.k0;
       d = 0;
@@ -738,8 +770,9 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
 #pragma unroll 1
       for (uint32_t w = 0; w < cnt; ++w) {
         const bool leaf = lev == (int)z - 1;
-        const uint32_t* lo = leaf ? H + (size_t)(lab + (w << A.L)) * RW : acc + (size_t)w * RW;
-        const uint32_t* hi = leaf ? H + (size_t)(lab + (w << A.L) + (1u << lev)) * RW : acc + (size_t)(w + cnt) * RW;
+        // leaves lab + 2^L w and lab + 2^L (w + cnt) are rows w l + lab and (w + cnt) l + lab
+        const uint32_t* lo = leaf ? H + (size_t)(w * A.l + lab) * RW : acc + (size_t)w * RW;
+        const uint32_t* hi = leaf ? H + (size_t)((w + cnt) * A.l + lab) * RW : acc + (size_t)(w + cnt) * RW;
         uint32_t* dst = acc + (size_t)w * RW;
 #pragma unroll 1
         for (int pw = 0; pw < 2 * NQ; ++pw) {

@@ -141,7 +141,7 @@ def mnist_pair(n):
 
 def test_mnist_shape_training_sampled():
     pair, _ = mnist_pair(2)
-    assert (pair.k0, pair.k1) == (196, 32)
+    assert (pair.k0, pair.k1) == (196, 20)  # k1 = l 2^a / N = 10 * 4096 / 2048 (Def. 2)
     H, cnt, _, _ = train_dev(pair)
     rams = [0, 97, 195]
     Ho = pair.oracle_train(rams)
@@ -189,7 +189,7 @@ def test_ham_shape_sampled():
     Xtr, ytr, Xte, _ = synth.ham_like(3, n_train=20, n_test=1)
     bits = CL.thermometer(CL.quantize_u8(Xtr[:1], 2), 2)
     pair = Pair(4096, 3, 16384, 4704, 7, 12, bits, ytr[:1], seed=4)
-    assert (pair.k0, pair.k1) == (392, 8)
+    assert (pair.k0, pair.k1) == (392, 7)  # k1 = 7 * 4096 / 4096
     H, cnt, _, _ = train_dev(pair)
     rams = [0, 391]
     Ho = pair.oracle_train(rams)

@@ -286,6 +286,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extras:
         result["inference"] = infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev)
+        result["merge"] = merge_pass(ctx, H, k0, k1)
         result["ntt"] = ntt_pass(ctx, N, nq, dev)
         result["hbm_copy_gbs"] = hbm_copy(dev)
         if not args.no_batched:
@@ -336,6 +337,30 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
         "xp_per_s": round(inf_xp / (inf_ms / 1000.0), 1) if inf_ms else None,
         "n_test": nt, "pd_act": "bin", "test_accuracy": round(acc, 4),
     }
+
+
+def merge_pass(ctx, H, k0, k1):
+    """Model merge (hw_rlwe_add) of pairs of models of the workload's shape:
+    12 bytes of HBM traffic per word (two reads, one write).  Merges rotate
+    over 4 distinct pairs (about 1 GB for the MNIST shape) so that no pair is
+    still in the 256 MB last-level cache when it is merged again."""
+    import torch
+    count = k0 * k1
+    pairs = [(H.clone(), H.clone()) for _ in range(4)]
+    for g, h in pairs:
+        ctx.rlwe_add(g, h, count)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_reset()
+    for r in range(20):
+        g, h = pairs[r % 4]
+        ctx.rlwe_add(g, h, count)
+    ms, launches, words = ctx.profile_read("rlwe_add")
+    ctx.profile(False)
+    gbs = words * 12 / (ms / 1000.0) / 1e9
+    del pairs
+    return {"model_mib": round(count * ctx.rlwe_words * 4 / 2**20, 1), "ms_per_merge": round(ms / launches, 3),
+            "gbs": round(gbs, 1), "hbm_frac": round(gbs / PEAK_HBM_GBS, 4)}
 
 
 def ntt_pass(ctx, N, nq, dev):

@@ -190,6 +190,17 @@ hw_status hw_wisard_infer_encrypted(hw_ctx* ctx, const hw_wisard_shape* shape,
                                     uint64_t n, uint32_t* ram_scores_dev,
                                     uint32_t* class_scores_dev, hipStream_t stream);
 
+/* Merge of models trained apart (Sec. 3.7.2: Integer WiSARD models of
+ * federated entities are merged by adding their RAMs; the merged model is
+ * the one centralised training on the union would give, bit for bit, since
+ * training adds each sample's contribution mod q_i): dst[k] += src[k] for
+ * count RLWE ciphertexts, residue by residue.  Also adds class counters and
+ * continues training from a checkpoint.  dst and src: device, [count] RLWE,
+ * 16-byte aligned; dst may equal src (doubling); otherwise they must not
+ * overlap.  HW_EINVAL for null or misaligned buffers. */
+hw_status hw_rlwe_add(hw_ctx* ctx, uint32_t* dst_dev, const uint32_t* src_dev, uint64_t count,
+                      hipStream_t stream);
+
 /* ---- batching ----------------------------------------------------------------- */
 
 typedef struct {
@@ -352,7 +363,7 @@ const char* hw_tune_variant_name(const char* kernel, int variant);
  * bracketed by a pair of HIP events recorded on the caller's stream.  Kernel
  * names: "train", "reduce", "train_batch", "reduce_batch", "batch_plan" (a whole
  * plan replay), "infer", "class_sums", "encrypt_rgsw", "encrypt_rlwe",
- * "decrypt_rlwe", "decrypt_lwe", "xp", "ntt". */
+ * "decrypt_rlwe", "decrypt_lwe", "xp", "ntt", "rlwe_add". */
 hw_status hw_profile_enable(hw_ctx* ctx, int enable);
 
 /* Waits for the recorded events and returns, for kernel `name`, the summed

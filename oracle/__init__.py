@@ -75,6 +75,7 @@ def lib():
                 "orc_ivp": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.c_uint32, u32p, u32p]),
                 "orc_ivp_pruned": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.c_uint32, C.c_uint32, u32p, u32p]),
                 "orc_leaf_row": (C.c_int32, [C.c_uint32, C.c_uint32, C.c_uint32]),
+                "orc_rlwe_add_n": (None, [C.c_void_p, u32p, u32p, C.c_uint64, u32p]),
                 "orc_extract_lwe0": (None, [C.c_void_p, u32p, u32p]),
                 "orc_vp": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_uint8), C.c_uint32, u32p, u32p]),
                 "orc_permutation": (None, [C.c_uint64, C.c_uint32, u32p]),
@@ -367,6 +368,15 @@ class Ctx:
         ct = np.ascontiguousarray(ct, np.uint32)
         out = np.zeros((self.nq, self.N + 1), np.uint32)
         lib().orc_extract_lwe0(self.h, _p(ct, u32p), _p(out, u32p))
+        return out
+
+    def rlwe_add(self, x, y) -> np.ndarray:
+        """x + y over RLWE arrays of any leading shape (model merge, Sec. 3.7.2)"""
+        x = np.ascontiguousarray(x, np.uint32)
+        y = np.ascontiguousarray(y, np.uint32)
+        assert x.shape == y.shape and x.size % (2 * self.nq * self.N) == 0
+        out = np.zeros_like(x)
+        lib().orc_rlwe_add_n(self.h, _p(x, u32p), _p(y, u32p), x.size // (2 * self.nq * self.N), _p(out, u32p))
         return out
 
     def lwe_add(self, x, y) -> np.ndarray:

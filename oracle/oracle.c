@@ -1005,6 +1005,14 @@ void orc_infer_one(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const u
   free(clear);
 }
 
+/* Merge of Integer WiSARD models trained apart (Sec. 3.7.2: the federated
+ * entities' models are merged by adding their RAMs): out = x + y for count
+ * RLWE ciphertexts (model rows or class counters), residue by residue */
+void orc_rlwe_add_n(const orc_ctx* c, const uint32_t* x, const uint32_t* y, uint64_t count, uint32_t* out) {
+  size_t rw = rlwe_words(c);
+  for (uint64_t k = 0; k < count; ++k) rlwe_add(c, x + k * rw, y + k * rw, out + k * rw);
+}
+
 /* LWE addition, used for the per-class sums u_c = sum_j u[c][j] */
 void orc_lwe_add(const orc_ctx* c, const uint32_t* x, const uint32_t* y, uint32_t* out) {
   for (uint32_t i = 0; i < c->nq; ++i)

@@ -70,3 +70,30 @@ def pd_act_predict(cells, kind: str = "bin", thr: int = 0, cap: int = 4) -> np.n
     """cells[n][l][k0] decrypted RAM cells -> predicted class per sample."""
     scores = activate(cells, kind, thr, cap).sum(axis=2)
     return np.argmax(scores, axis=1)  # numpy takes the first maximum: the lowest index
+
+
+def save_checkpoint(path, model, class_count=None, **meta):
+    """Write a model (and its class counter) with integer metadata to an .npz
+    file: the parameters, the shape, and the number of samples trained so far
+    (the cursor to resume from).  Training adds each sample's contribution, so
+    resuming is training the remaining samples into the loaded model (or
+    merging with hw_rlwe_add a model trained on them elsewhere)."""
+    import numpy as np
+    arrays = {"model": model.detach().cpu().numpy()}
+    if class_count is not None:
+        arrays["class_count"] = class_count.detach().cpu().numpy()
+    for k, v in meta.items():
+        arrays["meta_" + k] = np.asarray(int(v), np.int64)
+    np.savez(path, **arrays)
+
+
+def load_checkpoint(path, device="cuda"):
+    """(model, class_count or None, meta) from save_checkpoint; loaded
+    without unpickling."""
+    import numpy as np
+    import torch
+    with np.load(path, allow_pickle=False) as z:
+        model = torch.from_numpy(z["model"]).to(device)
+        cnt = torch.from_numpy(z["class_count"]).to(device) if "class_count" in z.files else None
+        meta = {k[len("meta_"):]: int(z[k]) for k in z.files if k.startswith("meta_")}
+    return model, cnt, meta

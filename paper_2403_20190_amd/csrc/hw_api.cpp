@@ -665,6 +665,18 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
   return ok();
 }
 
+extern "C" hw_status hw_rlwe_add(hw_ctx* c, uint32_t* dst, const uint32_t* src, uint64_t count, hipStream_t st) {
+  CHECK(enter(c));
+  if (count == 0) return ok();
+  if (!dst || !src) return fail(HW_EINVAL, "null buffer");
+  if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) & 15)
+    return fail(HW_EINVAL, "buffers must be 16-byte aligned");
+  const uint64_t words = count * rlwe_words(c);
+  HIP_TRY(timed(c, "rlwe_add", (double)words, st,
+                [&] { return hw::launch_rlwe_add(c->tabs, dst, src, words, c->prm.N, c->prm.nq, st); }));
+  return ok();
+}
+
 // ---------------------------------------------------------------------------
 // batched training
 // ---------------------------------------------------------------------------

@@ -130,5 +130,7 @@ hipError_t launch_reduce_batch(const Tabs& T, const BJob* jobs, uint32_t njobs, 
                                uint32_t N, uint32_t nq, const uint32_t* acc, hipStream_t st);
 hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int occ, hipStream_t st);
 hipError_t launch_class_sums(const Tabs& T, const SumArgs& A, hipStream_t st);
+hipError_t launch_rlwe_add(const Tabs& T, uint32_t* dst, const uint32_t* src, uint64_t words, uint32_t N, uint32_t nq,
+                           hipStream_t st);
 
 }  // namespace hw

@@ -828,6 +828,20 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
   }
 }
 
+// dst += src over `words` words of RLWE ciphertexts (2 nq N words each),
+// residue by residue; a thread adds four consecutive words (16-byte accesses)
+__global__ __launch_bounds__(256) void k_rlwe_add(Tabs T, uint32_t* __restrict__ dst,
+                                                  const uint32_t* __restrict__ src, uint64_t words, uint32_t N,
+                                                  uint32_t nq) {
+  const uint64_t n4 = words / 4;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n4; v += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t q = T.pt[(uint32_t)((4 * v / N) % nq)].q;  // N >= 4: four words share a prime
+    const uint4 a = reinterpret_cast<const uint4*>(dst)[v], b = reinterpret_cast<const uint4*>(src)[v];
+    reinterpret_cast<uint4*>(dst)[v] = make_uint4(addq(a.x, b.x, q), addq(a.y, b.y, q), addq(a.z, b.z, q),
+                                                  addq(a.w, b.w, q));
+  }
+}
+
 // sums[i][c] = sum_j scores[i][c][j] (LWE addition), one thread per word
 __global__ __launch_bounds__(256) void k_class_sums(Tabs T, SumArgs A) {
   const size_t LW = (size_t)A.nq * (A.N + 1);
@@ -1071,6 +1085,15 @@ hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int
   const dim3 grid = A.map == 0 ? dim3(A.k0, A.l, A.nsub) : dim3((uint32_t)((G + 7) / 8 * 8));
   HW_DISPATCH_OCC(logN, nq, occ,
                   hipLaunchKernelGGL((k_infer<LN, NQ, OC>), grid, dim3(Geo<LN>::T), 0, st, T, A));
+  return hipGetLastError();
+}
+
+hipError_t launch_rlwe_add(const Tabs& T, uint32_t* dst, const uint32_t* src, uint64_t words, uint32_t N, uint32_t nq,
+                           hipStream_t st) {
+  const uint64_t n4 = words / 4;
+  const uint32_t blocks = (uint32_t)((n4 + 255) / 256 < 65536 ? (n4 + 255) / 256 : 65536);
+  if (!blocks) return hipSuccess;
+  hipLaunchKernelGGL(k_rlwe_add, dim3(blocks), dim3(256), 0, st, T, dst, src, words, N, nq);
   return hipGetLastError();
 }
 

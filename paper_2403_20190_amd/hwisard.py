@@ -84,6 +84,7 @@ _SIG = {
     "hw_external_product": [_vp, _vp, _vp, _u64, _vp, _vp],
     "hw_wisard_train_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_wisard_infer_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
+    "hw_rlwe_add": [_vp, _vp, _vp, _u64, _vp],
     "hw_batch_train": [_vp, C.POINTER(TrainJob), _u32, _vp],
     "hw_batch_plan_create": [_vp, C.POINTER(TrainJob), _u32, C.POINTER(C.c_void_p)],
     "hw_batch_plan_launch": [_vp, _vp],
@@ -236,6 +237,10 @@ class Context:
     def train(self, sh: Shape, x_rgsw, y_rgsw, n: int, model, class_count=None):
         _check(_lib.hw_wisard_train_encrypted(self._h, C.byref(sh), _ptr(x_rgsw), _ptr(y_rgsw), n, _ptr(model),
                                               _ptr(class_count), _stream()))
+
+    def rlwe_add(self, dst, src, count: int):
+        """dst += src over count RLWE ciphertexts (model merge, Sec. 3.7.2)"""
+        _check(_lib.hw_rlwe_add(self._h, _ptr(dst), _ptr(src), count, _stream()))
 
     def batch_train(self, jobs):
         """jobs: iterable of (shape, x_rgsw, y_rgsw, n, model, class_count) -- one

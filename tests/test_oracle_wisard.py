@@ -153,6 +153,7 @@ def test_model_additivity_and_order():
     HB = m.train(range(3, 6))
     q = m.c.primes[0]
     assert np.array_equal(H, ((HA.astype(np.uint64) + HB) % q).astype(np.uint32))
+    assert np.array_equal(H, m.c.rlwe_add(HA, HB))  # the oracle's merge
     assert np.array_equal(H, m.train([5, 2, 0, 4, 1, 3]))
 
 
@@ -163,3 +164,16 @@ def test_class_counter():
     dec = m.c.dec_rlwe(m.sk, cnt)
     assert dec[:3].tolist() == [int((m.y == c).sum()) for c in range(3)]
     assert not dec[3:].any()
+
+
+def test_checkpoint_roundtrip_host(tmp_path):
+    """save_checkpoint / load_checkpoint keep the words and the metadata (host tensors)."""
+    import torch
+
+    from paper_2403_20190_amd import client as CL
+    rng = np.random.default_rng(1)
+    H = torch.from_numpy(rng.integers(0, 2**31, (3, 2, 2, 1, 16)).astype(np.int32))
+    C = torch.from_numpy(rng.integers(0, 2**31, (2, 1, 16)).astype(np.int32))
+    CL.save_checkpoint(tmp_path / "c.npz", H, C, N=16, trained=7)
+    H2, C2, meta = CL.load_checkpoint(tmp_path / "c.npz", device="cpu")
+    assert torch.equal(H, H2) and torch.equal(C, C2) and meta == {"N": 16, "trained": 7}

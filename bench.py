@@ -226,6 +226,10 @@ def main():
     value = n / (ms_per_step / 1000.0)
     tr_ms, tr_launch, tr_xp = ctx.profile_read("train")
     rd_ms, _, _ = ctx.profile_read("reduce")
+    # bytes the reductions read and write: per launch every live leaf of every
+    # (sample, RAM) block (4 B) plus the model read and written (8 B per word)
+    rd_bytes = args.steps * (n * (k0 * k1 + (1 if W["balance"] else 0)) * ctx.rlwe_words * 4
+                             + -(-n // chunk) * (k0 * k1 + (1 if W["balance"] else 0)) * ctx.rlwe_words * 8)
     en_ms, en_launch, en_rows = ctx.profile_read("encrypt_rgsw")
     ctx.profile(False)
     print("bench: %.1f ms/step, %.2f samples/s" % (ms_per_step, value), file=sys.stderr, flush=True)
@@ -269,6 +273,8 @@ def main():
     result["kernels"] = {
         "train_ms_per_step": round(train_kernel_ms, 2),
         "reduce_ms_per_step": round(rd_ms / args.steps, 2),
+        # k_reduce_model reads every sample's leaf block once: bytes / time
+        "reduce_hbm_frac": round(rd_bytes / (rd_ms / 1000.0) / 1e9 / PEAK_HBM_GBS, 4) if rd_ms else None,
         "encrypt_ms_per_step": round(en_ms / args.steps, 2),
         "train_only_samples_per_s": round(n / (train_kernel_ms / 1000.0), 3) if train_kernel_ms else None,
         "encrypt_only_samples_per_s": round(n / (en_ms / args.steps / 1000.0), 3) if en_ms else None,
@@ -328,13 +334,19 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     inf_ms, inf_launch, inf_xp = ctx.profile_read("infer")
+    cs_ms, _, cs_words = ctx.profile_read("class_sums")
     ctx.profile(False)
     pred = CL.pd_act_predict(cells, "bin")
     acc = float((pred == np.asarray(yte[:nt])).mean())
+    N, nq = ctx.N, ctx.nq
+    tops = inf_xp * ops_per_xp(N, nq) / (inf_ms / 1000.0) / 1e12 if inf_ms else 0.0
     return {
         "samples_per_s": round(nt / dt, 3),
         "infer_kernel_samples_per_s": round(nt / (inf_ms / 1000.0), 3) if inf_ms else None,
         "xp_per_s": round(inf_xp / (inf_ms / 1000.0), 1) if inf_ms else None,
+        "roofline": {"bound": "alu", "kernel": "k_infer", "achieved": round(tops, 3),
+                     "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOPS(int32)",
+                     "frac": round(tops / PEAK_INT32_TOPS, 4)},
         "n_test": nt, "pd_act": "bin", "test_accuracy": round(acc, 4),
     }
 
@@ -407,7 +419,7 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     for j, J in enumerate(jobs):
         groups.setdefault(J["N"], []).append((j, J))
     out = {"jobs": len(jobs), "scale": scale, "samples": 0, "xp": 0.0, "batched_ms": 0.0, "single_ms": 0.0,
-           "plan_ms": 0.0, "plan_max_pieces": 0, "kernel_ms": {}, "bit_identical": True}
+           "plan_ms": 0.0, "plan_max_pieces": 0, "kernel_ms": {}, "ops": 0.0, "bit_identical": True}
     for N, members in sorted(groups.items()):
         nq = 2 if N == 2048 else 3
         ctx = HW.Context(N, nq, 4096)
@@ -453,7 +465,9 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
             out["single_ms"] += e1.elapsed_time(e2)
             out["plan_ms"] += e2.elapsed_time(e3)
             out["plan_max_pieces"] = max(out["plan_max_pieces"], plan.max_pieces)
-            out["xp"] += ctx.profile_read("train_batch")[2]
+            xpb = ctx.profile_read("train_batch")[2]
+            out["xp"] += xpb
+            out["ops"] += xpb * ops_per_xp(N, nq)
             for k in ("train_batch", "reduce_batch", "train", "reduce", "batch_plan"):
                 out["kernel_ms"][k] = out["kernel_ms"].get(k, 0.0) + ctx.profile_read(k)[0]
             ctx.profile(False)
@@ -477,6 +491,15 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     out["batched_samples_per_s"] = round(out["samples"] / (out["batched_ms"] / 1000.0), 2)
     out["single_job_samples_per_s"] = round(out["samples"] / (out["single_ms"] / 1000.0), 2)
     out["batched_xp_per_s"] = round(out["xp"] / (out["batched_ms"] / 1000.0), 1)
+    # k_train_batch against the int32 peak: external products of each ring
+    # degree x that degree's op model / the persistent kernel's time
+    tb = out["kernel_ms"].get("train_batch", 0.0)
+    if tb:
+        tops = out["ops"] / (tb / 1000.0) / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": "k_train_batch", "achieved": round(tops, 3),
+                           "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOPS(int32)",
+                           "frac": round(tops / PEAK_INT32_TOPS, 4)}
+    del out["ops"]
     out["speedup"] = round(out["single_ms"] / out["batched_ms"], 3)
     out["plan_speedup"] = round(out["single_ms"] / out["plan_ms"], 3)
     out["batched_ms"] = round(out["batched_ms"], 1)

@@ -76,6 +76,9 @@ def lib():
                 "orc_ivp_pruned": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.c_uint32, C.c_uint32, u32p, u32p]),
                 "orc_leaf_row": (C.c_int32, [C.c_uint32, C.c_uint32, C.c_uint32]),
                 "orc_rlwe_add_n": (None, [C.c_void_p, u32p, u32p, C.c_uint64, u32p]),
+                "orc_pks_keygen": (None, [C.c_void_p, i32p, C.c_uint64, C.c_uint32, C.c_uint32, u32p]),
+                "orc_pks_partial": (None, [C.c_void_p, u32p, u32p, C.c_uint32, C.c_uint32, C.c_uint32, u32p]),
+                "orc_pks_finish": (None, [C.c_void_p, u32p, C.c_uint32, u32p, u32p]),
                 "orc_extract_lwe0": (None, [C.c_void_p, u32p, u32p]),
                 "orc_vp": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_uint8), C.c_uint32, u32p, u32p]),
                 "orc_permutation": (None, [C.c_uint64, C.c_uint32, u32p]),
@@ -377,6 +380,40 @@ class Ctx:
         assert x.shape == y.shape and x.size % (2 * self.nq * self.N) == 0
         out = np.zeros_like(x)
         lib().orc_rlwe_add_n(self.h, _p(x, u32p), _p(y, u32p), x.size // (2 * self.nq * self.N), _p(out, u32p))
+        return out
+
+    # -- PackingKeySwitching ----------------------------------------------
+    def pks_keygen(self, s, seed: int, threads=None) -> np.ndarray:
+        """K[j][r] = RLWE_s(s_j G_r) for j < N, r < D: [N][D][2][nq][N]
+        (rows are independent; ranges of j go to threads)"""
+        s = np.ascontiguousarray(s, np.int32)
+        K = np.zeros((self.N, self.D, 2, self.nq, self.N), np.uint32)
+        ranges = [(j0, min(self.N, j0 + 64)) for j0 in range(0, self.N, 64)]
+        _parallel(lambda r: lib().orc_pks_keygen(self.h, _p(s, i32p), seed, r[0], r[1], _p(K, u32p)), ranges,
+                  threads)
+        return K
+
+    def pack_lwe(self, K, lwes, threads=None) -> np.ndarray:
+        """one RLWE whose phase is sum_i phase(lwes[i]) X^i (k = len(lwes) <= N);
+        the sum over key coordinates is split over threads"""
+        K = np.ascontiguousarray(K, np.uint32)
+        lwes = np.ascontiguousarray(lwes, np.uint32)
+        k = lwes.shape[0]
+        assert k <= self.N and lwes.shape[1:] == (self.nq, self.N + 1)
+        step = 64
+        ranges = [(j0, min(self.N, j0 + step)) for j0 in range(0, self.N, step)]
+        parts = [self.rlwe() for _ in ranges]
+
+        def run(t):
+            j0, j1 = ranges[t]
+            lib().orc_pks_partial(self.h, _p(K, u32p), _p(lwes, u32p), k, j0, j1, _p(parts[t], u32p))
+
+        _parallel(run, range(len(ranges)), threads)
+        acc = parts[0]
+        for p in parts[1:]:
+            acc = self.rlwe_add(acc, p)
+        out = self.rlwe()
+        lib().orc_pks_finish(self.h, _p(lwes, u32p), k, _p(acc, u32p), _p(out, u32p))
         return out
 
     def lwe_add(self, x, y) -> np.ndarray:

@@ -1022,6 +1022,88 @@ void orc_lwe_add(const orc_ctx* c, const uint32_t* x, const uint32_t* y, uint32_
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* PackingKeySwitching (Sec. 2.5.1; the PD-act return value of Alg. 7)        */
+/* ------------------------------------------------------------------------ */
+/* k LWE ciphertexts (a^(i), b^(i)), phase_i = b^(i) - sum_j a^(i)_j s_j under
+ * the RLWE key's coefficients (the key ExtractLWE leaves them under), become
+ * one RLWE whose phase is sum_i phase_i X^i (plus key-switching noise).
+ * Key: K[j][r] = RLWE_s(s_j G_r) for j < N and the RNS gadget rows r < D
+ * (G_r = base^t in residue g for r = g digits + t, 0 in the others), each a
+ * row drawn like an RGSW row (seed, ciphertext j, D rows, a by its
+ * evaluations).  Packing: with P_{j,r}(X) = sum_i d_r(a^(i)_j) X^i (d_r: the
+ * balanced digit of the external product's decomposition),
+ *   out = (0, sum_i b^(i) X^i) - sum_{j,r} P_{j,r} K[j][r],
+ * whose phase is sum_i X^i (b^(i) - sum_j (sum_r d_r(a^(i)_j) G_r) s_j). */
+
+/* the balanced base-2^log_base digits of one centered residue (as orc_decompose) */
+static void value_digits(const orc_ctx* c, int64_t v, int64_t q, int32_t* d) {
+  int64_t B = 1ll << c->log_base;
+  if (v > (q - 1) / 2) v -= q;
+  for (uint32_t t = 0; t + 1 < c->digits; ++t) {
+    int64_t x = ((v % B) + B) % B;
+    if (x >= B / 2) x -= B;
+    d[t] = (int32_t)x;
+    v = (v - x) / B;
+  }
+  d[c->digits - 1] = (int32_t)v;
+}
+
+/* rows j_lo <= j < j_hi of the key (K holds all N x D rows) */
+void orc_pks_keygen(const orc_ctx* c, const int32_t* s, uint64_t seed, uint32_t j_lo, uint32_t j_hi, uint32_t* K) {
+  uint32_t N = c->N, nq = c->nq, D = c->D;
+  size_t rw = rlwe_words(c);
+  for (uint32_t j = j_lo; j < j_hi; ++j)
+    for (uint32_t r = 0; r < D; ++r) {
+      uint32_t* row = K + ((size_t)j * D + r) * rw;
+      enc_row(c, s, NULL, seed, j, D, r, 1, row);
+      uint32_t g = r / c->digits, t = r % c->digits;
+      uint64_t q = c->q[g];
+      uint64_t G = powmod(1ull << c->log_base, t, q);
+      uint64_t m = s[j] == 0 ? 0 : (s[j] > 0 ? G : q - G);
+      uint32_t* b0 = row + ((size_t)nq + g) * N;
+      b0[0] = (uint32_t)addmod(b0[0], m, q);
+    }
+}
+
+/* acc (+)= sum_{j in [j_lo, j_hi), r} P_{j,r} K[j][r]; lwe: [k][nq][N+1] */
+void orc_pks_partial(const orc_ctx* c, const uint32_t* K, const uint32_t* lwe, uint32_t k, uint32_t j_lo,
+                     uint32_t j_hi, uint32_t* acc) {
+  uint32_t N = c->N, nq = c->nq, D = c->D;
+  size_t rw = rlwe_words(c);
+  int32_t* P = (int32_t*)calloc((size_t)c->digits * N, sizeof(int32_t));
+  int32_t* dg = (int32_t*)malloc(sizeof(int32_t) * c->digits);
+  for (uint32_t j = j_lo; j < j_hi; ++j)
+    for (uint32_t g = 0; g < nq; ++g) {
+      for (uint32_t i = 0; i < k; ++i) {
+        value_digits(c, lwe[((size_t)i * nq + g) * (N + 1) + j], (int64_t)c->q[g], dg);
+        for (uint32_t t = 0; t < c->digits; ++t) P[(size_t)t * N + i] = dg[t];
+      }
+      for (uint32_t t = 0; t < c->digits; ++t) {
+        const uint32_t* row = K + ((size_t)j * D + g * c->digits + t) * rw;
+        for (uint32_t part = 0; part < 2; ++part)
+          for (uint32_t ip = 0; ip < nq; ++ip)
+            mul_acc_small(c, ip, P + (size_t)t * N, row + ((size_t)part * nq + ip) * N,
+                          acc + ((size_t)part * nq + ip) * N);
+      }
+    }
+  free(P);
+  free(dg);
+}
+
+/* out = (0, sum_i b^(i) X^i) - acc */
+void orc_pks_finish(const orc_ctx* c, const uint32_t* lwe, uint32_t k, const uint32_t* acc, uint32_t* out) {
+  uint32_t N = c->N, nq = c->nq;
+  for (uint32_t ip = 0; ip < nq; ++ip) {
+    uint64_t q = c->q[ip];
+    for (uint32_t x = 0; x < N; ++x) {
+      uint64_t b = x < k ? lwe[((size_t)x * nq + ip) * (N + 1) + N] : 0;
+      out[(size_t)ip * N + x] = (uint32_t)submod(0, acc[(size_t)ip * N + x], q);
+      out[((size_t)nq + ip) * N + x] = (uint32_t)submod(b, acc[((size_t)nq + ip) * N + x], q);
+    }
+  }
+}
+
 /* exported sizes for the Python wrapper */
 uint64_t orc_rlwe_words(const orc_ctx* c) { return rlwe_words(c); }
 uint64_t orc_rgsw_words(const orc_ctx* c) { return rgsw_words(c); }

@@ -1,0 +1,85 @@
+"""Pins of the oracle's PackingKeySwitching (Sec. 2.5.1 building block; the
+PD-act return value of Alg. 7): with a noiseless key the packed RLWE's phase
+is exactly sum_i phase_i X^i, computed here independently from the LWE
+definition; with a real key the packed RLWE decrypts to the LWE messages;
+key rows decrypt to s_j G_r."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+
+def _lwe_phases(c, s, lwes):
+    """phase_i = b_i - sum_j a_ij s_j mod q_g for every prime g (Python ints)"""
+    k = lwes.shape[0]
+    out = np.zeros((c.nq, k), np.int64)
+    for g, q in enumerate(c.primes):
+        for i in range(k):
+            a = [int(x) for x in lwes[i, g, :c.N]]
+            acc = int(lwes[i, g, c.N])
+            for j in range(c.N):
+                acc -= a[j] * int(s[j])
+            out[g, i] = acc % q
+    return out
+
+
+@pytest.mark.parametrize("N,nq", [(64, 2), (32, 3), (1024, 1)])
+def test_noiseless_key_packs_phases_exactly(N, nq):
+    c = O.Ctx(N, nq, 16)
+    s = c.keygen(3)
+    rng = np.random.default_rng(N + nq)
+    k = N // 2 + 3
+    lwes = np.zeros((k, nq, N + 1), np.uint32)
+    for g, q in enumerate(c.primes):
+        lwes[:, g, :] = rng.integers(0, q, (k, N + 1))
+    K = np.zeros((N, c.D, 2, nq, N), np.uint32)  # (0, s_j G_r): no mask, no error
+    for j in range(N):
+        for r in range(c.D):
+            g, t = divmod(r, 5)
+            q = c.primes[g]
+            K[j, r, 1, g, 0] = (int(s[j]) * pow(64, t, q)) % q
+    out = c.pack_lwe(K, lwes)
+    assert not out[0].any()
+    want = _lwe_phases(c, s, lwes)
+    for g in range(nq):
+        assert np.array_equal(out[1, g, :k].astype(np.int64), want[g]), g
+        assert not out[1, g, k:].any()
+
+
+@pytest.mark.parametrize("N,nq,p", [(1024, 1, 64), (64, 2, 256)])
+def test_packing_decrypts_to_lwe_messages(N, nq, p):
+    c = O.Ctx(N, nq, p)
+    s = c.keygen(4)
+    K = c.pks_keygen(s, 77)
+    rng = np.random.default_rng(p)
+    k = 24
+    msgs = rng.integers(0, p, k)
+    lwes = []
+    for i, m in enumerate(msgs):
+        mu = rng.integers(0, p, N).astype(np.uint64)
+        mu[0] = m
+        lwes.append(c.extract_lwe0(c.enc_rlwe(s, mu, 5, i)))
+    lwes = np.stack(lwes)
+    assert [c.dec_lwe(s, x) for x in lwes] == list(msgs)
+    out = c.pack_lwe(K, lwes)
+    dec = c.dec_rlwe(s, out)
+    assert np.array_equal(dec[:k], msgs.astype(np.uint64)) and not dec[k:].any()
+
+
+def test_key_rows_decrypt_to_gadget_times_secret():
+    c = O.Ctx(64, 2, 16)
+    s = c.keygen(6)
+    K = c.pks_keygen(s, 9)
+    for j in (0, 5, 63):
+        for r in (0, 4, 7):
+            g, t = divmod(r, 5)
+            for i, q in enumerate(c.primes):
+                a = K[j, r, 0, i].astype(np.uint64)
+                sl = np.array([(int(x) + q) % q for x in s], np.uint64)
+                ph = (K[j, r, 1, i].astype(np.int64) - c.negmul(i, a, sl).astype(np.int64)) % q
+                ph = np.where(ph > q // 2, ph - q, ph)
+                want = np.zeros(64, np.int64)
+                if i == g:
+                    want[0] = int(s[j]) * pow(64, t, q)
+                    want[0] = want[0] - q if want[0] > q // 2 else want[0]
+                assert np.abs(ph - want).max() <= 41, (j, r, i)

@@ -334,8 +334,30 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     inf_ms, inf_launch, inf_xp = ctx.profile_read("infer")
-    cs_ms, _, cs_words = ctx.profile_read("class_sums")
     ctx.profile(False)
+    # PackingKeySwitching of the last chunk's scores: l k0 LWE -> one RLWE per
+    # sample (when l k0 <= N), decrypting to the same cells
+    packed = None
+    k = l * k0
+    if k <= ctx.N:
+        key = torch.empty(ctx.pks_key_words, dtype=torch.int32, device=dev)
+        ctx.pks_keygen(sk, seeds["key"] + 100, key)
+        m = nt - (nt - 1) // chunk * chunk
+        out = torch.empty(m, ctx.rlwe_words, dtype=torch.int32, device=dev)
+        ctx.pack_lwe(key, scores, k, m, out)  # warm-up
+        ctx.profile(True)
+        ctx.profile_reset()
+        for _ in range(3):
+            ctx.pack_lwe(key, scores, k, m, out)
+        pk_ms, _, pk_groups = ctx.profile_read("pack_lwe")
+        ctx.profile(False)
+        pdec = torch.empty(m, ctx.N, dtype=torch.int64, device=dev)
+        ctx.decrypt_rlwe(sk, out, m, pdec)
+        same = np.array_equal(pdec.cpu().numpy()[:, :k].reshape(m, l, k0), cells[nt - m:])
+        packed = {"lwe_per_sample": k, "ms_per_sample": round(pk_ms / pk_groups, 3),
+                  "bytes_per_sample": ctx.rlwe_words * 4, "lwe_bytes_per_sample": k * ctx.lwe_words * 4,
+                  "decrypts_equal": bool(same), "key_mib": round(ctx.pks_key_words * 4 / 2**20, 1)}
+        del key, out
     pred = CL.pd_act_predict(cells, "bin")
     acc = float((pred == np.asarray(yte[:nt])).mean())
     N, nq = ctx.N, ctx.nq
@@ -348,6 +370,7 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
                      "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOPS(int32)",
                      "frac": round(tops / PEAK_INT32_TOPS, 4)},
         "n_test": nt, "pd_act": "bin", "test_accuracy": round(acc, 4),
+        "packing": packed,
     }
 
 

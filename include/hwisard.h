@@ -190,6 +190,29 @@ hw_status hw_wisard_infer_encrypted(hw_ctx* ctx, const hw_wisard_shape* shape,
                                     uint64_t n, uint32_t* ram_scores_dev,
                                     uint32_t* class_scores_dev, hipStream_t stream);
 
+/* PackingKeySwitching (Sec. 2.5.1; Alg. 7 returns the PD-act scores packed
+ * by it): k LWE ciphertexts (a^(i), b^(i)) under the RLWE key's coefficients
+ * (as ExtractLWE leaves them) become one RLWE whose phase is sum_i phase_i X^i,
+ * so it decrypts (hw_decrypt_rlwe) to the k messages in coefficients 0..k-1
+ * and zeros after.
+ * Key: K[j][r] = RLWE_s(s_j G_r) for j < N and the D = 5 nq RNS gadget rows
+ * (G_r = 64^t in residue g for r = 5 g + t, 0 in the others).  Row (j, r) is
+ * drawn like row r of RGSW ciphertext j with D rows (a by its evaluations,
+ * see hw_encrypt_rgsw_bits) from `seed`.  Device layout [N][D][2][nq][N]
+ * uint32 in the evaluation domain: N D 8 nq N bytes (640 MiB at N = 2048,
+ * nq = 2), caller-owned.  hw_pks_key_export_canonical writes the same rows in
+ * the coefficient domain (tests).
+ * Packing: out = (0, sum_i b^(i) X^i) - sum_{j,r} P_{j,r} K[j][r], where
+ * P_{j,r} = sum_i d_r(a^(i)_j) X^i collects the balanced base-64 digits of the
+ * external product's decomposition.  lwe_dev: [count][k] LWE; out_dev: [count]
+ * RLWE (coefficient domain); 1 <= k <= N (HW_EINVAL otherwise). */
+hw_status hw_pks_keygen(hw_ctx* ctx, const int32_t* sk_dev, uint64_t seed, uint32_t* key_dev,
+                        hipStream_t stream);
+hw_status hw_pks_key_export_canonical(hw_ctx* ctx, const uint32_t* key_dev, uint32_t* out_dev,
+                                      hipStream_t stream);
+hw_status hw_pack_lwe(hw_ctx* ctx, const uint32_t* key_dev, const uint32_t* lwe_dev, uint32_t k,
+                      uint64_t count, uint32_t* out_dev, hipStream_t stream);
+
 /* Merge of models trained apart (Sec. 3.7.2: Integer WiSARD models of
  * federated entities are merged by adding their RAMs; the merged model is
  * the one centralised training on the union would give, bit for bit, since
@@ -363,7 +386,8 @@ const char* hw_tune_variant_name(const char* kernel, int variant);
  * bracketed by a pair of HIP events recorded on the caller's stream.  Kernel
  * names: "train", "reduce", "train_batch", "reduce_batch", "batch_plan" (a whole
  * plan replay), "infer", "class_sums", "encrypt_rgsw", "encrypt_rlwe",
- * "decrypt_rlwe", "decrypt_lwe", "xp", "ntt", "rlwe_add". */
+ * "decrypt_rlwe", "decrypt_lwe", "xp", "ntt", "rlwe_add",
+ * "encrypt_pks", "pack_lwe". */
 hw_status hw_profile_enable(hw_ctx* ctx, int enable);
 
 /* Waits for the recorded events and returns, for kernel `name`, the summed

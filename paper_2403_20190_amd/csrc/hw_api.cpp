@@ -665,6 +665,59 @@ extern "C" hw_status hw_wisard_infer_encrypted(hw_ctx* c, const hw_wisard_shape*
   return ok();
 }
 
+// ---------------------------------------------------------------------------
+// PackingKeySwitching
+// ---------------------------------------------------------------------------
+
+extern "C" hw_status hw_pks_keygen(hw_ctx* c, const int32_t* sk, uint64_t seed, uint32_t* key, hipStream_t st) {
+  CHECK(enter(c));
+  if (!sk || !key) return fail(HW_EINVAL, "null buffer");
+  CHECK(sk_hat(c, sk, st));
+  hw::EncArgs A{};
+  A.sk = sk;
+  A.sk_hat = c->d_skhat;
+  A.out = key;
+  A.seed = seed;
+  A.log_base = c->prm.log_base;
+  HIP_TRY(timed(c, "encrypt_pks", (double)c->prm.N * 5 * c->prm.nq, st,
+                [&] { return hw::launch_enc_pks(c->logN, c->prm.nq, c->tabs, c->cdt, A, st); }));
+  return ok();
+}
+
+extern "C" hw_status hw_pks_key_export_canonical(hw_ctx* c, const uint32_t* key, uint32_t* out, hipStream_t st) {
+  CHECK(enter(c));
+  if (!key || !out) return fail(HW_EINVAL, "null buffer");
+  if (key == out) return fail(HW_EINVAL, "output must not alias input");
+  // N x D rows have the row layout of N / 2 RGSW ciphertexts (2 D rows each)
+  HIP_TRY(hw::launch_rgsw_export(c->logN, c->prm.nq, c->tabs, key, c->prm.N / 2, out, st));
+  return ok();
+}
+
+extern "C" hw_status hw_pack_lwe(hw_ctx* c, const uint32_t* key, const uint32_t* lwe, uint32_t k, uint64_t count,
+                                 uint32_t* out, hipStream_t st) {
+  CHECK(enter(c));
+  if (count == 0) return ok();
+  if (!key || !lwe || !out) return fail(HW_EINVAL, "null buffer");
+  if (k < 1 || k > c->prm.N) return fail(HW_EINVAL, "k = %u out of range [1, N = %u]", k, c->prm.N);
+  const uint32_t nblk = hw::pks_blocks(c->logN);
+  const size_t per_group = (size_t)c->prm.nq * nblk * 2 * c->prm.N * 4;
+  uint64_t n_sub = std::max<uint64_t>(1, c->ws_budget / per_group);
+  n_sub = std::min<uint64_t>(std::min<uint64_t>(n_sub, count), 65535);
+  CHECK(ensure_ws(c, n_sub * per_group));
+  for (uint64_t c0 = 0; c0 < count; c0 += n_sub) {
+    const uint64_t m = std::min<uint64_t>(n_sub, count - c0);
+    hw::PksArgs A{};
+    A.key = key;
+    A.lwe = lwe + c0 * k * lwe_words(c);
+    A.part = static_cast<uint32_t*>(c->d_ws);
+    A.out = out + c0 * rlwe_words(c);
+    A.k = k;
+    HIP_TRY(timed(c, "pack_lwe", (double)m, st,
+                  [&] { return hw::launch_pks(c->logN, c->prm.nq, c->tabs, A, (uint32_t)m, st); }));
+  }
+  return ok();
+}
+
 extern "C" hw_status hw_rlwe_add(hw_ctx* c, uint32_t* dst, const uint32_t* src, uint64_t count, hipStream_t st) {
   CHECK(enter(c));
   if (count == 0) return ok();

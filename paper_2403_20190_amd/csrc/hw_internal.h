@@ -96,6 +96,14 @@ struct BatchArgs {
   uint64_t rgsw_words;
 };
 
+struct PksArgs {
+  const uint32_t* key;      // [N][D][2][NQ][N] evaluation domain
+  const uint32_t* lwe;      // [count][k] LWE ([NQ][N+1] each)
+  uint32_t* part;           // [count][NQ][blocks][2][N] evaluation-domain partial sums
+  uint32_t* out;            // [count] RLWE
+  uint32_t k;               // LWE per group, <= N
+};
+
 struct SumArgs {
   const uint32_t* scores;   // [n][l][k0] LWE
   uint32_t* sums;           // [n][l] LWE
@@ -130,6 +138,9 @@ hipError_t launch_reduce_batch(const Tabs& T, const BJob* jobs, uint32_t njobs, 
                                uint32_t N, uint32_t nq, const uint32_t* acc, hipStream_t st);
 hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int occ, hipStream_t st);
 hipError_t launch_class_sums(const Tabs& T, const SumArgs& A, hipStream_t st);
+hipError_t launch_enc_pks(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, hipStream_t st);
+uint32_t pks_blocks(int logN);  // key-coordinate blocks of the packing (partial sums per group and prime)
+hipError_t launch_pks(int logN, int nq, const Tabs& T, const PksArgs& A, uint32_t count, hipStream_t st);
 hipError_t launch_rlwe_add(const Tabs& T, uint32_t* dst, const uint32_t* src, uint64_t words, uint32_t N, uint32_t nq,
                            hipStream_t st);
 

@@ -210,6 +210,61 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncA
   }
 }
 
+// PackingKeySwitching key rows K[j][r] = RLWE_s(s_j G_r) in the evaluation
+// domain, drawn like RGSW rows (ciphertext j, D rows): b_hat = a_hat * s_hat +
+// NTT(e) + s_j G_r, the constant s_j 64^t added at every point of prime g
+// for r = 5 g + t.  One workgroup per row.
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_pks(Tabs T, Cdt cdt, EncArgs A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  __shared__ __attribute__((aligned(16))) uint32_t stage[1 << LOGN];
+  __shared__ uint64_t tab[42];
+  constexpr int N = 1 << LOGN, D = 5 * NQ;
+  const uint32_t t = threadIdx.x, r = blockIdx.x, j = blockIdx.y;
+  if (t < 42) tab[t] = cdt.T[t];
+  const uint64_t rid = (uint64_t)j * D + r;
+  const int32_t sj = A.sk[j];
+  int32_t ev[8];
+  gen_gauss<LOGN>(A.seed, rid * (N / 2), tab, stage, t, ev);
+  const uint32_t gi = r / 5, gt = r % 5;
+  uint32_t* row = A.out + rid * (size_t)(2 * NQ * N);
+  uint32_t xc = 0;
+#pragma unroll 1
+  for (int i = 0; i < NQ; ++i) {
+    const PrimeTab P = T.pt[i];
+    __syncthreads();
+    load_tw_lds<LOGN>(twl, T.fwd[i], t);
+    const uint4* sp = reinterpret_cast<const uint4*>(A.sk_hat + (size_t)i * N + (t << 3));
+    const uint4 s0 = sp[0], s1 = sp[1];
+    const uint32_t sh[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+    uint32_t xa[8], xe[8];
+    const uint64_t blk0 = (rid * NQ + i) * (N / 2) + 4 * t;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      uint64_t d0, d1;
+      draw_pair(A.seed, DOM_ENC_A, blk0 + f, d0, d1);
+      xa[2 * f] = red64(d0, P);
+      xa[2 * f + 1] = red64(d1, P);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) xe[e] = ev[e] < 0 ? (uint32_t)(ev[e] + (int32_t)P.q) : (uint32_t)ev[e];
+    ntt_fwd<LOGN>(xe, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
+    const uint32_t G = gi == (uint32_t)i ? (1u << (A.log_base * gt)) : 0u;
+    const uint32_t g = sj == 0 || G == 0 ? 0u : (sj > 0 ? G : P.q - G);
+    uint32_t ob[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      ob[e] = addq(addq(mulq(xa[e], sh[e], P), red4q(xe[e], P.q, P.two_q), P.q), g, P.q);
+    uint4* pa = reinterpret_cast<uint4*>(row + (size_t)i * N + (t << 3));
+    uint4* pb = reinterpret_cast<uint4*>(row + (size_t)(NQ + i) * N + (t << 3));
+    pa[0] = make_uint4(xa[0], xa[1], xa[2], xa[3]);
+    pa[1] = make_uint4(xa[4], xa[5], xa[6], xa[7]);
+    pb[0] = make_uint4(ob[0], ob[1], ob[2], ob[3]);
+    pb[1] = make_uint4(ob[4], ob[5], ob[6], ob[7]);
+  }
+}
+
 // RLWE encryption in the coefficient domain: b = a*s + Delta*msg + e
 template <int LOGN, int NQ>
 __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rlwe(Tabs T, Cdt cdt, EncArgs A) {
@@ -828,6 +883,137 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
   }
 }
 
+// ---------------------------------------------------------------------------
+// PackingKeySwitching: count groups of k LWE -> one RLWE each
+// ---------------------------------------------------------------------------
+// out = (0, sum_i b_i X^i) - sum_{j,r} P_{j,r} K[j][r] with P_{j,r} = sum_i
+// d_r(a_{i,j}) X^i.  k_pks_partial: one workgroup per (group, output prime,
+// block of PKS_J key coordinates) builds each P_{j,r} in registers (thread t
+// holds i = t + T e), transforms it and multiply-accumulates it with the
+// evaluation-domain key rows; the block's partial sums (a and b parts) go to
+// the workspace in the evaluation domain.  k_pks_finish adds the blocks,
+// transforms back and subtracts from (0, sum_i b_i X^i).
+constexpr uint32_t PKS_J = 32;
+
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_pks_partial(
+    Tabs T, PksArgs A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr int N = 1 << LOGN, TT = N / 8, D = 5 * NQ;
+  constexpr size_t ROW = (size_t)2 * NQ * N, LW = (size_t)NQ * (N + 1);
+  const uint32_t t = threadIdx.x, ip = blockIdx.y, jb = blockIdx.z;
+  const uint64_t c = blockIdx.x;  // group fastest: concurrent workgroups share the key block in L2
+  const uint32_t* lwe = A.lwe + c * A.k * LW;
+  const PrimeTab P = T.pt[ip];
+  load_tw_lds<LOGN>(twl, T.fwd[ip], t);  // read after the first exchange's barrier
+  uint64_t acc_a[8], acc_b[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) acc_a[e] = acc_b[e] = 0;
+  int cnt = 0;
+  uint32_t xc = 0;
+  const uint32_t j1 = (jb + 1) * PKS_J < (uint32_t)N ? (jb + 1) * PKS_J : (uint32_t)N;
+#pragma unroll 1
+  for (uint32_t j = jb * PKS_J; j < j1; ++j) {
+#pragma unroll 1
+    for (int g = 0; g < NQ; ++g) {
+      const uint32_t qg = T.pt[g].q;
+      int32_t v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t i = t + TT * e;
+        const uint32_t r = i < A.k ? lwe[(size_t)i * LW + (size_t)g * (N + 1) + j] : 0u;
+        v[e] = r > (qg - 1) / 2 ? (int32_t)(r - qg) : (int32_t)r;
+      }
+#pragma unroll 1
+      for (int dt = 0; dt < 5; ++dt) {
+        const uint4* kra = reinterpret_cast<const uint4*>(A.key + ((size_t)j * D + g * 5 + dt) * ROW + (size_t)ip * N);
+        const uint4* krb = kra + (size_t)NQ * N / 4;
+        const uint4 ka0 = kra[2 * t], ka1 = kra[2 * t + 1];
+        const uint4 kb0 = krb[2 * t], kb1 = krb[2 * t + 1];
+        uint32_t x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          int32_t d;
+          if (dt < 4) {
+            d = ((v[e] + 32) & 63) - 32;
+            v[e] = (v[e] - d) >> 6;
+          } else {
+            d = v[e];
+          }
+          x[e] = d < 0 ? (uint32_t)(d + (int32_t)P.q) : (uint32_t)d;
+        }
+        ntt_fwd<LOGN>(x, T.fwd[ip], twl, P.q, P.two_q, lds, xc, t);
+        const uint32_t ka[8] = {ka0.x, ka0.y, ka0.z, ka0.w, ka1.x, ka1.y, ka1.z, ka1.w};
+        const uint32_t kb[8] = {kb0.x, kb0.y, kb0.z, kb0.w, kb1.x, kb1.y, kb1.z, kb1.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t xr = red4q(x[e], P.q, P.two_q);
+          acc_a[e] += (uint64_t)xr * ka[e];
+          acc_b[e] += (uint64_t)xr * kb[e];
+        }
+        if (++cnt == 15) {
+          cnt = 0;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            acc_a[e] = red64(acc_a[e], P);
+            acc_b[e] = red64(acc_b[e], P);
+          }
+        }
+      }
+    }
+  }
+  uint32_t* o = A.part + ((c * NQ + ip) * gridDim.z + jb) * (size_t)(2 * N);
+  uint4* oa = reinterpret_cast<uint4*>(o + (t << 3));
+  uint4* ob = reinterpret_cast<uint4*>(o + N + (t << 3));
+  oa[0] = make_uint4(red64(acc_a[0], P), red64(acc_a[1], P), red64(acc_a[2], P), red64(acc_a[3], P));
+  oa[1] = make_uint4(red64(acc_a[4], P), red64(acc_a[5], P), red64(acc_a[6], P), red64(acc_a[7], P));
+  ob[0] = make_uint4(red64(acc_b[0], P), red64(acc_b[1], P), red64(acc_b[2], P), red64(acc_b[3], P));
+  ob[1] = make_uint4(red64(acc_b[4], P), red64(acc_b[5], P), red64(acc_b[6], P), red64(acc_b[7], P));
+}
+
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) void k_pks_finish(Tabs T, PksArgs A, uint32_t nblk) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  constexpr size_t LW = (size_t)NQ * (N + 1);
+  const uint32_t t = threadIdx.x, ip = blockIdx.x;
+  const uint64_t c = blockIdx.y;
+  const PrimeTab P = T.pt[ip];
+  const uint32_t* part = A.part + (c * NQ + ip) * (size_t)nblk * (2 * N);
+  uint64_t sa[8], sb[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) sa[e] = sb[e] = 0;
+#pragma unroll 1
+  for (uint32_t b = 0; b < nblk; ++b) {  // at most 128 words below 2^30 each: no overflow
+    const uint4* pa = reinterpret_cast<const uint4*>(part + (size_t)b * 2 * N + (t << 3));
+    const uint4* pb = reinterpret_cast<const uint4*>(part + (size_t)b * 2 * N + N + (t << 3));
+    const uint4 a0 = pa[0], a1 = pa[1], b0 = pb[0], b1 = pb[1];
+    sa[0] += a0.x; sa[1] += a0.y; sa[2] += a0.z; sa[3] += a0.w;
+    sa[4] += a1.x; sa[5] += a1.y; sa[6] += a1.z; sa[7] += a1.w;
+    sb[0] += b0.x; sb[1] += b0.y; sb[2] += b0.z; sb[3] += b0.w;
+    sb[4] += b1.x; sb[5] += b1.y; sb[6] += b1.z; sb[7] += b1.w;
+  }
+  uint32_t ha[8], hb[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    ha[e] = red64(sa[e], P);
+    hb[e] = red64(sb[e], P);
+  }
+  uint32_t xc = 0;
+  ntt_inv<LOGN>(ha, T.inv[ip], P, lds, xc, t);
+  ntt_inv<LOGN>(hb, T.inv[ip], P, lds, xc, t);
+  const uint32_t* lwe = A.lwe + c * A.k * LW;
+  uint32_t* out = A.out + c * (size_t)(2 * NQ * N);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t i = t + TT * e;
+    const uint32_t b = i < A.k ? lwe[(size_t)i * LW + (size_t)ip * (N + 1) + N] : 0u;
+    out[(size_t)ip * N + i] = subq(0u, ha[e], P.q);
+    out[(size_t)(NQ + ip) * N + i] = subq(b, hb[e], P.q);
+  }
+}
+
 // dst += src over `words` words of RLWE ciphertexts (2 nq N words each),
 // residue by residue; a thread adds four consecutive words (16-byte accesses)
 __global__ __launch_bounds__(256) void k_rlwe_add(Tabs T, uint32_t* __restrict__ dst,
@@ -1085,6 +1271,27 @@ hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int
   const dim3 grid = A.map == 0 ? dim3(A.k0, A.l, A.nsub) : dim3((uint32_t)((G + 7) / 8 * 8));
   HW_DISPATCH_OCC(logN, nq, occ,
                   hipLaunchKernelGGL((k_infer<LN, NQ, OC>), grid, dim3(Geo<LN>::T), 0, st, T, A));
+  return hipGetLastError();
+}
+
+hipError_t launch_enc_pks(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, hipStream_t st) {
+  const uint32_t N = 1u << logN;
+  HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_pks<LN, NQ>), dim3(5 * NQ, N), dim3(Geo<LN>::T), 0, st, T, cdt, A));
+  return hipGetLastError();
+}
+
+uint32_t pks_blocks(int logN) { return ((1u << logN) + PKS_J - 1) / PKS_J; }
+
+hipError_t launch_pks(int logN, int nq, const Tabs& T, const PksArgs& A, uint32_t count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  const uint32_t nblk = pks_blocks(logN);
+  HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_pks_partial<LN, NQ>), dim3(count, NQ, nblk), dim3(Geo<LN>::T), 0, st,
+                                            T, A));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_pks_finish<LN, NQ>), dim3(NQ, count), dim3(Geo<LN>::T), 0, st, T, A,
+                                            nblk));
   return hipGetLastError();
 }
 

@@ -85,6 +85,9 @@ _SIG = {
     "hw_wisard_train_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_wisard_infer_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_rlwe_add": [_vp, _vp, _vp, _u64, _vp],
+    "hw_pks_keygen": [_vp, _vp, _u64, _vp, _vp],
+    "hw_pks_key_export_canonical": [_vp, _vp, _vp, _vp],
+    "hw_pack_lwe": [_vp, _vp, _vp, _u32, _u64, _vp, _vp],
     "hw_batch_train": [_vp, C.POINTER(TrainJob), _u32, _vp],
     "hw_batch_plan_create": [_vp, C.POINTER(TrainJob), _u32, C.POINTER(C.c_void_p)],
     "hw_batch_plan_launch": [_vp, _vp],
@@ -237,6 +240,21 @@ class Context:
     def train(self, sh: Shape, x_rgsw, y_rgsw, n: int, model, class_count=None):
         _check(_lib.hw_wisard_train_encrypted(self._h, C.byref(sh), _ptr(x_rgsw), _ptr(y_rgsw), n, _ptr(model),
                                               _ptr(class_count), _stream()))
+
+    @property
+    def pks_key_words(self) -> int:
+        """uint32 words of a PackingKeySwitching key: N x D rows"""
+        return self.N * 5 * self.nq * self.rlwe_words
+
+    def pks_keygen(self, sk, seed: int, key):
+        _check(_lib.hw_pks_keygen(self._h, _ptr(sk), seed, _ptr(key), _stream()))
+
+    def pks_key_export(self, key, out):
+        _check(_lib.hw_pks_key_export_canonical(self._h, _ptr(key), _ptr(out), _stream()))
+
+    def pack_lwe(self, key, lwe, k: int, count: int, out):
+        """out[c] = PackingKeySwitching(lwe[c][0 .. k)) for c < count"""
+        _check(_lib.hw_pack_lwe(self._h, _ptr(key), _ptr(lwe), k, count, _ptr(out), _stream()))
 
     def rlwe_add(self, dst, src, count: int):
         """dst += src over count RLWE ciphertexts (model merge, Sec. 3.7.2)"""

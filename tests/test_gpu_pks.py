@@ -22,7 +22,8 @@ def _setup(N, nq, p):
     return HW, ctx, orc, sk, sk_o, key
 
 
-@pytest.mark.parametrize("N,nq,p,k,count", [(1024, 1, 64, 1000, 3), (2048, 2, 1024, 1960, 1)])
+@pytest.mark.parametrize("N,nq,p,k,count", [(1024, 1, 64, 1000, 3), (1024, 1, 64, 1024, 1), (1024, 1, 64, 1, 2),
+                                             (2048, 2, 1024, 1960, 1)])
 def test_key_and_packing_bit_exact(N, nq, p, k, count):
     HW, ctx, orc, sk, sk_o, key = _setup(N, nq, p)
     K_o = orc.pks_keygen(sk_o, 99)

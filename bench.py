@@ -429,7 +429,8 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     the replay of a batch plan (the same launches captured into a HIP graph),
     versus the same kernels one job at a time, on the same encrypted inputs.
     Jobs of one ring degree share a context (p = 4096 covers every job's
-    counts)."""
+    counts); they are taken in groups whose input ciphertexts fit in
+    `window_bytes` of device memory, each group one batch."""
     import numpy as np
     import torch
 

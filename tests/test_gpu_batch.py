@@ -1,6 +1,7 @@
 """GPU parity of batched training (one persistent launch over many uneven
 jobs): every job's model and class counter equal, bit for bit, the per-job
-call and the oracle; window splitting does not change any bit."""
+call and the oracle; the cut of RAMs into pieces of samples does not change
+any bit; captured batch plans replay the same result."""
 import os
 
 import numpy as np

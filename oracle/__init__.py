@@ -83,8 +83,15 @@ def lib():
                 "orc_vp": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_uint8), C.c_uint32, u32p, u32p]),
                 "orc_permutation": (None, [C.c_uint64, C.c_uint32, u32p]),
                 "orc_k1": (C.c_uint32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32]),
+                "orc_k1_layout": (C.c_uint32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),
                 "orc_train": (None, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, u32p, C.POINTER(C.c_void_p),
-                                     C.POINTER(C.c_void_p), C.c_uint64, C.c_uint32, C.c_uint32, u32p]),
+                                     C.POINTER(C.c_void_p), C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                     u32p]),
+                "orc_infer_packed": (None, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, u32p, u32p,
+                                            C.POINTER(C.c_void_p), C.c_uint32, u32p]),
+                "orc_extract_lwe": (None, [C.c_void_p, u32p, C.c_uint32, u32p]),
+                "orc_vp_rlwe": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_uint8), C.c_uint32, u32p,
+                                       u32p]),
                 "orc_class_count": (None, [C.c_void_p, C.c_uint32, C.POINTER(C.c_void_p), C.c_uint64, u32p]),
                 "orc_infer_one": (None, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, u32p, u32p,
                                          C.POINTER(C.c_void_p), C.c_uint32, C.c_uint32, u32p]),
@@ -367,6 +374,21 @@ class Ctx:
         lib().orc_vp(self.h, _ptr_array(rg), cl, len(rg), _p(lut, u32p), _p(out, u32p))
         return out
 
+    def vp_rlwe(self, rgsws, clear, lut) -> np.ndarray:
+        """the VP accumulator before ExtractLWE"""
+        rg = [None if r is None else np.ascontiguousarray(r, np.uint32) for r in rgsws]
+        cl = (C.c_uint8 * max(1, len(rg)))(*[int(x) for x in clear])
+        lut = np.ascontiguousarray(lut, np.uint32)
+        out = self.rlwe()
+        lib().orc_vp_rlwe(self.h, _ptr_array(rg), cl, len(rg), _p(lut, u32p), _p(out, u32p))
+        return out
+
+    def extract_lwe(self, ct, idx: int) -> np.ndarray:
+        ct = np.ascontiguousarray(ct, np.uint32)
+        out = np.zeros((self.nq, self.N + 1), np.uint32)
+        lib().orc_extract_lwe(self.h, _p(ct, u32p), idx, _p(out, u32p))
+        return out
+
     def extract_lwe0(self, ct) -> np.ndarray:
         ct = np.ascontiguousarray(ct, np.uint32)
         out = np.zeros((self.nq, self.N + 1), np.uint32)
@@ -424,13 +446,15 @@ class Ctx:
         return out
 
     # -- WiSARD --------------------------------------------------------------
-    def k1(self, s: int, l: int, a: int) -> int:
-        return int(lib().orc_k1(self.h, s, l, a))
+    def k1(self, s: int, l: int, a: int, layout: int = 0) -> int:
+        """rows per RAM: layout 0 label-pruned (Def. 2), 1 class-packed"""
+        return int(lib().orc_k1_layout(self.h, s, l, a, layout))
 
-    def train(self, s, l, a, pi, x_get, y_get, n, H, rams=None, threads=None):
+    def train(self, s, l, a, pi, x_get, y_get, n, H, rams=None, threads=None, layout=0):
         """Alg. 6 over samples [0, n) for the RAMs in `rams` (default: all),
         accumulating into H ([k0][k1] RLWE, uint32).  x_get(i, k) returns the
-        RGSW (numpy) of input bit k of sample i; y_get(i, u) that of label bit u."""
+        RGSW (numpy) of input bit k of sample i; y_get(i, u) that of label bit u.
+        layout 0: label-pruned rows; 1: class-packed rows."""
         L = ceil_log2(l)
         k0 = -(-s // a)
         rams = list(range(k0)) if rams is None else list(rams)
@@ -455,7 +479,7 @@ class Ctx:
 
         def one(j):
             xp, yp = ptrs_for(j)
-            lib().orc_train(self.h, s, l, a, _p(pi, u32p), xp, yp, n, j, j + 1, _p(H, u32p))
+            lib().orc_train(self.h, s, l, a, _p(pi, u32p), xp, yp, n, j, j + 1, layout, _p(H, u32p))
 
         _parallel(one, rams, threads)
         return H
@@ -476,6 +500,19 @@ class Ctx:
         out = np.zeros((self.nq, self.N + 1), np.uint32)
         lib().orc_infer_one(self.h, s, l, a, _p(pi, u32p), _p(H, u32p), _ptr_array(xs), j, label,
                             _p(out, u32p))
+        return out
+
+
+    def infer_packed(self, s, l, a, pi, H, x_get, j) -> np.ndarray:
+        """class-packed inference of RAM j for one sample: one VP, then the
+        LWE of every class, [l][nq][N+1]; x_get(k) -> RGSW of bit k."""
+        pi = np.ascontiguousarray(pi, np.uint32)
+        xs = [None] * s
+        for t in range(min(a, s - j * a)):
+            k = int(pi[j * a + t])
+            xs[k] = np.ascontiguousarray(x_get(k), np.uint32)
+        out = np.zeros((l, self.nq, self.N + 1), np.uint32)
+        lib().orc_infer_packed(self.h, s, l, a, _p(pi, u32p), _p(H, u32p), _ptr_array(xs), j, _p(out, u32p))
         return out
 
 

@@ -808,6 +808,21 @@ int32_t orc_leaf_row(uint32_t d, uint32_t z, uint32_t l) {
   return (int32_t)((d >> L) * l + cls);
 }
 
+/* ExtractLWE(c, i) (Sec. 2.5.1): the LWE of coefficient i of c's phase under
+ * the key's coefficients: a'_k = a_{i-k} for k <= i, a'_k = -a_{N+i-k} for
+ * k > i (X^N = -1), b' = b_i */
+void orc_extract_lwe(const orc_ctx* c, const uint32_t* in, uint32_t idx, uint32_t* lwe) {
+  uint32_t N = c->N, nq = c->nq;
+  for (uint32_t i = 0; i < nq; ++i) {
+    uint64_t q = c->q[i];
+    const uint32_t* a = in + (size_t)i * N;
+    uint32_t* o = lwe + (size_t)i * (N + 1);
+    for (uint32_t k = 0; k < N; ++k)
+      o[k] = k <= idx ? a[idx - k] : (uint32_t)((q - a[N + idx - k]) % q);
+    o[N] = in[((size_t)nq + i) * N + idx];
+  }
+}
+
 /* ExtractLWE(c, 0): a'_0 = a_0, a'_k = -a_{N-k} (k >= 1), b' = b_0 */
 void orc_extract_lwe0(const orc_ctx* c, const uint32_t* in, uint32_t* lwe) {
   uint32_t N = c->N, nq = c->nq;
@@ -829,8 +844,23 @@ void orc_extract_lwe0(const orc_ctx* c, const uint32_t* in, uint32_t* lwe) {
  * Then the blind rotation by X^{-2^t} over bits z..nb and ExtractLWE(., 0).
  * A cleartext bit is applied as the exact selection a noiseless RGSW of that
  * bit produces. */
+static void vp_core(const orc_ctx* c, const uint32_t* const* C, const uint8_t* clear, uint32_t nb,
+                    const uint32_t* lut, uint32_t* acc_out, uint32_t* lwe);
+
 void orc_vp(const orc_ctx* c, const uint32_t* const* C, const uint8_t* clear, uint32_t nb,
             const uint32_t* lut, uint32_t* lwe) {
+  vp_core(c, C, clear, nb, lut, NULL, lwe);
+}
+
+/* the same Vertical Packing, returning the rotated accumulator (RLWE)
+ * before extraction */
+void orc_vp_rlwe(const orc_ctx* c, const uint32_t* const* C, const uint8_t* clear, uint32_t nb,
+                 const uint32_t* lut, uint32_t* acc_out) {
+  vp_core(c, C, clear, nb, lut, acc_out, NULL);
+}
+
+static void vp_core(const orc_ctx* c, const uint32_t* const* C, const uint8_t* clear, uint32_t nb,
+                    const uint32_t* lut, uint32_t* acc_out, uint32_t* lwe) {
   size_t rw = rlwe_words(c);
   uint32_t nr = nb < c->logN ? nb : c->logN;
   uint32_t z = nb - nr;
@@ -865,7 +895,8 @@ void orc_vp(const orc_ctx* c, const uint32_t* const* C, const uint8_t* clear, ui
       memcpy(acc, rot, sizeof(uint32_t) * rw);
     }
   }
-  orc_extract_lwe0(c, acc, lwe);
+  if (lwe) orc_extract_lwe0(c, acc, lwe);
+  if (acc_out) memcpy(acc_out, acc, sizeof(uint32_t) * rw);
   free(T);
   free(rot);
   free(tmp);
@@ -916,6 +947,22 @@ uint32_t orc_k1(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a) {
   return live_leaves(z, l);
 }
 
+/* Class-packed layout (the horizontal packing the paper lists among its
+ * further improvements: one evaluation serves the RAMs of every
+ * discriminator).  The IVP index is [tuple bits, label bits] with the label
+ * bits on top, so cell (c, addr) of RAM j is m = addr + 2^a_j c: tree leaf
+ * m mod 2^z, coefficient (addr >> z) + c 2^(a_j - z).  A row holds all 2^z
+ * leaves, each with every class of its cells; one VP over the tuple bits
+ * brings the cells of all classes to coefficients c 2^(a_j - z). */
+uint32_t orc_k1_layout(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, uint32_t layout) {
+  if (layout == 0) return orc_k1(c, s, l, a);
+  uint32_t aj, nb, z;
+  ram_geometry(c, s, l, a, 0, &aj, &nb, &z);
+  (void)aj;
+  (void)nb;
+  return 1u << z;
+}
+
 /* Homomorphic training (Alg. 6) restricted to RAMs [ram_lo, ram_hi):
  * for each sample i in order and each RAM j: b = [Y_i bits 0..L), X_i[pi[j a
  * + t]] for t < a_j]; h = IVP(b, (0, Delta)) with the live tree nodes only;
@@ -926,10 +973,10 @@ uint32_t orc_k1(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a) {
  * u] at label bit u (LSB first); H is [k0][k1] RLWE. */
 void orc_train(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const uint32_t* pi,
                const uint32_t* const* x_ptr, const uint32_t* const* y_ptr, uint64_t n,
-               uint32_t ram_lo, uint32_t ram_hi, uint32_t* H) {
+               uint32_t ram_lo, uint32_t ram_hi, uint32_t layout, uint32_t* H) {
   size_t rw = rlwe_words(c);
   uint32_t L = ceil_log2_u(l);
-  uint32_t k1 = orc_k1(c, s, l, a);
+  uint32_t k1 = orc_k1_layout(c, s, l, a, layout);
   const uint32_t** bits = (const uint32_t**)malloc(sizeof(uint32_t*) * (L + a + 1));
   uint32_t* in = (uint32_t*)calloc(rw, sizeof(uint32_t));
   uint32_t aj0, nb0, z0;
@@ -940,11 +987,17 @@ void orc_train(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const uint3
     for (uint32_t j = ram_lo; j < ram_hi; ++j) {
       uint32_t aj, nb, z;
       ram_geometry(c, s, l, a, j, &aj, &nb, &z);
-      for (uint32_t u = 0; u < L; ++u) bits[u] = y_ptr[smp * L + u];
-      for (uint32_t t = 0; t < aj; ++t) bits[L + t] = x_ptr[smp * s + pi[j * a + t]];
-      orc_ivp_pruned(c, bits, nb, l, in, h);
+      if (layout == 0) {
+        for (uint32_t u = 0; u < L; ++u) bits[u] = y_ptr[smp * L + u];
+        for (uint32_t t = 0; t < aj; ++t) bits[L + t] = x_ptr[smp * s + pi[j * a + t]];
+        orc_ivp_pruned(c, bits, nb, l, in, h);
+      } else {  /* class-packed: [tuple bits, label bits], every leaf kept */
+        for (uint32_t t = 0; t < aj; ++t) bits[t] = x_ptr[smp * s + pi[j * a + t]];
+        for (uint32_t u = 0; u < L; ++u) bits[aj + u] = y_ptr[smp * L + u];
+        orc_ivp(c, bits, nb, in, h);
+      }
       for (uint32_t d = 0; d < (1u << z); ++d) {
-        int32_t row = orc_leaf_row(d, z, l);
+        int32_t row = layout == 0 ? orc_leaf_row(d, z, l) : (int32_t)d;
         if (row < 0) continue;
         uint32_t* dst = H + ((size_t)j * k1 + (uint32_t)row) * rw;
         rlwe_add(c, dst, h + (size_t)d * rw, dst);
@@ -1001,6 +1054,33 @@ void orc_infer_one(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const u
   }
   orc_vp(c, bits, clear, nb, lut, lwe);
   free(lut);
+  free(bits);
+  free(clear);
+}
+
+/* Homomorphic inference over the class-packed layout: for one sample and
+ * RAM j, one VP over the tuple bits (encrypted) of row H[j] with the label
+ * bits left out; the cell of class c then sits at coefficient c 2^(a_j - z)
+ * and out[c] = ExtractLWE(acc, c 2^(a_j - z)) for c < l (the scores Alg. 7
+ * computes per label, all from one evaluation).  out: [l] LWE. */
+void orc_infer_packed(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const uint32_t* pi,
+                      const uint32_t* H, const uint32_t* const* x_ptr, uint32_t j, uint32_t* out) {
+  size_t rw = rlwe_words(c);
+  uint32_t k1 = orc_k1_layout(c, s, l, a, 1);
+  uint32_t aj, nb, z;
+  ram_geometry(c, s, l, a, j, &aj, &nb, &z);
+  /* the VP over all nb index bits with the label bits as cleartext zeros: z
+   * <= a_j (L <= log2 N), so the tree takes tuple bits only and the label
+   * bits leave the accumulator where the tuple bits put it */
+  const uint32_t** bits = (const uint32_t**)calloc(nb + 1, sizeof(uint32_t*));
+  uint8_t* clear = (uint8_t*)calloc(nb + 1, 1);
+  for (uint32_t t = 0; t < aj; ++t) bits[t] = x_ptr[pi[j * a + t]];
+  uint32_t* acc = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  orc_vp_rlwe(c, bits, clear, nb, H + (size_t)j * k1 * rw, acc);
+  uint32_t stride = 1u << (aj - z);
+  for (uint32_t cl = 0; cl < l; ++cl)
+    orc_extract_lwe(c, acc, cl * stride, out + (size_t)cl * c->nq * (c->N + 1));
+  free(acc);
   free(bits);
   free(clear);
 }

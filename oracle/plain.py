@@ -151,17 +151,22 @@ def model_row(d: int, z: int, L: int, l: int) -> int:
     return w * l + c if c < l else -1
 
 
-def expected_model_cells(W: np.ndarray, s: int, l: int, a: int, N: int) -> np.ndarray:
+def expected_model_cells(W: np.ndarray, s: int, l: int, a: int, N: int, layout: int = 0) -> np.ndarray:
     """Decrypted content of H (shape [k0][k1][N]) implied by a plaintext Integer
-    WiSARD W: with m = c + 2^L addr, tree leaf d = m mod 2^z_j of RAM j holds
-    W[c][j][addr] at coefficient m >> z_j, and leaf d is row model_row(d) of
-    H[j]; every other cell is 0."""
+    WiSARD W.  Layout 0 (label-pruned): with m = c + 2^L addr, tree leaf
+    d = m mod 2^z_j of RAM j holds W[c][j][addr] at coefficient m >> z_j, and
+    leaf d is row model_row(d) of H[j].  Layout 1 (class-packed): with
+    m = addr + 2^a_j c, row m mod 2^z_j holds it at coefficient m >> z_j.
+    Every other cell is 0."""
     L = ceil_log2(l)
     logN = N.bit_length() - 1
     k0 = -(-s // a)
     nb_full = L + a
     z0 = nb_full - min(nb_full, logN)
-    k1 = l << (z0 - L) if z0 >= L else 1 << z0
+    if layout == 0:
+        k1 = l << (z0 - L) if z0 >= L else 1 << z0
+    else:
+        k1 = 1 << z0
     out = np.zeros((k0, k1, N), np.int64)
     for j in range(k0):
         aj = min(a, s - j * a)
@@ -169,8 +174,12 @@ def expected_model_cells(W: np.ndarray, s: int, l: int, a: int, N: int) -> np.nd
         z = nb - min(nb, logN)
         for c in range(l):
             for addr in range(1 << aj):
-                m = c + (addr << L)
-                out[j, model_row(m % (1 << z), z, L, l), m >> z] = W[c, j, addr]
+                if layout == 0:
+                    m = c + (addr << L)
+                    out[j, model_row(m % (1 << z), z, L, l), m >> z] = W[c, j, addr]
+                else:
+                    m = addr + (c << aj)
+                    out[j, m % (1 << z), m >> z] = W[c, j, addr]
     return out
 
 

@@ -76,25 +76,29 @@ class Micro:
     """Small encrypted WiSARD: exercises a ragged last tuple, an encrypted
     CDEMUX/CMUX tree level (z > L) and cleartext label bits in the chain."""
 
-    def __init__(self, N, s, l, a, n, p=64, nq=1, seed=0):
+    def __init__(self, N, s, l, a, n, p=64, nq=1, seed=0, layout=0):
         self.c = O.Ctx(N, nq, p)
         self.s, self.l, self.a, self.n = s, l, a, n
+        self.layout = layout
         self.L = O.ceil_log2(l)
         self.k0 = -(-s // a)
-        self.k1 = self.c.k1(s, l, a)
+        self.k1 = self.c.k1(s, l, a, layout)
         X, y = synth.prototype_bits(seed, n, s, l, flip=0.2)
         self.X, self.y = X, y
         self.sk = self.c.keygen(100 + seed)
         self.pi = O.permutation(200 + seed, s)
         self.xr = self.c.enc_rgsw_bits(self.sk, X.reshape(-1), 300 + seed, 0).reshape(n, s, -1)
         yb = np.array([[(v >> u) & 1 for u in range(self.L)] for v in y]).reshape(-1)
-        self.yr = self.c.enc_rgsw_bits(self.sk, yb, 400 + seed, 0).reshape(n, self.L, -1)
+        if self.L:
+            self.yr = self.c.enc_rgsw_bits(self.sk, yb, 400 + seed, 0).reshape(n, self.L, -1)
+        else:  # l = 1: no label bits
+            self.yr = np.zeros((n, 0, self.xr.shape[-1]), np.uint32)
 
     def train(self, idx=None):
         idx = list(range(self.n)) if idx is None else list(idx)
         H = np.zeros((self.k0, self.k1, 2, self.c.nq, self.c.N), np.uint32)
         self.c.train(self.s, self.l, self.a, self.pi, lambda i, k: self.xr[idx[i], k],
-                     lambda i, u: self.yr[idx[i], u], len(idx), H)
+                     lambda i, u: self.yr[idx[i], u], len(idx), H, layout=self.layout)
         return H
 
 
@@ -143,6 +147,61 @@ def test_encrypted_inference_pd_act(cfg):
         assert sums == list(want.sum(axis=1) % m.c.p)
         for kind in ("bin", "log", "blog"):
             assert P.pd_act_predict(cells, kind) == P.predict(W, Xt[t], m.a, m.pi, kind)
+
+
+PACKED = [
+    dict(N=16, s=14, l=3, a=4, n=6),   # z = 2 tuple bits in the tree, chain: 2 tuple + 2 label bits
+    dict(N=8, s=10, l=2, a=4, n=5),    # z = 2, a ragged last tuple of 2 bits (z = 0 there)
+    dict(N=32, s=9, l=5, a=3, n=6),    # z = 1, label bits on top of a 3-bit tuple
+    dict(N=8, s=10, l=3, a=4, n=6),    # z = 3: 3 of the 4 tuple bits in the tree
+    dict(N=16, s=7, l=1, a=7, n=4),    # l = 1: no label bits at all
+]
+
+
+@pytest.mark.parametrize("cfg", PACKED)
+def test_class_packed_training_matches_integer_wisard(cfg):
+    """Class-packed layout: every cell of the plaintext Integer WiSARD (Alg. 4)
+    at row (addr + 2^a_j c) mod 2^z, coefficient (addr + 2^a_j c) >> z."""
+    m = Micro(**cfg, layout=1)
+    assert m.k1 == 1 << max(0, m.L + m.a - (m.c.N.bit_length() - 1))
+    H = m.train()
+    W = P.train_integer(m.X, m.y, m.l, m.a, m.pi)
+    want = P.expected_model_cells(W, m.s, m.l, m.a, m.c.N, layout=1)
+    got = np.stack([[m.c.dec_rlwe(m.sk, H[j, d]) for d in range(m.k1)] for j in range(m.k0)])
+    assert np.array_equal(got.astype(np.int64), want)
+
+
+@pytest.mark.parametrize("cfg", PACKED)
+def test_class_packed_inference_scores(cfg):
+    """One VP per RAM gives the cell of every class: the extracted LWEs decrypt
+    to the plaintext RAM scores of Alg. 2, and PD-act picks the same class."""
+    m = Micro(**cfg, layout=1)
+    H = m.train()
+    W = P.train_integer(m.X, m.y, m.l, m.a, m.pi)
+    Xt, _ = synth.prototype_bits(51, 3, m.s, m.l, flip=0.3)
+    for t in range(3):
+        xr = m.c.enc_rgsw_bits(m.sk, Xt[t], 600 + t, 0)
+        cells = np.zeros((m.l, m.k0), np.int64)
+        for j in range(m.k0):
+            lw = m.c.infer_packed(m.s, m.l, m.a, m.pi, H, lambda k: xr[k], j)
+            for c in range(m.l):
+                cells[c, j] = m.c.dec_lwe(m.sk, lw[c])
+        want = P.ram_scores(W, Xt[t], m.a, m.pi)
+        assert np.array_equal(cells, want)
+        for kind in ("bin", "log", "blog"):
+            assert P.pd_act_predict(cells, kind) == P.predict(W, Xt[t], m.a, m.pi, kind)
+
+
+def test_extract_lwe_any_index():
+    """ExtractLWE(c, i) decrypts to coefficient i of c's phase for every i,
+    the phase taken by the negacyclic product of the decryption."""
+    c = O.Ctx(16, 2, 64)
+    sk = c.keygen(7)
+    msg = (np.arange(16, dtype=np.uint64) * 5 + 3) % 64
+    ct = c.enc_rlwe(sk, msg, 8, 0)
+    for i in range(16):
+        assert c.dec_lwe(sk, c.extract_lwe(ct, i)) == int(msg[i])
+    assert np.array_equal(c.extract_lwe(ct, 0), c.extract_lwe0(ct))
 
 
 def test_model_additivity_and_order():

@@ -63,12 +63,25 @@ typedef struct {
 } hw_params;
 
 /* WiSARD shape (Def. 1-2): s input bits, l classes, tuple (address) size a,
- * seed of the pseudo-random input permutation pi_r. */
+ * seed of the pseudo-random input permutation pi_r, and the layout of the
+ * encrypted model:
+ *   0  label-pruned rows (Def. 2): the IVP index is [label bits, tuple bits];
+ *      a row holds only the tree leaves of classes below l; inference runs
+ *      one VP per (RAM, label).
+ *   1  class-packed rows (the horizontal packing of the paper's further
+ *      improvements, Sec. 5.1): the index is [tuple bits, label bits], so the
+ *      cell (class c, address m) of RAM j sits in row (m + 2^a_j c) mod 2^z
+ *      at coefficient (m + 2^a_j c) >> z; every tree leaf is a row
+ *      (k1 = 2^z); one VP per RAM over the tuple bits brings the cell of
+ *      every class to coefficient c 2^(a_j - z) and inference extracts all l
+ *      scores from it.  Same scores, fewer external products at inference,
+ *      more at training when l < 2^L.
+ * Other values are rejected (HW_EINVAL). */
 typedef struct {
   uint32_t s;
   uint32_t l;
   uint32_t a;
-  uint32_t reserved;   /* must be 0 */
+  uint32_t layout;     /* model layout: 0 or 1, see below */
   uint64_t perm_seed;
 } hw_wisard_shape;
 
@@ -92,11 +105,12 @@ hw_status hw_ctx_params(const hw_ctx* ctx, hw_params* out);
 hw_status hw_sizes(const hw_ctx* ctx, uint64_t* rlwe_bytes, uint64_t* rgsw_bytes,
                    uint64_t* lwe_bytes);
 
-/* Model geometry of Def. 2: k0 = ceil(s/a) RAMs and k1 RLWE per RAM, the
- * ciphertexts that hold a class below l.  With L = ceil(log2 l) label bits
- * and z = L + a - min(L + a, log2 N) tree bits, the IVP's leaf d = c + 2^L w
- * holds class c; a RAM row keeps the leaves with c < l in row w l + c, so
- * k1 = l 2^(z-L) = ceil(l 2^a / N) when z >= L, and k1 = 2^z otherwise.
+/* Model geometry of Def. 2: k0 = ceil(s/a) RAMs and k1 RLWE per RAM.  With
+ * L = ceil(log2 l) label bits and z = L + a - min(L + a, log2 N) tree bits:
+ * layout 0 keeps the ciphertexts that hold a class below l (leaf
+ * d = c + 2^L w holds class c and goes to row w l + c), so
+ * k1 = l 2^(z-L) = ceil(l 2^a / N) when z >= L, and k1 = 2^z otherwise;
+ * layout 1 keeps all k1 = 2^z leaves.
  * model_bytes is the size of H = [k0][k1] RLWE. */
 hw_status hw_wisard_dims(const hw_ctx* ctx, const hw_wisard_shape* shape, uint32_t* k0,
                          uint32_t* k1, uint64_t* model_bytes);
@@ -166,11 +180,12 @@ hw_status hw_external_product(hw_ctx* ctx, const uint32_t* rgsw_dev, const uint3
 /* Homomorphic training (Alg. 6) of n samples, accumulated into the model in
  * place.  x_rgsw_dev: RGSW[n][s] of the unpermuted input bits; y_rgsw_dev:
  * RGSW[n][L] of the label bits, LSB first (L = ceil(log2 l)).  For sample i
- * and RAM j the IVP (Alg. 5) runs on b = [label bits, x[pi[j a + t]] for
- * t < a_j] (a_j = min(a, s - j a)) with input (0, Delta), creating only the
- * CDEMUX tree nodes that lead to a class below l, and each such leaf is
- * added to its row of model_dev[j] (RLWE[k0][k1], coefficient domain; see
- * hw_wisard_dims).
+ * and RAM j the IVP (Alg. 5) runs with input (0, Delta) on b = [label bits,
+ * x[pi[j a + t]] for t < a_j] (a_j = min(a, s - j a)), creating only the
+ * CDEMUX tree nodes that lead to a class below l (layout 0), or on
+ * b = [x[pi[j a + t]] for t < a_j, label bits] with every node (layout 1);
+ * each kept leaf is added to its row of model_dev[j] (RLWE[k0][k1],
+ * coefficient domain; see hw_wisard_dims).
  * class_count_dev (one RLWE, may be NULL) receives the balancing counter
  * (Sec. 3.7.1): the IVP of the label bits alone.  Results are exact:
  * independent of chunking, sample order and launch configuration. */
@@ -179,12 +194,16 @@ hw_status hw_wisard_train_encrypted(hw_ctx* ctx, const hw_wisard_shape* shape,
                                     uint64_t n, uint32_t* model_dev, uint32_t* class_count_dev,
                                     hipStream_t stream);
 
-/* Homomorphic inference, PD-act branch (Alg. 7): for each sample, RAM j and
- * label c < l, the Vertical Packing (Alg. 3, read as the inverse of the IVP
- * layout) of model row j with the label bits of c in the clear and the
- * sample's permuted tuple bits encrypted, then ExtractLWE(., 0).
- * ram_scores_dev: LWE[n][l][k0]; class_scores_dev (may be NULL):
- * LWE[n][l], the sums over j.  model_dev is read only. */
+/* Homomorphic inference, PD-act branch (Alg. 7).  Layout 0: for each
+ * sample, RAM j and label c < l, the Vertical Packing (Alg. 3, read as the
+ * inverse of the IVP layout) of model row j with the label bits of c in the
+ * clear and the sample's permuted tuple bits encrypted, then
+ * ExtractLWE(., 0).  Layout 1: for each sample and RAM j one Vertical Packing
+ * over the tuple bits (label bits clear zeros), then ExtractLWE(., c
+ * 2^(a_j - z)) for every c < l (Sec. 2.5.1).  Either way
+ * ram_scores_dev: LWE[n][l][k0], decrypting to the cell of class c addressed
+ * by the sample in RAM j; class_scores_dev (may be NULL): LWE[n][l], the sums
+ * over j.  model_dev is read only. */
 hw_status hw_wisard_infer_encrypted(hw_ctx* ctx, const hw_wisard_shape* shape,
                                     const uint32_t* model_dev, const uint32_t* x_rgsw_dev,
                                     uint64_t n, uint32_t* ram_scores_dev,

@@ -293,7 +293,7 @@ uint32_t ivp_xp(uint32_t nb, int logN, uint32_t L, uint32_t l) {
 
 hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d) {
   if (!sh) return fail(HW_EINVAL, "null shape");
-  if (sh->reserved) return fail(HW_EINVAL, "shape.reserved must be 0");
+  if (sh->layout > 1) return fail(HW_EINVAL, "shape.layout = %u: must be 0 or 1", sh->layout);
   if (sh->s < 1 || sh->s > (1u << 24)) return fail(HW_EINVAL, "s = %u out of range [1, 2^24]", sh->s);
   if (sh->l < 1 || sh->l > 256) return fail(HW_EINVAL, "l = %u out of range [1, 256]", sh->l);
   if (sh->a < 1 || sh->a > 20) return fail(HW_EINVAL, "a = %u out of range [1, 20]", sh->a);
@@ -303,8 +303,35 @@ hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d) {
   const uint32_t nr = nb < (uint32_t)c->logN ? nb : (uint32_t)c->logN;
   d->z = nb - nr;
   d->kt = 1u << d->z;
-  d->k1 = live_rows(d->z, d->L, sh->l);
+  d->layout = sh->layout;
+  d->pL = sh->layout ? 0u : d->L;
+  d->pl = sh->layout ? 1u : sh->l;
+  d->k1 = live_rows(d->z, d->pL, d->pl);
   return HW_OK;
+}
+
+// CMUX-tree temporaries of one inference VP: the outputs of its widest
+// encrypted level
+uint32_t infer_slots(const Dims& d) { return d.z > d.pL + 1 ? (1u << (d.z - d.pL - 1)) : 1u; }
+
+// external products of the inference of one sample: per VP the encrypted
+// tree levels and the encrypted positions of the rotation chain; layout 0
+// runs one VP per (RAM, label), layout 1 one per RAM
+double infer_xp_per_sample(const hw_ctx* c, const hw_wisard_shape* sh, const Dims& d) {
+  double xp = 0;
+  for (uint32_t j = 0; j < d.k0; ++j) {
+    const uint32_t aj = std::min(sh->a, sh->s - j * sh->a);
+    const uint32_t nb = d.L + aj;
+    const uint32_t nr = std::min(nb, (uint32_t)c->logN), z = nb - nr;
+    const uint32_t tree = z > d.pL ? (1u << (z - d.pL)) - 1 : 0;
+    if (d.layout) {
+      xp += tree + (aj - z);  // the chain's tuple bits; the label bits on top stay clear zeros
+    } else {
+      const uint32_t chain = z >= d.L ? nr : (nr > d.L - z ? nr - (d.L - z) : 0);
+      xp += (double)sh->l * (tree + chain);
+    }
+  }
+  return xp;
 }
 
 extern "C" hw_status hw_wisard_dims(const hw_ctx* c, const hw_wisard_shape* sh, uint32_t* k0, uint32_t* k1,
@@ -496,8 +523,8 @@ size_t train_ws_per_sample(const hw_ctx* c, const Dims& d) {
 }
 
 size_t infer_ws_per_sample(const hw_ctx* c, const hw_wisard_shape* sh, const Dims& d) {
-  const uint32_t slots = d.z > d.L + 1 ? (1u << (d.z - d.L - 1)) : 1u;
-  return (size_t)sh->l * d.k0 * (slots + 1) * rlwe_words(c) * 4;  // + input slot
+  const uint32_t nlab = d.layout ? 1u : sh->l;
+  return (size_t)nlab * d.k0 * (infer_slots(d) + 1) * rlwe_words(c) * 4;  // + input slot
 }
 
 hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const uint32_t* perm,
@@ -523,6 +550,7 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   A.k1 = d.k1;
   A.kt = d.kt;
   A.l = sh->l;
+  A.layout = d.layout;
   hw::ReduceArgs R{};
   R.out = A.out;
   R.model = model;
@@ -534,6 +562,7 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   R.k1 = d.k1;
   R.kt = d.kt;
   R.l = sh->l;
+  R.layout = d.layout;
   R.logN = c->logN;
   R.N = c->prm.N;
   R.nq = c->prm.nq;
@@ -542,7 +571,7 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   double xp_per_sample = 0;
   for (uint32_t j = 0; j < nram; ++j) {
     const uint32_t nb = j < d.k0 ? d.L + std::min(sh->a, sh->s - j * sh->a) : d.L;
-    xp_per_sample += ivp_xp(nb, c->logN, d.L, sh->l);
+    xp_per_sample += ivp_xp(nb, c->logN, d.pL, d.pl);
   }
   const bool tm = timing && c->prof;
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
@@ -590,19 +619,11 @@ hw_status infer_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   uint64_t n_sub = ws_bytes / infer_ws_per_sample(c, sh, d);
   if (n_sub < 1) return fail(HW_ENOMEM, "inference workspace smaller than one sample");
   if (n_sub > n) n_sub = n;
-  n_sub = std::min<uint64_t>(n_sub, std::min<uint64_t>(65535, (1u << 22) / ((uint64_t)d.k0 * sh->l)));
+  const uint32_t nlab = d.layout ? 1u : sh->l;
+  n_sub = std::min<uint64_t>(n_sub, std::min<uint64_t>(65535, (1u << 22) / ((uint64_t)d.k0 * nlab)));
   if (n_sub < 1) return fail(HW_EINVAL, "too many (RAM, label) pairs for one launch");
-  const uint32_t slots = d.z > d.L + 1 ? (1u << (d.z - d.L - 1)) : 1u;
-  // external products per sample: for every RAM and label, the encrypted
-  // selection levels and the encrypted positions of the rotation chain
-  double xp_per_sample = 0;
-  for (uint32_t j = 0; j < d.k0; ++j) {
-    const uint32_t nb = d.L + std::min(sh->a, sh->s - j * sh->a);
-    const uint32_t nr = std::min(nb, (uint32_t)c->logN), z = nb - nr;
-    const uint32_t tree = z > d.L ? (1u << (z - d.L)) - 1 : 0;
-    const uint32_t chain = z >= d.L ? nr : (nr > d.L - z ? nr - (d.L - z) : 0);
-    xp_per_sample += (double)sh->l * (tree + chain);
-  }
+  const uint32_t slots = infer_slots(d);
+  const double xp_per_sample = infer_xp_per_sample(c, sh, d);
   hw::InferArgs A{};
   A.model = model;
   A.x_rgsw = x_rgsw;
@@ -617,6 +638,8 @@ hw_status infer_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   A.k0 = d.k0;
   A.k1 = d.k1;
   A.slots = slots;
+  A.layout = d.layout;
+  A.nlab = nlab;
   const bool tm = timing && c->prof;
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
     const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
@@ -792,7 +815,7 @@ static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
     nram[j] = d.k0 + (jobs[j].class_count_dev ? 1 : 0);
     for (uint32_t r = 0; r < nram[j]; ++r) {
       const uint32_t nb = r < d.k0 ? d.L + std::min(jobs[j].shape.a, jobs[j].shape.s - r * jobs[j].shape.a) : d.L;
-      const uint32_t xp = ivp_xp(nb, c->logN, d.L, jobs[j].shape.l);
+      const uint32_t xp = ivp_xp(nb, c->logN, d.pL, d.pl);
       xp_max[j] = std::max(xp_max[j], xp);
       xp_smp[j] += xp;
     }
@@ -841,6 +864,7 @@ static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
     b.nram = nram[j];
     b.per = per[j];
     b.pieces = pieces[j];
+    b.layout = d.layout;
     acc0 += (uint64_t)(pieces[j] - 1) * nram[j] * d.k1 * rw;
     if (pieces[j] > 1) B.words += (uint64_t)d.k0 * d.k1 * rw + (J.class_count_dev ? rw : 0);
     B.max_pieces = std::max(B.max_pieces, pieces[j]);
@@ -852,7 +876,7 @@ static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
       const uint64_t cnt = std::min<uint64_t>(per[j], J.n - (uint64_t)p * per[j]);
       for (uint32_t r = 0; r < nram[j]; ++r) {
         const uint32_t nb = r < d.k0 ? d.L + std::min(J.shape.a, J.shape.s - r * J.shape.a) : d.L;
-        const uint64_t ixp = cnt * ivp_xp(nb, c->logN, d.L, J.shape.l);
+        const uint64_t ixp = cnt * ivp_xp(nb, c->logN, d.pL, d.pl);
         B.items.push_back(hw::BItem{jb, r, p, (uint32_t)std::min<uint64_t>(ixp, 0xFFFFFFFFull)});
         B.xp += (double)ixp;
       }

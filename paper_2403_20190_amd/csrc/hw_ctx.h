@@ -144,11 +144,16 @@ static size_t lwe_words(const hw_ctx* c) { return (size_t)c->prm.nq * (c->prm.N 
 
 struct Dims {
   uint32_t L, k0, k1, z;
-  uint32_t kt;  // 2^z: leaves of a full RAM's IVP tree (k1 of them hold a class below l)
+  uint32_t kt;      // 2^z: leaves of a full RAM's IVP tree (k1 of them are model rows)
+  uint32_t layout;  // 0: label-pruned rows (label bits lowest in the index); 1: class-packed rows
+  uint32_t pL, pl;  // label bits at the bottom of the tree and the classes they take: (L, l)
+                    // for layout 0; (0, 1) for layout 1, whose tree holds tuple bits only
 };
 
 uint32_t live_rows(uint32_t z, uint32_t L, uint32_t l);
 uint32_t ivp_xp(uint32_t nb, int logN, uint32_t L, uint32_t l);
+uint32_t infer_slots(const Dims& d);
+double infer_xp_per_sample(const hw_ctx* c, const hw_wisard_shape* sh, const Dims& d);
 
 
 // error reporting: sets the calling thread's message

@@ -42,6 +42,7 @@ struct TrainArgs {
   uint32_t l, kt;           // classes; 2^z leaves of a full RAM's tree (slots per block: kt + 1)
   uint32_t nram, nsub;      // grid: nram RAM items (k0, + 1 for the counter) x nsub samples
   uint32_t map;             // 0: 2-D grid (RAM, sample); 1: 1-D, XCD-grouped
+  uint32_t layout;          // model layout: 0 label-pruned rows, 1 class-packed rows
 };
 
 struct ReduceArgs {
@@ -51,6 +52,7 @@ struct ReduceArgs {
   uint64_t n_sub;
   uint32_t s, a, L, k0, k1, logN, N, nq;
   uint32_t l, kt;           // classes; tree leaves per block (block = kt + 1 slots)
+  uint32_t layout;          // as TrainArgs::layout
 };
 
 struct InferArgs {
@@ -58,12 +60,14 @@ struct InferArgs {
   const uint32_t* x_rgsw;   // [n][s] RGSW
   const uint32_t* perm;     // [s]
   uint32_t* scores;         // [n][l][k0] LWE
-  uint32_t* scratch;        // [n_sub][l][k0][slots] RLWE
+  uint32_t* scratch;        // [n_sub][nlab][k0][slots + 1] RLWE
   uint64_t rgsw_words;
   uint64_t i0;
   uint32_t s, a, L, l, k0, k1, slots;
   uint32_t nsub;            // samples of this launch
   uint32_t map;             // 0: 3-D grid (RAM, label, sample); 1: 1-D, labels adjacent, XCD-grouped
+  uint32_t layout;          // 0: one VP per (RAM, label); 1: class-packed rows, one VP per RAM gives all l
+  uint32_t nlab;            // labels in the grid: l for layout 0, 1 for layout 1
 };
 
 // batched training: one entry per job
@@ -79,6 +83,7 @@ struct BJob {
   uint32_t l, kt;           // classes; tree leaves of a full RAM (scratch slots beyond the input slot)
   uint32_t nram;            // k0, + 1 with a class counter
   uint32_t per, pieces;     // samples per piece, pieces per RAM
+  uint32_t layout;          // as TrainArgs::layout
 };
 
 struct BItem {

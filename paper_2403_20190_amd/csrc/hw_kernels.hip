@@ -617,6 +617,32 @@ __device__ __forceinline__ uint32_t ram_rows(uint32_t nb, uint32_t logN, uint32_
   return z >= L ? l << (z - L) : 1u << z;
 }
 
+// Two model layouts.  Layout 0 (label-pruned rows): the IVP index is [label
+// bits, tuple bits], the label bits are the lowest tree levels and only the
+// leaves of classes below l are rows.  Layout 1 (class-packed rows): the
+// index is [tuple bits, label bits]; the tree holds tuple bits only, every
+// leaf is a row and the class of a cell sets its coefficient, so one VP over
+// the tuple bits reads the cells of all classes.  tree_L / tree_l give the
+// label bits at the bottom of the tree and their classes: (L, l), or (0, 1)
+// for layout 1, for which node_live, leaf_row and ram_rows keep every node.
+__device__ __forceinline__ uint32_t tree_L(uint32_t layout, uint32_t L) { return layout ? 0u : L; }
+__device__ __forceinline__ uint32_t tree_l(uint32_t layout, uint32_t l) { return layout ? 1u : l; }
+
+// RGSW of bit u of the IVP index of (sample gi, RAM ram), nb index bits; the
+// class counter (ram == k0) has only label bits
+__device__ __forceinline__ const uint32_t* index_bit(uint32_t layout, uint32_t u, uint32_t nb, uint32_t L,
+                                                     const uint32_t* __restrict__ x, const uint32_t* __restrict__ y,
+                                                     const uint32_t* __restrict__ perm, uint64_t gi, uint32_t s,
+                                                     uint32_t ram, uint32_t a, uint64_t rgsw_words) {
+  if (layout == 0) {
+    if (u < L) return y + (gi * L + u) * rgsw_words;
+    return x + (gi * s + perm[ram * a + (u - L)]) * rgsw_words;
+  }
+  const uint32_t aj = nb - L;
+  if (u < aj) return x + (gi * s + perm[ram * a + u]) * rgsw_words;
+  return y + (gi * L + (u - aj)) * rgsw_words;
+}
+
 template <int LOGN, int NQ, int OCC>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_train(Tabs T, TrainArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
@@ -636,10 +662,11 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
   }
   const uint64_t gi = A.i0 + smp;
   uint32_t* slot0 = A.out + ((size_t)smp * (A.k0 + 1) + ram) * (A.kt + 1) * RW;
-  ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)A.kt * RW, ram_bits(ram, A.k0, A.s, A.a, A.L), A.L, A.l,
+  const uint32_t nb = ram_bits(ram, A.k0, A.s, A.a, A.L);
+  ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)A.kt * RW, nb, tree_L(A.layout, A.L), tree_l(A.layout, A.l),
                       [&](uint32_t u) -> const uint32_t* {
-                        if (u < A.L) return A.y_rgsw + (gi * A.L + u) * A.rgsw_words;
-                        return A.x_rgsw + (gi * A.s + A.perm[ram * A.a + (u - A.L)]) * A.rgsw_words;
+                        return index_bit(A.layout, u, nb, A.L, A.x_rgsw, A.y_rgsw, A.perm, gi, A.s, ram, A.a,
+                                         A.rgsw_words);
                       },
                       lds, twl, t);
 }
@@ -684,10 +711,10 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
 #pragma unroll 1
     for (uint32_t smp = s0; smp < s1; ++smp) {
       const uint64_t gi = smp;
-      ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)J.kt * RW, nb, J.L, J.l,
+      ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)J.kt * RW, nb, tree_L(J.layout, J.L), tree_l(J.layout, J.l),
                           [&](uint32_t u) -> const uint32_t* {
-                            if (u < J.L) return J.y + (gi * J.L + u) * A.rgsw_words;
-                            return J.x + (gi * J.s + J.perm[I.ram * J.a + (u - J.L)]) * A.rgsw_words;
+                            return index_bit(J.layout, u, nb, J.L, J.x, J.y, J.perm, gi, J.s, I.ram, J.a,
+                                             A.rgsw_words);
                           },
                           lds, twl, t, dest, I.piece != 0 && smp == s0);
       __syncthreads();
@@ -722,7 +749,9 @@ __global__ __launch_bounds__(256) void k_reduce_batch(Tabs T, const BJob* __rest
     if (x < model_words) {
       ram = (uint32_t)(x / per_ram);
       off = x - (size_t)ram * per_ram;
-      if (off / RW >= ram_rows(ram_bits(ram, J.k0, J.s, J.a, J.L), logN, J.L, J.l)) continue;
+      if (off / RW >= ram_rows(ram_bits(ram, J.k0, J.s, J.a, J.L), logN, tree_L(J.layout, J.L),
+                               tree_l(J.layout, J.l)))
+        continue;
     } else {
       ram = J.k0;
       off = x - model_words;
@@ -756,9 +785,10 @@ __global__ __launch_bounds__(256) void k_reduce_model(Tabs T, ReduceArgs A) {
       const uint32_t row = (uint32_t)(rem / RW);
       rem -= (size_t)row * RW;
       const uint32_t nb = ram_bits(ram, A.k0, A.s, A.a, A.L);
-      if (row >= ram_rows(nb, A.logN, A.L, A.l)) continue;
+      const uint32_t pL = tree_L(A.layout, A.L), pl = tree_l(A.layout, A.l);
+      if (row >= ram_rows(nb, A.logN, pL, pl)) continue;
       const uint32_t z = nb - (nb < A.logN ? nb : A.logN);
-      d = z < A.L ? row : ((row / A.l) << A.L) + row % A.l;  // the leaf of this row
+      d = z < pL ? row : ((row / pl) << pL) + row % pl;  // the leaf of this row
     } else {
       ram = A.k0;
       d = 0;
@@ -775,12 +805,16 @@ __global__ __launch_bounds__(256) void k_reduce_model(Tabs T, ReduceArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// inference: one workgroup per (RAM, label, sample)
+// inference: one workgroup per (RAM, label, sample), or per (RAM, sample)
 // ---------------------------------------------------------------------------
-// Vertical Packing of row `ram` of the model for the label bits of c (clear)
-// and the sample's tuple bits (encrypted).  Levels of the selection tree that
-// carry label bits select exactly; only the 2^{z-L} - 1 CMUXes whose outputs
-// reach the result are evaluated (the discarded ones do not change it).
+// Layout 0: Vertical Packing of row `ram` of the model for the label bits of
+// c (clear) and the sample's tuple bits (encrypted).  Levels of the selection
+// tree that carry label bits select exactly; only the 2^{z-L} - 1 CMUXes
+// whose outputs reach the result are evaluated (the discarded ones do not
+// change it).  Layout 1: one VP over the tuple bits (the full tree over the
+// row's 2^z leaves, then the chain); the label bits above them are clear
+// zeros, and the cell of class c ends at coefficient c 2^(a_j - z), so the
+// workgroup extracts the LWE of every class.
 
 template <int LOGN, int NQ, int OCC>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_infer(Tabs T, InferArgs A) {
@@ -795,12 +829,12 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
     lab = blockIdx.y;
     smp = blockIdx.z;
   } else {  // 1-D grid, the labels of one (sample, RAM) adjacent, XCD x takes the x-th eighth
-    const uint32_t G = A.k0 * A.l * A.nsub, per = (G + 7) >> 3;
+    const uint32_t G = A.k0 * A.nlab * A.nsub, per = (G + 7) >> 3;
     const uint32_t lg = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
     if (lg >= G) return;
-    lab = lg % A.l;
-    ram = (lg / A.l) % A.k0;
-    smp = lg / A.l / A.k0;
+    lab = lg % A.nlab;
+    ram = (lg / A.nlab) % A.k0;
+    smp = lg / A.nlab / A.k0;
   }
   const uint64_t gi = A.i0 + smp;
   const uint32_t rem = A.s - ram * A.a;
@@ -808,26 +842,28 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
   const uint32_t nb = A.L + aj;
   const uint32_t nr = nb < (uint32_t)LOGN ? nb : (uint32_t)LOGN;
   const uint32_t z = nb - nr;
+  const uint32_t TL = tree_L(A.layout, A.L);  // label bits at the bottom of the tree
+  const uint32_t tl = tree_l(A.layout, A.l);  // rows per group of leaves
   const uint32_t* H = A.model + (size_t)ram * A.k1 * RW;
-  uint32_t* acc = A.scratch + (((size_t)smp * A.l + lab) * A.k0 + ram) * (A.slots + 1) * RW;
+  uint32_t* acc = A.scratch + (((size_t)smp * A.nlab + lab) * A.k0 + ram) * (A.slots + 1) * RW;
   uint32_t* xin = acc + (size_t)A.slots * RW;
   auto xbit = [&](uint32_t u) -> const uint32_t* {
-    return A.x_rgsw + (gi * A.s + A.perm[ram * A.a + (u - A.L)]) * A.rgsw_words;
+    return A.x_rgsw + (gi * A.s + A.perm[ram * A.a + (u - TL)]) * A.rgsw_words;
   };
   uint32_t xc = 0;
-  if (z > A.L) {
-    // encrypted levels z-1 .. L over the leaves lab + (w << L); the clear
-    // levels below L then select leaf index lab exactly
+  if (z > TL) {
+    // encrypted levels z-1 .. TL over the leaves lab + (w << TL); the clear
+    // levels below TL then select leaf index lab exactly
 #pragma unroll 1
-    for (int lev = (int)z - 1; lev >= (int)A.L; --lev) {
+    for (int lev = (int)z - 1; lev >= (int)TL; --lev) {
       const uint32_t* C = xbit((uint32_t)lev);
-      const uint32_t cnt = 1u << (lev - A.L);
+      const uint32_t cnt = 1u << (lev - TL);
 #pragma unroll 1
       for (uint32_t w = 0; w < cnt; ++w) {
         const bool leaf = lev == (int)z - 1;
-        // leaves lab + 2^L w and lab + 2^L (w + cnt) are rows w l + lab and (w + cnt) l + lab
-        const uint32_t* lo = leaf ? H + (size_t)(w * A.l + lab) * RW : acc + (size_t)w * RW;
-        const uint32_t* hi = leaf ? H + (size_t)((w + cnt) * A.l + lab) * RW : acc + (size_t)(w + cnt) * RW;
+        // leaves lab + 2^TL w and lab + 2^TL (w + cnt) are rows w tl + lab and (w + cnt) tl + lab
+        const uint32_t* lo = leaf ? H + (size_t)(w * tl + lab) * RW : acc + (size_t)w * RW;
+        const uint32_t* hi = leaf ? H + (size_t)((w + cnt) * tl + lab) * RW : acc + (size_t)(w + cnt) * RW;
         uint32_t* dst = acc + (size_t)w * RW;
 #pragma unroll 1
         for (int pw = 0; pw < 2 * NQ; ++pw) {
@@ -848,7 +884,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
   for (uint32_t st = 0; st < nr; ++st) {
     const uint32_t u = z + st;
     const int32_t ex = -(1 << st);
-    if (u < A.L) {
+    if (A.layout && u >= aj) break;  // the label bits on top: clear zeros, no rotation
+    if (!A.layout && u < A.L) {
       if ((lab >> u) & 1u) {  // clear bit 1: exact rotation by X^{-2^st}
         rot_diff<LOGN, NQ>(T, acc, ex, xin, t);  // xin = X^ex acc - acc
         __syncthreads();
@@ -866,20 +903,29 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
     }
     cmux_rot<LOGN, NQ>(T, acc, ex, xbit(u), xin, lds, twl, xc, t);
   }
-  // ExtractLWE(acc, 0): a'_0 = a_0, a'_k = -a_{N-k}, b' = b_0
-  uint32_t* out = A.scores + ((gi * A.l + lab) * A.k0 + ram) * (size_t)NQ * (N + 1);
+  // ExtractLWE(acc, idx) for the class(es) of this workgroup: a'_k = a_{idx-k}
+  // for k <= idx, -a_{N+idx-k} above, b' = b_idx; idx = 0 for layout 0, c
+  // 2^(a_j - z) for class c of layout 1 (below 2^nr <= N)
+  const uint32_t nout = A.layout ? A.l : 1u;
 #pragma unroll 1
-  for (int i = 0; i < NQ; ++i) {
-    const uint32_t q = T.pt[i].q;
-    const uint32_t* a = acc + (size_t)i * N;
-    uint32_t* o = out + (size_t)i * (N + 1);
+  for (uint32_t cc = 0; cc < nout; ++cc) {
+    const uint32_t cls = A.layout ? cc : lab;
+    const uint32_t idx = A.layout ? cc << (aj - z) : 0u;
+    uint32_t* out = A.scores + ((gi * A.l + cls) * A.k0 + ram) * (size_t)NQ * (N + 1);
+#pragma unroll 1
+    for (int i = 0; i < NQ; ++i) {
+      const uint32_t q = T.pt[i].q;
+      const uint32_t* a = acc + (size_t)i * N;
+      uint32_t* o = out + (size_t)i * (N + 1);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const uint32_t k = t + TT * e;
-      const uint32_t x = a[(N - k) & (N - 1)];  // k = 0 reads a_0
-      (o + TT * e)[t] = (k == 0 || x == 0) ? x : q - x;
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t k = t + TT * e;
+        const bool lo = k <= idx;
+        const uint32_t x = a[lo ? idx - k : N + idx - k];
+        (o + TT * e)[t] = (lo || x == 0) ? x : q - x;
+      }
+      if (t == 0) o[N] = acc[(size_t)(NQ + i) * N + idx];
     }
-    if (t == 0) o[N] = acc[(size_t)(NQ + i) * N];
   }
 }
 
@@ -1265,10 +1311,10 @@ hipError_t launch_reduce_model(const Tabs& T, const ReduceArgs& A, hipStream_t s
 }
 
 hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int occ, hipStream_t st) {
-  const uint64_t G = (uint64_t)A.k0 * A.l * A.nsub;
+  const uint64_t G = (uint64_t)A.k0 * A.nlab * A.nsub;
   if (G == 0) return hipSuccess;
   if (G > (1u << 22)) return hipErrorInvalidValue;
-  const dim3 grid = A.map == 0 ? dim3(A.k0, A.l, A.nsub) : dim3((uint32_t)((G + 7) / 8 * 8));
+  const dim3 grid = A.map == 0 ? dim3(A.k0, A.nlab, A.nsub) : dim3((uint32_t)((G + 7) / 8 * 8));
   HW_DISPATCH_OCC(logN, nq, occ,
                   hipLaunchKernelGGL((k_infer<LN, NQ, OC>), grid, dim3(Geo<LN>::T), 0, st, T, A));
   return hipGetLastError();

@@ -46,7 +46,7 @@ class Params(C.Structure):
 
 
 class Shape(C.Structure):
-    _fields_ = [("s", C.c_uint32), ("l", C.c_uint32), ("a", C.c_uint32), ("reserved", C.c_uint32),
+    _fields_ = [("s", C.c_uint32), ("l", C.c_uint32), ("a", C.c_uint32), ("layout", C.c_uint32),
                 ("perm_seed", C.c_uint64)]
 
 
@@ -150,8 +150,13 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def shape(s: int, l: int, a: int, perm_seed: int) -> Shape:
-    return Shape(s, l, a, 0, perm_seed)
+LAYOUT_PRUNED, LAYOUT_PACKED = 0, 1
+
+
+def shape(s: int, l: int, a: int, perm_seed: int, layout: int = LAYOUT_PRUNED) -> Shape:
+    """layout 0: label-pruned model rows (Def. 2); 1: class-packed rows (one
+    VP per RAM at inference gives the scores of every class)"""
+    return Shape(s, l, a, layout, perm_seed)
 
 
 def permutation(sh: Shape) -> np.ndarray:

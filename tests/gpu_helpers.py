@@ -41,7 +41,7 @@ class Pair:
     """Seeded WiSARD workload on both sides.  Seeds: key, input-bit
     encryption, label-bit encryption, permutation."""
 
-    def __init__(self, N, nq, p, s, l, a, X, y, seed=7):
+    def __init__(self, N, nq, p, s, l, a, X, y, seed=7, layout=0):
         from paper_2403_20190_amd import hwisard as HW
         self.HW = HW
         self.N, self.nq, self.p, self.s, self.l, self.a = N, nq, p, s, l, a
@@ -51,7 +51,8 @@ class Pair:
         self.seed_key, self.seed_x, self.seed_y, self.seed_perm = seed * 4 + 1, seed * 4 + 2, seed * 4 + 3, seed * 4 + 4
         self.ctx = HW.Context(N, nq, p)
         self.orc = O.Ctx(N, nq, p)
-        self.shape = HW.shape(s, l, a, self.seed_perm)
+        self.layout = layout
+        self.shape = HW.shape(s, l, a, self.seed_perm, layout)
         self.k0, self.k1, _ = self.ctx.dims(self.shape)
         self.pi = O.permutation(self.seed_perm, s)
         self.sk_o = self.orc.keygen(self.seed_key)
@@ -99,5 +100,5 @@ class Pair:
                 for t in range(min(self.a, self.s - j * self.a))]
         O._parallel(lambda ik: self.xo(*ik), need)
         O._parallel(lambda iu: self.yo(*iu), [(i, u) for i in range(n) for u in range(self.L)])
-        self.orc.train(self.s, self.l, self.a, self.pi, self.xo, self.yo, n, H, rams=rams)
+        self.orc.train(self.s, self.l, self.a, self.pi, self.xo, self.yo, n, H, rams=rams, layout=self.layout)
         return H

@@ -1,0 +1,171 @@
+"""GPU parity of the class-packed model layout (horizontal packing across
+discriminators): training with the index [tuple bits, label bits] and every
+tree leaf kept, and inference by one VP per RAM whose accumulator holds the
+cell of every class, each bit-exact against the oracle; the decrypted cells
+equal the plaintext Integer WiSARD and the label-pruned layout's scores."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import plain as P
+from gpu_helpers import Pair, host_u32, host_u64, zeros_u32, zeros_u64
+from paper_2403_20190_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def train_dev(pair, class_count=True):
+    xr = pair.encrypt_dev()
+    yr = pair.encrypt_labels_dev()
+    H = zeros_u32(pair.k0, pair.k1, 2, pair.nq, pair.N)
+    cnt = zeros_u32(2, pair.nq, pair.N) if class_count else None
+    pair.ctx.train(pair.shape, xr, yr, pair.n, H, cnt)
+    return H, cnt, xr, yr
+
+
+def decrypt_model(pair, H):
+    cnt = pair.k0 * pair.k1
+    out = zeros_u64(cnt, pair.N)
+    pair.ctx.decrypt_rlwe(pair.sk, H, cnt, out)
+    return host_u64(out).reshape(pair.k0, pair.k1, pair.N).astype(np.int64)
+
+
+def decrypt_scores(pair, scores, n):
+    cnt = n * pair.l * pair.k0
+    dec = zeros_u64(cnt)
+    pair.ctx.decrypt_lwe(pair.sk, scores, cnt, dec)
+    return host_u64(dec).reshape(n, pair.l, pair.k0).astype(np.int64)
+
+
+SHAPES = [
+    dict(N=1024, nq=1, p=64, s=128, l=2, a=8, n=4),    # nb = 9 <= log N: no tree, a chain of 8 tuple bits
+    dict(N=1024, nq=2, p=64, s=30, l=3, a=11, n=3),    # z = 3 tuple bits in the tree; ragged last tuple (8 bits)
+    dict(N=2048, nq=1, p=32, s=20, l=1, a=7, n=2),     # l = 1: no label bits; ragged last tuple
+    dict(N=4096, nq=2, p=64, s=14, l=5, a=14, n=2),    # z = 5, single RAM, 5 classes at stride 2^9
+]
+
+
+@pytest.mark.parametrize("cfg", SHAPES)
+def test_packed_training_and_inference_bit_exact(cfg):
+    cfg = dict(cfg)
+    n = cfg.pop("n")
+    X, y = synth.prototype_bits(11, n, cfg["s"], cfg["l"], flip=0.2)
+    pair = Pair(X=X, y=y, seed=9, layout=1, **cfg)
+    nb = pair.L + pair.a
+    assert pair.k1 == 1 << max(0, nb - (pair.N.bit_length() - 1))
+    assert pair.k1 == pair.orc.k1(pair.s, pair.l, pair.a, 1)
+    H, cnt, _, _ = train_dev(pair)
+    Ho = pair.oracle_train(range(pair.k0))
+    assert np.array_equal(host_u32(H), Ho)
+    if pair.L:
+        cnt_o = np.zeros((2, pair.nq, pair.N), np.uint32)
+        pair.orc.class_count(pair.l, pair.yo, pair.n, cnt_o)
+        assert np.array_equal(host_u32(cnt), cnt_o)
+    W = P.train_integer(pair.X, pair.y, pair.l, pair.a, pair.pi)
+    assert np.array_equal(decrypt_model(pair, H),
+                          P.expected_model_cells(W, pair.s, pair.l, pair.a, pair.N, layout=1))
+    nt = 2
+    Xt, _ = synth.prototype_bits(12, nt, cfg["s"], cfg["l"], flip=0.3)
+    xt = pair.encrypt_dev(Xt, seed_x=56)
+    scores = zeros_u32(nt, pair.l, pair.k0, pair.orc.lwe_words)
+    sums = zeros_u32(nt, pair.l, pair.orc.lwe_words)
+    pair.ctx.infer(pair.shape, H, xt, nt, scores, sums)
+    got = host_u32(scores).reshape(nt, pair.l, pair.k0, pair.nq, pair.N + 1)
+    want = {}
+    jobs = [(i, j) for i in range(nt) for j in range(pair.k0)]
+    O._parallel(lambda ij: want.__setitem__(ij, pair.orc.infer_packed(
+        pair.s, pair.l, pair.a, pair.pi, Ho, lambda k: pair.xo(ij[0], k, Xt, 56, "t"), ij[1])), jobs)
+    for i, j in jobs:
+        for c in range(pair.l):
+            assert np.array_equal(got[i, c, j], want[(i, j)][c]), (i, c, j)
+    gsum = host_u32(sums).reshape(nt, pair.l, pair.nq, pair.N + 1)
+    for i in range(nt):
+        for c in range(pair.l):
+            acc = want[(i, 0)][c]
+            for j in range(1, pair.k0):
+                acc = pair.orc.lwe_add(acc, want[(i, j)][c])
+            assert np.array_equal(gsum[i, c], acc)
+    cells = decrypt_scores(pair, scores, nt)
+    for i in range(nt):
+        assert np.array_equal(cells[i], P.ram_scores(W, Xt[i], pair.a, pair.pi))
+
+
+def test_packed_inference_schedules_agree():
+    """every schedule variant of the inference kernel gives the same bits"""
+    X, y = synth.prototype_bits(13, 3, 40, 4, flip=0.2)
+    pair = Pair(1024, 2, 64, 40, 4, 10, X, y, seed=10, layout=1)
+    H, _, _, _ = train_dev(pair, class_count=False)
+    Xt, _ = synth.prototype_bits(14, 3, 40, 4, flip=0.3)
+    xt = pair.encrypt_dev(Xt, seed_x=57)
+    _, _, nvar = pair.ctx.tune_get("infer")
+    outs = []
+    for v in range(nvar):
+        pair.ctx.tune_set("infer", v)
+        scores = zeros_u32(3, pair.l, pair.k0, pair.orc.lwe_words)
+        pair.ctx.infer(pair.shape, H, xt, 3, scores, None)
+        outs.append(host_u32(scores))
+    pair.ctx.tune_set("infer", -1)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_packed_batch_equals_single_job():
+    """batched training over a mix of layouts equals the per-job calls"""
+    from paper_2403_20190_amd import hwisard as HW
+    ctx = HW.Context(1024, 2, 64)
+    jobs, refs = [], []
+    base = None
+    for k, (s, l, a, n, layout) in enumerate([(40, 4, 10, 3, 1), (23, 3, 11, 2, 0), (23, 3, 11, 2, 1),
+                                              (17, 1, 6, 2, 1)]):
+        X, y = synth.prototype_bits(30 + k, n, s, l, flip=0.2)
+        pair = Pair(1024, 2, 64, s, l, a, X, y, seed=20 + k, layout=layout)
+        if base is None:
+            base = pair
+        pair.ctx, pair.sk, pair.sk_o = ctx, base.sk, base.sk_o
+        xr, yr = pair.encrypt_dev(), pair.encrypt_labels_dev()
+        H = zeros_u32(pair.k0, pair.k1, 2, 2, 1024)
+        Cn = zeros_u32(2, 2, 1024)
+        jobs.append((pair.shape, xr, yr, n, H, Cn))
+        H1, C1 = zeros_u32(pair.k0, pair.k1, 2, 2, 1024), zeros_u32(2, 2, 1024)
+        ctx.train(pair.shape, xr, yr, n, H1, C1)
+        refs.append((H1, C1, pair))
+    ctx.batch_train(jobs)
+    for j, (H1, C1, pair) in zip(jobs, refs):
+        assert np.array_equal(host_u32(j[4]), host_u32(H1)), pair.shape.layout
+        assert np.array_equal(host_u32(j[5]), host_u32(C1))
+    # the class-packed job of the batch against the oracle
+    H1, _, pair = refs[2]
+    assert np.array_equal(host_u32(jobs[2][4]), pair.oracle_train(range(pair.k0)))
+
+
+def test_mnist_shape_packed_sampled():
+    """MNIST shape (N = 2048, a = 12, l = 10): k1 = 2^5 rows; sampled RAMs
+    against the oracle, every cell by decryption, and the same decrypted
+    scores as the label-pruned layout's inference."""
+    from paper_2403_20190_amd import client as CL
+    Xtr, ytr, Xte, _ = synth.mnist_like(1, per_class_train=1, per_class_test=1)
+    bits = CL.thermometer(CL.quantize_u8(Xtr[:2], 3), 3)
+    pair = Pair(2048, 2, 1024, 2352, 10, 12, bits, ytr[:2], seed=3, layout=1)
+    assert (pair.k0, pair.k1) == (196, 32)
+    H, _, _, _ = train_dev(pair, class_count=False)
+    rams = [0, 195]
+    Ho = pair.oracle_train(rams)
+    Hg = host_u32(H)
+    for j in rams:
+        assert np.array_equal(Hg[j], Ho[j]), j
+    W = P.train_integer(pair.X, pair.y, pair.l, pair.a, pair.pi)
+    assert np.array_equal(decrypt_model(pair, H),
+                          P.expected_model_cells(W, pair.s, pair.l, pair.a, pair.N, layout=1))
+    tb = CL.thermometer(CL.quantize_u8(Xte[:1], 3), 3)
+    xt = pair.encrypt_dev(tb, seed_x=77)
+    scores = zeros_u32(1, 10, 196, pair.orc.lwe_words)
+    pair.ctx.infer(pair.shape, H, xt, 1, scores, None)
+    got = host_u32(scores).reshape(1, 10, 196, 2, 2049)
+    want = {}
+    O._parallel(lambda j: want.__setitem__(j, pair.orc.infer_packed(
+        pair.s, pair.l, pair.a, pair.pi, Ho, lambda k: pair.xo(0, k, tb, 77, "t"), j)), rams)
+    for j in rams:
+        for c in range(10):
+            assert np.array_equal(got[0, c, j], want[j][c]), (c, j)
+    cells = decrypt_scores(pair, scores, 1)[0]
+    assert np.array_equal(cells, P.ram_scores(W, tb[0], pair.a, pair.pi))

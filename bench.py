@@ -291,7 +291,8 @@ def main():
     del xr, yr, xb, yb
     torch.cuda.empty_cache()
     if not args.no_extras:
-        result["inference"] = infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev)
+        result["inference"], cells0 = infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev)
+        result["class_packed"] = packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev)
         result["merge"] = merge_pass(ctx, H, k0, k1)
         result["ntt"] = ntt_pass(ctx, N, nq, dev)
         result["hbm_copy_gbs"] = hbm_copy(dev)
@@ -306,14 +307,13 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
-    """Encrypted inference of the test set (device encryption + VP + PD-act)."""
+def infer_loop(ctx, sh, H, sk, bits, W, seeds, k0, dev):
+    """device encryption + inference + decryption of the test bits, chunk by
+    chunk: (decrypted cells [nt][l][k0], seconds, infer kernel ms, XP, the
+    last chunk's scores)"""
     import numpy as np
     import torch
-
-    from paper_2403_20190_amd import client as CL
-    T, l = W["T"], W["l"]
-    bits = CL.thermometer(CL.quantize_u8(Xte[:W["n_test"]], T), T)
+    l = W["l"]
     nt, s = bits.shape
     xb = torch.from_numpy(bits).to(dev)
     chunk = max(1, W["chunk"])
@@ -335,6 +335,20 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
     dt = time.perf_counter() - t0
     inf_ms, inf_launch, inf_xp = ctx.profile_read("infer")
     ctx.profile(False)
+    return cells, dt, inf_ms, inf_xp, scores
+
+
+def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
+    """Encrypted inference of the test set (device encryption + VP + PD-act)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_20190_amd import client as CL
+    T, l = W["T"], W["l"]
+    bits = CL.thermometer(CL.quantize_u8(Xte[:W["n_test"]], T), T)
+    nt = len(bits)
+    chunk = max(1, W["chunk"])
+    cells, dt, inf_ms, inf_xp, scores = infer_loop(ctx, sh, H, sk, bits, W, seeds, k0, dev)
     # PackingKeySwitching of the last chunk's scores: l k0 LWE -> one RLWE per
     # sample (when l k0 <= N), decrypting to the same cells
     packed = None
@@ -371,6 +385,64 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
                      "frac": round(tops / PEAK_INT32_TOPS, 4)},
         "n_test": nt, "pd_act": "bin", "test_accuracy": round(acc, 4),
         "packing": packed,
+    }, cells
+
+
+def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev):
+    """The class-packed model layout (horizontal packing across
+    discriminators) on the same data and key: training with the index [tuple
+    bits, label bits] (every tree leaf kept), then inference by one VP per
+    RAM that yields the scores of all classes.  Reports the training and
+    inference kernel rates and whether the decrypted scores equal those of
+    the label-pruned layout."""
+    import numpy as np
+    import torch
+
+    from paper_2403_20190_amd import client as CL
+    from paper_2403_20190_amd import hwisard as HW
+    N, nq, l, a, T = W["N"], W["nq"], W["l"], W["a"], W["T"]
+    n, s = bits_tr.shape
+    L = CL.ceil_log2(l)
+    sh = HW.shape(s, l, a, seeds["perm"], HW.LAYOUT_PACKED)
+    k0, k1, model_bytes = ctx.dims(sh)
+    chunk = W["chunk"]
+    xb = torch.from_numpy(bits_tr).to(dev)
+    yb = torch.from_numpy(lab_tr).to(dev)
+    xr = torch.empty(chunk * s, ctx.rgsw_words, dtype=torch.int32, device=dev)
+    yr = torch.empty(max(1, chunk * L), ctx.rgsw_words, dtype=torch.int32, device=dev)
+    H = torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev)
+    ctx.profile(True)
+    ctx.profile_reset()
+    for c0 in range(0, n, chunk):
+        m = min(chunk, n - c0)
+        ctx.encrypt_rgsw_bits(sk, xb[c0:c0 + m].reshape(-1), seeds["x"], c0 * s, xr[:m * s])
+        if L:
+            ctx.encrypt_rgsw_bits(sk, yb[c0:c0 + m].reshape(-1), seeds["y"], c0 * L, yr[:m * L])
+        ctx.train(sh, xr, yr, m, H, None)
+    torch.cuda.synchronize()
+    tr_ms, _, tr_xp = ctx.profile_read("train")
+    rd_ms, _, _ = ctx.profile_read("reduce")
+    ctx.profile(False)
+    del xr, yr, xb, yb
+    bits = CL.thermometer(CL.quantize_u8(Xte[:W["n_test"]], T), T)
+    nt = len(bits)
+    cells, dt, inf_ms, inf_xp, _ = infer_loop(ctx, sh, H, sk, bits, W, seeds, k0, dev)
+    del H
+    torch.cuda.empty_cache()
+    opx = ops_per_xp(N, nq)
+    tops = inf_xp * opx / (inf_ms / 1000.0) / 1e12 if inf_ms else 0.0
+    return {
+        "k1": k1, "model_mib": round(model_bytes / 2**20, 1),
+        "train_kernel_samples_per_s": round(n / (tr_ms / 1000.0), 3) if tr_ms else None,
+        "train_xp_per_sample": round(tr_xp / n, 1),
+        "reduce_ms": round(rd_ms, 2),
+        "infer_samples_per_s": round(nt / dt, 3),
+        "infer_kernel_samples_per_s": round(nt / (inf_ms / 1000.0), 3) if inf_ms else None,
+        "infer_xp_per_sample": round(inf_xp / nt, 1),
+        "infer_roofline": {"bound": "alu", "kernel": "k_infer (class-packed)", "achieved": round(tops, 3),
+                           "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOPS(int32)",
+                           "frac": round(tops / PEAK_INT32_TOPS, 4)},
+        "scores_equal_label_pruned": bool(np.array_equal(cells, cells0)),
     }
 
 

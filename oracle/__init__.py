@@ -88,7 +88,10 @@ def lib():
                                      C.POINTER(C.c_void_p), C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                      u32p]),
                 "orc_infer_packed": (None, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, u32p, u32p,
-                                            C.POINTER(C.c_void_p), C.c_uint32, u32p]),
+                                            C.POINTER(C.c_void_p), C.c_uint32, C.c_uint32, u32p]),
+                "orc_rams_per_row": (C.c_uint32, [C.c_void_p, C.c_uint32, C.c_uint32]),
+                "orc_model_rows": (C.c_uint32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]),
+                "orc_pack_rams": (None, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32, u32p, u32p]),
                 "orc_extract_lwe": (None, [C.c_void_p, u32p, C.c_uint32, u32p]),
                 "orc_vp_rlwe": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_uint8), C.c_uint32, u32p,
                                        u32p]),
@@ -503,16 +506,32 @@ class Ctx:
         return out
 
 
-    def infer_packed(self, s, l, a, pi, H, x_get, j) -> np.ndarray:
+    def rams_per_row(self, l: int, a: int) -> int:
+        return int(lib().orc_rams_per_row(self.h, l, a))
+
+    def model_rows(self, s: int, l: int, a: int, layout: int) -> int:
+        return int(lib().orc_model_rows(self.h, s, l, a, layout))
+
+    def pack_rams(self, s, l, a, H1) -> np.ndarray:
+        """layout-2 rows from class-packed rows: row R = sum_t X^(t 2^(L+a)) H1[R r + t]"""
+        H1 = np.ascontiguousarray(H1, np.uint32)
+        k1 = self.k1(s, l, a, 1)
+        out = np.zeros((self.model_rows(s, l, a, 2), k1, 2, self.nq, self.N), np.uint32)
+        lib().orc_pack_rams(self.h, s, l, a, _p(H1, u32p), _p(out, u32p))
+        return out
+
+    def infer_packed(self, s, l, a, pi, H, x_get, j, layout=1) -> np.ndarray:
         """class-packed inference of RAM j for one sample: one VP, then the
-        LWE of every class, [l][nq][N+1]; x_get(k) -> RGSW of bit k."""
+        LWE of every class, [l][nq][N+1]; x_get(k) -> RGSW of bit k.  layout
+        2 reads RAM j from its block of row j / r."""
         pi = np.ascontiguousarray(pi, np.uint32)
         xs = [None] * s
         for t in range(min(a, s - j * a)):
             k = int(pi[j * a + t])
             xs[k] = np.ascontiguousarray(x_get(k), np.uint32)
         out = np.zeros((l, self.nq, self.N + 1), np.uint32)
-        lib().orc_infer_packed(self.h, s, l, a, _p(pi, u32p), _p(H, u32p), _ptr_array(xs), j, _p(out, u32p))
+        lib().orc_infer_packed(self.h, s, l, a, _p(pi, u32p), _p(H, u32p), _ptr_array(xs), j, layout,
+                               _p(out, u32p))
         return out
 
 

@@ -956,11 +956,54 @@ uint32_t orc_k1(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a) {
  * brings the cells of all classes to coefficients c 2^(a_j - z). */
 uint32_t orc_k1_layout(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, uint32_t layout) {
   if (layout == 0) return orc_k1(c, s, l, a);
+  /* layouts 1 and 2: every tree leaf */
   uint32_t aj, nb, z;
   ram_geometry(c, s, l, a, 0, &aj, &nb, &z);
   (void)aj;
   (void)nb;
   return 1u << z;
+}
+
+/* Several small RAMs per RLWE (layout 2, the other half of horizontal
+ * packing): with nb = L + a index bits and 2^nb < N, r = N / 2^nb RAMs share
+ * a model row, RAM j at coefficient offset (j mod r) 2^nb of row j / r.
+ * Built from the class-packed rows H1 (one RLWE per RAM, since z = 0) as
+ * row R = sum_t X^(t 2^nb) H1[R r + t] over the RAMs of the row.  Rotation
+ * by a monomial and addition are exact, so the packed rows of a model
+ * trained sample by sample equal the packed rows of its sum. */
+uint32_t orc_rams_per_row(const orc_ctx* c, uint32_t l, uint32_t a) {
+  uint32_t nb = ceil_log2_u(l) + a;
+  return nb < c->logN ? 1u << (c->logN - nb) : 1u;
+}
+
+uint32_t orc_model_rows(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, uint32_t layout) {
+  uint32_t k0 = (s + a - 1) / a;
+  if (layout != 2) return k0;
+  uint32_t r = orc_rams_per_row(c, l, a);
+  return (k0 + r - 1) / r;
+}
+
+void orc_pack_rams(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const uint32_t* H1, uint32_t* Hp) {
+  size_t rw = rlwe_words(c);
+  uint32_t k0 = (s + a - 1) / a;
+  uint32_t k1 = orc_k1_layout(c, s, l, a, 1);
+  uint32_t r = orc_rams_per_row(c, l, a);
+  uint32_t rows = orc_model_rows(c, s, l, a, 2);
+  int64_t stride = (int64_t)1 << (ceil_log2_u(l) + a);
+  if (r == 1) {
+    memcpy(Hp, H1, sizeof(uint32_t) * rw * k1 * k0);
+    return;
+  }
+  uint32_t* rot = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  for (uint32_t R = 0; R < rows; ++R) {
+    uint32_t* dst = Hp + (size_t)R * rw;
+    memset(dst, 0, sizeof(uint32_t) * rw);
+    for (uint32_t t = 0; t < r && R * r + t < k0; ++t) {
+      orc_rlwe_rotate(c, H1 + (size_t)(R * r + t) * rw, (int64_t)t * stride, rot);
+      rlwe_add(c, dst, rot, dst);
+    }
+  }
+  free(rot);
 }
 
 /* Homomorphic training (Alg. 6) restricted to RAMs [ram_lo, ram_hi):
@@ -1064,9 +1107,15 @@ void orc_infer_one(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const u
  * and out[c] = ExtractLWE(acc, c 2^(a_j - z)) for c < l (the scores Alg. 7
  * computes per label, all from one evaluation).  out: [l] LWE. */
 void orc_infer_packed(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, const uint32_t* pi,
-                      const uint32_t* H, const uint32_t* const* x_ptr, uint32_t j, uint32_t* out) {
+                      const uint32_t* H, const uint32_t* const* x_ptr, uint32_t j, uint32_t layout,
+                      uint32_t* out) {
   size_t rw = rlwe_words(c);
   uint32_t k1 = orc_k1_layout(c, s, l, a, 1);
+  /* layout 2: RAM j is the (j mod r)-th block of 2^(L + a) coefficients of
+   * row j / r; the VP's rotations move only within it */
+  uint32_t r = layout == 2 ? orc_rams_per_row(c, l, a) : 1u;
+  uint32_t row = j / r;
+  uint32_t off = (j % r) << (ceil_log2_u(l) + a);
   uint32_t aj, nb, z;
   ram_geometry(c, s, l, a, j, &aj, &nb, &z);
   /* the VP over all nb index bits with the label bits as cleartext zeros: z
@@ -1076,10 +1125,10 @@ void orc_infer_packed(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, cons
   uint8_t* clear = (uint8_t*)calloc(nb + 1, 1);
   for (uint32_t t = 0; t < aj; ++t) bits[t] = x_ptr[pi[j * a + t]];
   uint32_t* acc = (uint32_t*)malloc(sizeof(uint32_t) * rw);
-  orc_vp_rlwe(c, bits, clear, nb, H + (size_t)j * k1 * rw, acc);
+  orc_vp_rlwe(c, bits, clear, nb, H + (size_t)row * k1 * rw, acc);
   uint32_t stride = 1u << (aj - z);
   for (uint32_t cl = 0; cl < l; ++cl)
-    orc_extract_lwe(c, acc, cl * stride, out + (size_t)cl * c->nq * (c->N + 1));
+    orc_extract_lwe(c, acc, off + cl * stride, out + (size_t)cl * c->nq * (c->N + 1));
   free(acc);
   free(bits);
   free(clear);

@@ -157,7 +157,9 @@ def expected_model_cells(W: np.ndarray, s: int, l: int, a: int, N: int, layout: 
     d = m mod 2^z_j of RAM j holds W[c][j][addr] at coefficient m >> z_j, and
     leaf d is row model_row(d) of H[j].  Layout 1 (class-packed): with
     m = addr + 2^a_j c, row m mod 2^z_j holds it at coefficient m >> z_j.
-    Every other cell is 0."""
+    Layout 2 (several RAMs per row, when 2^(L+a) < N): RAM j's layout-1 row
+    sits at offset (j mod r) 2^(L+a) of row j / r, r = N / 2^(L+a); the
+    result has shape [ceil(k0 / r)][1][N].  Every other cell is 0."""
     L = ceil_log2(l)
     logN = N.bit_length() - 1
     k0 = -(-s // a)
@@ -167,6 +169,16 @@ def expected_model_cells(W: np.ndarray, s: int, l: int, a: int, N: int, layout: 
         k1 = l << (z0 - L) if z0 >= L else 1 << z0
     else:
         k1 = 1 << z0
+    if layout == 2:
+        one = expected_model_cells(W, s, l, a, N, layout=1)
+        r = N >> nb_full if nb_full < logN else 1
+        if r == 1:
+            return one
+        out = np.zeros((-(-k0 // r), 1, N), np.int64)
+        for j in range(k0):
+            off = (j % r) << nb_full
+            out[j // r, 0, off:off + (1 << nb_full)] = one[j, 0, :1 << nb_full]
+        return out
     out = np.zeros((k0, k1, N), np.int64)
     for j in range(k0):
         aj = min(a, s - j * a)

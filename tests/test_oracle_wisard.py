@@ -192,6 +192,40 @@ def test_class_packed_inference_scores(cfg):
             assert P.pd_act_predict(cells, kind) == P.predict(W, Xt[t], m.a, m.pi, kind)
 
 
+RAM_PACKED = [
+    dict(N=16, s=9, l=2, a=2, n=5),    # 2^(L+a) = 8: two RAMs per row; ragged last tuple, a half-empty last row
+    dict(N=32, s=12, l=3, a=2, n=6),   # 2^(L+a) = 16: two RAMs per row, l = 3 leaves a class block empty
+    dict(N=64, s=10, l=1, a=3, n=4),   # l = 1: 2^a = 8, eight RAMs per row
+]
+
+
+@pytest.mark.parametrize("cfg", RAM_PACKED)
+def test_several_rams_per_row(cfg):
+    """Layout 2: packing the class-packed rows of r = N / 2^(L+a) RAMs into
+    one RLWE puts every Alg. 4 count at offset (j mod r) 2^(L+a) of row
+    j / r, and the VP of each RAM over its block gives the Alg. 2 scores."""
+    m = Micro(**cfg, layout=1)
+    H1 = m.train()
+    r = m.c.rams_per_row(m.l, m.a)
+    assert r == m.c.N >> (m.L + m.a) and r >= 2
+    rows = m.c.model_rows(m.s, m.l, m.a, 2)
+    assert rows == -(-m.k0 // r)
+    H2 = m.c.pack_rams(m.s, m.l, m.a, H1)
+    W = P.train_integer(m.X, m.y, m.l, m.a, m.pi)
+    want = P.expected_model_cells(W, m.s, m.l, m.a, m.c.N, layout=2)
+    got = np.stack([[m.c.dec_rlwe(m.sk, H2[R, 0])] for R in range(rows)])
+    assert np.array_equal(got.astype(np.int64), want)
+    Xt, _ = synth.prototype_bits(52, 2, m.s, m.l, flip=0.3)
+    for t in range(2):
+        xr = m.c.enc_rgsw_bits(m.sk, Xt[t], 700 + t, 0)
+        cells = np.zeros((m.l, m.k0), np.int64)
+        for j in range(m.k0):
+            lw = m.c.infer_packed(m.s, m.l, m.a, m.pi, H2, lambda k: xr[k], j, layout=2)
+            for c in range(m.l):
+                cells[c, j] = m.c.dec_lwe(m.sk, lw[c])
+        assert np.array_equal(cells, P.ram_scores(W, Xt[t], m.a, m.pi))
+
+
 def test_extract_lwe_any_index():
     """ExtractLWE(c, i) decrypts to coefficient i of c's phase for every i,
     the phase taken by the negacyclic product of the decryption."""

@@ -76,6 +76,13 @@ typedef struct {
  *      every class to coefficient c 2^(a_j - z) and inference extracts all l
  *      scores from it.  Same scores, fewer external products at inference,
  *      more at training when l < 2^L.
+ *   2  class-packed rows with several RAMs per row: when 2^(L+a) < N, the
+ *      r = N / 2^(L+a) RAMs j = R r + t share model row R, RAM j's layout-1
+ *      row rotated by X^(t 2^(L+a)); the model is [ceil(k0 / r)][1] RLWE
+ *      (hw_wisard_model_rows).  Same scores and external products as
+ *      layout 1, r times less model memory.  With r = 1 it is layout 1.
+ *      Batched training rejects it (its rows are written in place per RAM);
+ *      batch-train layout 1 and convert with hw_wisard_pack_rams.
  * Other values are rejected (HW_EINVAL). */
 typedef struct {
   uint32_t s;
@@ -110,10 +117,26 @@ hw_status hw_sizes(const hw_ctx* ctx, uint64_t* rlwe_bytes, uint64_t* rgsw_bytes
  * layout 0 keeps the ciphertexts that hold a class below l (leaf
  * d = c + 2^L w holds class c and goes to row w l + c), so
  * k1 = l 2^(z-L) = ceil(l 2^a / N) when z >= L, and k1 = 2^z otherwise;
- * layout 1 keeps all k1 = 2^z leaves.
- * model_bytes is the size of H = [k0][k1] RLWE. */
+ * layouts 1 and 2 keep all k1 = 2^z leaves.
+ * model_bytes is the size of H = [rows][k1] RLWE (rows = k0 except for
+ * layout 2, see hw_wisard_model_rows). */
 hw_status hw_wisard_dims(const hw_ctx* ctx, const hw_wisard_shape* shape, uint32_t* k0,
                          uint32_t* k1, uint64_t* model_bytes);
+
+/* Rows of the model and RAMs per row: (k0, 1) for layouts 0 and 1;
+ * (ceil(k0 / r), r) for layout 2 with r = N / 2^(L+a) when 2^(L+a) < N. */
+hw_status hw_wisard_model_rows(const hw_ctx* ctx, const hw_wisard_shape* shape, uint32_t* rows,
+                               uint32_t* rams_per_row);
+
+/* Layout-2 model from the class-packed rows of the same WiSARD (the
+ * horizontal packing of several RAMs into one RLWE, Sec. 5.1): row R of
+ * model_out = sum over t < r, R r + t < k0 of X^(t 2^(L+a)) model_in[R r + t].
+ * shape: the layout-2 shape; model_in: [k0][k1] RLWE trained with layout 1
+ * (same s, l, a, perm_seed); model_out: [rows][k1] RLWE, overwritten, not
+ * overlapping model_in.  Exact: training into layout 2 directly gives the
+ * same bits.  Models of layout 2 merge with hw_rlwe_add like any other. */
+hw_status hw_wisard_pack_rams(hw_ctx* ctx, const hw_wisard_shape* shape, const uint32_t* model_in,
+                              uint32_t* model_out, hipStream_t stream);
 
 /* The permutation pi_r of Def. 1 for `shape` (host output, s entries):
  * Fisher-Yates driven by the library's counter-based generator; the permuted

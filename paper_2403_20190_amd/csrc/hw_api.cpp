@@ -293,7 +293,7 @@ uint32_t ivp_xp(uint32_t nb, int logN, uint32_t L, uint32_t l) {
 
 hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d) {
   if (!sh) return fail(HW_EINVAL, "null shape");
-  if (sh->layout > 1) return fail(HW_EINVAL, "shape.layout = %u: must be 0 or 1", sh->layout);
+  if (sh->layout > 2) return fail(HW_EINVAL, "shape.layout = %u: must be 0, 1 or 2", sh->layout);
   if (sh->s < 1 || sh->s > (1u << 24)) return fail(HW_EINVAL, "s = %u out of range [1, 2^24]", sh->s);
   if (sh->l < 1 || sh->l > 256) return fail(HW_EINVAL, "l = %u out of range [1, 256]", sh->l);
   if (sh->a < 1 || sh->a > 20) return fail(HW_EINVAL, "a = %u out of range [1, 20]", sh->a);
@@ -307,6 +307,9 @@ hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d) {
   d->pL = sh->layout ? 0u : d->L;
   d->pl = sh->layout ? 1u : sh->l;
   d->k1 = live_rows(d->z, d->pL, d->pl);
+  d->nbf = nb;
+  d->rpr = sh->layout == 2 && nb < (uint32_t)c->logN ? 1u << (c->logN - nb) : 1u;
+  d->rows = (d->k0 + d->rpr - 1) / d->rpr;
   return HW_OK;
 }
 
@@ -342,7 +345,18 @@ extern "C" hw_status hw_wisard_dims(const hw_ctx* c, const hw_wisard_shape* sh, 
   if (st) return st;
   if (k0) *k0 = d.k0;
   if (k1) *k1 = d.k1;
-  if (model_bytes) *model_bytes = (uint64_t)d.k0 * d.k1 * 4 * rlwe_words(c);
+  if (model_bytes) *model_bytes = (uint64_t)d.rows * d.k1 * 4 * rlwe_words(c);
+  return ok();
+}
+
+extern "C" hw_status hw_wisard_model_rows(const hw_ctx* c, const hw_wisard_shape* sh, uint32_t* rows,
+                                          uint32_t* rams_per_row) {
+  if (!c) return fail(HW_EINVAL, "null context");
+  Dims d;
+  hw_status st = check_shape(c, sh, &d);
+  if (st) return st;
+  if (rows) *rows = d.rows;
+  if (rams_per_row) *rams_per_row = d.rpr;
   return ok();
 }
 
@@ -587,8 +601,26 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
     };
     HIP_TRY(tm ? timed(c, "train", xp, st, lt) : lt());
     R.n_sub = m;
-    auto lr = [&] { return hw::launch_reduce_model(c->tabs, R, st); };
-    HIP_TRY(tm ? timed(c, "reduce", (double)d.k0 * d.k1 * rw, st, lr) : lr());
+    hw::RowPackArgs P{};
+    const bool rowpack = d.rpr > 1;  // layout 2 with several RAMs per row (then z = 0)
+    if (rowpack) {  // one leaf per RAM: slot 0 of each block, rotated into its row
+      P.src = ws;
+      P.rstride = (uint64_t)(d.kt + 1) * rw;
+      P.sstride = (uint64_t)(d.k0 + 1) * P.rstride;
+      P.nsmp = m;
+      P.dst = model;
+      P.cnt = class_count;
+      P.k0 = d.k0;
+      P.rpr = d.rpr;
+      P.nbf = d.nbf;
+      P.rows = d.rows;
+      P.N = c->prm.N;
+      P.nq = c->prm.nq;
+    }
+    auto lr = [&] {
+      return rowpack ? hw::launch_row_pack(c->tabs, P, st) : hw::launch_reduce_model(c->tabs, R, st);
+    };
+    HIP_TRY(tm ? timed(c, "reduce", (double)d.rows * d.k1 * rw, st, lr) : lr());
   }
   return HW_OK;
 }
@@ -640,6 +672,8 @@ hw_status infer_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   A.slots = slots;
   A.layout = d.layout;
   A.nlab = nlab;
+  A.rpr = d.rpr;
+  A.nbf = d.layout == 2 ? d.nbf : 0u;
   const bool tm = timing && c->prof;
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
     const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
@@ -753,6 +787,38 @@ extern "C" hw_status hw_rlwe_add(hw_ctx* c, uint32_t* dst, const uint32_t* src, 
   return ok();
 }
 
+extern "C" hw_status hw_wisard_pack_rams(hw_ctx* c, const hw_wisard_shape* sh, const uint32_t* model_in,
+                                         uint32_t* model_out, hipStream_t st) {
+  CHECK(enter(c));
+  Dims d;
+  CHECK(check_shape(c, sh, &d));
+  if (d.layout != 2) return fail(HW_EINVAL, "shape.layout must be 2 (the layout of model_out)");
+  if (!model_in || !model_out) return fail(HW_EINVAL, "null buffer");
+  const size_t rw = rlwe_words(c);
+  const uintptr_t i0 = reinterpret_cast<uintptr_t>(model_in), i1 = i0 + (uintptr_t)d.k0 * d.k1 * rw * 4;
+  const uintptr_t o0 = reinterpret_cast<uintptr_t>(model_out), o1 = o0 + (uintptr_t)d.rows * d.k1 * rw * 4;
+  if (i0 < o1 && o0 < i1) return fail(HW_EINVAL, "model_out must not overlap model_in");
+  if (d.rpr == 1) {  // one RAM per row: the rows are the class-packed rows
+    HIP_TRY(hipMemcpyAsync(model_out, model_in, (size_t)d.k0 * d.k1 * rw * 4, hipMemcpyDeviceToDevice, st));
+    return ok();
+  }
+  hw::RowPackArgs P{};
+  P.src = model_in;
+  P.rstride = (uint64_t)d.k1 * rw;
+  P.sstride = 0;
+  P.nsmp = 1;
+  P.dst = model_out;
+  P.k0 = d.k0;
+  P.rpr = d.rpr;
+  P.nbf = d.nbf;
+  P.rows = d.rows;
+  P.N = c->prm.N;
+  P.nq = c->prm.nq;
+  P.store = 1;
+  HIP_TRY(timed(c, "pack_rams", (double)d.rows * rw, st, [&] { return hw::launch_row_pack(c->tabs, P, st); }));
+  return ok();
+}
+
 // ---------------------------------------------------------------------------
 // batched training
 // ---------------------------------------------------------------------------
@@ -790,6 +856,8 @@ static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
     hw_status e = check_shape(c, &J.shape, &dims[j]);
     if (e) return fail(e, "job %u: %s", j, hw_last_error());
     if (J.n == 0) continue;
+    if (J.shape.layout == 2)
+      return fail(HW_EINVAL, "job %u: layout 2 rows are shared by several RAMs; batch-train layout 1 and pack", j);
     if (!J.x_rgsw_dev || !J.model_dev) return fail(HW_EINVAL, "job %u: null buffer", j);
     if (dims[j].L > 0 && !J.y_rgsw_dev) return fail(HW_EINVAL, "job %u: null label ciphertexts", j);
     if (J.n > 0xFFFFFFFFull) return fail(HW_EINVAL, "job %u: too many samples", j);

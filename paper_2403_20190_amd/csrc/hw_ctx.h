@@ -145,9 +145,13 @@ static size_t lwe_words(const hw_ctx* c) { return (size_t)c->prm.nq * (c->prm.N 
 struct Dims {
   uint32_t L, k0, k1, z;
   uint32_t kt;      // 2^z: leaves of a full RAM's IVP tree (k1 of them are model rows)
-  uint32_t layout;  // 0: label-pruned rows (label bits lowest in the index); 1: class-packed rows
+  uint32_t layout;  // 0: label-pruned rows (label bits lowest in the index); 1: class-packed rows;
+                    // 2: class-packed, several RAMs per row
   uint32_t pL, pl;  // label bits at the bottom of the tree and the classes they take: (L, l)
-                    // for layout 0; (0, 1) for layout 1, whose tree holds tuple bits only
+                    // for layout 0; (0, 1) for layouts 1-2, whose tree holds tuple bits only
+  uint32_t rpr;     // RAMs per model row: N / 2^(L+a) for layout 2 when that is >= 2, else 1
+  uint32_t rows;    // model rows: ceil(k0 / rpr)
+  uint32_t nbf;     // L + a: RAM j of layout 2 starts at coefficient (j mod rpr) 2^nbf
 };
 
 uint32_t live_rows(uint32_t z, uint32_t L, uint32_t l);

@@ -66,8 +66,23 @@ struct InferArgs {
   uint32_t s, a, L, l, k0, k1, slots;
   uint32_t nsub;            // samples of this launch
   uint32_t map;             // 0: 3-D grid (RAM, label, sample); 1: 1-D, labels adjacent, XCD-grouped
-  uint32_t layout;          // 0: one VP per (RAM, label); 1: class-packed rows, one VP per RAM gives all l
-  uint32_t nlab;            // labels in the grid: l for layout 0, 1 for layout 1
+  uint32_t layout;          // 0: one VP per (RAM, label); 1, 2: class-packed rows, one VP per RAM gives all l
+  uint32_t nlab;            // labels in the grid: l for layout 0, 1 otherwise
+  uint32_t rpr, nbf;        // layout 2: RAM j in row j / rpr from coefficient (j mod rpr) 2^nbf (else 1, 0)
+};
+
+// layout 2 rows from per-RAM rows: dst[R] (+)= sum over samples s < nsmp and
+// RAMs j = R rpr + t < k0 of X^(t 2^nbf) src(s, j), src(s, j) = src + s
+// sstride + j rstride (one RLWE each); the class counter (cnt) sums
+// src(s, k0) unrotated
+struct RowPackArgs {
+  const uint32_t* src;
+  uint64_t sstride, rstride;  // words
+  uint64_t nsmp;
+  uint32_t* dst;              // [rows] RLWE
+  uint32_t* cnt;              // one RLWE or nullptr
+  uint32_t k0, rpr, nbf, rows, N, nq;
+  uint32_t store;             // 1: dst = sum (cnt is then not written); 0: dst += sum
 };
 
 // batched training: one entry per job
@@ -136,6 +151,7 @@ hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, cons
 // occ: occupancy target of the external-product kernels, 3 or 4 (4 only for log2 N = 12)
 hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st);
 hipError_t launch_reduce_model(const Tabs& T, const ReduceArgs& A, hipStream_t st);
+hipError_t launch_row_pack(const Tabs& T, const RowPackArgs& A, hipStream_t st);
 hipError_t batch_grid(int logN, int nq, int occ, uint32_t* grid);  // persistent workgroups that fit the device
 hipError_t launch_train_batch(int logN, int nq, const Tabs& T, const BatchArgs& A, uint32_t grid, int occ,
                               hipStream_t st);

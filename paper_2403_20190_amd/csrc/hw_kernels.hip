@@ -804,6 +804,50 @@ __global__ __launch_bounds__(256) void k_reduce_model(Tabs T, ReduceArgs A) {
   }
 }
 
+// layout 2 rows (several RAMs per row): dst[R] (+)= the sum over samples s
+// and the RAMs t of the row of X^(t 2^nbf) src(s, R rpr + t).  Coefficient k
+// of X^e f is f[k - e] for k >= e and -f[N + k - e] below (0 <= e < N).  One
+// thread per output word; the class counter's words follow the rows.
+__global__ __launch_bounds__(256) void k_row_pack(Tabs T, RowPackArgs A) {
+  const size_t RW = (size_t)2 * A.nq * A.N;
+  const size_t row_words = (size_t)A.rows * RW;
+  const size_t total = row_words + (A.cnt && !A.store ? RW : 0);
+  for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < total; w += (size_t)gridDim.x * blockDim.x) {
+    uint64_t acc = 0;
+    uint32_t* dst;
+    uint32_t i;
+    if (w < row_words) {
+      const uint32_t R = (uint32_t)(w / RW);
+      const size_t rem = w - (size_t)R * RW;
+      const uint32_t k = (uint32_t)(rem % A.N);
+      const size_t poly = rem - k;  // the polynomial's first word within an RLWE
+      i = (uint32_t)((rem / A.N) % A.nq);
+      const uint32_t q = T.pt[i].q;
+      for (uint32_t t = 0; t < A.rpr; ++t) {
+        const uint32_t j = R * A.rpr + t;
+        if (j >= A.k0) break;
+        const uint32_t e = t << A.nbf;  // t 2^nbf < N
+        const bool wrap = k < e;
+        const uint32_t* src = A.src + (size_t)j * A.rstride + poly + (wrap ? k + A.N - e : k - e);
+        for (uint64_t sm = 0; sm < A.nsmp; ++sm) {
+          const uint32_t v = src[sm * A.sstride];
+          acc += wrap ? (v ? q - v : 0u) : v;
+        }
+      }
+      dst = A.dst + w;
+    } else {  // class counter: sample sums of RAM block k0, unrotated
+      const size_t rem = w - row_words;
+      i = (uint32_t)((rem / A.N) % A.nq);
+      const uint32_t* src = A.src + (size_t)A.k0 * A.rstride + rem;
+      for (uint64_t sm = 0; sm < A.nsmp; ++sm) acc += src[sm * A.sstride];
+      dst = A.cnt + rem;
+    }
+    const PrimeTab P = T.pt[i];
+    const uint32_t r = red64(acc, P);
+    *dst = A.store ? r : addq(*dst, r, P.q);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // inference: one workgroup per (RAM, label, sample), or per (RAM, sample)
 // ---------------------------------------------------------------------------
@@ -814,7 +858,9 @@ __global__ __launch_bounds__(256) void k_reduce_model(Tabs T, ReduceArgs A) {
 // change it).  Layout 1: one VP over the tuple bits (the full tree over the
 // row's 2^z leaves, then the chain); the label bits above them are clear
 // zeros, and the cell of class c ends at coefficient c 2^(a_j - z), so the
-// workgroup extracts the LWE of every class.
+// workgroup extracts the LWE of every class.  Layout 2 reads RAM j from row
+// j / rpr, whose block from coefficient (j mod rpr) 2^nbf holds it; the
+// extraction indices move by that offset.
 
 template <int LOGN, int NQ, int OCC>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_infer(Tabs T, InferArgs A) {
@@ -844,7 +890,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
   const uint32_t z = nb - nr;
   const uint32_t TL = tree_L(A.layout, A.L);  // label bits at the bottom of the tree
   const uint32_t tl = tree_l(A.layout, A.l);  // rows per group of leaves
-  const uint32_t* H = A.model + (size_t)ram * A.k1 * RW;
+  const uint32_t* H = A.model + (size_t)(ram / A.rpr) * A.k1 * RW;
+  const uint32_t off = (ram % A.rpr) << A.nbf;  // 0 unless layout 2
   uint32_t* acc = A.scratch + (((size_t)smp * A.nlab + lab) * A.k0 + ram) * (A.slots + 1) * RW;
   uint32_t* xin = acc + (size_t)A.slots * RW;
   auto xbit = [&](uint32_t u) -> const uint32_t* {
@@ -904,13 +951,13 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
     cmux_rot<LOGN, NQ>(T, acc, ex, xbit(u), xin, lds, twl, xc, t);
   }
   // ExtractLWE(acc, idx) for the class(es) of this workgroup: a'_k = a_{idx-k}
-  // for k <= idx, -a_{N+idx-k} above, b' = b_idx; idx = 0 for layout 0, c
-  // 2^(a_j - z) for class c of layout 1 (below 2^nr <= N)
+  // for k <= idx, -a_{N+idx-k} above, b' = b_idx; idx = 0 for layout 0,
+  // off + c 2^(a_j - z) for class c of layouts 1-2 (below N: off + 2^nbf <= N)
   const uint32_t nout = A.layout ? A.l : 1u;
 #pragma unroll 1
   for (uint32_t cc = 0; cc < nout; ++cc) {
     const uint32_t cls = A.layout ? cc : lab;
-    const uint32_t idx = A.layout ? cc << (aj - z) : 0u;
+    const uint32_t idx = A.layout ? off + (cc << (aj - z)) : 0u;
     uint32_t* out = A.scores + ((gi * A.l + cls) * A.k0 + ram) * (size_t)NQ * (N + 1);
 #pragma unroll 1
     for (int i = 0; i < NQ; ++i) {
@@ -1310,7 +1357,18 @@ hipError_t launch_reduce_model(const Tabs& T, const ReduceArgs& A, hipStream_t s
   return hipGetLastError();
 }
 
+hipError_t launch_row_pack(const Tabs& T, const RowPackArgs& A, hipStream_t st) {
+  const size_t RW = (size_t)2 * A.nq * A.N;
+  const size_t total = (size_t)A.rows * RW + (A.cnt && !A.store ? RW : 0);
+  if (total == 0) return hipSuccess;
+  if (A.rpr == 0 || ((size_t)(A.rpr - 1) << A.nbf) >= A.N) return hipErrorInvalidValue;
+  const uint32_t blocks = (uint32_t)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
+  hipLaunchKernelGGL(k_row_pack, dim3(blocks), dim3(256), 0, st, T, A);
+  return hipGetLastError();
+}
+
 hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int occ, hipStream_t st) {
+  if (A.rpr == 0) return hipErrorInvalidValue;
   const uint64_t G = (uint64_t)A.k0 * A.nlab * A.nsub;
   if (G == 0) return hipSuccess;
   if (G > (1u << 22)) return hipErrorInvalidValue;

@@ -74,6 +74,8 @@ _SIG = {
     "hw_sizes": [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)],
     "hw_wisard_dims": [_vp, C.POINTER(Shape), C.POINTER(_u32), C.POINTER(_u32), C.POINTER(_u64)],
     "hw_permutation": [C.POINTER(Shape), _vp],
+    "hw_wisard_model_rows": [_vp, C.POINTER(Shape), C.POINTER(_u32), C.POINTER(_u32)],
+    "hw_wisard_pack_rams": [_vp, C.POINTER(Shape), _vp, _vp, _vp],
     "hw_keygen": [_vp, _u64, _vp, _vp],
     "hw_encrypt_rgsw_bits": [_vp, _vp, _vp, _u64, _u64, _u64, _vp, _vp],
     "hw_encrypt_rlwe": [_vp, _vp, _vp, _u64, _u64, _u64, _vp, _vp],
@@ -150,12 +152,13 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-LAYOUT_PRUNED, LAYOUT_PACKED = 0, 1
+LAYOUT_PRUNED, LAYOUT_PACKED, LAYOUT_RAM_PACKED = 0, 1, 2
 
 
 def shape(s: int, l: int, a: int, perm_seed: int, layout: int = LAYOUT_PRUNED) -> Shape:
     """layout 0: label-pruned model rows (Def. 2); 1: class-packed rows (one
-    VP per RAM at inference gives the scores of every class)"""
+    VP per RAM at inference gives the scores of every class); 2: class-packed
+    rows with several small RAMs per row"""
     return Shape(s, l, a, layout, perm_seed)
 
 
@@ -200,6 +203,16 @@ class Context:
         k0, k1, mb = _u32(), _u32(), _u64()
         _check(_lib.hw_wisard_dims(self._h, C.byref(sh), C.byref(k0), C.byref(k1), C.byref(mb)))
         return k0.value, k1.value, mb.value
+
+    def model_rows(self, sh: Shape):
+        """(rows of the model, RAMs per row)"""
+        rows, rpr = _u32(), _u32()
+        _check(_lib.hw_wisard_model_rows(self._h, C.byref(sh), C.byref(rows), C.byref(rpr)))
+        return rows.value, rpr.value
+
+    def pack_rams(self, sh: Shape, model_in, model_out):
+        """layout-2 rows (sh.layout == 2) from the layout-1 rows of the same WiSARD"""
+        _check(_lib.hw_wisard_pack_rams(self._h, C.byref(sh), _ptr(model_in), _ptr(model_out), _stream()))
 
     # -- client side ------------------------------------------------------------
     def keygen(self, seed: int, sk):

@@ -169,3 +169,82 @@ def test_mnist_shape_packed_sampled():
             assert np.array_equal(got[0, c, j], want[j][c]), (c, j)
     cells = decrypt_scores(pair, scores, 1)[0]
     assert np.array_equal(cells, P.ram_scores(W, tb[0], pair.a, pair.pi))
+
+
+RAM_SHAPES = [
+    dict(N=1024, nq=1, p=64, s=96, l=2, a=6, n=3),    # 2^(L+a) = 128: 8 RAMs per row, 16 RAMs in 2 rows
+    dict(N=1024, nq=2, p=64, s=47, l=3, a=5, n=3),    # 8 per row; 10 RAMs, the last of 2 bits, last row half empty
+    dict(N=2048, nq=2, p=64, s=480, l=2, a=8, n=2),   # Wisconsin-shaped: 4 RAMs per row, 60 RAMs in 15 rows
+]
+
+
+@pytest.mark.parametrize("cfg", RAM_SHAPES)
+def test_several_rams_per_row_bit_exact(cfg):
+    """Layout 2: training straight into shared rows equals the oracle's
+    packing of the class-packed model and the device packing of a layout-1
+    model; inference reads each RAM's block, bit-exact with the oracle, and
+    decrypts to the Alg. 2 scores."""
+    from paper_2403_20190_amd import hwisard as HW
+    cfg = dict(cfg)
+    n = cfg.pop("n")
+    X, y = synth.prototype_bits(15, n, cfg["s"], cfg["l"], flip=0.2)
+    pair = Pair(X=X, y=y, seed=15, layout=2, **cfg)
+    rows, rpr = pair.ctx.model_rows(pair.shape)
+    assert rpr == pair.N >> (pair.L + pair.a) and rows == -(-pair.k0 // rpr) and pair.k1 == 1
+    assert rows == pair.orc.model_rows(pair.s, pair.l, pair.a, 2)
+    xr, yr = pair.encrypt_dev(), pair.encrypt_labels_dev()
+    H2 = zeros_u32(rows, 1, 2, pair.nq, pair.N)
+    cnt = zeros_u32(2, pair.nq, pair.N)
+    pair.ctx.train(pair.shape, xr, yr, pair.n, H2, cnt)
+    Ho1 = pair.oracle_train(range(pair.k0))  # the class-packed rows, one per RAM
+    Ho2 = pair.orc.pack_rams(pair.s, pair.l, pair.a, Ho1)
+    assert np.array_equal(host_u32(H2), Ho2)
+    cnt_o = np.zeros((2, pair.nq, pair.N), np.uint32)
+    pair.orc.class_count(pair.l, pair.yo, pair.n, cnt_o)
+    assert np.array_equal(host_u32(cnt), cnt_o)
+    # the same rows from a layout-1 model through the packing entry point
+    sh1 = HW.shape(pair.s, pair.l, pair.a, pair.seed_perm, HW.LAYOUT_PACKED)
+    H1 = zeros_u32(pair.k0, 1, 2, pair.nq, pair.N)
+    pair.ctx.train(sh1, xr, yr, pair.n, H1, None)
+    Hp = zeros_u32(rows, 1, 2, pair.nq, pair.N)
+    pair.ctx.pack_rams(pair.shape, H1, Hp)
+    assert np.array_equal(host_u32(Hp), host_u32(H2))
+    W = P.train_integer(pair.X, pair.y, pair.l, pair.a, pair.pi)
+    dec = zeros_u64(rows, pair.N)
+    pair.ctx.decrypt_rlwe(pair.sk, H2, rows, dec)
+    assert np.array_equal(host_u64(dec).reshape(rows, 1, pair.N).astype(np.int64),
+                          P.expected_model_cells(W, pair.s, pair.l, pair.a, pair.N, layout=2))
+    nt = 2
+    Xt, _ = synth.prototype_bits(16, nt, cfg["s"], cfg["l"], flip=0.3)
+    xt = pair.encrypt_dev(Xt, seed_x=58)
+    scores = zeros_u32(nt, pair.l, pair.k0, pair.orc.lwe_words)
+    pair.ctx.infer(pair.shape, H2, xt, nt, scores, None)
+    got = host_u32(scores).reshape(nt, pair.l, pair.k0, pair.nq, pair.N + 1)
+    rams = sorted({0, 1, rpr - 1, pair.k0 - 1} & set(range(pair.k0)))
+    want = {}
+    jobs = [(i, j) for i in range(nt) for j in rams]
+    O._parallel(lambda ij: want.__setitem__(ij, pair.orc.infer_packed(
+        pair.s, pair.l, pair.a, pair.pi, Ho2, lambda k: pair.xo(ij[0], k, Xt, 58, "t"), ij[1], layout=2)), jobs)
+    for i, j in jobs:
+        for c in range(pair.l):
+            assert np.array_equal(got[i, c, j], want[(i, j)][c]), (i, c, j)
+    cells = decrypt_scores(pair, scores, nt)
+    for i in range(nt):
+        assert np.array_equal(cells[i], P.ram_scores(W, Xt[i], pair.a, pair.pi))
+
+
+def test_several_rams_per_row_argument_checks():
+    from paper_2403_20190_amd import hwisard as HW
+    ctx = HW.Context(1024, 1, 64)
+    sh2 = HW.shape(96, 2, 6, 3, HW.LAYOUT_RAM_PACKED)
+    assert ctx.model_rows(sh2) == (2, 8)
+    assert ctx.model_rows(HW.shape(96, 2, 6, 3, HW.LAYOUT_PACKED)) == (16, 1)
+    assert ctx.model_rows(HW.shape(96, 2, 12, 3, HW.LAYOUT_RAM_PACKED)) == (8, 1)  # 2^13 > N: one RAM per row
+    x = zeros_u32(96, ctx.rgsw_words)
+    H = zeros_u32(2, 1, 2, 1, 1024)
+    with pytest.raises(HW.HwError):  # shared rows are not written by the batched kernel
+        ctx.batch_train([(sh2, x, x, 1, H, None)])
+    with pytest.raises(HW.HwError):  # packing needs the layout-2 shape
+        ctx.pack_rams(HW.shape(96, 2, 6, 3, HW.LAYOUT_PACKED), zeros_u32(16, 1, 2, 1, 1024), H)
+    with pytest.raises(HW.HwError):
+        ctx.train(HW.shape(96, 2, 6, 3, 3), x, x, 1, H, None)

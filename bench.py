@@ -37,6 +37,10 @@ WORKLOADS = {
                   N=2048, nq=2, p=1024, l=10, a=12, T=3, n_train=1000, n_test=1000, chunk=50, balance=False),
     "ham": dict(name="ham10000-shaped 28x28x3, 7 skewed classes, therm 2, tuple 12, 10000 train + 1000 test, N=4096 x 3 primes",
                 N=4096, nq=3, p=16384, l=7, a=12, T=2, n_train=10000, n_test=1000, chunk=10, balance=True),
+    "wisconsin": dict(name="wisconsin-shaped 30 float features, 2 classes 357/212, therm 16 (480 bits), tuple 8, "
+                           "400 train + 169 test, N=2048 x 2 primes",
+                      N=2048, nq=2, p=512, l=2, a=8, T=16, n_train=400, n_test=169, chunk=100, balance=False,
+                      cpu_samples=12),
     "tiny": dict(name="tiny 8x8, 2 classes, therm 2, tuple 8, 32 train + 16 test, N=1024 x 1 prime",
                  N=1024, nq=1, p=64, l=2, a=8, T=2, n_train=32, n_test=16, chunk=32, balance=False),
 }
@@ -95,6 +99,10 @@ def rgsw_bytes(N: int, nq: int) -> int:
 
 def gen_data(wl: str, W: dict):
     from paper_2403_20190_amd import synth
+    if wl == "wisconsin":
+        X, y = synth.wisconsin_like(4)
+        n = W["n_train"]
+        return X[:n], y[:n], X[n:], y[n:]
     if wl == "mnist":
         return synth.mnist_like(1, per_class_train=W["n_train"] // 10, per_class_test=W["n_test"] // 10)
     if wl == "ham":
@@ -102,16 +110,27 @@ def gen_data(wl: str, W: dict):
     return synth.tiny(0, W["n_train"], W["n_test"])
 
 
-def cpu_baseline(W: dict, Xtr, ytr, threads: int, seeds: dict):
+def levels_of(mod, W: dict, X, ref):
+    """quantisation levels of X with `mod`'s quantiser (the client's or the
+    oracle's plain one): uint8 images by value, float features by min-max
+    over the reference data"""
+    if W.get("minmax"):
+        return mod.quantize_minmax(X, W["T"], ref.min(axis=0), ref.max(axis=0))
+    return mod.quantize_u8(X, W["T"])
+
+
+def cpu_baseline(W: dict, Xtr, ytr, threads: int, seeds: dict, ref=None):
     """The oracle, as it is, on a bounded sample: client encryption plus
-    homomorphic training of ONE training sample over every RAM."""
+    homomorphic training of a few training samples (one for the image
+    workloads) over every RAM."""
     import numpy as np
 
     import oracle as O
     from oracle import plain as P
     N, nq, p, l, a, T = W["N"], W["nq"], W["p"], W["l"], W["a"], W["T"]
+    m = W.get("cpu_samples", 1)
     orc = O.Ctx(N, nq, p)
-    bits = P.encode(P.quantize_u8(Xtr[:1], T), T)
+    bits = P.encode(levels_of(P, W, Xtr[:m], ref), T)
     s = bits.shape[1]
     L = O.ceil_log2(l)
     sk = orc.keygen(seeds["key"])
@@ -121,20 +140,22 @@ def cpu_baseline(W: dict, Xtr, ytr, threads: int, seeds: dict):
     xr = {}
     yr = {}
 
-    def enc_x(k):
-        xr[k] = orc.enc_rgsw(sk, int(bits[0, k]), seeds["x"], k)
+    def enc_x(ik):
+        i, k = ik
+        xr[ik] = orc.enc_rgsw(sk, int(bits[i, k]), seeds["x"], i * s + k)
 
-    def enc_y(u):
-        yr[u] = orc.enc_rgsw(sk, (int(ytr[0]) >> u) & 1, seeds["y"], u)
+    def enc_y(iu):
+        i, u = iu
+        yr[iu] = orc.enc_rgsw(sk, (int(ytr[i]) >> u) & 1, seeds["y"], i * L + u)
 
-    O._parallel(enc_x, range(s), threads)
-    O._parallel(enc_y, range(L), threads)
+    O._parallel(enc_x, [(i, k) for i in range(m) for k in range(s)], threads)
+    O._parallel(enc_y, [(i, u) for i in range(m) for u in range(L)], threads)
     H = np.zeros((k0, k1, 2, nq, N), np.uint32)
-    orc.train(s, l, a, pi, lambda i, k: xr[k], lambda i, u: yr[u], 1, H, threads=threads)
+    orc.train(s, l, a, pi, lambda i, k: xr[(i, k)], lambda i, u: yr[(i, u)], m, H, threads=threads)
     dt = time.perf_counter() - t0
-    return dict(value=1.0 / dt, unit="samples/s", cores=threads, kind="oracle",
-                sample="1 training sample: oracle encryption of its %d RGSW + IVP training of all %d RAMs "
-                       "(%.1f s on %d threads)" % (s + L, k0, dt, threads))
+    return dict(value=m / dt, unit="samples/s", cores=threads, kind="oracle",
+                sample="%d training sample(s): oracle encryption of %d RGSW each + IVP training of all %d RAMs "
+                       "(%.1f s on %d threads)" % (m, s + L, k0, dt, threads))
 
 
 def main():
@@ -177,9 +198,12 @@ def main():
     N, nq, p, l, a, T = W["N"], W["nq"], W["p"], W["l"], W["a"], W["T"]
     seeds = dict(key=11, x=12, y=13, perm=14, xt=15)
     Xtr, ytr, Xte, yte = gen_data(args.workload, W)
+    W["minmax"] = args.workload == "wisconsin"
+    ref = np.concatenate([Xtr, Xte])  # min-max range of the float features
+    W["ref"] = ref
     Xtr, ytr = Xtr[:W["n_train"]], ytr[:W["n_train"]]
     n = len(Xtr)
-    bits_tr = CL.thermometer(CL.quantize_u8(Xtr, T), T)
+    bits_tr = CL.thermometer(levels_of(CL, W, Xtr, ref), T)
     s = bits_tr.shape[1]
     L = CL.ceil_log2(l)
     lab_tr = CL.label_bits(ytr, l)
@@ -303,7 +327,7 @@ def main():
     if not args.no_extras:
         result["schedule"] = ctx.schedule()
     if not args.no_cpu_baseline and not args.no_extras:
-        result["cpu_baseline"] = cpu_baseline(W, Xtr, ytr, min(16, os.cpu_count() or 1), seeds)
+        result["cpu_baseline"] = cpu_baseline(W, Xtr, ytr, min(16, os.cpu_count() or 1), seeds, ref)
     print(json.dumps(result), flush=True)
 
 
@@ -345,7 +369,7 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
 
     from paper_2403_20190_amd import client as CL
     T, l = W["T"], W["l"]
-    bits = CL.thermometer(CL.quantize_u8(Xte[:W["n_test"]], T), T)
+    bits = CL.thermometer(levels_of(CL, W, Xte[:W["n_test"]], W.get("ref")), T)
     nt = len(bits)
     chunk = max(1, W["chunk"])
     cells, dt, inf_ms, inf_xp, scores = infer_loop(ctx, sh, H, sk, bits, W, seeds, k0, dev)
@@ -424,9 +448,23 @@ def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev):
     rd_ms, _, _ = ctx.profile_read("reduce")
     ctx.profile(False)
     del xr, yr, xb, yb
-    bits = CL.thermometer(CL.quantize_u8(Xte[:W["n_test"]], T), T)
+    bits = CL.thermometer(levels_of(CL, W, Xte[:W["n_test"]], W.get("ref")), T)
     nt = len(bits)
     cells, dt, inf_ms, inf_xp, _ = infer_loop(ctx, sh, H, sk, bits, W, seeds, k0, dev)
+    # several small RAMs per row (layout 2) when a RAM fills less than half an RLWE
+    ram_packed = None
+    sh2 = HW.shape(s, l, a, seeds["perm"], HW.LAYOUT_RAM_PACKED)
+    rows, rpr = ctx.model_rows(sh2)
+    if rpr > 1:
+        _, _, bytes2 = ctx.dims(sh2)
+        H2 = torch.empty(rows, 1, 2, nq, N, dtype=torch.int32, device=dev)
+        ctx.pack_rams(sh2, H, H2)
+        cells2, dt2, inf2_ms, _, _ = infer_loop(ctx, sh2, H2, sk, bits, W, seeds, k0, dev)
+        ram_packed = {"rams_per_row": rpr, "rows": rows, "model_mib": round(bytes2 / 2**20, 2),
+                      "infer_samples_per_s": round(nt / dt2, 3),
+                      "infer_kernel_samples_per_s": round(nt / (inf2_ms / 1000.0), 3) if inf2_ms else None,
+                      "scores_equal_label_pruned": bool(np.array_equal(cells2, cells0))}
+        del H2
     del H
     torch.cuda.empty_cache()
     opx = ops_per_xp(N, nq)
@@ -443,6 +481,7 @@ def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev):
                            "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOPS(int32)",
                            "frac": round(tops / PEAK_INT32_TOPS, 4)},
         "scores_equal_label_pruned": bool(np.array_equal(cells, cells0)),
+        "several_rams_per_row": ram_packed,
     }
 
 
@@ -491,8 +530,14 @@ def ntt_pass(ctx, N, nq, dev):
     ctx.profile(False)
     nt_s = work / (ms / 1000.0)
     bytes_moved = work * N * 4 * 2  # read + write per transform
+    # 9 int32 ops per Harvey butterfly (the op model of ops_per_xp): 6.2
+    # ops per byte moved at N = 2048, above the chip's 4.9 (39.3 T / 8 TB/s),
+    # so the transform is bound by the VALU before HBM
+    ops = 9.0 * (N // 2) * (N.bit_length() - 1)
     return {"polys": count * nq, "ntt_per_s": round(nt_s, 1), "gbs": round(bytes_moved / (ms / 1000.0) / 1e9, 1),
-            "hbm_frac": round(bytes_moved / (ms / 1000.0) / 1e9 / PEAK_HBM_GBS, 4)}
+            "hbm_frac": round(bytes_moved / (ms / 1000.0) / 1e9 / PEAK_HBM_GBS, 4),
+            "ops_per_ntt": ops, "valu_frac": round(nt_s * ops / 1e12 / PEAK_INT32_TOPS, 4),
+            "bound": "alu" if ops / (N * 8) > PEAK_INT32_TOPS * 1e12 / (PEAK_HBM_GBS * 1e9) else "hbm"}
 
 
 def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):

@@ -4,7 +4,8 @@
 Workload (default): MNIST-shaped synthetic data -- 28x28 uint8 images, 10
 balanced classes, 3-level thermometer code (s = 2352 bits), tuple size 12
 (196 RAMs), 1000 training + 1000 test samples, RLWE N = 2048 with two 30-bit
-primes, plaintext modulus 1024.
+primes, plaintext modulus 1024.  `--workload ham`, `wisconsin` and `tiny`
+select the other shapes (see WORKLOADS).
 
 A step is one encrypted training pass over the 1000 training samples: the
 client-side RGSW encryption of every input and label bit (on the device, from

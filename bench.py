@@ -86,6 +86,23 @@ def ops_per_xp(N: int, nq: int) -> float:
             + 6.0 * 10 * nq * nq * N)
 
 
+def ops_first_xp(N: int, nq: int) -> float:
+    """Algorithmic ops of the first external product of an IVP chain, whose
+    input (0, Delta (X - 1)) has a zero a side and two-coefficient digit
+    polynomials: no forward NTT; per output prime and side, 5 nq gadget rows
+    x N coefficients x two multiply-accumulates (2 ops each), 15 ops of
+    reduction and the evaluation product per coefficient; 2 nq inverse
+    NTTs."""
+    logN = N.bit_length() - 1
+    return (9.0 * (N // 2) * logN + 6.0 * N) * 2 * nq + 4.0 * 5 * nq * nq * 2 * N + 15.0 * 2 * nq * N
+
+
+def train_ops(N: int, nq: int, xp: float, ivps: float) -> float:
+    """ops of a training launch with `xp` external products over `ivps` IVP
+    chains (each chain's first product is the cheaper one above)"""
+    return (xp - ivps) * ops_per_xp(N, nq) + ivps * ops_first_xp(N, nq)
+
+
 def modmul_per_xp(N: int, nq: int) -> float:
     """Modular multiplications of one external product:
     (2 l nq^2 + 2 nq) (N/2) log2 N + 4 l nq^2 N with l = 5 digits."""
@@ -268,6 +285,8 @@ def main():
         del src, dst
 
     steps_xp = tr_xp / args.steps
+    steps_ivps = n * (k0 + (1 if W["balance"] and L else 0))  # IVP chains per step
+    steps_full = steps_xp - steps_ivps                         # external products other than the chains' first
     train_kernel_ms = tr_ms / args.steps
     opx = ops_per_xp(N, nq)
     result = {
@@ -286,7 +305,9 @@ def main():
         "config": {"workload": W["name"], "n_train": n, "s": s, "k0": k0, "k1": k1,
                    "chunk": chunk, "step": "device RGSW encryption + homomorphic training of n_train samples"},
     }
-    a_ops = tr_xp / tr_launch * opx / (tr_ms / tr_launch / 1000.0) / 1e12 if tr_launch else 0.0
+    # IVP chains per step: every (sample, RAM) plus the class counter's (label bits only)
+    ivps = args.steps * steps_ivps
+    a_ops = train_ops(N, nq, tr_xp, ivps) / (tr_ms / 1000.0) / 1e12 if tr_launch else 0.0
     result["roofline"] = {
         "bound": "alu", "kernel": "k_train", "achieved": round(a_ops, 3), "peak": round(PEAK_INT32_TOPS, 2),
         "unit": "TOPS(int32)", "frac": round(a_ops / PEAK_INT32_TOPS, 4),
@@ -294,6 +315,7 @@ def main():
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
         "launches": tr_launch, "avg_launch_ms": round(tr_ms / max(1, tr_launch), 3),
         "xp_per_launch": tr_xp / max(1, tr_launch), "ops_per_xp": opx,
+        "ops_per_launch": train_ops(N, nq, tr_xp, ivps) / max(1, tr_launch), "ops_first_xp": ops_first_xp(N, nq),
     }
     result["kernels"] = {
         "train_ms_per_step": round(train_kernel_ms, 2),
@@ -304,12 +326,14 @@ def main():
         "train_only_samples_per_s": round(n / (train_kernel_ms / 1000.0), 3) if train_kernel_ms else None,
         "encrypt_only_samples_per_s": round(n / (en_ms / args.steps / 1000.0), 3) if en_ms else None,
         "xp_per_s": round(steps_xp / (train_kernel_ms / 1000.0), 1) if train_kernel_ms else None,
-        "ntt_per_s_in_xp": round(steps_xp * (10 * nq * nq + 2 * nq) / (train_kernel_ms / 1000.0), 1)
+        # the first product of each chain: 2 nq inverse NTTs, 2 nq N evaluation products, half the RGSW
+        "ntt_per_s_in_xp": round((steps_full * (10 * nq * nq + 2 * nq) + steps_ivps * 2 * nq)
+                                 / (train_kernel_ms / 1000.0), 1) if train_kernel_ms else None,
+        "modmul_per_s": round((steps_full * modmul_per_xp(N, nq) + steps_ivps * (
+            2 * nq * (N // 2) * (N.bit_length() - 1) + 2 * nq * N)) / (train_kernel_ms / 1000.0), 1)
         if train_kernel_ms else None,
-        "modmul_per_s": round(steps_xp * modmul_per_xp(N, nq) / (train_kernel_ms / 1000.0), 1)
-        if train_kernel_ms else None,
-        "rgsw_read_gbs": round(steps_xp * rgsw_bytes(N, nq) / (train_kernel_ms / 1000.0) / 1e9, 1)
-        if train_kernel_ms else None,
+        "rgsw_read_gbs": round((steps_full + steps_ivps / 2) * rgsw_bytes(N, nq) / (train_kernel_ms / 1000.0) / 1e9,
+                               1) if train_kernel_ms else None,
     }
 
     result["schedule"] = ctx.schedule()
@@ -448,6 +472,7 @@ def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev):
     tr_ms, _, tr_xp = ctx.profile_read("train")
     rd_ms, _, _ = ctx.profile_read("reduce")
     ctx.profile(False)
+    tr_tops = train_ops(N, nq, tr_xp, n * k0) / (tr_ms / 1000.0) / 1e12 if tr_ms else 0.0
     del xr, yr, xb, yb
     bits = CL.thermometer(levels_of(CL, W, Xte[:W["n_test"]], W.get("ref")), T)
     nt = len(bits)
@@ -474,6 +499,7 @@ def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev):
         "k1": k1, "model_mib": round(model_bytes / 2**20, 1),
         "train_kernel_samples_per_s": round(n / (tr_ms / 1000.0), 3) if tr_ms else None,
         "train_xp_per_sample": round(tr_xp / n, 1),
+        "train_frac": round(tr_tops / PEAK_INT32_TOPS, 4),
         "reduce_ms": round(rd_ms, 2),
         "infer_samples_per_s": round(nt / dt, 3),
         "infer_kernel_samples_per_s": round(nt / (inf_ms / 1000.0), 3) if inf_ms else None,
@@ -609,7 +635,7 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
             out["plan_max_pieces"] = max(out["plan_max_pieces"], plan.max_pieces)
             xpb = ctx.profile_read("train_batch")[2]
             out["xp"] += xpb
-            out["ops"] += xpb * ops_per_xp(N, nq)
+            out["ops"] += train_ops(N, nq, xpb, sum(b[3] * b[4] for b in bufs))
             for k in ("train_batch", "reduce_batch", "train", "reduce", "batch_plan"):
                 out["kernel_ms"][k] = out["kernel_ms"].get(k, 0.0) + ctx.profile_read(k)[0]
             ctx.profile(False)

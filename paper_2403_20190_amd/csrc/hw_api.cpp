@@ -183,21 +183,25 @@ extern "C" hw_status hw_ctx_create(const hw_params* params, int device, hw_ctx**
     return fail(HW_EINVAL, "plain_mod too large for Q");
   }
 
-  // tables: for each prime fwd[N] then inv[N] of (w, Shoup)
-  std::vector<uint2> host((size_t)2 * P.nq * N);
+  // tables: for each prime fwd[N], inv[N] and evx[N] of (w, Shoup)
+  std::vector<uint2> host((size_t)3 * P.nq * N);
   for (uint32_t i = 0; i < P.nq; ++i) {
     const uint32_t q = P.primes[i];
     uint64_t g = 2;  // smallest quadratic non-residue: psi = g^((q-1)/2N) has order 2N
     while (powm(g, (q - 1) / 2, q) != q - 1) ++g;
     const uint64_t psi = powm(g, (q - 1) / m, q);
     const uint64_t psi_inv = powm(psi, q - 2, q);
-    uint2* fw = host.data() + (size_t)2 * i * N;
+    uint2* fw = host.data() + (size_t)3 * i * N;
     uint2* iv = fw + N;
+    uint2* ev = iv + N;
     for (uint32_t k = 0; k < N; ++k) {
       const uint32_t w = (uint32_t)powm(psi, brv(k, logN), q);
       const uint32_t wi = (uint32_t)powm(psi_inv, brv(k, logN), q);
+      // the forward transform's output k is the evaluation at psi^(2 brv(k) + 1): for X, that point
+      const uint32_t x = (uint32_t)powm(psi, 2ull * brv(k, logN) + 1, q);
       fw[k] = make_uint2(w, shoup(w, q));
       iv[k] = make_uint2(wi, shoup(wi, q));
+      ev[k] = make_uint2(x, shoup(x, q));
     }
     hw::PrimeTab& pt = c->tabs.pt[i];
     pt.q = q;
@@ -228,8 +232,9 @@ extern "C" hw_status hw_ctx_create(const hw_params* params, int device, hw_ctx**
     return fail(e == hipErrorOutOfMemory ? HW_ENOMEM : HW_EDEVICE, "table upload: %s", hipGetErrorString(e));
   }
   for (uint32_t i = 0; i < P.nq; ++i) {
-    c->tabs.fwd[i] = reinterpret_cast<const uint2*>(c->d_tables) + (size_t)2 * i * N;
+    c->tabs.fwd[i] = reinterpret_cast<const uint2*>(c->d_tables) + (size_t)3 * i * N;
     c->tabs.inv[i] = c->tabs.fwd[i] + N;
+    c->tabs.evx[i] = c->tabs.fwd[i] + 2 * N;
   }
   const char* wb = getenv("HWISARD_WS_BYTES");
   c->ws_budget = wb ? (size_t)strtoull(wb, nullptr, 10) : ((size_t)16 << 30);

@@ -39,6 +39,7 @@ struct Tabs {
   PrimeTab pt[MAXQ];
   const uint2* fwd[MAXQ];   // [N]: (psi^{brv(k)}, Shoup companion), k >= 1
   const uint2* inv[MAXQ];   // [N]: (psi^{-brv(k)}, Shoup companion)
+  const uint2* evx[MAXQ];   // [N]: the forward transform of X, psi^{2 brv(k) + 1}, with its Shoup companion
 };
 
 // ---------------------------------------------------------------------------
@@ -369,6 +370,39 @@ struct XpOut {
   int mode;
 };
 
+// inverse transforms of the a and b sums of output prime ip (inputs in [0, q))
+// and the write of the external product by out.mode
+template <int LOGN, int NQ>
+__device__ __forceinline__ void xp_finish(uint32_t (&ha)[8], uint32_t (&hb)[8], int ip, const Tabs& T, uint32_t* lds,
+                                          uint32_t& xc, uint32_t t, const XpOut& out) {
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  const PrimeTab P = T.pt[ip];
+  ntt_inv<LOGN>(ha, T.inv[ip], P, lds, xc, t);
+  ntt_inv<LOGN>(hb, T.inv[ip], P, lds, xc, t);
+  const size_t oa = (size_t)ip * N, ob = (size_t)(NQ + ip) * N;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const size_t ea = oa + TT * e, eb = ob + TT * e;
+    if (out.mode == XP_STORE) {
+      (out.dst + ea)[t] = ha[e];
+      (out.dst + eb)[t] = hb[e];
+    } else if (out.mode == XP_ADD) {
+      (out.dst + ea)[t] = addq((out.src + ea)[t], ha[e], P.q);
+      (out.dst + eb)[t] = addq((out.src + eb)[t], hb[e], P.q);
+    } else if (out.mode == XP_DEMUX) {
+      (out.dst + ea)[t] = subq((out.src + ea)[t], ha[e], P.q);
+      (out.dst + eb)[t] = subq((out.src + eb)[t], hb[e], P.q);
+      (out.dst2 + ea)[t] = ha[e];
+      (out.dst2 + eb)[t] = hb[e];
+    } else {
+      (out.dst + ea)[t] = addq((out.dst + ea)[t], subq((out.src + ea)[t], ha[e], P.q), P.q);
+      (out.dst + eb)[t] = addq((out.dst + eb)[t], subq((out.src + eb)[t], hb[e], P.q), P.q);
+      (out.dst2 + ea)[t] = addq((out.dst2 + ea)[t], ha[e], P.q);
+      (out.dst2 + eb)[t] = addq((out.dst2 + eb)[t], hb[e], P.q);
+    }
+  }
+}
+
 template <int LOGN, int NQ>
 __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const uint32_t* __restrict__ C,
                                       const Tabs& T, uint32_t* lds, uint2* twl, uint32_t& xc, uint32_t t,
@@ -440,30 +474,78 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
       ha[e] = red64(acc_a[e], P);
       hb[e] = red64(acc_b[e], P);
     }
-    ntt_inv<LOGN>(ha, T.inv[ip], P, lds, xc, t);
-    ntt_inv<LOGN>(hb, T.inv[ip], P, lds, xc, t);
-    const size_t oa = (size_t)ip * N, ob = (size_t)(NQ + ip) * N;
+    xp_finish<LOGN, NQ>(ha, hb, ip, T, lds, xc, t, out);
+  }
+}
+
+// External product with the trivial RLWE (0, Delta (X - 1)): the first CMUX
+// of an IVP chain, whose accumulator starts at (0, Delta).  Its a side is
+// zero, so only the D gadget rows of the b side take part, and each digit
+// polynomial is d0 + d1 X with the scalar digits d0, d1 of the centred
+// residues of -Delta and Delta.  Its transform at evaluation point k is
+// d0 + d1 E[k] (E = the transform of X), so
+//   acc[k] = sum_r d0_r C_r[k] + E[k] sum_r d1_r C_r[k]  (mod q)
+// with small signed multipliers.  Both sums are reduced to [0, q) before the
+// inverse transform, as in ext_prod, so the result is the same residues
+// ext_prod computes for that input, without its 10 nq^2 forward transforms
+// and with half its RGSW reads.
+template <int LOGN, int NQ>
+__device__ __forceinline__ void ext_prod_delta(const uint32_t* __restrict__ C, const Tabs& T, uint32_t* lds,
+                                               uint32_t& xc, uint32_t t, XpOut out) {
+  constexpr int N = 1 << LOGN;
+  constexpr size_t ROW = (size_t)2 * NQ * N;
+#pragma unroll 1
+  for (int ip = 0; ip < NQ; ++ip) {
+    const PrimeTab P = T.pt[ip];
+    uint32_t h[2][8];  // a and b sums, reduced
+#pragma unroll 1
+    for (int side = 0; side < 2; ++side) {  // one output polynomial at a time keeps the sums in registers
+      int64_t s0[8], s1[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const size_t ea = oa + TT * e, eb = ob + TT * e;
-      if (out.mode == XP_STORE) {
-        (out.dst + ea)[t] = ha[e];
-        (out.dst + eb)[t] = hb[e];
-      } else if (out.mode == XP_ADD) {
-        (out.dst + ea)[t] = addq((out.src + ea)[t], ha[e], P.q);
-        (out.dst + eb)[t] = addq((out.src + eb)[t], hb[e], P.q);
-      } else if (out.mode == XP_DEMUX) {
-        (out.dst + ea)[t] = subq((out.src + ea)[t], ha[e], P.q);
-        (out.dst + eb)[t] = subq((out.src + eb)[t], hb[e], P.q);
-        (out.dst2 + ea)[t] = ha[e];
-        (out.dst2 + eb)[t] = hb[e];
-      } else {
-        (out.dst + ea)[t] = addq((out.dst + ea)[t], subq((out.src + ea)[t], ha[e], P.q), P.q);
-        (out.dst + eb)[t] = addq((out.dst + eb)[t], subq((out.src + eb)[t], hb[e], P.q), P.q);
-        (out.dst2 + ea)[t] = addq((out.dst2 + ea)[t], ha[e], P.q);
-        (out.dst2 + eb)[t] = addq((out.dst2 + eb)[t], hb[e], P.q);
+      for (int e = 0; e < 8; ++e) s0[e] = s1[e] = 0;
+#pragma unroll 1
+      for (int i = 0; i < NQ; ++i) {
+        // centred residues of -Delta and Delta mod q_i, decomposed digit by digit
+        // exactly as ext_prod decomposes its input (uniform over the workgroup)
+        const uint32_t qi = T.pt[i].q, dl = T.pt[i].delta;
+        const uint32_t r0 = dl ? qi - dl : 0u;
+        int32_t v0 = r0 > (qi - 1) / 2 ? (int32_t)(r0 - qi) : (int32_t)r0;
+        int32_t v1 = dl > (qi - 1) / 2 ? (int32_t)(dl - qi) : (int32_t)dl;
+#pragma unroll 1
+        for (int j = 0; j < 5; ++j) {
+          int32_t e0 = v0, e1 = v1;
+          if (j < 4) {
+            e0 = ((v0 + 32) & 63) - 32;
+            e1 = ((v1 + 32) & 63) - 32;
+            v0 = (v0 - e0) >> 6;
+            v1 = (v1 - e1) >> 6;
+          }
+          const uint4* cr = reinterpret_cast<const uint4*>(C + (size_t)(i * 5 + j) * ROW +
+                                                           ((size_t)side * NQ + ip) * N);
+          const uint4 c0 = cr[2 * t], c1 = cr[2 * t + 1];
+          const int32_t cv[8] = {(int32_t)c0.x, (int32_t)c0.y, (int32_t)c0.z, (int32_t)c0.w,
+                                 (int32_t)c1.x, (int32_t)c1.y, (int32_t)c1.z, (int32_t)c1.w};
+          const int64_t d0 = e0, d1 = e1;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            s0[e] += d0 * cv[e];
+            s1[e] += d1 * cv[e];
+          }
+        }
+      }
+      // |s| < 5 NQ 2^5 2^30 < 2^39 <= 2^10 q: shifting by 2^10 q makes it nonnegative, same residue
+      const int64_t sh = (int64_t)P.q << 10;
+      const uint4* ev = reinterpret_cast<const uint4*>(T.evx[ip] + 8 * (size_t)t);
+#pragma unroll
+      for (int hh = 0; hh < 4; ++hh) {
+        const uint4 w = ev[hh];
+        const uint32_t r0 = csub(mulsh(red64((uint64_t)(s1[2 * hh] + sh), P), w.x, w.y, P.q), P.q);
+        const uint32_t r1 = csub(mulsh(red64((uint64_t)(s1[2 * hh + 1] + sh), P), w.z, w.w, P.q), P.q);
+        h[side][2 * hh] = addq(red64((uint64_t)(s0[2 * hh] + sh), P), r0, P.q);
+        h[side][2 * hh + 1] = addq(red64((uint64_t)(s0[2 * hh + 1] + sh), P), r1, P.q);
       }
     }
+    xp_finish<LOGN, NQ>(h[0], h[1], ip, T, lds, xc, t, out);
   }
 }
 

@@ -578,8 +578,12 @@ __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ 
   }
   __syncthreads();
   uint32_t xc = 0;
+  if (nr > 0) {  // the first CMUX acts on (0, Delta): X acc - acc = (0, Delta (X - 1))
+    ext_prod_delta<LOGN, NQ>(bit(z), T, lds, xc, t, XpOut{slot0, slot0, nullptr, XP_ADD});
+    __syncthreads();
+  }
 #pragma unroll 1
-  for (uint32_t st = 0; st < nr; ++st) cmux_rot<LOGN, NQ>(T, slot0, 1 << st, bit(z + st), xin, lds, twl, xc, t);
+  for (uint32_t st = 1; st < nr; ++st) cmux_rot<LOGN, NQ>(T, slot0, 1 << st, bit(z + st), xin, lds, twl, xc, t);
 #pragma unroll 1
   for (uint32_t lev = 0; lev < z; ++lev) {
     const uint32_t* C = bit(lev);

@@ -90,23 +90,37 @@ def test_packed_training_and_inference_bit_exact(cfg):
         assert np.array_equal(cells[i], P.ram_scores(W, Xt[i], pair.a, pair.pi))
 
 
-def test_packed_inference_schedules_agree():
-    """every schedule variant of the inference kernel gives the same bits"""
-    X, y = synth.prototype_bits(13, 3, 40, 4, flip=0.2)
-    pair = Pair(1024, 2, 64, 40, 4, 10, X, y, seed=10, layout=1)
+@pytest.mark.parametrize("N,nq,s,l,a", [
+    (1024, 2, 40, 4, 10),   # z = 2: a tree of three CMUXes
+    (2048, 1, 60, 3, 14),   # z = 5: levels of 16, 8, 4, 2, 1 CMUXes; a ragged last tuple (4 bits, no tree)
+    (4096, 3, 30, 5, 15),   # z = 6 over N = 4096 with three primes (occupancy-4 variants too)
+])
+def test_packed_inference_schedules_agree(N, nq, s, l, a):
+    """every schedule variant of the class-packed inference gives the same
+    bits, equal to the oracle on the first and last RAM"""
+    X, y = synth.prototype_bits(13, 2, s, l, flip=0.2)
+    pair = Pair(N, nq, 64, s, l, a, X, y, seed=10, layout=1)
     H, _, _, _ = train_dev(pair, class_count=False)
-    Xt, _ = synth.prototype_bits(14, 3, 40, 4, flip=0.3)
+    Xt, _ = synth.prototype_bits(14, 2, s, l, flip=0.3)
     xt = pair.encrypt_dev(Xt, seed_x=57)
     _, _, nvar = pair.ctx.tune_get("infer")
+    assert nvar == (4 if N == 4096 else 2)
     outs = []
     for v in range(nvar):
         pair.ctx.tune_set("infer", v)
-        scores = zeros_u32(3, pair.l, pair.k0, pair.orc.lwe_words)
-        pair.ctx.infer(pair.shape, H, xt, 3, scores, None)
+        scores = zeros_u32(2, pair.l, pair.k0, pair.orc.lwe_words)
+        pair.ctx.infer(pair.shape, H, xt, 2, scores, None)
         outs.append(host_u32(scores))
+        assert pair.ctx.tune_get("infer")[0] == v
     pair.ctx.tune_set("infer", -1)
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+    Ho = pair.oracle_train([0, pair.k0 - 1])
+    got = outs[0].reshape(2, pair.l, pair.k0, pair.nq, pair.N + 1)
+    for j in sorted({0, pair.k0 - 1}):
+        want = pair.orc.infer_packed(pair.s, pair.l, pair.a, pair.pi, Ho, lambda k: pair.xo(1, k, Xt, 57, "t"), j)
+        for c in range(pair.l):
+            assert np.array_equal(got[1, c, j], want[c]), (c, j)
 
 
 def test_packed_batch_equals_single_job():

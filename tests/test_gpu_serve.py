@@ -13,10 +13,22 @@ from paper_2403_20190_amd import synth
 pytestmark = pytest.mark.gpu
 
 N, NQ, PM = 1024, 1, 1024
-JOBS = [dict(s=48, l=3, a=8, seed=31), dict(s=64, l=4, a=10, seed=32)]
+# model layouts 0 (label-pruned), 1 (class-packed) and 2 (four RAMs of 2^8 cells per RLWE)
+JOBS = [dict(s=48, l=3, a=8, seed=31), dict(s=64, l=4, a=10, seed=32), dict(s=40, l=3, a=7, seed=33, layout=1),
+        dict(s=60, l=2, a=7, seed=34, layout=2)]
 # (job, kind, n, data seed)
 REQS = [(0, "train", 5, 1), (1, "train", 6, 2), (0, "infer", 4, 3), (1, "infer", 3, 4),
-        (0, "train", 3, 5), (0, "infer", 2, 6), (1, "infer", 5, 7)]
+        (0, "train", 3, 5), (0, "infer", 2, 6), (1, "infer", 5, 7), (2, "train", 4, 8), (3, "train", 5, 9),
+        (2, "infer", 3, 10), (3, "infer", 2, 11), (3, "train", 2, 12), (3, "infer", 2, 13)]
+
+
+def job_shape(HW, J):
+    return HW.shape(J["s"], J["l"], J["a"], J["seed"], J.get("layout", 0))
+
+
+def model_buffer(ctx, sh):
+    rows, _ = ctx.model_rows(sh)
+    return zeros_u32(rows, ctx.dims(sh)[1], 2, NQ, N)
 
 
 def label_bits(y, L):
@@ -28,9 +40,8 @@ def setup(HW, sk):
     ctx = HW.Context(N, NQ, PM)
     models, ids, shapes = [], [], []
     for J in JOBS:
-        sh = HW.shape(J["s"], J["l"], J["a"], J["seed"])
-        k0, k1, _ = ctx.dims(sh)
-        H = zeros_u32(k0, k1, 2, NQ, N)
+        sh = job_shape(HW, J)
+        H = model_buffer(ctx, sh)
         models.append(H)
         shapes.append(sh)
         ids.append(eng.add_job(sh, H))
@@ -79,11 +90,11 @@ def test_alone_equals_mix_and_direct_path():
     for a, b in zip(o_alone, o_mix):
         assert (a is None and b is None) or np.array_equal(a, b)
     # direct path: the same ciphertexts (seed 500 + k, index sample * s + bit) through the library calls
-    for j in range(2):
+    for j in range(len(JOBS)):
         J = JOBS[j]
-        sh = HW.shape(J["s"], J["l"], J["a"], J["seed"])
+        sh = job_shape(HW, J)
         k0, k1, _ = ctx.dims(sh)
-        H = zeros_u32(k0, k1, 2, NQ, N)
+        H = model_buffer(ctx, sh)
         W = np.zeros((J["l"], k0, 1 << J["a"]), np.int64)
         pi = O.permutation(J["seed"], J["s"])
         L = O.ceil_log2(J["l"])

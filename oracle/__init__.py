@@ -450,7 +450,11 @@ class Ctx:
 
     # -- WiSARD --------------------------------------------------------------
     def k1(self, s: int, l: int, a: int, layout: int = 0) -> int:
-        """rows per RAM: layout 0 label-pruned (Def. 2), 1 class-packed"""
+        """rows per RAM: layout 0 label-pruned (Def. 2), 1 and 2 class-packed
+        (these need L = ceil(log2 l) <= log2 N, so that the tree holds tuple
+        bits only)"""
+        if layout and ceil_log2(l) > self.logN:
+            raise ValueError("class-packed layouts need ceil(log2 l) <= log2 N")
         return int(lib().orc_k1_layout(self.h, s, l, a, layout))
 
     def train(self, s, l, a, pi, x_get, y_get, n, H, rams=None, threads=None, layout=0):
@@ -459,6 +463,7 @@ class Ctx:
         RGSW (numpy) of input bit k of sample i; y_get(i, u) that of label bit u.
         layout 0: label-pruned rows; 1: class-packed rows."""
         L = ceil_log2(l)
+        self.k1(s, l, a, layout)  # rejects a class-packed layout the ring cannot hold
         k0 = -(-s // a)
         rams = list(range(k0)) if rams is None else list(rams)
         pi = np.ascontiguousarray(pi, np.uint32)
@@ -524,6 +529,7 @@ class Ctx:
         """class-packed inference of RAM j for one sample: one VP, then the
         LWE of every class, [l][nq][N+1]; x_get(k) -> RGSW of bit k.  layout
         2 reads RAM j from its block of row j / r."""
+        self.k1(s, l, a, layout)
         pi = np.ascontiguousarray(pi, np.uint32)
         xs = [None] * s
         for t in range(min(a, s - j * a)):

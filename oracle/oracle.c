@@ -956,7 +956,9 @@ uint32_t orc_k1(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a) {
  * brings the cells of all classes to coefficients c 2^(a_j - z). */
 uint32_t orc_k1_layout(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, uint32_t layout) {
   if (layout == 0) return orc_k1(c, s, l, a);
-  /* layouts 1 and 2: every tree leaf */
+  /* layouts 1 and 2: every tree leaf.  They need the tree to hold tuple bits
+   * only, z <= a_j, i.e. L <= log2 N; 0 marks the shape as invalid for them */
+  if (ceil_log2_u(l) > c->logN) return 0;
   uint32_t aj, nb, z;
   ram_geometry(c, s, l, a, 0, &aj, &nb, &z);
   (void)aj;
@@ -1111,6 +1113,7 @@ void orc_infer_packed(const orc_ctx* c, uint32_t s, uint32_t l, uint32_t a, cons
                       uint32_t* out) {
   size_t rw = rlwe_words(c);
   uint32_t k1 = orc_k1_layout(c, s, l, a, 1);
+  if (k1 == 0) return; /* L > log2 N: no class-packed layout (the wrapper rejects it first) */
   /* layout 2: RAM j is the (j mod r)-th block of 2^(L + a) coefficients of
    * row j / r; the VP's rotations move only within it */
   uint32_t r = layout == 2 ? orc_rams_per_row(c, l, a) : 1u;

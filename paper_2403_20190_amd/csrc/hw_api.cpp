@@ -303,6 +303,10 @@ hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d) {
   if (sh->l < 1 || sh->l > 256) return fail(HW_EINVAL, "l = %u out of range [1, 256]", sh->l);
   if (sh->a < 1 || sh->a > 20) return fail(HW_EINVAL, "a = %u out of range [1, 20]", sh->a);
   d->L = ceil_log2(sh->l);
+  // class-packed rows need the tree to hold tuple bits only (z <= a_j): L <= log2 N,
+  // which the supported rings (N >= 1024) and l <= 256 always meet
+  if (sh->layout && d->L > (uint32_t)c->logN)
+    return fail(HW_EINVAL, "layout %u needs ceil(log2 l) <= log2 N", sh->layout);
   d->k0 = (sh->s + sh->a - 1) / sh->a;
   const uint32_t nb = d->L + sh->a;
   const uint32_t nr = nb < (uint32_t)c->logN ? nb : (uint32_t)c->logN;

@@ -103,6 +103,8 @@ class Micro:
 
 
 CONFIGS = [
+    dict(N=32, s=5, l=200, a=2, n=5),  # L = 8 > z = 5: label bits in the tree and the chain; l not a power of two
+    dict(N=16, s=3, l=2, a=1, n=4),    # one-bit tuples: nb = 2 <= log N, no tree
     dict(N=16, s=14, l=3, a=4, n=6),   # nb = 6, log N = 4: z = 2 = L -> tree levels are the label bits
     dict(N=8, s=10, l=2, a=4, n=5),    # nb = 5, log N = 3: z = 2 > L = 1 -> one encrypted tree level
     dict(N=32, s=9, l=5, a=3, n=6),    # nb = 6, log N = 5: z = 1 < L = 3 -> label bits in the chain
@@ -150,6 +152,7 @@ def test_encrypted_inference_pd_act(cfg):
 
 
 PACKED = [
+    dict(N=256, s=5, l=200, a=2, n=5),  # L = 8 = log2 N: z = 2 = a, every chain bit a label bit
     dict(N=16, s=14, l=3, a=4, n=6),   # z = 2 tuple bits in the tree, chain: 2 tuple + 2 label bits
     dict(N=8, s=10, l=2, a=4, n=5),    # z = 2, a ragged last tuple of 2 bits (z = 0 there)
     dict(N=32, s=9, l=5, a=3, n=6),    # z = 1, label bits on top of a 3-bit tuple
@@ -224,6 +227,16 @@ def test_several_rams_per_row(cfg):
             for c in range(m.l):
                 cells[c, j] = m.c.dec_lwe(m.sk, lw[c])
         assert np.array_equal(cells, P.ram_scores(W, Xt[t], m.a, m.pi))
+
+
+def test_class_packed_needs_label_bits_within_the_ring():
+    """with L > log2 N the tree would hold label bits, which one VP cannot
+    serve for every class: the oracle refuses the layout"""
+    c = O.Ctx(32, 1, 64)
+    assert c.k1(5, 200, 2, 0) == 32  # layout 0 holds it (z = 5 < L = 8: all leaves)
+    for layout in (1, 2):
+        with pytest.raises(ValueError):
+            c.k1(5, 200, 2, layout)
 
 
 def test_extract_lwe_any_index():

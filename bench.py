@@ -121,6 +121,20 @@ def train_ops(N: int, nq: int, xp: float, ivps: float) -> float:
     return (xp - ivps) * ops_per_xp(N, nq) + ivps * ops_first_xp(N, nq)
 
 
+def ops_per_enc_row(N: int, nq: int) -> float:
+    """Algorithmic int32 ops of one RGSW row (an RLWE encryption of 0 plus the
+    gadget term), drawn as k_enc_rgsw draws it: Philox4x32-10 blocks for the
+    uniform a (nq N / 2, two 64-bit words each) and for the Gaussian e (N / 2),
+    80 ops a block (10 rounds of two 32x32->64 products at 2 ops and 4 XORs;
+    the key schedule is scalar); 10 ops to reduce a 64-bit word mod q; 30 per
+    CDT sample (6 search steps of a 64-bit compare and selects, the sign); the
+    forward NTT of e under each prime (9 ops a butterfly); 22 per coefficient
+    and prime for the lift of e and b = a s + e + gadget."""
+    logN = N.bit_length() - 1
+    return (80.0 * (nq + 1) * N / 2 + 10.0 * nq * N + 30.0 * N + 9.0 * nq * (N // 2) * logN
+            + 22.0 * nq * N)
+
+
 def modmul_per_xp(N: int, nq: int) -> float:
     """Modular multiplications of one external product:
     (2 l nq^2 + 2 nq) (N/2) log2 N + 4 l nq^2 N with l = 5 digits."""
@@ -345,6 +359,12 @@ def main():
         "encrypt_ms_per_step": round(en_ms / args.steps, 2),
         "train_only_samples_per_s": round(n / (train_kernel_ms / 1000.0), 3) if train_kernel_ms else None,
         "encrypt_only_samples_per_s": round(n / (en_ms / args.steps / 1000.0), 3) if en_ms else None,
+        "encrypt_roofline": {
+            "bound": "alu", "kernel": "k_enc_rgsw", "unit": "TOPS(int32)", "peak": round(PEAK_INT32_TOPS, 2),
+            "achieved": round(en_rows * ops_per_enc_row(N, nq) / (en_ms / 1000.0) / 1e12, 3) if en_ms else None,
+            "frac": round(en_rows * ops_per_enc_row(N, nq) / (en_ms / 1000.0) / 1e12 / PEAK_INT32_TOPS, 4)
+            if en_ms else None,
+            "rows": en_rows, "ops_per_row": ops_per_enc_row(N, nq)},
         "xp_per_s": round(steps_xp / (train_kernel_ms / 1000.0), 1) if train_kernel_ms else None,
         # the first product of each chain: 2 nq inverse NTTs, 2 nq N evaluation products, half the RGSW
         "ntt_per_s_in_xp": round((steps_full * (10 * nq * nq + 2 * nq) + steps_ivps * 2 * nq)

@@ -50,6 +50,8 @@ def lib():
                 "orc_find_primes": (C.c_int, [C.c_uint32, C.c_uint32, u32p]),
                 "orc_philox4x32_10": (None, [u32p, u32p, u32p]),
                 "orc_w64": (C.c_uint64, [C.c_uint64, C.c_uint32, C.c_uint64]),
+                "orc_w32": (C.c_uint32, [C.c_uint64, C.c_uint32, C.c_uint64]),
+                "orc_uniform_mod": (C.c_uint64, [C.c_uint64, C.c_uint64, C.c_uint64]),
                 "orc_cdt_table": (None, [C.c_double, u64p]),
                 "orc_cdt_sample": (C.c_int64, [u64p, C.c_uint64]),
                 "orc_ctx_new": (C.c_void_p, [C.c_uint32, C.c_uint32, u32p, C.c_uint32, C.c_uint32, C.c_uint64, C.c_double]),
@@ -154,6 +156,16 @@ def leaf_row(d: int, z: int, l: int) -> int:
 
 def w64(seed: int, domain: int, index: int) -> int:
     return int(lib().orc_w64(seed, domain, index))
+
+
+def w32(seed: int, domain: int, index: int) -> int:
+    return int(lib().orc_w32(seed, domain, index))
+
+
+def uniform_mod(seed: int, x: int, q: int) -> int:
+    """uniform residue mod q of encryption draw x (32-bit word with rejection,
+    64-bit fallback draw)"""
+    return int(lib().orc_uniform_mod(seed, x, q))
 
 
 def cdt_table(sigma: float = 3.2) -> np.ndarray:

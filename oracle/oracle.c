@@ -47,6 +47,7 @@ typedef unsigned __int128 u128;
 #define DOM_PERM 2u
 #define DOM_ENC_A 3u
 #define DOM_ENC_E 4u
+#define DOM_ENC_A2 5u
 #define CDT_TAIL 41
 
 /* ------------------------------------------------------------------------ */
@@ -132,6 +133,29 @@ uint64_t orc_w64(uint64_t seed, uint32_t domain, uint64_t index) {
   orc_philox4x32_10(ctr, key, o);
   if (index & 1) return (uint64_t)o[2] | ((uint64_t)o[3] << 32);
   return (uint64_t)o[0] | ((uint64_t)o[1] << 32);
+}
+
+/* 32-bit draw number `index` of stream (seed, domain): word index mod 4 of
+ * block index / 4 (counter (block, domain, 0), key = seed). */
+uint32_t orc_w32(uint64_t seed, uint32_t domain, uint64_t index) {
+  uint64_t blk = index >> 2;
+  uint32_t ctr[4] = {(uint32_t)blk, (uint32_t)(blk >> 32), domain, 0u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t o[4];
+  orc_philox4x32_10(ctr, key, o);
+  return o[index & 3];
+}
+
+/* Uniform residue mod q of draw x of the encryption stream: the 32-bit word
+ * w = w32(seed, ENC_A, x) when w < floor(2^32 / q) q, as w mod q (each
+ * residue then has exactly floor(2^32 / q) preimages); otherwise the 64-bit
+ * draw w64(seed, ENC_A2, x) mod q (probability (2^32 mod q) / 2^32, about
+ * 3e-5 for q near 2^30). */
+uint64_t orc_uniform_mod(uint64_t seed, uint64_t x, uint64_t q) {
+  uint32_t w = orc_w32(seed, DOM_ENC_A, x);
+  uint64_t lim = (((uint64_t)1 << 32) / q) * q;
+  if (w < lim) return w % q;
+  return orc_w64(seed, DOM_ENC_A2, x) % q;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -449,7 +473,7 @@ static void from_evaluations(const orc_ctx* c, uint32_t i, const uint64_t* ev, u
 /* EncRLWE of an integer polynomial mu (coefficients in [0, p)):
  * b = a*s + Delta*mu + e, a uniform in R_q (Sec. 2.5.1).  The draws of row
  * `row` of ciphertext `ct` among `rows` rows per ciphertext are
- *   u_{i,k} = w64(seed, ENC_A, ((ct*rows + row)*nq + i)*N + k) mod q_i
+ *   u_{i,k} = uniform_mod(seed, ((ct*rows + row)*nq + i)*N + k, q_i)
  *   e_k     = CDT(w64(seed, ENC_E, (ct*rows + row)*N + k)),
  * e being one integer polynomial shared by all primes.  With a_eval == 0
  * the u_{i,k} are the coefficients of a mod q_i; with a_eval != 0 they are
@@ -468,7 +492,7 @@ static void enc_row(const orc_ctx* c, const int32_t* s, const uint64_t* mu, uint
   for (uint32_t i = 0; i < nq; ++i) {
     uint64_t q = c->q[i];
     for (uint32_t k = 0; k < N; ++k) {
-      P[k] = orc_w64(seed, DOM_ENC_A, (rid * nq + i) * N + k) % q;
+      P[k] = orc_uniform_mod(seed, (rid * nq + i) * N + k, q);
       S[k] = (uint64_t)(s[k] < 0 ? (int64_t)q + s[k] : s[k]);
     }
     if (a_eval)

@@ -248,8 +248,8 @@ def test_rgsw_rows_draw_a_by_its_evaluations(N, nq):
                 acc = 0
                 for coef in reversed(a):
                     acc = (acc * x + coef) % q
-                assert acc == O.w64(seed, 3, ((ct * rows + r) * nq + i) * N + k) % q, (r, i, k)
+                assert acc == O.uniform_mod(seed, ((ct * rows + r) * nq + i) * N + k, q), (r, i, k)
     rl = c.enc_rlwe(s, np.zeros(N, np.uint64), seed, ct)
     for i, q in enumerate(c.primes):
         for k in (0, 5, N - 1):
-            assert int(rl[0, i, k]) == O.w64(seed, 3, (ct * nq + i) * N + k) % q
+            assert int(rl[0, i, k]) == O.uniform_mod(seed, (ct * nq + i) * N + k, q)

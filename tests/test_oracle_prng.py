@@ -31,6 +31,42 @@ def test_w64_layout():
         assert O.w64(seed, dom, idx) == want
 
 
+def test_w32_layout():
+    # word index mod 4 of block index / 4; key = seed, ctr = (blk, domain, 0)
+    seed, dom = 0x0123456789ABCDEF, 3
+    for idx in [0, 1, 2, 3, 4, 7, 12345, 2**34 + 6]:
+        blk = idx >> 2
+        o = O.philox4x32_10([blk & 0xFFFFFFFF, blk >> 32, dom, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        assert O.w32(seed, dom, idx) == o[idx & 3]
+
+
+def test_uniform_residue_rule():
+    """Accepted words (below floor(2^32/q) q) give w mod q; the rejected ones
+    (found by search: about 3e-5 of them at q near 2^30) take the 64-bit
+    fallback draw of domain 5.  Accepted words are exactly uniform: every
+    residue has floor(2^32/q) preimages below the limit."""
+    q = 1073707009
+    lim = (2**32 // q) * q
+    seed = 91
+    rejected = [x for x in range(300000) if O.w32(seed, 3, x) >= lim]
+    assert rejected, "expected a rejected word among 300000 draws"
+    for x in rejected[:5]:
+        assert O.uniform_mod(seed, x, q) == O.w64(seed, 5, x) % q
+    for x in [0, 1, 2, 3, 99, 123457]:
+        if x not in rejected:
+            assert O.uniform_mod(seed, x, q) == O.w32(seed, 3, x) % q
+    # small prime: the rejection rate is (2^32 mod q) / 2^32 and the limit is a multiple of q
+    q2 = 12289
+    lim2 = (2**32 // q2) * q2
+    assert lim2 % q2 == 0 and 2**32 - lim2 == 2**32 % q2 < q2
+    vals = [O.uniform_mod(7, x, q2) for x in range(20000)]
+    assert min(vals) >= 0 and max(vals) < q2
+    # a crude uniformity check: the mean of 20000 residues within 5 sigma of (q - 1) / 2
+    mean = sum(vals) / len(vals)
+    sd = (q2 / 12 ** 0.5) / len(vals) ** 0.5
+    assert abs(mean - (q2 - 1) / 2) < 5 * sd
+
+
 def test_cdt_table_matches_distribution():
     sigma = 3.2
     T = O.cdt_table(sigma)

@@ -124,14 +124,16 @@ def train_ops(N: int, nq: int, xp: float, ivps: float) -> float:
 def ops_per_enc_row(N: int, nq: int) -> float:
     """Algorithmic int32 ops of one RGSW row (an RLWE encryption of 0 plus the
     gadget term), drawn as k_enc_rgsw draws it: Philox4x32-10 blocks for the
-    uniform a (nq N / 2, two 64-bit words each) and for the Gaussian e (N / 2),
-    80 ops a block (10 rounds of two 32x32->64 products at 2 ops and 4 XORs;
-    the key schedule is scalar); 10 ops to reduce a 64-bit word mod q; 30 per
-    CDT sample (6 search steps of a 64-bit compare and selects, the sign); the
-    forward NTT of e under each prime (9 ops a butterfly); 22 per coefficient
-    and prime for the lift of e and b = a s + e + gadget."""
+    uniform a (nq N / 4: one 32-bit word per residue; the rare rejected word's
+    fallback draw is not counted) and for the Gaussian e (N / 2, one 64-bit
+    word per sample), 80 ops a block (10 rounds of two 32x32->64 products at
+    2 ops and 4 XORs; the key schedule is scalar); 6 ops to reduce a word mod
+    q and test it; 30 per CDT sample (6 fixed search steps of a 64-bit
+    compare and a select, the sign); the forward NTT of e under each prime
+    (9 ops a butterfly); 22 per coefficient and prime for the lift of e and
+    b = a s + e + gadget."""
     logN = N.bit_length() - 1
-    return (80.0 * (nq + 1) * N / 2 + 10.0 * nq * N + 30.0 * N + 9.0 * nq * (N // 2) * logN
+    return (80.0 * (nq * N / 4 + N / 2) + 6.0 * nq * N + 30.0 * N + 9.0 * nq * (N // 2) * logN
             + 22.0 * nq * N)
 
 

@@ -44,16 +44,57 @@ __device__ __forceinline__ void draw_pair(uint64_t seed, uint32_t domain, uint64
   d1 = (uint64_t)o.z | ((uint64_t)o.w << 32);
 }
 
-constexpr uint32_t DOM_KEY = 1, DOM_ENC_A = 3, DOM_ENC_E = 4;
+constexpr uint32_t DOM_KEY = 1, DOM_ENC_A = 3, DOM_ENC_E = 4, DOM_ENC_A2 = 5;
 
+// the four 32-bit draws 4*blk .. 4*blk+3 of stream (seed, domain)
+__device__ __forceinline__ uint4 draw4(uint64_t seed, uint32_t domain, uint64_t blk) {
+  return philox10(make_uint4((uint32_t)blk, (uint32_t)(blk >> 32), domain, 0u), (uint32_t)seed,
+                  (uint32_t)(seed >> 32));
+}
+
+// Uniform residues mod q of encryption draws x0 .. x0+K-1 (x0 a multiple of
+// 4), from their 32-bit words of stream (seed, ENC_A): w mod q when
+// w < floor(2^32 / q) q, which is exactly uniform; otherwise (probability
+// (2^32 mod q) / 2^32, about 3e-5 near 2^30) the 64-bit draw x of
+// (seed, ENC_A2) mod q.  floor(2^32 / q) q < 2^32 is one_sh * q in 32 bits.
+// The accepted path is branch-free; one branch per call, almost never taken,
+// replaces the rejected words.
+template <int K>
+__device__ __forceinline__ void uniform_k(uint64_t seed, uint64_t x0, const PrimeTab& P, uint32_t (&xa)[K]) {
+  const uint32_t lim = P.one_sh * P.q;
+  uint32_t rej = 0;
+#pragma unroll
+  for (int f = 0; f < K / 4; ++f) {
+    const uint4 w = draw4(seed, DOM_ENC_A, (x0 >> 2) + f);
+    const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      xa[4 * f + u] = csub(mulsh(ww[u], 1u, P.one_sh, P.q), P.q);
+      rej |= (uint32_t)(ww[u] >= lim) << (4 * f + u);
+    }
+  }
+  if (__builtin_expect(rej != 0u, 0)) {
+#pragma unroll 1
+    for (int u = 0; u < K; ++u)
+      if ((rej >> u) & 1u) {
+        const uint64_t x = x0 + u;
+        uint64_t d0, d1;
+        draw_pair(seed, DOM_ENC_A2, x >> 1, d0, d1);
+        xa[u] = red64((x & 1) ? d1 : d0, P);
+      }
+  }
+}
+
+// magnitude = the smallest k with r < T[k] (T[41] = 2^63 > r), i.e. the
+// number of entries T[j] <= r: T is non-decreasing, so those form a prefix.
+// Six fixed steps of 32, 16, .., 1 find it without data-dependent branches.
 __device__ __forceinline__ int32_t cdt_sample(const uint64_t* T, uint64_t w) {
   const uint64_t r = w >> 1;
-  int lo = 0, hi = 41;  // smallest k with r < T[k]; T[41] = 2^63 > r
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (r < T[mid]) hi = mid; else lo = mid + 1;
-  }
-  return (lo != 0 && (w & 1)) ? -lo : lo;
+  int k = 0;
+#pragma unroll
+  for (int b = 32; b >= 1; b >>= 1)
+    if (k + b <= 41 && T[k + b - 1] <= r) k += b;
+  return (k != 0 && (w & 1)) ? -k : k;
 }
 
 // ---------------------------------------------------------------------------
@@ -98,23 +139,25 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_sk_hat(Tabs T, const int32_t* 
 // ---------------------------------------------------------------------------
 // encryption
 // ---------------------------------------------------------------------------
-// Draws of row `rid` (= ciphertext * rows + row): u_{i,k} is draw
-// (rid*NQ + i)*N + k of stream ENC_A reduced mod q_i, the coefficient k of a
-// for an RLWE ciphertext and the value of a at psi^(2 brv(k) + 1) for an RGSW
-// row; e_k is the CDT sample of draw rid*N + k of stream ENC_E.  Coefficient
-// draws are generated in pairs and staged through LDS into the natural layout.
+// Draws of row `rid` (= ciphertext * rows + row): u_{i,k} is the uniform
+// residue mod q_i of encryption draw (rid*NQ + i)*N + k (uniform_residue: its
+// 32-bit word of stream ENC_A, with rejection), the coefficient k of a for an
+// RLWE ciphertext and the value of a at psi^(2 brv(k) + 1) for an RGSW row;
+// e_k is the CDT sample of 64-bit draw rid*N + k of stream ENC_E.
+// Coefficient draws are generated four at a time and staged through LDS into
+// the natural layout.
 
 template <int LOGN>
-__device__ __forceinline__ void gen_uniform(uint64_t seed, uint64_t base_blk, const PrimeTab& P,
+__device__ __forceinline__ void gen_uniform(uint64_t seed, uint64_t x0, const PrimeTab& P,
                                             uint32_t* __restrict__ stage, uint32_t t, uint32_t (&x)[8]) {
   constexpr int N = 1 << LOGN, TT = N / 8;
   __syncthreads();
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
+  for (int f = 0; f < 2; ++f) {  // thread t draws coefficients 4b .. 4b+3, b = t + TT f
     const uint32_t b = t + TT * f;
-    uint64_t d0, d1;
-    draw_pair(seed, DOM_ENC_A, base_blk + b, d0, d1);
-    *reinterpret_cast<uint2*>(stage + 2 * b) = make_uint2(red64(d0, P), red64(d1, P));
+    uint32_t r[4];
+    uniform_k<4>(seed, x0 + 4 * (uint64_t)b, P, r);
+    *reinterpret_cast<uint4*>(stage + 4 * b) = make_uint4(r[0], r[1], r[2], r[3]);
   }
   __syncthreads();
 #pragma unroll
@@ -176,14 +219,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncA
       const uint32_t r = r0 + k;
       const uint64_t rid = ct * ROWS + r;
       uint32_t xa[8], xe[8];
-      const uint64_t blk0 = (rid * NQ + i) * (N / 2) + 4 * t;
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        uint64_t d0, d1;
-        draw_pair(A.seed, DOM_ENC_A, blk0 + f, d0, d1);
-        xa[2 * f] = red64(d0, P);
-        xa[2 * f + 1] = red64(d1, P);
-      }
+      uniform_k<8>(A.seed, (rid * NQ + i) * (uint64_t)N + 8 * t, P, xa);  // evaluation positions 8t .. 8t+7
 #pragma unroll
       for (int e = 0; e < 8; ++e) xe[e] = ev[k][e] < 0 ? (uint32_t)(ev[k][e] + (int32_t)P.q) : (uint32_t)ev[k][e];
       ntt_fwd<LOGN>(xe, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
@@ -239,14 +275,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_pks(Tabs T, Cdt cdt, EncAr
     const uint4 s0 = sp[0], s1 = sp[1];
     const uint32_t sh[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
     uint32_t xa[8], xe[8];
-    const uint64_t blk0 = (rid * NQ + i) * (N / 2) + 4 * t;
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      uint64_t d0, d1;
-      draw_pair(A.seed, DOM_ENC_A, blk0 + f, d0, d1);
-      xa[2 * f] = red64(d0, P);
-      xa[2 * f + 1] = red64(d1, P);
-    }
+    uniform_k<8>(A.seed, (rid * NQ + i) * (uint64_t)N + 8 * t, P, xa);  // evaluation positions 8t .. 8t+7
 #pragma unroll
     for (int e = 0; e < 8; ++e) xe[e] = ev[e] < 0 ? (uint32_t)(ev[e] + (int32_t)P.q) : (uint32_t)ev[e];
     ntt_fwd<LOGN>(xe, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
@@ -287,7 +316,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rlwe(Tabs T, Cdt cdt, EncA
     __syncthreads();
     load_tw_lds<LOGN>(twl, T.fwd[i], t);
     uint32_t xa[8], a0[8];
-    gen_uniform<LOGN>(A.seed, (rid * NQ + i) * (N / 2), P, stage, t, xa);
+    gen_uniform<LOGN>(A.seed, (rid * NQ + i) * (uint64_t)N, P, stage, t, xa);
 #pragma unroll
     for (int e = 0; e < 8; ++e) a0[e] = xa[e];
     ntt_fwd<LOGN>(xa, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);

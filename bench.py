@@ -130,11 +130,11 @@ def ops_per_enc_row(N: int, nq: int) -> float:
     2 ops and 4 XORs; the key schedule is scalar); 6 ops to reduce a word mod
     q and test it; 30 per CDT sample (6 fixed search steps of a 64-bit
     compare and a select, the sign); the forward NTT of e under each prime
-    (9 ops a butterfly); 22 per coefficient and prime for the lift of e and
-    b = a s + e + gadget."""
+    (9 ops a butterfly); 16 per coefficient and prime for the lift of e and
+    b = a s + e + gadget (a Shoup product with the transformed key)."""
     logN = N.bit_length() - 1
     return (80.0 * (nq * N / 4 + N / 2) + 6.0 * nq * N + 30.0 * N + 9.0 * nq * (N // 2) * logN
-            + 22.0 * nq * N)
+            + 16.0 * nq * N)
 
 
 def modmul_per_xp(N: int, nq: int) -> float:

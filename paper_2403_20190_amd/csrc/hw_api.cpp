@@ -226,7 +226,7 @@ extern "C" hw_status hw_ctx_create(const hw_params* params, int device, hw_ctx**
 
   hipError_t e = hipMalloc(&c->d_tables, host.size() * sizeof(uint2));
   if (e == hipSuccess) e = hipMemcpy(c->d_tables, host.data(), host.size() * sizeof(uint2), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc(&c->d_skhat, sizeof(uint32_t) * P.nq * N);
+  if (e == hipSuccess) e = hipMalloc(&c->d_skhat, sizeof(uint32_t) * sk_hat_words(c));
   if (e != hipSuccess) {
     hw_ctx_destroy(c);
     return fail(e == hipErrorOutOfMemory ? HW_ENOMEM : HW_EDEVICE, "table upload: %s", hipGetErrorString(e));

@@ -48,7 +48,7 @@ struct hw_ctx {
   hw::Cdt cdt;
   u128 Q;
   void* d_tables = nullptr;        // twiddle tables of every prime
-  uint32_t* d_skhat = nullptr;     // [nq][N]
+  uint32_t* d_skhat = nullptr;     // sk_hat_words(): [nq][N] transformed key, then [nq][N] Shoup companions
   void* d_ws = nullptr;            // workspace
   size_t ws_bytes = 0;
   size_t ws_budget = 0;
@@ -182,6 +182,8 @@ hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d);
 hw_status perm_for(hw_ctx* c, const hw_wisard_shape* sh, hipStream_t st, const uint32_t** out);
 
 // workspace bytes per sample of one training / inference call
+// words of a transformed key buffer (launch_sk_hat's output): values and Shoup companions
+inline size_t sk_hat_words(const hw_ctx* c) { return (size_t)2 * c->prm.nq * c->prm.N; }
 size_t train_ws_per_sample(const hw_ctx* c, const Dims& d);
 size_t infer_ws_per_sample(const hw_ctx* c, const hw_wisard_shape* sh, const Dims& d);
 

@@ -328,7 +328,7 @@ extern "C" hw_status hw_engine_create(const hw_params* params, int device, const
     hw_engine_destroy(E);
     return st;
   };
-  hipError_t e = hipMalloc(&E->skhat, sizeof(uint32_t) * c->prm.nq * c->prm.N);
+  hipError_t e = hipMalloc(&E->skhat, sizeof(uint32_t) * sk_hat_words(c));
   if (e == hipSuccess) e = hw::launch_sk_hat(c->logN, c->prm.nq, c->tabs, sk_dev, E->skhat, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e == hipSuccess) e = hipMalloc(&E->arena, cfg->arena_bytes);

@@ -22,7 +22,7 @@ struct Cdt {
 
 struct EncArgs {
   const int32_t* sk;        // [N]
-  const uint32_t* sk_hat;   // [NQ][N] evaluation domain (layout P=3)
+  const uint32_t* sk_hat;   // [NQ][N] evaluation domain (layout P=3), then [NQ][N] Shoup companions
   const uint8_t* bits;      // RGSW: one bit per ciphertext
   const uint64_t* msg;      // RLWE: [count][N] or nullptr
   uint32_t* out;
@@ -133,6 +133,7 @@ struct SumArgs {
 
 // launchers (hw_kernels.hip); return hipSuccess or the launch error
 hipError_t launch_keygen(uint32_t N, uint64_t seed, int32_t* sk, hipStream_t st);
+// sk_hat: 2 nq N words (the transformed key, then its Shoup companions)
 hipError_t launch_sk_hat(int logN, int nq, const Tabs& T, const int32_t* sk, uint32_t* sk_hat, hipStream_t st);
 hipError_t launch_enc_rgsw(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
                            int rows_per_wg, hipStream_t st);

@@ -110,7 +110,7 @@ __global__ void k_keygen(uint32_t N, uint64_t seed, int32_t* sk) {
   sk[k] = (int32_t)(w % 3) - 1;
 }
 
-// sk_hat[i] = NTT(s mod q_i), evaluation layout
+// sk_hat[i] = NTT(s mod q_i), evaluation layout; sk_hat[NQ + i] = its Shoup companions
 template <int LOGN, int NQ>
 __global__ __launch_bounds__(Geo<LOGN>::T) void k_sk_hat(Tabs T, const int32_t* __restrict__ sk,
                                                           uint32_t* __restrict__ out) {
@@ -129,11 +129,31 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_sk_hat(Tabs T, const int32_t* 
   __syncthreads();
   uint32_t xc = 0;
   ntt_fwd<LOGN>(x, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
+  uint32_t v[8], w[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    v[e] = red4q(x[e], P.q, P.two_q);
+    w[e] = (uint32_t)(((uint64_t)v[e] << 32) / P.q);  // Shoup companion floor(v 2^32 / q)
+  }
   uint4* o = reinterpret_cast<uint4*>(out + (size_t)i * N + (t << 3));
-  o[0] = make_uint4(red4q(x[0], P.q, P.two_q), red4q(x[1], P.q, P.two_q), red4q(x[2], P.q, P.two_q),
-                    red4q(x[3], P.q, P.two_q));
-  o[1] = make_uint4(red4q(x[4], P.q, P.two_q), red4q(x[5], P.q, P.two_q), red4q(x[6], P.q, P.two_q),
-                    red4q(x[7], P.q, P.two_q));
+  o[0] = make_uint4(v[0], v[1], v[2], v[3]);
+  o[1] = make_uint4(v[4], v[5], v[6], v[7]);
+  uint4* os = reinterpret_cast<uint4*>(out + (size_t)(NQ + i) * N + (t << 3));
+  os[0] = make_uint4(w[0], w[1], w[2], w[3]);
+  os[1] = make_uint4(w[4], w[5], w[6], w[7]);
+}
+
+// the transformed key and its Shoup companions for thread t's entries 8t .. 8t+7 of prime i
+template <int LOGN, int NQ>
+__device__ __forceinline__ void load_sk_hat(const uint32_t* __restrict__ sk_hat, int i, uint32_t t,
+                                            uint32_t (&sh)[8], uint32_t (&shs)[8]) {
+  constexpr int N = 1 << LOGN;
+  const uint4* sp = reinterpret_cast<const uint4*>(sk_hat + (size_t)i * N + (t << 3));
+  const uint4* ss = reinterpret_cast<const uint4*>(sk_hat + (size_t)(NQ + i) * N + (t << 3));
+  const uint4 s0 = sp[0], s1 = sp[1], c0 = ss[0], c1 = ss[1];
+  sh[0] = s0.x; sh[1] = s0.y; sh[2] = s0.z; sh[3] = s0.w; sh[4] = s1.x; sh[5] = s1.y; sh[6] = s1.z; sh[7] = s1.w;
+  shs[0] = c0.x; shs[1] = c0.y; shs[2] = c0.z; shs[3] = c0.w; shs[4] = c1.x; shs[5] = c1.y; shs[6] = c1.z;
+  shs[7] = c1.w;
 }
 
 // ---------------------------------------------------------------------------
@@ -211,9 +231,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncA
     const PrimeTab P = T.pt[i];
     __syncthreads();
     load_tw_lds<LOGN>(twl, T.fwd[i], t);
-    const uint4* sp = reinterpret_cast<const uint4*>(A.sk_hat + (size_t)i * N + (t << 3));
-    const uint4 s0 = sp[0], s1 = sp[1];
-    const uint32_t sh[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+    uint32_t sh[8], shs[8];
+    load_sk_hat<LOGN, NQ>(A.sk_hat, i, t, sh, shs);
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       const uint32_t r = r0 + k;
@@ -231,7 +250,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncA
       for (int e = 0; e < 8; ++e) {
         const uint32_t av = xa[e];
         const uint32_t ee = red4q(xe[e], P.q, P.two_q);
-        const uint32_t bv = addq(mulq(av, sh[e], P), ee, P.q);
+        const uint32_t bv = addq(csub(mulsh(av, sh[e], shs[e], P.q), P.q), ee, P.q);
         oa[e] = brow ? av : addq(av, g, P.q);
         ob[e] = brow ? addq(bv, g, P.q) : bv;
       }
@@ -271,9 +290,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_pks(Tabs T, Cdt cdt, EncAr
     const PrimeTab P = T.pt[i];
     __syncthreads();
     load_tw_lds<LOGN>(twl, T.fwd[i], t);
-    const uint4* sp = reinterpret_cast<const uint4*>(A.sk_hat + (size_t)i * N + (t << 3));
-    const uint4 s0 = sp[0], s1 = sp[1];
-    const uint32_t sh[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+    uint32_t sh[8], shs[8];
+    load_sk_hat<LOGN, NQ>(A.sk_hat, i, t, sh, shs);
     uint32_t xa[8], xe[8];
     uniform_k<8>(A.seed, (rid * NQ + i) * (uint64_t)N + 8 * t, P, xa);  // evaluation positions 8t .. 8t+7
 #pragma unroll
@@ -284,7 +302,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_pks(Tabs T, Cdt cdt, EncAr
     uint32_t ob[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-      ob[e] = addq(addq(mulq(xa[e], sh[e], P), red4q(xe[e], P.q, P.two_q), P.q), g, P.q);
+      ob[e] = addq(addq(csub(mulsh(xa[e], sh[e], shs[e], P.q), P.q), red4q(xe[e], P.q, P.two_q), P.q), g, P.q);
     uint4* pa = reinterpret_cast<uint4*>(row + (size_t)i * N + (t << 3));
     uint4* pb = reinterpret_cast<uint4*>(row + (size_t)(NQ + i) * N + (t << 3));
     pa[0] = make_uint4(xa[0], xa[1], xa[2], xa[3]);
@@ -320,11 +338,10 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rlwe(Tabs T, Cdt cdt, EncA
 #pragma unroll
     for (int e = 0; e < 8; ++e) a0[e] = xa[e];
     ntt_fwd<LOGN>(xa, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
-    const uint4* sp = reinterpret_cast<const uint4*>(A.sk_hat + (size_t)i * N + (t << 3));
-    const uint4 s0 = sp[0], s1 = sp[1];
-    const uint32_t sh[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+    uint32_t sh[8], shs[8];
+    load_sk_hat<LOGN, NQ>(A.sk_hat, i, t, sh, shs);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) xa[e] = csub(mulq(red4q(xa[e], P.q, P.two_q), sh[e], P), P.two_q);
+    for (int e = 0; e < 8; ++e) xa[e] = csub(mulsh(red4q(xa[e], P.q, P.two_q), sh[e], shs[e], P.q), P.q);
     ntt_inv<LOGN>(xa, T.inv[i], P, lds, xc, t);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {

@@ -370,6 +370,24 @@ struct XpOut {
   int mode;
 };
 
+// Balanced base-2^6 digits of a centred residue v (|v| < 2^29), read off
+// w = v + DIGIT_OFFSET, DIGIT_OFFSET = 32 (1 + 64 + 64^2 + 64^3): since
+// v = sum_{j<4} d_j 64^j + d_4 64^4 with d_j in [-32, 32), the low 24 bits
+// of w are the d_j + 32 and w >> 24 (arithmetic) is d_4.  These are the
+// digits that repeating d = ((v + 32) mod 64) - 32, v = (v - d) / 64 gives;
+// one bit-field extract per digit instead of that carry chain.  Returned
+// lifted into [0, q).
+constexpr int32_t DIGIT_OFFSET = 32 * (1 + 64 + 4096 + 262144);
+
+__device__ __forceinline__ uint32_t digit_lift(int32_t w, int j, uint32_t q) {
+  if (j < 4) {
+    const uint32_t u = ((uint32_t)w >> (6 * j)) & 63u;
+    return u < 32u ? u + (q - 32u) : u - 32u;
+  }
+  const int32_t d = w >> 24;
+  return d < 0 ? (uint32_t)(d + (int32_t)q) : (uint32_t)d;
+}
+
 // inverse transforms of the a and b sums of output prime ip (inputs in [0, q))
 // and the write of the external product by out.mode
 template <int LOGN, int NQ>
@@ -425,11 +443,11 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
       const int p = side == 0 ? 1 : 0;
       const uint32_t qi = T.pt[i].q;
       const uint32_t* src = xin + ((size_t)p * NQ + i) * N;
-      int32_t v[8];
+      int32_t w[8];  // centred residues plus DIGIT_OFFSET
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const uint32_t r = (src + TT * e)[t];
-        v[e] = r > (qi - 1) / 2 ? (int32_t)(r - qi) : (int32_t)r;
+        w[e] = (r > (qi - 1) / 2 ? (int32_t)(r - qi) : (int32_t)r) + DIGIT_OFFSET;
       }
 #pragma unroll 1
       for (int j = 0; j < 5; ++j) {
@@ -439,16 +457,7 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
         const uint4 cb0 = crb[2 * t], cb1 = crb[2 * t + 1];
         uint32_t x[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          int32_t d;
-          if (j < 4) {
-            d = ((v[e] + 32) & 63) - 32;
-            v[e] = (v[e] - d) >> 6;
-          } else {
-            d = v[e];
-          }
-          x[e] = d < 0 ? (uint32_t)(d + (int32_t)P.q) : (uint32_t)d;
-        }
+        for (int e = 0; e < 8; ++e) x[e] = digit_lift(w[e], j, P.q);
         ntt_fwd<LOGN>(x, T.fwd[ip], twl, P.q, P.two_q, lds, xc, t);
         const uint32_t ca[8] = {ca0.x, ca0.y, ca0.z, ca0.w, ca1.x, ca1.y, ca1.z, ca1.w};
         const uint32_t cb[8] = {cb0.x, cb0.y, cb0.z, cb0.w, cb1.x, cb1.y, cb1.z, cb1.w};

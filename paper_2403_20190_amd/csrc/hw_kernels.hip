@@ -1066,7 +1066,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WA
       for (int e = 0; e < 8; ++e) {
         const uint32_t i = t + TT * e;
         const uint32_t r = i < A.k ? lwe[(size_t)i * LW + (size_t)g * (N + 1) + j] : 0u;
-        v[e] = r > (qg - 1) / 2 ? (int32_t)(r - qg) : (int32_t)r;
+        v[e] = (r > (qg - 1) / 2 ? (int32_t)(r - qg) : (int32_t)r) + DIGIT_OFFSET;
       }
 #pragma unroll 1
       for (int dt = 0; dt < 5; ++dt) {
@@ -1076,16 +1076,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WA
         const uint4 kb0 = krb[2 * t], kb1 = krb[2 * t + 1];
         uint32_t x[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          int32_t d;
-          if (dt < 4) {
-            d = ((v[e] + 32) & 63) - 32;
-            v[e] = (v[e] - d) >> 6;
-          } else {
-            d = v[e];
-          }
-          x[e] = d < 0 ? (uint32_t)(d + (int32_t)P.q) : (uint32_t)d;
-        }
+        for (int e = 0; e < 8; ++e) x[e] = digit_lift(v[e], dt, P.q);  // v: centred residues + DIGIT_OFFSET
         ntt_fwd<LOGN>(x, T.fwd[ip], twl, P.q, P.two_q, lds, xc, t);
         const uint32_t ka[8] = {ka0.x, ka0.y, ka0.z, ka0.w, ka1.x, ka1.y, ka1.z, ka1.w};
         const uint32_t kb[8] = {kb0.x, kb0.y, kb0.z, kb0.w, kb1.x, kb1.y, kb1.z, kb1.w};

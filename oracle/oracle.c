@@ -474,7 +474,7 @@ static void from_evaluations(const orc_ctx* c, uint32_t i, const uint64_t* ev, u
  * b = a*s + Delta*mu + e, a uniform in R_q (Sec. 2.5.1).  The draws of row
  * `row` of ciphertext `ct` among `rows` rows per ciphertext are
  *   u_{i,k} = uniform_mod(seed, ((ct*rows + row)*nq + i)*N + k, q_i)
- *   e_k     = CDT(w64(seed, ENC_E, (ct*rows + row)*N + k)),
+ *   e_k     = CDT(w64(seed, ENC_E, (ct*rows + row)*N + 8 (k mod N/8) + floor(k / (N/8)))),
  * e being one integer polynomial shared by all primes.  With a_eval == 0
  * the u_{i,k} are the coefficients of a mod q_i; with a_eval != 0 they are
  * its values at the points psi_i^(2 brv(k) + 1) (the same uniform
@@ -488,7 +488,12 @@ static void enc_row(const orc_ctx* c, const int32_t* s, const uint64_t* mu, uint
   uint64_t* P = (uint64_t*)malloc(sizeof(uint64_t) * N);
   int64_t* e = (int64_t*)malloc(sizeof(int64_t) * N);
   uint64_t rid = ct * rows + row;
-  for (uint32_t k = 0; k < N; ++k) e[k] = orc_cdt_sample(c->cdt, orc_w64(seed, DOM_ENC_E, rid * N + k));
+  /* coefficient k takes error draw 8 (k mod N/8) + k / (N/8): a bijection
+   * of [0, N) (the order in which the draws are consumed is a convention) */
+  for (uint32_t k = 0; k < N; ++k) {
+    uint32_t pos = 8u * (k % (N / 8u)) + k / (N / 8u);
+    e[k] = orc_cdt_sample(c->cdt, orc_w64(seed, DOM_ENC_E, rid * N + pos));
+  }
   for (uint32_t i = 0; i < nq; ++i) {
     uint64_t q = c->q[i];
     for (uint32_t k = 0; k < N; ++k) {

@@ -253,3 +253,24 @@ def test_rgsw_rows_draw_a_by_its_evaluations(N, nq):
     for i, q in enumerate(c.primes):
         for k in (0, 5, N - 1):
             assert int(rl[0, i, k]) == O.uniform_mod(seed, (ct * nq + i) * N + k, q)
+
+
+@pytest.mark.parametrize("N,nq", [(1024, 1), (2048, 2)])
+def test_rlwe_error_draw_order(N, nq):
+    """The error of an encryption of 0, b - a s recomputed with the
+    schoolbook product (no transform), is coefficient by coefficient the CDT
+    sample of error draw 8 (k mod N/8) + floor(k / (N/8)) of the row."""
+    c = O.Ctx(N, nq, 64)
+    s = c.keygen(9)
+    seed, ct = 41, 2
+    rl = c.enc_rlwe(s, np.zeros(N, np.uint64), seed, ct)
+    T = O.cdt_table(3.2)
+    q = c.primes[0]
+    a = rl[0, 0].astype(np.uint64)
+    b = rl[1, 0].astype(np.int64)
+    sk = np.array([(int(v) + q) % q for v in s], np.uint64)
+    e = (b - O.negmul_schoolbook(q, a, sk).astype(np.int64)) % q
+    e = np.where(e > q // 2, e - q, e)
+    for k in (0, 1, N // 8 - 1, N // 8, N // 8 + 1, N // 2 + 5, N - 1):
+        pos = 8 * (k % (N // 8)) + k // (N // 8)
+        assert e[k] == O.cdt_sample(T, O.w64(seed, 4, ct * N + pos)), k

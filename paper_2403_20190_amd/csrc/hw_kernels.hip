@@ -184,21 +184,20 @@ __device__ __forceinline__ void gen_uniform(uint64_t seed, uint64_t x0, const Pr
   for (int e = 0; e < 8; ++e) x[e] = stage[t + TT * e];
 }
 
+// Errors of thread t's coefficients t + (N/8) e, e < 8: coefficient k takes
+// error draw 8 (k mod N/8) + floor(k / (N/8)), so the thread's eight draws
+// 8t .. 8t+7 are the four consecutive generator blocks base_blk + 4t .. +3
+// (two 64-bit draws each) and need no exchange.
 template <int LOGN>
-__device__ __forceinline__ void gen_gauss(uint64_t seed, uint64_t base_blk, const uint64_t* cdt,
-                                          uint32_t* __restrict__ stage, uint32_t t, int32_t (&ev)[8]) {
-  constexpr int N = 1 << LOGN, TT = N / 8;
-  __syncthreads();
+__device__ __forceinline__ void gen_gauss(uint64_t seed, uint64_t base_blk, const uint64_t* cdt, uint32_t t,
+                                          int32_t (&ev)[8]) {
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
-    const uint32_t b = t + TT * f;
     uint64_t d0, d1;
-    draw_pair(seed, DOM_ENC_E, base_blk + b, d0, d1);
-    *reinterpret_cast<int2*>(stage + 2 * b) = make_int2(cdt_sample(cdt, d0), cdt_sample(cdt, d1));
+    draw_pair(seed, DOM_ENC_E, base_blk + 4 * (uint64_t)t + f, d0, d1);
+    ev[2 * f] = cdt_sample(cdt, d0);
+    ev[2 * f + 1] = cdt_sample(cdt, d1);
   }
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < 8; ++e) ev[e] = (int32_t)stage[t + TT * e];
 }
 
 // RGSW rows directly in the evaluation domain.  Draw k of prime i is the
@@ -213,7 +212,6 @@ template <int LOGN, int NQ, int R>
 __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
-  __shared__ __attribute__((aligned(16))) uint32_t stage[1 << LOGN];
   __shared__ uint64_t tab[42];
   constexpr int N = 1 << LOGN, D = 5 * NQ, ROWS = 2 * D;
   static_assert(ROWS % R == 0, "rows per workgroup must divide the rows of an RGSW");
@@ -223,8 +221,9 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncA
   const uint64_t ct = A.ct0 + c;
   const uint32_t m = A.bits[c];
   int32_t ev[R][8];
+  __syncthreads();  // the CDT table in LDS
 #pragma unroll
-  for (int k = 0; k < R; ++k) gen_gauss<LOGN>(A.seed, (ct * ROWS + r0 + k) * (N / 2), tab, stage, t, ev[k]);
+  for (int k = 0; k < R; ++k) gen_gauss<LOGN>(A.seed, (ct * ROWS + r0 + k) * (N / 2), tab, t, ev[k]);
   uint32_t xc = 0;
 #pragma unroll 1
   for (int i = 0; i < NQ; ++i) {
@@ -273,7 +272,6 @@ template <int LOGN, int NQ>
 __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_pks(Tabs T, Cdt cdt, EncArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
-  __shared__ __attribute__((aligned(16))) uint32_t stage[1 << LOGN];
   __shared__ uint64_t tab[42];
   constexpr int N = 1 << LOGN, D = 5 * NQ;
   const uint32_t t = threadIdx.x, r = blockIdx.x, j = blockIdx.y;
@@ -281,7 +279,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_pks(Tabs T, Cdt cdt, EncAr
   const uint64_t rid = (uint64_t)j * D + r;
   const int32_t sj = A.sk[j];
   int32_t ev[8];
-  gen_gauss<LOGN>(A.seed, rid * (N / 2), tab, stage, t, ev);
+  __syncthreads();  // the CDT table in LDS
+  gen_gauss<LOGN>(A.seed, rid * (N / 2), tab, t, ev);
   const uint32_t gi = r / 5, gt = r % 5;
   uint32_t* row = A.out + rid * (size_t)(2 * NQ * N);
   uint32_t xc = 0;
@@ -325,7 +324,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rlwe(Tabs T, Cdt cdt, EncA
   if (t < 42) tab[t] = cdt.T[t];
   const uint64_t rid = A.ct0 + c;  // one row per ciphertext
   int32_t ev[8];
-  gen_gauss<LOGN>(A.seed, rid * (N / 2), tab, stage, t, ev);
+  __syncthreads();  // the CDT table in LDS
+  gen_gauss<LOGN>(A.seed, rid * (N / 2), tab, t, ev);
   uint32_t* out = A.out + c * (size_t)(2 * NQ * N);
   uint32_t xc = 0;
 #pragma unroll 1

@@ -184,6 +184,41 @@ def test_mnist_shape_inference_sampled():
     assert np.array_equal(host_u64(ds).astype(np.int64), cells.sum(axis=1) % 1024)
 
 
+def test_mnist_bench_launch_configuration():
+    """The benchmark's launch configuration: one 50-sample chunk of the
+    MNIST shape trained in one call (50 x 196 workgroups) and 50 test samples
+    inferred in one call (50 x 196 x 10).  RAM 97 against the oracle over all
+    50 samples; every RAM by decryption against Alg. 4; sampled inference
+    outputs against the oracle and every cell by decryption against Alg. 2."""
+    CL = client()
+    Xtr, ytr, Xte, _ = synth.mnist_like(1, per_class_train=5, per_class_test=5)
+    bits = CL.thermometer(CL.quantize_u8(Xtr, 3), 3)
+    pair = Pair(2048, 2, 1024, 2352, 10, 12, bits, ytr, seed=6)
+    assert pair.n == 50
+    H, _, _, _ = train_dev(pair, class_count=False)
+    Ho = pair.oracle_train([97])
+    assert np.array_equal(host_u32(H)[97], Ho[97])
+    W = P.train_integer(pair.X, pair.y, pair.l, pair.a, pair.pi)
+    assert np.array_equal(decrypt_model(pair, H), P.expected_model_cells(W, pair.s, pair.l, pair.a, pair.N))
+    tb = CL.thermometer(CL.quantize_u8(Xte, 3), 3)
+    nt = len(tb)
+    xt = pair.encrypt_dev(tb, seed_x=88)
+    scores = zeros_u32(nt, 10, 196, pair.orc.lwe_words)
+    pair.ctx.infer(pair.shape, H, xt, nt, scores, None)
+    got = host_u32(scores).reshape(nt, 10, 196, 2, 2049)
+    picks = [(0, 0), (17, 3), (49, 9)]
+    want = {}
+    O._parallel(lambda ic: want.__setitem__(ic, pair.orc.infer_one(
+        pair.s, pair.l, pair.a, pair.pi, Ho, lambda k: pair.xo(ic[0], k, tb, 88, "t"), 97, ic[1])), picks)
+    for i, c in picks:
+        assert np.array_equal(got[i, c, 97], want[(i, c)]), (i, c)
+    dec = zeros_u64(nt * 10 * 196)
+    pair.ctx.decrypt_lwe(pair.sk, scores, nt * 10 * 196, dec)
+    cells = host_u64(dec).reshape(nt, 10, 196).astype(np.int64)
+    for i in range(nt):
+        assert np.array_equal(cells[i], P.ram_scores(W, tb[i], pair.a, pair.pi)), i
+
+
 def test_ham_shape_sampled():
     CL = client()
     Xtr, ytr, Xte, _ = synth.ham_like(3, n_train=20, n_test=1)

@@ -118,6 +118,19 @@ struct Geo {
   static_assert(LOGN >= 10 && LOGN <= 12, "N must be 1024, 2048 or 4096");
 };
 
+// Whether ext_prod transforms its digit polynomials two at a time: where
+// the LDS of a second pair of exchange buffers still leaves room for the
+// workgroups per CU the kernels run at (three at N = 2048; at N = 4096 two
+// 512-thread workgroups would no longer fit), and with more than one prime
+// (with one, the compiler's schedule of the pair spills registers).
+template <int LOGN, int NQ>
+__host__ __device__ constexpr bool xp_pair() { return LOGN <= 11 && NQ > 1; }
+
+// exchange words (two buffers per polynomial in flight) of a kernel whose
+// ext_prod runs with (PR) or without pairs
+template <int LOGN, bool PR>
+__host__ __device__ constexpr int xp_words() { return (PR ? 4 : 2) * Geo<LOGN>::LDSW; }
+
 __host__ __device__ constexpr uint32_t lds_ix(uint32_t k) { return k + ((k >> 5) << 2); }
 
 // In layouts P = 0..2 the index of element e of thread t splits into two
@@ -147,10 +160,11 @@ __device__ __forceinline__ uint32_t pos(uint32_t t, uint32_t e) {
 // Exchange through LDS from layout PF to layout PT.  Two buffers alternate
 // (selected by the running counter xc) so that one barrier per exchange
 // suffices: a buffer is written again only after the next exchange's barrier.
-template <int LOGN, int PF, int PT>
-__device__ __forceinline__ void xchg(uint32_t (&x)[8], uint32_t* lds, uint32_t& xc, uint32_t t) {
-  uint32_t* buf = lds + (xc & 1u) * Geo<LOGN>::LDSW;
-  ++xc;
+// K polynomials pass through one exchange; polynomial k uses the buffer of
+// the running parity 2 k LDSW words further on, so the buffers of
+// consecutive exchanges stay disjoint whatever their K.
+template <int LOGN, int PF>
+__device__ __forceinline__ void xput(const uint32_t (&x)[8], uint32_t* buf, uint32_t t) {
   if constexpr (PF == 3) {
     uint4* p = reinterpret_cast<uint4*>(buf + lds_ix(t << 3));
     p[0] = make_uint4(x[0], x[1], x[2], x[3]);
@@ -160,7 +174,10 @@ __device__ __forceinline__ void xchg(uint32_t (&x)[8], uint32_t* lds, uint32_t& 
 #pragma unroll
     for (int e = 0; e < 8; ++e) b[lds_ix((uint32_t)e << eshift<LOGN, PF>())] = x[e];
   }
-  __syncthreads();
+}
+
+template <int LOGN, int PT>
+__device__ __forceinline__ void xget(uint32_t (&x)[8], const uint32_t* buf, uint32_t t) {
   if constexpr (PT == 3) {
     const uint4* p = reinterpret_cast<const uint4*>(buf + lds_ix(t << 3));
     const uint4 u = p[0], v = p[1];
@@ -171,6 +188,22 @@ __device__ __forceinline__ void xchg(uint32_t (&x)[8], uint32_t* lds, uint32_t& 
 #pragma unroll
     for (int e = 0; e < 8; ++e) x[e] = b[lds_ix((uint32_t)e << eshift<LOGN, PT>())];
   }
+}
+
+template <int LOGN, int PF, int PT, int K>
+__device__ __forceinline__ void xchg_k(uint32_t (&x)[K][8], uint32_t* lds, uint32_t& xc, uint32_t t) {
+  uint32_t* buf = lds + (xc & 1u) * Geo<LOGN>::LDSW;
+  ++xc;
+#pragma unroll
+  for (int k = 0; k < K; ++k) xput<LOGN, PF>(x[k], buf + 2 * k * Geo<LOGN>::LDSW, t);
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) xget<LOGN, PT>(x[k], buf + 2 * k * Geo<LOGN>::LDSW, t);
+}
+
+template <int LOGN, int PF, int PT>
+__device__ __forceinline__ void xchg(uint32_t (&x)[8], uint32_t* lds, uint32_t& xc, uint32_t t) {
+  xchg_k<LOGN, PF, PT, 1>(*reinterpret_cast<uint32_t(*)[1][8]>(&x), lds, xc, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -220,61 +253,81 @@ __device__ __forceinline__ void tw_phase(uint2 (&w)[7], const uint2* __restrict_
   w[6] = make_uint2(u1.z, u1.w);
 }
 
-// Input values below 2q; output values are left in [0, 4q).
-template <int LOGN>
-__device__ __forceinline__ void ntt_fwd(uint32_t (&x)[8], const uint2* __restrict__ tab, const uint2* __restrict__ twl,
-                                        uint32_t q, uint32_t two_q, uint32_t* lds, uint32_t& xc, uint32_t t) {
+// K polynomials at once (sharing twiddle loads and exchanges).  Input
+// values below 2q; output values are left in [0, 4q).
+template <int LOGN, int K>
+__device__ __forceinline__ void ntt_fwd_k(uint32_t (&x)[K][8], const uint2* __restrict__ tab,
+                                          const uint2* __restrict__ twl, uint32_t q, uint32_t two_q, uint32_t* lds,
+                                          uint32_t& xc, uint32_t t) {
   constexpr int R = Geo<LOGN>::R;
   {  // phase 0: stages 0..2, twiddles uniform over the workgroup
     const uint2 w1 = tab[1], w2 = tab[2], w3 = tab[3], w4 = tab[4], w5 = tab[5], w6 = tab[6], w7 = tab[7];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bf_fwd0(x[e], x[e + 4], w1.x, w1.y, q, two_q);
-    bf_fwd(x[0], x[2], w2.x, w2.y, q, two_q);
-    bf_fwd(x[1], x[3], w2.x, w2.y, q, two_q);
-    bf_fwd(x[4], x[6], w3.x, w3.y, q, two_q);
-    bf_fwd(x[5], x[7], w3.x, w3.y, q, two_q);
-    bf_fwd(x[0], x[1], w4.x, w4.y, q, two_q);
-    bf_fwd(x[2], x[3], w5.x, w5.y, q, two_q);
-    bf_fwd(x[4], x[5], w6.x, w6.y, q, two_q);
-    bf_fwd(x[6], x[7], w7.x, w7.y, q, two_q);
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bf_fwd0(x[k][e], x[k][e + 4], w1.x, w1.y, q, two_q);
+      bf_fwd(x[k][0], x[k][2], w2.x, w2.y, q, two_q);
+      bf_fwd(x[k][1], x[k][3], w2.x, w2.y, q, two_q);
+      bf_fwd(x[k][4], x[k][6], w3.x, w3.y, q, two_q);
+      bf_fwd(x[k][5], x[k][7], w3.x, w3.y, q, two_q);
+      bf_fwd(x[k][0], x[k][1], w4.x, w4.y, q, two_q);
+      bf_fwd(x[k][2], x[k][3], w5.x, w5.y, q, two_q);
+      bf_fwd(x[k][4], x[k][5], w6.x, w6.y, q, two_q);
+      bf_fwd(x[k][6], x[k][7], w7.x, w7.y, q, two_q);
+    }
   }
-  xchg<LOGN, 0, 1>(x, lds, xc, t);
+  xchg_k<LOGN, 0, 1, K>(x, lds, xc, t);
   {
     uint2 w[7];
     tw_phase(w, twl, 3, t >> (LOGN - 6));
-    fwd8(x, w, q, two_q);
+#pragma unroll
+    for (int k = 0; k < K; ++k) fwd8(x[k], w, q, two_q);
   }
-  xchg<LOGN, 1, 2>(x, lds, xc, t);
+  xchg_k<LOGN, 1, 2, K>(x, lds, xc, t);
   {
     uint2 w[7];
     tw_phase(w, twl, 6, t >> (LOGN - 9));
-    fwd8(x, w, q, two_q);
+#pragma unroll
+    for (int k = 0; k < K; ++k) fwd8(x[k], w, q, two_q);
   }
-  xchg<LOGN, 2, 3>(x, lds, xc, t);
+  xchg_k<LOGN, 2, 3, K>(x, lds, xc, t);
   if constexpr (R == 3) {
     uint2 w[7];
     tw_phase(w, twl, 9, t);
-    fwd8(x, w, q, two_q);
+#pragma unroll
+    for (int k = 0; k < K; ++k) fwd8(x[k], w, q, two_q);
   } else if constexpr (R == 2) {
     const uint4 v = *reinterpret_cast<const uint4*>(twl + 512 + 2 * t);
-    bf_fwd(x[0], x[2], v.x, v.y, q, two_q);
-    bf_fwd(x[1], x[3], v.x, v.y, q, two_q);
-    bf_fwd(x[4], x[6], v.z, v.w, q, two_q);
-    bf_fwd(x[5], x[7], v.z, v.w, q, two_q);
     const uint4 u0 = *reinterpret_cast<const uint4*>(twl + 1024 + 4 * t);
     const uint4 u1 = *reinterpret_cast<const uint4*>(twl + 1024 + 4 * t + 2);
-    bf_fwd(x[0], x[1], u0.x, u0.y, q, two_q);
-    bf_fwd(x[2], x[3], u0.z, u0.w, q, two_q);
-    bf_fwd(x[4], x[5], u1.x, u1.y, q, two_q);
-    bf_fwd(x[6], x[7], u1.z, u1.w, q, two_q);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      bf_fwd(x[k][0], x[k][2], v.x, v.y, q, two_q);
+      bf_fwd(x[k][1], x[k][3], v.x, v.y, q, two_q);
+      bf_fwd(x[k][4], x[k][6], v.z, v.w, q, two_q);
+      bf_fwd(x[k][5], x[k][7], v.z, v.w, q, two_q);
+      bf_fwd(x[k][0], x[k][1], u0.x, u0.y, q, two_q);
+      bf_fwd(x[k][2], x[k][3], u0.z, u0.w, q, two_q);
+      bf_fwd(x[k][4], x[k][5], u1.x, u1.y, q, two_q);
+      bf_fwd(x[k][6], x[k][7], u1.z, u1.w, q, two_q);
+    }
   } else {
     const uint4 u0 = *reinterpret_cast<const uint4*>(twl + 512 + 4 * t);
     const uint4 u1 = *reinterpret_cast<const uint4*>(twl + 512 + 4 * t + 2);
-    bf_fwd(x[0], x[1], u0.x, u0.y, q, two_q);
-    bf_fwd(x[2], x[3], u0.z, u0.w, q, two_q);
-    bf_fwd(x[4], x[5], u1.x, u1.y, q, two_q);
-    bf_fwd(x[6], x[7], u1.z, u1.w, q, two_q);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      bf_fwd(x[k][0], x[k][1], u0.x, u0.y, q, two_q);
+      bf_fwd(x[k][2], x[k][3], u0.z, u0.w, q, two_q);
+      bf_fwd(x[k][4], x[k][5], u1.x, u1.y, q, two_q);
+      bf_fwd(x[k][6], x[k][7], u1.z, u1.w, q, two_q);
+    }
   }
+}
+
+template <int LOGN>
+__device__ __forceinline__ void ntt_fwd(uint32_t (&x)[8], const uint2* __restrict__ tab, const uint2* __restrict__ twl,
+                                        uint32_t q, uint32_t two_q, uint32_t* lds, uint32_t& xc, uint32_t t) {
+  ntt_fwd_k<LOGN, 1>(*reinterpret_cast<uint32_t(*)[1][8]>(&x), tab, twl, q, two_q, lds, xc, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -421,7 +474,7 @@ __device__ __forceinline__ void xp_finish(uint32_t (&ha)[8], uint32_t (&hb)[8], 
   }
 }
 
-template <int LOGN, int NQ>
+template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>()>
 __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const uint32_t* __restrict__ C,
                                       const Tabs& T, uint32_t* lds, uint2* twl, uint32_t& xc, uint32_t t,
                                       XpOut out) {
@@ -449,9 +502,50 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
         const uint32_t r = (src + TT * e)[t];
         w[e] = (r > (qi - 1) / 2 ? (int32_t)(r - qi) : (int32_t)r) + DIGIT_OFFSET;
       }
+      const uint32_t* crow = C + (size_t)(side * D + i * 5) * ROW + (size_t)ip * N;
+      if constexpr (PR) {
+        // digits (0, 1) and (2, 3) through one two-polynomial transform each
 #pragma unroll 1
-      for (int j = 0; j < 5; ++j) {
-        const uint4* cra = reinterpret_cast<const uint4*>(C + (size_t)(side * D + i * 5 + j) * ROW + (size_t)ip * N);
+        for (int j = 0; j < 4; j += 2) {
+          const uint4* c0 = reinterpret_cast<const uint4*>(crow + (size_t)j * ROW);
+          const uint4* c1 = reinterpret_cast<const uint4*>(crow + (size_t)(j + 1) * ROW);
+          const uint4 ca00 = c0[2 * t], ca01 = c0[2 * t + 1];
+          const uint4 cb00 = (c0 + NQ * N / 4)[2 * t], cb01 = (c0 + NQ * N / 4)[2 * t + 1];
+          const uint4 ca10 = c1[2 * t], ca11 = c1[2 * t + 1];
+          const uint4 cb10 = (c1 + NQ * N / 4)[2 * t], cb11 = (c1 + NQ * N / 4)[2 * t + 1];
+          uint32_t x[2][8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            x[0][e] = digit_lift(w[e], j, P.q);
+            x[1][e] = digit_lift(w[e], j + 1, P.q);
+          }
+          ntt_fwd_k<LOGN, 2>(x, T.fwd[ip], twl, P.q, P.two_q, lds, xc, t);
+          const uint32_t ca[2][8] = {{ca00.x, ca00.y, ca00.z, ca00.w, ca01.x, ca01.y, ca01.z, ca01.w},
+                                     {ca10.x, ca10.y, ca10.z, ca10.w, ca11.x, ca11.y, ca11.z, ca11.w}};
+          const uint32_t cb[2][8] = {{cb00.x, cb00.y, cb00.z, cb00.w, cb01.x, cb01.y, cb01.z, cb01.w},
+                                     {cb10.x, cb10.y, cb10.z, cb10.w, cb11.x, cb11.y, cb11.z, cb11.w}};
+#pragma unroll
+          for (int k = 0; k < 2; ++k)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              const uint32_t xr = red4q(x[k][e], P.q, P.two_q);
+              acc_a[e] += (uint64_t)xr * ca[k][e];
+              acc_b[e] += (uint64_t)xr * cb[k][e];
+            }
+          cnt += 2;
+          if (cnt >= 14) {  // at most 15 products of two values below q since the last reduction
+            cnt = 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+              acc_a[e] = red64(acc_a[e], P);
+              acc_b[e] = red64(acc_b[e], P);
+            }
+          }
+        }
+      }
+#pragma unroll 1
+      for (int j = PR ? 4 : 0; j < 5; ++j) {
+        const uint4* cra = reinterpret_cast<const uint4*>(crow + (size_t)j * ROW);
         const uint4* crb = cra + (size_t)NQ * N / 4;
         const uint4 ca0 = cra[2 * t], ca1 = cra[2 * t + 1];
         const uint4 cb0 = crb[2 * t], cb1 = crb[2 * t + 1];
@@ -467,7 +561,7 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
           acc_a[e] += (uint64_t)xr * ca[e];
           acc_b[e] += (uint64_t)xr * cb[e];
         }
-        if (++cnt == 15) {
+        if (++cnt >= (PR ? 14 : 15)) {
           cnt = 0;
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
@@ -557,12 +651,6 @@ __device__ __forceinline__ void ext_prod_delta(const uint32_t* __restrict__ C, c
     xp_finish<LOGN, NQ>(h[0], h[1], ip, T, lds, xc, t, out);
   }
 }
-
-// LDS needed by a kernel that runs ext_prod: two exchange buffers + one table
-template <int LOGN>
-struct XpLds {
-  static constexpr int WORDS = 2 * Geo<LOGN>::LDSW + 2 * (1 << LOGN);
-};
 
 // ---------------------------------------------------------------------------
 // RLWE slots in global memory, natural layout

@@ -511,7 +511,7 @@ template <int LOGN, int NQ>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_xp(Tabs T, const uint32_t* __restrict__ rgsw,
                                                       const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                       uint64_t rgsw_words) {
-  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, xp_pair<LOGN, NQ>()>()];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   constexpr int N = 1 << LOGN;
   const uint32_t t = threadIdx.x;
@@ -545,12 +545,12 @@ __device__ __forceinline__ void rot_diff(const Tabs& T, const uint32_t* __restri
 }
 
 // CMUX step of a blind rotation: acc <- acc + C [.] (X^ex acc - acc)
-template <int LOGN, int NQ>
+template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>()>
 __device__ __forceinline__ void cmux_rot(const Tabs& T, uint32_t* __restrict__ acc, int32_t ex,
                                          const uint32_t* __restrict__ C, uint32_t* __restrict__ xin, uint32_t* lds,
                                          uint2* twl, uint32_t& xc, uint32_t t) {
   rot_diff<LOGN, NQ>(T, acc, ex, xin, t);
-  ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t, XpOut{acc, acc, nullptr, XP_ADD});
+  ext_prod<LOGN, NQ, PR>(xin, C, T, lds, twl, xc, t, XpOut{acc, acc, nullptr, XP_ADD});
   __syncthreads();  // the next rotation reads coefficients other threads wrote
 }
 
@@ -607,7 +607,7 @@ __device__ __forceinline__ void acc_rlwe(const Tabs& T, uint32_t* __restrict__ d
 // bits and l classes.  Without `dest` leaf d is left in slot d.  With
 // `dest`, live leaf d goes to dest[leaf_row(d)] instead: stored when
 // `store`, else added (the last tree level writes there directly).
-template <int LOGN, int NQ, class BitFn>
+template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>(), class BitFn>
 __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ slot0, uint32_t* __restrict__ xin,
                                           uint32_t nb, uint32_t L, uint32_t l, BitFn&& bit, uint32_t* lds,
                                           uint2* twl, uint32_t t, uint32_t* __restrict__ dest = nullptr,
@@ -629,7 +629,7 @@ __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ 
     __syncthreads();
   }
 #pragma unroll 1
-  for (uint32_t st = 1; st < nr; ++st) cmux_rot<LOGN, NQ>(T, slot0, 1 << st, bit(z + st), xin, lds, twl, xc, t);
+  for (uint32_t st = 1; st < nr; ++st) cmux_rot<LOGN, NQ, PR>(T, slot0, 1 << st, bit(z + st), xin, lds, twl, xc, t);
 #pragma unroll 1
   for (uint32_t lev = 0; lev < z; ++lev) {
     const uint32_t* C = bit(lev);
@@ -642,11 +642,11 @@ __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ 
       if (node_live(j + n, z, L, l)) {
         copy_rlwe<LOGN, NQ>(xin, sj, t);
         if (last)
-          ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t,
-                             XpOut{dest + leaf_row(j, z, L, l) * RW, xin, dest + leaf_row(j + n, z, L, l) * RW,
+          ext_prod<LOGN, NQ, PR>(xin, C, T, lds, twl, xc, t,
+                                 XpOut{dest + leaf_row(j, z, L, l) * RW, xin, dest + leaf_row(j + n, z, L, l) * RW,
                                    store ? XP_DEMUX : XP_DEMUX_ACC});
         else
-          ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t, XpOut{sj, xin, slot0 + (j + n) * RW, XP_DEMUX});
+          ext_prod<LOGN, NQ, PR>(xin, C, T, lds, twl, xc, t, XpOut{sj, xin, slot0 + (j + n) * RW, XP_DEMUX});
       } else if (last) {  // unsplit live leaf
         acc_rlwe<LOGN, NQ>(T, dest + leaf_row(j, z, L, l) * RW, sj, store, t);
       }
@@ -695,7 +695,7 @@ __device__ __forceinline__ const uint32_t* index_bit(uint32_t layout, uint32_t u
 
 template <int LOGN, int NQ, int OCC>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_train(Tabs T, TrainArgs A) {
-  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, xp_pair<LOGN, NQ>()>()];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   constexpr size_t RW = (size_t)2 * NQ * (1 << LOGN);
   const uint32_t t = threadIdx.x;
@@ -736,7 +736,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
 template <int LOGN, int NQ, int OCC>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_train_batch(
     Tabs T, BatchArgs A) {
-  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, false>()];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   __shared__ uint32_t next;
   constexpr size_t RW = (size_t)2 * NQ * (1 << LOGN);
@@ -761,7 +761,9 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
 #pragma unroll 1
     for (uint32_t smp = s0; smp < s1; ++smp) {
       const uint64_t gi = smp;
-      ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)J.kt * RW, nb, tree_L(J.layout, J.L), tree_l(J.layout, J.l),
+      // single transforms: with pairs the queue state next to them spills registers
+      ivp_block<LOGN, NQ, false>(T, slot0, slot0 + (size_t)J.kt * RW, nb, tree_L(J.layout, J.L),
+                                 tree_l(J.layout, J.l),
                           [&](uint32_t u) -> const uint32_t* {
                             return index_bit(J.layout, u, nb, J.L, J.x, J.y, J.perm, gi, J.s, I.ram, J.a,
                                              A.rgsw_words);
@@ -914,7 +916,7 @@ __global__ __launch_bounds__(256) void k_row_pack(Tabs T, RowPackArgs A) {
 
 template <int LOGN, int NQ, int OCC>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_infer(Tabs T, InferArgs A) {
-  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, xp_pair<LOGN, NQ>()>()];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   constexpr int N = 1 << LOGN, TT = N / 8;
   constexpr size_t RW = (size_t)2 * NQ * N;

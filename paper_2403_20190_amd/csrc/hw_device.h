@@ -334,58 +334,82 @@ __device__ __forceinline__ void ntt_fwd(uint32_t (&x)[8], const uint2* __restric
 // inverse NTT (layout P=3 -> natural layout), input in [0, 2q), output [0, q)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void inv_bf(uint32_t& X, uint32_t& Y, const uint2* __restrict__ tab, uint32_t idx,
-                                       uint32_t q, uint32_t two_q) {
-  const uint2 w = tab[idx];
-  bf_inv(X, Y, w.x, w.y, q, two_q);
+// three inverse stages (s0+2, s0+1, s0) of a phase whose index bits vary with
+// e, on K polynomials; base(s) gives 2^s + (k >> (log2 N - s)) with the
+// e-dependent part removed
+template <int K>
+__device__ __forceinline__ void inv8_k(uint32_t (&x)[K][8], const uint2* __restrict__ tab, uint32_t i2,
+                                       uint32_t i1, uint32_t i0, uint32_t q, uint32_t two_q) {
+  uint2 w2[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) w2[e] = tab[i2 + e];
+  const uint2 w1a = tab[i1], w1b = tab[i1 + 1], w0 = tab[i0];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bf_inv(x[k][2 * e], x[k][2 * e + 1], w2[e].x, w2[e].y, q, two_q);
+    bf_inv(x[k][0], x[k][2], w1a.x, w1a.y, q, two_q);
+    bf_inv(x[k][1], x[k][3], w1a.x, w1a.y, q, two_q);
+    bf_inv(x[k][4], x[k][6], w1b.x, w1b.y, q, two_q);
+    bf_inv(x[k][5], x[k][7], w1b.x, w1b.y, q, two_q);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bf_inv(x[k][e], x[k][e + 4], w0.x, w0.y, q, two_q);
+  }
 }
 
-// three inverse stages (s0+2, s0+1, s0) of a phase whose index bits vary with e;
-// base(s) gives 2^s + (k >> (log2 N - s)) with the e-dependent part removed
-__device__ __forceinline__ void inv8(uint32_t (&x)[8], const uint2* __restrict__ tab, uint32_t i2,
-                                     uint32_t i1, uint32_t i0, uint32_t q, uint32_t two_q) {
+// K polynomials at once (sharing twiddle loads and exchanges)
+template <int LOGN, int K>
+__device__ __forceinline__ void ntt_inv_k(uint32_t (&x)[K][8], const uint2* __restrict__ tab, const PrimeTab& P,
+                                          uint32_t* lds, uint32_t& xc, uint32_t t) {
+  constexpr int R = Geo<LOGN>::R;
+  const uint32_t q = P.q, two_q = P.two_q;
+  if constexpr (R == 3) {
+    inv8_k<K>(x, tab, 2048 + (t << 2), 1024 + (t << 1), 512 + t, q, two_q);
+  } else if constexpr (R == 2) {
+    uint2 w2[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) inv_bf(x[2 * e], x[2 * e + 1], tab, i2 + e, q, two_q);
-  inv_bf(x[0], x[2], tab, i1, q, two_q);
-  inv_bf(x[1], x[3], tab, i1, q, two_q);
-  inv_bf(x[4], x[6], tab, i1 + 1, q, two_q);
-  inv_bf(x[5], x[7], tab, i1 + 1, q, two_q);
+    for (int e = 0; e < 4; ++e) w2[e] = tab[1024 + (t << 2) + e];
+    const uint2 w1a = tab[512 + (t << 1)], w1b = tab[512 + (t << 1) + 1];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) inv_bf(x[e], x[e + 4], tab, i0, q, two_q);
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bf_inv(x[k][2 * e], x[k][2 * e + 1], w2[e].x, w2[e].y, q, two_q);
+      bf_inv(x[k][0], x[k][2], w1a.x, w1a.y, q, two_q);
+      bf_inv(x[k][1], x[k][3], w1a.x, w1a.y, q, two_q);
+      bf_inv(x[k][4], x[k][6], w1b.x, w1b.y, q, two_q);
+      bf_inv(x[k][5], x[k][7], w1b.x, w1b.y, q, two_q);
+    }
+  } else {
+    uint2 w2[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) w2[e] = tab[512 + (t << 2) + e];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bf_inv(x[k][2 * e], x[k][2 * e + 1], w2[e].x, w2[e].y, q, two_q);
+  }
+  xchg_k<LOGN, 3, 2, K>(x, lds, xc, t);
+  {
+    const uint32_t tc = t >> (LOGN - 9);
+    inv8_k<K>(x, tab, 256 + (tc << 2), 128 + (tc << 1), 64 + tc, q, two_q);
+  }
+  xchg_k<LOGN, 2, 1, K>(x, lds, xc, t);
+  {
+    const uint32_t tb = t >> (LOGN - 6);
+    inv8_k<K>(x, tab, 32 + (tb << 2), 16 + (tb << 1), 8 + tb, q, two_q);
+  }
+  xchg_k<LOGN, 1, 0, K>(x, lds, xc, t);
+  inv8_k<K>(x, tab, 4, 2, 1, q, two_q);
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[k][e] = csub(mulsh(x[k][e], P.ninv, P.ninv_sh, q), q);
 }
 
 template <int LOGN>
 __device__ __forceinline__ void ntt_inv(uint32_t (&x)[8], const uint2* __restrict__ tab, const PrimeTab& P,
                                         uint32_t* lds, uint32_t& xc, uint32_t t) {
-  constexpr int R = Geo<LOGN>::R;
-  const uint32_t q = P.q, two_q = P.two_q;
-  if constexpr (R == 3) {
-    inv8(x, tab, 2048 + (t << 2), 1024 + (t << 1), 512 + t, q, two_q);
-  } else if constexpr (R == 2) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) inv_bf(x[2 * e], x[2 * e + 1], tab, 1024 + (t << 2) + e, q, two_q);
-    inv_bf(x[0], x[2], tab, 512 + (t << 1), q, two_q);
-    inv_bf(x[1], x[3], tab, 512 + (t << 1), q, two_q);
-    inv_bf(x[4], x[6], tab, 512 + (t << 1) + 1, q, two_q);
-    inv_bf(x[5], x[7], tab, 512 + (t << 1) + 1, q, two_q);
-  } else {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) inv_bf(x[2 * e], x[2 * e + 1], tab, 512 + (t << 2) + e, q, two_q);
-  }
-  xchg<LOGN, 3, 2>(x, lds, xc, t);
-  {
-    const uint32_t tc = t >> (LOGN - 9);
-    inv8(x, tab, 256 + (tc << 2), 128 + (tc << 1), 64 + tc, q, two_q);
-  }
-  xchg<LOGN, 2, 1>(x, lds, xc, t);
-  {
-    const uint32_t tb = t >> (LOGN - 6);
-    inv8(x, tab, 32 + (tb << 2), 16 + (tb << 1), 8 + tb, q, two_q);
-  }
-  xchg<LOGN, 1, 0>(x, lds, xc, t);
-  inv8(x, tab, 4, 2, 1, q, two_q);
-#pragma unroll
-  for (int e = 0; e < 8; ++e) x[e] = csub(mulsh(x[e], P.ninv, P.ninv_sh, q), q);
+  ntt_inv_k<LOGN, 1>(*reinterpret_cast<uint32_t(*)[1][8]>(&x), tab, P, lds, xc, t);
 }
 
 // reduce forward-NTT output [0, 4q) -> [0, q)
@@ -443,13 +467,28 @@ __device__ __forceinline__ uint32_t digit_lift(int32_t w, int j, uint32_t q) {
 
 // inverse transforms of the a and b sums of output prime ip (inputs in [0, q))
 // and the write of the external product by out.mode
-template <int LOGN, int NQ>
+template <int LOGN, int NQ, bool PR>
 __device__ __forceinline__ void xp_finish(uint32_t (&ha)[8], uint32_t (&hb)[8], int ip, const Tabs& T, uint32_t* lds,
                                           uint32_t& xc, uint32_t t, const XpOut& out) {
   constexpr int N = 1 << LOGN, TT = N / 8;
   const PrimeTab P = T.pt[ip];
-  ntt_inv<LOGN>(ha, T.inv[ip], P, lds, xc, t);
-  ntt_inv<LOGN>(hb, T.inv[ip], P, lds, xc, t);
+  if constexpr (PR) {  // both sums through one two-polynomial transform
+    uint32_t h[2][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      h[0][e] = ha[e];
+      h[1][e] = hb[e];
+    }
+    ntt_inv_k<LOGN, 2>(h, T.inv[ip], P, lds, xc, t);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      ha[e] = h[0][e];
+      hb[e] = h[1][e];
+    }
+  } else {
+    ntt_inv<LOGN>(ha, T.inv[ip], P, lds, xc, t);
+    ntt_inv<LOGN>(hb, T.inv[ip], P, lds, xc, t);
+  }
   const size_t oa = (size_t)ip * N, ob = (size_t)(NQ + ip) * N;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
@@ -577,7 +616,7 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
       ha[e] = red64(acc_a[e], P);
       hb[e] = red64(acc_b[e], P);
     }
-    xp_finish<LOGN, NQ>(ha, hb, ip, T, lds, xc, t, out);
+    xp_finish<LOGN, NQ, PR>(ha, hb, ip, T, lds, xc, t, out);
   }
 }
 
@@ -592,7 +631,7 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
 // inverse transform, as in ext_prod, so the result is the same residues
 // ext_prod computes for that input, without its 10 nq^2 forward transforms
 // and with half its RGSW reads.
-template <int LOGN, int NQ>
+template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>()>
 __device__ __forceinline__ void ext_prod_delta(const uint32_t* __restrict__ C, const Tabs& T, uint32_t* lds,
                                                uint32_t& xc, uint32_t t, XpOut out) {
   constexpr int N = 1 << LOGN;
@@ -648,7 +687,7 @@ __device__ __forceinline__ void ext_prod_delta(const uint32_t* __restrict__ C, c
         h[side][2 * hh + 1] = addq(red64((uint64_t)(s0[2 * hh + 1] + sh), P), r1, P.q);
       }
     }
-    xp_finish<LOGN, NQ>(h[0], h[1], ip, T, lds, xc, t, out);
+    xp_finish<LOGN, NQ, PR>(h[0], h[1], ip, T, lds, xc, t, out);
   }
 }
 

@@ -625,7 +625,7 @@ __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ 
   __syncthreads();
   uint32_t xc = 0;
   if (nr > 0) {  // the first CMUX acts on (0, Delta): X acc - acc = (0, Delta (X - 1))
-    ext_prod_delta<LOGN, NQ>(bit(z), T, lds, xc, t, XpOut{slot0, slot0, nullptr, XP_ADD});
+    ext_prod_delta<LOGN, NQ, PR>(bit(z), T, lds, xc, t, XpOut{slot0, slot0, nullptr, XP_ADD});
     __syncthreads();
   }
 #pragma unroll 1

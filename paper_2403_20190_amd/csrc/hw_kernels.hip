@@ -447,11 +447,14 @@ __global__ __launch_bounds__(256) void k_dec_lwe(Tabs T, CrtTab K, uint32_t N, c
 // ---------------------------------------------------------------------------
 
 // `per` consecutive polynomials of one prime per workgroup (the prime's
-// forward table is copied to LDS once for all of them)
+// forward table is copied to LDS once for all of them), two at a time at
+// N <= 2048 (one exchange and one set of twiddle loads serve both)
 template <int LOGN, int NQ>
 __global__ __launch_bounds__(Geo<LOGN>::T) void k_ntt(Tabs T, uint32_t* __restrict__ polys, uint64_t count,
                                                      uint32_t per, int inverse) {
-  __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
+  constexpr bool PR = LOGN <= 11;
+  constexpr int KP = PR ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, PR>()];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   constexpr int N = 1 << LOGN, TT = N / 8;
   const uint32_t t = threadIdx.x, i = blockIdx.x;
@@ -460,9 +463,43 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_ntt(Tabs T, uint32_t* __restri
   uint32_t xc = 0;
   if (!inverse) load_tw_lds<LOGN>(twl, T.fwd[i], t);  // read after the first exchange's barrier
 #pragma unroll 1
-  for (uint32_t k = 0; k < per; ++k) {
+  for (uint32_t k = 0; k < per; k += KP) {
     const uint64_t c = grp * per + k;
     if (c >= count) break;
+    if (PR && k + 1 < per && c + 1 < count) {
+      uint32_t* p[2] = {polys + (c * NQ + i) * (size_t)N, polys + ((c + 1) * NQ + i) * (size_t)N};
+      uint32_t x[2][8];
+      if (!inverse) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) x[m][e] = p[m][t + TT * e];
+        ntt_fwd_k<LOGN, 2>(x, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          uint4* o = reinterpret_cast<uint4*>(p[m] + (t << 3));
+          o[0] = make_uint4(red4q(x[m][0], P.q, P.two_q), red4q(x[m][1], P.q, P.two_q),
+                            red4q(x[m][2], P.q, P.two_q), red4q(x[m][3], P.q, P.two_q));
+          o[1] = make_uint4(red4q(x[m][4], P.q, P.two_q), red4q(x[m][5], P.q, P.two_q),
+                            red4q(x[m][6], P.q, P.two_q), red4q(x[m][7], P.q, P.two_q));
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          const uint4* s = reinterpret_cast<const uint4*>(p[m] + (t << 3));
+          const uint4 u = s[0], v = s[1];
+          x[m][0] = u.x; x[m][1] = u.y; x[m][2] = u.z; x[m][3] = u.w;
+          x[m][4] = v.x; x[m][5] = v.y; x[m][6] = v.z; x[m][7] = v.w;
+        }
+        __syncthreads();  // every thread has read its inputs before anyone overwrites them
+        ntt_inv_k<LOGN, 2>(x, T.inv[i], P, lds, xc, t);
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) p[m][t + TT * e] = x[m][e];
+      }
+      continue;
+    }
     uint32_t* p = polys + (c * NQ + i) * (size_t)N;
     uint32_t x[8];
     if (!inverse) {

@@ -183,7 +183,9 @@ extern "C" hw_status hw_ctx_create(const hw_params* params, int device, hw_ctx**
     return fail(HW_EINVAL, "plain_mod too large for Q");
   }
 
-  // tables: for each prime fwd[N], inv[N] and evx[N] of (w, Shoup)
+  // tables: for each prime fwd[N], inv[N] and evx[N] of (w, Shoup); the
+  // forward table holds -w mod 2^32 in place of w (its butterflies form the
+  // negated product directly)
   std::vector<uint2> host((size_t)3 * P.nq * N);
   for (uint32_t i = 0; i < P.nq; ++i) {
     const uint32_t q = P.primes[i];
@@ -199,7 +201,7 @@ extern "C" hw_status hw_ctx_create(const hw_params* params, int device, hw_ctx**
       const uint32_t wi = (uint32_t)powm(psi_inv, brv(k, logN), q);
       // the forward transform's output k is the evaluation at psi^(2 brv(k) + 1): for X, that point
       const uint32_t x = (uint32_t)powm(psi, 2ull * brv(k, logN) + 1, q);
-      fw[k] = make_uint2(w, shoup(w, q));
+      fw[k] = make_uint2(0u - w, shoup(w, q));
       iv[k] = make_uint2(wi, shoup(wi, q));
       ev[k] = make_uint2(x, shoup(x, q));
     }

@@ -37,7 +37,7 @@ constexpr int MAXQ = 3;
 
 struct Tabs {
   PrimeTab pt[MAXQ];
-  const uint2* fwd[MAXQ];   // [N]: (psi^{brv(k)}, Shoup companion), k >= 1
+  const uint2* fwd[MAXQ];   // [N]: (-psi^{brv(k)} mod 2^32, Shoup companion of psi^{brv(k)}), k >= 1
   const uint2* inv[MAXQ];   // [N]: (psi^{-brv(k)}, Shoup companion)
   const uint2* evx[MAXQ];   // [N]: the forward transform of X, psi^{2 brv(k) + 1}, with its Shoup companion
 };
@@ -81,21 +81,32 @@ __device__ __forceinline__ uint32_t mulq(uint32_t a, uint32_t b, const PrimeTab&
   return red64((uint64_t)a * b, P);
 }
 
-// Harvey butterflies: forward (Cooley-Tukey) on [0, 4q), inverse
-// (Gentleman-Sande) on [0, 2q).  bf_fwd0 is the forward butterfly for an
-// upper input already below 2q (the first stage: transform inputs are < 2q).
-__device__ __forceinline__ void bf_fwd0(uint32_t& X, uint32_t& Y, uint32_t w, uint32_t wsh, uint32_t q,
-                                        uint32_t two_q) {
-  const uint32_t x = X;
-  const uint32_t t = mulsh(Y, w, wsh, q);
-  X = x + t;
-  Y = x - t + two_q;
+// -(y w mod q) mod 2^32 with y w mod q in [0, 2q) as in mulsh, from nw =
+// -w mod 2^32 and w's Shoup companion: floor(y wsh / 2^32) q - y w, one
+// multiply-add with q (only the low 32 bits are kept)
+__device__ __forceinline__ uint32_t mulsh_neg(uint32_t y, uint32_t nw, uint32_t wsh, uint32_t q) {
+  const uint32_t qh = __umulhi(y, wsh);
+  return (uint32_t)mad64(qh, q, (uint64_t)(y * nw));
 }
 
-__device__ __forceinline__ void bf_fwd(uint32_t& X, uint32_t& Y, uint32_t w, uint32_t wsh, uint32_t q,
+// Harvey butterflies: forward (Cooley-Tukey) on [0, 4q), inverse
+// (Gentleman-Sande) on [0, 2q).  The forward twiddles come as (-w mod 2^32,
+// Shoup companion of w): with nt = -t for the product t in [0, 2q),
+// X + t = X - nt and X - t + 2q = X + 2q + nt, one subtraction and one
+// three-operand add.  bf_fwd0 is the forward butterfly for an upper input
+// already below 2q (the first stage: transform inputs are < 2q).
+__device__ __forceinline__ void bf_fwd0(uint32_t& X, uint32_t& Y, uint32_t nw, uint32_t wsh, uint32_t q,
+                                        uint32_t two_q) {
+  const uint32_t x = X;
+  const uint32_t nt = mulsh_neg(Y, nw, wsh, q);
+  X = x - nt;
+  Y = x + two_q + nt;
+}
+
+__device__ __forceinline__ void bf_fwd(uint32_t& X, uint32_t& Y, uint32_t nw, uint32_t wsh, uint32_t q,
                                        uint32_t two_q) {
   X = csub(X, two_q);
-  bf_fwd0(X, Y, w, wsh, q, two_q);
+  bf_fwd0(X, Y, nw, wsh, q, two_q);
 }
 
 __device__ __forceinline__ void bf_inv(uint32_t& X, uint32_t& Y, uint32_t w, uint32_t wsh, uint32_t q,
@@ -226,7 +237,7 @@ __device__ __forceinline__ void load_tw_lds(uint2* __restrict__ twl, const uint2
   for (int e = 0; e < 4; ++e) (dst + TT * e)[t] = (src + TT * e)[t];
 }
 
-// three forward stages with twiddle (w, Shoup) pairs w0 | w1,w2 | w3..w6
+// three forward stages with twiddle (-w, Shoup) pairs w0 | w1,w2 | w3..w6
 __device__ __forceinline__ void fwd8(uint32_t (&x)[8], const uint2 (&w)[7], uint32_t q, uint32_t two_q) {
 #pragma unroll
   for (int e = 0; e < 4; ++e) bf_fwd(x[e], x[e + 4], w[0].x, w[0].y, q, two_q);

@@ -463,17 +463,15 @@ struct XpOut {
 // v = sum_{j<4} d_j 64^j + d_4 64^4 with d_j in [-32, 32), the low 24 bits
 // of w are the d_j + 32 and w >> 24 (arithmetic) is d_4.  These are the
 // digits that repeating d = ((v + 32) mod 64) - 32, v = (v - d) / 64 gives;
-// one bit-field extract per digit instead of that carry chain.  Returned
-// lifted into [0, q).
+// one bit-field extract per digit instead of that carry chain.  Returned as
+// d + q, in [q - 32, q + 32]: congruent to d and below 2q, which is all the
+// forward transform asks of its input (its reduced outputs are the same as
+// for d mod q).
 constexpr int32_t DIGIT_OFFSET = 32 * (1 + 64 + 4096 + 262144);
 
 __device__ __forceinline__ uint32_t digit_lift(int32_t w, int j, uint32_t q) {
-  if (j < 4) {
-    const uint32_t u = ((uint32_t)w >> (6 * j)) & 63u;
-    return u < 32u ? u + (q - 32u) : u - 32u;
-  }
-  const int32_t d = w >> 24;
-  return d < 0 ? (uint32_t)(d + (int32_t)q) : (uint32_t)d;
+  if (j < 4) return (((uint32_t)w >> (6 * j)) & 63u) + (q - 32u);
+  return (uint32_t)((w >> 24) + (int32_t)q);
 }
 
 // inverse transforms of the a and b sums of output prime ip (inputs in [0, q))

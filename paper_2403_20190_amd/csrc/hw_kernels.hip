@@ -21,6 +21,12 @@ constexpr int WAVES_XP = 3;
 // counter-based generator: Philox4x32-10 (Salmon et al., SC'11)
 // ---------------------------------------------------------------------------
 
+// a ^ b ^ c in one instruction: gfx950's three-input bitwise operation with
+// truth table 0x96 (the compiler leaves two two-input XORs otherwise)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
@@ -30,7 +36,8 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
     }
     // each 32 x 32 -> 64-bit product in one instruction (both halves used)
     const uint64_t p0 = mad64(0xD2511F53u, c.x, 0ull), p1 = mad64(0xCD9E8D57u, c.z, 0ull);
-    c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+    c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1, xor3((uint32_t)(p0 >> 32), c.w, k1),
+                   (uint32_t)p0);
   }
   return c;
 }

@@ -88,7 +88,7 @@ typedef struct {
   uint32_t s;
   uint32_t l;
   uint32_t a;
-  uint32_t layout;     /* model layout: 0 or 1, see below */
+  uint32_t layout;     /* model layout: 0, 1 or 2, see above */
   uint64_t perm_seed;
 } hw_wisard_shape;
 
@@ -108,8 +108,9 @@ const char* hw_last_error(void);
 /* The resolved parameter set (primes filled in). */
 hw_status hw_ctx_params(const hw_ctx* ctx, hw_params* out);
 
-/* Bytes of one RLWE, one RGSW (device layout) and one LWE ciphertext. */
-hw_status hw_sizes(const hw_ctx* ctx, uint64_t* rlwe_bytes, uint64_t* rgsw_bytes,
+/* Bytes of the secret key (int32[N]), of one RLWE, one RGSW (device layout)
+ * and one LWE ciphertext.  Any output pointer may be NULL. */
+hw_status hw_sizes(const hw_ctx* ctx, uint64_t* sk_bytes, uint64_t* rlwe_bytes, uint64_t* rgsw_bytes,
                    uint64_t* lwe_bytes);
 
 /* Model geometry of Def. 2: k0 = ceil(s/a) RAMs and k1 RLWE per RAM.  With
@@ -201,7 +202,10 @@ hw_status hw_external_product(hw_ctx* ctx, const uint32_t* rgsw_dev, const uint3
 /* ---- server side: the hot path -------------------------------------------- */
 
 /* Homomorphic training (Alg. 6) of n samples, accumulated into the model in
- * place.  x_rgsw_dev: RGSW[n][s] of the unpermuted input bits; y_rgsw_dev:
+ * place.  Capacity: every sample adds Delta to one cell per RAM and to the
+ * class counter, so the model decrypts correctly while it holds at most
+ * p - 1 samples in total; the caller tracks that count for this call (the
+ * serving engine tracks it for its models and refuses requests past it).  x_rgsw_dev: RGSW[n][s] of the unpermuted input bits; y_rgsw_dev:
  * RGSW[n][L] of the label bits, LSB first (L = ceil(log2 l)).  For sample i
  * and RAM j the IVP (Alg. 5) runs with input (0, Delta) on b = [label bits,
  * x[pi[j a + t]] for t < a_j] (a_j = min(a, s - j a)), creating only the
@@ -312,6 +316,43 @@ hw_status hw_batch_plan_info(const hw_batch_plan* plan, uint64_t* items, uint32_
 /* Waits for the device to finish the plan's replays, then frees it. */
 void hw_batch_plan_destroy(hw_batch_plan* plan);
 
+/* One job of hw_batch_run: training (Alg. 6) or inference (Alg. 7, PD-act
+ * branch) of n samples under the parameter set ctxs[ctx_index].  The buffers
+ * mean what they mean for hw_wisard_train_encrypted (kind 0: x_rgsw, y_rgsw,
+ * model accumulated in place, class_count or NULL) and
+ * hw_wisard_infer_encrypted (kind 1: model read, x_rgsw, ram_scores,
+ * class_scores or NULL); the fields of the other kind are ignored. */
+typedef struct {
+  uint32_t ctx_index;           /* index into the context list */
+  uint32_t kind;                /* 0 = train, 1 = infer */
+  hw_wisard_shape shape;
+  const uint32_t* x_rgsw_dev;   /* [n][s] RGSW of the input bits */
+  const uint32_t* y_rgsw_dev;   /* train: [n][L] RGSW of the label bits (NULL when L = 0) */
+  uint64_t n;                   /* samples */
+  uint32_t* model_dev;          /* [rows][k1] RLWE: train accumulates into it, infer reads it */
+  uint32_t* class_count_dev;    /* train: one RLWE or NULL */
+  uint32_t* ram_scores_dev;     /* infer: [n][l][k0] LWE */
+  uint32_t* class_scores_dev;   /* infer: [n][l] LWE or NULL */
+} hw_job;
+
+/* A batch of training and inference jobs over several parameter sets.  For
+ * each context, in the order of `ctxs`: its training jobs run as one
+ * persistent launch (exactly hw_batch_train on them), then its inference jobs
+ * as one persistent launch over a queue of (job, RAM, label, piece of
+ * samples) items, longest first, each workgroup running the Vertical Packing
+ * of its item's samples one after another in private slots; per-class sums
+ * follow for the jobs that ask for them.  A launch is compiled for one ring
+ * degree and prime count, so it never spans two contexts: the contexts'
+ * launches follow one another on `stream`.  An inference job therefore sees
+ * every training job of its context in the same batch.  Every job's result
+ * is bit-identical to the single-job call on it.  Training jobs on the same
+ * model are rejected (layout 2 is rejected for training as in
+ * hw_batch_train), as are jobs whose outputs overlap each other or a model an
+ * inference job reads (HW_EINVAL); the checks run before anything is
+ * enqueued.  The contexts' calls are serialised as for any call on them. */
+hw_status hw_batch_run(hw_ctx* const* ctxs, uint32_t nctx, const hw_job* jobs, uint32_t njobs,
+                       hipStream_t stream);
+
 /* ---- serving engine (continuous batching) ------------------------------------- */
 
 /* A request loop on one device: train and infer requests against resident
@@ -341,8 +382,10 @@ typedef struct {
   const uint8_t* bits_host;    /* [n][s] input bits; host, read until the request completes */
   const uint8_t* labels_host;  /* train: [n][L] label bits, LSB first; NULL when L = 0 */
   uint64_t n;                  /* samples */
-  uint64_t enc_seed;           /* input bits use seed enc_seed, labels enc_seed + 1; ciphertext
-                                  index = sample * s + bit (sample * L + bit for labels) */
+  uint64_t enc_seed;           /* the request's encryption seeds are derived from it
+                                  (hw_request_seeds): inputs use seed_x, labels seed_y; ciphertext
+                                  index = sample * s + bit (sample * L + bit for labels).  Requests
+                                  must not share an enc_seed (their draws would repeat). */
   uint64_t* cells_host;        /* infer: [n][l][k0] decrypted per-RAM scores */
 } hw_request;
 
@@ -357,15 +400,33 @@ hw_status hw_engine_create(const hw_params* params, int device, const int32_t* s
 /* Wait for the chunks in flight, stop the scheduler and free the engine. */
 void hw_engine_destroy(hw_engine* engine);
 
+/* The two encryption seeds of a request (the engine's client step): the
+ * 64-bit draws 0 and 1 of the library's generator (Philox4x32-10, the
+ * counter-based generator of every random draw here) in domain 6 keyed by
+ * enc_seed.  Input and label streams of one request, and the streams of
+ * requests with different enc_seed, are thereby keyed apart: no RLWE draw
+ * is reused under the engine's one key (Sec. 2.5 security rests on fresh
+ * randomness per ciphertext). */
+hw_status hw_request_seeds(uint64_t enc_seed, uint64_t* seed_x, uint64_t* seed_y);
+
 /* Register a resident model (caller-owned device buffers, [k0][k1] RLWE and
- * an optional class counter) of the given shape; *job_id names it.  Call
- * before submitting requests that use it. */
+ * an optional class counter) of the given shape that already holds `trained`
+ * samples (0 for a zeroed model); *job_id names it.  Call before submitting
+ * requests that use it.  HW_EINVAL when trained > p - 1. */
 hw_status hw_engine_add_job(hw_engine* engine, const hw_wisard_shape* shape, uint32_t* model_dev,
-                            uint32_t* class_count_dev, uint32_t* job_id);
+                            uint32_t* class_count_dev, uint64_t trained, uint32_t* job_id);
 
 /* Queue a request.  HW_EBUSY: one chunk of it would not fit in the arena
- * (it could never be admitted); HW_EINVAL: bad job or buffers. */
+ * (it could never be admitted); HW_EINVAL: bad job or buffers, or a training
+ * request that could take its model past p - 1 samples.  Training adds Delta
+ * per sample to one cell of every RAM and to the class counter, so a count
+ * of p would wrap to 0 (Sec. 2.5.1 encoding, plaintexts mod p); the engine
+ * counts every admitted training request's samples against the model. */
 hw_status hw_engine_submit(hw_engine* engine, const hw_request* request, uint64_t* request_id);
+
+/* Samples counted against a model (trained plus admitted training requests)
+ * and the capacity p - 1. */
+hw_status hw_engine_job_samples(hw_engine* engine, uint32_t job, uint64_t* samples, uint64_t* capacity);
 
 /* State of a request (HW_REQ_*) and, once finished, its latency from submission. */
 hw_status hw_engine_poll(hw_engine* engine, uint64_t request_id, int* state, double* latency_ms);
@@ -421,6 +482,22 @@ hw_status hw_tune_get(hw_ctx* ctx, const char* kernel, int* variant, int* timing
 
 /* Description of a variant, or NULL for an unknown kernel or variant. */
 const char* hw_tune_variant_name(const char* kernel, int variant);
+
+/* ---- device peak probes (measurement) ----------------------------------------- */
+
+/* Measure a peak rate of device `device` on `stream` (waits for it):
+ *   "triad"          a = b + k c over three uint32 arrays of `size` bytes each
+ *                    (library-allocated, freed before return); *rate = bytes
+ *                    moved per second (2 size read + size written), best of 5;
+ *   "v_add_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_mad_u64_u32"
+ *                    eight independent chains of that one instruction per
+ *                    thread, 8 waves per SIMD on every CU, `size` loop trips
+ *                    of 128 instructions (0: 4096); *rate = lane-instructions
+ *                    per second (64 per wave instruction), best of 3.
+ * *ms (may be NULL): the best launch time.  These are the peaks the hot-path
+ * kernels' rooflines are priced against besides the published ones. */
+hw_status hw_microbench(int device, const char* kind, uint64_t size, double* rate, double* ms,
+                        hipStream_t stream);
 
 /* ---- per-kernel timing ------------------------------------------------------ */
 

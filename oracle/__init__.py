@@ -158,6 +158,19 @@ def w64(seed: int, domain: int, index: int) -> int:
     return int(lib().orc_w64(seed, domain, index))
 
 
+# domain of the serving engine's per-request seed derivation
+DOM_REQ = 6
+
+
+def request_seeds(enc_seed: int) -> tuple[int, int]:
+    """Encryption seeds (inputs, labels) that a serving request with seed
+    enc_seed uses: the 64-bit draws 0 and 1 of stream (enc_seed, DOM_REQ).
+    Deriving both by the generator, not by seed arithmetic, keys every
+    request's input and label streams apart (Sec. 2.5: each RLWE sample takes
+    fresh randomness)."""
+    return w64(enc_seed, DOM_REQ, 0), w64(enc_seed, DOM_REQ, 1)
+
+
 def w32(seed: int, domain: int, index: int) -> int:
     return int(lib().orc_w32(seed, domain, index))
 

@@ -118,6 +118,8 @@ static uint64_t draw64(uint64_t seed, uint32_t domain, uint64_t index) {
   return (index & 1) ? ((uint64_t)c[2] | ((uint64_t)c[3] << 32)) : ((uint64_t)c[0] | ((uint64_t)c[1] << 32));
 }
 
+uint64_t lib_draw64(uint64_t seed, uint32_t domain, uint64_t index) { return draw64(seed, domain, index); }
+
 // T[k] = floor(2^63 P(|X| <= k)), X ~ discrete Gaussian(sigma) cut at 41; the
 // cumulative weights 1, 2 rho(1), 2 rho(2), ... are summed in increasing order
 static void build_cdt(double sigma, uint64_t T[42]) {
@@ -256,6 +258,8 @@ extern "C" void hw_ctx_destroy(hw_ctx* c) {
   for (auto& kv : c->perms) hipFree(kv.second);
   if (c->h_btab) hipHostFree(c->h_btab);
   if (c->d_btab) hipFree(c->d_btab);
+  if (c->h_itab) hipHostFree(c->h_itab);
+  if (c->d_itab) hipFree(c->d_itab);
   if (c->d_counter) hipFree(c->d_counter);
   for (auto& kv : c->tune)
     for (auto& p : kv.second.pend) {
@@ -271,8 +275,9 @@ extern "C" hw_status hw_ctx_params(const hw_ctx* c, hw_params* out) {
   return ok();
 }
 
-extern "C" hw_status hw_sizes(const hw_ctx* c, uint64_t* rlwe, uint64_t* rgsw, uint64_t* lwe) {
+extern "C" hw_status hw_sizes(const hw_ctx* c, uint64_t* sk, uint64_t* rlwe, uint64_t* rgsw, uint64_t* lwe) {
   if (!c) return fail(HW_EINVAL, "null context");
+  if (sk) *sk = 4ull * c->prm.N;
   if (rlwe) *rlwe = 4 * rlwe_words(c);
   if (rgsw) *rgsw = 4 * rgsw_words(c);
   if (lwe) *lwe = 4 * lwe_words(c);
@@ -386,7 +391,7 @@ extern "C" hw_status hw_permutation(const hw_wisard_shape* sh, uint32_t* perm_ho
   return ok();
 }
 
-static hw_status ensure_ws(hw_ctx* c, size_t bytes) {
+hw_status ensure_ws(hw_ctx* c, size_t bytes) {
   if (bytes <= c->ws_bytes) return HW_OK;
   if (c->d_ws) {
     HIP_TRY(hipDeviceSynchronize());
@@ -416,7 +421,7 @@ hw_status perm_for(hw_ctx* c, const hw_wisard_shape* sh, hipStream_t st, const u
   return HW_OK;
 }
 
-static hw_status enter(hw_ctx* c) {
+hw_status enter(hw_ctx* c) {
   if (!c) return fail(HW_EINVAL, "null context");
   HIP_TRY(hipSetDevice(c->device));
   return HW_OK;
@@ -1154,6 +1159,7 @@ const std::vector<TuneKernel>& tune_table() {
       {"infer", 5e4, {"ram-major 3-D grid", "labels-adjacent xcd-grouped 1-D grid",
                       "ram-major 3-D grid, 4 waves/SIMD", "labels-adjacent xcd-grouped 1-D grid, 4 waves/SIMD"}},
       {"train_batch", 5e4, {"persistent, 3 waves/SIMD", "persistent, 4 waves/SIMD"}},
+      {"infer_batch", 5e4, {"persistent, 3 waves/SIMD", "persistent, 4 waves/SIMD"}},
       {"ntt", 16384, {"1 polynomial/workgroup", "2 polynomials/workgroup", "4 polynomials/workgroup",
                       "8 polynomials/workgroup"}},
       {"ntt_inverse", 16384, {"1 polynomial/workgroup", "2 polynomials/workgroup", "4 polynomials/workgroup",
@@ -1176,7 +1182,7 @@ int tune_variants(const hw_ctx* c, const char* kernel) {
   const int n = table_variants(kernel);
   if (c->logN == 12) return n;
   if (!strcmp(kernel, "train") || !strcmp(kernel, "infer")) return 2;
-  if (!strcmp(kernel, "train_batch")) return 1;
+  if (!strcmp(kernel, "train_batch") || !strcmp(kernel, "infer_batch")) return 1;
   return n;
 }
 

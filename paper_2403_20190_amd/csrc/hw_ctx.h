@@ -58,7 +58,11 @@ struct hw_ctx {
   void* h_btab = nullptr;
   void* d_btab = nullptr;
   size_t btab_bytes = 0;
-  uint32_t* d_counter = nullptr;
+  uint32_t* d_counter = nullptr;   // 64 bytes: word 0 the training queue, word 16 the inference queue
+  // batched inference: job/item tables (pinned host staging, device copy)
+  void* h_itab = nullptr;
+  void* d_itab = nullptr;
+  size_t itab_bytes = 0;
   // per-kernel timing
   bool prof = false;
   struct Rec {
@@ -179,6 +183,12 @@ hw_status ok();
   } while (0)
 
 hw_status check_shape(const hw_ctx* c, const hw_wisard_shape* sh, Dims* d);
+// 64-bit draw `index` of stream (seed, domain) of the library's generator (Philox4x32-10)
+uint64_t lib_draw64(uint64_t seed, uint32_t domain, uint64_t index);
+// make the context current on this thread (HW_EINVAL for a null context)
+hw_status enter(hw_ctx* c);
+// grow the context's workspace to at least `bytes` (waits for the device when it reallocates)
+hw_status ensure_ws(hw_ctx* c, size_t bytes);
 hw_status perm_for(hw_ctx* c, const hw_wisard_shape* sh, hipStream_t st, const uint32_t** out);
 
 // workspace bytes per sample of one training / inference call

@@ -88,11 +88,13 @@ struct Job {
   const uint32_t* perm;
   uint32_t* model;
   uint32_t* cnt;
+  uint64_t samples;           // trained into the model, plus those of admitted training requests
   std::deque<uint64_t> fifo;  // requests on this model, in submission order
 };
 
 struct Req {
   hw_request r;
+  uint64_t seed_x = 0, seed_y = 0;  // encryption seeds of the inputs and labels (hw_request_seeds)
   int state = HW_REQ_QUEUED;
   uint64_t chunks = 0, next = 0, done = 0;
   uint32_t inflight = 0;
@@ -176,7 +178,7 @@ static hw_status launch_chunk(hw_engine* E, Slot& S, Req& R, const Job& J) {
   A.sk_hat = E->skhat;
   A.bits = d_bits;
   A.out = xr;
-  A.seed = R.r.enc_seed;
+  A.seed = R.seed_x;
   A.ct0 = o * s;
   A.log_base = c->prm.log_base;
   HIP_TRY(tuned(c, "encrypt_rgsw", (double)m * s * 10 * c->prm.nq, S.st, [&](int v) {
@@ -187,7 +189,7 @@ static hw_status launch_chunk(hw_engine* E, Slot& S, Req& R, const Job& J) {
     if (L) {
       A.bits = d_bits + m * s;
       A.out = yr;
-      A.seed = R.r.enc_seed + 1;
+      A.seed = R.seed_y;
       A.ct0 = o * L;
       HIP_TRY(tuned(c, "encrypt_rgsw", (double)m * L * 10 * c->prm.nq, S.st, [&](int v) {
         return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, m * L, enc_rows_per_wg(v), S.st);
@@ -374,11 +376,28 @@ extern "C" void hw_engine_destroy(hw_engine* E) {
   delete E;
 }
 
+// the request's two encryption seeds: draws 0 and 1 of the library's
+// generator in domain DOM_REQ keyed by enc_seed, so that the input and label
+// streams of one request, and those of requests with different enc_seed, are
+// keyed apart (no arithmetic relation between seeds makes two streams equal)
+constexpr uint32_t DOM_REQ = 6;
+
+extern "C" hw_status hw_request_seeds(uint64_t enc_seed, uint64_t* seed_x, uint64_t* seed_y) {
+  if (!seed_x || !seed_y) return fail(HW_EINVAL, "null argument");
+  *seed_x = lib_draw64(enc_seed, DOM_REQ, 0);
+  *seed_y = lib_draw64(enc_seed, DOM_REQ, 1);
+  return ok();
+}
+
 extern "C" hw_status hw_engine_add_job(hw_engine* E, const hw_wisard_shape* sh, uint32_t* model,
-                                       uint32_t* cnt, uint32_t* job_id) {
+                                       uint32_t* cnt, uint64_t trained, uint32_t* job_id) {
   if (!E || !sh || !model || !job_id) return fail(HW_EINVAL, "null argument");
   Job J{};
   CHECK(check_shape(E->ctx, sh, &J.d));
+  if (trained > E->ctx->prm.plain_mod - 1)
+    return fail(HW_EINVAL, "trained = %llu: a model holds at most p - 1 = %llu samples",
+                (unsigned long long)trained, (unsigned long long)(E->ctx->prm.plain_mod - 1));
+  J.samples = trained;
   if (sh->s > E->cfg.max_s) return fail(HW_EINVAL, "s = %u exceeds the engine's max_s %u", sh->s, E->cfg.max_s);
   if ((uint64_t)sh->l * J.d.k0 > E->cfg.max_cells) return fail(HW_EINVAL, "l * k0 exceeds the engine's max_cells");
   if (J.d.L > 8) return fail(HW_EINVAL, "too many label bits for the engine's staging");
@@ -406,8 +425,19 @@ extern "C" hw_status hw_engine_submit(hw_engine* E, const hw_request* r, uint64_
   const uint64_t m = std::min<uint64_t>(E->cfg.chunk, r->n);
   if (chunk_bytes(E, J, r->kind, m) > E->cfg.arena_bytes)
     return fail(HW_EBUSY, "a chunk of this request needs more device memory than the engine's arena");
+  // Training adds Delta per sample to a cell and to the class counter, so a
+  // count reaching p would wrap (Sec. 2.5.1 encoding): refuse a request that
+  // could take the model past p - 1 samples.  Admitted requests count in full
+  // (a cancelled one may have run some chunks).
+  const uint64_t cap = E->ctx->prm.plain_mod - 1;
+  if (r->kind == 0 && (J.samples > cap || r->n > cap - J.samples))
+    return fail(HW_EINVAL, "training %llu more samples would take the model to %llu samples: counters hold at "
+                "most p - 1 = %llu", (unsigned long long)r->n, (unsigned long long)(J.samples + r->n),
+                (unsigned long long)cap);
   Req R;
   R.r = *r;
+  (void)hw_request_seeds(r->enc_seed, &R.seed_x, &R.seed_y);
+  if (r->kind == 0) E->jobs[r->job].samples += r->n;
   R.chunks = (r->n + E->cfg.chunk - 1) / E->cfg.chunk;
   R.t_submit = now_ms();
   *id = E->next_id++;
@@ -450,6 +480,15 @@ extern "C" hw_status hw_engine_cancel(hw_engine* E, uint64_t id) {
   if (it == E->reqs.end()) return fail(HW_EINVAL, "unknown request %llu", (unsigned long long)id);
   if (it->second.state < HW_REQ_DONE) it->second.cancel = true;
   E->cv.notify_all();
+  return ok();
+}
+
+extern "C" hw_status hw_engine_job_samples(hw_engine* E, uint32_t job, uint64_t* samples, uint64_t* capacity) {
+  if (!E) return fail(HW_EINVAL, "null engine");
+  std::lock_guard<std::mutex> g(E->mu);
+  if (job >= E->jobs.size()) return fail(HW_EINVAL, "unknown job %u", job);
+  if (samples) *samples = E->jobs[job].samples;
+  if (capacity) *capacity = E->ctx->prm.plain_mod - 1;
   return ok();
 }
 

@@ -116,6 +116,26 @@ struct BatchArgs {
   uint64_t rgsw_words;
 };
 
+// batched inference: one entry per job (args.i0, nsub and map unused; args.scratch unused)
+struct IJob {
+  InferArgs args;           // the job's model, inputs, scores and shape fields
+  uint32_t nsmp;            // samples
+  uint32_t per;             // samples per piece
+};
+
+struct IItem {
+  uint32_t job, ram, lab, piece;
+};
+
+struct IBatchArgs {
+  const IJob* jobs;
+  const IItem* items;
+  uint32_t nitems;
+  uint32_t* counter;
+  uint32_t* ws;             // per persistent workgroup: scratch_words (slots + 1 RLWE)
+  uint64_t scratch_words;
+};
+
 struct PksArgs {
   const uint32_t* key;      // [N][D][2][NQ][N] evaluation domain
   const uint32_t* lwe;      // [count][k] LWE ([NQ][N+1] each)
@@ -159,6 +179,9 @@ hipError_t launch_train_batch(int logN, int nq, const Tabs& T, const BatchArgs& 
 hipError_t launch_reduce_batch(const Tabs& T, const BJob* jobs, uint32_t njobs, uint64_t total, uint32_t logN,
                                uint32_t N, uint32_t nq, const uint32_t* acc, hipStream_t st);
 hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int occ, hipStream_t st);
+hipError_t infer_batch_grid(int logN, int nq, int occ, uint32_t* grid);
+hipError_t launch_infer_batch(int logN, int nq, const Tabs& T, const IBatchArgs& B, uint32_t grid, int occ,
+                              hipStream_t st);
 hipError_t launch_class_sums(const Tabs& T, const SumArgs& A, hipStream_t st);
 hipError_t launch_enc_pks(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, hipStream_t st);
 uint32_t pks_blocks(int logN);  // key-coordinate blocks of the packing (partial sums per group and prime)

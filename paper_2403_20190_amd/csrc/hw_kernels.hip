@@ -958,27 +958,14 @@ __global__ __launch_bounds__(256) void k_row_pack(Tabs T, RowPackArgs A) {
 // j / rpr, whose block from coefficient (j mod rpr) 2^nbf holds it; the
 // extraction indices move by that offset.
 
-template <int LOGN, int NQ, int OCC>
-__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_infer(Tabs T, InferArgs A) {
-  __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, xp_pair<LOGN, NQ>()>()];
-  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+// The VP of (sample gi, RAM ram, label lab) with the workgroup's slots acc
+// (A.slots RLWE) and input slot xin; writes its LWE score(s) into A.scores.
+template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>()>
+__device__ __forceinline__ void vp_one(const Tabs& T, const InferArgs& A, uint64_t gi, uint32_t ram, uint32_t lab,
+                                       uint32_t* __restrict__ acc, uint32_t* __restrict__ xin, uint32_t* lds,
+                                       uint2* twl, uint32_t t) {
   constexpr int N = 1 << LOGN, TT = N / 8;
   constexpr size_t RW = (size_t)2 * NQ * N;
-  const uint32_t t = threadIdx.x;
-  uint32_t ram, lab, smp;
-  if (A.map == 0) {  // 3-D grid (RAM, label, sample)
-    ram = blockIdx.x;
-    lab = blockIdx.y;
-    smp = blockIdx.z;
-  } else {  // 1-D grid, the labels of one (sample, RAM) adjacent, XCD x takes the x-th eighth
-    const uint32_t G = A.k0 * A.nlab * A.nsub, per = (G + 7) >> 3;
-    const uint32_t lg = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
-    if (lg >= G) return;
-    lab = lg % A.nlab;
-    ram = (lg / A.nlab) % A.k0;
-    smp = lg / A.nlab / A.k0;
-  }
-  const uint64_t gi = A.i0 + smp;
   const uint32_t rem = A.s - ram * A.a;
   const uint32_t aj = rem < A.a ? rem : A.a;
   const uint32_t nb = A.L + aj;
@@ -988,8 +975,6 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
   const uint32_t tl = tree_l(A.layout, A.l);  // rows per group of leaves
   const uint32_t* H = A.model + (size_t)(ram / A.rpr) * A.k1 * RW;
   const uint32_t off = (ram % A.rpr) << A.nbf;  // 0 unless layout 2
-  uint32_t* acc = A.scratch + (((size_t)smp * A.nlab + lab) * A.k0 + ram) * (A.slots + 1) * RW;
-  uint32_t* xin = acc + (size_t)A.slots * RW;
   auto xbit = [&](uint32_t u) -> const uint32_t* {
     return A.x_rgsw + (gi * A.s + A.perm[ram * A.a + (u - TL)]) * A.rgsw_words;
   };
@@ -1016,7 +1001,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
           for (int e = 0; e < 8; ++e)
             (xin + o + TT * e)[t] = subq((hi + o + TT * e)[t], (lo + o + TT * e)[t], q);
         }
-        ext_prod<LOGN, NQ>(xin, C, T, lds, twl, xc, t, XpOut{dst, lo, nullptr, XP_ADD});
+        ext_prod<LOGN, NQ, PR>(xin, C, T, lds, twl, xc, t, XpOut{dst, lo, nullptr, XP_ADD});
       }
     }
   } else {
@@ -1044,7 +1029,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
       }
       continue;
     }
-    cmux_rot<LOGN, NQ>(T, acc, ex, xbit(u), xin, lds, twl, xc, t);
+    cmux_rot<LOGN, NQ, PR>(T, acc, ex, xbit(u), xin, lds, twl, xc, t);
   }
   // ExtractLWE(acc, idx) for the class(es) of this workgroup: a'_k = a_{idx-k}
   // for k <= idx, -a_{N+idx-k} above, b' = b_idx; idx = 0 for layout 0,
@@ -1068,6 +1053,66 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
         (o + TT * e)[t] = (lo || x == 0) ? x : q - x;
       }
       if (t == 0) o[N] = acc[(size_t)(NQ + i) * N + idx];
+    }
+  }
+}
+
+template <int LOGN, int NQ, int OCC>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_infer(Tabs T, InferArgs A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, xp_pair<LOGN, NQ>()>()];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr size_t RW = (size_t)2 * NQ * (1 << LOGN);
+  const uint32_t t = threadIdx.x;
+  uint32_t ram, lab, smp;
+  if (A.map == 0) {  // 3-D grid (RAM, label, sample)
+    ram = blockIdx.x;
+    lab = blockIdx.y;
+    smp = blockIdx.z;
+  } else {  // 1-D grid, the labels of one (sample, RAM) adjacent, XCD x takes the x-th eighth
+    const uint32_t G = A.k0 * A.nlab * A.nsub, per = (G + 7) >> 3;
+    const uint32_t lg = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    if (lg >= G) return;
+    lab = lg % A.nlab;
+    ram = (lg / A.nlab) % A.k0;
+    smp = lg / A.nlab / A.k0;
+  }
+  uint32_t* acc = A.scratch + (((size_t)smp * A.nlab + lab) * A.k0 + ram) * (A.slots + 1) * RW;
+  vp_one<LOGN, NQ>(T, A, A.i0 + smp, ram, lab, acc, acc + (size_t)A.slots * RW, lds, twl, t);
+}
+
+// ---------------------------------------------------------------------------
+// batched inference: one persistent launch over many jobs of one parameter set
+// ---------------------------------------------------------------------------
+// An item is (job, RAM, label, piece): the VPs of the piece's samples [piece
+// per, ...) for that RAM and label (every label at once for layouts 1-2),
+// one after another in the workgroup's private slots.  Each VP writes its
+// own scores, so no reduction follows.  Items come from a queue (a device
+// counter), longest first; a workgroup leaves when the queue is exhausted.
+template <int LOGN, int NQ, int OCC>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_infer_batch(
+    Tabs T, IBatchArgs B) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, false>()];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  __shared__ uint32_t next;
+  const uint32_t t = threadIdx.x;
+  uint32_t* acc = B.ws + (size_t)blockIdx.x * B.scratch_words;
+#pragma unroll 1
+  for (;;) {
+    if (t == 0) next = atomicAdd(B.counter, 1u);
+    __syncthreads();
+    const uint32_t it = __builtin_amdgcn_readfirstlane(next);
+    __syncthreads();
+    if (it >= B.nitems) break;
+    const IItem I = B.items[it];
+    const IJob& J = B.jobs[I.job];
+    const uint32_t s0 = I.piece * J.per;
+    const uint32_t s1 = s0 + J.per < J.nsmp ? s0 + J.per : J.nsmp;
+    const size_t slot_words = (size_t)J.args.slots * 2 * NQ * (1 << LOGN);
+#pragma unroll 1
+    for (uint32_t smp = s0; smp < s1; ++smp) {
+      // single transforms: with pairs the queue state next to them spills registers
+      vp_one<LOGN, NQ, false>(T, J.args, smp, I.ram, I.lab, acc, acc + slot_words, lds, twl, t);
+      __syncthreads();
     }
   }
 }
@@ -1462,6 +1507,34 @@ hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int
   const dim3 grid = A.map == 0 ? dim3(A.k0, A.nlab, A.nsub) : dim3((uint32_t)((G + 7) / 8 * 8));
   HW_DISPATCH_OCC(logN, nq, occ,
                   hipLaunchKernelGGL((k_infer<LN, NQ, OC>), grid, dim3(Geo<LN>::T), 0, st, T, A));
+  return hipGetLastError();
+}
+
+template <int LN, int NQ, int OC>
+static hipError_t infer_batch_grid_t(uint32_t* grid) {
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_infer_batch<LN, NQ, OC>, Geo<LN>::T,
+                                                     0);
+  if (e != hipSuccess) return e;
+  *grid = (uint32_t)(cus * (per_cu > 0 ? per_cu : 1));
+  return hipSuccess;
+}
+
+hipError_t infer_batch_grid(int logN, int nq, int occ, uint32_t* grid) {
+  HW_DISPATCH_OCC(logN, nq, occ, return infer_batch_grid_t<LN, NQ, OC>(grid));
+  return hipSuccess;
+}
+
+hipError_t launch_infer_batch(int logN, int nq, const Tabs& T, const IBatchArgs& B, uint32_t grid, int occ,
+                              hipStream_t st) {
+  if (grid > B.nitems) grid = B.nitems;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, B.counter, 1u);
+  HW_DISPATCH_OCC(logN, nq, occ,
+                  hipLaunchKernelGGL((k_infer_batch<LN, NQ, OC>), dim3(grid), dim3(Geo<LN>::T), 0, st, T, B));
   return hipGetLastError();
 }
 

@@ -55,6 +55,13 @@ class TrainJob(C.Structure):
                 ("model", C.c_void_p), ("class_count", C.c_void_p)]
 
 
+class Job(C.Structure):
+    """hw_job: one training (kind 0) or inference (kind 1) job of hw_batch_run"""
+    _fields_ = [("ctx_index", C.c_uint32), ("kind", C.c_uint32), ("shape", Shape), ("x_rgsw", C.c_void_p),
+                ("y_rgsw", C.c_void_p), ("n", C.c_uint64), ("model", C.c_void_p), ("class_count", C.c_void_p),
+                ("ram_scores", C.c_void_p), ("class_scores", C.c_void_p)]
+
+
 class EngineConfig(C.Structure):
     _fields_ = [("slots", C.c_uint32), ("chunk", C.c_uint32), ("max_s", C.c_uint32), ("max_cells", C.c_uint32),
                 ("arena_bytes", C.c_uint64)]
@@ -71,7 +78,7 @@ _vp, _u64, _u32, _i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
 _SIG = {
     "hw_ctx_create": [C.POINTER(Params), _i32, C.POINTER(C.c_void_p)],
     "hw_ctx_params": [_vp, C.POINTER(Params)],
-    "hw_sizes": [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)],
+    "hw_sizes": [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)],
     "hw_wisard_dims": [_vp, C.POINTER(Shape), C.POINTER(_u32), C.POINTER(_u32), C.POINTER(_u64)],
     "hw_permutation": [C.POINTER(Shape), _vp],
     "hw_wisard_model_rows": [_vp, C.POINTER(Shape), C.POINTER(_u32), C.POINTER(_u32)],
@@ -91,11 +98,15 @@ _SIG = {
     "hw_pks_key_export_canonical": [_vp, _vp, _vp, _vp],
     "hw_pack_lwe": [_vp, _vp, _vp, _u32, _u64, _vp, _vp],
     "hw_batch_train": [_vp, C.POINTER(TrainJob), _u32, _vp],
+    "hw_batch_run": [C.POINTER(C.c_void_p), _u32, C.POINTER(Job), _u32, _vp],
     "hw_batch_plan_create": [_vp, C.POINTER(TrainJob), _u32, C.POINTER(C.c_void_p)],
     "hw_batch_plan_launch": [_vp, _vp],
     "hw_batch_plan_info": [_vp, C.POINTER(_u64), C.POINTER(_u32), C.POINTER(C.c_double), C.POINTER(_u64)],
     "hw_engine_create": [C.POINTER(Params), _i32, _vp, C.POINTER(EngineConfig), C.POINTER(C.c_void_p)],
-    "hw_engine_add_job": [_vp, C.POINTER(Shape), _vp, _vp, C.POINTER(_u32)],
+    "hw_engine_add_job": [_vp, C.POINTER(Shape), _vp, _vp, _u64, C.POINTER(_u32)],
+    "hw_engine_job_samples": [_vp, _u32, C.POINTER(_u64), C.POINTER(_u64)],
+    "hw_request_seeds": [_u64, C.POINTER(_u64), C.POINTER(_u64)],
+    "hw_microbench": [_i32, C.c_char_p, _u64, C.POINTER(C.c_double), C.POINTER(C.c_double), _vp],
     "hw_engine_submit": [_vp, C.POINTER(Request), C.POINTER(_u64)],
     "hw_engine_poll": [_vp, _u64, C.POINTER(_i32), C.POINTER(C.c_double)],
     "hw_engine_wait": [_vp, _u64, C.POINTER(_i32), C.POINTER(C.c_double)],
@@ -122,7 +133,7 @@ _lib.hw_last_error.argtypes = []
 _lib.hw_tune_variant_name.restype = C.c_char_p
 _lib.hw_tune_variant_name.argtypes = [C.c_char_p, _i32]
 
-TUNED_KERNELS = ("train", "infer", "train_batch", "ntt", "ntt_inverse", "encrypt_rgsw")
+TUNED_KERNELS = ("train", "infer", "train_batch", "infer_batch", "ntt", "ntt_inverse", "encrypt_rgsw")
 
 
 def tune_variant_name(kernel: str, variant: int):
@@ -183,8 +194,9 @@ class Context:
         _check(_lib.hw_ctx_params(h, C.byref(out)))
         self.N, self.nq, self.p, self.device = N, nq, p, device
         self.primes = [int(out.primes[i]) for i in range(nq)]
-        r, g, w = _u64(), _u64(), _u64()
-        _check(_lib.hw_sizes(h, C.byref(r), C.byref(g), C.byref(w)))
+        k, r, g, w = _u64(), _u64(), _u64(), _u64()
+        _check(_lib.hw_sizes(h, C.byref(k), C.byref(r), C.byref(g), C.byref(w)))
+        self.sk_bytes = k.value
         self.rlwe_words, self.rgsw_words, self.lwe_words = r.value // 4, g.value // 4, w.value // 4
 
     def close(self):
@@ -315,6 +327,38 @@ class Context:
                                               _ptr(ram_scores), _ptr(class_scores), _stream()))
 
 
+def request_seeds(enc_seed: int):
+    """(seed_x, seed_y): the encryption seeds the serving engine derives from
+    a request's enc_seed for its input and label bits"""
+    a, b = _u64(), _u64()
+    _check(_lib.hw_request_seeds(enc_seed, C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def microbench(kind: str, size: int = 0, device: int = 0):
+    """(rate, best ms) of a device peak probe: "triad" (bytes/s over three
+    arrays of `size` bytes) or one of "v_add_u32", "v_mul_lo_u32",
+    "v_mul_hi_u32", "v_mad_u64_u32" (lane-instructions/s; size = loop trips)"""
+    r, ms = C.c_double(), C.c_double()
+    _check(_lib.hw_microbench(device, kind.encode(), size, C.byref(r), C.byref(ms), _stream()))
+    return r.value, ms.value
+
+
+def batch_run(ctxs, jobs):
+    """hw_batch_run.  ctxs: list of Context; jobs: dicts with ctx (index),
+    kind ("train" | "infer"), shape, x, n and: train -- y, model, cnt (optional);
+    infer -- model, scores, sums (optional)."""
+    ctxs = list(ctxs)
+    jobs = list(jobs)
+    harr = (C.c_void_p * max(1, len(ctxs)))(*[c._h for c in ctxs])
+    arr = (Job * max(1, len(jobs)))()
+    for i, J in enumerate(jobs):
+        train = J["kind"] == "train"
+        arr[i] = Job(J.get("ctx", 0), 0 if train else 1, J["shape"], _ptr(J["x"]), _ptr(J.get("y")), J["n"],
+                     _ptr(J["model"]), _ptr(J.get("cnt")), _ptr(J.get("scores")), _ptr(J.get("sums")))
+    _check(_lib.hw_batch_run(harr, len(ctxs), arr, len(jobs), _stream()))
+
+
 class BatchPlan:
     """hw_batch_plan_*: the queue of a batch computed once and captured into
     a HIP graph; launch() replays it on the current stream.  The job buffers
@@ -376,18 +420,48 @@ class Engine:
         except Exception:
             pass
 
-    def add_job(self, sh: Shape, model, class_count=None) -> int:
+    def add_job(self, sh: Shape, model, class_count=None, trained: int = 0) -> int:
+        """register a resident model that already holds `trained` samples"""
         j = _u32()
-        _check(_lib.hw_engine_add_job(self._h, C.byref(sh), _ptr(model), _ptr(class_count), C.byref(j)))
-        self._keep[("job", j.value)] = (model, class_count)
+        _check(_lib.hw_engine_add_job(self._h, C.byref(sh), _ptr(model), _ptr(class_count), trained, C.byref(j)))
+        L = max(0, int(sh.l - 1).bit_length())
+        k0 = -(-sh.s // sh.a)
+        self._keep[("job", j.value)] = (model, class_count, (sh.s, L, sh.l, k0))
         return j.value
+
+    def job_samples(self, job: int):
+        """(samples counted against the model, capacity p - 1)"""
+        n, cap = _u64(), _u64()
+        _check(_lib.hw_engine_job_samples(self._h, job, C.byref(n), C.byref(cap)))
+        return n.value, cap.value
 
     def submit(self, job: int, kind: str, bits: np.ndarray, enc_seed: int, labels: np.ndarray = None,
                cells: np.ndarray = None) -> int:
+        """bits: uint8 [n][s]; train: labels uint8 [n][L]; infer: cells uint64 [n][l][k0] (written)"""
+        if ("job", job) not in self._keep:
+            raise HwError(HW_EINVAL, "unknown job %d" % job)
+        if kind not in ("train", "infer"):
+            raise HwError(HW_EINVAL, "kind must be 'train' or 'infer'")
+        s, L, l, k0 = self._keep[("job", job)][2]
         bits = np.ascontiguousarray(bits, np.uint8)
-        labels = None if labels is None else np.ascontiguousarray(labels, np.uint8)
+        if bits.ndim != 2 or bits.shape[1] != s or bits.shape[0] < 1:
+            raise HwError(HW_EINVAL, "bits must be uint8 [n][s = %d], got shape %s" % (s, bits.shape))
+        n = bits.shape[0]
+        if kind == "train":
+            labels = np.ascontiguousarray(labels if labels is not None else np.zeros((n, 0)), np.uint8)
+            if labels.shape != (n, L):
+                raise HwError(HW_EINVAL, "labels must be uint8 [n][L = %d], got shape %s" % (L, labels.shape))
+            if cells is not None:
+                raise HwError(HW_EINVAL, "a training request has no output cells")
+        else:
+            if labels is not None:
+                raise HwError(HW_EINVAL, "an inference request has no labels")
+            if (not isinstance(cells, np.ndarray) or cells.dtype != np.uint64 or cells.shape != (n, l, k0)
+                    or not cells.flags.c_contiguous or not cells.flags.writeable):
+                raise HwError(HW_EINVAL, "cells must be a writable C-contiguous uint64 array [n][l = %d][k0 = %d]"
+                              % (l, k0))
         r = Request(job, 0 if kind == "train" else 1, bits.ctypes.data,
-                    None if labels is None or labels.size == 0 else labels.ctypes.data, bits.shape[0], enc_seed,
+                    None if labels is None or labels.size == 0 else labels.ctypes.data, n, enc_seed,
                     None if cells is None else cells.ctypes.data)
         rid = _u64()
         _check(_lib.hw_engine_submit(self._h, C.byref(r), C.byref(rid)))

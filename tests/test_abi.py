@@ -50,10 +50,26 @@ def test_host_only_calls():
 def test_tune_variant_names():
     """The tuned kernels and their variant tables (host only)."""
     from paper_2403_20190_amd import hwisard as HW
-    counts = {"train": 4, "infer": 4, "train_batch": 2, "ntt": 4, "ntt_inverse": 4, "encrypt_rgsw": 3}
+    counts = {"train": 4, "infer": 4, "train_batch": 2, "infer_batch": 2, "ntt": 4, "ntt_inverse": 4,
+              "encrypt_rgsw": 3}
     assert set(counts) == set(HW.TUNED_KERNELS)
     for k, n in counts.items():
         names = [HW.tune_variant_name(k, v) for v in range(n)]
         assert all(names) and len(set(names)) == n
         assert HW.tune_variant_name(k, n) is None and HW.tune_variant_name(k, -1) is None
     assert HW.tune_variant_name("xp", 0) is None
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhwisard.so not built")
+def test_request_seeds_match_oracle():
+    """The serving engine's per-request seeds (host only): the library and the
+    oracle derive them with their own generators; the input and label seeds
+    of one request differ, and neighbouring enc_seed values share no seed."""
+    import oracle as O
+    from paper_2403_20190_amd import hwisard as HW
+    seen = set()
+    for e in [0, 1, 2, 500, 501, 8000, 8001, 2**63 + 5, 2**64 - 1]:
+        sx, sy = HW.request_seeds(e)
+        assert (sx, sy) == O.request_seeds(e)
+        assert sx != sy and sx not in seen and sy not in seen
+        seen.update((sx, sy))

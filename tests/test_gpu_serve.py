@@ -89,7 +89,8 @@ def test_alone_equals_mix_and_direct_path():
         assert np.array_equal(a, b)
     for a, b in zip(o_alone, o_mix):
         assert (a is None and b is None) or np.array_equal(a, b)
-    # direct path: the same ciphertexts (seed 500 + k, index sample * s + bit) through the library calls
+    # direct path: the same ciphertexts (the seeds the engine derives from 500 + k, index sample * s + bit)
+    # through the library calls
     for j in range(len(JOBS)):
         J = JOBS[j]
         sh = job_shape(HW, J)
@@ -102,11 +103,12 @@ def test_alone_equals_mix_and_direct_path():
             if jj != j:
                 continue
             X, y = request_data(k)
+            sx, sy = O.request_seeds(500 + k)
             xr = zeros_u32(n * J["s"], ctx.rgsw_words)
-            ctx.encrypt_rgsw_bits(sk, dev(X.reshape(-1).astype(np.uint8)), 500 + k, 0, xr)
+            ctx.encrypt_rgsw_bits(sk, dev(X.reshape(-1).astype(np.uint8)), sx, 0, xr)
             if kind == "train":
                 yr = zeros_u32(n * L, ctx.rgsw_words)
-                ctx.encrypt_rgsw_bits(sk, dev(label_bits(y, L).reshape(-1)), 501 + k, 0, yr)
+                ctx.encrypt_rgsw_bits(sk, dev(label_bits(y, L).reshape(-1)), sy, 0, yr)
                 ctx.train(sh, xr, yr, n, H, None)
                 W += P.train_integer(X, y, J["l"], J["a"], pi)
             else:
@@ -142,3 +144,59 @@ def test_cancel_and_admission():
         small.submit(j, "train", X[:2], 1, labels=label_bits(y[:2], 2))
     assert e.value.status == HW.HW_EBUSY
     small.close()
+
+
+def test_counter_capacity_refusal():
+    """Training adds Delta per sample, so a model holds at most p - 1 samples
+    (Sec. 2.5.1 encoding): the engine counts samples per model, refuses a
+    training request that would pass p - 1, and still serves the others."""
+    import torch
+    from paper_2403_20190_amd import hwisard as HW
+    p = 16
+    sk = torch.zeros(N, dtype=torch.int32, device="cuda")
+    HW.Context(N, NQ, p).keygen(79, sk)
+    eng = HW.Engine(N, NQ, p, sk, slots=2, chunk=4, max_s=64, max_cells=4096, arena_bytes=2 << 30)
+    ctx = HW.Context(N, NQ, p)
+    sh = HW.shape(48, 3, 8, 31)
+    H = model_buffer(ctx, sh)
+    with pytest.raises(HW.HwError):
+        eng.add_job(sh, H, trained=p)  # more than p - 1 already
+    j = eng.add_job(sh, H, trained=9)
+    assert eng.job_samples(j) == (9, p - 1)
+    X, y = synth.prototype_bits(21, 7, 48, 3, flip=0.2)
+    with pytest.raises(HW.HwError) as e:
+        eng.submit(j, "train", X, 1000, labels=label_bits(y, 2))  # 9 + 7 = 16 = p
+    assert e.value.status == HW.HW_EINVAL
+    assert eng.job_samples(j) == (9, p - 1)  # a refused request counts nothing
+    rid = eng.submit(j, "train", X[:6], 1001, labels=label_bits(y[:6], 2))  # 15 = p - 1: accepted
+    assert eng.wait(rid)[0] == HW.REQ_DONE
+    assert eng.job_samples(j) == (15, p - 1)
+    with pytest.raises(HW.HwError):
+        eng.submit(j, "train", X[:1], 1002, labels=label_bits(y[:1], 2))
+    cells = np.zeros((1, 3, 6), np.uint64)
+    rid = eng.submit(j, "infer", X[6:7], 1003, cells=cells)  # inference is not limited
+    assert eng.wait(rid)[0] == HW.REQ_DONE
+    eng.close()
+
+
+def test_submit_shape_checks():
+    """Mis-shaped host arrays are refused in the binding before the C call."""
+    import torch
+    from paper_2403_20190_amd import hwisard as HW
+    sk = torch.zeros(N, dtype=torch.int32, device="cuda")
+    HW.Context(N, NQ, PM).keygen(80, sk)
+    eng = HW.Engine(N, NQ, PM, sk, slots=1, chunk=2, max_s=64, max_cells=4096, arena_bytes=1 << 30)
+    ctx = HW.Context(N, NQ, PM)
+    sh = HW.shape(48, 3, 8, 31)
+    j = eng.add_job(sh, model_buffer(ctx, sh))
+    X = np.zeros((2, 48), np.uint8)
+    for bad in [dict(bits=np.zeros((2, 47), np.uint8), labels=np.zeros((2, 2), np.uint8)),
+                dict(bits=X, labels=np.zeros((2, 1), np.uint8)),
+                dict(bits=X, labels=None)]:
+        with pytest.raises(HW.HwError):
+            eng.submit(j, "train", bad["bits"], 1, labels=bad["labels"])
+    for cells in [None, np.zeros((2, 3, 5), np.uint64), np.zeros((2, 3, 6), np.int32),
+                  np.zeros((2, 6, 3), np.uint64).transpose(0, 2, 1)]:
+        with pytest.raises(HW.HwError):
+            eng.submit(j, "infer", X, 2, cells=cells)
+    eng.close()

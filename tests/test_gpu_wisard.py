@@ -231,6 +231,9 @@ def test_ham_shape_sampled():
     Hg = host_u32(H)
     for j in rams:
         assert np.array_equal(Hg[j], Ho[j]), j
+    cnt_o = np.zeros((2, 3, 4096), np.uint32)  # the balancing counter (Sec. 3.7.1)
+    pair.orc.class_count(pair.l, pair.yo, pair.n, cnt_o)
+    assert np.array_equal(host_u32(cnt), cnt_o)
     W = P.train_integer(pair.X, pair.y, pair.l, pair.a, pair.pi)
     assert np.array_equal(decrypt_model(pair, H), P.expected_model_cells(W, pair.s, pair.l, pair.a, pair.N))
     tb = CL.thermometer(CL.quantize_u8(Xte[:1], 2), 2)

@@ -221,6 +221,28 @@ hw_status hw_wisard_train_encrypted(hw_ctx* ctx, const hw_wisard_shape* shape,
                                     uint64_t n, uint32_t* model_dev, uint32_t* class_count_dev,
                                     hipStream_t stream);
 
+/* Bytes of the fixed device scratch behind hw_wisard_train_encrypted_noalloc. */
+#define HW_NOALLOC_SCRATCH_BYTES (256ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * training as hw_wisard_train_encrypted, same arguments and same bits, but
+ * the call allocates nothing.  Its workspace (the per-sample IVP leaf blocks)
+ * and the device permutation live in a fixed device array of
+ * HW_NOALLOC_SCRATCH_BYTES bytes, which each GPU holds from the first call on
+ * it until the process ends; samples run in sub-batches that fit it.  The
+ * kernels run their settled schedules (forced with hw_tune_set, or chosen by
+ * earlier tuned calls; else the default) and no timing events are recorded.
+ * HW_EINVAL when one sample's workspace plus the permutation exceeds the
+ * array ((k0 + 1)(2^z + 1) RLWE per sample: the tiny, Wisconsin- and
+ * MNIST-shaped sets fit, the HAM-shaped one does not).  Every call on one GPU
+ * shares that GPU's array, so calls whose work overlaps on one GPU race: the
+ * caller serialises them (one stream, or a wait between streams). */
+hw_status hw_wisard_train_encrypted_noalloc(hw_ctx* ctx, const hw_wisard_shape* shape,
+                                            const uint32_t* x_rgsw_dev, const uint32_t* y_rgsw_dev,
+                                            uint64_t n, uint32_t* model_dev, uint32_t* class_count_dev,
+                                            hipStream_t stream);
+
 /* Homomorphic inference, PD-act branch (Alg. 7).  Layout 0: for each
  * sample, RAM j and label c < l, the Vertical Packing (Alg. 3, read as the
  * inverse of the IVP layout) of model row j with the label bits of c in the

@@ -559,7 +559,8 @@ size_t infer_ws_per_sample(const hw_ctx* c, const hw_wisard_shape* sh, const Dim
 
 hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const uint32_t* perm,
                      const uint32_t* x_rgsw, const uint32_t* y_rgsw, uint64_t n, uint32_t* model,
-                     uint32_t* class_count, uint32_t* ws, size_t ws_bytes, hipStream_t st, bool timing) {
+                     uint32_t* class_count, uint32_t* ws, size_t ws_bytes, hipStream_t st, bool timing,
+                     bool tune) {
   const size_t rw = rlwe_words(c);
   uint64_t n_sub = ws_bytes / train_ws_per_sample(c, d);
   if (n_sub < 1) return fail(HW_ENOMEM, "training workspace smaller than one sample");
@@ -609,12 +610,11 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
     A.i0 = i0;
     A.nsub = (uint32_t)m;
     const double xp = (double)m * xp_per_sample;
-    auto lt = [&] {
-      return tuned(c, "train", xp, st, [&](int v) {
-        A.map = (uint32_t)(v & 1);
-        return hw::launch_train(c->logN, c->prm.nq, c->tabs, A, v & 2 ? 4 : 3, st);
-      });
+    auto run = [&](int v) {
+      A.map = (uint32_t)(v & 1);
+      return hw::launch_train(c->logN, c->prm.nq, c->tabs, A, v & 2 ? 4 : 3, st);
     };
+    auto lt = [&] { return tune ? tuned(c, "train", xp, st, run) : run(settled_variant(c, "train")); };
     HIP_TRY(tm ? timed(c, "train", xp, st, lt) : lt());
     R.n_sub = m;
     hw::RowPackArgs P{};

@@ -126,6 +126,15 @@ static hipError_t tuned(hw_ctx* c, const char* kernel, double work, hipStream_t 
   return e;
 }
 
+// the variant `tuned` would settle on without timing anything (no events are
+// created): the forced one, else the tuner's choice, else variant 0
+static int settled_variant(const hw_ctx* c, const char* kernel) {
+  const auto it = c->tune.find(kernel);
+  if (it == c->tune.end()) return 0;
+  if (it->second.forced >= 0) return it->second.forced;
+  return it->second.chosen >= 0 ? it->second.chosen : 0;
+}
+
 // run `launch` between two events on `st` when profiling is on
 template <class F>
 static hipError_t timed(hw_ctx* c, const char* name, double work, hipStream_t st, F&& launch) {
@@ -199,10 +208,12 @@ size_t infer_ws_per_sample(const hw_ctx* c, const hw_wisard_shape* sh, const Dim
 
 // training / inference of n samples with an explicit workspace of ws_bytes
 // (at least one sample's worth) and a resolved device permutation; the
-// arguments are not checked again.  `timing` records per-kernel events.
+// arguments are not checked again.  `timing` records per-kernel events;
+// without `tune` the training kernel runs its settled schedule and no event
+// is created.
 hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const uint32_t* perm,
                      const uint32_t* x, const uint32_t* y, uint64_t n, uint32_t* model, uint32_t* cnt,
-                     uint32_t* ws, size_t ws_bytes, hipStream_t st, bool timing);
+                     uint32_t* ws, size_t ws_bytes, hipStream_t st, bool timing, bool tune = true);
 hw_status infer_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const uint32_t* perm,
                      const uint32_t* model, const uint32_t* x, uint64_t n, uint32_t* scores, uint32_t* sums,
                      uint32_t* ws, size_t ws_bytes, hipStream_t st, bool timing);

@@ -170,6 +170,8 @@ hipError_t launch_ntt(int logN, int nq, const Tabs& T, uint32_t* polys, uint64_t
 hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, const uint32_t* in, uint64_t count,
                      uint32_t* out, hipStream_t st);
 // occ: occupancy target of the external-product kernels, 3 or 4 (4 only for log2 N = 12)
+// the permutation of (s, seed) written to pi[0..s) on the device (one thread)
+hipError_t launch_perm(uint32_t s, uint64_t seed, uint32_t* pi, hipStream_t st);
 hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st);
 hipError_t launch_reduce_model(const Tabs& T, const ReduceArgs& A, hipStream_t st);
 hipError_t launch_row_pack(const Tabs& T, const RowPackArgs& A, hipStream_t st);

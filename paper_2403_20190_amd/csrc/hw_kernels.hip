@@ -51,7 +51,7 @@ __device__ __forceinline__ void draw_pair(uint64_t seed, uint32_t domain, uint64
   d1 = (uint64_t)o.z | ((uint64_t)o.w << 32);
 }
 
-constexpr uint32_t DOM_KEY = 1, DOM_ENC_A = 3, DOM_ENC_E = 4, DOM_ENC_A2 = 5;
+constexpr uint32_t DOM_KEY = 1, DOM_PERM = 2, DOM_ENC_A = 3, DOM_ENC_E = 4, DOM_ENC_A2 = 5;
 
 // the four 32-bit draws 4*blk .. 4*blk+3 of stream (seed, domain)
 __device__ __forceinline__ uint4 draw4(uint64_t seed, uint32_t domain, uint64_t blk) {
@@ -115,6 +115,24 @@ __global__ void k_keygen(uint32_t N, uint64_t seed, int32_t* sk) {
   draw_pair(seed, DOM_KEY, k >> 1, d0, d1);
   const uint64_t w = (k & 1) ? d1 : d0;
   sk[k] = (int32_t)(w % 3) - 1;
+}
+
+// The Fisher-Yates permutation of [0, s) with the generator's PERM stream
+// (the host's make_perm, on the device): for k = s-1 down to 1, swap entries
+// k and j = draw64(seed, PERM, s-1-k) mod (k+1).  One thread: the swaps are
+// sequential, and s is at most a few thousand bits.
+__global__ void k_perm(uint32_t s, uint64_t seed, uint32_t* __restrict__ pi) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (uint32_t k = 0; k < s; ++k) pi[k] = k;
+  for (uint32_t k = s - 1; k >= 1 && k < s; --k) {
+    const uint64_t x = (uint64_t)(s - 1 - k);
+    uint64_t d0, d1;
+    draw_pair(seed, DOM_PERM, x >> 1, d0, d1);
+    const uint32_t j = (uint32_t)(((x & 1) ? d1 : d0) % (uint64_t)(k + 1));
+    const uint32_t t = pi[k];
+    pi[k] = pi[j];
+    pi[j] = t;
+  }
 }
 
 // sk_hat[i] = NTT(s mod q_i), evaluation layout; sk_hat[NQ + i] = its Shoup companions
@@ -1433,6 +1451,12 @@ hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, cons
                                               in + off * rw, out + off * rw, gw));
     return hipGetLastError();
   });
+}
+
+hipError_t launch_perm(uint32_t s, uint64_t seed, uint32_t* pi, hipStream_t st) {
+  if (s == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_perm, dim3(1), dim3(64), 0, st, s, seed, pi);
+  return hipGetLastError();
 }
 
 hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st) {

@@ -72,6 +72,8 @@ class Request(C.Structure):
                 ("n", C.c_uint64), ("enc_seed", C.c_uint64), ("cells_host", C.c_void_p)]
 
 
+NOALLOC_SCRATCH_BYTES = 256 << 20  # HW_NOALLOC_SCRATCH_BYTES
+
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED, REQ_CANCELLED = 0, 1, 2, 3, 4
 
 _vp, _u64, _u32, _i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
@@ -92,6 +94,7 @@ _SIG = {
     "hw_ntt": [_vp, _vp, _u64, _i32, _vp],
     "hw_external_product": [_vp, _vp, _vp, _u64, _vp, _vp],
     "hw_wisard_train_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
+    "hw_wisard_train_encrypted_noalloc": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_wisard_infer_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_rlwe_add": [_vp, _vp, _vp, _u64, _vp],
     "hw_pks_keygen": [_vp, _vp, _u64, _vp, _vp],
@@ -270,6 +273,12 @@ class Context:
     def train(self, sh: Shape, x_rgsw, y_rgsw, n: int, model, class_count=None):
         _check(_lib.hw_wisard_train_encrypted(self._h, C.byref(sh), _ptr(x_rgsw), _ptr(y_rgsw), n, _ptr(model),
                                               _ptr(class_count), _stream()))
+
+    def train_noalloc(self, sh: Shape, x_rgsw, y_rgsw, n: int, model, class_count=None):
+        """train() through the entry point that allocates no device memory
+        (a fixed library-held scratch; see NOALLOC_SCRATCH_BYTES)"""
+        _check(_lib.hw_wisard_train_encrypted_noalloc(self._h, C.byref(sh), _ptr(x_rgsw), _ptr(y_rgsw), n,
+                                                      _ptr(model), _ptr(class_count), _stream()))
 
     @property
     def pks_key_words(self) -> int:

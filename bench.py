@@ -37,7 +37,7 @@ WORKLOADS = {
     "mnist": dict(name="mnist-shaped 28x28x1, 10 classes, therm 3, tuple 12, 1000 train + 1000 test, N=2048 x 2 primes",
                   N=2048, nq=2, p=1024, l=10, a=12, T=3, n_train=1000, n_test=1000, chunk=50, balance=False),
     "ham": dict(name="ham10000-shaped 28x28x3, 7 skewed classes, therm 2, tuple 12, 10000 train + 1000 test, N=4096 x 3 primes",
-                N=4096, nq=3, p=16384, l=7, a=12, T=2, n_train=10000, n_test=1000, chunk=10, balance=True),
+                N=4096, nq=3, p=16384, l=7, a=12, T=2, n_train=10000, n_test=1000, chunk=10, balance=True, cpu_rams=49),
     "wisconsin": dict(name="wisconsin-shaped 30 float features, 2 classes 357/212, therm 16 (480 bits), tuple 8, "
                            "400 train + 169 test, N=2048 x 2 primes",
                       N=2048, nq=2, p=512, l=2, a=8, T=16, n_train=400, n_test=169, chunk=100, balance=False,
@@ -149,6 +149,65 @@ def rgsw_bytes(N: int, nq: int) -> int:
     return 2 * 5 * nq * 2 * nq * N * 4
 
 
+def device_peaks(dev) -> dict:
+    """The device's peak rates measured on this GPU (hw_microbench): a stream
+    triad over three 1 GiB arrays (GB/s) and the lane-instruction rate of the
+    32-bit VALU instructions of the modular arithmetic (T/s)."""
+    from paper_2403_20190_amd import hwisard as HW
+    out = {"triad_gbs": round(HW.microbench("triad", 1 << 30, dev.index or 0)[0] / 1e9, 1)}
+    for k in ("v_add_u32", "v_mul_lo_u32", "v_mul_hi_u32", "v_mad_u64_u32"):
+        out[k + "_tops"] = round(HW.microbench(k, 0, dev.index or 0)[0] / 1e12, 2)
+    return out
+
+
+# A modular multiplication by a precomputed operand (Shoup) issues three
+# 32-bit multiplies: mul_hi for the quotient estimate, mul_lo for the product
+# and one multiply-add (v_mad_u64_u32) with the modulus.
+MUL_PER_MODMUL = 3
+
+
+def xp_roofline(kernel: str, N: int, nq: int, xp: float, ms: float, launches: int, peaks: dict | None,
+                ops: float | None = None) -> dict:
+    """Roofline of a kernel made of external products, in per-product units:
+    each product streams one RGSW ciphertext (16 l nq^2 N bytes, l = 5
+    digits) and performs (2 l nq^2 + 2 nq)(N/2) log2 N + 4 l nq^2 N modular
+    multiplications.  `achieved` = those bytes / time against HBM and those
+    multiplies (MUL_PER_MODMUL int32 multiplies each) / time against the
+    VALU; `bound` is the resource with the larger fraction.  `ops` (the
+    builder's op model of the instructions, optional) is reported beside."""
+    if not ms or not launches:
+        return {"kernel": kernel, "bound": None}
+    sec = ms / 1000.0
+    per_launch = xp / launches
+    gbs = xp * rgsw_bytes(N, nq) / sec / 1e9
+    mm_s = xp * modmul_per_xp(N, nq) / sec
+    mul_t = mm_s * MUL_PER_MODMUL / 1e12
+    hbm = {"achieved_gbs": round(gbs, 1), "peak_gbs": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    valu = {"modmul_per_s": round(mm_s, 1), "int32_mul_per_modmul": MUL_PER_MODMUL,
+            "achieved_tops": round(mul_t, 3), "peak_tops": round(PEAK_INT32_TOPS, 2),
+            "frac": round(mul_t / PEAK_INT32_TOPS, 4)}
+    if peaks:
+        hbm["measured_peak_gbs"] = peaks["triad_gbs"]
+        hbm["frac_of_measured"] = round(gbs / peaks["triad_gbs"], 4)
+        mp = min(peaks["v_mul_lo_u32_tops"], peaks["v_mul_hi_u32_tops"])
+        valu["measured_peak_tops"] = mp
+        valu["frac_of_measured"] = round(mul_t / mp, 4)
+    bound = "hbm" if hbm["frac"] >= valu["frac"] else "alu"
+    r = {"bound": bound, "kernel": kernel}
+    if bound == "hbm":
+        r.update(achieved=hbm["achieved_gbs"], peak=PEAK_HBM_GBS, unit="GB/s", frac=hbm["frac"])
+    else:
+        r.update(achieved=valu["achieved_tops"], peak=round(PEAK_INT32_TOPS, 2), unit="TOPS(int32 mul)",
+                 frac=valu["frac"])
+    r.update(unit_of_work="external product", bytes_per_unit=rgsw_bytes(N, nq),
+             modmul_per_unit=modmul_per_xp(N, nq), units_per_launch=per_launch, launches=launches,
+             avg_launch_ms=round(ms / launches, 3), hbm=hbm, valu=valu)
+    if ops is not None:
+        r["op_model"] = {"int32_ops_per_launch": ops / launches, "achieved_tops": round(ops / sec / 1e12, 3),
+                         "frac": round(ops / sec / 1e12 / PEAK_INT32_TOPS, 4)}
+    return r
+
+
 def gen_data(wl: str, W: dict):
     from paper_2403_20190_amd import synth
     if wl == "wisconsin":
@@ -171,43 +230,153 @@ def levels_of(mod, W: dict, X, ref):
     return mod.quantize_u8(X, W["T"])
 
 
-def cpu_baseline(W: dict, Xtr, ytr, threads: int, seeds: dict, ref=None):
-    """The oracle, as it is, on a bounded sample: client encryption plus
-    homomorphic training of a few training samples (one for the image
-    workloads) over every RAM."""
+def host_info():
+    """host cores the oracle may use and the CPU model"""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "affinity": affinity, "cpu_model": model}
+
+
+# The paper's own CPU timings of encrypted training and evaluation (Table 7,
+# desktop i7-12700K at 5.0 GHz with AVX-512, TFHE torus parameters with one or
+# two digits), quoted as context: other parameters, other hardware.
+PAPER_CPU_CONTEXT = {
+    "mnist": "MNIST_T (1000 train samples, a = 12): training 12m16s on 1 thread, 1m33s on 8 threads "
+             "(10.8 samples/s); evaluation of the test set 2h11m / 19m40s (paper Table 7, i7-12700K)",
+    "ham": "HAM10000_S (1002 train samples, a = 12): training 54m13s on 1 thread, 6m50s on 8 threads "
+           "(paper Table 7, i7-12700K)",
+    "wisconsin": "Wisconsin (about 455 train samples, a = 10): training 11 s on 1 thread, 1436 ms on 8 threads "
+                 "(paper Table 7, i7-12700K)",
+    "tiny": None,
+}
+
+
+def cpu_baseline(wl: str, W: dict, Xtr, ytr, Xte, seeds: dict, ctx, sh, sk_dev, dev, ref=None):
+    """The oracle, as it is, on a bounded sample of the workload, timed on the
+    host's cores (at most 16 threads: the host share of one GPU), and checked
+    bit for bit against the GPU on the same sample:
+
+    * all threads: client encryption of the first m training samples and IVP
+      training of them over every RAM (`cpu_rams` RAMs when set) -> samples/s;
+      the oracle's model is compared with the GPU's model of the same samples;
+    * one thread: the same for one sample over 4 RAMs (the RGSW those RAMs
+      read), extrapolated linearly to all input bits and RAMs -> samples/s;
+    * all threads: inference of the first test sample on the m-sample model
+      over 8 RAMs x every label, extrapolated to all RAMs; the LWE scores are
+      compared with the GPU's scores of the same sample."""
     import numpy as np
+    import torch
 
     import oracle as O
     from oracle import plain as P
+    from paper_2403_20190_amd import client as CL
     N, nq, p, l, a, T = W["N"], W["nq"], W["p"], W["l"], W["a"], W["T"]
     m = W.get("cpu_samples", 1)
+    info = host_info()
+    threads = max(1, min(16, info["affinity"]))
     orc = O.Ctx(N, nq, p)
     bits = P.encode(levels_of(P, W, Xtr[:m], ref), T)
+    tbits = P.encode(levels_of(P, W, Xte[:1], ref), T)
     s = bits.shape[1]
     L = O.ceil_log2(l)
     sk = orc.keygen(seeds["key"])
     pi = O.permutation(seeds["perm"], s)
     k0, k1 = -(-s // a), orc.k1(s, l, a)
+    rams = list(range(min(k0, W.get("cpu_rams") or k0)))
+
+    def tuple_bits(js):
+        return sorted({int(pi[j * a + u]) for j in js for u in range(min(a, s - j * a))})
+
+    # --- all threads: encryption + training of m samples ---------------------------
     t0 = time.perf_counter()
-    xr = {}
-    yr = {}
-
-    def enc_x(ik):
-        i, k = ik
-        xr[ik] = orc.enc_rgsw(sk, int(bits[i, k]), seeds["x"], i * s + k)
-
-    def enc_y(iu):
-        i, u = iu
-        yr[iu] = orc.enc_rgsw(sk, (int(ytr[i]) >> u) & 1, seeds["y"], i * L + u)
-
-    O._parallel(enc_x, [(i, k) for i in range(m) for k in range(s)], threads)
-    O._parallel(enc_y, [(i, u) for i in range(m) for u in range(L)], threads)
+    xr, yr = {}, {}
+    need = tuple_bits(rams)
+    O._parallel(lambda ik: xr.__setitem__(ik, orc.enc_rgsw(sk, int(bits[ik[0], ik[1]]), seeds["x"],
+                                                                 ik[0] * s + ik[1])),
+                [(i, k) for i in range(m) for k in need], threads)
+    O._parallel(lambda iu: yr.__setitem__(iu, orc.enc_rgsw(sk, (int(ytr[iu[0]]) >> iu[1]) & 1, seeds["y"],
+                                                                 iu[0] * L + iu[1])),
+                [(i, u) for i in range(m) for u in range(L)], threads)
+    t_enc_all = time.perf_counter() - t0
     H = np.zeros((k0, k1, 2, nq, N), np.uint32)
-    orc.train(s, l, a, pi, lambda i, k: xr[(i, k)], lambda i, u: yr[(i, u)], m, H, threads=threads)
-    dt = time.perf_counter() - t0
-    return dict(value=m / dt, unit="samples/s", cores=threads, kind="oracle",
-                sample="%d training sample(s): oracle encryption of %d RGSW each + IVP training of all %d RAMs "
-                       "(%.1f s on %d threads)" % (m, s + L, k0, dt, threads))
+    t0 = time.perf_counter()
+    orc.train(s, l, a, pi, lambda i, k: xr[(i, k)], lambda i, u: yr[(i, u)], m, H, rams=rams, threads=threads)
+    t_tr_all = time.perf_counter() - t0
+    dt_all = t_enc_all + t_tr_all
+    # seconds per sample over every input bit and RAM (linear in both)
+    per_sample_all = (t_enc_all * (s + L) / (len(need) + L) + t_tr_all * k0 / len(rams)) / m
+    # --- one thread: one sample, 4 RAMs, extrapolated ----------------------------------
+    r1 = rams[:4]
+    need1 = tuple_bits(r1)
+    t0 = time.perf_counter()
+    x1 = {k: orc.enc_rgsw(sk, int(bits[0, k]), seeds["x"], k) for k in need1}
+    y1 = {u: orc.enc_rgsw(sk, (int(ytr[0]) >> u) & 1, seeds["y"], u) for u in range(L)}
+    t_enc1 = time.perf_counter() - t0
+    H1 = np.zeros((k0, k1, 2, nq, N), np.uint32)
+    t0 = time.perf_counter()
+    orc.train(s, l, a, pi, lambda i, k: x1[k], lambda i, u: y1[u], 1, H1, rams=r1, threads=1)
+    t_tr1 = time.perf_counter() - t0
+    sec_1thr = t_enc1 * (s + L) / (len(need1) + L) + t_tr1 * k0 / len(r1)
+    # --- all threads: inference of one test sample, 8 RAMs x every label ---------------
+    ri = rams[:8]
+    needi = tuple_bits(ri)
+    t0 = time.perf_counter()
+    xt = {}
+    O._parallel(lambda k: xt.__setitem__(k, orc.enc_rgsw(sk, int(tbits[0, k]), seeds["xt"], k)), needi, threads)
+    t_enci = time.perf_counter() - t0
+    out_o = {}
+    t0 = time.perf_counter()
+    O._parallel(lambda jc: out_o.__setitem__(jc, orc.infer_one(s, l, a, pi, H, lambda k: xt[k], jc[0], jc[1])),
+                [(j, c) for j in ri for c in range(l)], threads)
+    t_inf = time.perf_counter() - t0
+    sec_inf = t_enci * s / len(needi) + t_inf * k0 / len(ri)
+    # --- the GPU on the same samples ----------------------------------------------------
+    xb = torch.from_numpy(CL.thermometer(levels_of(CL, W, Xtr[:m], ref), T)).to(dev)
+    yb = torch.from_numpy(CL.label_bits(ytr[:m], l)).to(dev)
+    gx = torch.empty(m * s, ctx.rgsw_words, dtype=torch.int32, device=dev)
+    gy = torch.empty(max(1, m * L), ctx.rgsw_words, dtype=torch.int32, device=dev)
+    ctx.encrypt_rgsw_bits(sk_dev, xb.reshape(-1), seeds["x"], 0, gx)
+    if L:
+        ctx.encrypt_rgsw_bits(sk_dev, yb.reshape(-1), seeds["y"], 0, gy)
+    Hg = torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev)
+    ctx.train(sh, gx, gy, m, Hg, None)
+    del gx, gy
+    tx = torch.from_numpy(CL.thermometer(levels_of(CL, W, Xte[:1], ref), T)).to(dev)
+    gt = torch.empty(s, ctx.rgsw_words, dtype=torch.int32, device=dev)
+    ctx.encrypt_rgsw_bits(sk_dev, tx.reshape(-1), seeds["xt"], 0, gt)
+    sc = torch.empty(1, l, k0, ctx.lwe_words, dtype=torch.int32, device=dev)
+    ctx.infer(sh, Hg, gt, 1, sc, None)
+    torch.cuda.synchronize()
+    Hh = Hg.cpu().numpy().view(np.uint32)
+    sch = sc.cpu().numpy().view(np.uint32).reshape(l, k0, nq, N + 1)
+    del Hg, gt, sc
+    train_equal = bool(np.array_equal(Hh[rams], H[rams]))
+    infer_equal = all(np.array_equal(sch[c, j], out_o[(j, c)]) for j in ri for c in range(l))
+    return dict(
+        value=round(1.0 / per_sample_all, 5), unit="samples/s", cores=threads, kind="oracle",
+        sample="%d training sample(s): oracle encryption of the RGSW of %d input bits + %d label bits and IVP "
+               "training of %d of %d RAMs, %.1f s on %d threads%s" % (
+                   m, len(need), L, len(rams), k0, dt_all, threads,
+                   "" if len(rams) == k0 else " (extrapolated to all RAMs)"),
+        one_thread_samples_per_s=round(1.0 / sec_1thr, 6),
+        one_thread_sample="1 sample, RGSW of %d input bits + %d label bits, 4 RAMs: %.1f s encryption + %.1f s "
+                          "training on 1 thread, extrapolated to %d bits and %d RAMs" % (
+                              len(need1), L, t_enc1, t_tr1, s + L, k0),
+        infer_samples_per_s=round(1.0 / sec_inf, 5),
+        infer_sample="1 test sample, %d RAMs x %d labels: %.1f s encryption + %.1f s VP on %d threads, "
+                     "extrapolated to %d RAMs" % (len(ri), l, t_enci, t_inf, threads, k0),
+        bit_exact={"train_model_rams": train_equal, "infer_scores": infer_equal},
+        host=info, paper_context=PAPER_CPU_CONTEXT.get(wl))
 
 
 def main():
@@ -220,6 +389,11 @@ def main():
     ap.add_argument("--chunk", type=int, default=None, help="samples encrypted and trained per call")
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serial", action="store_true",
+                    help="encrypt and train on one stream (default: encryption of the next chunk overlaps training)")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the device peak probes")
+    ap.add_argument("--force", action="append", default=[], metavar="KERNEL=VARIANT",
+                    help="force a schedule variant of a tuned kernel (hw_tune_set), e.g. train=3")
     ap.add_argument("--calib-copy", type=int, default=0, help="also run a plain device copy of this many MiB")
     ap.add_argument("--batched-scale", type=float, nargs="*", default=[1.0 / 64, 1.0 / 512],
                     help="job sizes of the 256-job batched workload are scaled by these factors")
@@ -260,6 +434,9 @@ def main():
     L = CL.ceil_log2(l)
     lab_tr = CL.label_bits(ytr, l)
     ctx = HW.Context(N, nq, p)
+    for f in args.force:
+        kname, var = f.split("=")
+        ctx.tune_set(kname, int(var))
     sh = HW.shape(s, l, a, seeds["perm"])
     k0, k1, model_bytes = ctx.dims(sh)
     dev = torch.device("cuda:0")
@@ -269,23 +446,40 @@ def main():
     sk = torch.zeros(N, dtype=torch.int32, device=dev)
     ctx.keygen(seeds["key"], sk)
     chunk = W["chunk"]
-    xr = torch.empty(chunk * s, ctx.rgsw_words, dtype=torch.int32, device=dev)
-    yr = torch.empty(max(1, chunk * L), ctx.rgsw_words, dtype=torch.int32, device=dev)
+    # two chunk buffers: the client encrypts chunk k+1 on its own stream while
+    # the server trains chunk k (both streams at the default priority)
+    nbuf = 1 if args.serial else 2
+    xr = [torch.empty(chunk * s, ctx.rgsw_words, dtype=torch.int32, device=dev) for _ in range(nbuf)]
+    yr = [torch.empty(max(1, chunk * L), ctx.rgsw_words, dtype=torch.int32, device=dev) for _ in range(nbuf)]
     H = torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev)
     cnt = torch.zeros(2, nq, N, dtype=torch.int32, device=dev) if W["balance"] else None
+    s_train = torch.cuda.current_stream(dev)
+    s_enc = s_train if args.serial else torch.cuda.Stream(device=dev)
 
     def train_step():
         H.zero_()
         if cnt is not None:
             cnt.zero_()
         prog = Progress("training samples", n)
-        for c0 in range(0, n, chunk):
+        free = [None] * nbuf  # event: the training that last read buffer b is done
+        s_enc.wait_stream(s_train)
+        for idx, c0 in enumerate(range(0, n, chunk)):
             m = min(chunk, n - c0)
-            ctx.encrypt_rgsw_bits(sk, xb[c0:c0 + m].reshape(-1), seeds["x"], c0 * s, xr[:m * s])
-            if L:
-                ctx.encrypt_rgsw_bits(sk, yb[c0:c0 + m].reshape(-1), seeds["y"], c0 * L, yr[:m * L])
-            ctx.train(sh, xr, yr, m, H, cnt)
+            b = idx % nbuf
+            with torch.cuda.stream(s_enc):
+                if free[b] is not None:
+                    s_enc.wait_event(free[b])
+                ctx.encrypt_rgsw_bits(sk, xb[c0:c0 + m].reshape(-1), seeds["x"], c0 * s, xr[b][:m * s])
+                if L:
+                    ctx.encrypt_rgsw_bits(sk, yb[c0:c0 + m].reshape(-1), seeds["y"], c0 * L, yr[b][:m * L])
+                enc_done = torch.cuda.Event()
+                enc_done.record(s_enc)
+            s_train.wait_event(enc_done)
+            ctx.train(sh, xr[b], yr[b], m, H, cnt)
+            free[b] = torch.cuda.Event()
+            free[b].record(s_train)
             prog(c0 + m)
+        s_train.wait_stream(s_enc)
 
     print("bench: workload %s, n_train %d, chunk %d, k0 %d, k1 %d" % (args.workload, n, chunk, k0, k1),
           file=sys.stderr, flush=True)
@@ -343,17 +537,18 @@ def main():
     }
     # IVP chains per step: every (sample, RAM) plus the class counter's (label bits only)
     ivps = args.steps * steps_ivps
-    a_ops = train_ops(N, nq, tr_xp, ivps) / (tr_ms / 1000.0) / 1e12 if tr_launch else 0.0
-    result["roofline"] = {
-        "bound": "alu", "kernel": "k_train", "achieved": round(a_ops, 3), "peak": round(PEAK_INT32_TOPS, 2),
-        "unit": "TOPS(int32)", "frac": round(a_ops / PEAK_INT32_TOPS, 4),
-        "traffic": measured_traffic() if args.workload == "mnist" and chunk == 50 else None,
-        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)",
-        "launches": tr_launch, "avg_launch_ms": round(tr_ms / max(1, tr_launch), 3),
-        "xp_per_launch": tr_xp / max(1, tr_launch), "ops_per_xp": opx,
-        "ops_per_launch": train_ops(N, nq, tr_xp, ivps) / max(1, tr_launch), "ops_first_xp": ops_first_xp(N, nq),
-    }
+    peaks = None if args.no_peaks else device_peaks(dev)
+    result["roofline"] = xp_roofline("k_train", N, nq, tr_xp, tr_ms, tr_launch, peaks,
+                                     ops=train_ops(N, nq, tr_xp, ivps))
+    result["roofline"]["traffic"] = measured_traffic() if args.workload == "mnist" and chunk == 50 else None
+    result["roofline"]["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"
+    result["roofline"]["first_xp_of_chain"] = ("one product in %d reads half its RGSW (no forward transforms)"
+                                               % round(steps_xp / steps_ivps))
+    result["device_peaks"] = peaks
     result["kernels"] = {
+        # with encryption on its own stream the step takes less than the sum of its kernels
+        "overlap": "serial" if args.serial else "encryption of chunk k+1 on a second stream while chunk k trains",
+        "kernel_sum_ms_per_step": round((tr_ms + rd_ms + en_ms) / args.steps, 2),
         "train_ms_per_step": round(train_kernel_ms, 2),
         "reduce_ms_per_step": round(rd_ms / args.steps, 2),
         # k_reduce_model reads every sample's leaf block once: bytes / time
@@ -382,8 +577,8 @@ def main():
     del xr, yr, xb, yb
     torch.cuda.empty_cache()
     if not args.no_extras:
-        result["inference"], cells0 = infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev)
-        result["class_packed"] = packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev)
+        result["inference"], cells0 = infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev, peaks)
+        result["class_packed"] = packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev, peaks)
         result["merge"] = merge_pass(ctx, H, k0, k1)
         result["ntt"] = ntt_pass(ctx, N, nq, dev)
         result["hbm_copy_gbs"] = hbm_copy(dev)
@@ -394,7 +589,7 @@ def main():
     if not args.no_extras:
         result["schedule"] = ctx.schedule()
     if not args.no_cpu_baseline and not args.no_extras:
-        result["cpu_baseline"] = cpu_baseline(W, Xtr, ytr, min(16, os.cpu_count() or 1), seeds, ref)
+        result["cpu_baseline"] = cpu_baseline(args.workload, W, Xtr, ytr, Xte, seeds, ctx, sh, sk, dev, ref)
     print(json.dumps(result), flush=True)
 
 
@@ -428,10 +623,10 @@ def infer_loop(ctx, sh, H, sk, bits, W, seeds, k0, dev):
     dt = time.perf_counter() - t0
     inf_ms, inf_launch, inf_xp = ctx.profile_read("infer")
     ctx.profile(False)
-    return cells, dt, inf_ms, inf_xp, scores
+    return cells, dt, inf_ms, inf_xp, scores, inf_launch
 
 
-def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
+def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev, peaks=None):
     """Encrypted inference of the test set (device encryption + VP + PD-act)."""
     import numpy as np
     import torch
@@ -441,7 +636,7 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
     bits = CL.thermometer(levels_of(CL, W, Xte[:W["n_test"]], W.get("ref")), T)
     nt = len(bits)
     chunk = max(1, W["chunk"])
-    cells, dt, inf_ms, inf_xp, scores = infer_loop(ctx, sh, H, sk, bits, W, seeds, k0, dev)
+    cells, dt, inf_ms, inf_xp, scores, inf_launch = infer_loop(ctx, sh, H, sk, bits, W, seeds, k0, dev)
     # PackingKeySwitching of the last chunk's scores: l k0 LWE -> one RLWE per
     # sample (when l k0 <= N), decrypting to the same cells
     packed = None
@@ -468,20 +663,17 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev):
     pred = CL.pd_act_predict(cells, "bin")
     acc = float((pred == np.asarray(yte[:nt])).mean())
     N, nq = ctx.N, ctx.nq
-    tops = inf_xp * ops_per_xp(N, nq) / (inf_ms / 1000.0) / 1e12 if inf_ms else 0.0
     return {
         "samples_per_s": round(nt / dt, 3),
         "infer_kernel_samples_per_s": round(nt / (inf_ms / 1000.0), 3) if inf_ms else None,
         "xp_per_s": round(inf_xp / (inf_ms / 1000.0), 1) if inf_ms else None,
-        "roofline": {"bound": "alu", "kernel": "k_infer", "achieved": round(tops, 3),
-                     "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOPS(int32)",
-                     "frac": round(tops / PEAK_INT32_TOPS, 4)},
+        "roofline": xp_roofline("k_infer", N, nq, inf_xp, inf_ms, inf_launch, peaks, ops=inf_xp * ops_per_xp(N, nq)),
         "n_test": nt, "pd_act": "bin", "test_accuracy": round(acc, 4),
         "packing": packed,
     }, cells
 
 
-def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev):
+def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev, peaks=None):
     """The class-packed model layout (horizontal packing across
     discriminators) on the same data and key: training with the index [tuple
     bits, label bits] (every tree leaf kept), then inference by one VP per
@@ -515,16 +707,15 @@ def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev):
         ctx.train(sh, xr, yr, m, H, None)
         prog(c0 + m)
     torch.cuda.synchronize()
-    tr_ms, _, tr_xp = ctx.profile_read("train")
+    tr_ms, tr_launch, tr_xp = ctx.profile_read("train")
     rd_ms, _, _ = ctx.profile_read("reduce")
     ctx.profile(False)
-    tr_tops = train_ops(N, nq, tr_xp, n * k0) / (tr_ms / 1000.0) / 1e12 if tr_ms else 0.0
     del xr, yr, xb, yb
     bits = CL.thermometer(levels_of(CL, W, Xte[:W["n_test"]], W.get("ref")), T)
     nt = len(bits)
     # untimed: the online tuner's first launches try every schedule of this launch shape
     infer_loop(ctx, sh, H, sk, bits[:8 * W["chunk"]], W, seeds, k0, dev)
-    cells, dt, inf_ms, inf_xp, _ = infer_loop(ctx, sh, H, sk, bits, W, seeds, k0, dev)
+    cells, dt, inf_ms, inf_xp, _, inf_launch = infer_loop(ctx, sh, H, sk, bits, W, seeds, k0, dev)
     # several small RAMs per row (layout 2) when a RAM fills less than half an RLWE
     ram_packed = None
     sh2 = HW.shape(s, l, a, seeds["perm"], HW.LAYOUT_RAM_PACKED)
@@ -533,7 +724,7 @@ def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev):
         _, _, bytes2 = ctx.dims(sh2)
         H2 = torch.empty(rows, 1, 2, nq, N, dtype=torch.int32, device=dev)
         ctx.pack_rams(sh2, H, H2)
-        cells2, dt2, inf2_ms, _, _ = infer_loop(ctx, sh2, H2, sk, bits, W, seeds, k0, dev)
+        cells2, dt2, inf2_ms, _, _, _ = infer_loop(ctx, sh2, H2, sk, bits, W, seeds, k0, dev)
         ram_packed = {"rams_per_row": rpr, "rows": rows, "model_mib": round(bytes2 / 2**20, 2),
                       "infer_samples_per_s": round(nt / dt2, 3),
                       "infer_kernel_samples_per_s": round(nt / (inf2_ms / 1000.0), 3) if inf2_ms else None,
@@ -541,20 +732,18 @@ def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev):
         del H2
     del H
     torch.cuda.empty_cache()
-    opx = ops_per_xp(N, nq)
-    tops = inf_xp * opx / (inf_ms / 1000.0) / 1e12 if inf_ms else 0.0
     return {
         "k1": k1, "model_mib": round(model_bytes / 2**20, 1),
         "train_kernel_samples_per_s": round(n / (tr_ms / 1000.0), 3) if tr_ms else None,
         "train_xp_per_sample": round(tr_xp / n, 1),
-        "train_frac": round(tr_tops / PEAK_INT32_TOPS, 4),
+        "train_roofline": xp_roofline("k_train (class-packed)", N, nq, tr_xp, tr_ms, tr_launch, peaks,
+                                      ops=train_ops(N, nq, tr_xp, n * k0)),
         "reduce_ms": round(rd_ms, 2),
         "infer_samples_per_s": round(nt / dt, 3),
         "infer_kernel_samples_per_s": round(nt / (inf_ms / 1000.0), 3) if inf_ms else None,
         "infer_xp_per_sample": round(inf_xp / nt, 1),
-        "infer_roofline": {"bound": "alu", "kernel": "k_infer (class-packed)", "achieved": round(tops, 3),
-                           "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOPS(int32)",
-                           "frac": round(tops / PEAK_INT32_TOPS, 4)},
+        "infer_roofline": xp_roofline("k_infer (class-packed)", N, nq, inf_xp, inf_ms, inf_launch, peaks,
+                                      ops=inf_xp * ops_per_xp(N, nq)),
         "scores_equal_label_pruned": bool(np.array_equal(cells, cells0)),
         "several_rams_per_row": ram_packed,
     }
@@ -635,7 +824,8 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     for j, J in enumerate(jobs):
         groups.setdefault(J["N"], []).append((j, J))
     out = {"jobs": len(jobs), "scale": scale, "samples": 0, "xp": 0.0, "batched_ms": 0.0, "single_ms": 0.0,
-           "plan_ms": 0.0, "plan_max_pieces": 0, "kernel_ms": {}, "ops": 0.0, "bit_identical": True}
+           "plan_ms": 0.0, "plan_max_pieces": 0, "kernel_ms": {}, "ops": 0.0, "bytes": 0.0, "modmul": 0.0,
+           "bit_identical": True}
     for N, members in sorted(groups.items()):
         nq = 2 if N == 2048 else 3
         ctx = HW.Context(N, nq, 4096)
@@ -690,6 +880,8 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
             xpb = ctx.profile_read("train_batch")[2]
             out["xp"] += xpb
             out["ops"] += train_ops(N, nq, xpb, sum(b[3] * b[4] for b in bufs))
+            out["bytes"] += xpb * rgsw_bytes(N, nq)
+            out["modmul"] += xpb * modmul_per_xp(N, nq)
             for k in ("train_batch", "reduce_batch", "train", "reduce", "batch_plan"):
                 out["kernel_ms"][k] = out["kernel_ms"].get(k, 0.0) + ctx.profile_read(k)[0]
             ctx.profile(False)
@@ -713,15 +905,18 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     out["batched_samples_per_s"] = round(out["samples"] / (out["batched_ms"] / 1000.0), 2)
     out["single_job_samples_per_s"] = round(out["samples"] / (out["single_ms"] / 1000.0), 2)
     out["batched_xp_per_s"] = round(out["xp"] / (out["batched_ms"] / 1000.0), 1)
-    # k_train_batch against the int32 peak: external products of each ring
-    # degree x that degree's op model / the persistent kernel's time
+    # k_train_batch in per-product units (each ring degree's RGSW bytes and
+    # modular multiplications) over the persistent kernel's time
     tb = out["kernel_ms"].get("train_batch", 0.0)
     if tb:
-        tops = out["ops"] / (tb / 1000.0) / 1e12
-        out["roofline"] = {"bound": "alu", "kernel": "k_train_batch", "achieved": round(tops, 3),
-                           "peak": round(PEAK_INT32_TOPS, 2), "unit": "TOPS(int32)",
-                           "frac": round(tops / PEAK_INT32_TOPS, 4)}
-    del out["ops"]
+        sec = tb / 1000.0
+        hf = out["bytes"] / sec / 1e9 / PEAK_HBM_GBS
+        vf = out["modmul"] * MUL_PER_MODMUL / sec / 1e12 / PEAK_INT32_TOPS
+        out["roofline"] = {"kernel": "k_train_batch", "bound": "hbm" if hf >= vf else "alu",
+                           "hbm_gbs": round(out["bytes"] / sec / 1e9, 1), "hbm_frac": round(hf, 4),
+                           "modmul_per_s": round(out["modmul"] / sec, 1), "valu_frac": round(vf, 4),
+                           "op_model_frac": round(out["ops"] / sec / 1e12 / PEAK_INT32_TOPS, 4)}
+    del out["ops"], out["bytes"], out["modmul"]
     out["speedup"] = round(out["single_ms"] / out["batched_ms"], 3)
     out["plan_speedup"] = round(out["single_ms"] / out["plan_ms"], 3)
     out["batched_ms"] = round(out["batched_ms"], 1)

@@ -298,6 +298,18 @@ uint32_t live_rows(uint32_t z, uint32_t L, uint32_t l) { return z >= L ? l << (z
 
 // external products of one IVP over nb index bits: the rotation chain and
 // the live tree nodes (one split per live leaf beyond the first)
+// live splits of tree level lev (< z) of an IVP: nodes j < 2^lev that lead to
+// a class below l and whose new branch j + 2^lev does too (node_live of the
+// kernels; with L = 0 every node is live)
+uint32_t live_splits(uint32_t lev, uint32_t z, uint32_t L, uint32_t l) {
+  if (lev >= z) return 0;
+  auto live = [&](uint32_t u) { return z < L || (u & ((1u << L) - 1u)) < l; };
+  const uint32_t n = 1u << lev;
+  uint32_t c = 0;
+  for (uint32_t j = 0; j < n; ++j) c += live(j) && live(j + n);
+  return c;
+}
+
 uint32_t ivp_xp(uint32_t nb, int logN, uint32_t L, uint32_t l) {
   const uint32_t nr = std::min(nb, (uint32_t)logN);
   return nr + live_rows(nb - nr, L, l) - 1;
@@ -600,19 +612,35 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   A.nram = nram;
   // external products per sample: the rotation chain and the live CDEMUX tree of every RAM
   double xp_per_sample = 0;
+  std::vector<uint32_t> smax;  // per tree level: the most live splits any RAM has there
   for (uint32_t j = 0; j < nram; ++j) {
     const uint32_t nb = j < d.k0 ? d.L + std::min(sh->a, sh->s - j * sh->a) : d.L;
     xp_per_sample += ivp_xp(nb, c->logN, d.pL, d.pl);
+    const uint32_t z = nb - std::min(nb, (uint32_t)c->logN);
+    if (z > smax.size()) smax.resize(z, 0);
+    for (uint32_t lev = 0; lev < z; ++lev) smax[lev] = std::max(smax[lev], live_splits(lev, z, d.pL, d.pl));
   }
+  // staging the levels launches (splits of the widest level) x samples x RAMs workgroups
+  const bool can_stage = smax.empty() || *std::max_element(smax.begin(), smax.end()) <= 4096;
   const bool tm = timing && c->prof;
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
     const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
     A.i0 = i0;
     A.nsub = (uint32_t)m;
     const double xp = (double)m * xp_per_sample;
+    // variant v: bit 0 grid order, bit 1 tree levels staged (one launch per
+    // level after the chains), bit 2 occupancy target 4
     auto run = [&](int v) {
       A.map = (uint32_t)(v & 1);
-      return hw::launch_train(c->logN, c->prm.nq, c->tabs, A, v & 2 ? 4 : 3, st);
+      const int occ = v & 4 ? 4 : 3;
+      A.tree = (v & 2) && can_stage ? 0u : 1u;
+      hipError_t e = hw::launch_train(c->logN, c->prm.nq, c->tabs, A, occ, st);
+      for (uint32_t lev = 0; e == hipSuccess && !A.tree && lev < smax.size(); ++lev) {
+        A.lev = lev;
+        A.smax = smax[lev];
+        e = hw::launch_train_level(c->logN, c->prm.nq, c->tabs, A, occ, st);
+      }
+      return e;
     };
     auto lt = [&] { return tune ? tuned(c, "train", xp, st, run) : run(settled_variant(c, "train")); };
     HIP_TRY(tm ? timed(c, "train", xp, st, lt) : lt());
@@ -1150,12 +1178,14 @@ struct TuneKernel {
   double min_work;  // launches with less work (too few workgroups to fill the chip) are not timed
   std::vector<const char*> variants;
 };
-// variants past the first two of "train" / "infer" and past the first of
-// "train_batch" (occupancy target 4) exist for N = 4096 only
+// variants past the first four of "train", the first two of "infer" and the
+// first of "train_batch" (occupancy target 4) exist for N = 4096 only
 const std::vector<TuneKernel>& tune_table() {
   static const std::vector<TuneKernel> t = {
-      {"train", 5e4, {"ram-major 2-D grid", "xcd-grouped 1-D grid", "ram-major 2-D grid, 4 waves/SIMD",
-                      "xcd-grouped 1-D grid, 4 waves/SIMD"}},
+      {"train", 5e4, {"ram-major 2-D grid", "xcd-grouped 1-D grid", "ram-major 2-D grid, tree levels staged",
+                      "xcd-grouped 1-D grid, tree levels staged", "ram-major 2-D grid, 4 waves/SIMD",
+                      "xcd-grouped 1-D grid, 4 waves/SIMD", "ram-major 2-D grid, tree levels staged, 4 waves/SIMD",
+                      "xcd-grouped 1-D grid, tree levels staged, 4 waves/SIMD"}},
       {"infer", 5e4, {"ram-major 3-D grid", "labels-adjacent xcd-grouped 1-D grid",
                       "ram-major 3-D grid, 4 waves/SIMD", "labels-adjacent xcd-grouped 1-D grid, 4 waves/SIMD"}},
       {"train_batch", 5e4, {"persistent, 3 waves/SIMD", "persistent, 4 waves/SIMD"}},
@@ -1181,7 +1211,8 @@ static int table_variants(const char* kernel) {
 int tune_variants(const hw_ctx* c, const char* kernel) {
   const int n = table_variants(kernel);
   if (c->logN == 12) return n;
-  if (!strcmp(kernel, "train") || !strcmp(kernel, "infer")) return 2;
+  if (!strcmp(kernel, "train")) return 4;
+  if (!strcmp(kernel, "infer")) return 2;
   if (!strcmp(kernel, "train_batch") || !strcmp(kernel, "infer_batch")) return 1;
   return n;
 }

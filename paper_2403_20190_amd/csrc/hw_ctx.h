@@ -169,6 +169,7 @@ struct Dims {
 
 uint32_t live_rows(uint32_t z, uint32_t L, uint32_t l);
 uint32_t ivp_xp(uint32_t nb, int logN, uint32_t L, uint32_t l);
+uint32_t live_splits(uint32_t lev, uint32_t z, uint32_t L, uint32_t l);
 uint32_t infer_slots(const Dims& d);
 double infer_xp_per_sample(const hw_ctx* c, const hw_wisard_shape* sh, const Dims& d);
 

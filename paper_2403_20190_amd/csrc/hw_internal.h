@@ -43,6 +43,8 @@ struct TrainArgs {
   uint32_t nram, nsub;      // grid: nram RAM items (k0, + 1 for the counter) x nsub samples
   uint32_t map;             // 0: 2-D grid (RAM, sample); 1: 1-D, XCD-grouped
   uint32_t layout;          // model layout: 0 label-pruned rows, 1 class-packed rows
+  uint32_t tree;            // k_train: 1 runs the CDEMUX tree in the chain's workgroup, 0 the chain only
+  uint32_t lev, smax;       // k_train_level: the tree level and the most live splits a RAM has at it
 };
 
 struct ReduceArgs {
@@ -173,6 +175,9 @@ hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, cons
 // the permutation of (s, seed) written to pi[0..s) on the device (one thread)
 hipError_t launch_perm(uint32_t s, uint64_t seed, uint32_t* pi, hipStream_t st);
 hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st);
+// one CDEMUX level of every (sample, RAM) of a sub-batch whose chains k_train
+// (A.tree = 0) has run: A.nram x A.nsub x A.smax workgroups, one split each
+hipError_t launch_train_level(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st);
 hipError_t launch_reduce_model(const Tabs& T, const ReduceArgs& A, hipStream_t st);
 hipError_t launch_row_pack(const Tabs& T, const RowPackArgs& A, hipStream_t st);
 hipError_t batch_grid(int logN, int nq, int occ, uint32_t* grid);  // persistent workgroups that fit the device

@@ -663,8 +663,9 @@ __device__ __forceinline__ void acc_rlwe(const Tabs& T, uint32_t* __restrict__ d
 }
 
 // IVP of one (sample, RAM) into its block: acc = (0, Delta), the rotation
-// chain over bits z..nb-1, then the CDEMUX tree over bits 0..z-1 creating
-// only the live nodes (a split whose new branch is not live is skipped).
+// chain over bits z..nb-1, then (when `tree`) the CDEMUX tree over bits
+// 0..z-1 creating only the live nodes (a split whose new branch is not live
+// is skipped).
 // bit(u) returns the RGSW of bit u of the IVP index; the index has L label
 // bits and l classes.  Without `dest` leaf d is left in slot d.  With
 // `dest`, live leaf d goes to dest[leaf_row(d)] instead: stored when
@@ -673,7 +674,7 @@ template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>(), class BitFn>
 __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ slot0, uint32_t* __restrict__ xin,
                                           uint32_t nb, uint32_t L, uint32_t l, BitFn&& bit, uint32_t* lds,
                                           uint2* twl, uint32_t t, uint32_t* __restrict__ dest = nullptr,
-                                          bool store = false) {
+                                          bool store = false, bool tree = true) {
   constexpr int N = 1 << LOGN, TT = N / 8;
   constexpr size_t RW = (size_t)2 * NQ * N;
   const uint32_t nr = nb < (uint32_t)LOGN ? nb : (uint32_t)LOGN;
@@ -692,6 +693,7 @@ __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ 
   }
 #pragma unroll 1
   for (uint32_t st = 1; st < nr; ++st) cmux_rot<LOGN, NQ, PR>(T, slot0, 1 << st, bit(z + st), xin, lds, twl, xc, t);
+  if (!tree) return;
 #pragma unroll 1
   for (uint32_t lev = 0; lev < z; ++lev) {
     const uint32_t* C = bit(lev);
@@ -780,7 +782,63 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
                         return index_bit(A.layout, u, nb, A.L, A.x_rgsw, A.y_rgsw, A.perm, gi, A.s, ram, A.a,
                                          A.rgsw_words);
                       },
-                      lds, twl, t);
+                      lds, twl, t, nullptr, false, A.tree != 0);
+}
+
+// One level of the CDEMUX tree for a whole sub-batch, after k_train has run
+// the chains alone (A.tree = 0): one workgroup per (sample, RAM, live split
+// at level A.lev).  The splits of a level all use the RGSW of bit A.lev: the
+// label bits' are shared by every RAM of a sample (layout 0), a tuple bit's
+// by the splits of one (sample, RAM).  Items are numbered (sample, RAM,
+// split) with the split fastest and each XCD (workgroup id mod 8) takes a
+// contiguous eighth of them, so the workgroups that read one RGSW run
+// side by side on one XCD and share its L2, where the chain's workgroup
+// would stream that RGSW once per node.  Split j of node j (slot j) writes
+// h = C [.] slot j to slot j + 2^lev, then slot j -= h: the bits of the
+// in-workgroup tree (XP_DEMUX), with no input copy (ext_prod reads every
+// input coefficient before the subtraction, each thread its own).
+template <int LOGN, int NQ, int OCC>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_train_level(
+    Tabs T, TrainArgs A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, xp_pair<LOGN, NQ>()>()];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  constexpr size_t RW = (size_t)2 * NQ * N;
+  const uint32_t t = threadIdx.x;
+  const uint64_t G = (uint64_t)A.nram * A.nsub * A.smax, per = (G + 7) >> 3;
+  const uint64_t it = (uint64_t)(blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+  if (it >= G) return;
+  const uint32_t sp = (uint32_t)(it % A.smax);
+  const uint64_t rs = it / A.smax;
+  const uint32_t ram = (uint32_t)(rs % A.nram), smp = (uint32_t)(rs / A.nram);
+  const uint32_t nb = ram_bits(ram, A.k0, A.s, A.a, A.L);
+  const uint32_t z = nb - (nb < (uint32_t)LOGN ? nb : (uint32_t)LOGN);
+  if (A.lev >= z) return;
+  const uint32_t n = 1u << A.lev, tL = tree_L(A.layout, A.L), tl = tree_l(A.layout, A.l);
+  uint32_t j = 0, c = 0;  // the sp-th live split of the level (uniform over the workgroup)
+  for (; j < n; ++j)
+    if (node_live(j, z, tL, tl) && node_live(j + n, z, tL, tl)) {
+      if (c == sp) break;
+      ++c;
+    }
+  if (j == n) return;
+  const uint64_t gi = A.i0 + smp;
+  uint32_t* slot0 = A.out + ((size_t)smp * (A.k0 + 1) + ram) * (A.kt + 1) * RW;
+  uint32_t* sj = slot0 + (size_t)j * RW;
+  uint32_t* sn = slot0 + (size_t)(j + n) * RW;
+  const uint32_t* C = index_bit(A.layout, A.lev, nb, A.L, A.x_rgsw, A.y_rgsw, A.perm, gi, A.s, ram, A.a,
+                                A.rgsw_words);
+  uint32_t xc = 0;
+  ext_prod<LOGN, NQ>(sj, C, T, lds, twl, xc, t, XpOut{sn, nullptr, nullptr, XP_STORE});
+#pragma unroll 1
+  for (int w = 0; w < 2 * NQ; ++w) {
+    const uint32_t q = T.pt[w % NQ].q;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const size_t k = (size_t)w * N + TT * e + t;
+      sj[k] = subq(sj[k], sn[k], q);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1466,6 +1524,16 @@ hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, int
   const dim3 grid = A.map == 0 ? dim3(A.nram, A.nsub) : dim3((uint32_t)((G + 7) / 8 * 8));
   HW_DISPATCH_OCC(logN, nq, occ,
                   hipLaunchKernelGGL((k_train<LN, NQ, OC>), grid, dim3(Geo<LN>::T), 0, st, T, A));
+  return hipGetLastError();
+}
+
+hipError_t launch_train_level(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st) {
+  const uint64_t G = (uint64_t)A.nram * A.nsub * A.smax;
+  if (G == 0) return hipSuccess;
+  if (G > (1ull << 30)) return hipErrorInvalidValue;
+  const dim3 grid((uint32_t)((G + 7) / 8 * 8));
+  HW_DISPATCH_OCC(logN, nq, occ,
+                  hipLaunchKernelGGL((k_train_level<LN, NQ, OC>), grid, dim3(Geo<LN>::T), 0, st, T, A));
   return hipGetLastError();
 }
 

@@ -50,7 +50,7 @@ def test_host_only_calls():
 def test_tune_variant_names():
     """The tuned kernels and their variant tables (host only)."""
     from paper_2403_20190_amd import hwisard as HW
-    counts = {"train": 4, "infer": 4, "train_batch": 2, "infer_batch": 2, "ntt": 4, "ntt_inverse": 4,
+    counts = {"train": 8, "infer": 4, "train_batch": 2, "infer_batch": 2, "ntt": 4, "ntt_inverse": 4,
               "encrypt_rgsw": 3}
     assert set(counts) == set(HW.TUNED_KERNELS)
     for k, n in counts.items():

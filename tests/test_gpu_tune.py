@@ -63,14 +63,15 @@ def test_encrypt_rgsw_variants_match_oracle(N, nq, p):
 @pytest.mark.parametrize("N,nq,s,l,a", [(1024, 1, 23, 3, 11), (4096, 3, 30, 5, 12)])
 def test_train_and_infer_variants_identical(N, nq, s, l, a):
     """An encrypted tree level (z > L), a ragged last tuple and the class
-    counter, every variant of training, batched training and inference
-    forced in turn (N = 4096 adds the occupancy-4 builds)."""
+    counter, every variant of training (grid order, tree levels in the
+    chain's workgroup or staged one launch per level), batched training and
+    inference forced in turn (N = 4096 adds the occupancy-4 builds)."""
     X, y = synth.prototype_bits(5, 4 if N == 1024 else 2, s, l, flip=0.2)
     pair = Pair(N, nq, 64, s, l, a, X, y, seed=5)
     xr, yr = pair.encrypt_dev(), pair.encrypt_labels_dev()
     ctx = pair.ctx
     nv = ctx.tune_get("train")[2]
-    assert nv == (4 if N == 4096 else 2)
+    assert nv == (8 if N == 4096 else 4)
     Hs, Cs, Ss = [], [], []
     for v in range(nv):
         ctx.tune_set("train", v)
@@ -92,6 +93,8 @@ def test_train_and_infer_variants_identical(N, nq, s, l, a):
         ctx.batch_train([(pair.shape, xr, yr, pair.n, H, C)])
         assert np.array_equal(host_u32(H), Hs[0]) and np.array_equal(host_u32(C), Cs[0]), v
     Hd = dev(Hs[0])
+    nv = ctx.tune_get("infer")[2]
+    assert nv == (4 if N == 4096 else 2)
     for v in range(nv):
         ctx.tune_set("infer", v)
         sc = zeros_u32(pair.n, pair.l, pair.k0, pair.nq * (pair.N + 1))

@@ -50,17 +50,20 @@ WORKLOADS = {
 KERNEL_SOURCES = ["hw_device.h", "hw_kernels.hip", "hw_internal.h"]
 
 
-def measured_traffic():
-    """HBM bytes (read + write) per k_train launch measured with rocprofv3
-    FETCH_SIZE / WRITE_SIZE (profiles/k_train_mnist_pmc.md), or None when the
-    kernel sources changed since (their sha256 no longer matches)."""
+def measured_traffic(schedule: str | None):
+    """HBM bytes (read + write) per training call (k_train, plus the
+    k_train_level launches when the tree levels are staged) measured with
+    rocprofv3 FETCH_SIZE / WRITE_SIZE (profiles/k_train_mnist_pmc.md) for the
+    schedule in use, or None when the kernel sources changed since (their
+    sha256 no longer matches)."""
     import hashlib
     import re
     try:
         text = open(os.path.join(ROOT, "profiles", "k_train_mnist_pmc.md")).read()
     except OSError:
         return None
-    t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    kind = "staged" if schedule and "staged" in schedule else "fused"
+    t = re.search(r"traffic_bytes_per_launch_%s:\s*(\d+)" % kind, text)
     h = re.search(r"kernel_sources_sha256:\s*([0-9a-f]{64})", text)
     if not t or not h:
         return None
@@ -379,18 +382,54 @@ def cpu_baseline(wl: str, W: dict, Xtr, ytr, Xte, seeds: dict, ctx, sh, sk_dev, 
         host=info, paper_context=PAPER_CPU_CONTEXT.get(wl))
 
 
+def side_workload(args):
+    """--workload batched / served: one JSON line"""
+    import torch
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    if args.workload == "batched":
+        r = batched_full(dev, args.batched_ring, args.batched_window_gib, args.batched_per_job, args.batched_jobs)
+        line = {"metric": "batched encrypted train samples/s (training kernels)", "value": r["batched_samples_per_s"],
+                "unit": "samples/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u32", "data": "synthetic",
+                "config": {"workload": "256 uneven training jobs (n U{32..2000}, s U{128..2352}, a U{8..12}, "
+                                       "l U{2..10}), ring %d" % args.batched_ring}, "batched": r}
+    else:
+        r = served_full(dev, args.served_requests, args.served_max_size, args.served_loads or [],
+                        args.served_sat_rps, args.served_one_at_a_time)
+        line = {"metric": "served p50/p99 latency and throughput", "unit": "ms", "n_gpus": 1, "dtype": "u32",
+                "data": "synthetic", "config": {"workload": "Poisson train/infer requests, half Wisconsin- half "
+                                                            "MNIST-shaped, N=2048 x 2 primes, p=2^16"}, "served": r}
+    line["wall_s"] = round(time.perf_counter() - t0, 1)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mnist", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="mnist", choices=sorted(WORKLOADS) + ["batched", "served"],
+                    help="batched / served: the batched and served configurations at their stated sizes "
+                         "(separate runs, one JSON line each; see --batched-* / --served-*)")
+    ap.add_argument("--batched-ring", type=int, default=2048, choices=[2048, 4096])
+    ap.add_argument("--batched-jobs", type=int, nargs=2, default=None, metavar=("FIRST", "END"),
+                    help="only jobs [FIRST, END) of the ring's jobs")
+    ap.add_argument("--batched-window-gib", type=float, default=160.0)
+    ap.add_argument("--batched-per-job", type=int, default=2, help="samples per job per window")
+    ap.add_argument("--served-loads", type=float, nargs="*", default=None,
+                    help="loads (fractions of the saturated request rate) for --workload served")
+    ap.add_argument("--served-sat-rps", type=float, default=None,
+                    help="saturated request rate from an earlier run (skips the saturated run)")
+    ap.add_argument("--served-one-at-a-time", action="store_true",
+                    help="also replay the requests one job at a time")
     ap.add_argument("--n-train", type=int, default=None, help="override the number of training samples")
     ap.add_argument("--chunk", type=int, default=None, help="samples encrypted and trained per call")
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serial", action="store_true",
-                    help="encrypt and train on one stream (default: encryption of the next chunk overlaps training)")
+    ap.add_argument("--overlap", action="store_true",
+                    help="encrypt chunk k+1 on a second stream while chunk k trains (default: one stream; "
+                         "measured slower, as either kernel alone keeps the GPU busy)")
     ap.add_argument("--no-peaks", action="store_true", help="skip the device peak probes")
     ap.add_argument("--force", action="append", default=[], metavar="KERNEL=VARIANT",
                     help="force a schedule variant of a tuned kernel (hw_tune_set), e.g. train=3")
@@ -404,6 +443,11 @@ def main():
                     help="request sizes are U{1..max}; the served workload's 1..500 scaled down")
     ap.add_argument("--served-load", type=float, default=0.7, help="offered load as a fraction of saturation")
     args = ap.parse_args()
+    if args.workload in ("batched", "served"):
+        if args.gpus != 1:
+            print("bench.py: one GPU only.", file=sys.stderr)
+            sys.exit(2)
+        return side_workload(args)
     if args.gpus != 1:
         print("bench.py: one GPU only; the path shards by sample or by RAM across GPUs, which is not run here. "
               "Use --gpus 1.", file=sys.stderr)
@@ -446,15 +490,15 @@ def main():
     sk = torch.zeros(N, dtype=torch.int32, device=dev)
     ctx.keygen(seeds["key"], sk)
     chunk = W["chunk"]
-    # two chunk buffers: the client encrypts chunk k+1 on its own stream while
-    # the server trains chunk k (both streams at the default priority)
-    nbuf = 1 if args.serial else 2
+    # with --overlap, two chunk buffers: the client encrypts chunk k+1 on its
+    # own stream while the server trains chunk k (both at the default priority)
+    nbuf = 2 if args.overlap else 1
     xr = [torch.empty(chunk * s, ctx.rgsw_words, dtype=torch.int32, device=dev) for _ in range(nbuf)]
     yr = [torch.empty(max(1, chunk * L), ctx.rgsw_words, dtype=torch.int32, device=dev) for _ in range(nbuf)]
     H = torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev)
     cnt = torch.zeros(2, nq, N, dtype=torch.int32, device=dev) if W["balance"] else None
     s_train = torch.cuda.current_stream(dev)
-    s_enc = s_train if args.serial else torch.cuda.Stream(device=dev)
+    s_enc = torch.cuda.Stream(device=dev) if args.overlap else s_train
 
     def train_step():
         H.zero_()
@@ -540,14 +584,16 @@ def main():
     peaks = None if args.no_peaks else device_peaks(dev)
     result["roofline"] = xp_roofline("k_train", N, nq, tr_xp, tr_ms, tr_launch, peaks,
                                      ops=train_ops(N, nq, tr_xp, ivps))
-    result["roofline"]["traffic"] = measured_traffic() if args.workload == "mnist" and chunk == 50 else None
-    result["roofline"]["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"
+    result["roofline"]["traffic"] = (measured_traffic(ctx.schedule().get("train"))
+                                     if args.workload == "mnist" and chunk == 50 else None)
+    result["roofline"]["traffic_unit"] = ("HBM bytes per training call of the schedule in use (rocprofv3 "
+                                          "FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)")
     result["roofline"]["first_xp_of_chain"] = ("one product in %d reads half its RGSW (no forward transforms)"
                                                % round(steps_xp / steps_ivps))
     result["device_peaks"] = peaks
     result["kernels"] = {
         # with encryption on its own stream the step takes less than the sum of its kernels
-        "overlap": "serial" if args.serial else "encryption of chunk k+1 on a second stream while chunk k trains",
+        "overlap": "encryption of chunk k+1 on a second stream while chunk k trains" if args.overlap else "serial",
         "kernel_sum_ms_per_step": round((tr_ms + rd_ms + en_ms) / args.steps, 2),
         "train_ms_per_step": round(train_kernel_ms, 2),
         "reduce_ms_per_step": round(rd_ms / args.steps, 2),
@@ -926,13 +972,13 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     return out
 
 
-def served_pass(dev, n_req: int, max_size: int, load: float):
-    """Continuous batching of Poisson-arrival train/infer requests: half
-    Wisconsin-shaped (30 features, 2 classes 357/212, min-max + 16-level
-    thermometer = 480 bits, tuple 8), half MNIST-shaped, 4 resident models of
-    each shape pre-trained with 64 samples, one parameter set (N=2048, two
-    primes, p=2^16).  First all requests at once (saturation), then Poisson
-    arrivals at `load` x the saturated request rate: p50/p99 latency."""
+def served_setup(dev, n_req: int, max_size: int, seed: int = 5):
+    """The served workload: one parameter set (N=2048, two primes, p=2^16)
+    and key; half Wisconsin-shaped (30 features, 2 classes 357/212, min-max +
+    16-level thermometer = 480 bits, tuple 8), half MNIST-shaped models, 4
+    resident models of each shape pre-trained with 64 samples; n_req
+    requests, half train and half infer, sizes U{1..max_size}.  Returns
+    (ctx, make_engine, reqs)."""
     import numpy as np
     import torch
 
@@ -944,14 +990,17 @@ def served_pass(dev, n_req: int, max_size: int, load: float):
     ctx = HW.Context(N, nq, p)
     sk = torch.zeros(N, dtype=torch.int32, device=dev)
     ctx.keygen(202, sk)
-    # data pools
     Xw, yw = synth.wisconsin_like(4)
     lo, hi = Xw.min(axis=0), Xw.max(axis=0)
     bits_w = CL.thermometer(CL.quantize_minmax(Xw, 16, lo, hi), 16)
     Xm, ym, _, _ = synth.mnist_like(1, per_class_train=60, per_class_test=1)
     bits_m = CL.thermometer(CL.quantize_u8(Xm, 3), 3)
     shapes = {"wisconsin": (bits_w, yw, 2, 8), "mnist": (bits_m, ym, 10, 12)}
-    g = np.random.Generator(np.random.PCG64(5))
+    g = np.random.Generator(np.random.PCG64(seed))
+    pre = {}  # the pre-training samples of each model, drawn once
+    for name, (bits, y, l, a) in shapes.items():
+        for r in range(4):
+            pre[(name, r)] = g.integers(0, len(bits), 64)
 
     def make_engine():
         eng = HW.Engine(N, nq, p, sk, slots=4, chunk=8, max_s=2352, max_cells=2048, arena_bytes=64 << 30)
@@ -962,7 +1011,7 @@ def served_pass(dev, n_req: int, max_size: int, load: float):
                 k0, k1, _ = ctx.dims(sh)
                 H = torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev)
                 j = eng.add_job(sh, H)
-                idx = g.integers(0, len(bits), 64)
+                idx = pre[(name, r)]
                 rid = eng.submit(j, "train", bits[idx], 8000 + j, labels=CL.label_bits(y[idx], l))
                 eng.wait(rid)
                 jobs.append((j, name, H, k0))
@@ -976,33 +1025,68 @@ def served_pass(dev, n_req: int, max_size: int, load: float):
         idx = g.integers(0, len(bits), size)
         reqs.append(dict(shape=name, kind="train" if g.random() < 0.5 else "infer", job=int(g.integers(0, 4)),
                          bits=bits[idx], labels=CL.label_bits(y[idx], l), l=l, size=size, seed=9000 + 7 * k))
+    return ctx, make_engine, reqs
 
-    def play(arrivals):
-        eng, jobs = make_engine()
-        by = {}
-        for j, name, H, k0 in jobs:
-            by.setdefault(name, []).append((j, k0))
-        t0 = time.perf_counter()
-        ids = []
-        for r, t_arr in zip(reqs, arrivals):
-            dt = t0 + t_arr - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
-            j, k0 = by[r["shape"]][r["job"]]
-            cells = np.zeros((r["size"], r["l"], k0), np.uint64) if r["kind"] == "infer" else None
-            ids.append(eng.submit(j, r["kind"], r["bits"], r["seed"],
-                                  labels=r["labels"] if r["kind"] == "train" else None, cells=cells))
-        lat = [eng.wait(i)[1] for i in ids]
-        span = time.perf_counter() - t0
-        st = eng.stats()
-        eng.close()
-        return np.array(lat), span, st
 
-    lat0, span0, st0 = play([0.0] * n_req)
+def served_play(make_engine, reqs, arrivals, one_at_a_time: bool = False):
+    """Submit the requests at their arrival times (s from the start) to a
+    fresh engine; (latencies ms, span s, engine stats).  one_at_a_time: each
+    request is submitted only after the previous one finished (the plain
+    one-job-at-a-time path; latencies are then service times)."""
+    import numpy as np
+    eng, jobs = make_engine()
+    by = {}
+    for j, name, H, k0 in jobs:
+        by.setdefault(name, []).append((j, k0))
+    prog = Progress("served requests", len(reqs))
+    t0 = time.perf_counter()
+    ids, lat = [], []
+    for i, (r, t_arr) in enumerate(zip(reqs, arrivals)):
+        dt = t0 + t_arr - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        j, k0 = by[r["shape"]][r["job"]]
+        cells = np.zeros((r["size"], r["l"], k0), np.uint64) if r["kind"] == "infer" else None
+        rid = eng.submit(j, r["kind"], r["bits"], r["seed"], labels=r["labels"] if r["kind"] == "train" else None,
+                         cells=cells)
+        if one_at_a_time:
+            lat.append(eng.wait(rid)[1])
+        else:
+            ids.append(rid)
+        if i % 16 == 15:
+            print("bench: served %d / %d submitted" % (i + 1, len(reqs)), file=sys.stderr, flush=True)
+    lat += [eng.wait(i)[1] for i in ids]
+    span = time.perf_counter() - t0
+    st = eng.stats()
+    eng.close()
+    return np.array(lat), span, st
+
+
+def lindley(service_ms, arrivals_s):
+    """Latencies (ms) of a single FIFO server with the given service times
+    under the given arrivals: W_{k+1} = max(0, W_k + S_k - (A_{k+1} - A_k))."""
+    import numpy as np
+    S = np.asarray(service_ms, float)
+    A = np.asarray(arrivals_s, float) * 1000.0
+    W = np.zeros_like(S)
+    for k in range(1, len(S)):
+        W[k] = max(0.0, W[k - 1] + S[k - 1] - (A[k] - A[k - 1]))
+    return W + S
+
+
+def served_pass(dev, n_req: int, max_size: int, load: float):
+    """Continuous batching of Poisson-arrival train/infer requests (the
+    default run's scaled-down served mix): all requests at once
+    (saturation), then Poisson arrivals at `load` x the saturated rate."""
+    import numpy as np
+
+    from paper_2403_20190_amd import synth
+    ctx, make_engine, reqs = served_setup(dev, n_req, max_size)
+    lat0, span0, st0 = served_play(make_engine, reqs, [0.0] * n_req)
     sat_rps = n_req / span0
     qps = load * sat_rps
     arr = synth.poisson_arrivals(6, qps, n_req)
-    lat1, span1, st1 = play(list(arr - arr[0]))
+    lat1, span1, st1 = served_play(make_engine, reqs, list(arr - arr[0]))
     samples = sum(r["size"] for r in reqs)
     ctx.close()
     return {
@@ -1015,6 +1099,196 @@ def served_pass(dev, n_req: int, max_size: int, load: float):
         "saturated_p99_ms": round(float(np.percentile(lat0, 99)), 2),
         "peak_inflight_chunks": st1["peak_inflight"], "peak_arena_gib": round(st1["peak_arena_bytes"] / 2**30, 2),
     }
+
+
+def served_full(dev, n_req: int, max_size: int, loads, sat_rps: float | None, sequential: bool) -> dict:
+    """The served configuration at its stated size: 400 requests of U{1..500}
+    samples.  Runs whichever parts are asked for (each can be its own
+    process, so that one run stays within a time limit): the saturated run
+    (all requests at t = 0), which sets the request rate the loads scale;
+    Poisson arrivals at each load x that rate (p50/p99 latency, throughput);
+    and the same request list one job at a time (service times, from which
+    the one-job-at-a-time latencies under the same arrivals follow by the
+    single-server recursion)."""
+    import numpy as np
+
+    from paper_2403_20190_amd import synth
+    ctx, make_engine, reqs = served_setup(dev, n_req, max_size)
+    samples = sum(r["size"] for r in reqs)
+    out = {"requests": n_req, "sizes": "U{1..%d}" % max_size, "samples": samples,
+           "mix": {"train": sum(r["kind"] == "train" for r in reqs), "mnist": sum(r["shape"] == "mnist" for r in reqs)}}
+
+    def pct(x):
+        return {"p50_ms": round(float(np.percentile(x, 50)), 1), "p99_ms": round(float(np.percentile(x, 99)), 1)}
+
+    if sat_rps is None:
+        lat0, span0, st0 = served_play(make_engine, reqs, [0.0] * n_req)
+        sat_rps = n_req / span0
+        out["saturated"] = dict(req_per_s=round(sat_rps, 4), samples_per_s=round(samples / span0, 2),
+                                span_s=round(span0, 1), peak_inflight_chunks=st0["peak_inflight"], **pct(lat0))
+    out["saturated_req_per_s"] = round(sat_rps, 4)
+    if sequential:
+        svc, span1, _ = served_play(make_engine, reqs, [0.0] * n_req, one_at_a_time=True)
+        # the same Poisson arrivals as the loaded runs, served one request at a time
+        q = []
+        for load in (0.25, 0.5, 0.75, 0.9):
+            arr = synth.poisson_arrivals(6, load * sat_rps, n_req)
+            q.append(dict(load=load, **pct(lindley(svc, arr - arr[0]))))
+        out["one_at_a_time"] = dict(samples_per_s=round(samples / span1, 2), span_s=round(span1, 1),
+                                    service=pct(svc), poisson=q)
+    out["loads"] = []
+    for load in loads:
+        qps = load * sat_rps
+        arr = synth.poisson_arrivals(6, qps, n_req)
+        arr = list(arr - arr[0])
+        lat, span, st = served_play(make_engine, reqs, arr)
+        out["loads"].append(dict(load=load, offered_qps=round(qps, 4), throughput_samples_per_s=round(samples / span, 2),
+                                 span_s=round(span, 1), peak_inflight_chunks=st["peak_inflight"],
+                                 peak_arena_gib=round(st["peak_arena_bytes"] / 2**30, 2), **pct(lat)))
+    ctx.close()
+    return out
+
+
+def batched_full(dev, ring: int, window_gib: float, per_job: int, jobs_range=None, chunk: int = 50) -> dict:
+    """The batched configuration at its stated size: the 256 jobs of
+    synth.batched_jobs (n U{32..2000}, s U{128..2352}, a U{8..12}, l
+    U{2..10}), those of ring degree `ring` (two primes at 2048, three at
+    4096, p = 4096 >= every job's count).  Their input ciphertexts (up to
+    several TB) are streamed: each window takes the next `per_job` samples of
+    as many unfinished jobs as fit `window_gib` GiB of encrypted inputs,
+    encrypts them on the device, then trains them once as one batch
+    (hw_batch_train: one persistent launch over the window's jobs) and once
+    job by job (hw_wisard_train_encrypted), into two model sets that must end
+    bit-identical.  Times are HIP events around the two training passes;
+    encryption is timed apart.  Then the plain one-job-at-a-time path: each
+    job alone, its samples encrypted and trained in chunks of `chunk` (as
+    many as fit the window), into a third model set that must equal the
+    others."""
+    import numpy as np
+    import torch
+
+    from paper_2403_20190_amd import client as CL
+    from paper_2403_20190_amd import hwisard as HW
+    from paper_2403_20190_amd import synth
+    torch.cuda.empty_cache()
+    nq = 2 if ring == 2048 else 3
+    alljobs = [(j, J) for j, J in enumerate(synth.batched_jobs(2)) if J["N"] == ring]
+    if jobs_range:
+        alljobs = alljobs[jobs_range[0]:jobs_range[1]]
+    ctx = HW.Context(ring, nq, 4096)
+    sk = torch.zeros(ring, dtype=torch.int32, device=dev)
+    ctx.keygen(101, sk)
+    rg = ctx.rgsw_words * 4
+    st = []
+    for j, J in alljobs:
+        X, y = synth.prototype_bits(J["seed"] % (2 ** 31), J["n"], J["s"], J["l"])
+        sh = HW.shape(J["s"], J["l"], J["a"], 3000 + j)
+        k0, k1, _ = ctx.dims(sh)
+        st.append(dict(j=j, J=J, X=X, y=y, L=CL.ceil_log2(J["l"]), sh=sh, done=0,
+                       mb=torch.zeros(k0, k1, 2, nq, ring, dtype=torch.int32, device=dev),
+                       ms=torch.zeros(k0, k1, 2, nq, ring, dtype=torch.int32, device=dev)))
+    out = {"ring": ring, "jobs": len(st), "samples": int(sum(S["J"]["n"] for S in st)), "windows": 0,
+           "batched_ms": 0.0, "single_ms": 0.0, "encrypt_ms": 0.0, "xp": 0.0, "bytes": 0.0, "modmul": 0.0}
+    ctx.profile(True)
+    ctx.profile_reset()
+    prog = Progress("batched samples", out["samples"])
+    trained = 0
+    while any(S["done"] < S["J"]["n"] for S in st):
+        win, used = [], 0
+        for S in st:
+            m = min(per_job, S["J"]["n"] - S["done"])
+            if m <= 0:
+                continue
+            need = m * (S["J"]["s"] + S["L"]) * rg
+            if win and used + need > window_gib * 2**30:
+                continue
+            win.append((S, m))
+            used += need
+        e0, e1, e2, e3 = (torch.cuda.Event(enable_timing=True) for _ in range(4))
+        e0.record()
+        bufs = []
+        for S, m in win:
+            J, c0 = S["J"], S["done"]
+            xr = torch.empty(m * J["s"], ctx.rgsw_words, dtype=torch.int32, device=dev)
+            ctx.encrypt_rgsw_bits(sk, torch.from_numpy(S["X"][c0:c0 + m].reshape(-1)).to(dev), 1000 + S["j"],
+                                  c0 * J["s"], xr)
+            yr = None
+            if S["L"]:
+                yr = torch.empty(m * S["L"], ctx.rgsw_words, dtype=torch.int32, device=dev)
+                ctx.encrypt_rgsw_bits(sk, torch.from_numpy(CL.label_bits(S["y"][c0:c0 + m], J["l"]).reshape(-1))
+                                      .to(dev), 2000 + S["j"], c0 * S["L"], yr)
+            bufs.append((S, m, xr, yr))
+        e1.record()
+        ctx.batch_train([(S["sh"], xr, yr, m, S["mb"], None) for S, m, xr, yr in bufs])
+        e2.record()
+        for S, m, xr, yr in bufs:
+            ctx.train(S["sh"], xr, yr, m, S["ms"], None)
+        e3.record()
+        torch.cuda.synchronize()
+        out["encrypt_ms"] += e0.elapsed_time(e1)
+        out["batched_ms"] += e1.elapsed_time(e2)
+        out["single_ms"] += e2.elapsed_time(e3)
+        out["windows"] += 1
+        for S, m, _, _ in bufs:
+            S["done"] += m
+            trained += m
+        del bufs
+        prog(trained)
+    xpb = ctx.profile_read("train_batch")[2]
+    out["xp"] = xpb
+    out["kernel_ms"] = {k: round(ctx.profile_read(k)[0], 1) for k in ("train_batch", "reduce_batch", "train", "reduce",
+                                                                      "encrypt_rgsw")}
+    ctx.profile(False)
+    out["bit_identical"] = all(torch.equal(S["mb"], S["ms"]) for S in st)
+    # the plain one-job-at-a-time path: job after job, each in chunks that fill the GPU
+    for S in st:
+        S["ms"].zero_()
+    jt = 0.0
+    prog = Progress("one-job-at-a-time samples", out["samples"])
+    done = 0
+    for S in st:
+        J = S["J"]
+        cmax = max(1, min(chunk, int(window_gib * 2**30 // ((J["s"] + S["L"]) * rg))))
+        for c0 in range(0, J["n"], cmax):
+            m = min(cmax, J["n"] - c0)
+            xr = torch.empty(m * J["s"], ctx.rgsw_words, dtype=torch.int32, device=dev)
+            ctx.encrypt_rgsw_bits(sk, torch.from_numpy(S["X"][c0:c0 + m].reshape(-1)).to(dev), 1000 + S["j"],
+                                  c0 * J["s"], xr)
+            yr = None
+            if S["L"]:
+                yr = torch.empty(m * S["L"], ctx.rgsw_words, dtype=torch.int32, device=dev)
+                ctx.encrypt_rgsw_bits(sk, torch.from_numpy(CL.label_bits(S["y"][c0:c0 + m], J["l"]).reshape(-1))
+                                      .to(dev), 2000 + S["j"], c0 * S["L"], yr)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.train(S["sh"], xr, yr, m, S["ms"], None)
+            e1.record()
+            torch.cuda.synchronize()
+            jt += e0.elapsed_time(e1)
+            del xr, yr
+            done += m
+            prog(done)
+    out["job_by_job_ms"] = round(jt, 1)
+    out["job_by_job_chunk"] = chunk
+    out["job_by_job_samples_per_s"] = round(out["samples"] / (jt / 1000.0), 2)
+    out["speedup_vs_job_by_job"] = round(jt / out["batched_ms"], 4)
+    out["bit_identical"] &= all(torch.equal(S["mb"], S["ms"]) for S in st)
+    out["schedule"] = ctx.schedule()
+    ctx.close()
+    sec_b, sec_s = out["batched_ms"] / 1000.0, out["single_ms"] / 1000.0
+    out["batched_samples_per_s"] = round(out["samples"] / sec_b, 2)
+    out["single_job_samples_per_s"] = round(out["samples"] / sec_s, 2)
+    out["speedup"] = round(sec_s / sec_b, 4)
+    tb = out["kernel_ms"]["train_batch"] / 1000.0
+    hf = xpb * rgsw_bytes(ring, nq) / tb / 1e9 / PEAK_HBM_GBS if tb else 0.0
+    vf = xpb * modmul_per_xp(ring, nq) * MUL_PER_MODMUL / tb / 1e12 / PEAK_INT32_TOPS if tb else 0.0
+    out["roofline"] = {"kernel": "k_train_batch", "bound": "hbm" if hf >= vf else "alu",
+                       "hbm_gbs": round(xpb * rgsw_bytes(ring, nq) / tb / 1e9, 1) if tb else None,
+                       "hbm_frac": round(hf, 4), "valu_frac": round(vf, 4)}
+    for k in ("batched_ms", "single_ms", "encrypt_ms"):
+        out[k] = round(out[k], 1)
+    del out["bytes"], out["modmul"]
+    return out
 
 
 def hbm_copy(dev):

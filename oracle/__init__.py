@@ -82,6 +82,8 @@ def lib():
                 "orc_pks_partial": (None, [C.c_void_p, u32p, u32p, C.c_uint32, C.c_uint32, C.c_uint32, u32p]),
                 "orc_pks_finish": (None, [C.c_void_p, u32p, C.c_uint32, u32p, u32p]),
                 "orc_extract_lwe0": (None, [C.c_void_p, u32p, u32p]),
+                "orc_modswitch": (None, [C.c_void_p, u32p, C.c_uint32, C.POINTER(C.c_int64)]),
+                "orc_pbs": (None, [C.c_void_p, C.POINTER(C.c_void_p), u32p, C.c_uint32, u64p, u32p]),
                 "orc_vp": (None, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_uint8), C.c_uint32, u32p, u32p]),
                 "orc_permutation": (None, [C.c_uint64, C.c_uint32, u32p]),
                 "orc_k1": (C.c_uint32, [C.c_void_p, C.c_uint32, C.c_uint32, C.c_uint32]),
@@ -421,6 +423,34 @@ class Ctx:
         ct = np.ascontiguousarray(ct, np.uint32)
         out = np.zeros((self.nq, self.N + 1), np.uint32)
         lib().orc_extract_lwe0(self.h, _p(ct, u32p), _p(out, u32p))
+        return out
+
+    # -- programmable bootstrapping (Sec. 2.5.3; circuits in oracle.pbs) --------
+    def modswitch(self, lwe, n: int) -> np.ndarray:
+        """round(2N x / Q) mod 2N of the first n mask coefficients and the body"""
+        lwe = np.ascontiguousarray(lwe, np.uint32)
+        out = np.zeros(n + 1, np.int64)
+        lib().orc_modswitch(self.h, _p(lwe, u32p), n, out.ctypes.data_as(C.POINTER(C.c_int64)))
+        return out
+
+    def pbs_keygen(self, s, seed: int, n: int) -> list:
+        """bootstrapping key for the first n key coefficients: RGSW([s_k = 1])
+        and RGSW([s_k = -1]) as ciphertexts 2k and 2k + 1 of stream `seed`"""
+        bits = []
+        for k in range(n):
+            bits += [1 if int(s[k]) == 1 else 0, 1 if int(s[k]) == -1 else 0]
+        out = [None] * (2 * n)
+        _parallel(lambda t: out.__setitem__(t, self.enc_rgsw(s, bits[t], seed, t)), range(2 * n))
+        return out
+
+    def pbs(self, bsk, lwe, n: int, V: int) -> np.ndarray:
+        """programmable bootstrap with the constant test polynomial V: an LWE of
+        V when the switched phase lies in [0, N), of -V otherwise"""
+        lwe = np.ascontiguousarray(lwe, np.uint32)
+        rg = [np.ascontiguousarray(r, np.uint32) for r in bsk[: 2 * n]]
+        v = np.array([V % q for q in self.primes], np.uint64)
+        out = np.zeros((self.nq, self.N + 1), np.uint32)
+        lib().orc_pbs(self.h, _ptr_array(rg), _p(lwe, u32p), n, _p(v, u64p), _p(out, u32p))
         return out
 
     def rlwe_add(self, x, y) -> np.ndarray:

@@ -1266,6 +1266,70 @@ void orc_pks_finish(const orc_ctx* c, const uint32_t* lwe, uint32_t k, const uin
 }
 
 /* exported sizes for the Python wrapper */
+/* ------------------------------------------------------------------------ */
+/* programmable bootstrapping of LWE ciphertexts (Sec. 2.5.3, Sec. 3.5.2)    */
+/* ------------------------------------------------------------------------ */
+
+/* Modulus switch Q -> 2N of an LWE ciphertext [prime][N+1] whose mask is
+ * zero past its first n coefficients: each a_k (k < n) and the body b, read
+ * as integers in [0, Q) through the CRT, becomes round(2N x / Q) mod 2N,
+ * i.e. floor((2N x + floor(Q/2)) / Q) mod 2N (Q is odd, so no value rounds
+ * from exactly one half).  out[0..n) = the mask, out[n] = the body. */
+void orc_modswitch(const orc_ctx* c, const uint32_t* lwe, uint32_t n, int64_t* out) {
+  uint32_t N = c->N, nq = c->nq;
+  uint64_t x[ORC_MAXQ];
+  for (uint32_t k = 0; k <= n; ++k) {
+    uint32_t idx = k < n ? k : N;
+    for (uint32_t i = 0; i < nq; ++i) x[i] = lwe[(size_t)i * (N + 1) + idx];
+    u128 v = crt(c, x);
+    u128 r = (v * (u128)(2 * N) + c->Q / 2) / c->Q;
+    out[k] = (int64_t)(r % (2 * N));
+  }
+}
+
+/* Programmable bootstrap with a constant test polynomial V (v[i] = V mod
+ * q_i) of an LWE ciphertext whose mask is zero past its first n
+ * coefficients, with the bootstrapping key bsk[2k] = RGSW([s_k = 1]),
+ * bsk[2k+1] = RGSW([s_k = -1]) (k < n, RGSW under the ring key s):
+ *   (a~, b~) = modulus switch to 2N;
+ *   ACC = the trivial RLWE (0, X^{-b~} TV), TV = V (1 + X + ... + X^{N-1});
+ *   for k < n: ACC <- CMUX(bsk[2k], X^{a~_k} ACC, ACC),
+ *              ACC <- CMUX(bsk[2k+1], X^{-a~_k} ACC, ACC)
+ *     (at most one of the two bits is 1, so the pair multiplies ACC by
+ *      X^{a~_k s_k}), which leaves ACC encrypting X^{-phi~} TV with
+ *      phi~ = b~ - sum_k a~_k s_k mod 2N;
+ *   out = ExtractLWE(ACC, 0): coefficient 0 of X^{-phi~} TV is TV[phi~] = V
+ *     when phi~ < N and -TV[phi~ - N] = -V otherwise (X^N = -1), plus the
+ *     noise of 2n external products. */
+void orc_pbs(const orc_ctx* c, const uint32_t* const* bsk, const uint32_t* lwe, uint32_t n, const uint64_t* v,
+             uint32_t* out) {
+  uint32_t N = c->N, nq = c->nq;
+  size_t rw = rlwe_words(c);
+  int64_t* ms = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+  int64_t* ex = (int64_t*)malloc(sizeof(int64_t) * (2 * (size_t)n + 1));
+  uint32_t* acc = (uint32_t*)calloc(rw, sizeof(uint32_t));
+  uint32_t* res = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  orc_modswitch(c, lwe, n, ms);
+  /* the test polynomial TV = V (1 + X + ... + X^{N-1}), rotated by X^{-b~} */
+  for (uint32_t i = 0; i < nq; ++i) {
+    uint64_t vi = v[i] % c->q[i];
+    uint32_t* b = res + ((size_t)nq + i) * N;
+    memset(res + (size_t)i * N, 0, sizeof(uint32_t) * N);
+    for (uint32_t j = 0; j < N; ++j) b[j] = (uint32_t)vi;
+  }
+  orc_rlwe_rotate(c, res, -ms[n], acc);
+  for (uint32_t k = 0; k < n; ++k) {
+    ex[2 * k] = ms[k];
+    ex[2 * k + 1] = -ms[k];
+  }
+  orc_blind_rotate(c, acc, bsk, ex, 2 * n, res);
+  orc_extract_lwe0(c, res, out);
+  free(ms);
+  free(ex);
+  free(acc);
+  free(res);
+}
+
 uint64_t orc_rlwe_words(const orc_ctx* c) { return rlwe_words(c); }
 uint64_t orc_rgsw_words(const orc_ctx* c) { return rgsw_words(c); }
 uint32_t orc_logN(const orc_ctx* c) { return c->logN; }

@@ -1038,7 +1038,6 @@ def served_play(make_engine, reqs, arrivals, one_at_a_time: bool = False):
     by = {}
     for j, name, H, k0 in jobs:
         by.setdefault(name, []).append((j, k0))
-    prog = Progress("served requests", len(reqs))
     t0 = time.perf_counter()
     ids, lat = [], []
     for i, (r, t_arr) in enumerate(zip(reqs, arrivals)):
@@ -1055,7 +1054,12 @@ def served_play(make_engine, reqs, arrivals, one_at_a_time: bool = False):
             ids.append(rid)
         if i % 16 == 15:
             print("bench: served %d / %d submitted" % (i + 1, len(reqs)), file=sys.stderr, flush=True)
-    lat += [eng.wait(i)[1] for i in ids]
+    last = time.perf_counter()
+    for k, i in enumerate(ids):
+        lat.append(eng.wait(i)[1])
+        if time.perf_counter() - last > 10.0:
+            print("bench: served %d / %d done" % (k + 1, len(ids)), file=sys.stderr, flush=True)
+            last = time.perf_counter()
     span = time.perf_counter() - t0
     st = eng.stats()
     eng.close()

@@ -281,6 +281,75 @@ hw_status hw_pks_key_export_canonical(hw_ctx* ctx, const uint32_t* key_dev, uint
 hw_status hw_pack_lwe(hw_ctx* ctx, const uint32_t* key_dev, const uint32_t* lwe_dev, uint32_t k,
                       uint64_t count, uint32_t* out_dev, hipStream_t stream);
 
+/* ---- programmable bootstrapping: Activate and EncryptedArgMax (OTF-act) --------- */
+
+/* The paper evaluates the activation of the inference scores (OTF-act,
+ * Sec. 3.5.2) and the final ArgMax (Alg. 7) with the programmable
+ * bootstrapping, taken as a black box (Sec. 2.5.3).  Here the bootstrap
+ * decides one sign at a time, and the functions are circuits of such
+ * bootstraps and exact linear operations on LWE ciphertexts, all under the
+ * ring key s (LWE [prime][N+1] as ExtractLWE leaves them), modulus Q.
+ *
+ * Bootstrapping key (hw_pbs_keygen): for the first n key coefficients,
+ * bsk[2k] = RGSW([s_k = 1]) and bsk[2k+1] = RGSW([s_k = -1]), ciphertexts 2k
+ * and 2k+1 of hw_encrypt_rgsw_bits' stream `seed`; [2n] RGSW in device
+ * layout, caller-owned (2n hw_sizes().rgsw bytes: 2.7 GB at N = 2048, nq = 2,
+ * n = N).  1 <= n <= N. */
+hw_status hw_pbs_keygen(hw_ctx* ctx, const int32_t* sk_dev, uint64_t seed, uint32_t n, uint32_t* bsk_dev,
+                        hipStream_t stream);
+
+/* Bootstrap with the constant test polynomial V (v: its nq residues, host)
+ * of `count` LWE ciphertexts whose mask is zero past its first n
+ * coefficients (n = N for ExtractLWE outputs; bsk from hw_pbs_keygen with at
+ * least n coefficients): the mask and body switched to round(2N x / Q) mod 2N
+ * (x read through the CRT, half up), ACC = (0, X^{-b~} V (1 + X + ... +
+ * X^{N-1})), then for k < n ACC <- CMUX(bsk[2k], X^{a~_k} ACC, ACC) and
+ * ACC <- CMUX(bsk[2k+1], X^{-a~_k} ACC, ACC), out = ExtractLWE(ACC, 0): an
+ * LWE of V when the switched phase lies in [0, N), of -V otherwise.
+ * lwe_dev, out_dev: [count] LWE, not overlapping. */
+hw_status hw_pbs(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const uint32_t* lwe_dev, uint64_t count,
+                 const uint32_t* v_host, uint32_t* out_dev, hipStream_t stream);
+
+/* Activate with the threshold activation (bin of PD-act with thr = T - 1):
+ * out[j] encrypts [m_j >= T] for the message m_j in [0, p) of lwe[j] (phase
+ * ~ floor(Q/p) m_j, p = the context's plaintext modulus, p >= 8,
+ * 1 <= T <= p), with phase ~ 2 V_o [m_j >= T], V_o = floor(floor(Q / p_o) / 2),
+ * p_o = 2^log_p_out (decrypt with plaintext modulus p_o).  Steps (P = log2 p,
+ * V_b = floor(floor(Q/p) / 2), V_c = floor(Q/16), all on every ciphertext):
+ *   bits, k = 0..P-1: y = 2^(P-1-k) x + floor(Q/4); E_k = V_b - PBS(y, V_b);
+ *     x = x - 2^k E_k  (E_k ~ 2 V_b bit_k of m, least significant first);
+ *   carry of m + (p - T), t = p - T, c = 0, k = 0..P-1:
+ *     z = 2^(P-3) E_k + c - (V_c if bit k of t else 3 V_c);
+ *     c = PBS(z, V) + V with V = V_o for k = P-1, else V_c.
+ * Each bootstrap decides a sign with a margin of N/8 switched positions or
+ * more.  2P bootstraps per ciphertext; lwe_dev, out_dev: [count] LWE. */
+hw_status hw_activate_ge(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const uint32_t* lwe_dev,
+                         uint64_t count, uint64_t T, uint32_t log_p_out, uint32_t* out_dev, hipStream_t stream);
+
+/* EncryptedArgMax (Alg. 7): for each of `count` samples, the l class scores
+ * u[j][c] (phase ~ 2 V_i s_c, V_i = floor(floor(Q / p_in) / 2),
+ * p_in = 2^log_p_in >= 8, every s_c < p_in / 2) give out[j], an LWE of the
+ * index of the largest score, ties to the lowest index, with phase
+ * ~ 2 V_x index, V_x = floor(floor(Q / 2^(L+1)) / 2), L = ceil(log2 l)
+ * (decrypt with plaintext modulus 2^(L+1)).  Steps (P = log_p_in): for
+ * a < b, D = u_a - u_b + (p_in/2) 2 V_i, E = the bits of D (as in
+ * hw_activate_ge, at p_in), G(a, b) = 2^(P-3) E_(P-1) (= [s_a >= s_b]),
+ * G(b, a) = 2^(P-3) 2 V_i - G(a, b); W_a = 2 G(a, b) for l = 2, else the
+ * AND of G(a, b) over b != a in order (acc = G(a, b_1); acc = PBS(acc +
+ * G(a, b_j) - 3 V_c, V) + V with V = V_x for the last b_j, else V_c);
+ * index = sum_a a W_a.  u_dev: [count][l] LWE; out_dev: [count] LWE.
+ * 2 <= l <= 64, 3 <= log_p_in <= 20. */
+hw_status hw_encrypted_argmax(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const uint32_t* u_dev,
+                              uint64_t count, uint32_t l, uint32_t log_p_in, uint32_t* out_dev,
+                              hipStream_t stream);
+
+/* Per-class sums of per-RAM LWE scores (Alg. 2's sum over RAMs, on
+ * ciphertexts): sums[j][c] = sum over r < k0 of scores[j][c][r], residue by
+ * residue, e.g. of hw_activate_ge outputs before hw_encrypted_argmax.
+ * scores_dev: [n][l][k0] LWE; sums_dev: [n][l] LWE. */
+hw_status hw_class_sums(hw_ctx* ctx, const uint32_t* scores_dev, uint64_t n, uint32_t l, uint32_t k0,
+                        uint32_t* sums_dev, hipStream_t stream);
+
 /* Merge of models trained apart (Sec. 3.7.2: Integer WiSARD models of
  * federated entities are merged by adding their RAMs; the merged model is
  * the one centralised training on the union would give, bit for bit, since
@@ -381,10 +450,12 @@ hw_status hw_batch_run(hw_ctx* const* ctxs, uint32_t nctx, const hw_job* jobs, u
  * models are cut into chunks of samples; a scheduler thread starts a chunk
  * as soon as a stream slot is free and the chunk's device footprint (input
  * ciphertexts, workspace, scores) fits in the engine's arena, interleaving
- * chunks of all admitted requests.  Requests on one model run in submission
- * order (a request starts after the previous one on its model completed;
- * training chunks of a request run one after another); requests on
- * different models overlap on the device.  Results depend only on the
+ * chunks of all admitted requests.  Requests on one model keep submission
+ * order: a training request starts after every earlier request on its model
+ * completed (its chunks run one after another), an inference request once
+ * every earlier request on its model is an inference (inferences only read
+ * the model, so several overlap); requests on different models overlap on
+ * the device.  Results depend only on the
  * model state and the request, so each is bit-identical alone and in a mix.
  * For measurement the engine also plays the client: it encrypts request bits
  * on the device with the key it was given and returns decrypted PD-act cells. */
@@ -528,7 +599,7 @@ hw_status hw_microbench(int device, const char* kind, uint64_t size, double* rat
  * names: "train", "reduce", "train_batch", "reduce_batch", "batch_plan" (a whole
  * plan replay), "infer", "class_sums", "encrypt_rgsw", "encrypt_rlwe",
  * "decrypt_rlwe", "decrypt_lwe", "xp", "ntt", "rlwe_add",
- * "encrypt_pks", "pack_lwe". */
+ * "encrypt_pks", "pack_lwe", "pbs", "activate", "argmax". */
 hw_status hw_profile_enable(hw_ctx* ctx, int enable);
 
 /* Waits for the recorded events and returns, for kernel `name`, the summed

@@ -612,16 +612,24 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
   A.nram = nram;
   // external products per sample: the rotation chain and the live CDEMUX tree of every RAM
   double xp_per_sample = 0;
-  std::vector<uint32_t> smax;  // per tree level: the most live splits any RAM has there
+  // per tree level: the most live splits any RAM has there (z <= L + a - 10 < 32
+  // levels; a fixed array, so that the no-allocation entry point allocates nothing)
+  uint32_t smax[32] = {}, levels = 0, widest = 0, seen[3] = {0, 0, 0}, nseen = 0;
   for (uint32_t j = 0; j < nram; ++j) {
     const uint32_t nb = j < d.k0 ? d.L + std::min(sh->a, sh->s - j * sh->a) : d.L;
     xp_per_sample += ivp_xp(nb, c->logN, d.pL, d.pl);
-    const uint32_t z = nb - std::min(nb, (uint32_t)c->logN);
-    if (z > smax.size()) smax.resize(z, 0);
-    for (uint32_t lev = 0; lev < z; ++lev) smax[lev] = std::max(smax[lev], live_splits(lev, z, d.pL, d.pl));
+    // RAMs have at most three index widths: full tuples, the last tuple, the counter
+    if (std::find(seen, seen + nseen, nb + 1) != seen + nseen) continue;
+    if (nseen < 3) seen[nseen++] = nb + 1;
+    const uint32_t z = std::min<uint32_t>(nb - std::min(nb, (uint32_t)c->logN), 32);
+    levels = std::max(levels, z);
+    for (uint32_t lev = 0; lev < z; ++lev) {
+      smax[lev] = std::max(smax[lev], live_splits(lev, z, d.pL, d.pl));
+      widest = std::max(widest, smax[lev]);
+    }
   }
   // staging the levels launches (splits of the widest level) x samples x RAMs workgroups
-  const bool can_stage = smax.empty() || *std::max_element(smax.begin(), smax.end()) <= 4096;
+  const bool can_stage = widest <= 4096;
   const bool tm = timing && c->prof;
   for (uint64_t i0 = 0; i0 < n; i0 += n_sub) {
     const uint64_t m = n - i0 < n_sub ? n - i0 : n_sub;
@@ -635,7 +643,7 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
       const int occ = v & 4 ? 4 : 3;
       A.tree = (v & 2) && can_stage ? 0u : 1u;
       hipError_t e = hw::launch_train(c->logN, c->prm.nq, c->tabs, A, occ, st);
-      for (uint32_t lev = 0; e == hipSuccess && !A.tree && lev < smax.size(); ++lev) {
+      for (uint32_t lev = 0; e == hipSuccess && !A.tree && lev < levels; ++lev) {
         A.lev = lev;
         A.smax = smax[lev];
         e = hw::launch_train_level(c->logN, c->prm.nq, c->tabs, A, occ, st);

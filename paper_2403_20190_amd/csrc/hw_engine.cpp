@@ -223,6 +223,21 @@ static void finish_request(hw_engine* E, uint64_t id, Req& R, int state) {
   E->cv.notify_all();
 }
 
+// Per-model order: a training request starts only at the front of its
+// model's FIFO (every earlier request, training or inference, has finished);
+// an inference request starts once every request ahead of it is an
+// inference (they only read the model), so it sees exactly the training
+// submitted before it and no later training can change the model under it.
+static bool may_start(const hw_engine* E, const Job& J, uint64_t id, const Req& R) {
+  for (uint64_t f : J.fifo) {
+    if (f == id) return true;
+    if (R.r.kind == 0) return false;
+    const auto it = E->reqs.find(f);
+    if (it == E->reqs.end() || it->second.r.kind == 0) return false;
+  }
+  return false;
+}
+
 static void scheduler(hw_engine* E) {
   hipSetDevice(E->ctx->device);
   std::unique_lock<std::mutex> lk(E->mu);
@@ -266,7 +281,7 @@ static void scheduler(hw_engine* E) {
           if (R.inflight == 0) finish_request(E, id, R, R.state == HW_REQ_FAILED ? HW_REQ_FAILED : HW_REQ_CANCELLED);
           continue;
         }
-        if (J.fifo.empty() || J.fifo.front() != id) continue;  // an earlier request on this model runs
+        if (!may_start(E, J, id, R)) continue;  // an earlier request on this model must finish first
         if (R.next >= R.chunks) continue;
         if (R.r.kind == 0 && R.inflight > 0) continue;          // training chunks one at a time
         Slot* free_slot = nullptr;

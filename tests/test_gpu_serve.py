@@ -200,3 +200,44 @@ def test_submit_shape_checks():
         with pytest.raises(HW.HwError):
             eng.submit(j, "infer", X, 2, cells=cells)
     eng.close()
+
+
+def test_infer_requests_on_one_model_overlap():
+    """Inference requests only read the model: two of them on one model, with
+    no training between them, run at the same time (two chunks in flight on a
+    one-model engine), and each result equals the one it gives alone."""
+    import torch
+    from paper_2403_20190_amd import hwisard as HW
+    sk = torch.zeros(N, dtype=torch.int32, device="cuda")
+    HW.Context(N, NQ, PM).keygen(78, sk)
+    J = JOBS[0]
+    L = O.ceil_log2(J["l"])
+    Xt, yt = synth.prototype_bits(300, 6, J["s"], J["l"], flip=0.2)
+    Xa, _ = synth.prototype_bits(301, 8, J["s"], J["l"], flip=0.2)
+    Xb, _ = synth.prototype_bits(302, 8, J["s"], J["l"], flip=0.2)
+
+    def engine():
+        eng = HW.Engine(N, NQ, PM, sk, slots=2, chunk=8, max_s=64, max_cells=4096, arena_bytes=2 << 30)
+        ctx = HW.Context(N, NQ, PM)
+        sh = job_shape(HW, J)
+        H = model_buffer(ctx, sh)
+        jid = eng.add_job(sh, H)
+        assert eng.wait(eng.submit(jid, "train", Xt, 600, labels=label_bits(yt, L)))[0] == HW.REQ_DONE
+        return eng, jid, ctx.dims(sh)[0]
+
+    alone = []
+    for k, X in enumerate((Xa, Xb)):
+        eng, jid, k0 = engine()
+        cells = np.zeros((len(X), J["l"], k0), np.uint64)
+        assert eng.wait(eng.submit(jid, "infer", X, 610 + k, cells=cells))[0] == HW.REQ_DONE
+        alone.append(cells)
+        eng.close()
+    eng, jid, k0 = engine()
+    ca = np.zeros((len(Xa), J["l"], k0), np.uint64)
+    cb = np.zeros((len(Xb), J["l"], k0), np.uint64)
+    ra = eng.submit(jid, "infer", Xa, 610, cells=ca)
+    rb = eng.submit(jid, "infer", Xb, 611, cells=cb)
+    assert eng.wait(ra)[0] == HW.REQ_DONE and eng.wait(rb)[0] == HW.REQ_DONE
+    assert eng.stats()["peak_inflight"] == 2  # one chunk each, both in flight
+    eng.close()
+    assert np.array_equal(ca, alone[0]) and np.array_equal(cb, alone[1])

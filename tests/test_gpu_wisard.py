@@ -186,7 +186,8 @@ def test_mnist_shape_inference_sampled():
 
 def test_mnist_bench_launch_configuration():
     """The benchmark's launch configuration: one 50-sample chunk of the
-    MNIST shape trained in one call (50 x 196 workgroups) and 50 test samples
+    MNIST shape trained in one call (50 x 196 workgroups, every schedule of
+    the training call giving the same model) and 50 test samples
     inferred in one call (50 x 196 x 10).  RAM 97 against the oracle over all
     50 samples; every RAM by decryption against Alg. 4; sampled inference
     outputs against the oracle and every cell by decryption against Alg. 2."""
@@ -195,9 +196,20 @@ def test_mnist_bench_launch_configuration():
     bits = CL.thermometer(CL.quantize_u8(Xtr, 3), 3)
     pair = Pair(2048, 2, 1024, 2352, 10, 12, bits, ytr, seed=6)
     assert pair.n == 50
-    H, _, _, _ = train_dev(pair, class_count=False)
+    # every schedule of the training call: grid order x tree levels fused / staged
+    Hv = []
+    xr, yr = pair.encrypt_dev(), pair.encrypt_labels_dev()
+    for v in range(pair.ctx.tune_get("train")[2]):
+        pair.ctx.tune_set("train", v)
+        H = zeros_u32(pair.k0, pair.k1, 2, pair.nq, pair.N)
+        pair.ctx.train(pair.shape, xr, yr, pair.n, H, None)
+        Hv.append(host_u32(H))
+    del xr, yr
+    pair.ctx.tune_set("train", -1)
+    for v in range(1, len(Hv)):
+        assert np.array_equal(Hv[0], Hv[v]), v
     Ho = pair.oracle_train([97])
-    assert np.array_equal(host_u32(H)[97], Ho[97])
+    assert np.array_equal(Hv[0][97], Ho[97])
     W = P.train_integer(pair.X, pair.y, pair.l, pair.a, pair.pi)
     assert np.array_equal(decrypt_model(pair, H), P.expected_model_cells(W, pair.s, pair.l, pair.a, pair.N))
     tb = CL.thermometer(CL.quantize_u8(Xte, 3), 3)

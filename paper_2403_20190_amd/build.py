@@ -11,8 +11,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhwisard.so")
-SOURCES = ["hw_kernels.hip", "hw_microbench.hip", "hw_noalloc.hip", "hw_api.cpp", "hw_batch_run.cpp",
-           "hw_engine.cpp"]
+SOURCES = ["hw_kernels.hip", "hw_microbench.hip", "hw_noalloc.hip", "hw_pbs.hip", "hw_api.cpp",
+           "hw_batch_run.cpp", "hw_engine.cpp"]
 HEADERS = ["hw_device.h", "hw_internal.h", "hw_ctx.h"]
 
 FLAGS = [

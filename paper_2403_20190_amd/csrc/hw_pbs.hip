@@ -1,0 +1,508 @@
+// hw_pbs.hip -- programmable bootstrapping of LWE ciphertexts (Sec. 2.5.3) and
+// the Activate and EncryptedArgMax functions of OTF-act (Sec. 3.5.2, Alg. 7)
+// built from bootstraps that each decide one sign.
+//
+// Bootstrap (constant test polynomial V, mask length n <= N, key = the ring
+// key s, ternary): switch the ciphertext's mask and body from Q to 2N
+// (round(2N x / Q)), start from the trivial RLWE (0, X^{-b~} TV) with
+// TV = V (1 + X + ... + X^{N-1}), multiply it by X^{a~_k s_k} for k < n with
+// two CMUXes against bsk[2k] = RGSW([s_k = 1]) and bsk[2k+1] = RGSW([s_k = -1]),
+// and extract coefficient 0: V when the switched phase lies in [0, N), -V
+// otherwise.  The circuits (bits, activate_ge, argmax) combine bootstraps with
+// exact linear operations on LWE ciphertexts; their steps and constants are
+// stated at hw_activate_ge and hw_encrypted_argmax in include/hwisard.h.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/hwisard.h"
+#include "hw_ctx.h"
+#include "hw_device.h"
+
+namespace hw {
+namespace {
+
+typedef unsigned __int128 u128;
+
+__device__ __forceinline__ double u128_dbl(u128 x) {
+  return (double)(uint64_t)(x >> 64) * 18446744073709551616.0 + (double)(uint64_t)x;
+}
+
+// round(two_n x / Q) mod two_n (two_n a power of two) of the integer x in
+// [0, Q) with residues r, rounding half up: floor((two_n x + floor(Q/2)) / Q)
+template <int NQ>
+__device__ __forceinline__ uint32_t switch_2n(const uint32_t (&r)[NQ], const Tabs& T, const CrtTab& K,
+                                              uint32_t two_n) {
+  const u128 Q = ((u128)K.Q_hi << 64) | K.Q_lo;
+  u128 x = 0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const uint32_t y = mulq(r[i], K.inv[i], T.pt[i]);
+    const u128 M = ((u128)K.M_hi[i] << 64) | K.M_lo[i];
+    x += (u128)y * M;
+    if (x >= Q) x -= Q;
+  }
+  const u128 num = (u128)two_n * x + (((u128)K.half_hi << 64) | K.half_lo);
+  uint64_t qt = (uint64_t)(u128_dbl(num) / u128_dbl(Q));
+  while (qt > 0 && (u128)qt * Q > num) --qt;
+  while ((u128)(qt + 1) * Q <= num) ++qt;
+  return (uint32_t)(qt & (two_n - 1));
+}
+
+// modulus switch of `count` LWE ciphertexts: out[c][k] for the first n mask
+// coefficients, out[c][n] for the body; one thread per value
+template <int NQ>
+__global__ __launch_bounds__(256) void k_pbs_switch(Tabs T, CrtTab K, uint32_t N, uint32_t n,
+                                                    const uint32_t* __restrict__ lwe, uint64_t count,
+                                                    uint32_t* __restrict__ out) {
+  const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= count * (n + 1)) return;
+  const uint64_t c = g / (n + 1);
+  const uint32_t k = (uint32_t)(g - c * (n + 1));
+  const uint32_t idx = k < n ? k : N;
+  uint32_t r[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) r[i] = lwe[(c * NQ + i) * (N + 1) + idx];
+  out[g] = switch_2n<NQ>(r, T, K, 2 * N);
+}
+
+struct RotArgs {
+  const uint32_t* bsk;   // [2n] RGSW, device layout
+  const uint32_t* ms;    // [count][n + 1] switched mask and body
+  uint32_t* slots;       // [count][2] RLWE: the accumulator and the CMUX input
+  uint32_t* out;         // [count] LWE
+  uint64_t rgsw_words;
+  uint64_t count;
+  uint32_t n;
+  uint32_t v[MAXQ];      // V mod q_i
+};
+
+// xin <- X^ex acc - acc, each thread its coefficients t + T e of every polynomial
+template <int LOGN, int NQ>
+__device__ __forceinline__ void pbs_rot_diff(const Tabs& T, const uint32_t* __restrict__ acc, int32_t ex,
+                                             uint32_t* __restrict__ xin, uint32_t t) {
+  constexpr int N = 1 << LOGN, TT = N / 8;
+#pragma unroll 1
+  for (int w = 0; w < 2 * NQ; ++w) {
+    const uint32_t* f = acc + (size_t)w * N;
+    uint32_t* o = xin + (size_t)w * N;
+    const uint32_t q = T.pt[w % NQ].q;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int32_t k = t + TT * e;
+      (o + TT * e)[t] = subq(rot_coef<LOGN>(f, k, ex, q), (f + TT * e)[t], q);
+    }
+  }
+}
+
+// blind rotation and extraction: one workgroup per ciphertext
+template <int LOGN, int NQ>
+__global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_pbs_rotate(
+    Tabs T, RotArgs A) {
+  __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, xp_pair<LOGN, NQ>()>()];
+  __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
+  constexpr int N = 1 << LOGN, TT = N / 8;
+  constexpr size_t RW = (size_t)2 * NQ * N;
+  const uint32_t t = threadIdx.x;
+  const uint64_t c = blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
+  if (c >= A.count) return;
+  const uint32_t* ms = A.ms + c * (A.n + 1);
+  uint32_t* acc = A.slots + c * 2 * RW;
+  uint32_t* xin = acc + RW;
+  const uint32_t bt = ms[A.n];
+  // (0, X^{-b~} TV): coefficient k of X^{-b~} TV is V when (k + b~) mod 2N < N, else -V
+#pragma unroll 1
+  for (int w = 0; w < 2 * NQ; ++w) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t k = t + TT * e;
+      uint32_t val = 0;
+      if (w >= NQ) {
+        const uint32_t v = A.v[w - NQ], q = T.pt[w - NQ].q;
+        val = ((k + bt) & (2 * N - 1)) < (uint32_t)N ? v : (v ? q - v : 0u);
+      }
+      acc[(size_t)w * N + k] = val;
+    }
+  }
+  __syncthreads();
+  uint32_t xc = 0;
+#pragma unroll 1
+  for (uint32_t k = 0; k < A.n; ++k) {
+    const int32_t a = (int32_t)ms[k];
+#pragma unroll 1
+    for (int sg = 0; sg < 2; ++sg) {
+      pbs_rot_diff<LOGN, NQ>(T, acc, sg ? -a : a, xin, t);
+      ext_prod<LOGN, NQ>(xin, A.bsk + (size_t)(2 * k + sg) * A.rgsw_words, T, lds, twl, xc, t,
+                         XpOut{acc, acc, nullptr, XP_ADD});
+      __syncthreads();  // the next rotation reads coefficients other threads wrote
+    }
+  }
+  // ExtractLWE(ACC, 0): a'_0 = a_0, a'_j = -a_{N-j}, b' = b_0
+  uint32_t* o = A.out + c * (size_t)NQ * (N + 1);
+#pragma unroll 1
+  for (int i = 0; i < NQ; ++i) {
+    const uint32_t q = T.pt[i].q;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t j = t + TT * e;
+      const uint32_t av = acc[(size_t)i * N + (j ? N - j : 0)];
+      o[(size_t)i * (N + 1) + j] = j ? (av ? q - av : 0u) : av;
+    }
+    if (t == 0) o[(size_t)i * (N + 1) + N] = acc[(size_t)(NQ + i) * N];
+  }
+}
+
+struct LinArgs {
+  const uint32_t* x;   // [count] LWE at stride sx words
+  const uint32_t* y;   // may be null
+  uint32_t* out;       // may alias x or y (each word is read before it is written)
+  uint64_t sx, sy, so;
+  uint64_t count;
+  uint32_t N, nq;
+  uint32_t ax[MAXQ], by[MAXQ], g[MAXQ];  // residues of alpha, beta and the body constant
+};
+
+// out = alpha x + beta y + (0, g), mod each q_i
+__global__ __launch_bounds__(256) void k_lwe_lin(Tabs T, LinArgs A) {
+  const uint64_t lw = (uint64_t)A.nq * (A.N + 1);
+  const uint64_t w = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (w >= A.count * lw) return;
+  const uint64_t c = w / lw;
+  const uint32_t r = (uint32_t)(w - c * lw);
+  const uint32_t i = r / (A.N + 1), k = r - i * (A.N + 1);
+  const PrimeTab P = T.pt[i];
+  uint32_t v = mulq(A.ax[i], A.x[c * A.sx + r], P);
+  if (A.y) v = addq(v, mulq(A.by[i], A.y[c * A.sy + r], P), P.q);
+  if (k == A.N) v = addq(v, A.g[i], P.q);
+  A.out[c * A.so + r] = v;
+}
+
+// the bootstrapping-key bits of the first n key coefficients: [s_k = 1], [s_k = -1]
+__global__ void k_pbs_bits(const int32_t* __restrict__ sk, uint32_t n, uint8_t* __restrict__ bits) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  bits[2 * k] = sk[k] == 1;
+  bits[2 * k + 1] = sk[k] == -1;
+}
+
+}  // namespace
+}  // namespace hw
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+using hw::u128;
+
+// kernel templates for the supported (log2 N, primes)
+#define PBS_DISPATCH(logN, nq, ...)                                                  \
+  do {                                                                               \
+    if (logN == 10 && nq == 1) { constexpr int LN = 10, NQ = 1; __VA_ARGS__; }       \
+    else if (logN == 10 && nq == 2) { constexpr int LN = 10, NQ = 2; __VA_ARGS__; }  \
+    else if (logN == 10 && nq == 3) { constexpr int LN = 10, NQ = 3; __VA_ARGS__; }  \
+    else if (logN == 11 && nq == 1) { constexpr int LN = 11, NQ = 1; __VA_ARGS__; }  \
+    else if (logN == 11 && nq == 2) { constexpr int LN = 11, NQ = 2; __VA_ARGS__; }  \
+    else if (logN == 11 && nq == 3) { constexpr int LN = 11, NQ = 3; __VA_ARGS__; }  \
+    else if (logN == 12 && nq == 1) { constexpr int LN = 12, NQ = 1; __VA_ARGS__; }  \
+    else if (logN == 12 && nq == 2) { constexpr int LN = 12, NQ = 2; __VA_ARGS__; }  \
+    else if (logN == 12 && nq == 3) { constexpr int LN = 12, NQ = 3; __VA_ARGS__; }  \
+    else return hipErrorInvalidValue;                                                \
+  } while (0)
+
+struct Pbs {
+  hw_ctx* c;
+  const uint32_t* bsk;
+  uint32_t n;
+  hipStream_t st;
+  uint32_t* ms;     // [cmax][n + 1]
+  uint32_t* slots;  // [cmax][2] RLWE
+  size_t lw;        // words of an LWE ciphertext
+};
+
+uint32_t res_of(u128 x, uint32_t q) { return (uint32_t)(x % q); }
+
+// residue of a signed integer (|v| < 2^63) mod q
+uint32_t res_signed(int64_t v, uint32_t q) {
+  const int64_t r = v % (int64_t)q;
+  return (uint32_t)(r < 0 ? r + (int64_t)q : r);
+}
+
+// out = alpha x + beta y + (0, g) over `count` ciphertexts at the given strides (in LWE units)
+hipError_t lin(const Pbs& B, uint64_t count, uint32_t* out, uint64_t so, int64_t alpha, const uint32_t* x,
+               uint64_t sx, int64_t beta = 0, const uint32_t* y = nullptr, uint64_t sy = 0, u128 g = 0,
+               bool g_neg = false) {
+  hw_ctx* c = B.c;
+  hw::LinArgs A{};
+  A.x = x;
+  A.y = y;
+  A.out = out;
+  A.sx = sx * B.lw;
+  A.sy = sy * B.lw;
+  A.so = so * B.lw;
+  A.count = count;
+  A.N = c->prm.N;
+  A.nq = c->prm.nq;
+  for (uint32_t i = 0; i < c->prm.nq; ++i) {
+    const uint32_t q = c->tabs.pt[i].q;
+    A.ax[i] = res_signed(alpha, q);
+    A.by[i] = res_signed(beta, q);
+    const uint32_t gr = res_of(g, q);
+    A.g[i] = g_neg ? (gr ? q - gr : 0u) : gr;
+  }
+  const uint64_t words = count * B.lw;
+  if (!words) return hipSuccess;
+  hipLaunchKernelGGL(hw::k_lwe_lin, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, B.st, c->tabs, A);
+  return hipGetLastError();
+}
+
+// out[j] = PBS(in[j], V) for j < count (count <= the workspace's cmax); contiguous arrays
+hipError_t pbs(const Pbs& B, uint64_t count, const uint32_t* in, uint32_t* out, u128 V) {
+  hw_ctx* c = B.c;
+  if (!count) return hipSuccess;
+  const uint32_t N = c->prm.N, nq = c->prm.nq;
+  const uint64_t vals = count * (B.n + 1);
+  const dim3 gs((uint32_t)((vals + 255) / 256));
+  if (nq == 1) hipLaunchKernelGGL(hw::k_pbs_switch<1>, gs, dim3(256), 0, B.st, c->tabs, c->crt, N, B.n, in, count, B.ms);
+  else if (nq == 2) hipLaunchKernelGGL(hw::k_pbs_switch<2>, gs, dim3(256), 0, B.st, c->tabs, c->crt, N, B.n, in, count, B.ms);
+  else hipLaunchKernelGGL(hw::k_pbs_switch<3>, gs, dim3(256), 0, B.st, c->tabs, c->crt, N, B.n, in, count, B.ms);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hw::RotArgs A{};
+  A.bsk = B.bsk;
+  A.ms = B.ms;
+  A.slots = B.slots;
+  A.out = out;
+  A.rgsw_words = rgsw_words(c);
+  A.count = count;
+  A.n = B.n;
+  for (uint32_t i = 0; i < nq; ++i) A.v[i] = res_of(V, c->tabs.pt[i].q);
+  const dim3 g((uint32_t)std::min<uint64_t>(count, 65535), (uint32_t)((count + 65534) / 65535));
+  PBS_DISPATCH(c->logN, nq,
+               hipLaunchKernelGGL((hw::k_pbs_rotate<LN, NQ>), g, dim3(hw::Geo<LN>::T), 0, B.st, c->tabs, A));
+  return hipGetLastError();
+}
+
+// the bits of the messages of x (phase ~ floor(Q/p) m, m < p = 2^P), least
+// significant first: E[k] (count LWE each, contiguous) with phase ~ 2 V_b bit_k.
+// x is consumed (it ends as the encryption of 0); y and o are scratch.
+hipError_t bits(const Pbs& B, uint64_t count, uint32_t P, uint32_t* x, uint32_t* const* E, uint32_t* y,
+                uint32_t* o) {
+  const u128 Q = B.c->Q;
+  const u128 vb = (Q >> P) / 2;
+  for (uint32_t k = 0; k < P; ++k) {
+    hipError_t e = lin(B, count, y, 1, (int64_t)1 << (P - 1 - k), x, 1, 0, nullptr, 0, Q / 4);
+    if (e == hipSuccess) e = pbs(B, count, y, o, vb);
+    if (e == hipSuccess) e = lin(B, count, E[k], 1, -1, o, 1, 0, nullptr, 0, vb);
+    if (e == hipSuccess) e = lin(B, count, x, 1, 1, x, 1, -((int64_t)1 << k), E[k], 1);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hw_status pbs_setup(hw_ctx* c, const uint32_t* bsk, uint32_t n, uint64_t count, size_t extra_lwe, hipStream_t st,
+                    Pbs* B, uint64_t* cmax, uint32_t** lwes) {
+  B->c = c;
+  B->bsk = bsk;
+  B->n = n;
+  B->st = st;
+  B->lw = lwe_words(c);
+  // per ciphertext: the switched values, two RLWE slots, extra_lwe LWE temporaries
+  const size_t per = (size_t)(n + 1) * 4 + 2 * rlwe_words(c) * 4 + extra_lwe * B->lw * 4;
+  uint64_t m = std::max<uint64_t>(1, c->ws_budget / per);
+  m = std::min<uint64_t>(m, count);
+  CHECK(ensure_ws(c, m * per + 256));
+  uint32_t* base = static_cast<uint32_t*>(c->d_ws);
+  B->slots = base;
+  B->ms = base + m * 2 * rlwe_words(c);
+  *lwes = B->ms + ((m * (n + 1) + 63) / 64) * 64;
+  *cmax = m;
+  return HW_OK;
+}
+
+hw_status check_pbs(hw_ctx* c, const uint32_t* bsk, uint32_t n) {
+  if (!bsk) return fail(HW_EINVAL, "null bootstrapping key");
+  if (n < 1 || n > c->prm.N) return fail(HW_EINVAL, "n = %u out of range [1, N = %u]", n, c->prm.N);
+  return HW_OK;
+}
+
+}  // namespace
+
+extern "C" hw_status hw_pbs_keygen(hw_ctx* c, const int32_t* sk, uint64_t seed, uint32_t n, uint32_t* bsk,
+                                   hipStream_t st) {
+  CHECK(enter(c));
+  if (!sk || !bsk) return fail(HW_EINVAL, "null buffer");
+  if (n < 1 || n > c->prm.N) return fail(HW_EINVAL, "n = %u out of range [1, N = %u]", n, c->prm.N);
+  CHECK(ensure_ws(c, 2 * (size_t)n));
+  uint8_t* bits = static_cast<uint8_t*>(c->d_ws);
+  hipLaunchKernelGGL(hw::k_pbs_bits, dim3((n + 255) / 256), dim3(256), 0, st, sk, n, bits);
+  HIP_TRY(hipGetLastError());
+  return hw_encrypt_rgsw_bits(c, sk, bits, 2 * (uint64_t)n, seed, 0, bsk, st);
+}
+
+extern "C" hw_status hw_pbs(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* lwe, uint64_t count,
+                            const uint32_t* v, uint32_t* out, hipStream_t st) {
+  CHECK(enter(c));
+  CHECK(check_pbs(c, bsk, n));
+  if (count == 0) return ok();
+  if (!lwe || !out || !v) return fail(HW_EINVAL, "null buffer");
+  if (lwe == out) return fail(HW_EINVAL, "output must not alias input");
+  u128 V = 0;
+  {  // the constant from its residues (CRT), so that one value is used for every prime
+    for (uint32_t i = 0; i < c->prm.nq; ++i) {
+      if (v[i] >= c->tabs.pt[i].q) return fail(HW_EINVAL, "v[%u] not below q_%u", i, i);
+      const uint32_t q = c->tabs.pt[i].q;
+      const u128 M = c->Q / q;
+      const uint64_t y = (uint64_t)((u128)v[i] * c->crt.inv[i] % q);
+      V = (V + (u128)y * M) % c->Q;
+    }
+  }
+  Pbs B;
+  uint64_t cmax = 0;
+  uint32_t* tmp = nullptr;
+  CHECK(pbs_setup(c, bsk, n, count, 0, st, &B, &cmax, &tmp));
+  for (uint64_t c0 = 0; c0 < count; c0 += cmax) {
+    const uint64_t m = std::min(cmax, count - c0);
+    HIP_TRY(timed(c, "pbs", (double)m, st, [&] { return pbs(B, m, lwe + c0 * B.lw, out + c0 * B.lw, V); }));
+  }
+  return ok();
+}
+
+extern "C" hw_status hw_activate_ge(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* lwe,
+                                    uint64_t count, uint64_t T, uint32_t log_p_out, uint32_t* out,
+                                    hipStream_t st) {
+  CHECK(enter(c));
+  CHECK(check_pbs(c, bsk, n));
+  const uint64_t p = c->prm.plain_mod;
+  uint32_t P = 0;
+  while ((1ull << P) < p) ++P;
+  if (P < 3) return fail(HW_EINVAL, "the activation needs p >= 8 (p = %llu)", (unsigned long long)p);
+  if (T < 1 || T > p) return fail(HW_EINVAL, "T = %llu out of range [1, p = %llu]", (unsigned long long)T,
+                                  (unsigned long long)p);
+  if (log_p_out < 1 || log_p_out > 60) return fail(HW_EINVAL, "log_p_out = %u out of range [1, 60]", log_p_out);
+  if (count == 0) return ok();
+  if (!lwe || !out) return fail(HW_EINVAL, "null buffer");
+  const u128 Q = c->Q, vc = Q / 16, vo = (Q >> log_p_out) / 2;
+  // temporaries per ciphertext: x, y, o, carry and the P bits
+  Pbs B;
+  uint64_t cmax = 0;
+  uint32_t* tmp = nullptr;
+  CHECK(pbs_setup(c, bsk, n, count, 4 + P, st, &B, &cmax, &tmp));
+  const uint64_t t = p - T;
+  for (uint64_t c0 = 0; c0 < count; c0 += cmax) {
+    const uint64_t m = std::min(cmax, count - c0);
+    uint32_t* x = tmp;
+    uint32_t* y = x + cmax * B.lw;
+    uint32_t* o = y + cmax * B.lw;
+    uint32_t* carry = o + cmax * B.lw;
+    std::vector<uint32_t*> E(P);
+    for (uint32_t k = 0; k < P; ++k) E[k] = carry + (k + 1) * cmax * B.lw;
+    auto run = [&]() -> hipError_t {
+      hipError_t e = lin(B, m, x, 1, 1, lwe + c0 * B.lw, 1);
+      if (e == hipSuccess) e = bits(B, m, P, x, E.data(), y, o);
+      if (e == hipSuccess) e = lin(B, m, carry, 1, 0, x, 1);  // zero
+      for (uint32_t k = 0; e == hipSuccess && k < P; ++k) {
+        const u128 thr = ((t >> k) & 1) ? vc : 3 * vc;
+        const u128 V = k + 1 == P ? vo : vc;
+        e = lin(B, m, y, 1, (int64_t)1 << (P - 3), E[k], 1, 1, carry, 1, thr, true);
+        if (e == hipSuccess) e = pbs(B, m, y, o, V);
+        if (e == hipSuccess) e = lin(B, m, k + 1 == P ? out + c0 * B.lw : carry, 1, 1, o, 1, 0, nullptr, 0, V);
+      }
+      return e;
+    };
+    HIP_TRY(timed(c, "activate", (double)m, st, run));
+  }
+  return ok();
+}
+
+extern "C" hw_status hw_encrypted_argmax(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* u,
+                                         uint64_t count, uint32_t l, uint32_t log_p_in, uint32_t* out,
+                                         hipStream_t st) {
+  CHECK(enter(c));
+  CHECK(check_pbs(c, bsk, n));
+  if (l < 2 || l > 64) return fail(HW_EINVAL, "l = %u out of range [2, 64]", l);
+  if (log_p_in < 3 || log_p_in > 20) return fail(HW_EINVAL, "log_p_in = %u out of range [3, 20]", log_p_in);
+  if (count == 0) return ok();
+  if (!u || !out) return fail(HW_EINVAL, "null buffer");
+  const uint32_t P = log_p_in;
+  uint32_t L = 0;
+  while ((1u << L) < l) ++L;
+  const u128 Q = c->Q, vi = (Q >> P) / 2, vc = Q / 16, vx = (Q >> (L + 1)) / 2;
+  const u128 s8 = ((u128)1 << (P - 3)) * 2 * vi;
+  // temporaries per sample: d, y, o, acc, the P bits, l (l - 1) G values and l W values
+  const size_t ntmp = 4 + P + (size_t)l * (l - 1) + l;
+  Pbs B;
+  uint64_t cmax = 0;
+  uint32_t* tmp = nullptr;
+  CHECK(pbs_setup(c, bsk, n, count, ntmp, st, &B, &cmax, &tmp));
+  for (uint64_t c0 = 0; c0 < count; c0 += cmax) {
+    const uint64_t m = std::min(cmax, count - c0);
+    const size_t A = cmax * B.lw;  // words of one temporary array
+    uint32_t* d = tmp;
+    uint32_t* y = d + A;
+    uint32_t* o = y + A;
+    uint32_t* acc = o + A;
+    std::vector<uint32_t*> E(P);
+    for (uint32_t k = 0; k < P; ++k) E[k] = acc + (k + 1) * A;
+    uint32_t* G0 = acc + (P + 1) * A;
+    auto G = [&](uint32_t a, uint32_t b) { return G0 + ((size_t)a * (l - 1) + (b < a ? b : b - 1)) * A; };
+    uint32_t* W0 = G0 + (size_t)l * (l - 1) * A;
+    const uint32_t* ub = u + c0 * l * B.lw;  // sample j, class a at ub + (j l + a) lw
+    auto run = [&]() -> hipError_t {
+      hipError_t e = hipSuccess;
+      for (uint32_t a = 0; e == hipSuccess && a < l; ++a)
+        for (uint32_t b = a + 1; e == hipSuccess && b < l; ++b) {
+          e = lin(B, m, d, 1, 1, ub + a * B.lw, l, -1, ub + b * B.lw, l, (u128)(1ull << (P - 1)) * 2 * vi);
+          if (e == hipSuccess) e = bits(B, m, P, d, E.data(), y, o);
+          if (e == hipSuccess) e = lin(B, m, G(a, b), 1, (int64_t)1 << (P - 3), E[P - 1], 1);
+          if (e == hipSuccess) e = lin(B, m, G(b, a), 1, -1, G(a, b), 1, 0, nullptr, 0, s8);
+        }
+      for (uint32_t a = 0; e == hipSuccess && a < l; ++a) {
+        uint32_t* W = W0 + (size_t)a * A;
+        std::vector<uint32_t> others;
+        for (uint32_t b = 0; b < l; ++b)
+          if (b != a) others.push_back(b);
+        if (l == 2) {
+          e = lin(B, m, W, 1, 2, G(a, others[0]), 1);
+          continue;
+        }
+        e = lin(B, m, acc, 1, 1, G(a, others[0]), 1);
+        for (size_t j = 1; e == hipSuccess && j < others.size(); ++j) {
+          const bool last = j + 1 == others.size();
+          const u128 V = last ? vx : vc;
+          e = lin(B, m, y, 1, 1, acc, 1, 1, G(a, others[j]), 1, 3 * vc, true);
+          if (e == hipSuccess) e = pbs(B, m, y, o, V);
+          if (e == hipSuccess) e = lin(B, m, last ? W : acc, 1, 1, o, 1, 0, nullptr, 0, V);
+        }
+      }
+      // index = sum_a a W_a
+      if (e == hipSuccess) e = lin(B, m, out + c0 * B.lw, 1, 0, W0, 1);
+      for (uint32_t a = 1; e == hipSuccess && a < l; ++a)
+        e = lin(B, m, out + c0 * B.lw, 1, 1, out + c0 * B.lw, 1, a, W0 + (size_t)a * A, 1);
+      return e;
+    };
+    HIP_TRY(timed(c, "argmax", (double)m, st, run));
+  }
+  return ok();
+}
+
+extern "C" hw_status hw_class_sums(hw_ctx* c, const uint32_t* scores, uint64_t n, uint32_t l, uint32_t k0,
+                                   uint32_t* sums, hipStream_t st) {
+  CHECK(enter(c));
+  if (n == 0) return ok();
+  if (!scores || !sums) return fail(HW_EINVAL, "null buffer");
+  if (l < 1 || k0 < 1) return fail(HW_EINVAL, "l and k0 must be >= 1");
+  hw::SumArgs S{};
+  S.scores = scores;
+  S.sums = sums;
+  S.n = n;
+  S.l = l;
+  S.k0 = k0;
+  S.N = c->prm.N;
+  S.nq = c->prm.nq;
+  HIP_TRY(hw::launch_class_sums(c->tabs, S, st));
+  return ok();
+}

@@ -97,6 +97,11 @@ _SIG = {
     "hw_wisard_train_encrypted_noalloc": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_wisard_infer_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_rlwe_add": [_vp, _vp, _vp, _u64, _vp],
+    "hw_pbs_keygen": [_vp, _vp, _u64, _u32, _vp, _vp],
+    "hw_pbs": [_vp, _vp, _u32, _vp, _u64, _vp, _vp, _vp],
+    "hw_activate_ge": [_vp, _vp, _u32, _vp, _u64, _u64, _u32, _vp, _vp],
+    "hw_encrypted_argmax": [_vp, _vp, _u32, _vp, _u64, _u32, _u32, _vp, _vp],
+    "hw_class_sums": [_vp, _vp, _u64, _u32, _u32, _vp, _vp],
     "hw_pks_keygen": [_vp, _vp, _u64, _vp, _vp],
     "hw_pks_key_export_canonical": [_vp, _vp, _vp, _vp],
     "hw_pack_lwe": [_vp, _vp, _vp, _u32, _u64, _vp, _vp],
@@ -279,6 +284,29 @@ class Context:
         (a fixed library-held scratch; see NOALLOC_SCRATCH_BYTES)"""
         _check(_lib.hw_wisard_train_encrypted_noalloc(self._h, C.byref(sh), _ptr(x_rgsw), _ptr(y_rgsw), n,
                                                       _ptr(model), _ptr(class_count), _stream()))
+
+    # -- programmable bootstrapping: Activate and EncryptedArgMax (OTF-act) --------
+    def pbs_key_words(self, n: int) -> int:
+        """uint32 words of a bootstrapping key for the first n key coefficients"""
+        return 2 * n * self.rgsw_words
+
+    def pbs_keygen(self, sk, seed: int, n: int, bsk):
+        _check(_lib.hw_pbs_keygen(self._h, _ptr(sk), seed, n, _ptr(bsk), _stream()))
+
+    def pbs(self, bsk, n: int, lwe, count: int, V: int, out):
+        """bootstrap with the constant test polynomial V (an integer below Q)"""
+        v = np.array([V % q for q in self.primes], np.uint32)
+        _check(_lib.hw_pbs(self._h, _ptr(bsk), n, _ptr(lwe), count, v.ctypes.data_as(C.c_void_p), _ptr(out),
+                           _stream()))
+
+    def activate_ge(self, bsk, n: int, lwe, count: int, T: int, log_p_out: int, out):
+        _check(_lib.hw_activate_ge(self._h, _ptr(bsk), n, _ptr(lwe), count, T, log_p_out, _ptr(out), _stream()))
+
+    def class_sums(self, scores, n: int, l: int, k0: int, sums):
+        _check(_lib.hw_class_sums(self._h, _ptr(scores), n, l, k0, _ptr(sums), _stream()))
+
+    def encrypted_argmax(self, bsk, n: int, u, count: int, l: int, log_p_in: int, out):
+        _check(_lib.hw_encrypted_argmax(self._h, _ptr(bsk), n, _ptr(u), count, l, log_p_in, _ptr(out), _stream()))
 
     @property
     def pks_key_words(self) -> int:

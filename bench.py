@@ -41,7 +41,7 @@ WORKLOADS = {
     "wisconsin": dict(name="wisconsin-shaped 30 float features, 2 classes 357/212, therm 16 (480 bits), tuple 8, "
                            "400 train + 169 test, N=2048 x 2 primes",
                       N=2048, nq=2, p=512, l=2, a=8, T=16, n_train=400, n_test=169, chunk=100, balance=False,
-                      cpu_samples=12),
+                      cpu_samples=12, otf=16),
     "tiny": dict(name="tiny 8x8, 2 classes, therm 2, tuple 8, 32 train + 16 test, N=1024 x 1 prime",
                  N=1024, nq=1, p=64, l=2, a=8, T=2, n_train=32, n_test=16, chunk=32, balance=False),
 }
@@ -625,6 +625,8 @@ def main():
     if not args.no_extras:
         result["inference"], cells0 = infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev, peaks)
         result["class_packed"] = packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev, peaks)
+        if W.get("otf"):
+            result["otf_act"] = otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0)
         result["merge"] = merge_pass(ctx, H, k0, k1)
         result["ntt"] = ntt_pass(ctx, N, nq, dev)
         result["hbm_copy_gbs"] = hbm_copy(dev)
@@ -717,6 +719,69 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev, peaks=None):
         "n_test": nt, "pd_act": "bin", "test_accuracy": round(acc, 4),
         "packing": packed,
     }, cells
+
+
+def otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0):
+    """OTF-act (Sec. 3.5.2, Alg. 7) on the first W["otf"] test samples: every
+    per-RAM score activated with bin(thr = 0), i.e. [count >= 1], by the
+    bootstrapped circuit (hw_activate_ge), summed per class (hw_class_sums),
+    then EncryptedArgMax: only the class index is decrypted.  Compared with
+    the PD-act prediction of the same samples (decrypted cells, bin(0),
+    ArgMax on the client)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_20190_amd import client as CL
+    from paper_2403_20190_amd import hwisard as HW
+    N, nq, l, T = W["N"], W["nq"], W["l"], W["T"]
+    m = min(W["otf"], W["n_test"])
+    bits = CL.thermometer(levels_of(CL, W, Xte[:m], W.get("ref")), T)
+    s = bits.shape[1]
+    xr = torch.empty(m * s, ctx.rgsw_words, dtype=torch.int32, device=dev)
+    ctx.encrypt_rgsw_bits(sk, torch.from_numpy(bits).to(dev).reshape(-1), seeds["xt"], 0, xr)
+    sc = torch.empty(m, l, k0, ctx.lwe_words, dtype=torch.int32, device=dev)
+    ctx.infer(sh, H, xr, m, sc, None)
+    del xr
+    bsk = torch.empty(ctx.pbs_key_words(N), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.pbs_keygen(sk, seeds["key"] + 200, N, bsk)
+    torch.cuda.synchronize()
+    key_s = time.perf_counter() - t0
+    lp = (k0 + 1 - 1).bit_length() + 1  # class sums below p_out / 2
+    act = torch.empty(m * l * k0, ctx.lwe_words, dtype=torch.int32, device=dev)
+    sums = torch.empty(m, l, ctx.lwe_words, dtype=torch.int32, device=dev)
+    idx = torch.empty(m, ctx.lwe_words, dtype=torch.int32, device=dev)
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.activate_ge(bsk, N, sc, m * l * k0, 1, lp, act)
+    ctx.class_sums(act, m, l, k0, sums)
+    ctx.encrypted_argmax(bsk, N, sums, m, l, lp, idx)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    a_ms = ctx.profile_read("activate")[0]
+    g_ms = ctx.profile_read("argmax")[0]
+    ctx.profile(False)
+    L = (l - 1).bit_length()
+    dc = HW.Context(N, nq, 1 << (L + 1))
+    out = torch.empty(m, dtype=torch.int64, device=dev)
+    dc.decrypt_lwe(sk, idx, m, out)
+    got = out.cpu().numpy()
+    want = CL.pd_act_predict(cells0[:m], "bin", 0)
+    P = (W["p"] - 1).bit_length()
+    pbs_per_sample = l * k0 * 2 * P + (l * (l - 1) // 2) * lp + l * max(0, l - 2)
+    del bsk, act, sums, idx, sc
+    torch.cuda.empty_cache()
+    return {"samples": m, "activation": "bin, thr = 0: [count >= 1]", "bootstraps_per_sample": pbs_per_sample,
+            "external_products_per_bootstrap": 2 * N,
+            "seconds": round(dt, 3), "samples_per_s": round(m / dt, 4),
+            "activate_ms_per_sample": round(a_ms / m, 2), "argmax_ms_per_sample": round(g_ms / m, 2),
+            "external_products_per_s": round(m * pbs_per_sample * 2 * N / dt, 1),
+            "key_gib": round(ctx.pbs_key_words(N) * 4 / 2**30, 2), "keygen_s": round(key_s, 3),
+            "predictions_equal_pd_act": bool(np.array_equal(got, want)),
+            "paper_estimate": "OTF-act 3.7 min per inference at 9-bit precision on one thread (paper Table 9)"}
 
 
 def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev, peaks=None):

@@ -30,6 +30,15 @@ t = p - T, carry c_0 = 0, V_c = floor(Q/16), for k = 0 .. P-1:
 (with b_k + c_k in {0, 1, 2} at scale ~Q/8, subtracting Q/16 decides
 b_k OR c_k, subtracting 3Q/16 decides b_k AND c_k).
 
+fm_act(H, K, T, p_out): FM-act (Sec. 3.5.3), the activation applied once to
+every cell of a trained model: for every model row (one RLWE), the LWE of
+each of its coefficients 0..K-1 (ExtractLWE), activate_ge of it, and the K
+results packed back into one RLWE at the same coefficients
+(PackingKeySwitching, Sec. 2.5.1); coefficients from K on decrypt to 0.  K
+(fm_cells) covers every cell a RAM's index can address: with nb = ceil(log2
+l) + a index bits, cell m sits at coefficient m >> z, z = nb - min(nb, log2
+N), so K = 2^min(nb, log2 N); rows holding several RAMs fill all N.
+
 argmax(u, p_in): the index of the largest of l class scores s_c in
 [0, p_in/2) (phase ~ 2 V_i s_c, V_i = floor(Delta_{p_in} / 2)), ties to the
 lowest index: for c < c', D = s_c - s_c' + p_in/2 lies in [0, p_in) and its
@@ -161,3 +170,32 @@ def argmax(ctx, bsk, n: int, u, p_in: int) -> np.ndarray:
             acc = lin(ctx, [(1, ctx.pbs(bsk, z, n, V))], V)
         W.append(acc)
     return lin(ctx, [(c, W[c]) for c in range(1, l)])
+
+
+def fm_cells(N: int, l: int, a: int, layout: int = 0) -> int:
+    """coefficients of a model row that hold cells: 2^min(ceil(log2 l) + a,
+    log2 N), or N when a row holds several RAMs (layout 2)"""
+    logN = N.bit_length() - 1
+    nb = (l - 1).bit_length() + a
+    return N if layout == 2 else 1 << min(nb, logN)
+
+
+def fm_act(ctx, bsk, n: int, K_pks, H, cells: int, T: int, p_out: int) -> np.ndarray:
+    """FM-act of a model H (RLWE rows of any leading shape, [..][2][nq][N]):
+    each row's coefficients 0..cells-1 extracted, activated with [m >= T]
+    (activate_ge, output modulus p_out) and packed back into one RLWE"""
+    from . import _parallel
+    H = np.ascontiguousarray(H, np.uint32)
+    rows = H.reshape(-1, 2, ctx.nq, ctx.N)
+    jobs = [(r, i) for r in range(len(rows)) for i in range(cells)]
+    act = {}
+
+    def one(ri):
+        r, i = ri
+        act[ri] = activate_ge(ctx, bsk, n, ctx.extract_lwe(rows[r], i), T, p_out)
+
+    _parallel(one, jobs)
+    out = np.zeros_like(rows)
+    for r in range(len(rows)):
+        out[r] = ctx.pack_lwe(K_pks, np.stack([act[(r, i)] for i in range(cells)]))
+    return out.reshape(H.shape)

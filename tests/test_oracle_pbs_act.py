@@ -9,6 +9,9 @@ the whole key, as it does at full size:
 * the bit extraction returns the binary digits of the message, least
   significant first, across the carry boundaries of a 9-bit count;
 * activate_ge decrypts to [m >= T] on both sides of every threshold tried;
+* activate_log decrypts to floor(log2(m + 1)) and, with a cap, to
+  min(floor(log2(m + 1)), cap) (Sec. 2.4.2) on both sides of every power of
+  two, m = p - 1 (where m + 1 wraps to 0) included;
 * argmax decrypts to the index of the largest score, ties to the lowest.
 """
 import numpy as np
@@ -16,6 +19,7 @@ import pytest
 
 import oracle as O
 from oracle import pbs as B
+from oracle import plain as PL
 
 N, P_MOD = 128, 512
 
@@ -114,3 +118,18 @@ def test_argmax_index_with_ties_to_the_lowest(setup):
 
     for sc, got in zip(cases, run_all(one, cases)):
         assert got == int(np.argmax(sc)), sc
+
+
+def test_log_and_bounded_log_activations(setup):
+    ctx, s, bsk = setup
+    ms = sorted({0, 1, 2, 3} | {v for i in range(3, 10) for v in ((1 << i) - 2, (1 << i) - 1, (1 << i)) if v < P_MOD})
+    cases = [(m, cap) for m in ms for cap in (None, 1, 4)]
+
+    def one(mc):
+        m, cap = mc
+        x = B.encrypt_short(ctx, s, m, N, P_MOD, np.random.default_rng(5000 + m))
+        return B.decode(ctx, s, B.activate_log(ctx, bsk, N, x, 64, cap), 64)
+
+    for (m, cap), got in zip(cases, run_all(one, cases)):
+        want = int(PL.act_log(m)) if cap is None else int(PL.act_blog(m, cap))
+        assert got == want, (m, cap)

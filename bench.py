@@ -41,7 +41,7 @@ WORKLOADS = {
     "wisconsin": dict(name="wisconsin-shaped 30 float features, 2 classes 357/212, therm 16 (480 bits), tuple 8, "
                            "400 train + 169 test, N=2048 x 2 primes",
                       N=2048, nq=2, p=512, l=2, a=8, T=16, n_train=400, n_test=169, chunk=100, balance=False,
-                      cpu_samples=12, otf=16),
+                      cpu_samples=12, otf=16, fm=4, act=("log", 0)),
     "tiny": dict(name="tiny 8x8, 2 classes, therm 2, tuple 8, 32 train + 16 test, N=1024 x 1 prime",
                  N=1024, nq=1, p=64, l=2, a=8, T=2, n_train=32, n_test=16, chunk=32, balance=False),
 }
@@ -436,6 +436,8 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0, help="also run a plain device copy of this many MiB")
     ap.add_argument("--batched-scale", type=float, nargs="*", default=[1.0 / 64, 1.0 / 512],
                     help="job sizes of the 256-job batched workload are scaled by these factors")
+    ap.add_argument("--fm-full", action="store_true",
+                    help="wisconsin: FM-act of the whole model, then inference on it (minutes)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=200)
@@ -627,6 +629,8 @@ def main():
         result["class_packed"] = packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev, peaks)
         if W.get("otf"):
             result["otf_act"] = otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0)
+        if W.get("fm"):
+            result["fm_act"] = fm_pass(ctx, sh, H, sk, Xte, W, seeds, k0, k1, dev, cells0, args.fm_full)
         result["merge"] = merge_pass(ctx, H, k0, k1)
         result["ntt"] = ntt_pass(ctx, N, nq, dev)
         result["hbm_copy_gbs"] = hbm_copy(dev)
@@ -721,13 +725,42 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev, peaks=None):
     }, cells
 
 
+def act_max(kind: str, param: int, P: int) -> int:
+    """largest value the activation takes on m < 2^P"""
+    return 1 if kind == "ge" else (P if kind == "log" else min(param, P))
+
+
+def act_bootstraps(kind: str, param: int, P: int) -> int:
+    """bootstraps of one activation (hw_activate)"""
+    if kind == "ge":
+        return 2 * P
+    return 3 * P - 3 if kind == "log" or param >= P else 2 * P + param - 1
+
+
+def act_name(kind: str, param: int) -> str:
+    return {"ge": "bin, thr = %d: [count >= %d]" % (param - 1, param), "log": "log: floor(log2(count + 1))",
+            "blog": "b-log: min(floor(log2(count + 1)), %d)" % param}[kind]
+
+
+def act_plain(CL, x, kind: str, param: int):
+    """the activation in the clear (the client's functions)"""
+    return CL.activate(x, *{"ge": ("bin", param - 1, 4), "log": ("log", 0, 4), "blog": ("blog", 0, param)}[kind])
+
+
+def pd_predict(CL, cells, kind: str, param: int):
+    """PD-act predictions with the same activation"""
+    k, thr, cap = {"ge": ("bin", param - 1, 4), "log": ("log", 0, 4), "blog": ("blog", 0, param)}[kind]
+    return CL.pd_act_predict(cells, k, thr, cap)
+
+
 def otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0):
     """OTF-act (Sec. 3.5.2, Alg. 7) on the first W["otf"] test samples: every
-    per-RAM score activated with bin(thr = 0), i.e. [count >= 1], by the
-    bootstrapped circuit (hw_activate_ge), summed per class (hw_class_sums),
+    per-RAM score activated with the model's activation (W["act"]: the
+    paper's parameter table gives the Wisconsin model log) by the
+    bootstrapped circuit (hw_activate), summed per class (hw_class_sums),
     then EncryptedArgMax: only the class index is decrypted.  Compared with
-    the PD-act prediction of the same samples (decrypted cells, bin(0),
-    ArgMax on the client)."""
+    the PD-act prediction of the same samples (decrypted cells, the same
+    activation, ArgMax on the client)."""
     import numpy as np
     import torch
 
@@ -748,7 +781,9 @@ def otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0):
     ctx.pbs_keygen(sk, seeds["key"] + 200, N, bsk)
     torch.cuda.synchronize()
     key_s = time.perf_counter() - t0
-    lp = (k0 + 1 - 1).bit_length() + 1  # class sums below p_out / 2
+    kind, param = W["act"]
+    P = (W["p"] - 1).bit_length()
+    lp = (k0 * act_max(kind, param, P)).bit_length() + 1  # class sums below p_out / 2
     act = torch.empty(m * l * k0, ctx.lwe_words, dtype=torch.int32, device=dev)
     sums = torch.empty(m, l, ctx.lwe_words, dtype=torch.int32, device=dev)
     idx = torch.empty(m, ctx.lwe_words, dtype=torch.int32, device=dev)
@@ -756,7 +791,7 @@ def otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0):
     ctx.profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.activate_ge(bsk, N, sc, m * l * k0, 1, lp, act)
+    ctx.activate(bsk, N, sc, m * l * k0, kind, param, lp, act)
     ctx.class_sums(act, m, l, k0, sums)
     ctx.encrypted_argmax(bsk, N, sums, m, l, lp, idx)
     torch.cuda.synchronize()
@@ -769,12 +804,12 @@ def otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0):
     out = torch.empty(m, dtype=torch.int64, device=dev)
     dc.decrypt_lwe(sk, idx, m, out)
     got = out.cpu().numpy()
-    want = CL.pd_act_predict(cells0[:m], "bin", 0)
-    P = (W["p"] - 1).bit_length()
-    pbs_per_sample = l * k0 * 2 * P + (l * (l - 1) // 2) * lp + l * max(0, l - 2)
+    want = pd_predict(CL, cells0[:m], kind, param)
+    pbs_per_sample = l * k0 * act_bootstraps(kind, param, P) + (l * (l - 1) // 2) * lp + l * max(0, l - 2)
     del bsk, act, sums, idx, sc
     torch.cuda.empty_cache()
-    return {"samples": m, "activation": "bin, thr = 0: [count >= 1]", "bootstraps_per_sample": pbs_per_sample,
+    return {"samples": m, "activation": act_name(kind, param), "output_modulus": 1 << lp,
+            "bootstraps_per_sample": pbs_per_sample,
             "external_products_per_bootstrap": 2 * N,
             "seconds": round(dt, 3), "samples_per_s": round(m / dt, 4),
             "activate_ms_per_sample": round(a_ms / m, 2), "argmax_ms_per_sample": round(g_ms / m, 2),
@@ -782,6 +817,92 @@ def otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0):
             "key_gib": round(ctx.pbs_key_words(N) * 4 / 2**30, 2), "keygen_s": round(key_s, 3),
             "predictions_equal_pd_act": bool(np.array_equal(got, want)),
             "paper_estimate": "OTF-act 3.7 min per inference at 9-bit precision on one thread (paper Table 9)"}
+
+
+def fm_pass(ctx, sh, H, sk, Xte, W, seeds, k0, k1, dev, cells0, full=False):
+    """FM-act (Sec. 3.5.3): the model's cells activated once with the
+    model's activation (W["act"]) by bootstraps and packed back into their
+    rows (hw_fm_act).  By default the first W["fm"] RAMs (every cell of their
+    rows), timed, with the full model's time extrapolated from the cell
+    rate; each activated cell is checked against the decrypted cell.  With
+    `full`, the whole model, then inference on it for the first W["otf"]
+    test samples (VP, class sums, EncryptedArgMax: Alg. 7's FM-act branch),
+    compared with the PD-act prediction of the same samples."""
+    import numpy as np
+    import torch
+
+    from paper_2403_20190_amd import client as CL
+    from paper_2403_20190_amd import hwisard as HW
+    N, nq, l, a, T = W["N"], W["nq"], W["l"], W["a"], W["T"]
+    rows = k0 if full else min(W["fm"], k0)
+    shs = sh if full else HW.shape(rows * a, l, a, seeds["perm"], 0)  # the first `rows` RAMs
+    src = H.view(k0 * k1, -1)[: rows * k1]
+    bsk = torch.empty(ctx.pbs_key_words(N), dtype=torch.int32, device=dev)
+    key = torch.empty(ctx.pks_key_words, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.pbs_keygen(sk, seeds["key"] + 300, N, bsk)
+    ctx.pks_keygen(sk, seeds["key"] + 301, key)
+    torch.cuda.synchronize()
+    key_s = time.perf_counter() - t0
+    kind, param = W["act"]
+    P = (W["p"] - 1).bit_length()
+    lp = (k0 * act_max(kind, param, P)).bit_length() + 1  # class sums below p_out / 2
+    act = torch.empty_like(src)
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.fm_act(shs, bsk, N, key, src, kind, param, lp, act)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = {k: ctx.profile_read(k)[0] for k in ("extract_cells", "activate", "pack_lwe")}
+    ctx.profile(False)
+    K = 1 << min((l - 1).bit_length() + a, N.bit_length() - 1)
+    cells = rows * k1 * K
+    dec0 = torch.empty(rows * k1, N, dtype=torch.int64, device=dev)
+    ctx.decrypt_rlwe(sk, src, rows * k1, dec0)
+    dc = HW.Context(N, nq, 1 << lp)
+    dec1 = torch.empty(rows * k1, N, dtype=torch.int64, device=dev)
+    dc.decrypt_rlwe(sk, act, rows * k1, dec1)
+    want = act_plain(CL, dec0.cpu().numpy(), kind, param)
+    want[:, K:] = 0
+    nb = act_bootstraps(kind, param, P)
+    out = {"rams": rows, "cells": cells, "activation": act_name(kind, param), "output_modulus": 1 << lp,
+           "bootstraps_per_cell": nb, "external_products_per_bootstrap": 2 * N,
+           "seconds": round(dt, 3), "cells_per_s": round(cells / dt, 2),
+           "external_products_per_s": round(cells * nb * 2 * N / dt, 1),
+           "ms": {k: round(v, 1) for k, v in ms.items()},
+           "full_model_cells": k0 * k1 * K, "full_model_s": round(k0 * k1 * K / (cells / dt), 1),
+           "keygen_s": round(key_s, 3), "pks_key_gib": round(ctx.pks_key_words * 4 / 2**30, 2),
+           "activated_cells_equal": bool(np.array_equal(dec1.cpu().numpy(), want)),
+           "paper_estimate": "FM-act 0.1 h for the Wisconsin model at 9-bit precision on 64 threads (paper Table 9)"}
+    if full:
+        m = min(W["otf"], W["n_test"])
+        bits = CL.thermometer(levels_of(CL, W, Xte[:m], W.get("ref")), T)
+        s = bits.shape[1]
+        xr = torch.empty(m * s, ctx.rgsw_words, dtype=torch.int32, device=dev)
+        ctx.encrypt_rgsw_bits(sk, torch.from_numpy(bits).to(dev).reshape(-1), seeds["xt"], 0, xr)
+        sc = torch.empty(m, l, k0, ctx.lwe_words, dtype=torch.int32, device=dev)
+        sums = torch.empty(m, l, ctx.lwe_words, dtype=torch.int32, device=dev)
+        idx = torch.empty(m, ctx.lwe_words, dtype=torch.int32, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.infer(sh, act.view(H.shape), xr, m, sc, None)
+        ctx.class_sums(sc, m, l, k0, sums)
+        ctx.encrypted_argmax(bsk, N, sums, m, l, lp, idx)
+        torch.cuda.synchronize()
+        di = time.perf_counter() - t0
+        L = (l - 1).bit_length()
+        got = torch.empty(m, dtype=torch.int64, device=dev)
+        HW.Context(N, nq, 1 << (L + 1)).decrypt_lwe(sk, idx, m, got)
+        out["inference"] = {"samples": m, "seconds": round(di, 3), "samples_per_s": round(m / di, 3),
+                            "predictions_equal_pd_act": bool(np.array_equal(got.cpu().numpy(),
+                                                                            pd_predict(CL, cells0[:m], kind, param)))}
+        del xr, sc, sums, idx
+    del bsk, key, act, dec0, dec1
+    torch.cuda.empty_cache()
+    return out
 
 
 def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev, peaks=None):

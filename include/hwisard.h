@@ -326,6 +326,30 @@ hw_status hw_pbs(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const uint32_
 hw_status hw_activate_ge(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const uint32_t* lwe_dev,
                          uint64_t count, uint64_t T, uint32_t log_p_out, uint32_t* out_dev, hipStream_t stream);
 
+/* The activations of Sec. 2.4.2 that the paper's models use (its parameter
+ * table: bin with a threshold, log, b-log), as bootstrapped circuits over
+ * `count` LWE (phase ~ floor(Q/p) m, m in [0, p), p >= 8), output phase
+ * ~ 2 V_o f(m), V_o = floor(floor(Q / 2^log_p_out) / 2), 1 <= log_p_out <= 60:
+ *   HW_ACT_GE   f(m) = [m >= param], 1 <= param <= p (hw_activate_ge; bin
+ *               with thr = param - 1), 2P bootstraps;
+ *   HW_ACT_LOG  f(m) = floor(log2(m + 1)) (param ignored), 3P - 3 bootstraps;
+ *   HW_ACT_BLOG f(m) = min(floor(log2(m + 1)), param), param >= 1 (param >= P
+ *               is log), 2P + param - 1 bootstraps.
+ * log and b-log: x' = x + (0, floor(Q/p)) encrypts m' = m + 1 mod p (0 only
+ * for m = p - 1); E = the bits of m' (as in hw_activate_ge); with o_i = [m' >=
+ * 2^i] = the OR of bits i..P-1, f = sum_{i=1}^{c} o_i + c (1 - o_0), c = P
+ * (log, the sum up to P - 1) or the cap.  The ORs run from the top:
+ * o = 2^(P-3) E_(P-1); for i = P-2 .. 0, z_i = 2^(P-3) E_i + o - V_c, and
+ * for i >= 1 o = PBS(z_i, V_c) + V_c; each needed o_i is bootstrapped again
+ * at the output scale, PBS(z_i, V_o) + V_o (o_(P-1) from 2^(P-3) E_(P-1) - V_c).
+ * lwe_dev, out_dev: [count] LWE.  HW_EINVAL for a kind, param or log_p_out
+ * out of range, before anything runs. */
+#define HW_ACT_GE 0u
+#define HW_ACT_LOG 1u
+#define HW_ACT_BLOG 2u
+hw_status hw_activate(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const uint32_t* lwe_dev, uint64_t count,
+                      uint32_t kind, uint64_t param, uint32_t log_p_out, uint32_t* out_dev, hipStream_t stream);
+
 /* EncryptedArgMax (Alg. 7): for each of `count` samples, the l class scores
  * u[j][c] (phase ~ 2 V_i s_c, V_i = floor(floor(Q / p_in) / 2),
  * p_in = 2^log_p_in >= 8, every s_c < p_in / 2) give out[j], an LWE of the
@@ -349,6 +373,26 @@ hw_status hw_encrypted_argmax(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, 
  * scores_dev: [n][l][k0] LWE; sums_dev: [n][l] LWE. */
 hw_status hw_class_sums(hw_ctx* ctx, const uint32_t* scores_dev, uint64_t n, uint32_t l, uint32_t k0,
                         uint32_t* sums_dev, hipStream_t stream);
+
+/* FM-act (Sec. 3.5.3): the activation applied once to every cell of a
+ * trained model, so that inference on the result (hw_wisard_infer_encrypted,
+ * hw_class_sums, hw_encrypted_argmax: Alg. 7's FM-act branch) needs no
+ * bootstrap.  For every model RLWE, coefficients 0..K-1 are taken out as LWE
+ * (ExtractLWE at each coefficient), activated as in hw_activate (kind and
+ * param, output plaintext modulus 2^log_p_out) and packed back into one RLWE at the
+ * same coefficients (hw_pack_lwe with pks_key_dev); coefficients from K on
+ * decrypt to 0.  K covers every cell a RAM's index can address: 2^min(L + a,
+ * log2 N) for layouts 0 and 1, N for layout 2.  model_dev, out_dev: the
+ * model of `shape` (hw_wisard_model_rows x k1 RLWE, coefficient domain,
+ * plaintext modulus the context's p); out_dev may be model_dev itself (in
+ * place) but must not overlap it otherwise.  K times the activation's
+ * bootstraps per RLWE.  The call works through the rows in chunks of about 65,536
+ * cells, allocates two LWE buffers of that many cells for the call and
+ * waits for the stream before returning.  Errors as hw_activate and
+ * hw_pack_lwe, checked before anything runs. */
+hw_status hw_fm_act(hw_ctx* ctx, const hw_wisard_shape* shape, const uint32_t* bsk_dev, uint32_t n,
+                    const uint32_t* pks_key_dev, const uint32_t* model_dev, uint32_t kind, uint64_t param,
+                    uint32_t log_p_out, uint32_t* out_dev, hipStream_t stream);
 
 /* Merge of models trained apart (Sec. 3.7.2: Integer WiSARD models of
  * federated entities are merged by adding their RAMs; the merged model is
@@ -599,7 +643,7 @@ hw_status hw_microbench(int device, const char* kind, uint64_t size, double* rat
  * names: "train", "reduce", "train_batch", "reduce_batch", "batch_plan" (a whole
  * plan replay), "infer", "class_sums", "encrypt_rgsw", "encrypt_rlwe",
  * "decrypt_rlwe", "decrypt_lwe", "xp", "ntt", "rlwe_add",
- * "encrypt_pks", "pack_lwe", "pbs", "activate", "argmax". */
+ * "encrypt_pks", "pack_lwe", "pbs", "activate", "argmax", "extract_cells". */
 hw_status hw_profile_enable(hw_ctx* ctx, int enable);
 
 /* Waits for the recorded events and returns, for kernel `name`, the summed

@@ -8,8 +8,11 @@
 // train or infer against the resident model, and for inference decrypt the
 // PD-act cells and copy them to pinned host memory.  An event marks the end;
 // the scheduler polls the events, retires chunks and completes requests.
-// Requests on one model run in submission order; a training request has at
-// most one chunk in flight (its chunks update the model one after another).
+// Chunks start in submission order (first come, first served; slots that the
+// earliest requests cannot use go to later ones).  Requests on one model
+// keep their order: a training request waits for every earlier request on
+// its model and has at most one chunk in flight (its chunks update the model
+// one after another); inference requests behind inference requests overlap.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -269,32 +272,37 @@ static void scheduler(hw_engine* E) {
         finish_request(E, S.run.req, R, R.state == HW_REQ_FAILED ? HW_REQ_FAILED
                                                                  : (all ? HW_REQ_DONE : HW_REQ_CANCELLED));
     }
-    // start chunks: round robin over admitted requests, one chunk per request per pass
-    bool started = true;
-    while (started) {
-      started = false;
-      for (uint64_t id : std::vector<uint64_t>(E->active)) {
-        Req& R = E->reqs[id];
-        Job& J = E->jobs[R.r.job];
-        if (R.state >= HW_REQ_DONE) continue;  // finished earlier in this pass
-        if (R.cancel) {
-          if (R.inflight == 0) finish_request(E, id, R, R.state == HW_REQ_FAILED ? HW_REQ_FAILED : HW_REQ_CANCELLED);
-          continue;
-        }
-        if (!may_start(E, J, id, R)) continue;  // an earlier request on this model must finish first
-        if (R.next >= R.chunks) continue;
-        if (R.r.kind == 0 && R.inflight > 0) continue;          // training chunks one at a time
+    // start chunks in submission order: a request takes every free slot it can
+    // use before a later request gets one (first come, first served); the
+    // slots it cannot use -- a training request runs one chunk at a time, a
+    // request may be waiting for an earlier one on its model or for arena
+    // memory -- go to the later requests
+    bool slots_left = true;
+    for (uint64_t id : std::vector<uint64_t>(E->active)) {
+      if (!slots_left) break;
+      Req& R = E->reqs[id];
+      Job& J = E->jobs[R.r.job];
+      if (R.state >= HW_REQ_DONE) continue;  // finished earlier in this pass
+      if (R.cancel) {
+        if (R.inflight == 0) finish_request(E, id, R, R.state == HW_REQ_FAILED ? HW_REQ_FAILED : HW_REQ_CANCELLED);
+        continue;
+      }
+      if (!may_start(E, J, id, R)) continue;  // an earlier request on this model must finish first
+      while (R.next < R.chunks && !R.cancel && !(R.r.kind == 0 && R.inflight > 0)) {  // training: one at a time
         Slot* free_slot = nullptr;
         for (Slot& S : E->slots)
           if (!S.busy) {
             free_slot = &S;
             break;
           }
-        if (!free_slot) break;
+        if (!free_slot) {
+          slots_left = false;
+          break;
+        }
         const uint64_t off = R.next * E->cfg.chunk;
         const uint64_t m = std::min<uint64_t>(E->cfg.chunk, R.r.n - off);
         size_t ao = 0;
-        if (!E->alloc.alloc(chunk_bytes(E, J, R.r.kind, m), &ao)) continue;  // wait for memory
+        if (!E->alloc.alloc(chunk_bytes(E, J, R.r.kind, m), &ao)) break;  // wait for memory
         Slot& S = *free_slot;
         S.run = Run{id, R.next, off, m, ao};
         S.busy = true;
@@ -304,6 +312,7 @@ static void scheduler(hw_engine* E) {
         E->inflight += 1;
         E->peak_inflight = std::max(E->peak_inflight, E->inflight);
         E->started += 1;
+        progress = true;
         const hw_status st = launch_chunk(E, S, R, J);
         if (st != HW_OK) {
           // nothing of this chunk may still run: wait for the slot before reuse
@@ -317,7 +326,6 @@ static void scheduler(hw_engine* E) {
           R.inflight -= 1;
           if (R.inflight == 0) finish_request(E, id, R, HW_REQ_FAILED);
         }
-        started = progress = true;
       }
     }
     if (E->stop && E->inflight == 0) break;

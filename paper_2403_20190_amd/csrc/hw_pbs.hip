@@ -179,6 +179,38 @@ __global__ __launch_bounds__(256) void k_lwe_lin(Tabs T, LinArgs A) {
   A.out[c * A.so + r] = v;
 }
 
+// ExtractLWE at coefficients 0..K-1 of each of `rows` RLWE (coefficient
+// domain): cell (r, k) gets a'_j = a_{k-j} for j <= k, -a_{N+k-j} for j > k,
+// b' = b_k, as [prime][N + 1]; one thread per output word
+struct CellArgs {
+  const uint32_t* rows;  // [rows][2][nq][N]
+  uint32_t* out;         // [rows][K] LWE
+  uint64_t nrows;
+  uint32_t K, N, nq;
+};
+
+__global__ __launch_bounds__(256) void k_extract_cells(Tabs T, CellArgs A) {
+  const uint64_t lw = (uint64_t)A.nq * (A.N + 1);
+  const uint64_t w = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (w >= A.nrows * A.K * lw) return;
+  const uint64_t cell = w / lw;
+  const uint32_t rem = (uint32_t)(w - cell * lw);
+  const uint32_t i = rem / (A.N + 1), j = rem - i * (A.N + 1);
+  const uint64_t r = cell / A.K;
+  const uint32_t k = (uint32_t)(cell - r * A.K);
+  const uint32_t* row = A.rows + r * 2 * A.nq * A.N;
+  uint32_t v;
+  if (j == A.N) {
+    v = row[(size_t)(A.nq + i) * A.N + k];
+  } else if (j <= k) {
+    v = row[(size_t)i * A.N + (k - j)];
+  } else {
+    const uint32_t x = row[(size_t)i * A.N + (A.N + k - j)];
+    v = x ? T.pt[i].q - x : 0u;
+  }
+  A.out[w] = v;
+}
+
 // the bootstrapping-key bits of the first n key coefficients: [s_k = 1], [s_k = -1]
 __global__ void k_pbs_bits(const int32_t* __restrict__ sk, uint32_t n, uint8_t* __restrict__ bits) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -323,6 +355,10 @@ hw_status pbs_setup(hw_ctx* c, const uint32_t* bsk, uint32_t n, uint64_t count, 
   return HW_OK;
 }
 
+// FM-act works through the model in chunks of about this many cells (two
+// LWE buffers of that size are allocated for the call)
+constexpr uint64_t FM_CHUNK_CELLS = 65536;
+
 hw_status check_pbs(hw_ctx* c, const uint32_t* bsk, uint32_t n) {
   if (!bsk) return fail(HW_EINVAL, "null bootstrapping key");
   if (n < 1 || n > c->prm.N) return fail(HW_EINVAL, "n = %u out of range [1, N = %u]", n, c->prm.N);
@@ -371,51 +407,95 @@ extern "C" hw_status hw_pbs(hw_ctx* c, const uint32_t* bsk, uint32_t n, const ui
   return ok();
 }
 
-extern "C" hw_status hw_activate_ge(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* lwe,
-                                    uint64_t count, uint64_t T, uint32_t log_p_out, uint32_t* out,
-                                    hipStream_t st) {
-  CHECK(enter(c));
+// the activation of `kind` (HW_ACT_*) over `count` LWE: the argument checks of
+// hw_activate, then the circuits stated there
+static hw_status activate_core(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* lwe, uint64_t count,
+                               uint32_t kind, uint64_t param, uint32_t log_p_out, uint32_t* out, hipStream_t st) {
   CHECK(check_pbs(c, bsk, n));
   const uint64_t p = c->prm.plain_mod;
   uint32_t P = 0;
   while ((1ull << P) < p) ++P;
   if (P < 3) return fail(HW_EINVAL, "the activation needs p >= 8 (p = %llu)", (unsigned long long)p);
-  if (T < 1 || T > p) return fail(HW_EINVAL, "T = %llu out of range [1, p = %llu]", (unsigned long long)T,
-                                  (unsigned long long)p);
+  if (kind > HW_ACT_BLOG) return fail(HW_EINVAL, "kind = %u: must be HW_ACT_GE, HW_ACT_LOG or HW_ACT_BLOG", kind);
+  if (kind == HW_ACT_GE && (param < 1 || param > p))
+    return fail(HW_EINVAL, "T = %llu out of range [1, p = %llu]", (unsigned long long)param, (unsigned long long)p);
+  if (kind == HW_ACT_BLOG && param < 1) return fail(HW_EINVAL, "the b-log cap must be >= 1");
   if (log_p_out < 1 || log_p_out > 60) return fail(HW_EINVAL, "log_p_out = %u out of range [1, 60]", log_p_out);
   if (count == 0) return ok();
   if (!lwe || !out) return fail(HW_EINVAL, "null buffer");
   const u128 Q = c->Q, vc = Q / 16, vo = (Q >> log_p_out) / 2;
-  // temporaries per ciphertext: x, y, o, carry and the P bits
+  // temporaries per ciphertext: x, y, o, the carry or OR chain, and the P bits
   Pbs B;
   uint64_t cmax = 0;
   uint32_t* tmp = nullptr;
   CHECK(pbs_setup(c, bsk, n, count, 4 + P, st, &B, &cmax, &tmp));
-  const uint64_t t = p - T;
+  // log / b-log: outputs o_1 .. o_top, constant k (1 - o_0)
+  const uint32_t top = kind == HW_ACT_LOG || param >= P ? P - 1 : (uint32_t)param;
+  const int64_t kc = kind == HW_ACT_LOG || param >= P ? P : (int64_t)param;
   for (uint64_t c0 = 0; c0 < count; c0 += cmax) {
     const uint64_t m = std::min(cmax, count - c0);
     uint32_t* x = tmp;
     uint32_t* y = x + cmax * B.lw;
     uint32_t* o = y + cmax * B.lw;
-    uint32_t* carry = o + cmax * B.lw;
+    uint32_t* chain = o + cmax * B.lw;
+    uint32_t* res = out + c0 * B.lw;
     std::vector<uint32_t*> E(P);
-    for (uint32_t k = 0; k < P; ++k) E[k] = carry + (k + 1) * cmax * B.lw;
-    auto run = [&]() -> hipError_t {
+    for (uint32_t k = 0; k < P; ++k) E[k] = chain + (k + 1) * cmax * B.lw;
+    auto run_ge = [&]() -> hipError_t {
+      const uint64_t t = p - param;
       hipError_t e = lin(B, m, x, 1, 1, lwe + c0 * B.lw, 1);
       if (e == hipSuccess) e = bits(B, m, P, x, E.data(), y, o);
-      if (e == hipSuccess) e = lin(B, m, carry, 1, 0, x, 1);  // zero
+      if (e == hipSuccess) e = lin(B, m, chain, 1, 0, x, 1);  // carry 0
       for (uint32_t k = 0; e == hipSuccess && k < P; ++k) {
         const u128 thr = ((t >> k) & 1) ? vc : 3 * vc;
         const u128 V = k + 1 == P ? vo : vc;
-        e = lin(B, m, y, 1, (int64_t)1 << (P - 3), E[k], 1, 1, carry, 1, thr, true);
+        e = lin(B, m, y, 1, (int64_t)1 << (P - 3), E[k], 1, 1, chain, 1, thr, true);
         if (e == hipSuccess) e = pbs(B, m, y, o, V);
-        if (e == hipSuccess) e = lin(B, m, k + 1 == P ? out + c0 * B.lw : carry, 1, 1, o, 1, 0, nullptr, 0, V);
+        if (e == hipSuccess) e = lin(B, m, k + 1 == P ? res : chain, 1, 1, o, 1, 0, nullptr, 0, V);
       }
       return e;
     };
-    HIP_TRY(timed(c, "activate", (double)m, st, run));
+    auto run_log = [&]() -> hipError_t {
+      const int64_t sh = (int64_t)1 << (P - 3);
+      hipError_t e = lin(B, m, x, 1, 1, lwe + c0 * B.lw, 1, 0, nullptr, 0, Q / p);  // m + 1
+      if (e == hipSuccess) e = bits(B, m, P, x, E.data(), y, o);
+      if (e == hipSuccess) e = lin(B, m, chain, 1, sh, E[P - 1], 1);
+      if (e == hipSuccess) e = lin(B, m, res, 1, 0, x, 1, 0, nullptr, 0, (u128)kc * 2 * vo);
+      if (e == hipSuccess && top == P - 1) {
+        e = lin(B, m, y, 1, sh, E[P - 1], 1, 0, nullptr, 0, vc, true);
+        if (e == hipSuccess) e = pbs(B, m, y, o, vo);
+        if (e == hipSuccess) e = lin(B, m, res, 1, 1, res, 1, 1, o, 1, vo);
+      }
+      for (int i = (int)P - 2; e == hipSuccess && i >= 0; --i) {
+        e = lin(B, m, y, 1, sh, E[i], 1, 1, chain, 1, vc, true);  // OR decision
+        if (e == hipSuccess && (uint32_t)i <= top) {
+          e = pbs(B, m, y, o, vo);
+          if (e == hipSuccess)
+            e = i ? lin(B, m, res, 1, 1, res, 1, 1, o, 1, vo) : lin(B, m, res, 1, 1, res, 1, -kc, o, 1, (u128)kc * vo, true);
+        }
+        if (e == hipSuccess && i >= 1) {
+          e = pbs(B, m, y, o, vc);
+          if (e == hipSuccess) e = lin(B, m, chain, 1, 1, o, 1, 0, nullptr, 0, vc);
+        }
+      }
+      return e;
+    };
+    HIP_TRY(timed(c, "activate", (double)m, st, [&] { return kind == HW_ACT_GE ? run_ge() : run_log(); }));
   }
   return ok();
+}
+
+extern "C" hw_status hw_activate(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* lwe, uint64_t count,
+                               uint32_t kind, uint64_t param, uint32_t log_p_out, uint32_t* out, hipStream_t st) {
+  CHECK(enter(c));
+  return activate_core(c, bsk, n, lwe, count, kind, param, log_p_out, out, st);
+}
+
+extern "C" hw_status hw_activate_ge(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* lwe,
+                                    uint64_t count, uint64_t T, uint32_t log_p_out, uint32_t* out,
+                                    hipStream_t st) {
+  CHECK(enter(c));
+  return activate_core(c, bsk, n, lwe, count, HW_ACT_GE, T, log_p_out, out, st);
 }
 
 extern "C" hw_status hw_encrypted_argmax(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* u,
@@ -504,5 +584,55 @@ extern "C" hw_status hw_class_sums(hw_ctx* c, const uint32_t* scores, uint64_t n
   S.N = c->prm.N;
   S.nq = c->prm.nq;
   HIP_TRY(hw::launch_class_sums(c->tabs, S, st));
+  return ok();
+}
+
+extern "C" hw_status hw_fm_act(hw_ctx* c, const hw_wisard_shape* sh, const uint32_t* bsk, uint32_t n,
+                               const uint32_t* pks_key, const uint32_t* model, uint32_t kind, uint64_t param,
+                               uint32_t log_p_out, uint32_t* out, hipStream_t st) {
+  CHECK(enter(c));
+  Dims d;
+  CHECK(check_shape(c, sh, &d));
+  CHECK(check_pbs(c, bsk, n));
+  if (!pks_key || !model || !out) return fail(HW_EINVAL, "null buffer");
+  // the activation's argument checks, before anything is allocated or run
+  CHECK(activate_core(c, bsk, n, nullptr, 0, kind, param, log_p_out, nullptr, st));
+  const uint32_t N = c->prm.N;
+  const size_t rw = rlwe_words(c), lw = lwe_words(c);
+  const uint64_t rows = (uint64_t)d.rows * d.k1;
+  {
+    const uintptr_t i0 = reinterpret_cast<uintptr_t>(model), i1 = i0 + (uintptr_t)rows * rw * 4;
+    const uintptr_t o0 = reinterpret_cast<uintptr_t>(out), o1 = o0 + (uintptr_t)rows * rw * 4;
+    if (o0 != i0 && i0 < o1 && o0 < i1) return fail(HW_EINVAL, "out must be model itself or not overlap it");
+  }
+  // cells of a row: every coefficient a RAM's index can address
+  const uint32_t K = d.layout == 2 ? N : 1u << std::min<uint32_t>(d.nbf, (uint32_t)c->logN);
+  const uint64_t per = std::max<uint64_t>(1, FM_CHUNK_CELLS / K);  // rows per chunk
+  const uint64_t cells = std::min<uint64_t>(per, rows) * K;
+  uint32_t* buf = nullptr;
+  HIP_TRY(hipMalloc(&buf, 2 * cells * lw * 4));
+  uint32_t* ext = buf;
+  uint32_t* act = buf + cells * lw;
+  hw_status rc = HW_OK;
+  for (uint64_t r0 = 0; rc == HW_OK && r0 < rows; r0 += per) {
+    const uint64_t m = std::min(per, rows - r0);
+    hw::CellArgs A{model + r0 * rw, ext, m, K, N, c->prm.nq};
+    const uint64_t words = m * K * lw;
+    hipError_t e = timed(c, "extract_cells", (double)(m * K), st, [&] {
+      hipLaunchKernelGGL(hw::k_extract_cells, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, c->tabs, A);
+      return hipGetLastError();
+    });
+    if (e != hipSuccess) {
+      rc = fail(HW_EDEVICE, "k_extract_cells: %s", hipGetErrorString(e));
+      break;
+    }
+    rc = activate_core(c, bsk, n, ext, m * K, kind, param, log_p_out, act, st);
+    if (rc == HW_OK) rc = hw_pack_lwe(c, pks_key, act, K, m, out + r0 * rw, st);
+  }
+  // the chunks' buffers are released once the stream has used them
+  const hipError_t es = hipStreamSynchronize(st);
+  (void)hipFree(buf);
+  if (rc != HW_OK) return rc;
+  HIP_TRY(es);
   return ok();
 }

@@ -73,6 +73,7 @@ class Request(C.Structure):
 
 
 NOALLOC_SCRATCH_BYTES = 256 << 20  # HW_NOALLOC_SCRATCH_BYTES
+ACT_KINDS = {"ge": 0, "log": 1, "blog": 2}  # HW_ACT_GE, HW_ACT_LOG, HW_ACT_BLOG
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED, REQ_CANCELLED = 0, 1, 2, 3, 4
 
@@ -102,6 +103,8 @@ _SIG = {
     "hw_activate_ge": [_vp, _vp, _u32, _vp, _u64, _u64, _u32, _vp, _vp],
     "hw_encrypted_argmax": [_vp, _vp, _u32, _vp, _u64, _u32, _u32, _vp, _vp],
     "hw_class_sums": [_vp, _vp, _u64, _u32, _u32, _vp, _vp],
+    "hw_fm_act": [_vp, _vp, _vp, _u32, _vp, _vp, _u32, _u64, _u32, _vp, _vp],
+    "hw_activate": [_vp, _vp, _u32, _vp, _u64, _u32, _u64, _u32, _vp, _vp],
     "hw_pks_keygen": [_vp, _vp, _u64, _vp, _vp],
     "hw_pks_key_export_canonical": [_vp, _vp, _vp, _vp],
     "hw_pack_lwe": [_vp, _vp, _vp, _u32, _u64, _vp, _vp],
@@ -304,6 +307,19 @@ class Context:
 
     def class_sums(self, scores, n: int, l: int, k0: int, sums):
         _check(_lib.hw_class_sums(self._h, _ptr(scores), n, l, k0, _ptr(sums), _stream()))
+
+    def activate(self, bsk, n: int, lwe, count: int, kind: str, param: int, log_p_out: int, out):
+        """kind "ge" ([m >= param]), "log" (floor(log2(m + 1))) or "blog"
+        (min(log, param)) over `count` LWE, output modulus 2^log_p_out"""
+        _check(_lib.hw_activate(self._h, _ptr(bsk), n, _ptr(lwe), count, ACT_KINDS[kind], param, log_p_out,
+                                _ptr(out), _stream()))
+
+    def fm_act(self, sh: Shape, bsk, n: int, pks_key, model, kind: str, param: int, log_p_out: int, out):
+        """FM-act: every cell of `model` activated (kind and param as in
+        activate, output modulus 2^log_p_out) and packed back into its row;
+        out may be model"""
+        _check(_lib.hw_fm_act(self._h, C.byref(sh), _ptr(bsk), n, _ptr(pks_key), _ptr(model), ACT_KINDS[kind],
+                              param, log_p_out, _ptr(out), _stream()))
 
     def encrypted_argmax(self, bsk, n: int, u, count: int, l: int, log_p_in: int, out):
         _check(_lib.hw_encrypted_argmax(self._h, _ptr(bsk), n, _ptr(u), count, l, log_p_in, _ptr(out), _stream()))

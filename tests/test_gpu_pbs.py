@@ -1,12 +1,14 @@
 """GPU parity of the programmable bootstrapping and the OTF-act functions
-(Activate as [m >= T], EncryptedArgMax; Sec. 2.5.3, Sec. 3.5.2, Alg. 7).
+(Activate as [m >= T], log and b-log; EncryptedArgMax; Sec. 2.5.3,
+Sec. 3.5.2, Alg. 7).
 
 Against the oracle, bit for bit: the bootstrapping key, single bootstraps
 over the whole key (N = 1024), and the activation and argmax circuits at
 p = 8 (their bootstraps in sequence take the oracle about a minute).  At the
 Wisconsin-shaped parameter set (N = 2048, two primes, p = 512) every output
-is checked by decryption: [m >= T] on both sides of the thresholds, the
-argmax with ties to the lowest index, and OTF-act end to end (inference,
+is checked by decryption: [m >= T] on both sides of the thresholds, log
+and b-log (Sec. 2.4.2) on both sides of every power of two, the argmax
+with ties to the lowest index, and OTF-act end to end (inference,
 activation of every RAM score, class sums, EncryptedArgMax) against the
 plaintext Alg. 2 with the bin activation."""
 import numpy as np
@@ -81,6 +83,24 @@ def test_activate_and_argmax_circuits_bit_exact():
     assert B.decode(orc, s, want[2], 4) == 1
 
 
+def test_log_activations_bit_exact():
+    """log at m = 3 and at m = p - 1 (m + 1 wraps to 0), b-log with cap 1"""
+    HW, ctx, orc, sk, s, bsk = setup(1024, 1, 8)
+    bsk_o = orc.pbs_keygen(s, 42, 1024)
+    X = lwes(orc, s, [3, 7, 5], 8, 6)
+    out = zeros_u32(3, orc.lwe_words)
+    ctx.activate(bsk, 1024, dev(X[:2]), 2, "log", 0, 4, out[:2])
+    ctx.activate(bsk, 1024, dev(X[2:]), 1, "blog", 1, 4, out[2:])
+    want = [None] * 3
+    jobs = [lambda: B.activate_log(orc, bsk_o, 1024, X[0], 16), lambda: B.activate_log(orc, bsk_o, 1024, X[1], 16),
+            lambda: B.activate_log(orc, bsk_o, 1024, X[2], 16, 1)]
+    O._parallel(lambda j: want.__setitem__(j, jobs[j]()), range(3))
+    got = host_u32(out).reshape(3, 1, 1025)
+    for j in range(3):
+        assert np.array_equal(got[j], want[j]), j
+    assert [B.decode(orc, s, got[j], 16) for j in range(3)] == [2, 3, 1]
+
+
 def decrypt_at(HW, N, nq, p, sk, lwe_dev, count):
     """GPU decryption with plaintext modulus p (same primes and key)"""
     c = HW.Context(N, nq, p)
@@ -97,6 +117,13 @@ def test_activate_and_argmax_by_decryption_wisconsin_params():
         out = zeros_u32(len(ms), orc.lwe_words)
         ctx.activate_ge(bsk, 2048, X, len(ms), T, 7, out)
         assert np.array_equal(decrypt_at(HW, 2048, 2, 128, sk, out, len(ms)), (ms >= T).astype(np.int64)), T
+    ml = np.array([0] + [v for i in range(1, 10) for v in ((1 << i) - 2, (1 << i) - 1) if v > 0])  # 2^i - 1 = m + 1 - 1
+    XL = dev(lwes(orc, s, ml, 512, 8))
+    for kind, cap in (("log", 0), ("blog", 2), ("blog", 4)):
+        out = zeros_u32(len(ml), orc.lwe_words)
+        ctx.activate(bsk, 2048, XL, len(ml), kind, cap, 7, out)
+        want = P.act_log(ml) if kind == "log" else P.act_blog(ml, cap)
+        assert np.array_equal(decrypt_at(HW, 2048, 2, 128, sk, out, len(ml)), want), (kind, cap)
     rng = np.random.default_rng(5)
     for l in (2, 3):
         S = rng.integers(0, 64, (12, l))

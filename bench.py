@@ -389,7 +389,8 @@ def side_workload(args):
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
     if args.workload == "batched":
-        r = batched_full(dev, args.batched_ring, args.batched_window_gib, args.batched_per_job, args.batched_jobs)
+        r = batched_full(dev, args.batched_ring, args.batched_window_gib, args.batched_per_job, args.batched_jobs,
+                         oracle_rams=0 if args.no_cpu_baseline else args.batched_oracle_rams)
         line = {"metric": "batched encrypted train samples/s (training kernels)", "value": r["batched_samples_per_s"],
                 "unit": "samples/s", "n_gpus": 1, "higher_is_better": True, "dtype": "u32", "data": "synthetic",
                 "config": {"workload": "256 uneven training jobs (n U{32..2000}, s U{128..2352}, a U{8..12}, "
@@ -417,6 +418,8 @@ def main():
                     help="only jobs [FIRST, END) of the ring's jobs")
     ap.add_argument("--batched-window-gib", type=float, default=160.0)
     ap.add_argument("--batched-per-job", type=int, default=2, help="samples per job per window")
+    ap.add_argument("--batched-oracle-rams", type=int, default=16,
+                    help="RAMs of the smallest job that the oracle trains over all its samples")
     ap.add_argument("--served-loads", type=float, nargs="*", default=None,
                     help="loads (fractions of the saturated request rate) for --workload served")
     ap.add_argument("--served-sat-rps", type=float, default=None,
@@ -732,9 +735,9 @@ def act_max(kind: str, param: int, P: int) -> int:
 
 def act_bootstraps(kind: str, param: int, P: int) -> int:
     """bootstraps of one activation (hw_activate)"""
-    if kind == "ge":
+    if kind == "ge" or kind == "log" or param >= P - 1:
         return 2 * P
-    return 3 * P - 3 if kind == "log" or param >= P else 2 * P + param - 1
+    return 2 * P - 1
 
 
 def act_name(kind: str, param: int) -> str:
@@ -1339,7 +1342,74 @@ def served_full(dev, n_req: int, max_size: int, loads, sat_rps: float | None, se
     return out
 
 
-def batched_full(dev, ring: int, window_gib: float, per_job: int, jobs_range=None, chunk: int = 50) -> dict:
+def batched_oracle_leg(st, ring: int, nq: int, nrams: int) -> dict:
+    """The oracle on the job of the mix with the fewest external products per
+    RAM over all its samples: the RGSW of every sample's bits for its first
+    RAMs (as many as host threads, at most `nrams`; the oracle trains RAMs in
+    parallel) and its label bits (the same seeds and ciphertext indices as
+    the device), then those RAMs trained over all of the job's samples; the
+    rows are compared bit for bit with the persistent batch's model, and the
+    oracle's rate is given per external product and extrapolated to the job
+    and the mix."""
+    import numpy as np
+
+    import oracle as O
+    S = min(st, key=lambda S: S["J"]["n"] * job_xp_per_ram(S["J"], ring))
+    J, j = S["J"], S["j"]
+    n, s_, l, a, L = J["n"], J["s"], J["l"], J["a"], S["L"]
+    info = host_info()
+    threads = max(1, min(16, info["affinity"]))
+    orc = O.Ctx(ring, nq, 4096)
+    sk = orc.keygen(101)
+    pi = O.permutation(3000 + j, s_)
+    k0 = -(-s_ // a)
+    rams = list(range(min(nrams, threads, k0)))
+    X, y = S["X"], S["y"]
+    xs, ys = {}, {}
+    need = [(i, int(pi[r * a + t])) for r in rams for i in range(n) for t in range(min(a, s_ - r * a))]
+    t0 = time.perf_counter()
+    O._parallel(lambda ik: xs.__setitem__(ik, orc.enc_rgsw(sk, int(X[ik[0], ik[1]]), 1000 + j, ik[0] * s_ + ik[1])),
+                need, threads)
+    O._parallel(lambda iu: ys.__setitem__(iu, orc.enc_rgsw(sk, (int(y[iu[0]]) >> iu[1]) & 1, 2000 + j,
+                                                           iu[0] * L + iu[1])),
+                [(i, u) for i in range(n) for u in range(L)], threads)
+    t_enc = time.perf_counter() - t0
+    H = np.zeros((k0, orc.k1(s_, l, a), 2, nq, ring), np.uint32)
+    t0 = time.perf_counter()
+    orc.train(s_, l, a, pi, lambda i, k: xs[(i, k)], lambda i, u: ys[(i, u)], n, H, rams=rams, threads=threads)
+    t_train = time.perf_counter() - t0
+    got = S["mb"].cpu().numpy().view(np.uint32)
+    xp = n * len(rams) * job_xp_per_ram(J, ring)
+    rate = xp / t_train
+    mix_xp = sum(S2["J"]["n"] * job_xp_per_sample(S2["J"], ring) for S2 in st)
+    return {"value": round(rate, 2), "unit": "external products/s (training)", "cores": threads, "kind": "oracle",
+            "sample": "job %d (n %d, s %d, a %d, l %d): RGSW of the bits of RAMs %s and of "
+                      "the labels for all %d samples (%.1f s), then those RAMs trained over all samples (%.1f s)"
+                      % (j, n, s_, a, l, rams, n, t_enc, t_train),
+            "job_s_extrapolated": round(n * job_xp_per_sample(J, ring) / rate, 1),
+            "mix_train_s_extrapolated": round(mix_xp / rate, 1),
+            "bit_exact_with_batch": bool(np.array_equal(got[rams], H[rams])), "host": info}
+
+
+def job_xp_per_ram(J, ring: int) -> int:
+    """training external products per (sample, full RAM): the rotation chain
+    and the live CDEMUX splits of the label-pruned tree"""
+    L = (J["l"] - 1).bit_length()
+    logN = ring.bit_length() - 1
+    nb = L + J["a"]
+    nr = min(nb, logN)
+    z = nb - nr
+    live = (lambda u: z < L or (u & ((1 << L) - 1)) < J["l"])
+    splits = sum(1 for lev in range(z) for u in range(1 << lev) if live(u) and live(u + (1 << lev)))
+    return nr + splits
+
+
+def job_xp_per_sample(J, ring: int) -> int:
+    return -(-J["s"] // J["a"]) * job_xp_per_ram(J, ring)
+
+
+def batched_full(dev, ring: int, window_gib: float, per_job: int, jobs_range=None, chunk: int = 50,
+                 oracle_rams: int = 0) -> dict:
     """The batched configuration at its stated size: the 256 jobs of
     synth.batched_jobs (n U{32..2000}, s U{128..2352}, a U{8..12}, l
     U{2..10}), those of ring degree `ring` (two primes at 2048, three at
@@ -1430,6 +1500,8 @@ def batched_full(dev, ring: int, window_gib: float, per_job: int, jobs_range=Non
                                                                       "encrypt_rgsw")}
     ctx.profile(False)
     out["bit_identical"] = all(torch.equal(S["mb"], S["ms"]) for S in st)
+    if oracle_rams:
+        out["cpu_baseline"] = batched_oracle_leg(st, ring, nq, oracle_rams)
     # the plain one-job-at-a-time path: job after job, each in chunks that fill the GPU
     for S in st:
         S["ms"].zero_()

@@ -332,18 +332,19 @@ hw_status hw_activate_ge(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const
  * ~ 2 V_o f(m), V_o = floor(floor(Q / 2^log_p_out) / 2), 1 <= log_p_out <= 60:
  *   HW_ACT_GE   f(m) = [m >= param], 1 <= param <= p (hw_activate_ge; bin
  *               with thr = param - 1), 2P bootstraps;
- *   HW_ACT_LOG  f(m) = floor(log2(m + 1)) (param ignored), 3P - 3 bootstraps;
+ *   HW_ACT_LOG  f(m) = floor(log2(m + 1)) (param ignored), 2P bootstraps;
  *   HW_ACT_BLOG f(m) = min(floor(log2(m + 1)), param), param >= 1 (param >= P
- *               is log), 2P + param - 1 bootstraps.
- * log and b-log: x' = x + (0, floor(Q/p)) encrypts m' = m + 1 mod p (0 only
- * for m = p - 1); E = the bits of m' (as in hw_activate_ge); with o_i = [m' >=
- * 2^i] = the OR of bits i..P-1, f = sum_{i=1}^{c} o_i + c (1 - o_0), c = P
- * (log, the sum up to P - 1) or the cap.  The ORs run from the top:
- * o = 2^(P-3) E_(P-1); for i = P-2 .. 0, z_i = 2^(P-3) E_i + o - V_c, and
- * for i >= 1 o = PBS(z_i, V_c) + V_c; each needed o_i is bootstrapped again
- * at the output scale, PBS(z_i, V_o) + V_o (o_(P-1) from 2^(P-3) E_(P-1) - V_c).
- * lwe_dev, out_dev: [count] LWE.  HW_EINVAL for a kind, param or log_p_out
- * out of range, before anything runs. */
+ *               is log), 2P - 1 bootstraps for param < P - 1.
+ * log and b-log need log_p_out >= 3.  They read x' = x + (0, floor(Q/p)),
+ * which encrypts m' = m + 1 mod p (0 only for m = p - 1); E = the bits of m'
+ * (as in hw_activate_ge); with o_i = [m' >= 2^i] = the OR of bits i..P-1,
+ * f = sum_{i=1}^{c} o_i + c (1 - o_0), c = P (log, the sum up to P - 1) or
+ * the cap.  The ORs run from the top: chain value o = 2^(P-3) E_(P-1) (scale
+ * ~Q/8); for i = P-2 .. 0, z_i = 2^(P-3) E_i + o - V_c, w_i = PBS(z_i, V_o) +
+ * V_o (o_i at the output scale) and, for i >= 1, o = 2^(log_p_out - 3) w_i
+ * (back at ~Q/8); o_(P-1), when the sum needs it, is PBS(2^(P-3) E_(P-1) -
+ * V_c, V_o) + V_o.  lwe_dev, out_dev: [count] LWE.  HW_EINVAL for a kind,
+ * param or log_p_out out of range, before anything runs. */
 #define HW_ACT_GE 0u
 #define HW_ACT_LOG 1u
 #define HW_ACT_BLOG 2u

@@ -32,16 +32,16 @@ b_k OR c_k, subtracting 3Q/16 decides b_k AND c_k).
 
 activate_log(x, p_out, cap): the logarithmic activations of Sec. 2.4.2,
 log(m) = floor(log2(m + 1)) and b-log(m) = min(log(m), cap), as LWE with
-phase ~ 2 V_o f(m).  With m' = m + 1 mod p (x plus Delta_p on the body; m'
-= 0 only for m = p - 1) and o_i = [m' >= 2^i] = OR of bits i..P-1 of m',
-log(m) = sum_{i=1}^{P-1} o_i + P (1 - o_0) and, for cap < P,
+phase ~ 2 V_o f(m), p_out >= 8.  With m' = m + 1 mod p (x plus Delta_p on
+the body; m' = 0 only for m = p - 1) and o_i = [m' >= 2^i] = OR of bits
+i..P-1 of m', log(m) = sum_{i=1}^{P-1} o_i + P (1 - o_0) and, for cap < P,
 b-log(m) = sum_{i=1}^{cap} o_i + cap (1 - o_0).  Steps: E = bits(x', p);
-chain value o = 2^(P-3) E_{P-1} (scale ~Q/8); for i = P-2 down to 0,
-z_i = 2^(P-3) E_i + o - V_c (the OR decision, as in the carry circuit)
-and, while i >= 1, o = PBS(z_i, V_c) + V_c.  Each needed o_i is also
-bootstrapped at the output scale: out_i = PBS(z_i, V_o) + V_o (for i = P-1
-from z = 2^(P-3) E_{P-1} - V_c).  3P - 3 bootstraps for log, 2P + cap - 1
-for b-log.
+chain value c = 2^(P-3) E_{P-1} (scale ~Q/8); for i = P-2 down to 0,
+z_i = 2^(P-3) E_i + c - V_c (the OR decision, as in the carry circuit),
+w_i = PBS(z_i, V_o) + V_o (o_i at the output scale) and, while i >= 1,
+c = 2^(log2 p_out - 3) w_i (o_i back at the chain scale ~Q/8).  o_(P-1),
+when the sum needs it, is PBS(2^(P-3) E_{P-1} - V_c, V_o) + V_o.  2P
+bootstraps for log, 2P - 1 for b-log with cap < P - 1.
 
 fm_act(H, K, T, p_out): FM-act (Sec. 3.5.3), the activation applied once to
 every cell of a trained model: for every model row (one RLWE), the LWE of
@@ -155,26 +155,31 @@ def activate_ge(ctx, bsk, n: int, x, T: int, p_out: int) -> np.ndarray:
 def activate_log(ctx, bsk, n: int, x, p_out: int, cap: int | None = None) -> np.ndarray:
     p = ctx.p
     P = log2_exact(p)
-    if P < 3 or (cap is not None and cap < 1):
-        raise ValueError("needs p >= 8 and cap >= 1")
+    lo = log2_exact(p_out)
+    if P < 3 or lo < 3 or (cap is not None and cap < 1):
+        raise ValueError("needs p >= 8, p_out >= 8 and cap >= 1")
     top = P - 1 if cap is None or cap >= P else cap  # outputs o_1 .. o_top
-    k_const = P if cap is None or cap >= P else cap
+    kc = P if cap is None or cap >= P else cap
     Q = ctx.Q
     vc = Q // 16
     vo = (Q // p_out) // 2
+    sh = 1 << (P - 3)
     E = bits(ctx, bsk, n, lin(ctx, [(1, x)], Q // p), p)
-    o = lin(ctx, [(1 << (P - 3), E[P - 1])])
-    outs = {}
+    chain = lin(ctx, [(sh, E[P - 1])])
+    terms = []
     if top == P - 1:
-        z = lin(ctx, [(1 << (P - 3), E[P - 1])], -vc)
-        outs[P - 1] = lin(ctx, [(1, ctx.pbs(bsk, z, n, vo))], vo)
+        z = lin(ctx, [(sh, E[P - 1])], -vc)
+        terms.append((1, lin(ctx, [(1, ctx.pbs(bsk, z, n, vo))], vo)))
     for i in range(P - 2, -1, -1):
-        z = lin(ctx, [(1 << (P - 3), E[i]), (1, o)], -vc)
-        if i <= top:
-            outs[i] = lin(ctx, [(1, ctx.pbs(bsk, z, n, vo))], vo)
+        z = lin(ctx, [(sh, E[i]), (1, chain)], -vc)
+        w = lin(ctx, [(1, ctx.pbs(bsk, z, n, vo))], vo)
+        if i == 0:
+            terms.append((-kc, w))
+        elif i <= top:
+            terms.append((1, w))
         if i >= 1:
-            o = lin(ctx, [(1, ctx.pbs(bsk, z, n, vc))], vc)
-    return lin(ctx, [(1, outs[i]) for i in range(1, top + 1)] + [(-k_const, outs[0])], k_const * 2 * vo)
+            chain = lin(ctx, [(1 << (lo - 3), w)])
+    return lin(ctx, terms, kc * 2 * vo)
 
 
 def argmax(ctx, bsk, n: int, u, p_in: int) -> np.ndarray:

@@ -421,6 +421,7 @@ static hw_status activate_core(hw_ctx* c, const uint32_t* bsk, uint32_t n, const
     return fail(HW_EINVAL, "T = %llu out of range [1, p = %llu]", (unsigned long long)param, (unsigned long long)p);
   if (kind == HW_ACT_BLOG && param < 1) return fail(HW_EINVAL, "the b-log cap must be >= 1");
   if (log_p_out < 1 || log_p_out > 60) return fail(HW_EINVAL, "log_p_out = %u out of range [1, 60]", log_p_out);
+  if (kind != HW_ACT_GE && log_p_out < 3) return fail(HW_EINVAL, "log and b-log need log_p_out >= 3");
   if (count == 0) return ok();
   if (!lwe || !out) return fail(HW_EINVAL, "null buffer");
   const u128 Q = c->Q, vc = Q / 16, vo = (Q >> log_p_out) / 2;
@@ -468,15 +469,12 @@ static hw_status activate_core(hw_ctx* c, const uint32_t* bsk, uint32_t n, const
       }
       for (int i = (int)P - 2; e == hipSuccess && i >= 0; --i) {
         e = lin(B, m, y, 1, sh, E[i], 1, 1, chain, 1, vc, true);  // OR decision
-        if (e == hipSuccess && (uint32_t)i <= top) {
-          e = pbs(B, m, y, o, vo);
-          if (e == hipSuccess)
-            e = i ? lin(B, m, res, 1, 1, res, 1, 1, o, 1, vo) : lin(B, m, res, 1, 1, res, 1, -kc, o, 1, (u128)kc * vo, true);
-        }
-        if (e == hipSuccess && i >= 1) {
-          e = pbs(B, m, y, o, vc);
-          if (e == hipSuccess) e = lin(B, m, chain, 1, 1, o, 1, 0, nullptr, 0, vc);
-        }
+        if (e == hipSuccess) e = pbs(B, m, y, o, vo);               // o_i at the output scale (o + V_o)
+        if (e == hipSuccess && i == 0) e = lin(B, m, res, 1, 1, res, 1, -kc, o, 1, (u128)kc * vo, true);
+        if (e == hipSuccess && i > 0 && (uint32_t)i <= top) e = lin(B, m, res, 1, 1, res, 1, 1, o, 1, vo);
+        // back at the chain scale: 2^(log_p_out - 3) (o + V_o)
+        if (e == hipSuccess && i > 0)
+          e = lin(B, m, chain, 1, (int64_t)1 << (log_p_out - 3), o, 1, 0, nullptr, 0, ((u128)1 << (log_p_out - 3)) * vo);
       }
       return e;
     };

@@ -397,7 +397,7 @@ def side_workload(args):
                                        "l U{2..10}), ring %d" % args.batched_ring}, "batched": r}
     else:
         r = served_full(dev, args.served_requests, args.served_max_size, args.served_loads or [],
-                        args.served_sat_rps, args.served_one_at_a_time)
+                        args.served_sat_rps, args.served_one_at_a_time, tuple(args.served_orders))
         line = {"metric": "served p50/p99 latency and throughput", "unit": "ms", "n_gpus": 1, "dtype": "u32",
                 "data": "synthetic", "config": {"workload": "Poisson train/infer requests, half Wisconsin- half "
                                                             "MNIST-shaped, N=2048 x 2 primes, p=2^16"}, "served": r}
@@ -424,6 +424,8 @@ def main():
                     help="loads (fractions of the saturated request rate) for --workload served")
     ap.add_argument("--served-sat-rps", type=float, default=None,
                     help="saturated request rate from an earlier run (skips the saturated run)")
+    ap.add_argument("--served-orders", nargs="+", default=["fifo"], choices=["fifo", "shortest"],
+                    help="engine orders to run each load with (the saturated run uses the first)")
     ap.add_argument("--served-one-at-a-time", action="store_true",
                     help="also replay the requests one job at a time")
     ap.add_argument("--n-train", type=int, default=None, help="override the number of training samples")
@@ -1191,8 +1193,8 @@ def served_setup(dev, n_req: int, max_size: int, seed: int = 5):
         for r in range(4):
             pre[(name, r)] = g.integers(0, len(bits), 64)
 
-    def make_engine():
-        eng = HW.Engine(N, nq, p, sk, slots=4, chunk=8, max_s=2352, max_cells=2048, arena_bytes=64 << 30)
+    def make_engine(order="fifo"):
+        eng = HW.Engine(N, nq, p, sk, slots=4, chunk=8, max_s=2352, max_cells=2048, arena_bytes=64 << 30, order=order)
         jobs = []
         for name, (bits, y, l, a) in shapes.items():
             for r in range(4):
@@ -1294,7 +1296,8 @@ def served_pass(dev, n_req: int, max_size: int, load: float):
     }
 
 
-def served_full(dev, n_req: int, max_size: int, loads, sat_rps: float | None, sequential: bool) -> dict:
+def served_full(dev, n_req: int, max_size: int, loads, sat_rps: float | None, sequential: bool,
+                orders=("fifo",)) -> dict:
     """The served configuration at its stated size: 400 requests of U{1..500}
     samples.  Runs whichever parts are asked for (each can be its own
     process, so that one run stays within a time limit): the saturated run
@@ -1302,7 +1305,8 @@ def served_full(dev, n_req: int, max_size: int, loads, sat_rps: float | None, se
     Poisson arrivals at each load x that rate (p50/p99 latency, throughput);
     and the same request list one job at a time (service times, from which
     the one-job-at-a-time latencies under the same arrivals follow by the
-    single-server recursion)."""
+    single-server recursion).  Each load runs once per engine order in
+    `orders` ("fifo", "shortest"), the saturated run with the first."""
     import numpy as np
 
     from paper_2403_20190_amd import synth
@@ -1315,7 +1319,7 @@ def served_full(dev, n_req: int, max_size: int, loads, sat_rps: float | None, se
         return {"p50_ms": round(float(np.percentile(x, 50)), 1), "p99_ms": round(float(np.percentile(x, 99)), 1)}
 
     if sat_rps is None:
-        lat0, span0, st0 = served_play(make_engine, reqs, [0.0] * n_req)
+        lat0, span0, st0 = served_play(lambda: make_engine(orders[0]), reqs, [0.0] * n_req)
         sat_rps = n_req / span0
         out["saturated"] = dict(req_per_s=round(sat_rps, 4), samples_per_s=round(samples / span0, 2),
                                 span_s=round(span0, 1), peak_inflight_chunks=st0["peak_inflight"], **pct(lat0))
@@ -1334,10 +1338,12 @@ def served_full(dev, n_req: int, max_size: int, loads, sat_rps: float | None, se
         qps = load * sat_rps
         arr = synth.poisson_arrivals(6, qps, n_req)
         arr = list(arr - arr[0])
-        lat, span, st = served_play(make_engine, reqs, arr)
-        out["loads"].append(dict(load=load, offered_qps=round(qps, 4), throughput_samples_per_s=round(samples / span, 2),
-                                 span_s=round(span, 1), peak_inflight_chunks=st["peak_inflight"],
-                                 peak_arena_gib=round(st["peak_arena_bytes"] / 2**30, 2), **pct(lat)))
+        for order in orders:
+            lat, span, st = served_play(lambda: make_engine(order), reqs, arr)
+            out["loads"].append(dict(load=load, order=order, offered_qps=round(qps, 4),
+                                     throughput_samples_per_s=round(samples / span, 2),
+                                     span_s=round(span, 1), peak_inflight_chunks=st["peak_inflight"],
+                                     peak_arena_gib=round(st["peak_arena_bytes"] / 2**30, 2), **pct(lat)))
     ctx.close()
     return out
 

@@ -494,8 +494,10 @@ hw_status hw_batch_run(hw_ctx* const* ctxs, uint32_t nctx, const hw_job* jobs, u
 /* A request loop on one device: train and infer requests against resident
  * models are cut into chunks of samples; a scheduler thread starts a chunk
  * as soon as a stream slot is free and the chunk's device footprint (input
- * ciphertexts, workspace, scores) fits in the engine's arena, interleaving
- * chunks of all admitted requests.  Requests on one model keep submission
+ * ciphertexts, workspace, scores) fits in the engine's arena.  Requests are
+ * served in the configured order (first come, first served, or the least
+ * remaining work first): the first request in that order takes every free
+ * slot it can use, later ones the slots it cannot.  Requests on one model keep submission
  * order: a training request starts after every earlier request on its model
  * completed (its chunks run one after another), an inference request once
  * every earlier request on its model is an inference (inferences only read
@@ -512,7 +514,14 @@ typedef struct {
   uint32_t max_s;        /* largest input width served (host staging size) */
   uint32_t max_cells;    /* largest l * k0 served (host staging size) */
   uint64_t arena_bytes;  /* device memory for the chunks in flight */
+  uint32_t order;        /* HW_ORDER_FIFO: requests in submission order;
+                            HW_ORDER_SHORTEST: the request with the fewest external
+                            products left to start first (its unstarted samples times its
+                            model's products per sample for its kind), ties in submission order */
+  uint32_t reserved;     /* 0 */
 } hw_engine_config;
+#define HW_ORDER_FIFO 0u
+#define HW_ORDER_SHORTEST 1u
 
 typedef struct {
   uint32_t job;                /* id from hw_engine_add_job */

@@ -93,6 +93,7 @@ struct Job {
   uint32_t* cnt;
   uint64_t samples;           // trained into the model, plus those of admitted training requests
   std::deque<uint64_t> fifo;  // requests on this model, in submission order
+  double xp_train, xp_infer;  // external products per sample of a training / inference request
 };
 
 struct Req {
@@ -272,13 +273,23 @@ static void scheduler(hw_engine* E) {
         finish_request(E, S.run.req, R, R.state == HW_REQ_FAILED ? HW_REQ_FAILED
                                                                  : (all ? HW_REQ_DONE : HW_REQ_CANCELLED));
     }
-    // start chunks in submission order: a request takes every free slot it can
-    // use before a later request gets one (first come, first served); the
-    // slots it cannot use -- a training request runs one chunk at a time, a
-    // request may be waiting for an earlier one on its model or for arena
-    // memory -- go to the later requests
+    // start chunks in the configured order (submission order, or the least
+    // remaining work first): a request takes every free slot it can use before
+    // the next one gets one; the slots it cannot use -- a training request
+    // runs one chunk at a time, a request may be waiting for an earlier one on
+    // its model or for arena memory -- go to the next requests
+    std::vector<uint64_t> order(E->active);
+    if (E->cfg.order == HW_ORDER_SHORTEST) {
+      auto left = [&](uint64_t id) {
+        const Req& R = E->reqs[id];
+        const Job& J = E->jobs[R.r.job];
+        const uint64_t started = std::min<uint64_t>(R.r.n, R.next * E->cfg.chunk);
+        return (double)(R.r.n - started) * (R.r.kind == 0 ? J.xp_train : J.xp_infer);
+      };
+      std::stable_sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) { return left(a) < left(b); });
+    }
     bool slots_left = true;
-    for (uint64_t id : std::vector<uint64_t>(E->active)) {
+    for (uint64_t id : order) {
       if (!slots_left) break;
       Req& R = E->reqs[id];
       Job& J = E->jobs[R.r.job];
@@ -343,6 +354,7 @@ extern "C" hw_status hw_engine_create(const hw_params* params, int device, const
   if (cfg->slots < 1 || cfg->slots > 16) return fail(HW_EINVAL, "slots must be 1..16");
   if (cfg->chunk < 1) return fail(HW_EINVAL, "chunk must be >= 1");
   if (cfg->max_s < 1 || cfg->max_cells < 1) return fail(HW_EINVAL, "max_s and max_cells must be >= 1");
+  if (cfg->order > HW_ORDER_SHORTEST) return fail(HW_EINVAL, "order must be HW_ORDER_FIFO or HW_ORDER_SHORTEST");
   hw_ctx* c = nullptr;
   CHECK(hw_ctx_create(params, device, &c));
   hw_engine* E = new hw_engine();
@@ -429,6 +441,10 @@ extern "C" hw_status hw_engine_add_job(hw_engine* E, const hw_wisard_shape* sh, 
   J.sh = *sh;
   J.model = model;
   J.cnt = cnt;
+  J.xp_train = 0;
+  for (uint32_t j = 0; j < J.d.k0; ++j)
+    J.xp_train += ivp_xp(J.d.L + std::min(sh->a, sh->s - j * sh->a), E->ctx->logN, J.d.pL, J.d.pl);
+  J.xp_infer = infer_xp_per_sample(E->ctx, sh, J.d);
   std::lock_guard<std::mutex> g(E->mu);
   *job_id = (uint32_t)E->jobs.size();
   E->jobs.push_back(J);

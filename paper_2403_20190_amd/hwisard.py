@@ -64,7 +64,7 @@ class Job(C.Structure):
 
 class EngineConfig(C.Structure):
     _fields_ = [("slots", C.c_uint32), ("chunk", C.c_uint32), ("max_s", C.c_uint32), ("max_cells", C.c_uint32),
-                ("arena_bytes", C.c_uint64)]
+                ("arena_bytes", C.c_uint64), ("order", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class Request(C.Structure):
@@ -451,10 +451,14 @@ class Engine:
     kept alive here until the request has finished."""
 
     def __init__(self, N: int, nq: int, p: int, sk, slots: int = 4, chunk: int = 8, max_s: int = 4096,
-                 max_cells: int = 4096, arena_bytes: int = 32 << 30, device: int = 0, sigma: float = 3.2):
+                 max_cells: int = 4096, arena_bytes: int = 32 << 30, device: int = 0, sigma: float = 3.2,
+                 order: str = "fifo"):
+        """order: "fifo" (submission order) or "shortest" (least remaining work first)"""
         prm = Params()
         prm.N, prm.nq, prm.log_base, prm.digits, prm.sigma, prm.plain_mod = N, nq, 6, 5, sigma, p
-        cfg = EngineConfig(slots, chunk, max_s, max_cells, arena_bytes)
+        if order not in ("fifo", "shortest"):
+            raise HwError(HW_EINVAL, "order must be 'fifo' or 'shortest'")
+        cfg = EngineConfig(slots, chunk, max_s, max_cells, arena_bytes, 0 if order == "fifo" else 1, 0)
         h = C.c_void_p()
         _check(_lib.hw_engine_create(C.byref(prm), device, _ptr(sk), C.byref(cfg), C.byref(h)))
         self._h = h

@@ -35,8 +35,8 @@ def label_bits(y, L):
     return np.array([[(int(v) >> u) & 1 for u in range(L)] for v in y], np.uint8).reshape(len(y), L)
 
 
-def setup(HW, sk):
-    eng = HW.Engine(N, NQ, PM, sk, slots=3, chunk=2, max_s=64, max_cells=4096, arena_bytes=2 << 30)
+def setup(HW, sk, order="fifo"):
+    eng = HW.Engine(N, NQ, PM, sk, slots=3, chunk=2, max_s=64, max_cells=4096, arena_bytes=2 << 30, order=order)
     ctx = HW.Context(N, NQ, PM)
     models, ids, shapes = [], [], []
     for J in JOBS:
@@ -55,8 +55,8 @@ def request_data(k):
     return X, y
 
 
-def run(HW, sk, concurrent):
-    eng, ctx, models, ids, shapes = setup(HW, sk)
+def run(HW, sk, concurrent, order="fifo"):
+    eng, ctx, models, ids, shapes = setup(HW, sk, order)
     outs, rids = [], []
     for k, (j, kind, n, ds) in enumerate(REQS):
         X, y = request_data(k)
@@ -76,14 +76,15 @@ def run(HW, sk, concurrent):
     return [host_u32(H) for H in models], outs, stats
 
 
-def test_alone_equals_mix_and_direct_path():
+@pytest.mark.parametrize("order", ["fifo", "shortest"])
+def test_alone_equals_mix_and_direct_path(order):
     import torch
     from paper_2403_20190_amd import hwisard as HW
     sk = torch.zeros(N, dtype=torch.int32, device="cuda")
     ctx = HW.Context(N, NQ, PM)
     ctx.keygen(77, sk)
     m_alone, o_alone, _ = run(HW, sk, False)
-    m_mix, o_mix, stats = run(HW, sk, True)
+    m_mix, o_mix, stats = run(HW, sk, True, order)
     assert stats["peak_inflight"] >= 2  # the mix really overlapped chunks
     for a, b in zip(m_alone, m_mix):
         assert np.array_equal(a, b)
@@ -241,3 +242,17 @@ def test_infer_requests_on_one_model_overlap():
     assert eng.stats()["peak_inflight"] == 2  # one chunk each, both in flight
     eng.close()
     assert np.array_equal(ca, alone[0]) and np.array_equal(cb, alone[1])
+
+
+def test_engine_order_is_checked():
+    import torch
+    from paper_2403_20190_amd import hwisard as HW
+    sk = torch.zeros(N, dtype=torch.int32, device="cuda")
+    with pytest.raises(HW.HwError):
+        HW.Engine(N, NQ, PM, sk, order="lifo")
+    cfg = HW.EngineConfig(2, 2, 64, 64, 1 << 30, 7, 0)  # an order the ABI does not define
+    prm = HW.Params()
+    prm.N, prm.nq, prm.log_base, prm.digits, prm.sigma, prm.plain_mod = N, NQ, 6, 5, 3.2, PM
+    import ctypes as C
+    h = C.c_void_p()
+    assert HW._lib.hw_engine_create(C.byref(prm), 0, HW._ptr(sk), C.byref(cfg), C.byref(h)) == HW.HW_EINVAL

@@ -9,7 +9,7 @@ trained model activated by bootstraps and packed back into its row.
   coefficient of the activated model is log(W) of the cell the layout puts
   there (0 past the cells), and inference on it with class sums and
   EncryptedArgMax gives Alg. 2 with the log activation, computed in the
-  clear."""
+  clear; the same with b-log on class-packed models (layouts 1 and 2)."""
 import numpy as np
 import pytest
 
@@ -122,4 +122,54 @@ def test_fm_act_wisconsin_shape_by_decryption():
     c4.decrypt_lwe(pair.sk, idx, nt, di)
     want = [P.predict(W, tb[i], a, pair.pi, "log") for i in range(nt)]
     assert len(set(want)) == 2
+    assert list(host_u64(di)) == want
+
+
+@pytest.mark.parametrize("layout", [1, 2])
+def test_fm_act_class_packed_layouts_by_decryption(layout):
+    """FM-act of class-packed models (layout 1: one row per RAM holding every
+    class; layout 2: four such RAMs per row, whose 2048 coefficients are all
+    cells) with b-log, cap 2 (Sec. 2.4.2), at the Wisconsin-shaped
+    parameters: every coefficient of the activated rows decrypts to b-log of
+    the cell the layout puts there, and inference on the activated model,
+    class sums and EncryptedArgMax give Alg. 2 with b-log."""
+    from paper_2403_20190_amd import client as CL
+    from paper_2403_20190_amd import synth
+    HW = hw()
+    N, s, a, l, cap, lp = 2048, 32, 8, 2, 2, 5  # class sums <= 4 RAMs x 2 < 2^5 / 2
+    Xw, yw = synth.wisconsin_like(4)
+    lo, hi = Xw.min(axis=0), Xw.max(axis=0)
+    bits = CL.thermometer(CL.quantize_minmax(Xw, 16, lo, hi), 16)[:, :s]
+    pair = Pair(N, 2, 512, s, l, a, bits[:60], yw[:60], seed=29, layout=layout)
+    ctx = pair.ctx
+    rows, _ = ctx.model_rows(pair.shape)
+    H = zeros_u32(rows, pair.k1, 2, 2, N)
+    ctx.train(pair.shape, pair.encrypt_dev(), pair.encrypt_labels_dev(), pair.n, H, None)
+    bsk = zeros_u32(ctx.pbs_key_words(N))
+    ctx.pbs_keygen(pair.sk, 46, N, bsk)
+    key = zeros_u32(ctx.pks_key_words)
+    ctx.pks_keygen(pair.sk, 47, key)
+    act = zeros_u32(*H.shape)
+    ctx.fm_act(pair.shape, bsk, N, key, H, "blog", cap, lp, act)
+    W = P.train_integer(pair.X, pair.y, l, a, pair.pi)
+    cells = P.expected_model_cells(W, s, l, a, N, layout=layout)
+    assert cells.shape == (rows, pair.k1, N) and B.fm_cells(N, l, a, layout) * rows * pair.k1 == 2048
+    assert set(P.act_blog(cells, cap).ravel()) == {0, 1, 2}
+    cp = HW.Context(N, 2, 1 << lp)
+    dec = zeros_u64(rows * pair.k1, N)
+    cp.decrypt_rlwe(pair.sk, act, rows * pair.k1, dec)
+    assert np.array_equal(host_u64(dec).reshape(cells.shape).astype(np.int64), P.act_blog(cells, cap))
+    tb = bits[[60, 61, 62, 63, 72, 74, 81, 91]]  # Alg. 2 with b-log predicts both classes among these
+    nt = len(tb)
+    xt = pair.encrypt_dev(tb, seed_x=68)
+    sc = zeros_u32(nt, l, pair.k0, ctx.lwe_words)
+    ctx.infer(pair.shape, act, xt, nt, sc, None)
+    sums = zeros_u32(nt, l, ctx.lwe_words)
+    ctx.class_sums(sc, nt, l, pair.k0, sums)
+    idx = zeros_u32(nt, ctx.lwe_words)
+    ctx.encrypted_argmax(bsk, N, sums, nt, l, lp, idx)
+    di = zeros_u64(nt)
+    HW.Context(N, 2, 4).decrypt_lwe(pair.sk, idx, nt, di)
+    want = [P.predict(W, tb[i], a, pair.pi, "blog", 0, cap) for i in range(nt)]
+    assert sorted(set(want)) == [0, 1]
     assert list(host_u64(di)) == want

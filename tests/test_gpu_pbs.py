@@ -34,8 +34,10 @@ def setup(N, nq, p, key_seed=41, bsk_seed=42):
     sk = zeros_u32(N)
     ctx.keygen(key_seed, sk)
     s = orc.keygen(key_seed)
-    bsk = zeros_u32(ctx.pbs_key_words(N))
-    ctx.pbs_keygen(sk, bsk_seed, N, bsk)
+    bsk = None
+    if bsk_seed is not None:
+        bsk = zeros_u32(ctx.pbs_key_words(N))
+        ctx.pbs_keygen(sk, bsk_seed, N, bsk)
     return HW, ctx, orc, sk, s, bsk
 
 
@@ -61,6 +63,35 @@ def test_key_and_single_bootstraps_bit_exact():
     got = host_u32(out).reshape(3, 1, 1025)
     for j in range(3):
         assert np.array_equal(got[j], want[j]), j
+
+
+@pytest.mark.parametrize("N,nq,p,n", [(2048, 2, 1024, 96), (4096, 3, 16384, 48)])
+def test_single_bootstraps_bit_exact_larger_rings(N, nq, p, n):
+    """the blind rotation at the two- and three-prime rings, over the first n
+    key coefficients (LWE masks zero past them), bit for bit"""
+    HW, ctx, orc, sk, s, _ = setup(N, nq, p, bsk_seed=None)
+    bsk = zeros_u32(ctx.pbs_key_words(n))
+    ctx.pbs_keygen(sk, 52, n, bsk)
+    exp = zeros_u32(4, ctx.rgsw_words)
+    ctx.rgsw_export(bsk[: 4 * ctx.rgsw_words], 4, exp)
+    bsk_o = orc.pbs_keygen(s, 52, n)
+    assert np.array_equal(host_u32(exp).reshape(4, *bsk_o[0].shape), np.stack(bsk_o[:4]))
+    X = lwes_n(orc, s, [p // 8, 3 * p // 8, 5 * p // 8], p, 9, n)  # phases Q/8, 3Q/8, 5Q/8
+    out = zeros_u32(3, orc.lwe_words)
+    V = orc.Q // 8
+    ctx.pbs(bsk, n, dev(X), 3, V, out)
+    want = [None] * 3
+    O._parallel(lambda j: want.__setitem__(j, orc.pbs(bsk_o, X[j], n, V)), range(3))
+    got = host_u32(out).reshape(3, nq, N + 1)
+    for j in range(3):
+        assert np.array_equal(got[j], want[j]), j
+    # V for a phase in [0, Q/2), -V above
+    assert [B.phase(orc, s, w) < orc.Q // 2 for w in want] == [True, True, False]
+
+
+def lwes_n(orc, s, ms, p, seed, n):
+    rng = np.random.default_rng(seed)
+    return np.stack([B.encrypt_short(orc, s, int(m), n, p, rng) for m in ms])
 
 
 def test_activate_and_argmax_circuits_bit_exact():
@@ -135,6 +166,18 @@ def test_activate_and_argmax_by_decryption_wisconsin_params():
         L = (l - 1).bit_length()
         got = decrypt_at(HW, 2048, 2, 1 << (L + 1), sk, idx, len(S))
         assert np.array_equal(got, np.argmax(S, axis=1)), l
+
+
+def test_log_activations_by_decryption_mnist_modulus():
+    """log and b-log (cap 4, the paper's MNIST activation) at p = 2^10"""
+    HW, ctx, orc, sk, s, bsk = setup(2048, 2, 1024)
+    ml = np.array([0, 1, 2, 3, 14, 15, 16, 30, 31, 62, 63, 126, 127, 510, 511, 1022, 1023])
+    X = dev(lwes(orc, s, ml, 1024, 11))
+    for kind, cap in (("log", 0), ("blog", 4)):
+        out = zeros_u32(len(ml), orc.lwe_words)
+        ctx.activate(bsk, 2048, X, len(ml), kind, cap, 6, out)
+        want = P.act_log(ml) if kind == "log" else P.act_blog(ml, cap)
+        assert np.array_equal(decrypt_at(HW, 2048, 2, 64, sk, out, len(ml)), want), kind
 
 
 def test_otf_act_end_to_end_wisconsin_shape():

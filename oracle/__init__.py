@@ -106,6 +106,11 @@ def lib():
                 "orc_rlwe_words": (C.c_uint64, [C.c_void_p]),
                 "orc_rgsw_words": (C.c_uint64, [C.c_void_p]),
                 "orc_logN": (C.c_uint32, [C.c_void_p]),
+                "orc_lwe_keygen": (None, [C.c_uint64, C.c_uint32, C.POINTER(C.c_uint8)]),
+                "orc_ksk_gen": (None, [C.c_void_p, i32p, C.POINTER(C.c_uint8), C.c_uint32, C.c_uint64, C.c_uint32,
+                                       C.c_uint32, u32p]),
+                "orc_key_switch": (None, [C.c_void_p, u32p, C.c_uint32, u32p, u32p]),
+                "orc_pbs_ks": (None, [C.c_void_p, C.POINTER(C.c_void_p), u32p, C.c_uint32, u32p, u64p, u32p]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -443,9 +448,43 @@ class Ctx:
         _parallel(lambda t: out.__setitem__(t, self.enc_rgsw(s, bits[t], seed, t)), range(2 * n))
         return out
 
+    def pbs_ks_keygen(self, s, seed: int, n: int) -> "KsKey":
+        """bootstrapping key through a key switch: the binary LWE key s1 of n
+        coefficients (stream seed, domain LWE_KEY), the key-switching key from
+        s to s1 (modulus 2^32, domains KSK_A and KSK_E of seed) and
+        bsk[i] = RGSW(s1_i) under s as ciphertext i of stream `seed`"""
+        s = np.ascontiguousarray(s, np.int32)
+        s1 = np.zeros(n, np.uint8)
+        lib().orc_lwe_keygen(seed, n, s1.ctypes.data_as(C.POINTER(C.c_uint8)))
+        ksk = np.zeros((self.N * KS_DIGITS, n + 1), np.uint32)
+        ranges = [(k0, min(self.N, k0 + 32)) for k0 in range(0, self.N, 32)]
+        _parallel(lambda r: lib().orc_ksk_gen(self.h, _p(s, i32p), s1.ctypes.data_as(C.POINTER(C.c_uint8)), n, seed,
+                                              r[0], r[1], _p(ksk, u32p)), ranges)
+        bsk = [None] * n
+        _parallel(lambda i: bsk.__setitem__(i, self.enc_rgsw(s, int(s1[i]), seed, i)), range(n))
+        return KsKey(n, s1, ksk, bsk)
+
+    def key_switch(self, key: "KsKey", lwe) -> np.ndarray:
+        """the LWE (ring key, modulus Q) switched to key.s1 at modulus 2^32: [n + 1] uint32"""
+        lwe = np.ascontiguousarray(lwe, np.uint32)
+        out = np.zeros(key.n + 1, np.uint32)
+        lib().orc_key_switch(self.h, _p(key.ksk, u32p), key.n, _p(lwe, u32p), _p(out, u32p))
+        return out
+
     def pbs(self, bsk, lwe, n: int, V: int) -> np.ndarray:
         """programmable bootstrap with the constant test polynomial V: an LWE of
-        V when the switched phase lies in [0, N), of -V otherwise"""
+        V when the switched phase lies in [0, N), of -V otherwise.  bsk: the
+        ring-key bootstrapping key (list of 2n RGSW; blind rotation over the
+        first n ring-key coefficients) or a KsKey (key switch, then blind
+        rotation over the binary key; n is then the key's)"""
+        if isinstance(bsk, KsKey):
+            lwe = np.ascontiguousarray(lwe, np.uint32)
+            rg = [np.ascontiguousarray(r, np.uint32) for r in bsk.bsk]
+            v = np.array([V % q for q in self.primes], np.uint64)
+            out = np.zeros((self.nq, self.N + 1), np.uint32)
+            lib().orc_pbs_ks(self.h, _ptr_array(rg), _p(bsk.ksk, u32p), bsk.n, _p(lwe, u32p), _p(v, u64p),
+                             _p(out, u32p))
+            return out
         lwe = np.ascontiguousarray(lwe, np.uint32)
         rg = [np.ascontiguousarray(r, np.uint32) for r in bsk[: 2 * n]]
         v = np.array([V % q for q in self.primes], np.uint64)
@@ -594,6 +633,18 @@ class Ctx:
         lib().orc_infer_packed(self.h, s, l, a, _p(pi, u32p), _p(H, u32p), _ptr_array(xs), j, layout,
                                _p(out, u32p))
         return out
+
+
+KS_LOG_BASE, KS_DIGITS = 4, 6  # the key switch's gadget (oracle.c)
+
+
+class KsKey:
+    """bootstrapping key through a key switch: n, the binary LWE key s1, the
+    key-switching key [N KS_DIGITS][n + 1] (uint32, modulus 2^32) and the n
+    RGSW(s1_i)"""
+
+    def __init__(self, n, s1, ksk, bsk):
+        self.n, self.s1, self.ksk, self.bsk = n, s1, ksk, bsk
 
 
 def _parallel(fn, items, threads=None):

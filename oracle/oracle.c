@@ -1333,3 +1333,136 @@ void orc_pbs(const orc_ctx* c, const uint32_t* const* bsk, const uint32_t* lwe, 
 uint64_t orc_rlwe_words(const orc_ctx* c) { return rlwe_words(c); }
 uint64_t orc_rgsw_words(const orc_ctx* c) { return rgsw_words(c); }
 uint32_t orc_logN(const orc_ctx* c) { return c->logN; }
+
+/* ------------------------------------------------------------------------ */
+/* bootstrapping through a key switch to a binary LWE key (Sec. 2.5.3: the  */
+/* TFHE setting keeps an LWE key in B^n beside the ring key)                 */
+/* ------------------------------------------------------------------------ */
+
+/* The key switch works at modulus 2^32 with a gadget of KS_DIGITS balanced
+ * digits of KS_LOG_BASE bits taken from the top of each coefficient; the
+ * key-switching key's errors are 2^13 c + u, c a discrete Gaussian sample of
+ * the context's table, u uniform in [-2^12, 2^12).  These parameters are
+ * this implementation's (the paper leaves the bootstrap to other work). */
+#define DOM_LWE_KEY 7u
+#define DOM_KSK_A 8u
+#define DOM_KSK_E 9u
+#define KS_LOG_BASE 4
+#define KS_DIGITS 6
+
+/* s1_i = bit 0 of w64(seed, LWE_KEY, i), i < n */
+void orc_lwe_keygen(uint64_t seed, uint32_t n, uint8_t* s1) {
+  for (uint32_t i = 0; i < n; ++i) s1[i] = (uint8_t)(orc_w64(seed, DOM_LWE_KEY, i) & 1u);
+}
+
+/* round(2^32 x / Q) mod 2^32 (half up) of the integer x in [0, Q) whose
+ * residues are r */
+static uint32_t switch_2_32(const orc_ctx* c, const uint64_t* r) {
+  u128 v = crt(c, r);
+  u128 w = ((v << 32) + c->Q / 2) / c->Q;
+  return (uint32_t)w;
+}
+
+/* Balanced base-16 digits of the top 24 bits of a (rounded): t = round(a /
+ * 2^8) mod 2^24, then from the lowest digit up d = (t mod 16) + carry,
+ * d >= 8 -> d - 16 with a carry of 1; the carry out of the top digit is
+ * dropped (weight 2^32).  a = sum_j d_j 2^(28 - 4j) + (a - 2^8 t) mod 2^32,
+ * d_j in [-8, 8). */
+static void ks_digits(uint32_t a, int32_t* d) {
+  uint32_t t = (uint32_t)((((uint64_t)a + 128u) >> 8) & 0xFFFFFFu);
+  int32_t carry = 0;
+  for (int j = KS_DIGITS - 1; j >= 0; --j) {
+    int32_t x = (int32_t)(t & 15u) + carry;
+    t >>= 4;
+    if (x >= 8) {
+      x -= 16;
+      carry = 1;
+    } else {
+      carry = 0;
+    }
+    d[j] = x;
+  }
+}
+
+/* Key-switching key rows r = k KS_DIGITS + j for k in [k_lo, k_hi): an LWE
+ * under s1 at modulus 2^32 of s_k 2^(28 - 4j):
+ *   A_r[i] = w32(seed, KSK_A, r n + i),
+ *   e_r = 2^13 cdt(w64(seed, KSK_E, 2r)) + (w64(seed, KSK_E, 2r + 1) >> 51) - 2^12,
+ *   B_r = sum_i A_r[i] s1_i + e_r + s_k 2^(28 - 4j)  mod 2^32.
+ * ksk: [N KS_DIGITS][n + 1] (A_r, then B_r). */
+void orc_ksk_gen(const orc_ctx* c, const int32_t* s, const uint8_t* s1, uint32_t n, uint64_t seed,
+                 uint32_t k_lo, uint32_t k_hi, uint32_t* ksk) {
+  for (uint32_t k = k_lo; k < k_hi; ++k)
+    for (uint32_t j = 0; j < KS_DIGITS; ++j) {
+      uint64_t r = (uint64_t)k * KS_DIGITS + j;
+      uint32_t* row = ksk + r * (n + 1);
+      uint32_t b = 0;
+      for (uint32_t i = 0; i < n; ++i) {
+        uint32_t a = orc_w32(seed, DOM_KSK_A, r * n + i);
+        row[i] = a;
+        if (s1[i]) b += a;
+      }
+      int64_t e = orc_cdt_sample(c->cdt, orc_w64(seed, DOM_KSK_E, 2 * r)) * 8192 +
+                  (int64_t)(orc_w64(seed, DOM_KSK_E, 2 * r + 1) >> 51) - 4096;
+      b += (uint32_t)e;
+      b += (uint32_t)((int64_t)s[k] * ((int64_t)1 << (28 - 4 * j)));
+      row[n] = b;
+    }
+}
+
+/* Key switch of an LWE ciphertext under the ring key (modulus Q, mask
+ * length N) to s1 at modulus 2^32: every mask coefficient and the body
+ * switched to 2^32 (round(2^32 x / Q)), then
+ *   out = (0, b') - sum_k sum_j d_j(a'_k) KSK[k KS_DIGITS + j]  mod 2^32,
+ * so that out decrypts under s1 to the switched phase of the input plus the
+ * rounding of the digits and the key's errors times the digits. */
+void orc_key_switch(const orc_ctx* c, const uint32_t* ksk, uint32_t n, const uint32_t* lwe, uint32_t* out) {
+  uint32_t N = c->N, nq = c->nq;
+  uint64_t x[ORC_MAXQ];
+  int32_t d[KS_DIGITS];
+  for (uint32_t i = 0; i < nq; ++i) x[i] = lwe[(size_t)i * (N + 1) + N];
+  memset(out, 0, sizeof(uint32_t) * (n + 1));
+  out[n] = switch_2_32(c, x);
+  for (uint32_t k = 0; k < N; ++k) {
+    for (uint32_t i = 0; i < nq; ++i) x[i] = lwe[(size_t)i * (N + 1) + k];
+    ks_digits(switch_2_32(c, x), d);
+    for (uint32_t j = 0; j < KS_DIGITS; ++j) {
+      if (!d[j]) continue;
+      const uint32_t* row = ksk + ((size_t)k * KS_DIGITS + j) * (n + 1);
+      for (uint32_t i = 0; i <= n; ++i) out[i] -= (uint32_t)d[j] * row[i];
+    }
+  }
+}
+
+/* Programmable bootstrap through the key switch: ks = orc_key_switch(lwe);
+ * (a~, b~) = round(2N ks / 2^32) mod 2N; ACC = (0, X^{-b~} TV) with
+ * TV = V (1 + X + ... + X^{N-1}); for i < n: ACC <- CMUX(bsk[i],
+ * X^{a~_i} ACC, ACC) with bsk[i] = RGSW(s1_i) under the ring key, which
+ * multiplies ACC by X^{a~_i s1_i}; out = ExtractLWE(ACC, 0): V when the
+ * switched phase b~ - sum_i a~_i s1_i mod 2N lies in [0, N), -V otherwise. */
+void orc_pbs_ks(const orc_ctx* c, const uint32_t* const* bsk, const uint32_t* ksk, uint32_t n,
+                const uint32_t* lwe, const uint64_t* v, uint32_t* out) {
+  uint32_t N = c->N, nq = c->nq;
+  size_t rw = rlwe_words(c);
+  uint32_t* ks = (uint32_t*)malloc(sizeof(uint32_t) * (n + 1));
+  int64_t* ex = (int64_t*)malloc(sizeof(int64_t) * (n + 1));
+  uint32_t* acc = (uint32_t*)calloc(rw, sizeof(uint32_t));
+  uint32_t* res = (uint32_t*)malloc(sizeof(uint32_t) * rw);
+  orc_key_switch(c, ksk, n, lwe, ks);
+  const uint32_t sh = 32 - (c->logN + 1);
+  for (uint32_t i = 0; i <= n; ++i)
+    ex[i] = (int64_t)((((uint64_t)ks[i] + ((uint64_t)1 << (sh - 1))) >> sh) % (2 * (uint64_t)N));
+  for (uint32_t i = 0; i < nq; ++i) {
+    uint64_t vi = v[i] % c->q[i];
+    uint32_t* b = res + ((size_t)nq + i) * N;
+    memset(res + (size_t)i * N, 0, sizeof(uint32_t) * N);
+    for (uint32_t j = 0; j < N; ++j) b[j] = (uint32_t)vi;
+  }
+  orc_rlwe_rotate(c, res, -ex[n], acc);
+  orc_blind_rotate(c, acc, bsk, ex, n, res);
+  orc_extract_lwe0(c, res, out);
+  free(ks);
+  free(ex);
+  free(acc);
+  free(res);
+}

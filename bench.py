@@ -41,7 +41,7 @@ WORKLOADS = {
     "wisconsin": dict(name="wisconsin-shaped 30 float features, 2 classes 357/212, therm 16 (480 bits), tuple 8, "
                            "400 train + 169 test, N=2048 x 2 primes",
                       N=2048, nq=2, p=512, l=2, a=8, T=16, n_train=400, n_test=169, chunk=100, balance=False,
-                      cpu_samples=12, otf=16, fm=4, act=("log", 0)),
+                      cpu_samples=12, otf=16, fm=4, act=("log", 0), boot_n=1024),
     "tiny": dict(name="tiny 8x8, 2 classes, therm 2, tuple 8, 32 train + 16 test, N=1024 x 1 prime",
                  N=1024, nq=1, p=64, l=2, a=8, T=2, n_train=32, n_test=16, chunk=32, balance=False),
 }
@@ -730,6 +730,29 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev, peaks=None):
     }, cells
 
 
+def boot_key(ctx, sk, seed: int, W: dict, dev):
+    """the bootstrapping key of the workload: through a key switch to a
+    binary LWE key of W["boot_n"] coefficients, or (boot_n = 0) over the
+    ring key.  Returns (key for the bootstrapping calls, description,
+    key generation seconds)."""
+    import torch
+    N = W["N"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if W.get("boot_n"):
+        key = ctx.pbs_ks_keygen(sk, seed, W["boot_n"], dev)
+        info = {"kind": "key switch to a binary LWE key", "n": W["boot_n"],
+                "external_products_per_bootstrap": W["boot_n"],
+                "bsk_gib": round(key.bsk.numel() * 4 / 2**30, 3), "ksk_mib": round(key.ksk.numel() / 2**20, 1)}
+    else:
+        key = torch.empty(ctx.pbs_key_words(N), dtype=torch.int32, device=dev)
+        ctx.pbs_keygen(sk, seed, N, key)
+        info = {"kind": "ring key (two CMUXes per coefficient)", "n": N, "external_products_per_bootstrap": 2 * N,
+                "bsk_gib": round(ctx.pbs_key_words(N) * 4 / 2**30, 3)}
+    torch.cuda.synchronize()
+    return key, info, time.perf_counter() - t0
+
+
 def act_max(kind: str, param: int, P: int) -> int:
     """largest value the activation takes on m < 2^P"""
     return 1 if kind == "ge" else (P if kind == "log" else min(param, P))
@@ -780,12 +803,7 @@ def otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0):
     sc = torch.empty(m, l, k0, ctx.lwe_words, dtype=torch.int32, device=dev)
     ctx.infer(sh, H, xr, m, sc, None)
     del xr
-    bsk = torch.empty(ctx.pbs_key_words(N), dtype=torch.int32, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.pbs_keygen(sk, seeds["key"] + 200, N, bsk)
-    torch.cuda.synchronize()
-    key_s = time.perf_counter() - t0
+    bsk, key_info, key_s = boot_key(ctx, sk, seeds["key"] + 200, W, dev)
     kind, param = W["act"]
     P = (W["p"] - 1).bit_length()
     lp = (k0 * act_max(kind, param, P)).bit_length() + 1  # class sums below p_out / 2
@@ -798,7 +816,7 @@ def otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0):
     t0 = time.perf_counter()
     ctx.activate(bsk, N, sc, m * l * k0, kind, param, lp, act)
     ctx.class_sums(act, m, l, k0, sums)
-    ctx.encrypted_argmax(bsk, N, sums, m, l, lp, idx)
+    ctx.encrypted_argmax(bsk, N, sums, m, l, lp, idx)  # n is the key's when bsk is key-switched
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     a_ms = ctx.profile_read("activate")[0]
@@ -813,13 +831,13 @@ def otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0):
     pbs_per_sample = l * k0 * act_bootstraps(kind, param, P) + (l * (l - 1) // 2) * lp + l * max(0, l - 2)
     del bsk, act, sums, idx, sc
     torch.cuda.empty_cache()
-    return {"samples": m, "activation": act_name(kind, param), "output_modulus": 1 << lp,
+    xpb = key_info["external_products_per_bootstrap"]
+    return {"samples": m, "activation": act_name(kind, param), "output_modulus": 1 << lp, "key": key_info,
             "bootstraps_per_sample": pbs_per_sample,
-            "external_products_per_bootstrap": 2 * N,
+            "external_products_per_bootstrap": xpb,
             "seconds": round(dt, 3), "samples_per_s": round(m / dt, 4),
             "activate_ms_per_sample": round(a_ms / m, 2), "argmax_ms_per_sample": round(g_ms / m, 2),
-            "external_products_per_s": round(m * pbs_per_sample * 2 * N / dt, 1),
-            "key_gib": round(ctx.pbs_key_words(N) * 4 / 2**30, 2), "keygen_s": round(key_s, 3),
+            "external_products_per_s": round(m * pbs_per_sample * xpb / dt, 1), "keygen_s": round(key_s, 3),
             "predictions_equal_pd_act": bool(np.array_equal(got, want)),
             "paper_estimate": "OTF-act 3.7 min per inference at 9-bit precision on one thread (paper Table 9)"}
 
@@ -842,14 +860,9 @@ def fm_pass(ctx, sh, H, sk, Xte, W, seeds, k0, k1, dev, cells0, full=False):
     rows = k0 if full else min(W["fm"], k0)
     shs = sh if full else HW.shape(rows * a, l, a, seeds["perm"], 0)  # the first `rows` RAMs
     src = H.view(k0 * k1, -1)[: rows * k1]
-    bsk = torch.empty(ctx.pbs_key_words(N), dtype=torch.int32, device=dev)
+    bsk, key_info, key_s = boot_key(ctx, sk, seeds["key"] + 300, W, dev)
     key = torch.empty(ctx.pks_key_words, dtype=torch.int32, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.pbs_keygen(sk, seeds["key"] + 300, N, bsk)
     ctx.pks_keygen(sk, seeds["key"] + 301, key)
-    torch.cuda.synchronize()
-    key_s = time.perf_counter() - t0
     kind, param = W["act"]
     P = (W["p"] - 1).bit_length()
     lp = (k0 * act_max(kind, param, P)).bit_length() + 1  # class sums below p_out / 2
@@ -873,10 +886,11 @@ def fm_pass(ctx, sh, H, sk, Xte, W, seeds, k0, k1, dev, cells0, full=False):
     want = act_plain(CL, dec0.cpu().numpy(), kind, param)
     want[:, K:] = 0
     nb = act_bootstraps(kind, param, P)
+    xpb = key_info["external_products_per_bootstrap"]
     out = {"rams": rows, "cells": cells, "activation": act_name(kind, param), "output_modulus": 1 << lp,
-           "bootstraps_per_cell": nb, "external_products_per_bootstrap": 2 * N,
+           "key": key_info, "bootstraps_per_cell": nb, "external_products_per_bootstrap": xpb,
            "seconds": round(dt, 3), "cells_per_s": round(cells / dt, 2),
-           "external_products_per_s": round(cells * nb * 2 * N / dt, 1),
+           "external_products_per_s": round(cells * nb * xpb / dt, 1),
            "ms": {k: round(v, 1) for k, v in ms.items()},
            "full_model_cells": k0 * k1 * K, "full_model_s": round(k0 * k1 * K / (cells / dt), 1),
            "keygen_s": round(key_s, 3), "pks_key_gib": round(ctx.pks_key_words * 4 / 2**30, 2),

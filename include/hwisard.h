@@ -298,6 +298,42 @@ hw_status hw_pack_lwe(hw_ctx* ctx, const uint32_t* key_dev, const uint32_t* lwe_
 hw_status hw_pbs_keygen(hw_ctx* ctx, const int32_t* sk_dev, uint64_t seed, uint32_t n, uint32_t* bsk_dev,
                         hipStream_t stream);
 
+/* Bootstrapping through a key switch (the TFHE setting of Sec. 2.5.3 keeps an
+ * LWE key S0 in B^n beside the ring key): the LWE ciphertext (ring key,
+ * modulus Q) is switched to modulus 2^32 (round(2^32 x / Q)), key-switched
+ * to a binary key s1 of n coefficients, switched to 2N, and blind-rotated
+ * with one CMUX per coefficient of s1 (n external products instead of the
+ * ring key's 2n per coefficient); the output is an LWE under the ring key as
+ * before.  Key switch: each switched mask coefficient a'_k is rounded to its
+ * top 24 bits and cut into 6 balanced base-16 digits d_j (weight 2^(28-4j));
+ * out = (0, b') - sum_{k,j} d_j(a'_k) KSK[6k + j] mod 2^32, with KSK[6k + j]
+ * an LWE under s1 at modulus 2^32 of s_k 2^(28-4j) whose error is 2^13 c + u
+ * (c the Gaussian sample, u uniform in [-2^12, 2^12)).  The sum over the 6N
+ * digits runs as a contraction of signed bytes on the matrix cores (the
+ * 32-bit key words cut into four signed bytes), exact mod 2^32.
+ * hw_pbs_ks_keygen: s1_i = bit 0 of draw i of stream (seed, domain 7)
+ * into lwe_key_dev (uint8 [n], device); bsk_dev = RGSW(s1_i) as ciphertexts
+ * 0..n-1 of hw_encrypt_rgsw_bits' stream `seed`; ksk_dev = the key in the
+ * contraction's layout, signed bytes [cols][6N], row l (n + 1) + i holding
+ * byte l of word i of every KSK row (A_r then B_r at i = n; A_r[i] = 32-bit
+ * draw r n + i of (seed, 8), the error from 64-bit draws 2r and 2r + 1 of
+ * (seed, 9)), cols = 4 (n + 1) rounded up to 64, the padding rows zero.
+ * Sizes from hw_pbs_ks_sizes.  1 <= n <= 8192. */
+hw_status hw_pbs_ks_sizes(const hw_ctx* ctx, uint32_t n, uint64_t* bsk_bytes, uint64_t* ksk_bytes);
+hw_status hw_pbs_ks_keygen(hw_ctx* ctx, const int32_t* sk_dev, uint64_t seed, uint32_t n, uint8_t* lwe_key_dev,
+                           uint32_t* bsk_dev, int8_t* ksk_dev, hipStream_t stream);
+
+/* The key every bootstrapping call takes: ksk == NULL for the ring-key
+ * bootstrap (bsk from hw_pbs_keygen, 2n RGSW, n <= N ring coefficients),
+ * otherwise the key-switched one (bsk and ksk from hw_pbs_ks_keygen, n the
+ * LWE key's length). */
+typedef struct {
+  const uint32_t* bsk;  /* device */
+  const int8_t* ksk;    /* device or NULL */
+  uint32_t n;
+  uint32_t reserved;    /* 0 */
+} hw_boot_key;
+
 /* Bootstrap with the constant test polynomial V (v: its nq residues, host)
  * of `count` LWE ciphertexts whose mask is zero past its first n
  * coefficients (n = N for ExtractLWE outputs; bsk from hw_pbs_keygen with at
@@ -305,9 +341,12 @@ hw_status hw_pbs_keygen(hw_ctx* ctx, const int32_t* sk_dev, uint64_t seed, uint3
  * (x read through the CRT, half up), ACC = (0, X^{-b~} V (1 + X + ... +
  * X^{N-1})), then for k < n ACC <- CMUX(bsk[2k], X^{a~_k} ACC, ACC) and
  * ACC <- CMUX(bsk[2k+1], X^{-a~_k} ACC, ACC), out = ExtractLWE(ACC, 0): an
- * LWE of V when the switched phase lies in [0, N), of -V otherwise.
+ * LWE of V when the switched phase lies in [0, N), of -V otherwise.  With a
+ * key-switched key (key->ksk set) the input may have a full mask; its switch
+ * to 2N is the one of hw_pbs_ks_keygen's key switch and the blind rotation
+ * is ACC <- CMUX(bsk[i], X^{a~_i} ACC, ACC) for i < key->n.
  * lwe_dev, out_dev: [count] LWE, not overlapping. */
-hw_status hw_pbs(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const uint32_t* lwe_dev, uint64_t count,
+hw_status hw_pbs(hw_ctx* ctx, const hw_boot_key* key, const uint32_t* lwe_dev, uint64_t count,
                  const uint32_t* v_host, uint32_t* out_dev, hipStream_t stream);
 
 /* Activate with the threshold activation (bin of PD-act with thr = T - 1):
@@ -323,8 +362,8 @@ hw_status hw_pbs(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const uint32_
  *     c = PBS(z, V) + V with V = V_o for k = P-1, else V_c.
  * Each bootstrap decides a sign with a margin of N/8 switched positions or
  * more.  2P bootstraps per ciphertext; lwe_dev, out_dev: [count] LWE. */
-hw_status hw_activate_ge(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const uint32_t* lwe_dev,
-                         uint64_t count, uint64_t T, uint32_t log_p_out, uint32_t* out_dev, hipStream_t stream);
+hw_status hw_activate_ge(hw_ctx* ctx, const hw_boot_key* key, const uint32_t* lwe_dev, uint64_t count,
+                         uint64_t T, uint32_t log_p_out, uint32_t* out_dev, hipStream_t stream);
 
 /* The activations of Sec. 2.4.2 that the paper's models use (its parameter
  * table: bin with a threshold, log, b-log), as bootstrapped circuits over
@@ -348,7 +387,7 @@ hw_status hw_activate_ge(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const
 #define HW_ACT_GE 0u
 #define HW_ACT_LOG 1u
 #define HW_ACT_BLOG 2u
-hw_status hw_activate(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const uint32_t* lwe_dev, uint64_t count,
+hw_status hw_activate(hw_ctx* ctx, const hw_boot_key* key, const uint32_t* lwe_dev, uint64_t count,
                       uint32_t kind, uint64_t param, uint32_t log_p_out, uint32_t* out_dev, hipStream_t stream);
 
 /* EncryptedArgMax (Alg. 7): for each of `count` samples, the l class scores
@@ -364,7 +403,7 @@ hw_status hw_activate(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const ui
  * G(a, b_j) - 3 V_c, V) + V with V = V_x for the last b_j, else V_c);
  * index = sum_a a W_a.  u_dev: [count][l] LWE; out_dev: [count] LWE.
  * 2 <= l <= 64, 3 <= log_p_in <= 20. */
-hw_status hw_encrypted_argmax(hw_ctx* ctx, const uint32_t* bsk_dev, uint32_t n, const uint32_t* u_dev,
+hw_status hw_encrypted_argmax(hw_ctx* ctx, const hw_boot_key* key, const uint32_t* u_dev,
                               uint64_t count, uint32_t l, uint32_t log_p_in, uint32_t* out_dev,
                               hipStream_t stream);
 
@@ -391,7 +430,7 @@ hw_status hw_class_sums(hw_ctx* ctx, const uint32_t* scores_dev, uint64_t n, uin
  * cells, allocates two LWE buffers of that many cells for the call and
  * waits for the stream before returning.  Errors as hw_activate and
  * hw_pack_lwe, checked before anything runs. */
-hw_status hw_fm_act(hw_ctx* ctx, const hw_wisard_shape* shape, const uint32_t* bsk_dev, uint32_t n,
+hw_status hw_fm_act(hw_ctx* ctx, const hw_wisard_shape* shape, const hw_boot_key* key,
                     const uint32_t* pks_key_dev, const uint32_t* model_dev, uint32_t kind, uint64_t param,
                     uint32_t log_p_out, uint32_t* out_dev, hipStream_t stream);
 

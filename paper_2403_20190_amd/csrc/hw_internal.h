@@ -155,6 +155,12 @@ struct SumArgs {
 
 // launchers (hw_kernels.hip); return hipSuccess or the launch error
 hipError_t launch_keygen(uint32_t N, uint64_t seed, int32_t* sk, hipStream_t st);
+// the binary LWE key s1[n] and the key-switching key from sk to it, D digits
+// per ring coefficient, as signed bytes [4 (n + 1)][N D] (the rows past
+// 4 (n + 1) of a padded buffer are left as they are)
+hipError_t launch_lwe_keygen(uint32_t n, uint64_t seed, uint8_t* s1, hipStream_t st);
+hipError_t launch_ksk_gen(const int32_t* sk, const uint8_t* s1, uint32_t N, uint32_t n, uint64_t seed, uint32_t D,
+                          const Cdt& cdt, int8_t* out, hipStream_t st);
 // sk_hat: 2 nq N words (the transformed key, then its Shoup companions)
 hipError_t launch_sk_hat(int logN, int nq, const Tabs& T, const int32_t* sk, uint32_t* sk_hat, hipStream_t st);
 hipError_t launch_enc_rgsw(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,

@@ -117,6 +117,75 @@ __global__ void k_keygen(uint32_t N, uint64_t seed, int32_t* sk) {
   sk[k] = (int32_t)(w % 3) - 1;
 }
 
+// Binary LWE key of n coefficients (the key the bootstrap switches to):
+// s1_i = bit 0 of the 64-bit draw i of stream (seed, LWE_KEY)
+constexpr uint32_t DOM_LWE_KEY = 7, DOM_KSK_A = 8, DOM_KSK_E = 9;
+
+__global__ void k_lwe_keygen(uint32_t n, uint64_t seed, uint8_t* __restrict__ s1) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t d0, d1;
+  draw_pair(seed, DOM_LWE_KEY, i >> 1, d0, d1);
+  s1[i] = (uint8_t)(((i & 1) ? d1 : d0) & 1u);
+}
+
+// the four signed bytes m_l in [-128, 128) with sum_l m_l 2^(8l) = v mod 2^32
+// (lowest first, a byte >= 128 taken as byte - 256 with a carry into the next;
+// the carry out of the top byte has weight 2^32)
+__device__ __forceinline__ void signed_bytes(uint32_t v, int8_t (&m)[4]) {
+  uint32_t carry = 0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    const uint32_t x = ((v >> (8 * l)) & 255u) + carry;
+    carry = x >= 128u;
+    m[l] = (int8_t)(int32_t)(carry ? (int32_t)x - 256 : (int32_t)x);
+  }
+}
+
+// Key-switching key from the ring key s to s1 at modulus 2^32: row r = k D + j
+// (D = KS digits, k < N, j < D) is A_r[i] = draw32(seed, KSK_A, r n + i) and
+// B_r = sum_i A_r[i] s1_i + e_r + s_k 2^(28 - 4j), e_r = 2^13 c + u with c the
+// Gaussian sample of draw64(seed, KSK_E, 2r) and u = (draw64(seed, KSK_E,
+// 2r + 1) >> 51) - 2^12.  Stored for the contraction as signed bytes:
+// out[(l (n + 1) + i) K + r] = byte l of A_r[i] (i < n) or of B_r (i = n),
+// K = N D.  One workgroup of 256 threads per row.
+__global__ __launch_bounds__(256) void k_ksk_gen(const int32_t* __restrict__ sk, const uint8_t* __restrict__ s1,
+                                                 uint32_t n, uint64_t seed, uint32_t D, uint64_t K, Cdt cdt,
+                                                 int8_t* __restrict__ out) {
+  __shared__ uint32_t part[256];
+  const uint64_t r = blockIdx.x;
+  const uint32_t t = threadIdx.x;
+  uint32_t dot = 0;
+  for (uint32_t i = t; i < n; i += 256) {
+    const uint64_t x = r * n + i;
+    const uint4 w = draw4(seed, DOM_KSK_A, x >> 2);
+    const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+    const uint32_t a = ww[x & 3];
+    if (s1[i]) dot += a;
+    int8_t m[4];
+    signed_bytes(a, m);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) out[((uint64_t)l * (n + 1) + i) * K + r] = m[l];
+  }
+  part[t] = dot;
+  __syncthreads();
+  for (uint32_t h = 128; h >= 1; h >>= 1) {
+    if (t < h) part[t] += part[t + h];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const uint32_t k = (uint32_t)(r / D), j = (uint32_t)(r - (uint64_t)k * D);
+    uint64_t d0, d1;
+    draw_pair(seed, DOM_KSK_E, r, d0, d1);
+    const int64_t e = (int64_t)cdt_sample(cdt.T, d0) * 8192 + (int64_t)(d1 >> 51) - 4096;
+    const uint32_t b = part[0] + (uint32_t)e + (uint32_t)((int64_t)sk[k] * ((int64_t)1 << (28 - 4 * j)));
+    int8_t m[4];
+    signed_bytes(b, m);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) out[((uint64_t)l * (n + 1) + n) * K + r] = m[l];
+  }
+}
+
 // The Fisher-Yates permutation of [0, s) with the generator's PERM stream
 // (the host's make_perm, on the device): for k = s-1 down to 1, swap entries
 // k and j = draw64(seed, PERM, s-1-k) mod (k+1).  One thread: the swaps are
@@ -1399,6 +1468,18 @@ static hipError_t for_rect(uint64_t count, F&& f) {
 
 hipError_t launch_keygen(uint32_t N, uint64_t seed, int32_t* sk, hipStream_t st) {
   hipLaunchKernelGGL(k_keygen, dim3((N + 255) / 256), dim3(256), 0, st, N, seed, sk);
+  return hipGetLastError();
+}
+
+hipError_t launch_lwe_keygen(uint32_t n, uint64_t seed, uint8_t* s1, hipStream_t st) {
+  hipLaunchKernelGGL(k_lwe_keygen, dim3((n + 255) / 256), dim3(256), 0, st, n, seed, s1);
+  return hipGetLastError();
+}
+
+hipError_t launch_ksk_gen(const int32_t* sk, const uint8_t* s1, uint32_t N, uint32_t n, uint64_t seed, uint32_t D,
+                          const Cdt& cdt, int8_t* out, hipStream_t st) {
+  const uint64_t K = (uint64_t)N * D;
+  hipLaunchKernelGGL(k_ksk_gen, dim3((uint32_t)K), dim3(256), 0, st, sk, s1, n, seed, D, K, cdt, out);
   return hipGetLastError();
 }
 

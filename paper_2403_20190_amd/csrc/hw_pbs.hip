@@ -69,13 +69,14 @@ __global__ __launch_bounds__(256) void k_pbs_switch(Tabs T, CrtTab K, uint32_t N
 }
 
 struct RotArgs {
-  const uint32_t* bsk;   // [2n] RGSW, device layout
+  const uint32_t* bsk;   // [2n] RGSW (ring key) or [n] RGSW (binary key), device layout
   const uint32_t* ms;    // [count][n + 1] switched mask and body
   uint32_t* slots;       // [count][2] RLWE: the accumulator and the CMUX input
   uint32_t* out;         // [count] LWE
   uint64_t rgsw_words;
   uint64_t count;
   uint32_t n;
+  uint32_t binary;       // 1: one CMUX per coefficient against bsk[k] (binary key)
   uint32_t v[MAXQ];      // V mod q_i
 };
 
@@ -132,10 +133,10 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(3,
   for (uint32_t k = 0; k < A.n; ++k) {
     const int32_t a = (int32_t)ms[k];
 #pragma unroll 1
-    for (int sg = 0; sg < 2; ++sg) {
+    for (int sg = 0; sg < (A.binary ? 1 : 2); ++sg) {
       pbs_rot_diff<LOGN, NQ>(T, acc, sg ? -a : a, xin, t);
-      ext_prod<LOGN, NQ>(xin, A.bsk + (size_t)(2 * k + sg) * A.rgsw_words, T, lds, twl, xc, t,
-                         XpOut{acc, acc, nullptr, XP_ADD});
+      const size_t row = A.binary ? (size_t)k : (size_t)(2 * k + sg);
+      ext_prod<LOGN, NQ>(xin, A.bsk + row * A.rgsw_words, T, lds, twl, xc, t, XpOut{acc, acc, nullptr, XP_ADD});
       __syncthreads();  // the next rotation reads coefficients other threads wrote
     }
   }
@@ -152,6 +153,112 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(3,
     }
     if (t == 0) o[(size_t)i * (N + 1) + N] = acc[(size_t)(NQ + i) * N];
   }
+}
+
+// ---- key switch to the binary LWE key (modulus 2^32) ----------------------
+
+constexpr uint32_t KS_DIGITS = 6;  // balanced base-16 digits of the top 24 bits
+
+// round(2^32 x / Q) mod 2^32 (half up) of x in [0, Q) with residues r
+template <int NQ>
+__device__ __forceinline__ uint32_t switch_2_32(const uint32_t (&r)[NQ], const Tabs& T, const CrtTab& K) {
+  const u128 Q = ((u128)K.Q_hi << 64) | K.Q_lo;
+  u128 x = 0;
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) {
+    const uint32_t y = mulq(r[i], K.inv[i], T.pt[i]);
+    const u128 M = ((u128)K.M_hi[i] << 64) | K.M_lo[i];
+    x += (u128)y * M;
+    if (x >= Q) x -= Q;
+  }
+  const u128 num = (x << 32) + (((u128)K.half_hi << 64) | K.half_lo);
+  uint64_t qt = (uint64_t)(u128_dbl(num) / u128_dbl(Q));
+  while (qt > 0 && (u128)qt * Q > num) --qt;
+  while ((u128)(qt + 1) * Q <= num) ++qt;
+  return (uint32_t)qt;
+}
+
+// Digits of the key switch: for ciphertext c and mask coefficient k < N, the
+// switched a'_k, rounded to its top 24 bits (t = round(a' / 2^8) mod 2^24),
+// as KS_DIGITS balanced base-16 digits d_j (weight 2^(28 - 4j)) into
+// dig[c][k KS_DIGITS + j]; for k = N the switched body into body[c].  One
+// thread per (c, k <= N).
+template <int NQ>
+__global__ __launch_bounds__(256) void k_ks_digits(Tabs T, CrtTab K, uint32_t N, const uint32_t* __restrict__ lwe,
+                                                   uint64_t count, int8_t* __restrict__ dig,
+                                                   uint32_t* __restrict__ body) {
+  const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= count * (N + 1)) return;
+  const uint64_t c = g / (N + 1);
+  const uint32_t k = (uint32_t)(g - c * (N + 1));
+  uint32_t r[NQ];
+#pragma unroll
+  for (int i = 0; i < NQ; ++i) r[i] = lwe[(c * NQ + i) * (N + 1) + k];
+  const uint32_t a = switch_2_32<NQ>(r, T, K);
+  if (k == N) {
+    body[c] = a;
+    return;
+  }
+  uint32_t t = (uint32_t)((((uint64_t)a + 128u) >> 8) & 0xFFFFFFu);
+  int32_t carry = 0;
+  int8_t d[KS_DIGITS];
+#pragma unroll
+  for (int j = KS_DIGITS - 1; j >= 0; --j) {
+    int32_t x = (int32_t)(t & 15u) + carry;
+    t >>= 4;
+    carry = x >= 8;
+    d[j] = (int8_t)(carry ? x - 16 : x);
+  }
+  int8_t* o = dig + c * ((uint64_t)N * KS_DIGITS) + (uint64_t)k * KS_DIGITS;
+#pragma unroll
+  for (int j = 0; j < (int)KS_DIGITS; ++j) o[j] = d[j];
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// The key switch's contraction C[c][col] = sum_r dig[c][r] ksk[col][r] over
+// r < Kd = N KS_DIGITS: signed bytes in, exact 32-bit sums out (|sum| <= 8 x
+// 128 x Kd < 2^31 for N <= 4096).  MFMA 16x16x32 (i8 -> i32): each wave
+// computes a 16 x 16 tile of C; lane l feeds A[l mod 16][8 (l / 16) + 0..7]
+// (8 consecutive bytes of a row of dig) and B[8 (l / 16) + 0..7][l mod 16]
+// (8 consecutive bytes of a row of ksk, which holds the key column-major) and
+// receives C[4 (l / 16) + 0..3][l mod 16].  Four waves per workgroup cover
+// 64 columns; rows of dig and ksk are Kd bytes (a multiple of 32), dig has
+// (a multiple of) 16 rows per block row, ksk (a multiple of) 64 rows.
+__global__ __launch_bounds__(256) void k_ks_gemm(const int8_t* __restrict__ dig, const int8_t* __restrict__ ksk,
+                                                 uint64_t Kd, uint32_t cols, int32_t* __restrict__ C) {
+  const uint32_t l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t row0 = (uint64_t)blockIdx.y * 16, col0 = (uint64_t)blockIdx.x * 64 + w * 16;
+  const int8_t* pa = dig + (row0 + (l & 15)) * Kd + 8 * (l >> 4);
+  const int8_t* pb = ksk + (col0 + (l & 15)) * Kd + 8 * (l >> 4);
+  v4i acc = {0, 0, 0, 0};
+#pragma unroll 4
+  for (uint64_t k = 0; k < Kd; k += 32) {
+    const long a = *reinterpret_cast<const long*>(pa + k);
+    const long b = *reinterpret_cast<const long*>(pb + k);
+    acc = __builtin_amdgcn_mfma_i32_16x16x32_i8(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) C[(row0 + 4 * (l >> 4) + i) * cols + col0 + (l & 15)] = acc[i];
+}
+
+// The switched ciphertext from the contraction and its modulus switch to 2N:
+// v_i = sum_l C[c][l (n + 1) + i] 2^(8l) mod 2^32 is sum_r d_r KSK_r[i]; the key
+// switch gives a_i = -v_i (i < n), b = body - v_n (mod 2^32), and
+// ms[c][i] = round(2N x / 2^32) mod 2N of each.  One thread per (c, i <= n).
+__global__ __launch_bounds__(256) void k_ks_combine(const int32_t* __restrict__ C, uint32_t cols, uint32_t n,
+                                                    const uint32_t* __restrict__ body, uint64_t count,
+                                                    uint32_t log2n2, uint32_t* __restrict__ ms) {
+  const uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= count * (n + 1)) return;
+  const uint64_t c = g / (n + 1);
+  const uint32_t i = (uint32_t)(g - c * (n + 1));
+  uint32_t v = 0;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) v += (uint32_t)C[c * cols + (uint64_t)l * (n + 1) + i] << (8 * l);
+  const uint32_t x = (i < n ? 0u : body[c]) - v;
+  const uint32_t sh = 32 - log2n2;
+  ms[g] = (uint32_t)((((uint64_t)x + (1ull << (sh - 1))) >> sh) & ((1ull << log2n2) - 1));
 }
 
 struct LinArgs {
@@ -248,12 +355,21 @@ using hw::u128;
 struct Pbs {
   hw_ctx* c;
   const uint32_t* bsk;
+  const int8_t* ksk;  // key switch to the binary LWE key; nullptr: the ring key
   uint32_t n;
   hipStream_t st;
   uint32_t* ms;     // [cmax][n + 1]
   uint32_t* slots;  // [cmax][2] RLWE
+  int8_t* dig;      // key switch: [cmax rounded up to 16][N KS_DIGITS] digits
+  int32_t* C;       // key switch: [same rows][cols] contraction
+  uint32_t* body;   // key switch: [same rows] switched bodies
+  uint32_t cols;    // key switch: 4 (n + 1) rounded up to 64
   size_t lw;        // words of an LWE ciphertext
 };
+
+// columns of the key switch's contraction for an LWE key of n coefficients:
+// four signed bytes of each of the n + 1 words, padded to 64
+uint32_t ks_cols(uint32_t n) { return ((4 * (n + 1) + 63) / 64) * 64; }
 
 uint32_t res_of(u128 x, uint32_t q) { return (uint32_t)(x % q); }
 
@@ -296,13 +412,33 @@ hipError_t pbs(const Pbs& B, uint64_t count, const uint32_t* in, uint32_t* out, 
   hw_ctx* c = B.c;
   if (!count) return hipSuccess;
   const uint32_t N = c->prm.N, nq = c->prm.nq;
-  const uint64_t vals = count * (B.n + 1);
-  const dim3 gs((uint32_t)((vals + 255) / 256));
-  if (nq == 1) hipLaunchKernelGGL(hw::k_pbs_switch<1>, gs, dim3(256), 0, B.st, c->tabs, c->crt, N, B.n, in, count, B.ms);
-  else if (nq == 2) hipLaunchKernelGGL(hw::k_pbs_switch<2>, gs, dim3(256), 0, B.st, c->tabs, c->crt, N, B.n, in, count, B.ms);
-  else hipLaunchKernelGGL(hw::k_pbs_switch<3>, gs, dim3(256), 0, B.st, c->tabs, c->crt, N, B.n, in, count, B.ms);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (B.ksk) {  // key switch to the binary key at 2^32, then to 2N
+    const uint64_t vals = count * (N + 1);
+    const dim3 gd((uint32_t)((vals + 255) / 256));
+    if (nq == 1) hipLaunchKernelGGL(hw::k_ks_digits<1>, gd, dim3(256), 0, B.st, c->tabs, c->crt, N, in, count, B.dig, B.body);
+    else if (nq == 2) hipLaunchKernelGGL(hw::k_ks_digits<2>, gd, dim3(256), 0, B.st, c->tabs, c->crt, N, in, count, B.dig, B.body);
+    else hipLaunchKernelGGL(hw::k_ks_digits<3>, gd, dim3(256), 0, B.st, c->tabs, c->crt, N, in, count, B.dig, B.body);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint64_t Kd = (uint64_t)N * hw::KS_DIGITS;
+    hipLaunchKernelGGL(hw::k_ks_gemm, dim3(B.cols / 64, (uint32_t)((count + 15) / 16)), dim3(256), 0, B.st, B.dig,
+                       B.ksk, Kd, B.cols, B.C);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const uint64_t outs = count * (B.n + 1);
+    hipLaunchKernelGGL(hw::k_ks_combine, dim3((uint32_t)((outs + 255) / 256)), dim3(256), 0, B.st, B.C, B.cols, B.n,
+                       B.body, count, (uint32_t)c->logN + 1, B.ms);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  } else {
+    const uint64_t vals = count * (B.n + 1);
+    const dim3 gs((uint32_t)((vals + 255) / 256));
+    if (nq == 1) hipLaunchKernelGGL(hw::k_pbs_switch<1>, gs, dim3(256), 0, B.st, c->tabs, c->crt, N, B.n, in, count, B.ms);
+    else if (nq == 2) hipLaunchKernelGGL(hw::k_pbs_switch<2>, gs, dim3(256), 0, B.st, c->tabs, c->crt, N, B.n, in, count, B.ms);
+    else hipLaunchKernelGGL(hw::k_pbs_switch<3>, gs, dim3(256), 0, B.st, c->tabs, c->crt, N, B.n, in, count, B.ms);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hw::RotArgs A{};
   A.bsk = B.bsk;
   A.ms = B.ms;
@@ -311,6 +447,7 @@ hipError_t pbs(const Pbs& B, uint64_t count, const uint32_t* in, uint32_t* out, 
   A.rgsw_words = rgsw_words(c);
   A.count = count;
   A.n = B.n;
+  A.binary = B.ksk != nullptr;
   for (uint32_t i = 0; i < nq; ++i) A.v[i] = res_of(V, c->tabs.pt[i].q);
   const dim3 g((uint32_t)std::min<uint64_t>(count, 65535), (uint32_t)((count + 65534) / 65535));
   PBS_DISPATCH(c->logN, nq,
@@ -335,22 +472,37 @@ hipError_t bits(const Pbs& B, uint64_t count, uint32_t P, uint32_t* x, uint32_t*
   return hipSuccess;
 }
 
-hw_status pbs_setup(hw_ctx* c, const uint32_t* bsk, uint32_t n, uint64_t count, size_t extra_lwe, hipStream_t st,
-                    Pbs* B, uint64_t* cmax, uint32_t** lwes) {
+hw_status pbs_setup(hw_ctx* c, const hw_boot_key* key, uint64_t count, size_t extra_lwe, hipStream_t st, Pbs* B,
+                    uint64_t* cmax, uint32_t** lwes) {
+  const uint32_t n = key->n;
   B->c = c;
-  B->bsk = bsk;
+  B->bsk = key->bsk;
+  B->ksk = reinterpret_cast<const int8_t*>(key->ksk);
   B->n = n;
   B->st = st;
   B->lw = lwe_words(c);
-  // per ciphertext: the switched values, two RLWE slots, extra_lwe LWE temporaries
-  const size_t per = (size_t)(n + 1) * 4 + 2 * rlwe_words(c) * 4 + extra_lwe * B->lw * 4;
+  B->cols = B->ksk ? ks_cols(n) : 0;
+  const size_t kd = (size_t)c->prm.N * hw::KS_DIGITS;
+  // per ciphertext: the switched values, two RLWE slots, extra_lwe LWE
+  // temporaries; with the key switch also its digits, contraction and body
+  const size_t per = (size_t)(n + 1) * 4 + 2 * rlwe_words(c) * 4 + extra_lwe * B->lw * 4 +
+                     (B->ksk ? kd + (size_t)B->cols * 4 + 4 : 0);
   uint64_t m = std::max<uint64_t>(1, c->ws_budget / per);
   m = std::min<uint64_t>(m, count);
-  CHECK(ensure_ws(c, m * per + 256));
-  uint32_t* base = static_cast<uint32_t*>(c->d_ws);
-  B->slots = base;
-  B->ms = base + m * 2 * rlwe_words(c);
-  *lwes = B->ms + ((m * (n + 1) + 63) / 64) * 64;
+  if (B->ksk && m > 16) m -= m % 16;
+  const uint64_t m16 = (m + 15) / 16 * 16;  // rows of the contraction
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b_slots = up(m * 2 * rlwe_words(c) * 4), b_ms = up(m * (n + 1) * 4);
+  const size_t b_dig = B->ksk ? up(m16 * kd) : 0, b_c = B->ksk ? up(m16 * B->cols * 4) : 0;
+  const size_t b_body = B->ksk ? up(m16 * 4) : 0;
+  CHECK(ensure_ws(c, b_slots + b_ms + b_dig + b_c + b_body + m * extra_lwe * B->lw * 4 + 256));
+  char* base = static_cast<char*>(c->d_ws);
+  B->slots = reinterpret_cast<uint32_t*>(base);
+  B->ms = reinterpret_cast<uint32_t*>(base + b_slots);
+  B->dig = B->ksk ? reinterpret_cast<int8_t*>(base + b_slots + b_ms) : nullptr;
+  B->C = B->ksk ? reinterpret_cast<int32_t*>(base + b_slots + b_ms + b_dig) : nullptr;
+  B->body = B->ksk ? reinterpret_cast<uint32_t*>(base + b_slots + b_ms + b_dig + b_c) : nullptr;
+  *lwes = reinterpret_cast<uint32_t*>(base + b_slots + b_ms + b_dig + b_c + b_body);
   *cmax = m;
   return HW_OK;
 }
@@ -359,9 +511,15 @@ hw_status pbs_setup(hw_ctx* c, const uint32_t* bsk, uint32_t n, uint64_t count, 
 // LWE buffers of that size are allocated for the call)
 constexpr uint64_t FM_CHUNK_CELLS = 65536;
 
-hw_status check_pbs(hw_ctx* c, const uint32_t* bsk, uint32_t n) {
-  if (!bsk) return fail(HW_EINVAL, "null bootstrapping key");
-  if (n < 1 || n > c->prm.N) return fail(HW_EINVAL, "n = %u out of range [1, N = %u]", n, c->prm.N);
+constexpr uint32_t KS_MAX_N = 8192;  // longest binary LWE key
+
+hw_status check_pbs(hw_ctx* c, const hw_boot_key* key) {
+  if (!key || !key->bsk) return fail(HW_EINVAL, "null bootstrapping key");
+  if (key->ksk) {
+    if (key->n < 1 || key->n > KS_MAX_N) return fail(HW_EINVAL, "n = %u out of range [1, %u]", key->n, KS_MAX_N);
+  } else if (key->n < 1 || key->n > c->prm.N) {
+    return fail(HW_EINVAL, "n = %u out of range [1, N = %u]", key->n, c->prm.N);
+  }
   return HW_OK;
 }
 
@@ -379,10 +537,33 @@ extern "C" hw_status hw_pbs_keygen(hw_ctx* c, const int32_t* sk, uint64_t seed, 
   return hw_encrypt_rgsw_bits(c, sk, bits, 2 * (uint64_t)n, seed, 0, bsk, st);
 }
 
-extern "C" hw_status hw_pbs(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* lwe, uint64_t count,
+extern "C" hw_status hw_pbs_ks_sizes(const hw_ctx* c, uint32_t n, uint64_t* bsk_bytes, uint64_t* ksk_bytes) {
+  if (!c || !bsk_bytes || !ksk_bytes) return fail(HW_EINVAL, "null argument");
+  if (n < 1 || n > KS_MAX_N) return fail(HW_EINVAL, "n = %u out of range [1, %u]", n, KS_MAX_N);
+  *bsk_bytes = (uint64_t)n * rgsw_words(c) * 4;
+  *ksk_bytes = (uint64_t)ks_cols(n) * c->prm.N * hw::KS_DIGITS;
+  return ok();
+}
+
+extern "C" hw_status hw_pbs_ks_keygen(hw_ctx* c, const int32_t* sk, uint64_t seed, uint32_t n, uint8_t* lwe_key,
+                                      uint32_t* bsk, int8_t* ksk, hipStream_t st) {
+  CHECK(enter(c));
+  if (!sk || !lwe_key || !bsk || !ksk) return fail(HW_EINVAL, "null buffer");
+  if (n < 1 || n > KS_MAX_N) return fail(HW_EINVAL, "n = %u out of range [1, %u]", n, KS_MAX_N);
+  HIP_TRY(hw::launch_lwe_keygen(n, seed, lwe_key, st));
+  CHECK(hw_encrypt_rgsw_bits(c, sk, lwe_key, n, seed, 0, bsk, st));
+  // the padding rows of the contraction's key are read but never used: zero them
+  const uint64_t kd = (uint64_t)c->prm.N * hw::KS_DIGITS;
+  const uint64_t used = (uint64_t)4 * (n + 1) * kd, all = (uint64_t)ks_cols(n) * kd;
+  if (all > used) HIP_TRY(hipMemsetAsync(ksk + used, 0, all - used, st));
+  HIP_TRY(hw::launch_ksk_gen(sk, lwe_key, c->prm.N, n, seed, hw::KS_DIGITS, c->cdt, ksk, st));
+  return ok();
+}
+
+extern "C" hw_status hw_pbs(hw_ctx* c, const hw_boot_key* key, const uint32_t* lwe, uint64_t count,
                             const uint32_t* v, uint32_t* out, hipStream_t st) {
   CHECK(enter(c));
-  CHECK(check_pbs(c, bsk, n));
+  CHECK(check_pbs(c, key));
   if (count == 0) return ok();
   if (!lwe || !out || !v) return fail(HW_EINVAL, "null buffer");
   if (lwe == out) return fail(HW_EINVAL, "output must not alias input");
@@ -399,7 +580,7 @@ extern "C" hw_status hw_pbs(hw_ctx* c, const uint32_t* bsk, uint32_t n, const ui
   Pbs B;
   uint64_t cmax = 0;
   uint32_t* tmp = nullptr;
-  CHECK(pbs_setup(c, bsk, n, count, 0, st, &B, &cmax, &tmp));
+  CHECK(pbs_setup(c, key, count, 0, st, &B, &cmax, &tmp));
   for (uint64_t c0 = 0; c0 < count; c0 += cmax) {
     const uint64_t m = std::min(cmax, count - c0);
     HIP_TRY(timed(c, "pbs", (double)m, st, [&] { return pbs(B, m, lwe + c0 * B.lw, out + c0 * B.lw, V); }));
@@ -409,9 +590,9 @@ extern "C" hw_status hw_pbs(hw_ctx* c, const uint32_t* bsk, uint32_t n, const ui
 
 // the activation of `kind` (HW_ACT_*) over `count` LWE: the argument checks of
 // hw_activate, then the circuits stated there
-static hw_status activate_core(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* lwe, uint64_t count,
+static hw_status activate_core(hw_ctx* c, const hw_boot_key* key, const uint32_t* lwe, uint64_t count,
                                uint32_t kind, uint64_t param, uint32_t log_p_out, uint32_t* out, hipStream_t st) {
-  CHECK(check_pbs(c, bsk, n));
+  CHECK(check_pbs(c, key));
   const uint64_t p = c->prm.plain_mod;
   uint32_t P = 0;
   while ((1ull << P) < p) ++P;
@@ -429,7 +610,7 @@ static hw_status activate_core(hw_ctx* c, const uint32_t* bsk, uint32_t n, const
   Pbs B;
   uint64_t cmax = 0;
   uint32_t* tmp = nullptr;
-  CHECK(pbs_setup(c, bsk, n, count, 4 + P, st, &B, &cmax, &tmp));
+  CHECK(pbs_setup(c, key, count, 4 + P, st, &B, &cmax, &tmp));
   // log / b-log: outputs o_1 .. o_top, constant k (1 - o_0)
   const uint32_t top = kind == HW_ACT_LOG || param >= P ? P - 1 : (uint32_t)param;
   const int64_t kc = kind == HW_ACT_LOG || param >= P ? P : (int64_t)param;
@@ -483,24 +664,23 @@ static hw_status activate_core(hw_ctx* c, const uint32_t* bsk, uint32_t n, const
   return ok();
 }
 
-extern "C" hw_status hw_activate(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* lwe, uint64_t count,
+extern "C" hw_status hw_activate(hw_ctx* c, const hw_boot_key* key, const uint32_t* lwe, uint64_t count,
                                uint32_t kind, uint64_t param, uint32_t log_p_out, uint32_t* out, hipStream_t st) {
   CHECK(enter(c));
-  return activate_core(c, bsk, n, lwe, count, kind, param, log_p_out, out, st);
+  return activate_core(c, key, lwe, count, kind, param, log_p_out, out, st);
 }
 
-extern "C" hw_status hw_activate_ge(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* lwe,
-                                    uint64_t count, uint64_t T, uint32_t log_p_out, uint32_t* out,
-                                    hipStream_t st) {
+extern "C" hw_status hw_activate_ge(hw_ctx* c, const hw_boot_key* key, const uint32_t* lwe, uint64_t count,
+                                    uint64_t T, uint32_t log_p_out, uint32_t* out, hipStream_t st) {
   CHECK(enter(c));
-  return activate_core(c, bsk, n, lwe, count, HW_ACT_GE, T, log_p_out, out, st);
+  return activate_core(c, key, lwe, count, HW_ACT_GE, T, log_p_out, out, st);
 }
 
-extern "C" hw_status hw_encrypted_argmax(hw_ctx* c, const uint32_t* bsk, uint32_t n, const uint32_t* u,
+extern "C" hw_status hw_encrypted_argmax(hw_ctx* c, const hw_boot_key* key, const uint32_t* u,
                                          uint64_t count, uint32_t l, uint32_t log_p_in, uint32_t* out,
                                          hipStream_t st) {
   CHECK(enter(c));
-  CHECK(check_pbs(c, bsk, n));
+  CHECK(check_pbs(c, key));
   if (l < 2 || l > 64) return fail(HW_EINVAL, "l = %u out of range [2, 64]", l);
   if (log_p_in < 3 || log_p_in > 20) return fail(HW_EINVAL, "log_p_in = %u out of range [3, 20]", log_p_in);
   if (count == 0) return ok();
@@ -515,7 +695,7 @@ extern "C" hw_status hw_encrypted_argmax(hw_ctx* c, const uint32_t* bsk, uint32_
   Pbs B;
   uint64_t cmax = 0;
   uint32_t* tmp = nullptr;
-  CHECK(pbs_setup(c, bsk, n, count, ntmp, st, &B, &cmax, &tmp));
+  CHECK(pbs_setup(c, key, count, ntmp, st, &B, &cmax, &tmp));
   for (uint64_t c0 = 0; c0 < count; c0 += cmax) {
     const uint64_t m = std::min(cmax, count - c0);
     const size_t A = cmax * B.lw;  // words of one temporary array
@@ -585,16 +765,16 @@ extern "C" hw_status hw_class_sums(hw_ctx* c, const uint32_t* scores, uint64_t n
   return ok();
 }
 
-extern "C" hw_status hw_fm_act(hw_ctx* c, const hw_wisard_shape* sh, const uint32_t* bsk, uint32_t n,
+extern "C" hw_status hw_fm_act(hw_ctx* c, const hw_wisard_shape* sh, const hw_boot_key* key,
                                const uint32_t* pks_key, const uint32_t* model, uint32_t kind, uint64_t param,
                                uint32_t log_p_out, uint32_t* out, hipStream_t st) {
   CHECK(enter(c));
   Dims d;
   CHECK(check_shape(c, sh, &d));
-  CHECK(check_pbs(c, bsk, n));
+  CHECK(check_pbs(c, key));
   if (!pks_key || !model || !out) return fail(HW_EINVAL, "null buffer");
   // the activation's argument checks, before anything is allocated or run
-  CHECK(activate_core(c, bsk, n, nullptr, 0, kind, param, log_p_out, nullptr, st));
+  CHECK(activate_core(c, key, nullptr, 0, kind, param, log_p_out, nullptr, st));
   const uint32_t N = c->prm.N;
   const size_t rw = rlwe_words(c), lw = lwe_words(c);
   const uint64_t rows = (uint64_t)d.rows * d.k1;
@@ -624,7 +804,7 @@ extern "C" hw_status hw_fm_act(hw_ctx* c, const hw_wisard_shape* sh, const uint3
       rc = fail(HW_EDEVICE, "k_extract_cells: %s", hipGetErrorString(e));
       break;
     }
-    rc = activate_core(c, bsk, n, ext, m * K, kind, param, log_p_out, act, st);
+    rc = activate_core(c, key, ext, m * K, kind, param, log_p_out, act, st);
     if (rc == HW_OK) rc = hw_pack_lwe(c, pks_key, act, K, m, out + r0 * rw, st);
   }
   // the chunks' buffers are released once the stream has used them

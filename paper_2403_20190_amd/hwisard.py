@@ -67,6 +67,25 @@ class EngineConfig(C.Structure):
                 ("arena_bytes", C.c_uint64), ("order", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class BootKey(C.Structure):
+    _fields_ = [("bsk", C.c_void_p), ("ksk", C.c_void_p), ("n", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class KsBootKey:
+    """a bootstrapping key through a key switch (hw_pbs_ks_keygen): the binary
+    LWE key (uint8 [n]), its RGSW (bsk) and the key-switching key (ksk),
+    device tensors"""
+
+    def __init__(self, n, lwe_key, bsk, ksk):
+        self.n, self.lwe_key, self.bsk, self.ksk = n, lwe_key, bsk, ksk
+
+
+def _boot_key(bsk, n: int) -> BootKey:
+    if isinstance(bsk, KsBootKey):
+        return BootKey(bsk.bsk.data_ptr(), bsk.ksk.data_ptr(), bsk.n, 0)
+    return BootKey(None if bsk is None else bsk.data_ptr(), None, n, 0)
+
+
 class Request(C.Structure):
     _fields_ = [("job", C.c_uint32), ("kind", C.c_uint32), ("bits_host", C.c_void_p), ("labels_host", C.c_void_p),
                 ("n", C.c_uint64), ("enc_seed", C.c_uint64), ("cells_host", C.c_void_p)]
@@ -99,12 +118,14 @@ _SIG = {
     "hw_wisard_infer_encrypted": [_vp, C.POINTER(Shape), _vp, _vp, _u64, _vp, _vp, _vp],
     "hw_rlwe_add": [_vp, _vp, _vp, _u64, _vp],
     "hw_pbs_keygen": [_vp, _vp, _u64, _u32, _vp, _vp],
-    "hw_pbs": [_vp, _vp, _u32, _vp, _u64, _vp, _vp, _vp],
-    "hw_activate_ge": [_vp, _vp, _u32, _vp, _u64, _u64, _u32, _vp, _vp],
-    "hw_encrypted_argmax": [_vp, _vp, _u32, _vp, _u64, _u32, _u32, _vp, _vp],
+    "hw_pbs": [_vp, _vp, _vp, _u64, _vp, _vp, _vp],
+    "hw_activate_ge": [_vp, _vp, _vp, _u64, _u64, _u32, _vp, _vp],
+    "hw_encrypted_argmax": [_vp, _vp, _vp, _u64, _u32, _u32, _vp, _vp],
+    "hw_pbs_ks_sizes": [_vp, _u32, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)],
+    "hw_pbs_ks_keygen": [_vp, _vp, _u64, _u32, _vp, _vp, _vp, _vp],
     "hw_class_sums": [_vp, _vp, _u64, _u32, _u32, _vp, _vp],
-    "hw_fm_act": [_vp, _vp, _vp, _u32, _vp, _vp, _u32, _u64, _u32, _vp, _vp],
-    "hw_activate": [_vp, _vp, _u32, _vp, _u64, _u32, _u64, _u32, _vp, _vp],
+    "hw_fm_act": [_vp, _vp, _vp, _vp, _vp, _u32, _u64, _u32, _vp, _vp],
+    "hw_activate": [_vp, _vp, _vp, _u64, _u32, _u64, _u32, _vp, _vp],
     "hw_pks_keygen": [_vp, _vp, _u64, _vp, _vp],
     "hw_pks_key_export_canonical": [_vp, _vp, _vp, _vp],
     "hw_pack_lwe": [_vp, _vp, _vp, _u32, _u64, _vp, _vp],
@@ -296,14 +317,30 @@ class Context:
     def pbs_keygen(self, sk, seed: int, n: int, bsk):
         _check(_lib.hw_pbs_keygen(self._h, _ptr(sk), seed, n, _ptr(bsk), _stream()))
 
+    def pbs_ks_keygen(self, sk, seed: int, n: int, device: str = "cuda") -> "KsBootKey":
+        """bootstrapping key through a key switch to a binary LWE key of n
+        coefficients (device tensors allocated here)"""
+        import torch
+        bb, kb = _u64(), _u64()
+        _check(_lib.hw_pbs_ks_sizes(self._h, n, C.byref(bb), C.byref(kb)))
+        lwe_key = torch.zeros(n, dtype=torch.uint8, device=device)
+        bsk = torch.empty(bb.value // 4, dtype=torch.int32, device=device)
+        ksk = torch.empty(kb.value, dtype=torch.int8, device=device)
+        _check(_lib.hw_pbs_ks_keygen(self._h, _ptr(sk), seed, n, _ptr(lwe_key), _ptr(bsk), _ptr(ksk), _stream()))
+        return KsBootKey(n, lwe_key, bsk, ksk)
+
     def pbs(self, bsk, n: int, lwe, count: int, V: int, out):
-        """bootstrap with the constant test polynomial V (an integer below Q)"""
+        """bootstrap with the constant test polynomial V (an integer below Q).
+        bsk: a ring-key bootstrapping key (device tensor, n its coefficients)
+        or a KsBootKey (n is then the key's)"""
         v = np.array([V % q for q in self.primes], np.uint32)
-        _check(_lib.hw_pbs(self._h, _ptr(bsk), n, _ptr(lwe), count, v.ctypes.data_as(C.c_void_p), _ptr(out),
+        k = _boot_key(bsk, n)
+        _check(_lib.hw_pbs(self._h, C.byref(k), _ptr(lwe), count, v.ctypes.data_as(C.c_void_p), _ptr(out),
                            _stream()))
 
     def activate_ge(self, bsk, n: int, lwe, count: int, T: int, log_p_out: int, out):
-        _check(_lib.hw_activate_ge(self._h, _ptr(bsk), n, _ptr(lwe), count, T, log_p_out, _ptr(out), _stream()))
+        k = _boot_key(bsk, n)
+        _check(_lib.hw_activate_ge(self._h, C.byref(k), _ptr(lwe), count, T, log_p_out, _ptr(out), _stream()))
 
     def class_sums(self, scores, n: int, l: int, k0: int, sums):
         _check(_lib.hw_class_sums(self._h, _ptr(scores), n, l, k0, _ptr(sums), _stream()))
@@ -311,18 +348,21 @@ class Context:
     def activate(self, bsk, n: int, lwe, count: int, kind: str, param: int, log_p_out: int, out):
         """kind "ge" ([m >= param]), "log" (floor(log2(m + 1))) or "blog"
         (min(log, param)) over `count` LWE, output modulus 2^log_p_out"""
-        _check(_lib.hw_activate(self._h, _ptr(bsk), n, _ptr(lwe), count, ACT_KINDS[kind], param, log_p_out,
+        k = _boot_key(bsk, n)
+        _check(_lib.hw_activate(self._h, C.byref(k), _ptr(lwe), count, ACT_KINDS[kind], param, log_p_out,
                                 _ptr(out), _stream()))
 
     def fm_act(self, sh: Shape, bsk, n: int, pks_key, model, kind: str, param: int, log_p_out: int, out):
         """FM-act: every cell of `model` activated (kind and param as in
         activate, output modulus 2^log_p_out) and packed back into its row;
         out may be model"""
-        _check(_lib.hw_fm_act(self._h, C.byref(sh), _ptr(bsk), n, _ptr(pks_key), _ptr(model), ACT_KINDS[kind],
+        k = _boot_key(bsk, n)
+        _check(_lib.hw_fm_act(self._h, C.byref(sh), C.byref(k), _ptr(pks_key), _ptr(model), ACT_KINDS[kind],
                               param, log_p_out, _ptr(out), _stream()))
 
     def encrypted_argmax(self, bsk, n: int, u, count: int, l: int, log_p_in: int, out):
-        _check(_lib.hw_encrypted_argmax(self._h, _ptr(bsk), n, _ptr(u), count, l, log_p_in, _ptr(out), _stream()))
+        k = _boot_key(bsk, n)
+        _check(_lib.hw_encrypted_argmax(self._h, C.byref(k), _ptr(u), count, l, log_p_in, _ptr(out), _stream()))
 
     @property
     def pks_key_words(self) -> int:

@@ -1,16 +1,20 @@
-// hw_pbs.hip -- programmable bootstrapping of LWE ciphertexts (Sec. 2.5.3) and
+// hw_pbs.hip -- programmable bootstrapping of LWE ciphertexts (Sec. 2.5.3),
 // the Activate and EncryptedArgMax functions of OTF-act (Sec. 3.5.2, Alg. 7)
-// built from bootstraps that each decide one sign.
+// built from bootstraps that each decide one sign, and FM-act (Sec. 3.5.3).
 //
-// Bootstrap (constant test polynomial V, mask length n <= N, key = the ring
-// key s, ternary): switch the ciphertext's mask and body from Q to 2N
+// Bootstrap (constant test polynomial V) over the ring key s (ternary, mask
+// length n <= N): switch the ciphertext's mask and body from Q to 2N
 // (round(2N x / Q)), start from the trivial RLWE (0, X^{-b~} TV) with
 // TV = V (1 + X + ... + X^{N-1}), multiply it by X^{a~_k s_k} for k < n with
 // two CMUXes against bsk[2k] = RGSW([s_k = 1]) and bsk[2k+1] = RGSW([s_k = -1]),
 // and extract coefficient 0: V when the switched phase lies in [0, N), -V
-// otherwise.  The circuits (bits, activate_ge, argmax) combine bootstraps with
-// exact linear operations on LWE ciphertexts; their steps and constants are
-// stated at hw_activate_ge and hw_encrypted_argmax in include/hwisard.h.
+// otherwise.  Through a key switch: the ciphertext goes to modulus 2^32, is
+// key-switched to a binary key s1 of n coefficients (digits, a contraction on
+// the matrix cores, a combine), then to 2N, and the blind rotation runs one
+// CMUX per coefficient of s1 against bsk[i] = RGSW(s1_i).  The circuits
+// (bits, activate, argmax) combine bootstraps with exact linear operations on
+// LWE ciphertexts; their steps and constants are stated at hw_activate and
+// hw_encrypted_argmax in include/hwisard.h.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

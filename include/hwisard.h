@@ -313,7 +313,15 @@ hw_status hw_pbs_keygen(hw_ctx* ctx, const int32_t* sk_dev, uint64_t seed, uint3
  * 32-bit key words cut into four signed bytes), exact mod 2^32.
  * hw_pbs_ks_keygen: s1_i = bit 0 of draw i of stream (seed, domain 7)
  * into lwe_key_dev (uint8 [n], device); bsk_dev = RGSW(s1_i) as ciphertexts
- * 0..n-1 of hw_encrypt_rgsw_bits' stream `seed`; ksk_dev = the key in the
+ * 0..n-1 of hw_encrypt_rgsw_bits' stream `seed`.  On one prime they use the
+ * training gadget (hw_sizes().rgsw bytes each).  On two or more primes they
+ * use 2 balanced digits of 15 bits per prime: 2 x 2 nq RLWE rows per RGSW
+ * (row d < 2 nq adds m 2^(15 (d % 2)) to the constant term of residue d / 2
+ * of b, row 2 nq + d to that of a), drawn like hw_encrypt_rgsw_bits' rows of
+ * a ciphertext with 2 x 2 nq rows, in the device layout
+ * (hw_rgsw_export_canonical exports them as rows); the blind rotation's
+ * noise stays near 2^27 at N = 2048 with 16 forward NTTs per product
+ * instead of 40.  ksk_dev = the key in the
  * contraction's layout, signed bytes [cols][6N], row l (n + 1) + i holding
  * byte l of word i of every KSK row (A_r then B_r at i = n; A_r[i] = 32-bit
  * draw r n + i of (seed, 8), the error from 64-bit draws 2r and 2r + 1 of

@@ -460,9 +460,23 @@ class Ctx:
         ranges = [(k0, min(self.N, k0 + 32)) for k0 in range(0, self.N, 32)]
         _parallel(lambda r: lib().orc_ksk_gen(self.h, _p(s, i32p), s1.ctypes.data_as(C.POINTER(C.c_uint8)), n, seed,
                                               r[0], r[1], _p(ksk, u32p)), ranges)
+        g = self.bsk_ctx()
         bsk = [None] * n
-        _parallel(lambda i: bsk.__setitem__(i, self.enc_rgsw(s, int(s1[i]), seed, i)), range(n))
-        return KsKey(n, s1, ksk, bsk)
+        _parallel(lambda i: bsk.__setitem__(i, g.enc_rgsw(s, int(s1[i]), seed, i)), range(n))
+        return KsKey(n, s1, ksk, bsk, g)
+
+    def bsk_ctx(self) -> "Ctx":
+        """the same ring with the key-switched bootstrapping key's gadget:
+        BSK_DIGITS balanced digits of BSK_LOG_BASE bits per prime when Q has
+        two or more primes; the training gadget (this context) on a one-prime
+        ring, whose 30-bit modulus leaves no room for the coarser digits'
+        noise"""
+        if self.nq < 2:
+            return self
+        if getattr(self, "_bsk_ctx", None) is None:
+            self._bsk_ctx = Ctx(self.N, self.nq, self.p, primes=list(self.primes), log_base=BSK_LOG_BASE,
+                                digits=BSK_DIGITS)
+        return self._bsk_ctx
 
     def key_switch(self, key: "KsKey", lwe) -> np.ndarray:
         """the LWE (ring key, modulus Q) switched to key.s1 at modulus 2^32: [n + 1] uint32"""
@@ -482,7 +496,7 @@ class Ctx:
             rg = [np.ascontiguousarray(r, np.uint32) for r in bsk.bsk]
             v = np.array([V % q for q in self.primes], np.uint64)
             out = np.zeros((self.nq, self.N + 1), np.uint32)
-            lib().orc_pbs_ks(self.h, _ptr_array(rg), _p(bsk.ksk, u32p), bsk.n, _p(lwe, u32p), _p(v, u64p),
+            lib().orc_pbs_ks(bsk.gctx.h, _ptr_array(rg), _p(bsk.ksk, u32p), bsk.n, _p(lwe, u32p), _p(v, u64p),
                              _p(out, u32p))
             return out
         lwe = np.ascontiguousarray(lwe, np.uint32)
@@ -636,15 +650,19 @@ class Ctx:
 
 
 KS_LOG_BASE, KS_DIGITS = 4, 6  # the key switch's gadget (oracle.c)
+# the gadget of the key-switched bootstrapping key's RGSW (its blind rotation's
+# external products) on rings of two or more primes: 2 balanced digits of 15
+# bits per prime (Ctx.bsk_ctx)
+BSK_LOG_BASE, BSK_DIGITS = 15, 2
 
 
 class KsKey:
     """bootstrapping key through a key switch: n, the binary LWE key s1, the
-    key-switching key [N KS_DIGITS][n + 1] (uint32, modulus 2^32) and the n
-    RGSW(s1_i)"""
+    key-switching key [N KS_DIGITS][n + 1] (uint32, modulus 2^32), the n
+    RGSW(s1_i) and the context of their gadget"""
 
-    def __init__(self, n, s1, ksk, bsk):
-        self.n, self.s1, self.ksk, self.bsk = n, s1, ksk, bsk
+    def __init__(self, n, s1, ksk, bsk, gctx):
+        self.n, self.s1, self.ksk, self.bsk, self.gctx = n, s1, ksk, bsk, gctx
 
 
 def _parallel(fn, items, threads=None):

@@ -469,10 +469,25 @@ struct XpOut {
 // for d mod q).
 constexpr int32_t DIGIT_OFFSET = 32 * (1 + 64 + 4096 + 262144);
 
-__device__ __forceinline__ uint32_t digit_lift(int32_t w, int j, uint32_t q) {
-  if (j < 4) return (((uint32_t)w >> (6 * j)) & 63u) + (q - 32u);
-  return (uint32_t)((w >> 24) + (int32_t)q);
+// The same for any gadget of DIG balanced base-2^LB digits per prime: the
+// offset is 2^(LB-1) (1 + B + .. + B^(DIG-2)), the digits below the top one are
+// LB-bit fields of w, the top one is w >> (LB (DIG - 1)) (arithmetic).  The
+// training gadget is (5, 6); the key-switched bootstrapping key uses (2, 15).
+template <int DIG, int LB>
+__host__ __device__ constexpr int32_t digit_offset() {
+  int64_t o = 0, b = 1;
+  for (int j = 0; j + 1 < DIG; ++j, b <<= LB) o += b << (LB - 1);
+  return (int32_t)o;
 }
+static_assert(digit_offset<5, 6>() == DIGIT_OFFSET, "the training gadget's offset");
+
+template <int DIG, int LB>
+__device__ __forceinline__ uint32_t digit_lift_g(int32_t w, int j, uint32_t q) {
+  if (j < DIG - 1) return (((uint32_t)w >> (LB * j)) & ((1u << LB) - 1u)) + (q - (1u << (LB - 1)));
+  return (uint32_t)((w >> (LB * (DIG - 1))) + (int32_t)q);
+}
+
+__device__ __forceinline__ uint32_t digit_lift(int32_t w, int j, uint32_t q) { return digit_lift_g<5, 6>(w, j, q); }
 
 // inverse transforms of the a and b sums of output prime ip (inputs in [0, q))
 // and the write of the external product by out.mode
@@ -522,12 +537,15 @@ __device__ __forceinline__ void xp_finish(uint32_t (&ha)[8], uint32_t (&hb)[8], 
   }
 }
 
-template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>()>
+// DIG, LB: the RGSW's gadget, DIG balanced base-2^LB digits per prime (rows
+// side * DIG NQ + i DIG + j); the training gadget is the default
+template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>(), int DIG = 5, int LB = 6>
 __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const uint32_t* __restrict__ C,
                                       const Tabs& T, uint32_t* lds, uint2* twl, uint32_t& xc, uint32_t t,
                                       XpOut out) {
   constexpr int N = 1 << LOGN, TT = N / 8;
-  constexpr int D = 5 * NQ;
+  constexpr int D = DIG * NQ;
+  constexpr int32_t OFF = digit_offset<DIG, LB>();
   constexpr size_t ROW = (size_t)2 * NQ * N;
 #pragma unroll 1
   for (int ip = 0; ip < NQ; ++ip) {
@@ -548,13 +566,13 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const uint32_t r = (src + TT * e)[t];
-        w[e] = (r > (qi - 1) / 2 ? (int32_t)(r - qi) : (int32_t)r) + DIGIT_OFFSET;
+        w[e] = (r > (qi - 1) / 2 ? (int32_t)(r - qi) : (int32_t)r) + OFF;
       }
-      const uint32_t* crow = C + (size_t)(side * D + i * 5) * ROW + (size_t)ip * N;
+      const uint32_t* crow = C + (size_t)(side * D + i * DIG) * ROW + (size_t)ip * N;
       if constexpr (PR) {
-        // digits (0, 1) and (2, 3) through one two-polynomial transform each
+        // digits (0, 1), (2, 3), .. through one two-polynomial transform each
 #pragma unroll 1
-        for (int j = 0; j < 4; j += 2) {
+        for (int j = 0; j < DIG - 1; j += 2) {
           const uint4* c0 = reinterpret_cast<const uint4*>(crow + (size_t)j * ROW);
           const uint4* c1 = reinterpret_cast<const uint4*>(crow + (size_t)(j + 1) * ROW);
           const uint4 ca00 = c0[2 * t], ca01 = c0[2 * t + 1];
@@ -564,8 +582,8 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
           uint32_t x[2][8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
-            x[0][e] = digit_lift(w[e], j, P.q);
-            x[1][e] = digit_lift(w[e], j + 1, P.q);
+            x[0][e] = digit_lift_g<DIG, LB>(w[e], j, P.q);
+            x[1][e] = digit_lift_g<DIG, LB>(w[e], j + 1, P.q);
           }
           ntt_fwd_k<LOGN, 2>(x, T.fwd[ip], twl, P.q, P.two_q, lds, xc, t);
           const uint32_t ca[2][8] = {{ca00.x, ca00.y, ca00.z, ca00.w, ca01.x, ca01.y, ca01.z, ca01.w},
@@ -592,14 +610,14 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
         }
       }
 #pragma unroll 1
-      for (int j = PR ? 4 : 0; j < 5; ++j) {
+      for (int j = PR ? DIG / 2 * 2 : 0; j < DIG; ++j) {
         const uint4* cra = reinterpret_cast<const uint4*>(crow + (size_t)j * ROW);
         const uint4* crb = cra + (size_t)NQ * N / 4;
         const uint4 ca0 = cra[2 * t], ca1 = cra[2 * t + 1];
         const uint4 cb0 = crb[2 * t], cb1 = crb[2 * t + 1];
         uint32_t x[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = digit_lift(w[e], j, P.q);
+        for (int e = 0; e < 8; ++e) x[e] = digit_lift_g<DIG, LB>(w[e], j, P.q);
         ntt_fwd<LOGN>(x, T.fwd[ip], twl, P.q, P.two_q, lds, xc, t);
         const uint32_t ca[8] = {ca0.x, ca0.y, ca0.z, ca0.w, ca1.x, ca1.y, ca1.z, ca1.w};
         const uint32_t cb[8] = {cb0.x, cb0.y, cb0.z, cb0.w, cb1.x, cb1.y, cb1.z, cb1.w};

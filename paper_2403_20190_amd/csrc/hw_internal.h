@@ -159,6 +159,10 @@ hipError_t launch_keygen(uint32_t N, uint64_t seed, int32_t* sk, hipStream_t st)
 // per ring coefficient, as signed bytes [4 (n + 1)][N D] (the rows past
 // 4 (n + 1) of a padded buffer are left as they are)
 hipError_t launch_lwe_keygen(uint32_t n, uint64_t seed, uint8_t* s1, hipStream_t st);
+// RGSW of count bits with a 2-digit gadget of A.log_base bits per prime
+// (rows 2 * 2 nq, drawn like hw_encrypt_rgsw_bits' rows of such a gadget)
+hipError_t launch_enc_rgsw_g2(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
+                              hipStream_t st);
 hipError_t launch_ksk_gen(const int32_t* sk, const uint8_t* s1, uint32_t N, uint32_t n, uint64_t seed, uint32_t D,
                           const Cdt& cdt, int8_t* out, hipStream_t st);
 // sk_hat: 2 nq N words (the transformed key, then its Shoup companions)

@@ -302,12 +302,12 @@ __device__ __forceinline__ void gen_gauss(uint64_t seed, uint64_t base_blk, cons
 // (the transform of a constant polynomial is constant).  A workgroup builds
 // R consecutive rows of one ciphertext, so each prime's twiddle table is
 // copied to LDS once per R rows.
-template <int LOGN, int NQ, int R>
+template <int LOGN, int NQ, int R, int DIG = 5>
 __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   __shared__ uint64_t tab[42];
-  constexpr int N = 1 << LOGN, D = 5 * NQ, ROWS = 2 * D;
+  constexpr int N = 1 << LOGN, D = DIG * NQ, ROWS = 2 * D;
   static_assert(ROWS % R == 0, "rows per workgroup must divide the rows of an RGSW");
   const uint32_t t = threadIdx.x, r0 = blockIdx.x * R;
   const uint64_t c = blockIdx.y + (uint64_t)blockIdx.z * gridDim.y;
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncA
       for (int e = 0; e < 8; ++e) xe[e] = ev[k][e] < 0 ? (uint32_t)(ev[k][e] + (int32_t)P.q) : (uint32_t)ev[k][e];
       ntt_fwd<LOGN>(xe, T.fwd[i], twl, P.q, P.two_q, lds, xc, t);
       const bool brow = r < D;
-      const uint32_t gi = (r % D) / 5, gj = (r % D) % 5;
+      const uint32_t gi = (r % D) / DIG, gj = (r % D) % DIG;
       const uint32_t g = (m && gi == (uint32_t)i) ? (1u << (A.log_base * gj)) : 0u;
       uint32_t oa[8], ob[8];
 #pragma unroll
@@ -1486,6 +1486,23 @@ hipError_t launch_ksk_gen(const int32_t* sk, const uint8_t* s1, uint32_t N, uint
 hipError_t launch_sk_hat(int logN, int nq, const Tabs& T, const int32_t* sk, uint32_t* sk_hat, hipStream_t st) {
   HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_sk_hat<LN, NQ>), dim3(NQ), dim3(Geo<LN>::T), 0, st, T, sk, sk_hat));
   return hipGetLastError();
+}
+
+// RGSW with the key-switched bootstrapping key's gadget: 2 digits of
+// A.log_base bits per prime (2 rows per workgroup)
+hipError_t launch_enc_rgsw_g2(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
+                              hipStream_t st) {
+  const size_t rg = (size_t)2 * 2 * nq * 2 * nq * ((size_t)1 << logN);
+  const uint32_t rows = 2 * 2 * nq;
+  return for_rect(count, [&](uint64_t off, dim3 g) -> hipError_t {
+    EncArgs B = A;
+    B.bits = A.bits + off;
+    B.out = A.out + off * rg;
+    B.ct0 = A.ct0 + off;
+    HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ, 2, 2>), dim3(rows / 2, g.x, g.y),
+                                              dim3(Geo<LN>::T), 0, st, T, cdt, B));
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_enc_rgsw(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,

@@ -102,8 +102,10 @@ __device__ __forceinline__ void pbs_rot_diff(const Tabs& T, const uint32_t* __re
   }
 }
 
-// blind rotation and extraction: one workgroup per ciphertext
-template <int LOGN, int NQ>
+// blind rotation and extraction: one workgroup per ciphertext; DIG, LB: the
+// bootstrapping key's gadget (the ring key's is the training gadget, the
+// key-switched key's 2 digits of 15 bits)
+template <int LOGN, int NQ, int DIG, int LB>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_pbs_rotate(
     Tabs T, RotArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, xp_pair<LOGN, NQ>()>()];
@@ -140,7 +142,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(3,
     for (int sg = 0; sg < (A.binary ? 1 : 2); ++sg) {
       pbs_rot_diff<LOGN, NQ>(T, acc, sg ? -a : a, xin, t);
       const size_t row = A.binary ? (size_t)k : (size_t)(2 * k + sg);
-      ext_prod<LOGN, NQ>(xin, A.bsk + row * A.rgsw_words, T, lds, twl, xc, t, XpOut{acc, acc, nullptr, XP_ADD});
+      ext_prod<LOGN, NQ, xp_pair<LOGN, NQ>(), DIG, LB>(xin, A.bsk + row * A.rgsw_words, T, lds, twl, xc, t,
+                                                       XpOut{acc, acc, nullptr, XP_ADD});
       __syncthreads();  // the next rotation reads coefficients other threads wrote
     }
   }
@@ -162,6 +165,9 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(3,
 // ---- key switch to the binary LWE key (modulus 2^32) ----------------------
 
 constexpr uint32_t KS_DIGITS = 6;  // balanced base-16 digits of the top 24 bits
+// gadget of the key-switched bootstrapping key's RGSW on rings of two or more
+// primes: 2 balanced digits of 15 bits per prime (exact for primes below 2^30)
+constexpr int BSK_DIG = 2, BSK_LB = 15;
 
 // round(2^32 x / Q) mod 2^32 (half up) of x in [0, Q) with residues r
 template <int NQ>
@@ -371,6 +377,16 @@ struct Pbs {
   size_t lw;        // words of an LWE ciphertext
 };
 
+// the key-switched bootstrapping key's RGSW use the coarser gadget on rings of
+// two or more primes; a one-prime ring's 30-bit modulus leaves no room for its
+// noise, so there they use the training gadget
+bool bsk_coarse(const hw_ctx* c) { return c->prm.nq >= 2; }
+
+// words of one RGSW of the key-switched bootstrapping key
+size_t bsk_rgsw_words(const hw_ctx* c) {
+  return bsk_coarse(c) ? (size_t)2 * hw::BSK_DIG * c->prm.nq * rlwe_words(c) : rgsw_words(c);
+}
+
 // columns of the key switch's contraction for an LWE key of n coefficients:
 // four signed bytes of each of the n + 1 words, padded to 64
 uint32_t ks_cols(uint32_t n) { return ((4 * (n + 1) + 63) / 64) * 64; }
@@ -448,14 +464,19 @@ hipError_t pbs(const Pbs& B, uint64_t count, const uint32_t* in, uint32_t* out, 
   A.ms = B.ms;
   A.slots = B.slots;
   A.out = out;
-  A.rgsw_words = rgsw_words(c);
+  A.rgsw_words = B.ksk ? bsk_rgsw_words(c) : rgsw_words(c);
   A.count = count;
   A.n = B.n;
   A.binary = B.ksk != nullptr;
   for (uint32_t i = 0; i < nq; ++i) A.v[i] = res_of(V, c->tabs.pt[i].q);
   const dim3 g((uint32_t)std::min<uint64_t>(count, 65535), (uint32_t)((count + 65534) / 65535));
-  PBS_DISPATCH(c->logN, nq,
-               hipLaunchKernelGGL((hw::k_pbs_rotate<LN, NQ>), g, dim3(hw::Geo<LN>::T), 0, B.st, c->tabs, A));
+  if (B.ksk && bsk_coarse(c))
+    PBS_DISPATCH(c->logN, nq,
+                 hipLaunchKernelGGL((hw::k_pbs_rotate<LN, NQ, hw::BSK_DIG, hw::BSK_LB>), g, dim3(hw::Geo<LN>::T), 0,
+                                    B.st, c->tabs, A));
+  else
+    PBS_DISPATCH(c->logN, nq,
+                 hipLaunchKernelGGL((hw::k_pbs_rotate<LN, NQ, 5, 6>), g, dim3(hw::Geo<LN>::T), 0, B.st, c->tabs, A));
   return hipGetLastError();
 }
 
@@ -544,7 +565,7 @@ extern "C" hw_status hw_pbs_keygen(hw_ctx* c, const int32_t* sk, uint64_t seed, 
 extern "C" hw_status hw_pbs_ks_sizes(const hw_ctx* c, uint32_t n, uint64_t* bsk_bytes, uint64_t* ksk_bytes) {
   if (!c || !bsk_bytes || !ksk_bytes) return fail(HW_EINVAL, "null argument");
   if (n < 1 || n > KS_MAX_N) return fail(HW_EINVAL, "n = %u out of range [1, %u]", n, KS_MAX_N);
-  *bsk_bytes = (uint64_t)n * rgsw_words(c) * 4;
+  *bsk_bytes = (uint64_t)n * bsk_rgsw_words(c) * 4;
   *ksk_bytes = (uint64_t)ks_cols(n) * c->prm.N * hw::KS_DIGITS;
   return ok();
 }
@@ -555,7 +576,21 @@ extern "C" hw_status hw_pbs_ks_keygen(hw_ctx* c, const int32_t* sk, uint64_t see
   if (!sk || !lwe_key || !bsk || !ksk) return fail(HW_EINVAL, "null buffer");
   if (n < 1 || n > KS_MAX_N) return fail(HW_EINVAL, "n = %u out of range [1, %u]", n, KS_MAX_N);
   HIP_TRY(hw::launch_lwe_keygen(n, seed, lwe_key, st));
-  CHECK(hw_encrypt_rgsw_bits(c, sk, lwe_key, n, seed, 0, bsk, st));
+  // RGSW(s1_i) with the bootstrapping key's gadget, ciphertexts 0..n-1 of stream seed
+  if (bsk_coarse(c)) {
+    HIP_TRY(hw::launch_sk_hat(c->logN, c->prm.nq, c->tabs, sk, c->d_skhat, st));
+    hw::EncArgs A{};
+    A.sk = sk;
+    A.sk_hat = c->d_skhat;
+    A.bits = lwe_key;
+    A.out = bsk;
+    A.seed = seed;
+    A.ct0 = 0;
+    A.log_base = hw::BSK_LB;
+    HIP_TRY(hw::launch_enc_rgsw_g2(c->logN, c->prm.nq, c->tabs, c->cdt, A, n, st));
+  } else {
+    CHECK(hw_encrypt_rgsw_bits(c, sk, lwe_key, n, seed, 0, bsk, st));
+  }
   // the padding rows of the contraction's key are read but never used: zero them
   const uint64_t kd = (uint64_t)c->prm.N * hw::KS_DIGITS;
   const uint64_t used = (uint64_t)4 * (n + 1) * kd, all = (uint64_t)ks_cols(n) * kd;

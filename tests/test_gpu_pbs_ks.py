@@ -2,9 +2,10 @@
 (hw_pbs_ks_keygen, hw_boot_key with a key-switching key; the TFHE setting
 of Sec. 2.5.3 keeps an LWE key in B^n beside the ring key).
 
-* Against the oracle, bit for bit: the LWE key, the key's RGSW rows and
-  every key-switching word (rebuilt from the contraction layout's signed
-  bytes), and bootstraps of full-mask ciphertexts at the one-, two- and
+* Against the oracle, bit for bit: the LWE key, the key's RGSW rows (on
+  rings of two and three primes in the coarser gadget of 2 digits of 15 bits
+  per prime) and every key-switching word (rebuilt from the contraction
+  layout's signed bytes), and bootstraps of full-mask ciphertexts at the one-, two- and
   three-prime rings (the key switch's digits, its int8 matrix-core
   contraction, the switch to 2N and the one-CMUX-per-bit blind rotation all
   feed those bits).
@@ -65,6 +66,11 @@ def test_key_bit_exact():
 def test_bootstraps_bit_exact(N, nq, p, n):
     HW, ctx, orc, sk, s, key = setup(N, nq, p, n)
     ko = orc.pbs_ks_keygen(s, 71, n)
+    if nq >= 2:  # RGSW of 2 digits of 15 bits per prime: 5 of them fill 2 of the 5-digit layout
+        assert ko.bsk[0].shape == (2 * 2 * nq, 2, nq, N)
+        exp = zeros_u32(2, ctx.rgsw_words)
+        ctx.rgsw_export(key.bsk[: 2 * ctx.rgsw_words], 2, exp)
+        assert np.array_equal(host_u32(exp).reshape(5, *ko.bsk[0].shape), np.stack(ko.bsk[:5]))
     rng = np.random.default_rng(N + n)
     ms = [p // 8, 3 * p // 8, 5 * p // 8, 7 * p // 8, int(rng.integers(0, p))]
     X = np.stack([B.encrypt_short(orc, s, m, N, p, rng) for m in ms])  # full masks

@@ -12,7 +12,8 @@ of Sec. 2.5.3 keeps an LWE key in B^n beside the ring key), on a
 * the bootstrap returns V or -V by the half of the circle of the switched
   phase computed from the key-switched ciphertext;
 * the activation and argmax circuits decrypt to their plaintext values
-  with this key.
+  with this key, also on a two-prime ring, where the key's RGSW use the
+  coarser gadget of 2 digits of 15 bits per prime.
 """
 import numpy as np
 import pytest
@@ -102,3 +103,25 @@ def test_circuits_with_the_key_switched_bootstrap(setup):
         assert g == want, (kind, m, T)
     u = [B.encrypt_short(ctx, s, v, N, 128, np.random.default_rng(61 + v)) for v in (9, 40, 40)]
     assert B.decode(ctx, s, B.argmax(ctx, key, 0, u, 128), 4) == 1
+
+
+def test_two_prime_ring_uses_the_coarser_gadget_and_stays_correct():
+    """on a ring of two primes the key-switched key's RGSW use 2 digits of 15
+    bits per prime; the threshold and log circuits still decrypt right"""
+    ctx = O.Ctx(1024, 2, 512)
+    s = ctx.keygen(5)
+    key = ctx.pbs_ks_keygen(s, 91, 64)
+    assert (key.gctx.digits, key.gctx.log_base) == (O.BSK_DIGITS, O.BSK_LOG_BASE) == (2, 15)
+    assert key.bsk[0].shape == (2 * 2 * 2, 2, 2, 1024)
+    cases = [("ge", 99, 100), ("ge", 100, 100), ("ge", 511, 511), ("log", 6, 0), ("log", 255, 0), ("log", 511, 0)]
+
+    def one(c):
+        kind, m, T = c
+        x = B.encrypt_short(ctx, s, m, 1024, 512, np.random.default_rng(7 + m))
+        if kind == "ge":
+            return B.decode(ctx, s, B.activate_ge(ctx, key, 0, x, T, 128), 128)
+        return B.decode(ctx, s, B.activate_log(ctx, key, 0, x, 64), 64)
+
+    got = [None] * len(cases)
+    O._parallel(lambda i: got.__setitem__(i, one(cases[i])), range(len(cases)))
+    assert got == [int(m >= T) if k == "ge" else int(PL.act_log(m)) for k, m, T in cases]

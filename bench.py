@@ -140,16 +140,16 @@ def ops_per_enc_row(N: int, nq: int) -> float:
             + 16.0 * nq * N)
 
 
-def modmul_per_xp(N: int, nq: int) -> float:
+def modmul_per_xp(N: int, nq: int, dig: int = 5) -> float:
     """Modular multiplications of one external product:
-    (2 l nq^2 + 2 nq) (N/2) log2 N + 4 l nq^2 N with l = 5 digits."""
+    (2 l nq^2 + 2 nq) (N/2) log2 N + 4 l nq^2 N with l = dig digits per prime."""
     logN = N.bit_length() - 1
-    return (10 * nq * nq + 2 * nq) * (N // 2) * logN + 20 * nq * nq * N
+    return (2 * dig * nq * nq + 2 * nq) * (N // 2) * logN + 4 * dig * nq * nq * N
 
 
-def rgsw_bytes(N: int, nq: int) -> int:
-    """2D rows x 2 polynomials x nq residues x N words"""
-    return 2 * 5 * nq * 2 * nq * N * 4
+def rgsw_bytes(N: int, nq: int, dig: int = 5) -> int:
+    """2D rows (D = dig nq) x 2 polynomials x nq residues x N words"""
+    return 2 * dig * nq * 2 * nq * N * 4
 
 
 def device_peaks(dev) -> dict:
@@ -170,10 +170,10 @@ MUL_PER_MODMUL = 3
 
 
 def xp_roofline(kernel: str, N: int, nq: int, xp: float, ms: float, launches: int, peaks: dict | None,
-                ops: float | None = None) -> dict:
+                ops: float | None = None, dig: int = 5) -> dict:
     """Roofline of a kernel made of external products, in per-product units:
-    each product streams one RGSW ciphertext (16 l nq^2 N bytes, l = 5
-    digits) and performs (2 l nq^2 + 2 nq)(N/2) log2 N + 4 l nq^2 N modular
+    each product streams one RGSW ciphertext (16 l nq^2 N bytes, l = dig
+    digits per prime, 5 unless stated) and performs (2 l nq^2 + 2 nq)(N/2) log2 N + 4 l nq^2 N modular
     multiplications.  `achieved` = those bytes / time against HBM and those
     multiplies (MUL_PER_MODMUL int32 multiplies each) / time against the
     VALU; `bound` is the resource with the larger fraction.  `ops` (the
@@ -182,8 +182,8 @@ def xp_roofline(kernel: str, N: int, nq: int, xp: float, ms: float, launches: in
         return {"kernel": kernel, "bound": None}
     sec = ms / 1000.0
     per_launch = xp / launches
-    gbs = xp * rgsw_bytes(N, nq) / sec / 1e9
-    mm_s = xp * modmul_per_xp(N, nq) / sec
+    gbs = xp * rgsw_bytes(N, nq, dig) / sec / 1e9
+    mm_s = xp * modmul_per_xp(N, nq, dig) / sec
     mul_t = mm_s * MUL_PER_MODMUL / 1e12
     hbm = {"achieved_gbs": round(gbs, 1), "peak_gbs": PEAK_HBM_GBS, "frac": round(gbs / PEAK_HBM_GBS, 4)}
     valu = {"modmul_per_s": round(mm_s, 1), "int32_mul_per_modmul": MUL_PER_MODMUL,
@@ -202,8 +202,8 @@ def xp_roofline(kernel: str, N: int, nq: int, xp: float, ms: float, launches: in
     else:
         r.update(achieved=valu["achieved_tops"], peak=round(PEAK_INT32_TOPS, 2), unit="TOPS(int32 mul)",
                  frac=valu["frac"])
-    r.update(unit_of_work="external product", bytes_per_unit=rgsw_bytes(N, nq),
-             modmul_per_unit=modmul_per_xp(N, nq), units_per_launch=per_launch, launches=launches,
+    r.update(unit_of_work="external product", bytes_per_unit=rgsw_bytes(N, nq, dig),
+             modmul_per_unit=modmul_per_xp(N, nq, dig), units_per_launch=per_launch, launches=launches,
              avg_launch_ms=round(ms / launches, 3), hbm=hbm, valu=valu)
     if ops is not None:
         r["op_model"] = {"int32_ops_per_launch": ops / launches, "achieved_tops": round(ops / sec / 1e12, 3),
@@ -287,7 +287,7 @@ def cpu_baseline(wl: str, W: dict, Xtr, ytr, Xte, seeds: dict, ctx, sh, sk_dev, 
     m = W.get("cpu_samples", 1)
     info = host_info()
     threads = max(1, min(16, info["affinity"]))
-    orc = O.Ctx(N, nq, p)
+    orc = O.Ctx(N, nq, p, log_base=ctx.log_base, digits=ctx.digits)  # the gadget of the GPU run it checks
     bits = P.encode(levels_of(P, W, Xtr[:m], ref), T)
     tbits = P.encode(levels_of(P, W, Xte[:1], ref), T)
     s = bits.shape[1]
@@ -443,6 +443,11 @@ def main():
                     help="job sizes of the 256-job batched workload are scaled by these factors")
     ap.add_argument("--fm-full", action="store_true",
                     help="wisconsin: FM-act of the whole model, then inference on it (minutes)")
+    ap.add_argument("--gadget", default="6x5", choices=["6x5", "15x2"],
+                    help="RGSW gadget of the timed step: 5 digits of 6 bits per prime (default) or 2 of 15 bits "
+                         "(rings of two or more primes); the extras then skip the gadget leg")
+    ap.add_argument("--no-gadget-leg", action="store_true",
+                    help="skip the step and inference with RGSW of 2 digits of 15 bits per prime")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=200)
@@ -484,7 +489,8 @@ def main():
     s = bits_tr.shape[1]
     L = CL.ceil_log2(l)
     lab_tr = CL.label_bits(ytr, l)
-    ctx = HW.Context(N, nq, p)
+    lb, dig = (6, 5) if args.gadget == "6x5" else (15, 2)
+    ctx = HW.Context(N, nq, p, log_base=lb, digits=dig)
     for f in args.force:
         kname, var = f.split("=")
         ctx.tune_set(kname, int(var))
@@ -584,15 +590,16 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": W["name"], "n_train": n, "s": s, "k0": k0, "k1": k1,
-                   "chunk": chunk, "step": "device RGSW encryption + homomorphic training of n_train samples"},
+                   "chunk": chunk, "step": "device RGSW encryption + homomorphic training of n_train samples",
+                   "gadget": "%d balanced digits of %d bits per prime" % (dig, lb)},
     }
     # IVP chains per step: every (sample, RAM) plus the class counter's (label bits only)
     ivps = args.steps * steps_ivps
     peaks = None if args.no_peaks else device_peaks(dev)
     result["roofline"] = xp_roofline("k_train", N, nq, tr_xp, tr_ms, tr_launch, peaks,
-                                     ops=train_ops(N, nq, tr_xp, ivps))
+                                     ops=train_ops(N, nq, tr_xp, ivps) if dig == 5 else None, dig=dig)
     result["roofline"]["traffic"] = (measured_traffic(ctx.schedule().get("train"))
-                                     if args.workload == "mnist" and chunk == 50 else None)
+                                     if args.workload == "mnist" and chunk == 50 and dig == 5 else None)
     result["roofline"]["traffic_unit"] = ("HBM bytes per training call of the schedule in use (rocprofv3 "
                                           "FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)")
     result["roofline"]["first_xp_of_chain"] = ("one product in %d reads half its RGSW (no forward transforms)"
@@ -617,12 +624,12 @@ def main():
             "rows": en_rows, "ops_per_row": ops_per_enc_row(N, nq)},
         "xp_per_s": round(steps_xp / (train_kernel_ms / 1000.0), 1) if train_kernel_ms else None,
         # the first product of each chain: 2 nq inverse NTTs, 2 nq N evaluation products, half the RGSW
-        "ntt_per_s_in_xp": round((steps_full * (10 * nq * nq + 2 * nq) + steps_ivps * 2 * nq)
+        "ntt_per_s_in_xp": round((steps_full * (2 * dig * nq * nq + 2 * nq) + steps_ivps * 2 * nq)
                                  / (train_kernel_ms / 1000.0), 1) if train_kernel_ms else None,
-        "modmul_per_s": round((steps_full * modmul_per_xp(N, nq) + steps_ivps * (
+        "modmul_per_s": round((steps_full * modmul_per_xp(N, nq, dig) + steps_ivps * (
             2 * nq * (N // 2) * (N.bit_length() - 1) + 2 * nq * N)) / (train_kernel_ms / 1000.0), 1)
         if train_kernel_ms else None,
-        "rgsw_read_gbs": round((steps_full + steps_ivps / 2) * rgsw_bytes(N, nq) / (train_kernel_ms / 1000.0) / 1e9,
+        "rgsw_read_gbs": round((steps_full + steps_ivps / 2) * rgsw_bytes(N, nq, dig) / (train_kernel_ms / 1000.0) / 1e9,
                                1) if train_kernel_ms else None,
     }
 
@@ -631,6 +638,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extras:
         result["inference"], cells0 = infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev, peaks)
+        if not args.no_gadget_leg and dig == 5:
+            result["gadget_15x2"] = gadget_pass(W, bits_tr, lab_tr, Xte, seeds, s, k0, k1, dev, H, cells0,
+                                                args.steps, args.warmup, peaks)
         result["class_packed"] = packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev, peaks)
         if W.get("otf"):
             result["otf_act"] = otf_pass(ctx, sh, H, sk, Xte, W, seeds, k0, dev, cells0)
@@ -719,15 +729,99 @@ def infer_pass(ctx, sh, H, sk, Xte, yte, W, seeds, k0, dev, peaks=None):
         del key, out
     pred = CL.pd_act_predict(cells, "bin")
     acc = float((pred == np.asarray(yte[:nt])).mean())
-    N, nq = ctx.N, ctx.nq
+    N, nq, dig = ctx.N, ctx.nq, ctx.digits
     return {
         "samples_per_s": round(nt / dt, 3),
         "infer_kernel_samples_per_s": round(nt / (inf_ms / 1000.0), 3) if inf_ms else None,
         "xp_per_s": round(inf_xp / (inf_ms / 1000.0), 1) if inf_ms else None,
-        "roofline": xp_roofline("k_infer", N, nq, inf_xp, inf_ms, inf_launch, peaks, ops=inf_xp * ops_per_xp(N, nq)),
+        "roofline": xp_roofline("k_infer", N, nq, inf_xp, inf_ms, inf_launch, peaks,
+                                ops=inf_xp * ops_per_xp(N, nq) if dig == 5 else None, dig=dig),
         "n_test": nt, "pd_act": "bin", "test_accuracy": round(acc, 4),
         "packing": packed,
     }, cells
+
+
+def gadget_pass(W, bits_tr, lab_tr, Xte, seeds, s, k0, k1, dev, H0, cells0, steps: int, warmup: int,
+                peaks=None):
+    """The step (device RGSW encryption + homomorphic training of the n_train
+    samples) and the test-set inference again, with RGSW of 2 balanced
+    digits of 15 bits per prime (the digit size of the paper's HE1 TFHE
+    set) instead of 5 of 6 bits, on the same ring, key and seeds: rates, the
+    training call's per-product roofline in that gadget's units, and whether
+    the decrypted model and scores equal the default gadget's.  Rings of two
+    or more primes only (None otherwise)."""
+    import numpy as np
+    import torch
+
+    from paper_2403_20190_amd import client as CL
+    from paper_2403_20190_amd import hwisard as HW
+    N, nq, p, l, a, T = W["N"], W["nq"], W["p"], W["l"], W["a"], W["T"]
+    if nq < 2:
+        return None
+    ctx = HW.Context(N, nq, p, log_base=15, digits=2)
+    sh = HW.shape(s, l, a, seeds["perm"])
+    sk = torch.zeros(N, dtype=torch.int32, device=dev)
+    ctx.keygen(seeds["key"], sk)
+    n, L, chunk = len(bits_tr), CL.ceil_log2(l), W["chunk"]
+    xb = torch.from_numpy(bits_tr).to(dev)
+    yb = torch.from_numpy(lab_tr).to(dev)
+    xr = torch.empty(chunk * s, ctx.rgsw_words, dtype=torch.int32, device=dev)
+    yr = torch.empty(max(1, chunk * L), ctx.rgsw_words, dtype=torch.int32, device=dev)
+    H = torch.zeros(k0, k1, 2, nq, N, dtype=torch.int32, device=dev)
+    cnt = torch.zeros(2, nq, N, dtype=torch.int32, device=dev) if W["balance"] else None
+
+    def step():
+        H.zero_()
+        if cnt is not None:
+            cnt.zero_()
+        for c0 in range(0, n, chunk):
+            m = min(chunk, n - c0)
+            ctx.encrypt_rgsw_bits(sk, xb[c0:c0 + m].reshape(-1), seeds["x"], c0 * s, xr[:m * s])
+            if L:
+                ctx.encrypt_rgsw_bits(sk, yb[c0:c0 + m].reshape(-1), seeds["y"], c0 * L, yr[:m * L])
+            ctx.train(sh, xr, yr, m, H, cnt)
+
+    print("bench: the same step with RGSW of 2 digits of 15 bits", file=sys.stderr, flush=True)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / steps
+    tr_ms, tr_launch, tr_xp = ctx.profile_read("train")
+    en_ms, _, _ = ctx.profile_read("encrypt_rgsw")
+    ctx.profile(False)
+    del xr, yr, xb, yb
+    d0 = torch.empty(k0 * k1, N, dtype=torch.int64, device=dev)
+    d1 = torch.empty_like(d0)
+    ctx.decrypt_rlwe(sk, H0, k0 * k1, d0)  # RLWE under the same key: either context decrypts it
+    ctx.decrypt_rlwe(sk, H, k0 * k1, d1)
+    same_model = bool(torch.equal(d0, d1))
+    del d0, d1
+    bits = CL.thermometer(levels_of(CL, W, Xte[:W["n_test"]], W.get("ref")), T)
+    cells, dt, inf_ms, inf_xp, _, inf_launch = infer_loop(ctx, sh, H, sk, bits, W, seeds, k0, dev)
+    nt = len(bits)
+    out = {
+        "gadget": "2 balanced digits of 15 bits per prime (RGSW of 2 x 2 nq rows)",
+        "samples_per_s": round(n / (ms / 1000.0), 3), "ms_per_step": round(ms, 2), "steps": steps,
+        "train_ms_per_step": round(tr_ms / steps, 2), "encrypt_ms_per_step": round(en_ms / steps, 2),
+        "train_only_samples_per_s": round(n / (tr_ms / steps / 1000.0), 3) if tr_ms else None,
+        "xp_per_s": round(tr_xp / (tr_ms / 1000.0), 1) if tr_ms else None,
+        "roofline": xp_roofline("k_train", N, nq, tr_xp, tr_ms, tr_launch, peaks, dig=2),
+        "model_cells_equal_default_gadget": same_model,
+        "inference": {"samples_per_s": round(nt / dt, 3),
+                      "infer_kernel_samples_per_s": round(nt / (inf_ms / 1000.0), 3) if inf_ms else None,
+                      "xp_per_s": round(inf_xp / (inf_ms / 1000.0), 1) if inf_ms else None,
+                      "scores_equal_default_gadget": bool(np.array_equal(cells, cells0))},
+    }
+    del H, cnt
+    torch.cuda.empty_cache()
+    return out
 
 
 def boot_key(ctx, sk, seed: int, W: dict, dev):
@@ -988,13 +1082,15 @@ def packed_layout_pass(ctx, W, bits_tr, lab_tr, Xte, sk, seeds, cells0, dev, pea
         "train_kernel_samples_per_s": round(n / (tr_ms / 1000.0), 3) if tr_ms else None,
         "train_xp_per_sample": round(tr_xp / n, 1),
         "train_roofline": xp_roofline("k_train (class-packed)", N, nq, tr_xp, tr_ms, tr_launch, peaks,
-                                      ops=train_ops(N, nq, tr_xp, n * k0)),
+                                      ops=train_ops(N, nq, tr_xp, n * k0) if ctx.digits == 5 else None,
+                                      dig=ctx.digits),
         "reduce_ms": round(rd_ms, 2),
         "infer_samples_per_s": round(nt / dt, 3),
         "infer_kernel_samples_per_s": round(nt / (inf_ms / 1000.0), 3) if inf_ms else None,
         "infer_xp_per_sample": round(inf_xp / nt, 1),
         "infer_roofline": xp_roofline("k_infer (class-packed)", N, nq, inf_xp, inf_ms, inf_launch, peaks,
-                                      ops=inf_xp * ops_per_xp(N, nq)),
+                                      ops=inf_xp * ops_per_xp(N, nq) if ctx.digits == 5 else None,
+                                      dig=ctx.digits),
         "scores_equal_label_pruned": bool(np.array_equal(cells, cells0)),
         "several_rams_per_row": ram_packed,
     }

@@ -50,14 +50,20 @@ typedef enum {
 
 /* One RLWE parameter set (Setup, Sec. 2.5.1).  The paper fixes a 64-bit torus
  * modulus (Table 2); this library uses residues modulo 30-bit NTT-friendly
- * primes instead. */
+ * primes instead.  The RGSW gadget (log_base, digits) is (6, 5) or, on rings
+ * of two or more primes, (15, 2): the digit size of the paper's HE1 TFHE set
+ * (Sec. 4), with 2.5x fewer rows per RGSW and fewer forward transforms per
+ * external product; other pairs give HW_EUNSUPPORTED.  The gadget shapes
+ * RGSW only: keys, RLWE and LWE ciphertexts are the same under both, so two
+ * contexts of one ring with different gadgets share them.
+ * PackingKeySwitching keeps 5 digits of 6 bits per prime on every context. */
 typedef struct {
   uint32_t N;          /* ring degree: 1024, 2048 or 4096 */
   uint32_t nq;         /* number of primes: 1, 2 or 3 */
   uint32_t primes[4];  /* distinct primes q < 2^30, q = 1 mod 2N; primes[0] == 0
                           selects the nq largest such primes, decreasing */
-  uint32_t log_base;   /* gadget base 2^log_base; must be 6 */
-  uint32_t digits;     /* gadget digits per prime; must be 5 */
+  uint32_t log_base;   /* gadget base 2^log_base: 6, or 15 when nq >= 2 */
+  uint32_t digits;     /* gadget digits per prime: 5 with base 2^6, 2 with base 2^15 */
   double sigma;        /* standard deviation of the discrete Gaussian error */
   uint64_t plain_mod;  /* plaintext modulus p: a power of two, 2 <= p <= 2^20 */
 } hw_params;
@@ -193,7 +199,8 @@ hw_status hw_ntt(hw_ctx* ctx, uint32_t* polys_dev, uint64_t count, int inverse,
 
 /* External product (Sec. 2.5.1): out[k] = rgsw[k] [.] in[k] for k < count,
  * i.e. sum_{i,j} dec(b)_{i,j} C[i*digits+j] + sum_{i,j} dec(a)_{i,j}
- * C[D+i*digits+j] with balanced base-2^6 digits of the centered residues.
+ * C[D+i*digits+j] with the balanced base-2^log_base digits of the centered
+ * residues (the last digit takes what is left above the others).
  * in_dev/out_dev: RLWE[count]; rgsw_dev: RGSW[count] in device layout.
  * out must not alias in. */
 hw_status hw_external_product(hw_ctx* ctx, const uint32_t* rgsw_dev, const uint32_t* in_dev,
@@ -271,8 +278,9 @@ hw_status hw_wisard_infer_encrypted(hw_ctx* ctx, const hw_wisard_shape* shape,
  * nq = 2), caller-owned.  hw_pks_key_export_canonical writes the same rows in
  * the coefficient domain (tests).
  * Packing: out = (0, sum_i b^(i) X^i) - sum_{j,r} P_{j,r} K[j][r], where
- * P_{j,r} = sum_i d_r(a^(i)_j) X^i collects the balanced base-64 digits of the
- * external product's decomposition.  lwe_dev: [count][k] LWE; out_dev: [count]
+ * P_{j,r} = sum_i d_r(a^(i)_j) X^i collects the balanced base-64 digits (5 per
+ * residue, on every context: the paper gives PackingKeySwitching
+ * decomposition parameters of its own, Sec. 4).  lwe_dev: [count][k] LWE; out_dev: [count]
  * RLWE (coefficient domain); 1 <= k <= N (HW_EINVAL otherwise). */
 hw_status hw_pks_keygen(hw_ctx* ctx, const int32_t* sk_dev, uint64_t seed, uint32_t* key_dev,
                         hipStream_t stream);
@@ -314,7 +322,7 @@ hw_status hw_pbs_keygen(hw_ctx* ctx, const int32_t* sk_dev, uint64_t seed, uint3
  * hw_pbs_ks_keygen: s1_i = bit 0 of draw i of stream (seed, domain 7)
  * into lwe_key_dev (uint8 [n], device); bsk_dev = RGSW(s1_i) as ciphertexts
  * 0..n-1 of hw_encrypt_rgsw_bits' stream `seed`.  On one prime they use the
- * training gadget (hw_sizes().rgsw bytes each).  On two or more primes they
+ * context's gadget (hw_sizes().rgsw bytes each).  On two or more primes they
  * use 2 balanced digits of 15 bits per prime: 2 x 2 nq RLWE rows per RGSW
  * (row d < 2 nq adds m 2^(15 (d % 2)) to the constant term of residue d / 2
  * of b, row 2 nq + d to that of a), drawn like hw_encrypt_rgsw_bits' rows of

@@ -465,18 +465,32 @@ class Ctx:
         _parallel(lambda i: bsk.__setitem__(i, g.enc_rgsw(s, int(s1[i]), seed, i)), range(n))
         return KsKey(n, s1, ksk, bsk, g)
 
+    def gadget_ctx(self, log_base: int, digits: int) -> "Ctx":
+        """the same ring, primes, p and sigma with another gadget (this
+        context when it already has that one): RLWE and LWE ciphertexts are
+        the same under both, RGSW and PackingKeySwitching keys follow it"""
+        if (log_base, digits) == (self.log_base, self.digits):
+            return self
+        cache = self.__dict__.setdefault("_gadget_ctx", {})
+        if (log_base, digits) not in cache:
+            cache[(log_base, digits)] = Ctx(self.N, self.nq, self.p, primes=list(self.primes), log_base=log_base,
+                                            digits=digits, sigma=self.sigma)
+        return cache[(log_base, digits)]
+
     def bsk_ctx(self) -> "Ctx":
         """the same ring with the key-switched bootstrapping key's gadget:
         BSK_DIGITS balanced digits of BSK_LOG_BASE bits per prime when Q has
         two or more primes; the training gadget (this context) on a one-prime
         ring, whose 30-bit modulus leaves no room for the coarser digits'
         noise"""
-        if self.nq < 2:
-            return self
-        if getattr(self, "_bsk_ctx", None) is None:
-            self._bsk_ctx = Ctx(self.N, self.nq, self.p, primes=list(self.primes), log_base=BSK_LOG_BASE,
-                                digits=BSK_DIGITS)
-        return self._bsk_ctx
+        return self if self.nq < 2 else self.gadget_ctx(BSK_LOG_BASE, BSK_DIGITS)
+
+    def pks_ctx(self) -> "Ctx":
+        """the context of PackingKeySwitching: its decomposition has
+        parameters of its own (the paper's TFHE parameter table lists them
+        beside the RGSW gadget), here 5 balanced digits of 6 bits per prime
+        whatever this context's RGSW gadget"""
+        return self.gadget_ctx(PKS_LOG_BASE, PKS_DIGITS)
 
     def key_switch(self, key: "KsKey", lwe) -> np.ndarray:
         """the LWE (ring key, modulus Q) switched to key.s1 at modulus 2^32: [n + 1] uint32"""
@@ -518,7 +532,10 @@ class Ctx:
     # -- PackingKeySwitching ----------------------------------------------
     def pks_keygen(self, s, seed: int, threads=None) -> np.ndarray:
         """K[j][r] = RLWE_s(s_j G_r) for j < N, r < D: [N][D][2][nq][N]
-        (rows are independent; ranges of j go to threads)"""
+        (rows are independent; ranges of j go to threads), D = 5 nq: the
+        gadget of pks_ctx()"""
+        if self.pks_ctx() is not self:
+            return self.pks_ctx().pks_keygen(s, seed, threads)
         s = np.ascontiguousarray(s, np.int32)
         K = np.zeros((self.N, self.D, 2, self.nq, self.N), np.uint32)
         ranges = [(j0, min(self.N, j0 + 64)) for j0 in range(0, self.N, 64)]
@@ -529,6 +546,8 @@ class Ctx:
     def pack_lwe(self, K, lwes, threads=None) -> np.ndarray:
         """one RLWE whose phase is sum_i phase(lwes[i]) X^i (k = len(lwes) <= N);
         the sum over key coordinates is split over threads"""
+        if self.pks_ctx() is not self:
+            return self.pks_ctx().pack_lwe(K, lwes, threads)
         K = np.ascontiguousarray(K, np.uint32)
         lwes = np.ascontiguousarray(lwes, np.uint32)
         k = lwes.shape[0]
@@ -650,6 +669,7 @@ class Ctx:
 
 
 KS_LOG_BASE, KS_DIGITS = 4, 6  # the key switch's gadget (oracle.c)
+PKS_LOG_BASE, PKS_DIGITS = 6, 5  # PackingKeySwitching's gadget (Ctx.pks_ctx)
 # the gadget of the key-switched bootstrapping key's RGSW (its blind rotation's
 # external products) on rings of two or more primes: 2 balanced digits of 15
 # bits per prime (Ctx.bsk_ctx)

@@ -147,9 +147,10 @@ extern "C" hw_status hw_ctx_create(const hw_params* params, int device, hw_ctx**
   if ((1u << logN) != P.N || logN < 10 || logN > 12)
     return fail(HW_EUNSUPPORTED, "N = %u: supported ring degrees are 1024, 2048, 4096", P.N);
   if (P.nq < 1 || P.nq > 3) return fail(HW_EUNSUPPORTED, "nq = %u: 1..3 primes supported", P.nq);
-  if (P.log_base != 6 || P.digits != 5)
-    return fail(HW_EUNSUPPORTED, "gadget base 2^%u with %u digits: only base 2^6 with 5 digits is compiled",
-                P.log_base, P.digits);
+  if (!(P.log_base == 6 && P.digits == 5) && !(P.log_base == 15 && P.digits == 2 && P.nq >= 2))
+    return fail(HW_EUNSUPPORTED,
+                "gadget base 2^%u with %u digits: the kernels are built for base 2^6 with 5 digits, and for base "
+                "2^15 with 2 digits on rings of two or more primes", P.log_base, P.digits);
   if (!(P.sigma > 0.0 && P.sigma < 16.0)) return fail(HW_EINVAL, "sigma = %g out of range (0, 16)", P.sigma);
   if (P.plain_mod < 2 || P.plain_mod > (1ull << 20) || (P.plain_mod & (P.plain_mod - 1)))
     return fail(HW_EINVAL, "plain_mod = %llu: a power of two in [2, 2^20] is required",
@@ -471,10 +472,11 @@ extern "C" hw_status hw_encrypt_rgsw_bits(hw_ctx* c, const int32_t* sk, const ui
   A.seed = seed;
   A.ct0 = ct0;
   A.log_base = c->prm.log_base;
-  const double rows = (double)nbits * 10 * c->prm.nq;
+  const double rows = (double)nbits * 2 * c->prm.digits * c->prm.nq;
   HIP_TRY(timed(c, "encrypt_rgsw", rows, st, [&] {
     return tuned(c, "encrypt_rgsw", rows, st, [&](int v) {
-      return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, nbits, enc_rows_per_wg(v), st);
+      return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->prm.digits, c->tabs, c->cdt, A, nbits,
+                                 enc_rows_per_wg(v), st);
     });
   }));
   return ok();
@@ -527,7 +529,7 @@ extern "C" hw_status hw_rgsw_export_canonical(hw_ctx* c, const uint32_t* rgsw, u
   if (count == 0) return ok();
   if (!rgsw || !out) return fail(HW_EINVAL, "null buffer");
   if (rgsw == out) return fail(HW_EINVAL, "output must not alias input");
-  HIP_TRY(hw::launch_rgsw_export(c->logN, c->prm.nq, c->tabs, rgsw, count, out, st));
+  HIP_TRY(hw::launch_rgsw_export(c->logN, c->prm.nq, c->prm.digits, c->tabs, rgsw, count, out, st));
   return ok();
 }
 
@@ -552,7 +554,7 @@ extern "C" hw_status hw_external_product(hw_ctx* c, const uint32_t* rgsw, const 
   if (!rgsw || !in || !out) return fail(HW_EINVAL, "null buffer");
   if (in == out) return fail(HW_EINVAL, "output must not alias input");
   HIP_TRY(timed(c, "xp", (double)count, st,
-                [&] { return hw::launch_xp(c->logN, c->prm.nq, c->tabs, rgsw, in, count, out, st); }));
+                [&] { return hw::launch_xp(c->logN, c->prm.nq, c->prm.digits, c->tabs, rgsw, in, count, out, st); }));
   return ok();
 }
 
@@ -642,11 +644,11 @@ hw_status train_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
       A.map = (uint32_t)(v & 1);
       const int occ = v & 4 ? 4 : 3;
       A.tree = (v & 2) && can_stage ? 0u : 1u;
-      hipError_t e = hw::launch_train(c->logN, c->prm.nq, c->tabs, A, occ, st);
+      hipError_t e = hw::launch_train(c->logN, c->prm.nq, c->prm.digits, c->tabs, A, occ, st);
       for (uint32_t lev = 0; e == hipSuccess && !A.tree && lev < levels; ++lev) {
         A.lev = lev;
         A.smax = smax[lev];
-        e = hw::launch_train_level(c->logN, c->prm.nq, c->tabs, A, occ, st);
+        e = hw::launch_train_level(c->logN, c->prm.nq, c->prm.digits, c->tabs, A, occ, st);
       }
       return e;
     };
@@ -735,7 +737,7 @@ hw_status infer_core(hw_ctx* c, const hw_wisard_shape* sh, const Dims& d, const 
     auto li = [&] {
       return tuned(c, "infer", xp, st, [&](int v) {
         A.map = (uint32_t)(v & 1);
-        return hw::launch_infer(c->logN, c->prm.nq, c->tabs, A, v & 2 ? 4 : 3, st);
+        return hw::launch_infer(c->logN, c->prm.nq, c->prm.digits, c->tabs, A, v & 2 ? 4 : 3, st);
       });
     };
     HIP_TRY(tm ? timed(c, "infer", xp, st, li) : li());
@@ -787,7 +789,7 @@ extern "C" hw_status hw_pks_keygen(hw_ctx* c, const int32_t* sk, uint64_t seed, 
   A.sk_hat = c->d_skhat;
   A.out = key;
   A.seed = seed;
-  A.log_base = c->prm.log_base;
+  A.log_base = 6;  // PackingKeySwitching's own gadget: 5 digits of 6 bits per prime on every context
   HIP_TRY(timed(c, "encrypt_pks", (double)c->prm.N * 5 * c->prm.nq, st,
                 [&] { return hw::launch_enc_pks(c->logN, c->prm.nq, c->tabs, c->cdt, A, st); }));
   return ok();
@@ -798,7 +800,7 @@ extern "C" hw_status hw_pks_key_export_canonical(hw_ctx* c, const uint32_t* key,
   if (!key || !out) return fail(HW_EINVAL, "null buffer");
   if (key == out) return fail(HW_EINVAL, "output must not alias input");
   // N x D rows have the row layout of N / 2 RGSW ciphertexts (2 D rows each)
-  HIP_TRY(hw::launch_rgsw_export(c->logN, c->prm.nq, c->tabs, key, c->prm.N / 2, out, st));
+  HIP_TRY(hw::launch_rgsw_export(c->logN, c->prm.nq, 5, c->tabs, key, c->prm.N / 2, out, st));
   return ok();
 }
 
@@ -921,7 +923,7 @@ static hw_status plan_batch(hw_ctx* c, const hw_train_job* jobs, uint32_t njobs,
   for (uint32_t j = 0; j < njobs; ++j)
     if (jobs[j].n) CHECK(perm_for(c, &jobs[j].shape, st, &perms[j]));
   for (int v = 0; v < tune_variants(c, "train_batch"); ++v)
-    HIP_TRY(hw::batch_grid(c->logN, c->prm.nq, v ? 4 : 3, &B.grid_occ[v]));
+    HIP_TRY(hw::batch_grid(c->logN, c->prm.nq, c->prm.digits, v ? 4 : 3, &B.grid_occ[v]));
   B.grid = std::max(B.grid_occ[0], B.grid_occ[1]);
   const size_t rw = rlwe_words(c);
   // per job: RAMs, external products per (sample, RAM) and per sample
@@ -1025,7 +1027,7 @@ static hw_status run_batch(hw_ctx* c, const BPlan& B, const hw::BJob* djobs, con
   const bool tm = timing && c->prof;
   auto lt = [&] {
     return tuned(c, "train_batch", B.xp, st, [&](int v) {
-      return hw::launch_train_batch(c->logN, c->prm.nq, c->tabs, A, B.grid_occ[v], v ? 4 : 3, st);
+      return hw::launch_train_batch(c->logN, c->prm.nq, c->prm.digits, c->tabs, A, B.grid_occ[v], v ? 4 : 3, st);
     });
   };
   HIP_TRY(tm ? timed(c, "train_batch", B.xp, st, lt) : lt());
@@ -1218,6 +1220,7 @@ static int table_variants(const char* kernel) {
 
 int tune_variants(const hw_ctx* c, const char* kernel) {
   const int n = table_variants(kernel);
+  if (!strcmp(kernel, "encrypt_rgsw") && c->prm.digits == 2) return 2;  // 5 rows per workgroup divide no 4 nq
   if (c->logN == 12) return n;
   if (!strcmp(kernel, "train")) return 4;
   if (!strcmp(kernel, "infer")) return 2;

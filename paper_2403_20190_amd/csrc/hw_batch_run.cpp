@@ -35,7 +35,7 @@ struct IPlan {
 // workgroup's share of the batch; items longest first.
 hw_status plan_infer(hw_ctx* c, const std::vector<const hw_job*>& jobs, hipStream_t st, IPlan& B) {
   for (int v = 0; v < tune_variants(c, "infer_batch"); ++v)
-    HIP_TRY(hw::infer_batch_grid(c->logN, c->prm.nq, v ? 4 : 3, &B.grid_occ[v]));
+    HIP_TRY(hw::infer_batch_grid(c->logN, c->prm.nq, c->prm.digits, v ? 4 : 3, &B.grid_occ[v]));
   B.grid = std::max(B.grid_occ[0], B.grid_occ[1]);
   std::vector<Dims> dims(jobs.size());
   std::vector<double> unit(jobs.size(), 0.0);  // external products of one (sample, RAM, label) VP, on average
@@ -132,7 +132,7 @@ hw_status run_infer(hw_ctx* c, const std::vector<const hw_job*>& jobs, hipStream
   A.scratch_words = B.scratch_words;
   auto li = [&] {
     return tuned(c, "infer_batch", B.xp, st, [&](int v) {
-      return hw::launch_infer_batch(c->logN, c->prm.nq, c->tabs, A, B.grid_occ[v], v ? 4 : 3, st);
+      return hw::launch_infer_batch(c->logN, c->prm.nq, c->prm.digits, c->tabs, A, B.grid_occ[v], v ? 4 : 3, st);
     });
   };
   HIP_TRY(timed(c, "infer_batch", B.xp, st, li));

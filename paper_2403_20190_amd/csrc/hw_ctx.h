@@ -152,7 +152,7 @@ static hipError_t timed(hw_ctx* c, const char* name, double work, hipStream_t st
 }
 
 static size_t rlwe_words(const hw_ctx* c) { return (size_t)2 * c->prm.nq * c->prm.N; }
-static size_t rgsw_words(const hw_ctx* c) { return (size_t)2 * 5 * c->prm.nq * rlwe_words(c); }
+static size_t rgsw_words(const hw_ctx* c) { return (size_t)2 * c->prm.digits * c->prm.nq * rlwe_words(c); }
 static size_t lwe_words(const hw_ctx* c) { return (size_t)c->prm.nq * (c->prm.N + 1); }
 
 struct Dims {

@@ -489,6 +489,15 @@ __device__ __forceinline__ uint32_t digit_lift_g(int32_t w, int j, uint32_t q) {
 
 __device__ __forceinline__ uint32_t digit_lift(int32_t w, int j, uint32_t q) { return digit_lift_g<5, 6>(w, j, q); }
 
+// The two RGSW gadgets the kernels are built for, by digits per prime: 5
+// digits of 6 bits (the training default) and 2 digits of 15 bits (rings of
+// two or more primes).
+template <int DIG>
+__host__ __device__ constexpr int gadget_lb() {
+  static_assert(DIG == 5 || DIG == 2, "gadgets: 5 digits of 6 bits or 2 digits of 15 bits per prime");
+  return DIG == 5 ? 6 : 15;
+}
+
 // inverse transforms of the a and b sums of output prime ip (inputs in [0, q))
 // and the write of the external product by out.mode
 template <int LOGN, int NQ, bool PR>
@@ -656,9 +665,9 @@ __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const
 //   acc[k] = sum_r d0_r C_r[k] + E[k] sum_r d1_r C_r[k]  (mod q)
 // with small signed multipliers.  Both sums are reduced to [0, q) before the
 // inverse transform, as in ext_prod, so the result is the same residues
-// ext_prod computes for that input, without its 10 nq^2 forward transforms
-// and with half its RGSW reads.
-template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>()>
+// ext_prod computes for that input, without its 2 DIG nq^2 forward transforms
+// and with half its RGSW reads.  DIG, LB: the RGSW's gadget, as in ext_prod.
+template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>(), int DIG = 5, int LB = 6>
 __device__ __forceinline__ void ext_prod_delta(const uint32_t* __restrict__ C, const Tabs& T, uint32_t* lds,
                                                uint32_t& xc, uint32_t t, XpOut out) {
   constexpr int N = 1 << LOGN;
@@ -680,16 +689,17 @@ __device__ __forceinline__ void ext_prod_delta(const uint32_t* __restrict__ C, c
         const uint32_t r0 = dl ? qi - dl : 0u;
         int32_t v0 = r0 > (qi - 1) / 2 ? (int32_t)(r0 - qi) : (int32_t)r0;
         int32_t v1 = dl > (qi - 1) / 2 ? (int32_t)(dl - qi) : (int32_t)dl;
+        constexpr int32_t H = 1 << (LB - 1), M = (1 << LB) - 1;
 #pragma unroll 1
-        for (int j = 0; j < 5; ++j) {
+        for (int j = 0; j < DIG; ++j) {
           int32_t e0 = v0, e1 = v1;
-          if (j < 4) {
-            e0 = ((v0 + 32) & 63) - 32;
-            e1 = ((v1 + 32) & 63) - 32;
-            v0 = (v0 - e0) >> 6;
-            v1 = (v1 - e1) >> 6;
+          if (j < DIG - 1) {
+            e0 = ((v0 + H) & M) - H;
+            e1 = ((v1 + H) & M) - H;
+            v0 = (v0 - e0) >> LB;
+            v1 = (v1 - e1) >> LB;
           }
-          const uint4* cr = reinterpret_cast<const uint4*>(C + (size_t)(i * 5 + j) * ROW +
+          const uint4* cr = reinterpret_cast<const uint4*>(C + (size_t)(i * DIG + j) * ROW +
                                                            ((size_t)side * NQ + ip) * N);
           const uint4 c0 = cr[2 * t], c1 = cr[2 * t + 1];
           const int32_t cv[8] = {(int32_t)c0.x, (int32_t)c0.y, (int32_t)c0.z, (int32_t)c0.w,
@@ -702,8 +712,9 @@ __device__ __forceinline__ void ext_prod_delta(const uint32_t* __restrict__ C, c
           }
         }
       }
-      // |s| < 5 NQ 2^5 2^30 < 2^39 <= 2^10 q: shifting by 2^10 q makes it nonnegative, same residue
-      const int64_t sh = (int64_t)P.q << 10;
+      // |s| < DIG NQ 2^(LB-1) q <= 2^(LB+4) q (DIG NQ <= 15): shifting by 2^(LB+4) q
+      // makes it nonnegative, same residue
+      const int64_t sh = (int64_t)P.q << (LB + 4);
       const uint4* ev = reinterpret_cast<const uint4*>(T.evx[ip] + 8 * (size_t)t);
 #pragma unroll
       for (int hh = 0; hh < 4; ++hh) {

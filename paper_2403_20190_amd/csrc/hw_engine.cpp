@@ -185,8 +185,10 @@ static hw_status launch_chunk(hw_engine* E, Slot& S, Req& R, const Job& J) {
   A.seed = R.seed_x;
   A.ct0 = o * s;
   A.log_base = c->prm.log_base;
-  HIP_TRY(tuned(c, "encrypt_rgsw", (double)m * s * 10 * c->prm.nq, S.st, [&](int v) {
-    return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, m * s, enc_rows_per_wg(v), S.st);
+  const double rows_per_bit = 2.0 * c->prm.digits * c->prm.nq;
+  HIP_TRY(tuned(c, "encrypt_rgsw", (double)m * s * rows_per_bit, S.st, [&](int v) {
+    return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->prm.digits, c->tabs, c->cdt, A, m * s, enc_rows_per_wg(v),
+                               S.st);
   }));
   if (R.r.kind == 0) {
     uint32_t* yr = reinterpret_cast<uint32_t*>(carve(p, m * L * rgsw_words(c) * 4));
@@ -195,8 +197,9 @@ static hw_status launch_chunk(hw_engine* E, Slot& S, Req& R, const Job& J) {
       A.out = yr;
       A.seed = R.seed_y;
       A.ct0 = o * L;
-      HIP_TRY(tuned(c, "encrypt_rgsw", (double)m * L * 10 * c->prm.nq, S.st, [&](int v) {
-        return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->tabs, c->cdt, A, m * L, enc_rows_per_wg(v), S.st);
+      HIP_TRY(tuned(c, "encrypt_rgsw", (double)m * L * rows_per_bit, S.st, [&](int v) {
+        return hw::launch_enc_rgsw(c->logN, c->prm.nq, c->prm.digits, c->tabs, c->cdt, A, m * L,
+                                   enc_rows_per_wg(v), S.st);
       }));
     }
     const size_t wsb = m * train_ws_per_sample(c, J.d);

@@ -159,45 +159,44 @@ hipError_t launch_keygen(uint32_t N, uint64_t seed, int32_t* sk, hipStream_t st)
 // per ring coefficient, as signed bytes [4 (n + 1)][N D] (the rows past
 // 4 (n + 1) of a padded buffer are left as they are)
 hipError_t launch_lwe_keygen(uint32_t n, uint64_t seed, uint8_t* s1, hipStream_t st);
-// RGSW of count bits with a 2-digit gadget of A.log_base bits per prime
-// (rows 2 * 2 nq, drawn like hw_encrypt_rgsw_bits' rows of such a gadget)
-hipError_t launch_enc_rgsw_g2(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
-                              hipStream_t st);
 hipError_t launch_ksk_gen(const int32_t* sk, const uint8_t* s1, uint32_t N, uint32_t n, uint64_t seed, uint32_t D,
                           const Cdt& cdt, int8_t* out, hipStream_t st);
 // sk_hat: 2 nq N words (the transformed key, then its Shoup companions)
 hipError_t launch_sk_hat(int logN, int nq, const Tabs& T, const int32_t* sk, uint32_t* sk_hat, hipStream_t st);
-hipError_t launch_enc_rgsw(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
-                           int rows_per_wg, hipStream_t st);
+// dig: digits per prime of the RGSW gadget (5 of 6 bits, or 2 of 15 bits on
+// rings of two or more primes; A.log_base must match), 2 dig nq rows per RGSW
+hipError_t launch_enc_rgsw(int logN, int nq, int dig, const Tabs& T, const Cdt& cdt, const EncArgs& A,
+                           uint64_t count, int rows_per_wg, hipStream_t st);
 hipError_t launch_enc_rlwe(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
                            hipStream_t st);
 hipError_t launch_dec_rlwe(int logN, int nq, const Tabs& T, const CrtTab& K, const uint32_t* sk_hat,
                            const uint32_t* ct, uint64_t count, uint64_t* msg, hipStream_t st);
 hipError_t launch_dec_lwe(int logN, int nq, const Tabs& T, const CrtTab& K, const int32_t* sk,
                           const uint32_t* lwe, uint64_t count, uint64_t* msg, hipStream_t st);
-hipError_t launch_rgsw_export(int logN, int nq, const Tabs& T, const uint32_t* rgsw, uint64_t count,
+hipError_t launch_rgsw_export(int logN, int nq, int dig, const Tabs& T, const uint32_t* rgsw, uint64_t count,
                               uint32_t* out, hipStream_t st);
 hipError_t launch_ntt(int logN, int nq, const Tabs& T, uint32_t* polys, uint64_t count, int inverse,
                       uint32_t per, hipStream_t st);
-hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, const uint32_t* in, uint64_t count,
-                     uint32_t* out, hipStream_t st);
+hipError_t launch_xp(int logN, int nq, int dig, const Tabs& T, const uint32_t* rgsw, const uint32_t* in,
+                     uint64_t count, uint32_t* out, hipStream_t st);
 // occ: occupancy target of the external-product kernels, 3 or 4 (4 only for log2 N = 12)
 // the permutation of (s, seed) written to pi[0..s) on the device (one thread)
 hipError_t launch_perm(uint32_t s, uint64_t seed, uint32_t* pi, hipStream_t st);
-hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st);
+hipError_t launch_train(int logN, int nq, int dig, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st);
 // one CDEMUX level of every (sample, RAM) of a sub-batch whose chains k_train
 // (A.tree = 0) has run: A.nram x A.nsub x A.smax workgroups, one split each
-hipError_t launch_train_level(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st);
+hipError_t launch_train_level(int logN, int nq, int dig, const Tabs& T, const TrainArgs& A, int occ,
+                              hipStream_t st);
 hipError_t launch_reduce_model(const Tabs& T, const ReduceArgs& A, hipStream_t st);
 hipError_t launch_row_pack(const Tabs& T, const RowPackArgs& A, hipStream_t st);
-hipError_t batch_grid(int logN, int nq, int occ, uint32_t* grid);  // persistent workgroups that fit the device
-hipError_t launch_train_batch(int logN, int nq, const Tabs& T, const BatchArgs& A, uint32_t grid, int occ,
+hipError_t batch_grid(int logN, int nq, int dig, int occ, uint32_t* grid);  // persistent workgroups that fit
+hipError_t launch_train_batch(int logN, int nq, int dig, const Tabs& T, const BatchArgs& A, uint32_t grid, int occ,
                               hipStream_t st);
 hipError_t launch_reduce_batch(const Tabs& T, const BJob* jobs, uint32_t njobs, uint64_t total, uint32_t logN,
                                uint32_t N, uint32_t nq, const uint32_t* acc, hipStream_t st);
-hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int occ, hipStream_t st);
-hipError_t infer_batch_grid(int logN, int nq, int occ, uint32_t* grid);
-hipError_t launch_infer_batch(int logN, int nq, const Tabs& T, const IBatchArgs& B, uint32_t grid, int occ,
+hipError_t launch_infer(int logN, int nq, int dig, const Tabs& T, const InferArgs& A, int occ, hipStream_t st);
+hipError_t infer_batch_grid(int logN, int nq, int dig, int occ, uint32_t* grid);
+hipError_t launch_infer_batch(int logN, int nq, int dig, const Tabs& T, const IBatchArgs& B, uint32_t grid, int occ,
                               hipStream_t st);
 hipError_t launch_class_sums(const Tabs& T, const SumArgs& A, hipStream_t st);
 hipError_t launch_enc_pks(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, hipStream_t st);

@@ -638,7 +638,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) void k_rgsw_export(Tabs T, const uint
   }
 }
 
-template <int LOGN, int NQ>
+template <int LOGN, int NQ, int DIG = 5>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WAVES_XP, 8))) void k_xp(Tabs T, const uint32_t* __restrict__ rgsw,
                                                       const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
                                                       uint64_t rgsw_words) {
@@ -649,8 +649,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(WA
   const uint64_t c = blockIdx.x + (uint64_t)blockIdx.y * gridDim.x;
   uint32_t* o = out + c * (size_t)(2 * NQ * N);
   uint32_t xc = 0;
-  ext_prod<LOGN, NQ>(in + c * (size_t)(2 * NQ * N), rgsw + c * rgsw_words, T, lds, twl, xc, t,
-                     XpOut{o, nullptr, nullptr, XP_STORE});
+  ext_prod<LOGN, NQ, xp_pair<LOGN, NQ>(), DIG, gadget_lb<DIG>()>(in + c * (size_t)(2 * NQ * N), rgsw + c * rgsw_words,
+                                                                T, lds, twl, xc, t, XpOut{o, nullptr, nullptr, XP_STORE});
 }
 
 // ---------------------------------------------------------------------------
@@ -676,12 +676,12 @@ __device__ __forceinline__ void rot_diff(const Tabs& T, const uint32_t* __restri
 }
 
 // CMUX step of a blind rotation: acc <- acc + C [.] (X^ex acc - acc)
-template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>()>
+template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>(), int DIG = 5>
 __device__ __forceinline__ void cmux_rot(const Tabs& T, uint32_t* __restrict__ acc, int32_t ex,
                                          const uint32_t* __restrict__ C, uint32_t* __restrict__ xin, uint32_t* lds,
                                          uint2* twl, uint32_t& xc, uint32_t t) {
   rot_diff<LOGN, NQ>(T, acc, ex, xin, t);
-  ext_prod<LOGN, NQ, PR>(xin, C, T, lds, twl, xc, t, XpOut{acc, acc, nullptr, XP_ADD});
+  ext_prod<LOGN, NQ, PR, DIG, gadget_lb<DIG>()>(xin, C, T, lds, twl, xc, t, XpOut{acc, acc, nullptr, XP_ADD});
   __syncthreads();  // the next rotation reads coefficients other threads wrote
 }
 
@@ -739,7 +739,7 @@ __device__ __forceinline__ void acc_rlwe(const Tabs& T, uint32_t* __restrict__ d
 // bits and l classes.  Without `dest` leaf d is left in slot d.  With
 // `dest`, live leaf d goes to dest[leaf_row(d)] instead: stored when
 // `store`, else added (the last tree level writes there directly).
-template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>(), class BitFn>
+template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>(), int DIG = 5, class BitFn>
 __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ slot0, uint32_t* __restrict__ xin,
                                           uint32_t nb, uint32_t L, uint32_t l, BitFn&& bit, uint32_t* lds,
                                           uint2* twl, uint32_t t, uint32_t* __restrict__ dest = nullptr,
@@ -757,11 +757,12 @@ __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ 
   __syncthreads();
   uint32_t xc = 0;
   if (nr > 0) {  // the first CMUX acts on (0, Delta): X acc - acc = (0, Delta (X - 1))
-    ext_prod_delta<LOGN, NQ, PR>(bit(z), T, lds, xc, t, XpOut{slot0, slot0, nullptr, XP_ADD});
+    ext_prod_delta<LOGN, NQ, PR, DIG, gadget_lb<DIG>()>(bit(z), T, lds, xc, t, XpOut{slot0, slot0, nullptr, XP_ADD});
     __syncthreads();
   }
 #pragma unroll 1
-  for (uint32_t st = 1; st < nr; ++st) cmux_rot<LOGN, NQ, PR>(T, slot0, 1 << st, bit(z + st), xin, lds, twl, xc, t);
+  for (uint32_t st = 1; st < nr; ++st)
+    cmux_rot<LOGN, NQ, PR, DIG>(T, slot0, 1 << st, bit(z + st), xin, lds, twl, xc, t);
   if (!tree) return;
 #pragma unroll 1
   for (uint32_t lev = 0; lev < z; ++lev) {
@@ -775,11 +776,13 @@ __device__ __forceinline__ void ivp_block(const Tabs& T, uint32_t* __restrict__ 
       if (node_live(j + n, z, L, l)) {
         copy_rlwe<LOGN, NQ>(xin, sj, t);
         if (last)
-          ext_prod<LOGN, NQ, PR>(xin, C, T, lds, twl, xc, t,
-                                 XpOut{dest + leaf_row(j, z, L, l) * RW, xin, dest + leaf_row(j + n, z, L, l) * RW,
-                                   store ? XP_DEMUX : XP_DEMUX_ACC});
+          ext_prod<LOGN, NQ, PR, DIG, gadget_lb<DIG>()>(
+              xin, C, T, lds, twl, xc, t,
+              XpOut{dest + leaf_row(j, z, L, l) * RW, xin, dest + leaf_row(j + n, z, L, l) * RW,
+                    store ? XP_DEMUX : XP_DEMUX_ACC});
         else
-          ext_prod<LOGN, NQ, PR>(xin, C, T, lds, twl, xc, t, XpOut{sj, xin, slot0 + (j + n) * RW, XP_DEMUX});
+          ext_prod<LOGN, NQ, PR, DIG, gadget_lb<DIG>()>(xin, C, T, lds, twl, xc, t,
+                                                        XpOut{sj, xin, slot0 + (j + n) * RW, XP_DEMUX});
       } else if (last) {  // unsplit live leaf
         acc_rlwe<LOGN, NQ>(T, dest + leaf_row(j, z, L, l) * RW, sj, store, t);
       }
@@ -826,7 +829,7 @@ __device__ __forceinline__ const uint32_t* index_bit(uint32_t layout, uint32_t u
   return y + (gi * L + (u - aj)) * rgsw_words;
 }
 
-template <int LOGN, int NQ, int OCC>
+template <int LOGN, int NQ, int OCC, int DIG = 5>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_train(Tabs T, TrainArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, xp_pair<LOGN, NQ>()>()];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
@@ -846,7 +849,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
   const uint64_t gi = A.i0 + smp;
   uint32_t* slot0 = A.out + ((size_t)smp * (A.k0 + 1) + ram) * (A.kt + 1) * RW;
   const uint32_t nb = ram_bits(ram, A.k0, A.s, A.a, A.L);
-  ivp_block<LOGN, NQ>(T, slot0, slot0 + (size_t)A.kt * RW, nb, tree_L(A.layout, A.L), tree_l(A.layout, A.l),
+  ivp_block<LOGN, NQ, xp_pair<LOGN, NQ>(), DIG>(T, slot0, slot0 + (size_t)A.kt * RW, nb, tree_L(A.layout, A.L),
+                                               tree_l(A.layout, A.l),
                       [&](uint32_t u) -> const uint32_t* {
                         return index_bit(A.layout, u, nb, A.L, A.x_rgsw, A.y_rgsw, A.perm, gi, A.s, ram, A.a,
                                          A.rgsw_words);
@@ -866,7 +870,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
 // h = C [.] slot j to slot j + 2^lev, then slot j -= h: the bits of the
 // in-workgroup tree (XP_DEMUX), with no input copy (ext_prod reads every
 // input coefficient before the subtraction, each thread its own).
-template <int LOGN, int NQ, int OCC>
+template <int LOGN, int NQ, int OCC, int DIG = 5>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_train_level(
     Tabs T, TrainArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, xp_pair<LOGN, NQ>()>()];
@@ -898,7 +902,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
   const uint32_t* C = index_bit(A.layout, A.lev, nb, A.L, A.x_rgsw, A.y_rgsw, A.perm, gi, A.s, ram, A.a,
                                 A.rgsw_words);
   uint32_t xc = 0;
-  ext_prod<LOGN, NQ>(sj, C, T, lds, twl, xc, t, XpOut{sn, nullptr, nullptr, XP_STORE});
+  ext_prod<LOGN, NQ, xp_pair<LOGN, NQ>(), DIG, gadget_lb<DIG>()>(sj, C, T, lds, twl, xc, t,
+                                                                XpOut{sn, nullptr, nullptr, XP_STORE});
 #pragma unroll 1
   for (int w = 0; w < 2 * NQ; ++w) {
     const uint32_t q = T.pt[w % NQ].q;
@@ -922,7 +927,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
 // longest first; a workgroup leaves when the queue is exhausted.
 // k_reduce_batch then adds the accumulators of pieces >= 1 into the models.
 
-template <int LOGN, int NQ, int OCC>
+template <int LOGN, int NQ, int OCC, int DIG = 5>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_train_batch(
     Tabs T, BatchArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, false>()];
@@ -951,7 +956,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
     for (uint32_t smp = s0; smp < s1; ++smp) {
       const uint64_t gi = smp;
       // single transforms: with pairs the queue state next to them spills registers
-      ivp_block<LOGN, NQ, false>(T, slot0, slot0 + (size_t)J.kt * RW, nb, tree_L(J.layout, J.L),
+      ivp_block<LOGN, NQ, false, DIG>(T, slot0, slot0 + (size_t)J.kt * RW, nb, tree_L(J.layout, J.L),
                                  tree_l(J.layout, J.l),
                           [&](uint32_t u) -> const uint32_t* {
                             return index_bit(J.layout, u, nb, J.L, J.x, J.y, J.perm, gi, J.s, I.ram, J.a,
@@ -1105,7 +1110,7 @@ __global__ __launch_bounds__(256) void k_row_pack(Tabs T, RowPackArgs A) {
 
 // The VP of (sample gi, RAM ram, label lab) with the workgroup's slots acc
 // (A.slots RLWE) and input slot xin; writes its LWE score(s) into A.scores.
-template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>()>
+template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>(), int DIG = 5>
 __device__ __forceinline__ void vp_one(const Tabs& T, const InferArgs& A, uint64_t gi, uint32_t ram, uint32_t lab,
                                        uint32_t* __restrict__ acc, uint32_t* __restrict__ xin, uint32_t* lds,
                                        uint2* twl, uint32_t t) {
@@ -1146,7 +1151,7 @@ __device__ __forceinline__ void vp_one(const Tabs& T, const InferArgs& A, uint64
           for (int e = 0; e < 8; ++e)
             (xin + o + TT * e)[t] = subq((hi + o + TT * e)[t], (lo + o + TT * e)[t], q);
         }
-        ext_prod<LOGN, NQ, PR>(xin, C, T, lds, twl, xc, t, XpOut{dst, lo, nullptr, XP_ADD});
+        ext_prod<LOGN, NQ, PR, DIG, gadget_lb<DIG>()>(xin, C, T, lds, twl, xc, t, XpOut{dst, lo, nullptr, XP_ADD});
       }
     }
   } else {
@@ -1174,7 +1179,7 @@ __device__ __forceinline__ void vp_one(const Tabs& T, const InferArgs& A, uint64
       }
       continue;
     }
-    cmux_rot<LOGN, NQ, PR>(T, acc, ex, xbit(u), xin, lds, twl, xc, t);
+    cmux_rot<LOGN, NQ, PR, DIG>(T, acc, ex, xbit(u), xin, lds, twl, xc, t);
   }
   // ExtractLWE(acc, idx) for the class(es) of this workgroup: a'_k = a_{idx-k}
   // for k <= idx, -a_{N+idx-k} above, b' = b_idx; idx = 0 for layout 0,
@@ -1202,7 +1207,7 @@ __device__ __forceinline__ void vp_one(const Tabs& T, const InferArgs& A, uint64
   }
 }
 
-template <int LOGN, int NQ, int OCC>
+template <int LOGN, int NQ, int OCC, int DIG = 5>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_infer(Tabs T, InferArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, xp_pair<LOGN, NQ>()>()];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
@@ -1222,7 +1227,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
     smp = lg / A.nlab / A.k0;
   }
   uint32_t* acc = A.scratch + (((size_t)smp * A.nlab + lab) * A.k0 + ram) * (A.slots + 1) * RW;
-  vp_one<LOGN, NQ>(T, A, A.i0 + smp, ram, lab, acc, acc + (size_t)A.slots * RW, lds, twl, t);
+  vp_one<LOGN, NQ, xp_pair<LOGN, NQ>(), DIG>(T, A, A.i0 + smp, ram, lab, acc, acc + (size_t)A.slots * RW, lds, twl, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -1233,7 +1238,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
 // one after another in the workgroup's private slots.  Each VP writes its
 // own scores, so no reduction follows.  Items come from a queue (a device
 // counter), longest first; a workgroup leaves when the queue is exhausted.
-template <int LOGN, int NQ, int OCC>
+template <int LOGN, int NQ, int OCC, int DIG = 5>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void k_infer_batch(
     Tabs T, IBatchArgs B) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[xp_words<LOGN, false>()];
@@ -1256,7 +1261,7 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(OC
 #pragma unroll 1
     for (uint32_t smp = s0; smp < s1; ++smp) {
       // single transforms: with pairs the queue state next to them spills registers
-      vp_one<LOGN, NQ, false>(T, J.args, smp, I.ram, I.lab, acc, acc + slot_words, lds, twl, t);
+      vp_one<LOGN, NQ, false, DIG>(T, J.args, smp, I.ram, I.lab, acc, acc + slot_words, lds, twl, t);
       __syncthreads();
     }
   }
@@ -1466,6 +1471,35 @@ static hipError_t for_rect(uint64_t count, F&& f) {
     }                                                                                  \
   } while (0)
 
+// The gadget of the RGSW a launch reads, as DG (digits per prime): 5 (6-bit
+// digits) on any ring, 2 (15-bit digits) on rings of two or more primes; the
+// 2-digit kernels are built for those rings only.
+#define HW_DISPATCH_G(logN, nq, dig, ...)                                                     \
+  do {                                                                                        \
+    if (dig == 5) {                                                                           \
+      constexpr int DG = 5;                                                                   \
+      HW_DISPATCH(logN, nq, __VA_ARGS__);                                                     \
+    } else if (dig == 2 && nq >= 2) {                                                         \
+      constexpr int DG = 2;                                                                   \
+      HW_DISPATCH(logN, nq, if constexpr (NQ >= 2) { __VA_ARGS__; } else return hipErrorInvalidValue;); \
+    } else {                                                                                  \
+      return hipErrorInvalidValue;                                                            \
+    }                                                                                         \
+  } while (0)
+
+#define HW_DISPATCH_GOCC(logN, nq, occ, dig, ...)                                             \
+  do {                                                                                        \
+    if (dig == 5) {                                                                           \
+      constexpr int DG = 5;                                                                   \
+      HW_DISPATCH_OCC(logN, nq, occ, __VA_ARGS__);                                            \
+    } else if (dig == 2 && nq >= 2) {                                                         \
+      constexpr int DG = 2;                                                                   \
+      HW_DISPATCH_OCC(logN, nq, occ, if constexpr (NQ >= 2) { __VA_ARGS__; } else return hipErrorInvalidValue;); \
+    } else {                                                                                  \
+      return hipErrorInvalidValue;                                                            \
+    }                                                                                         \
+  } while (0)
+
 hipError_t launch_keygen(uint32_t N, uint64_t seed, int32_t* sk, hipStream_t st) {
   hipLaunchKernelGGL(k_keygen, dim3((N + 255) / 256), dim3(256), 0, st, N, seed, sk);
   return hipGetLastError();
@@ -1488,44 +1522,29 @@ hipError_t launch_sk_hat(int logN, int nq, const Tabs& T, const int32_t* sk, uin
   return hipGetLastError();
 }
 
-// RGSW with the key-switched bootstrapping key's gadget: 2 digits of
-// A.log_base bits per prime (2 rows per workgroup)
-hipError_t launch_enc_rgsw_g2(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
-                              hipStream_t st) {
-  const size_t rg = (size_t)2 * 2 * nq * 2 * nq * ((size_t)1 << logN);
-  const uint32_t rows = 2 * 2 * nq;
+hipError_t launch_enc_rgsw(int logN, int nq, int dig, const Tabs& T, const Cdt& cdt, const EncArgs& A,
+                           uint64_t count, int rows_per_wg, hipStream_t st) {
+  const size_t rg = (size_t)2 * dig * nq * 2 * nq * ((size_t)1 << logN);
+  const uint32_t rows = 2 * dig * nq;
+  if (rows_per_wg < 1 || rows % rows_per_wg) return hipErrorInvalidValue;
   return for_rect(count, [&](uint64_t off, dim3 g) -> hipError_t {
     EncArgs B = A;
     B.bits = A.bits + off;
     B.out = A.out + off * rg;
     B.ct0 = A.ct0 + off;
-    HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ, 2, 2>), dim3(rows / 2, g.x, g.y),
-                                              dim3(Geo<LN>::T), 0, st, T, cdt, B));
-    return hipGetLastError();
-  });
-}
-
-hipError_t launch_enc_rgsw(int logN, int nq, const Tabs& T, const Cdt& cdt, const EncArgs& A, uint64_t count,
-                           int rows_per_wg, hipStream_t st) {
-  const size_t rg = (size_t)2 * 5 * nq * 2 * nq * ((size_t)1 << logN);
-  const uint32_t rows = 2 * 5 * nq;
-  return for_rect(count, [&](uint64_t off, dim3 g) -> hipError_t {
-    EncArgs B = A;
-    B.bits = A.bits + off;
-    B.out = A.out + off * rg;
-    B.ct0 = A.ct0 + off;
+    const dim3 grid(rows / rows_per_wg, g.x, g.y);
     switch (rows_per_wg) {
       case 1:
-        HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ, 1>), dim3(rows, g.x, g.y), dim3(Geo<LN>::T),
-                                                  0, st, T, cdt, B));
+        HW_DISPATCH_G(logN, nq, dig, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ, 1, DG>), grid, dim3(Geo<LN>::T), 0, st,
+                                                         T, cdt, B));
         break;
       case 2:
-        HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ, 2>), dim3(rows / 2, g.x, g.y),
-                                                  dim3(Geo<LN>::T), 0, st, T, cdt, B));
+        HW_DISPATCH_G(logN, nq, dig, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ, 2, DG>), grid, dim3(Geo<LN>::T), 0, st,
+                                                         T, cdt, B));
         break;
       case 5:
-        HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ, 5>), dim3(rows / 5, g.x, g.y),
-                                                  dim3(Geo<LN>::T), 0, st, T, cdt, B));
+        if (dig != 5) return hipErrorInvalidValue;
+        HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_enc_rgsw<LN, NQ, 5>), grid, dim3(Geo<LN>::T), 0, st, T, cdt, B));
         break;
       default:
         return hipErrorInvalidValue;
@@ -1575,10 +1594,10 @@ hipError_t launch_dec_lwe(int logN, int nq, const Tabs& T, const CrtTab& K, cons
   return hipSuccess;
 }
 
-hipError_t launch_rgsw_export(int logN, int nq, const Tabs& T, const uint32_t* rgsw, uint64_t count,
+hipError_t launch_rgsw_export(int logN, int nq, int dig, const Tabs& T, const uint32_t* rgsw, uint64_t count,
                               uint32_t* out, hipStream_t st) {
   const size_t N = 1u << logN;
-  const uint64_t polys = count * 2 * 5 * nq * 2;
+  const uint64_t polys = count * 2 * dig * nq * 2;
   return for_rect(polys, [&](uint64_t off, dim3 g) -> hipError_t {
     HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_rgsw_export<LN, NQ>), g, dim3(Geo<LN>::T), 0, st, T,
                                               rgsw + off * nq * N, out + off * nq * N));
@@ -1598,13 +1617,13 @@ hipError_t launch_ntt(int logN, int nq, const Tabs& T, uint32_t* polys, uint64_t
   });
 }
 
-hipError_t launch_xp(int logN, int nq, const Tabs& T, const uint32_t* rgsw, const uint32_t* in, uint64_t count,
-                     uint32_t* out, hipStream_t st) {
+hipError_t launch_xp(int logN, int nq, int dig, const Tabs& T, const uint32_t* rgsw, const uint32_t* in,
+                     uint64_t count, uint32_t* out, hipStream_t st) {
   const size_t N = 1u << logN;
-  const uint64_t rw = 2ull * nq * N, gw = 2ull * 5 * nq * rw;
+  const uint64_t rw = 2ull * nq * N, gw = 2ull * dig * nq * rw;
   return for_rect(count, [&](uint64_t off, dim3 g) -> hipError_t {
-    HW_DISPATCH(logN, nq, hipLaunchKernelGGL((k_xp<LN, NQ>), g, dim3(Geo<LN>::T), 0, st, T, rgsw + off * gw,
-                                              in + off * rw, out + off * rw, gw));
+    HW_DISPATCH_G(logN, nq, dig, hipLaunchKernelGGL((k_xp<LN, NQ, DG>), g, dim3(Geo<LN>::T), 0, st, T, rgsw + off * gw,
+                                                     in + off * rw, out + off * rw, gw));
     return hipGetLastError();
   });
 }
@@ -1615,51 +1634,52 @@ hipError_t launch_perm(uint32_t s, uint64_t seed, uint32_t* pi, hipStream_t st) 
   return hipGetLastError();
 }
 
-hipError_t launch_train(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st) {
+hipError_t launch_train(int logN, int nq, int dig, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st) {
   const uint64_t G = (uint64_t)A.nram * A.nsub;
   if (G == 0) return hipSuccess;
   if (G > (1u << 22)) return hipErrorInvalidValue;
   const dim3 grid = A.map == 0 ? dim3(A.nram, A.nsub) : dim3((uint32_t)((G + 7) / 8 * 8));
-  HW_DISPATCH_OCC(logN, nq, occ,
-                  hipLaunchKernelGGL((k_train<LN, NQ, OC>), grid, dim3(Geo<LN>::T), 0, st, T, A));
+  HW_DISPATCH_GOCC(logN, nq, occ, dig,
+                   hipLaunchKernelGGL((k_train<LN, NQ, OC, DG>), grid, dim3(Geo<LN>::T), 0, st, T, A));
   return hipGetLastError();
 }
 
-hipError_t launch_train_level(int logN, int nq, const Tabs& T, const TrainArgs& A, int occ, hipStream_t st) {
+hipError_t launch_train_level(int logN, int nq, int dig, const Tabs& T, const TrainArgs& A, int occ,
+                              hipStream_t st) {
   const uint64_t G = (uint64_t)A.nram * A.nsub * A.smax;
   if (G == 0) return hipSuccess;
   if (G > (1ull << 30)) return hipErrorInvalidValue;
   const dim3 grid((uint32_t)((G + 7) / 8 * 8));
-  HW_DISPATCH_OCC(logN, nq, occ,
-                  hipLaunchKernelGGL((k_train_level<LN, NQ, OC>), grid, dim3(Geo<LN>::T), 0, st, T, A));
+  HW_DISPATCH_GOCC(logN, nq, occ, dig,
+                   hipLaunchKernelGGL((k_train_level<LN, NQ, OC, DG>), grid, dim3(Geo<LN>::T), 0, st, T, A));
   return hipGetLastError();
 }
 
-template <int LN, int NQ, int OC>
+template <int LN, int NQ, int OC, int DG>
 static hipError_t batch_grid_t(uint32_t* grid) {
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_train_batch<LN, NQ, OC>, Geo<LN>::T,
-                                                     0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_train_batch<LN, NQ, OC, DG>,
+                                                     Geo<LN>::T, 0);
   if (e != hipSuccess) return e;
   *grid = (uint32_t)(cus * (per_cu > 0 ? per_cu : 1));
   return hipSuccess;
 }
 
-hipError_t batch_grid(int logN, int nq, int occ, uint32_t* grid) {
-  HW_DISPATCH_OCC(logN, nq, occ, return batch_grid_t<LN, NQ, OC>(grid));
+hipError_t batch_grid(int logN, int nq, int dig, int occ, uint32_t* grid) {
+  HW_DISPATCH_GOCC(logN, nq, occ, dig, return batch_grid_t<LN, NQ, OC, DG>(grid));
   return hipSuccess;
 }
 
-hipError_t launch_train_batch(int logN, int nq, const Tabs& T, const BatchArgs& A, uint32_t grid, int occ,
+hipError_t launch_train_batch(int logN, int nq, int dig, const Tabs& T, const BatchArgs& A, uint32_t grid, int occ,
                               hipStream_t st) {
   if (grid > A.nitems) grid = A.nitems;
   if (grid == 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, A.counter, 1u);
-  HW_DISPATCH_OCC(logN, nq, occ,
-                  hipLaunchKernelGGL((k_train_batch<LN, NQ, OC>), dim3(grid), dim3(Geo<LN>::T), 0, st, T, A));
+  HW_DISPATCH_GOCC(logN, nq, occ, dig,
+                   hipLaunchKernelGGL((k_train_batch<LN, NQ, OC, DG>), dim3(grid), dim3(Geo<LN>::T), 0, st, T, A));
   return hipGetLastError();
 }
 
@@ -1689,42 +1709,42 @@ hipError_t launch_row_pack(const Tabs& T, const RowPackArgs& A, hipStream_t st) 
   return hipGetLastError();
 }
 
-hipError_t launch_infer(int logN, int nq, const Tabs& T, const InferArgs& A, int occ, hipStream_t st) {
+hipError_t launch_infer(int logN, int nq, int dig, const Tabs& T, const InferArgs& A, int occ, hipStream_t st) {
   if (A.rpr == 0) return hipErrorInvalidValue;
   const uint64_t G = (uint64_t)A.k0 * A.nlab * A.nsub;
   if (G == 0) return hipSuccess;
   if (G > (1u << 22)) return hipErrorInvalidValue;
   const dim3 grid = A.map == 0 ? dim3(A.k0, A.nlab, A.nsub) : dim3((uint32_t)((G + 7) / 8 * 8));
-  HW_DISPATCH_OCC(logN, nq, occ,
-                  hipLaunchKernelGGL((k_infer<LN, NQ, OC>), grid, dim3(Geo<LN>::T), 0, st, T, A));
+  HW_DISPATCH_GOCC(logN, nq, occ, dig,
+                   hipLaunchKernelGGL((k_infer<LN, NQ, OC, DG>), grid, dim3(Geo<LN>::T), 0, st, T, A));
   return hipGetLastError();
 }
 
-template <int LN, int NQ, int OC>
+template <int LN, int NQ, int OC, int DG>
 static hipError_t infer_batch_grid_t(uint32_t* grid) {
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_infer_batch<LN, NQ, OC>, Geo<LN>::T,
-                                                     0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_infer_batch<LN, NQ, OC, DG>,
+                                                     Geo<LN>::T, 0);
   if (e != hipSuccess) return e;
   *grid = (uint32_t)(cus * (per_cu > 0 ? per_cu : 1));
   return hipSuccess;
 }
 
-hipError_t infer_batch_grid(int logN, int nq, int occ, uint32_t* grid) {
-  HW_DISPATCH_OCC(logN, nq, occ, return infer_batch_grid_t<LN, NQ, OC>(grid));
+hipError_t infer_batch_grid(int logN, int nq, int dig, int occ, uint32_t* grid) {
+  HW_DISPATCH_GOCC(logN, nq, occ, dig, return infer_batch_grid_t<LN, NQ, OC, DG>(grid));
   return hipSuccess;
 }
 
-hipError_t launch_infer_batch(int logN, int nq, const Tabs& T, const IBatchArgs& B, uint32_t grid, int occ,
+hipError_t launch_infer_batch(int logN, int nq, int dig, const Tabs& T, const IBatchArgs& B, uint32_t grid, int occ,
                               hipStream_t st) {
   if (grid > B.nitems) grid = B.nitems;
   if (grid == 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, B.counter, 1u);
-  HW_DISPATCH_OCC(logN, nq, occ,
-                  hipLaunchKernelGGL((k_infer_batch<LN, NQ, OC>), dim3(grid), dim3(Geo<LN>::T), 0, st, T, B));
+  HW_DISPATCH_GOCC(logN, nq, occ, dig,
+                   hipLaunchKernelGGL((k_infer_batch<LN, NQ, OC, DG>), dim3(grid), dim3(Geo<LN>::T), 0, st, T, B));
   return hipGetLastError();
 }
 

@@ -166,7 +166,8 @@ __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(3,
 
 constexpr uint32_t KS_DIGITS = 6;  // balanced base-16 digits of the top 24 bits
 // gadget of the key-switched bootstrapping key's RGSW on rings of two or more
-// primes: 2 balanced digits of 15 bits per prime (exact for primes below 2^30)
+// primes: 2 balanced digits of 15 bits per prime (exact for primes below 2^30;
+// the digit size of the paper's HE1 TFHE parameter set, Sec. 4)
 constexpr int BSK_DIG = 2, BSK_LB = 15;
 
 // round(2^32 x / Q) mod 2^32 (half up) of x in [0, Q) with residues r
@@ -377,15 +378,14 @@ struct Pbs {
   size_t lw;        // words of an LWE ciphertext
 };
 
-// the key-switched bootstrapping key's RGSW use the coarser gadget on rings of
-// two or more primes; a one-prime ring's 30-bit modulus leaves no room for its
-// noise, so there they use the training gadget
-bool bsk_coarse(const hw_ctx* c) { return c->prm.nq >= 2; }
+// digits per prime of a bootstrapping key's RGSW: the key-switched key's use
+// the coarser gadget on rings of two or more primes (a one-prime ring's 30-bit
+// modulus leaves no room for its noise, so there they use the context's); the
+// ring key's use the context's gadget, as hw_encrypt_rgsw_bits makes them
+uint32_t bsk_digits(const hw_ctx* c, bool ks) { return ks && c->prm.nq >= 2 ? hw::BSK_DIG : c->prm.digits; }
 
-// words of one RGSW of the key-switched bootstrapping key
-size_t bsk_rgsw_words(const hw_ctx* c) {
-  return bsk_coarse(c) ? (size_t)2 * hw::BSK_DIG * c->prm.nq * rlwe_words(c) : rgsw_words(c);
-}
+// words of one RGSW of a bootstrapping key
+size_t bsk_rgsw_words(const hw_ctx* c, bool ks) { return (size_t)2 * bsk_digits(c, ks) * c->prm.nq * rlwe_words(c); }
 
 // columns of the key switch's contraction for an LWE key of n coefficients:
 // four signed bytes of each of the n + 1 words, padded to 64
@@ -464,16 +464,17 @@ hipError_t pbs(const Pbs& B, uint64_t count, const uint32_t* in, uint32_t* out, 
   A.ms = B.ms;
   A.slots = B.slots;
   A.out = out;
-  A.rgsw_words = B.ksk ? bsk_rgsw_words(c) : rgsw_words(c);
+  A.rgsw_words = bsk_rgsw_words(c, B.ksk != nullptr);
   A.count = count;
   A.n = B.n;
   A.binary = B.ksk != nullptr;
   for (uint32_t i = 0; i < nq; ++i) A.v[i] = res_of(V, c->tabs.pt[i].q);
   const dim3 g((uint32_t)std::min<uint64_t>(count, 65535), (uint32_t)((count + 65534) / 65535));
-  if (B.ksk && bsk_coarse(c))
-    PBS_DISPATCH(c->logN, nq,
-                 hipLaunchKernelGGL((hw::k_pbs_rotate<LN, NQ, hw::BSK_DIG, hw::BSK_LB>), g, dim3(hw::Geo<LN>::T), 0,
-                                    B.st, c->tabs, A));
+  if (bsk_digits(c, B.ksk != nullptr) == hw::BSK_DIG)
+    PBS_DISPATCH(c->logN, nq, if constexpr (NQ >= 2) {
+      hipLaunchKernelGGL((hw::k_pbs_rotate<LN, NQ, hw::BSK_DIG, hw::BSK_LB>), g, dim3(hw::Geo<LN>::T), 0, B.st,
+                         c->tabs, A);
+    } else return hipErrorInvalidValue;);
   else
     PBS_DISPATCH(c->logN, nq,
                  hipLaunchKernelGGL((hw::k_pbs_rotate<LN, NQ, 5, 6>), g, dim3(hw::Geo<LN>::T), 0, B.st, c->tabs, A));
@@ -565,7 +566,7 @@ extern "C" hw_status hw_pbs_keygen(hw_ctx* c, const int32_t* sk, uint64_t seed, 
 extern "C" hw_status hw_pbs_ks_sizes(const hw_ctx* c, uint32_t n, uint64_t* bsk_bytes, uint64_t* ksk_bytes) {
   if (!c || !bsk_bytes || !ksk_bytes) return fail(HW_EINVAL, "null argument");
   if (n < 1 || n > KS_MAX_N) return fail(HW_EINVAL, "n = %u out of range [1, %u]", n, KS_MAX_N);
-  *bsk_bytes = (uint64_t)n * bsk_rgsw_words(c) * 4;
+  *bsk_bytes = (uint64_t)n * bsk_rgsw_words(c, true) * 4;
   *ksk_bytes = (uint64_t)ks_cols(n) * c->prm.N * hw::KS_DIGITS;
   return ok();
 }
@@ -577,7 +578,7 @@ extern "C" hw_status hw_pbs_ks_keygen(hw_ctx* c, const int32_t* sk, uint64_t see
   if (n < 1 || n > KS_MAX_N) return fail(HW_EINVAL, "n = %u out of range [1, %u]", n, KS_MAX_N);
   HIP_TRY(hw::launch_lwe_keygen(n, seed, lwe_key, st));
   // RGSW(s1_i) with the bootstrapping key's gadget, ciphertexts 0..n-1 of stream seed
-  if (bsk_coarse(c)) {
+  if (bsk_digits(c, true) != c->prm.digits) {
     HIP_TRY(hw::launch_sk_hat(c->logN, c->prm.nq, c->tabs, sk, c->d_skhat, st));
     hw::EncArgs A{};
     A.sk = sk;
@@ -587,7 +588,7 @@ extern "C" hw_status hw_pbs_ks_keygen(hw_ctx* c, const int32_t* sk, uint64_t see
     A.seed = seed;
     A.ct0 = 0;
     A.log_base = hw::BSK_LB;
-    HIP_TRY(hw::launch_enc_rgsw_g2(c->logN, c->prm.nq, c->tabs, c->cdt, A, n, st));
+    HIP_TRY(hw::launch_enc_rgsw(c->logN, c->prm.nq, hw::BSK_DIG, c->tabs, c->cdt, A, n, 2, st));
   } else {
     CHECK(hw_encrypt_rgsw_bits(c, sk, lwe_key, n, seed, 0, bsk, st));
   }

@@ -214,9 +214,11 @@ def permutation(sh: Shape) -> np.ndarray:
 class Context:
     """One parameter set on one device (hw_ctx)."""
 
-    def __init__(self, N: int, nq: int, p: int, primes=None, sigma: float = 3.2, device: int = 0):
+    def __init__(self, N: int, nq: int, p: int, primes=None, sigma: float = 3.2, device: int = 0,
+                 log_base: int = 6, digits: int = 5):
+        """(log_base, digits): the RGSW gadget, (6, 5) or, with nq >= 2, (15, 2)"""
         prm = Params()
-        prm.N, prm.nq, prm.log_base, prm.digits, prm.sigma, prm.plain_mod = N, nq, 6, 5, sigma, p
+        prm.N, prm.nq, prm.log_base, prm.digits, prm.sigma, prm.plain_mod = N, nq, log_base, digits, sigma, p
         for i, q in enumerate(primes or []):
             prm.primes[i] = q
         h = C.c_void_p()
@@ -225,6 +227,7 @@ class Context:
         out = Params()
         _check(_lib.hw_ctx_params(h, C.byref(out)))
         self.N, self.nq, self.p, self.device = N, nq, p, device
+        self.log_base, self.digits = log_base, digits
         self.primes = [int(out.primes[i]) for i in range(nq)]
         k, r, g, w = _u64(), _u64(), _u64(), _u64()
         _check(_lib.hw_sizes(h, C.byref(k), C.byref(r), C.byref(g), C.byref(w)))

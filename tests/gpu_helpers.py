@@ -41,7 +41,7 @@ class Pair:
     """Seeded WiSARD workload on both sides.  Seeds: key, input-bit
     encryption, label-bit encryption, permutation."""
 
-    def __init__(self, N, nq, p, s, l, a, X, y, seed=7, layout=0):
+    def __init__(self, N, nq, p, s, l, a, X, y, seed=7, layout=0, gadget=(6, 5)):
         from paper_2403_20190_amd import hwisard as HW
         self.HW = HW
         self.N, self.nq, self.p, self.s, self.l, self.a = N, nq, p, s, l, a
@@ -49,8 +49,8 @@ class Pair:
         self.n = len(self.X)
         self.L = O.ceil_log2(l)
         self.seed_key, self.seed_x, self.seed_y, self.seed_perm = seed * 4 + 1, seed * 4 + 2, seed * 4 + 3, seed * 4 + 4
-        self.ctx = HW.Context(N, nq, p)
-        self.orc = O.Ctx(N, nq, p)
+        self.ctx = HW.Context(N, nq, p, log_base=gadget[0], digits=gadget[1])
+        self.orc = O.Ctx(N, nq, p, log_base=gadget[0], digits=gadget[1])
         self.layout = layout
         self.shape = HW.shape(s, l, a, self.seed_perm, layout)
         self.k0, self.k1, _ = self.ctx.dims(self.shape)

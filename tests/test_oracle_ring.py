@@ -119,3 +119,22 @@ def test_decomposition_identity(N, nq):
         centered = np.where(v > (q - 1) // 2, v - q, v)
         recon = sum(dig[i, j] * (64 ** j) for j in range(5))
         assert np.array_equal(recon, centered)
+
+
+@pytest.mark.parametrize("N,nq", [(2048, 2), (4096, 3)])
+def test_decomposition_identity_coarse_gadget(N, nq):
+    """2 balanced digits of 15 bits per prime (the gadget offered on rings of
+    two or more primes): digit bounds and exact reconstruction of the
+    centred residue, extreme residues included"""
+    c = O.Ctx(N, nq, 64, log_base=15, digits=2)
+    rng = np.random.default_rng(10 + nq)
+    poly = np.stack([rng.integers(0, q, N) for q in c.primes]).astype(np.uint32)
+    for i, q in enumerate(c.primes):
+        poly[i, :6] = [0, 1, q - 1, (q - 1) // 2, (q + 1) // 2, q // 3]
+    dig = c.decompose(poly).reshape(nq, 2, N).astype(np.int64)
+    assert dig[:, 0].min() >= -(1 << 14) and dig[:, 0].max() < (1 << 14)
+    assert np.abs(dig[:, 1]).max() <= (1 << 14)
+    for i, q in enumerate(c.primes):
+        v = poly[i].astype(np.int64)
+        centered = np.where(v > (q - 1) // 2, v - q, v)
+        assert np.array_equal(dig[i, 0] + dig[i, 1] * (1 << 15), centered)

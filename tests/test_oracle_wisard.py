@@ -76,8 +76,8 @@ class Micro:
     """Small encrypted WiSARD: exercises a ragged last tuple, an encrypted
     CDEMUX/CMUX tree level (z > L) and cleartext label bits in the chain."""
 
-    def __init__(self, N, s, l, a, n, p=64, nq=1, seed=0, layout=0):
-        self.c = O.Ctx(N, nq, p)
+    def __init__(self, N, s, l, a, n, p=64, nq=1, seed=0, layout=0, gadget=(6, 5)):
+        self.c = O.Ctx(N, nq, p, log_base=gadget[0], digits=gadget[1])
         self.s, self.l, self.a, self.n = s, l, a, n
         self.layout = layout
         self.L = O.ceil_log2(l)
@@ -125,6 +125,31 @@ def test_encrypted_training_matches_integer_wisard(cfg):
         for d in range(m.k1):
             mx, _ = m.c.noise_rlwe(m.sk, H[j, d], want[j, d].astype(np.uint64))
             assert mx * 16 < m.c.delta / 2
+
+
+@pytest.mark.parametrize("cfg", [CONFIGS[0], CONFIGS[3], CONFIGS[5]])
+def test_encrypted_training_and_inference_coarse_gadget(cfg):
+    """the same on two primes with RGSW of 2 digits of 15 bits per prime:
+    decrypted cells equal integer WiSARD's counts with the noise margin of
+    the default gadget's test, and PD-act predictions equal Alg. 2's"""
+    m = Micro(**cfg, nq=2, gadget=(15, 2))
+    assert m.c.D == 4 and m.xr.shape[-1] == m.c.rgsw_words
+    H = m.train()
+    W = P.train_integer(m.X, m.y, m.l, m.a, m.pi)
+    want = P.expected_model_cells(W, m.s, m.l, m.a, m.c.N)
+    got = np.stack([[m.c.dec_rlwe(m.sk, H[j, d]) for d in range(m.k1)] for j in range(m.k0)])
+    assert np.array_equal(got.astype(np.int64), want)
+    for j in range(m.k0):
+        for d in range(m.k1):
+            mx, _ = m.c.noise_rlwe(m.sk, H[j, d], want[j, d].astype(np.uint64))
+            assert mx * 16 < m.c.delta / 2
+    Xt, _ = synth.prototype_bits(50, 3, m.s, m.l, flip=0.3)
+    for t in range(3):
+        xr = m.c.enc_rgsw_bits(m.sk, Xt[t], 500 + t, 0)
+        cells = np.array([[m.c.dec_lwe(m.sk, m.c.infer_one(m.s, m.l, m.a, m.pi, H, lambda k: xr[k], j, c))
+                           for j in range(m.k0)] for c in range(m.l)], np.int64)
+        assert np.array_equal(cells, P.ram_scores(W, Xt[t], m.a, m.pi))
+        assert P.pd_act_predict(cells, "log") == P.predict(W, Xt[t], m.a, m.pi, "log")
 
 
 @pytest.mark.parametrize("cfg", CONFIGS)

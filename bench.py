@@ -50,13 +50,28 @@ WORKLOADS = {
 KERNEL_SOURCES = ["hw_device.h", "hw_kernels.hip", "hw_internal.h"]
 
 
+def kernel_code_sha256() -> str:
+    """sha256 of the training kernel's sources (KERNEL_SOURCES, in that
+    order) with comments removed and whitespace runs collapsed: it changes
+    when their code does, not when a comment does"""
+    import hashlib
+    import re
+    sha = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        text = open(os.path.join(ROOT, "paper_2403_20190_amd", "csrc", f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        sha.update(" ".join(text.split()).encode())
+        sha.update(b"\0")
+    return sha.hexdigest()
+
+
 def measured_traffic(schedule: str | None):
     """HBM bytes (read + write) per training call (k_train, plus the
     k_train_level launches when the tree levels are staged) measured with
     rocprofv3 FETCH_SIZE / WRITE_SIZE (profiles/k_train_mnist_pmc.md) for the
-    schedule in use, or None when the kernel sources changed since (their
-    sha256 no longer matches)."""
-    import hashlib
+    schedule in use, or None when the kernel code changed since
+    (kernel_code_sha256 no longer matches)."""
     import re
     try:
         text = open(os.path.join(ROOT, "profiles", "k_train_mnist_pmc.md")).read()
@@ -64,13 +79,10 @@ def measured_traffic(schedule: str | None):
         return None
     kind = "staged" if schedule and "staged" in schedule else "fused"
     t = re.search(r"traffic_bytes_per_launch_%s:\s*(\d+)" % kind, text)
-    h = re.search(r"kernel_sources_sha256:\s*([0-9a-f]{64})", text)
+    h = re.search(r"kernel_code_sha256:\s*([0-9a-f]{64})", text)
     if not t or not h:
         return None
-    sha = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        sha.update(open(os.path.join(ROOT, "paper_2403_20190_amd", "csrc", f), "rb").read())
-    return int(t.group(1)) if sha.hexdigest() == h.group(1) else None
+    return int(t.group(1)) if kernel_code_sha256() == h.group(1) else None
 
 
 class Progress:

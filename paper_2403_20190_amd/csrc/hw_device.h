@@ -3,7 +3,8 @@
 // product (decompose -> NTT -> multiply-accumulate -> inverse NTT).
 //
 // Ring R_q = Z_q[X]/(X^N+1) (Sec. 2.1); external product of Sec. 2.5.1 with
-// an RNS gadget of base 2^6 and 5 digits per prime.
+// an RNS gadget of base 2^6 and 5 digits per prime, or (rings of two or more
+// primes) of base 2^15 and 2 digits.
 //
 // Thread mapping.  One workgroup of T = N/8 threads owns one polynomial at a
 // time; each thread keeps 8 coefficients in registers.  The NTT's log2 N
@@ -472,7 +473,8 @@ constexpr int32_t DIGIT_OFFSET = 32 * (1 + 64 + 4096 + 262144);
 // The same for any gadget of DIG balanced base-2^LB digits per prime: the
 // offset is 2^(LB-1) (1 + B + .. + B^(DIG-2)), the digits below the top one are
 // LB-bit fields of w, the top one is w >> (LB (DIG - 1)) (arithmetic).  The
-// training gadget is (5, 6); the key-switched bootstrapping key uses (2, 15).
+// default gadget is (5, 6); contexts on rings of two or more primes may use
+// (2, 15), which the key-switched bootstrapping key always uses there.
 template <int DIG, int LB>
 __host__ __device__ constexpr int32_t digit_offset() {
   int64_t o = 0, b = 1;
@@ -547,7 +549,7 @@ __device__ __forceinline__ void xp_finish(uint32_t (&ha)[8], uint32_t (&hb)[8], 
 }
 
 // DIG, LB: the RGSW's gadget, DIG balanced base-2^LB digits per prime (rows
-// side * DIG NQ + i DIG + j); the training gadget is the default
+// side * DIG NQ + i DIG + j); (5, 6) unless stated
 template <int LOGN, int NQ, bool PR = xp_pair<LOGN, NQ>(), int DIG = 5, int LB = 6>
 __device__ __forceinline__ void ext_prod(const uint32_t* __restrict__ xin, const uint32_t* __restrict__ C,
                                       const Tabs& T, uint32_t* lds, uint2* twl, uint32_t& xc, uint32_t t,

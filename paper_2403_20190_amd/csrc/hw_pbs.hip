@@ -103,8 +103,8 @@ __device__ __forceinline__ void pbs_rot_diff(const Tabs& T, const uint32_t* __re
 }
 
 // blind rotation and extraction: one workgroup per ciphertext; DIG, LB: the
-// bootstrapping key's gadget (the ring key's is the training gadget, the
-// key-switched key's 2 digits of 15 bits)
+// bootstrapping key's gadget (the ring key's is the context's, the
+// key-switched key's 2 digits of 15 bits on rings of two or more primes)
 template <int LOGN, int NQ, int DIG, int LB>
 __global__ __launch_bounds__(Geo<LOGN>::T) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_pbs_rotate(
     Tabs T, RotArgs A) {

@@ -533,7 +533,7 @@ typedef struct {
  * samples) items, longest first, each workgroup running the Vertical Packing
  * of its item's samples one after another in private slots; per-class sums
  * follow for the jobs that ask for them.  A launch is compiled for one ring
- * degree and prime count, so it never spans two contexts: the contexts'
+ * degree, prime count and RGSW gadget, so it never spans two contexts: the contexts'
  * launches follow one another on `stream`.  An inference job therefore sees
  * every training job of its context in the same batch.  Every job's result
  * is bit-identical to the single-job call on it.  Training jobs on the same

@@ -5,9 +5,9 @@
 // Per context, in the order of the context list: its training jobs run as one
 // persistent launch (hw_batch_train), then its inference jobs as one
 // persistent launch of k_infer_batch over a queue of (job, RAM, label, piece)
-// items.  A kernel is compiled for one ring degree and prime count, so one
-// launch never spans two contexts; the contexts' launches follow each other
-// on the caller's stream.
+// items.  A kernel is compiled for one ring degree, prime count and RGSW
+// gadget, so one launch never spans two contexts; the contexts' launches
+// follow each other on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

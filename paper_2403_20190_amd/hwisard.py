@@ -495,10 +495,11 @@ class Engine:
 
     def __init__(self, N: int, nq: int, p: int, sk, slots: int = 4, chunk: int = 8, max_s: int = 4096,
                  max_cells: int = 4096, arena_bytes: int = 32 << 30, device: int = 0, sigma: float = 3.2,
-                 order: str = "fifo"):
-        """order: "fifo" (submission order) or "shortest" (least remaining work first)"""
+                 order: str = "fifo", log_base: int = 6, digits: int = 5):
+        """order: "fifo" (submission order) or "shortest" (least remaining work
+        first); (log_base, digits): the RGSW gadget, as for Context"""
         prm = Params()
-        prm.N, prm.nq, prm.log_base, prm.digits, prm.sigma, prm.plain_mod = N, nq, 6, 5, sigma, p
+        prm.N, prm.nq, prm.log_base, prm.digits, prm.sigma, prm.plain_mod = N, nq, log_base, digits, sigma, p
         if order not in ("fifo", "shortest"):
             raise HwError(HW_EINVAL, "order must be 'fifo' or 'shortest'")
         cfg = EngineConfig(slots, chunk, max_s, max_cells, arena_bytes, 0 if order == "fifo" else 1, 0)

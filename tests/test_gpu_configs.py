@@ -98,7 +98,9 @@ def test_pks_ham_params_bit_exact_and_2744_scores():
 # serving engine at the served parameter set
 # --------------------------------------------------------------------------
 
-def test_engine_served_params_wisconsin_and_mnist():
+@pytest.mark.parametrize("gadget", [(6, 5), (15, 2)])
+def test_engine_served_params_wisconsin_and_mnist(gadget):
+    """with the default RGSW gadget and with 2 digits of 15 bits per prime"""
     import torch
     from paper_2403_20190_amd import hwisard as HW
     CL = client()
@@ -111,9 +113,10 @@ def test_engine_served_params_wisconsin_and_mnist():
     bits_m = CL.thermometer(CL.quantize_u8(Xm, 3), 3)
     shapes = [dict(bits=bits_w, y=yw, l=2, a=8, seed=71), dict(bits=bits_m, y=ym, l=10, a=12, seed=72)]
     sk = torch.zeros(N, dtype=torch.int32, device="cuda")
-    ctx = HW.Context(N, nq, p)
+    ctx = HW.Context(N, nq, p, log_base=gadget[0], digits=gadget[1])
     ctx.keygen(81, sk)
-    eng = HW.Engine(N, nq, p, sk, slots=3, chunk=2, max_s=2352, max_cells=2048, arena_bytes=24 << 30)
+    eng = HW.Engine(N, nq, p, sk, slots=3, chunk=2, max_s=2352, max_cells=2048, arena_bytes=24 << 30,
+                    log_base=gadget[0], digits=gadget[1])
     models, jobs = [], []
     for S in shapes:
         sh = HW.shape(S["bits"].shape[1], S["l"], S["a"], S["seed"])
@@ -137,7 +140,7 @@ def test_engine_served_params_wisconsin_and_mnist():
     assert eng.stats()["peak_inflight"] >= 2
     eng.close()
     # the direct path on the same ciphertexts, request by request, and Alg. 2 on the decrypted cells
-    orc = O.Ctx(N, nq, p)
+    orc = O.Ctx(N, nq, p, log_base=gadget[0], digits=gadget[1])
     sk_o = orc.keygen(81)
     for shp, S in enumerate(shapes):
         sh, Hm, k0, k1 = models[shp]
@@ -187,28 +190,30 @@ def test_engine_served_params_wisconsin_and_mnist():
 
 def test_batch_run_mixed_rings_and_kinds():
     from paper_2403_20190_amd import hwisard as HW
-    specs = [  # (N, nq, p, s, l, a, n, layout, counter)
-        (2048, 2, 1024, 60, 3, 11, 3, 0, True),    # z = 2 = L: the tree holds the label bits
-        (2048, 2, 1024, 40, 4, 8, 2, 1, False),
-        (4096, 3, 16384, 50, 7, 12, 2, 0, True),   # z = 3 = L, ragged last tuple (2 bits)
-        (4096, 3, 16384, 30, 2, 13, 2, 1, False),  # class-packed, z = 2 tree levels over tuple bits
+    G = (6, 5)
+    specs = [  # (N, nq, p, s, l, a, n, layout, counter, RGSW gadget)
+        (2048, 2, 1024, 60, 3, 11, 3, 0, True, G),    # z = 2 = L: the tree holds the label bits
+        (2048, 2, 1024, 40, 4, 8, 2, 1, False, G),
+        (4096, 3, 16384, 50, 7, 12, 2, 0, True, G),   # z = 3 = L, ragged last tuple (2 bits)
+        (4096, 3, 16384, 30, 2, 13, 2, 1, False, G),  # class-packed, z = 2 tree levels over tuple bits
+        (2048, 2, 1024, 36, 3, 12, 2, 0, True, (15, 2)),  # a third context: 2 digits of 15 bits
     ]
     ctxs = {}
     pairs = []
-    for k, (N, nq, p, s, l, a, n, layout, cnt) in enumerate(specs):
+    for k, (N, nq, p, s, l, a, n, layout, cnt, g) in enumerate(specs):
         X, y = synth.prototype_bits(40 + k, n + 1, s, l, flip=0.2)
-        pair = Pair(N, nq, p, s, l, a, X[:n], y[:n], seed=40 + k, layout=layout)
-        if (N, nq) in ctxs:  # one context and key per parameter set
-            first = ctxs[(N, nq)]
+        pair = Pair(N, nq, p, s, l, a, X[:n], y[:n], seed=40 + k, layout=layout, gadget=g)
+        if (N, nq, g) in ctxs:  # one context and key per parameter set
+            first = ctxs[(N, nq, g)]
             pair.ctx, pair.sk, pair.sk_o = first.ctx, first.sk, first.sk_o
         else:
-            ctxs[(N, nq)] = pair
-        pairs.append((pair, cnt, X[n:]))
+            ctxs[(N, nq, g)] = pair
+        pairs.append((pair, cnt, X[n:], g))
     order = list(ctxs)
     cl = [ctxs[k].ctx for k in order]
     jobs, bufs = [], []
-    for pair, cnt, Xt in pairs:
-        ci = order.index((pair.N, pair.nq))
+    for pair, cnt, Xt, g in pairs:
+        ci = order.index((pair.N, pair.nq, g))
         xr, yr = pair.encrypt_dev(), pair.encrypt_labels_dev()
         H = zeros_u32(pair.k0, pair.k1, 2, pair.nq, pair.N)
         C = zeros_u32(2, pair.nq, pair.N) if cnt else None
@@ -220,7 +225,7 @@ def test_batch_run_mixed_rings_and_kinds():
         jobs.append(dict(ctx=ci, kind="infer", shape=pair.shape, x=xt, n=1, model=H, scores=sc, sums=sums))
         bufs.append((xr, yr, H, C, xt, sc, sums))
     HW.batch_run(cl, jobs)
-    for (pair, cnt, Xt), (xr, yr, H, C, xt, sc, sums) in zip(pairs, bufs):
+    for (pair, cnt, Xt, _), (xr, yr, H, C, xt, sc, sums) in zip(pairs, bufs):
         H1 = zeros_u32(pair.k0, pair.k1, 2, pair.nq, pair.N)
         C1 = zeros_u32(2, pair.nq, pair.N) if cnt else None
         pair.ctx.train(pair.shape, xr, yr, pair.n, H1, C1)

@@ -409,7 +409,8 @@ def side_workload(args):
                                        "l U{2..10}), ring %d" % args.batched_ring}, "batched": r}
     else:
         r = served_full(dev, args.served_requests, args.served_max_size, args.served_loads or [],
-                        args.served_sat_rps, args.served_one_at_a_time, tuple(args.served_orders))
+                        args.served_sat_rps, args.served_one_at_a_time, tuple(args.served_orders),
+                        gadget=(6, 5) if args.gadget == "6x5" else (15, 2))
         line = {"metric": "served p50/p99 latency and throughput", "unit": "ms", "n_gpus": 1, "dtype": "u32",
                 "data": "synthetic", "config": {"workload": "Poisson train/infer requests, half Wisconsin- half "
                                                             "MNIST-shaped, N=2048 x 2 primes, p=2^16"}, "served": r}
@@ -456,8 +457,9 @@ def main():
     ap.add_argument("--fm-full", action="store_true",
                     help="wisconsin: FM-act of the whole model, then inference on it (minutes)")
     ap.add_argument("--gadget", default="6x5", choices=["6x5", "15x2"],
-                    help="RGSW gadget of the timed step: 5 digits of 6 bits per prime (default) or 2 of 15 bits "
-                         "(rings of two or more primes); the extras then skip the gadget leg")
+                    help="RGSW gadget of the timed step (or of the served engine with --workload served): 5 "
+                         "digits of 6 bits per prime (default) or 2 of 15 bits (rings of two or more primes); "
+                         "the extras then skip the gadget leg")
     ap.add_argument("--no-gadget-leg", action="store_true",
                     help="skip the step and inference with RGSW of 2 digits of 15 bits per prime")
     ap.add_argument("--no-batched", action="store_true")
@@ -1285,9 +1287,9 @@ def batched_pass(scale: float, dev, window_bytes: int = 96 << 30):
     return out
 
 
-def served_setup(dev, n_req: int, max_size: int, seed: int = 5):
-    """The served workload: one parameter set (N=2048, two primes, p=2^16)
-    and key; half Wisconsin-shaped (30 features, 2 classes 357/212, min-max +
+def served_setup(dev, n_req: int, max_size: int, seed: int = 5, gadget=(6, 5)):
+    """The served workload: one parameter set (N=2048, two primes, p=2^16;
+    RGSW gadget (log_base, digits)) and key; half Wisconsin-shaped (30 features, 2 classes 357/212, min-max +
     16-level thermometer = 480 bits, tuple 8), half MNIST-shaped models, 4
     resident models of each shape pre-trained with 64 samples; n_req
     requests, half train and half infer, sizes U{1..max_size}.  Returns
@@ -1300,7 +1302,7 @@ def served_setup(dev, n_req: int, max_size: int, seed: int = 5):
     from paper_2403_20190_amd import synth
     N, nq, p = 2048, 2, 1 << 16
     torch.cuda.empty_cache()
-    ctx = HW.Context(N, nq, p)
+    ctx = HW.Context(N, nq, p, log_base=gadget[0], digits=gadget[1])
     sk = torch.zeros(N, dtype=torch.int32, device=dev)
     ctx.keygen(202, sk)
     Xw, yw = synth.wisconsin_like(4)
@@ -1316,7 +1318,8 @@ def served_setup(dev, n_req: int, max_size: int, seed: int = 5):
             pre[(name, r)] = g.integers(0, len(bits), 64)
 
     def make_engine(order="fifo"):
-        eng = HW.Engine(N, nq, p, sk, slots=4, chunk=8, max_s=2352, max_cells=2048, arena_bytes=64 << 30, order=order)
+        eng = HW.Engine(N, nq, p, sk, slots=4, chunk=8, max_s=2352, max_cells=2048, arena_bytes=64 << 30, order=order,
+                        log_base=gadget[0], digits=gadget[1])
         jobs = []
         for name, (bits, y, l, a) in shapes.items():
             for r in range(4):
@@ -1419,7 +1422,7 @@ def served_pass(dev, n_req: int, max_size: int, load: float):
 
 
 def served_full(dev, n_req: int, max_size: int, loads, sat_rps: float | None, sequential: bool,
-                orders=("fifo",)) -> dict:
+                orders=("fifo",), gadget=(6, 5)) -> dict:
     """The served configuration at its stated size: 400 requests of U{1..500}
     samples.  Runs whichever parts are asked for (each can be its own
     process, so that one run stays within a time limit): the saturated run
@@ -1432,9 +1435,10 @@ def served_full(dev, n_req: int, max_size: int, loads, sat_rps: float | None, se
     import numpy as np
 
     from paper_2403_20190_amd import synth
-    ctx, make_engine, reqs = served_setup(dev, n_req, max_size)
+    ctx, make_engine, reqs = served_setup(dev, n_req, max_size, gadget=gadget)
     samples = sum(r["size"] for r in reqs)
     out = {"requests": n_req, "sizes": "U{1..%d}" % max_size, "samples": samples,
+           "gadget": "%d digits of %d bits per prime" % (gadget[1], gadget[0]),
            "mix": {"train": sum(r["kind"] == "train" for r in reqs), "mnist": sum(r["shape"] == "mnist" for r in reqs)}}
 
     def pct(x):

@@ -14,7 +14,8 @@ against the oracle's context of the same gadget:
   results;
 * a ring-key bootstrap with a key of that gadget;
 * PackingKeySwitching keeps its own gadget of 5 digits of 6 bits on such a
-  context (key rows and a packed RLWE)."""
+  context (key rows and a packed RLWE);
+* FM-act on such a context with a key-switched bootstrapping key."""
 import numpy as np
 import pytest
 
@@ -208,3 +209,37 @@ def test_packing_keeps_its_own_gadget():
     out = zeros_u32(1, 2, nq, N)
     ctx.pack_lwe(key, dev(lwes[None]), k, 1, out)
     assert np.array_equal(host_u32(out)[0], orc.pack_lwe(K_o, lwes))
+
+
+def test_fm_act_two_primes_bit_exact():
+    """FM-act on a context of that gadget: a key-switched bootstrapping key
+    (its RGSW in the context's gadget), PackingKeySwitching in its own
+    5 x 6 gadget, bit for bit against the oracle (2 RAMs of 4 cells, p = 8,
+    a 32-coefficient LWE key), and every activated cell decrypting to
+    [cell >= T]"""
+    N, T, n = 1024, 2, 32
+    rng = np.random.default_rng(31)
+    X = rng.integers(0, 2, (6, 2)).astype(np.uint8)
+    y = np.array([0, 1, 0, 0, 1, 1])
+    pair = Pair(N, 2, 8, 2, 2, 1, X, y, seed=19, gadget=G)
+    ctx, orc = pair.ctx, pair.orc
+    H = zeros_u32(pair.k0, pair.k1, 2, 2, N)
+    ctx.train(pair.shape, pair.encrypt_dev(), pair.encrypt_labels_dev(), pair.n, H, None)
+    Ho = pair.oracle_train(range(pair.k0))
+    assert np.array_equal(host_u32(H), Ho)
+    key = ctx.pbs_ks_keygen(pair.sk, 43, n)
+    ko = orc.pbs_ks_keygen(pair.sk_o, 43, n)
+    assert ko.gctx is orc  # the context's own gadget
+    pks = zeros_u32(ctx.pks_key_words)
+    ctx.pks_keygen(pair.sk, 9, pks)
+    K_o = orc.pks_keygen(pair.sk_o, 9)
+    out = zeros_u32(*H.shape)
+    ctx.fm_act(pair.shape, key, 0, pks, H, "ge", T, 3, out)
+    want = B.fm_act(orc, ko, n, K_o, Ho, B.fm_cells(N, 2, 1), T, 8)
+    got = host_u32(out)
+    assert np.array_equal(got, want)
+    W = P.train_integer(pair.X, pair.y, 2, 1, pair.pi)
+    cells = P.expected_model_cells(W, 2, 2, 1, N)
+    dec = [[B.decode(orc, pair.sk_o, orc.extract_lwe(want[j, r], k), 8) for k in range(4)]
+           for j in range(pair.k0) for r in range(pair.k1)]
+    assert dec == [[int(v >= T) for v in cells[j, r, :4]] for j in range(pair.k0) for r in range(pair.k1)]

@@ -133,6 +133,25 @@ static void build_cdt(double sigma, uint64_t T[42]) {
   T[41] = 1ull << 63;
 }
 
+// The guide of the CDT search (hw::Cdt::guide): entry b counts the T[j]
+// (j <= 40) at or below the first draw of bucket b, plus CDT_GUIDE_WIDE when
+// more than two T[j] fall inside the bucket, where two comparisons from that
+// count would not finish the search.
+static void build_cdt_guide(const uint64_t T[42], uint8_t G[hw::CDT_GUIDE_SIZE]) {
+  const int sh = 63 - (int)hw::CDT_GUIDE_BITS;
+  for (uint32_t b = 0; b < hw::CDT_GUIDE_SIZE; ++b) {
+    const uint64_t lo = (uint64_t)b << sh, hi = lo + ((1ull << sh) - 1);
+    uint32_t below = 0, inside = 0;
+    for (int j = 0; j <= 40; ++j) {
+      if (T[j] <= lo)
+        ++below;
+      else if (T[j] <= hi)
+        ++inside;
+    }
+    G[b] = (uint8_t)(below | (inside > 2 ? hw::CDT_GUIDE_WIDE : 0u));
+  }
+}
+
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
@@ -228,9 +247,16 @@ extern "C" hw_status hw_ctx_create(const hw_params* params, int device, hw_ctx**
   c->crt.half_hi = (uint64_t)((c->Q / 2) >> 64);
   c->crt.p = P.plain_mod;
   build_cdt(P.sigma, c->cdt.T);
+  uint8_t guide[hw::CDT_GUIDE_SIZE];
+  build_cdt_guide(c->cdt.T, guide);
 
-  hipError_t e = hipMalloc(&c->d_tables, host.size() * sizeof(uint2));
-  if (e == hipSuccess) e = hipMemcpy(c->d_tables, host.data(), host.size() * sizeof(uint2), hipMemcpyHostToDevice);
+  // the twiddle tables, then the CDT guide (at a 16-byte aligned offset: 3 nq N uint2)
+  const size_t tw_bytes = host.size() * sizeof(uint2);
+  hipError_t e = hipMalloc(&c->d_tables, tw_bytes + hw::CDT_GUIDE_SIZE);
+  if (e == hipSuccess) e = hipMemcpy(c->d_tables, host.data(), tw_bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(static_cast<char*>(c->d_tables) + tw_bytes, guide, hw::CDT_GUIDE_SIZE, hipMemcpyHostToDevice);
+  c->cdt.guide = reinterpret_cast<const uint8_t*>(static_cast<char*>(c->d_tables) + tw_bytes);
   if (e == hipSuccess) e = hipMalloc(&c->d_skhat, sizeof(uint32_t) * sk_hat_words(c));
   if (e != hipSuccess) {
     hw_ctx_destroy(c);

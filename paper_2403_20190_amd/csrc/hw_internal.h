@@ -18,7 +18,13 @@ struct CrtTab {
 
 struct Cdt {
   uint64_t T[42];
+  // guide of the search (CDT_GUIDE_SIZE bytes, device): entry b, for the
+  // draws r with r >> (63 - CDT_GUIDE_BITS) == b, holds the number of
+  // T[j] <= b 2^(63 - CDT_GUIDE_BITS) (j <= 40), plus CDT_GUIDE_WIDE when
+  // more than two T[j] fall inside that bucket of draws
+  const uint8_t* guide;
 };
+constexpr uint32_t CDT_GUIDE_BITS = 12, CDT_GUIDE_SIZE = 1u << CDT_GUIDE_BITS, CDT_GUIDE_WIDE = 0x80;
 
 struct EncArgs {
   const int32_t* sk;        // [N]

@@ -104,6 +104,22 @@ __device__ __forceinline__ int32_t cdt_sample(const uint64_t* T, uint64_t w) {
   return (k != 0 && (w & 1)) ? -k : k;
 }
 
+// The same sample through a guide (Cdt::guide): the draw's bucket b = r >>
+// (63 - CDT_GUIDE_BITS) starts the count at G[b], the number of T[j] <= b
+// 2^(63 - CDT_GUIDE_BITS); when at most two T[j] fall inside the bucket, two
+// comparisons finish it (T is non-decreasing and T[41] = 2^63 > r stops a
+// scan at 41), else (a few buckets at the top of the range) the six-step
+// search runs.  Equal to cdt_sample for every draw.
+__device__ __forceinline__ int32_t cdt_sample_guided(const uint64_t* T, const uint8_t* G, uint64_t w) {
+  const uint64_t r = w >> 1;
+  const uint32_t g = G[(uint32_t)(r >> (63 - CDT_GUIDE_BITS))];
+  if (__builtin_expect((g & CDT_GUIDE_WIDE) != 0u, 0)) return cdt_sample(T, w);
+  int k = (int)g;
+  k += T[k] <= r ? 1 : 0;
+  k += T[k] <= r ? 1 : 0;
+  return (k != 0 && (w & 1)) ? -k : k;
+}
+
 // ---------------------------------------------------------------------------
 // keys
 // ---------------------------------------------------------------------------
@@ -294,6 +310,19 @@ __device__ __forceinline__ void gen_gauss(uint64_t seed, uint64_t base_blk, cons
   }
 }
 
+// gen_gauss with the guided CDT search (the guide in LDS)
+template <int LOGN>
+__device__ __forceinline__ void gen_gauss_guided(uint64_t seed, uint64_t base_blk, const uint64_t* cdt,
+                                                 const uint8_t* guide, uint32_t t, int32_t (&ev)[8]) {
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    uint64_t d0, d1;
+    draw_pair(seed, DOM_ENC_E, base_blk + 4 * (uint64_t)t + f, d0, d1);
+    ev[2 * f] = cdt_sample_guided(cdt, guide, d0);
+    ev[2 * f + 1] = cdt_sample_guided(cdt, guide, d1);
+  }
+}
+
 // RGSW rows directly in the evaluation domain.  Draw k of prime i is the
 // value of a at the point psi^(2 brv(k) + 1), which is position k of the
 // forward transform's output (thread t holds positions 8t..8t+7, i.e. the
@@ -301,23 +330,27 @@ __device__ __forceinline__ void gen_gauss(uint64_t seed, uint64_t base_blk, cons
 // NTT(e); the gadget constant m*base^j is added to every evaluation point
 // (the transform of a constant polynomial is constant).  A workgroup builds
 // R consecutive rows of one ciphertext, so each prime's twiddle table is
-// copied to LDS once per R rows.
+// copied to LDS once per R rows.  The errors use the guided CDT search.
 template <int LOGN, int NQ, int R, int DIG = 5>
 __global__ __launch_bounds__(Geo<LOGN>::T) void k_enc_rgsw(Tabs T, Cdt cdt, EncArgs A) {
   __shared__ __attribute__((aligned(16))) uint32_t lds[2 * Geo<LOGN>::LDSW];
   __shared__ __attribute__((aligned(16))) uint2 twl[1 << LOGN];
   __shared__ uint64_t tab[42];
+  __shared__ __attribute__((aligned(16))) uint8_t gtab[CDT_GUIDE_SIZE];
   constexpr int N = 1 << LOGN, D = DIG * NQ, ROWS = 2 * D;
   static_assert(ROWS % R == 0, "rows per workgroup must divide the rows of an RGSW");
   const uint32_t t = threadIdx.x, r0 = blockIdx.x * R;
   const uint64_t c = blockIdx.y + (uint64_t)blockIdx.z * gridDim.y;
   if (t < 42) tab[t] = cdt.T[t];
+#pragma unroll 1
+  for (uint32_t i = t; i < CDT_GUIDE_SIZE / 16; i += Geo<LOGN>::T)
+    reinterpret_cast<uint4*>(gtab)[i] = reinterpret_cast<const uint4*>(cdt.guide)[i];
   const uint64_t ct = A.ct0 + c;
   const uint32_t m = A.bits[c];
   int32_t ev[R][8];
-  __syncthreads();  // the CDT table in LDS
+  __syncthreads();  // the CDT table and its guide in LDS
 #pragma unroll
-  for (int k = 0; k < R; ++k) gen_gauss<LOGN>(A.seed, (ct * ROWS + r0 + k) * (N / 2), tab, t, ev[k]);
+  for (int k = 0; k < R; ++k) gen_gauss_guided<LOGN>(A.seed, (ct * ROWS + r0 + k) * (N / 2), tab, gtab, t, ev[k]);
   uint32_t xc = 0;
 #pragma unroll 1
   for (int i = 0; i < NQ; ++i) {

@@ -83,3 +83,29 @@ def test_key_rows_decrypt_to_gadget_times_secret():
                     want[0] = int(s[j]) * pow(64, t, q)
                     want[0] = want[0] - q if want[0] > q // 2 else want[0]
                 assert np.abs(ph - want).max() <= 41, (j, r, i)
+
+
+def test_packing_on_a_two_digit_context_keeps_its_own_gadget():
+    """on a context whose RGSW use 2 digits of 15 bits, the key has the 5 nq
+    rows of base-64 digits per coordinate and packing still decrypts to
+    the LWE messages; RLWE and LWE ciphertexts are the same under both"""
+    c = O.Ctx(64, 2, 256, log_base=15, digits=2)
+    c6 = O.Ctx(64, 2, 256)
+    assert c.primes == c6.primes and c.D == 4 and c6.D == 10
+    s = c.keygen(4)
+    assert np.array_equal(s, c6.keygen(4))
+    K = c.pks_keygen(s, 77)
+    assert K.shape == (64, 10, 2, 2, 64)
+    assert np.array_equal(K, c6.pks_keygen(s, 77))
+    rng = np.random.default_rng(5)
+    msgs = rng.integers(0, 256, 20)
+    lwes = []
+    for i, m in enumerate(msgs):
+        mu = rng.integers(0, 256, 64).astype(np.uint64)
+        mu[0] = m
+        ct = c.enc_rlwe(s, mu, 5, i)
+        assert np.array_equal(ct, c6.enc_rlwe(s, mu, 5, i))
+        lwes.append(c.extract_lwe0(ct))
+    out = c.pack_lwe(K, np.stack(lwes))
+    dec = c.dec_rlwe(s, out)
+    assert np.array_equal(dec[:20], msgs.astype(np.uint64)) and not dec[20:].any()

@@ -143,12 +143,13 @@ def ops_per_enc_row(N: int, nq: int) -> float:
     fallback draw is not counted) and for the Gaussian e (N / 2, one 64-bit
     word per sample), 80 ops a block (10 rounds of two 32x32->64 products at
     2 ops and 4 XORs; the key schedule is scalar); 6 ops to reduce a word mod
-    q and test it; 30 per CDT sample (6 fixed search steps of a 64-bit
-    compare and a select, the sign); the forward NTT of e under each prime
+    q and test it; 12 per CDT sample (the guide lookup, two steps of a
+    64-bit compare and a select, the sign; the six-step search of the top
+    bucket, 2.4e-4 of the draws, is not counted); the forward NTT of e under each prime
     (9 ops a butterfly); 16 per coefficient and prime for the lift of e and
     b = a s + e + gadget (a Shoup product with the transformed key)."""
     logN = N.bit_length() - 1
-    return (80.0 * (nq * N / 4 + N / 2) + 6.0 * nq * N + 30.0 * N + 9.0 * nq * (N // 2) * logN
+    return (80.0 * (nq * N / 4 + N / 2) + 6.0 * nq * N + 12.0 * N + 9.0 * nq * (N // 2) * logN
             + 16.0 * nq * N)
 
 

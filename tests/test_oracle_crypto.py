@@ -17,10 +17,12 @@ def rand_rlwe(c, rng):
     return np.stack([np.stack([rng.integers(0, q, c.N) for q in c.primes]) for _ in range(2)]).astype(np.uint32)
 
 
-@pytest.mark.parametrize("N,nq", [(16, 1), (16, 2), (1024, 1), (2048, 2), (64, 3)])
-def test_trivial_rgsw_is_identity(N, nq):
-    """G [.] c = c and 0 [.] c = 0 bit-exactly: fixes row order, digit order, sides."""
-    c = O.Ctx(N, nq, 64)
+@pytest.mark.parametrize("N,nq,gadget", [(16, 1, (6, 5)), (16, 2, (6, 5)), (1024, 1, (6, 5)), (2048, 2, (6, 5)),
+                                         (64, 3, (6, 5)), (16, 2, (15, 2)), (2048, 2, (15, 2)), (64, 3, (15, 2))])
+def test_trivial_rgsw_is_identity(N, nq, gadget):
+    """G [.] c = c and 0 [.] c = 0 bit-exactly: fixes row order, digit order, sides
+    (both gadgets: 5 digits of 6 bits, and 2 of 15 bits on two or more primes)."""
+    c = O.Ctx(N, nq, 64, log_base=gadget[0], digits=gadget[1])
     rng = np.random.default_rng(N + nq)
     ct = rand_rlwe(c, rng)
     assert np.array_equal(c.extprod(c.trivial_rgsw(1), ct), ct)
